@@ -1,0 +1,310 @@
+"""Pins of the CPU oracle against what the paper and the mathematics fix.
+
+Each test checks the oracle against something other than itself: closed
+forms, an independent dense NumPy implementation (numpy.linalg.pinv Kron and
+dense solves), invariants of Kron reduction, and hand-derived values.
+"""
+import itertools
+
+import numpy as np
+import pytest
+
+import dense_check as dc
+from synth_feeders import make_feeder
+
+
+def tiny(seed, n=10, seg=(3, 5), **kw):
+    return make_feeder("c1", seed, n=n, n_eligible=None, seg_size=seg, **kw)
+
+
+def hand_feeder(parent, phase, zs, loads, V0=None):
+    """Feeder dict from explicit branch impedances zs[i] (3x3, i >= 1) and
+    consumed powers loads[l][i][p]."""
+    n = len(parent)
+    Yo = np.zeros((n, 3, 3), complex)
+    Yd = np.zeros((n, 3, 3), complex)
+    for i in range(1, n):
+        idx = [p for p in range(3) if phase[i] >> p & 1]
+        y = np.zeros((3, 3), complex)
+        y[np.ix_(idx, idx)] = np.linalg.inv(np.asarray(zs[i])[np.ix_(idx, idx)])
+        Yo[i] = -y
+        Yd[i] += y
+        Yd[parent[i]] += y
+    S = np.asarray(loads, complex)
+    return dict(n=n, parent=np.asarray(parent, np.int32), phase=np.asarray(phase, np.uint8),
+                segment=np.full(n, -1, np.int32), Y_diag=Yd, Y_off=Yo, S_load=S,
+                V0=np.exp(-2j * np.pi / 3 * np.arange(3)) if V0 is None else np.asarray(V0, complex),
+                e_bar=0.003, v_min=0.95, v_max=1.05)
+
+
+# ---------------------------------------------------------------- pinv ----
+
+def test_pinv_is_moore_penrose_on_present_phases(oracle_lib):
+    rng = np.random.default_rng(0)
+    for mask in range(1, 8):
+        idx = [p for p in range(3) if mask >> p & 1]
+        A = np.zeros((3, 3), complex)
+        B = rng.normal(size=(3, 3)) + 1j * rng.normal(size=(3, 3))
+        B = B + B.T + 4 * np.eye(3)
+        A[np.ix_(idx, idx)] = B[np.ix_(idx, idx)]
+        got = oracle_lib.pinv3(A, mask)
+        np.testing.assert_allclose(got, np.linalg.pinv(A), rtol=0, atol=1e-13)
+
+
+# ------------------------------------------------------------ power flow --
+
+def test_two_bus_closed_form(oracle_lib):
+    """Single-phase two-bus feeder: |V2|^4 - (|V0|^2 - 2(RP+XQ))|V2|^2
+    + (R^2+X^2)(P^2+Q^2) = 0, high-voltage root."""
+    R, X, P, Q = 0.02, 0.05, 0.8, 0.3
+    z = np.zeros((3, 3), complex)
+    z[0, 0] = R + 1j * X
+    f = hand_feeder([-1, 0], [7, 1], [None, z], [[[0, 0, 0], [P + 1j * Q, 0, 0]]])
+    V, I, st, it = oracle_lib.powerflow(f)
+    assert st == 0
+    b = 1.0 - 2 * (R * P + X * Q)
+    c = (R * R + X * X) * (P * P + Q * Q)
+    v2sq = (b + np.sqrt(b * b - 4 * c)) / 2
+    assert abs(abs(V[0, 1, 0]) - np.sqrt(v2sq)) < 1e-12
+
+
+@pytest.mark.parametrize("seed", range(4))
+def test_power_balance_residual(oracle_lib, seed):
+    """The converged library satisfies V o conj(Y V) = -S_load at every
+    non-slack node-phase, with Y assembled densely from the input blocks."""
+    f = make_feeder("c1", seed)
+    V, I, st, it = oracle_lib.powerflow(f)
+    assert st == 0
+    Y = dc.dense_Y(f)
+    pres = dc.present(f)
+    for l in range(V.shape[0]):
+        v = V[l].reshape(-1)
+        sinj = v * np.conj(Y @ v)
+        res = (sinj + f["S_load"][l].reshape(-1))[3:][pres[3:]]
+        assert np.abs(res).max() < 1e-10
+        # returned injections equal Y V^ off the slack
+        np.testing.assert_allclose((Y @ v)[3:][pres[3:]], I[l].reshape(-1)[3:][pres[3:]],
+                                   rtol=0, atol=1e-10)
+
+
+def test_powerflow_reports_divergence(oracle_lib):
+    f = make_feeder("c1", 0)
+    f = dict(f, S_load=f["S_load"] * 400.0)
+    _, _, st, _ = oracle_lib.powerflow(f)
+    assert st == -5
+
+
+# ------------------------------------------------------- Kron reduction --
+
+def random_keep(rng, n, p=0.5):
+    keep = (rng.random(n) > p).astype(np.uint8)
+    keep[0] = 1
+    return keep
+
+
+@pytest.mark.parametrize("seed", range(6))
+def test_kron_blocks_match_dense_pinv(oracle_lib, seed):
+    """Y_Kron from block elimination equals the dense Schur complement with
+    numpy's pseudo-inverse; it stays symmetric and Laplacian (no shunts)."""
+    f = tiny(seed, n=11)
+    rng = np.random.default_rng(seed)
+    elig = f["eligible"].astype(bool)
+    for _ in range(4):
+        keep = np.ones(f["n"], np.uint8)
+        keep[elig & (rng.random(f["n"]) < 0.6)] = 0
+        kp, Ykd, Yko, extra = oracle_lib.kron_blocks(f, keep)
+        Yk, K = dc.dense_kron(f, keep)
+        kept = [i for i in range(f["n"]) if keep[i]]
+        pos = {i: j for j, i in enumerate(kept)}
+        for i in kept:
+            np.testing.assert_allclose(Ykd[i], Yk[3 * pos[i]:3 * pos[i] + 3, 3 * pos[i]:3 * pos[i] + 3],
+                                       rtol=0, atol=1e-9 * np.abs(Yk).max())
+            if i > 0:
+                j = kp[i]
+                np.testing.assert_allclose(Yko[i], Yk[3 * pos[i]:3 * pos[i] + 3, 3 * pos[j]:3 * pos[j] + 3],
+                                           rtol=0, atol=1e-9 * np.abs(Yk).max())
+        # eligible nodes have at most one child: the reduction stays radial
+        assert extra == 0
+        np.testing.assert_allclose(Yk, Yk.T, rtol=0, atol=1e-9 * np.abs(Yk).max())
+        # Y_Kron (1 (x) v) = 0 for any phase vector v restricted to each node's phases
+        v = np.array([1.0, 0.3 - 0.2j, -0.7 + 0.1j])
+        pres = dc.present(f).reshape(f["n"], 3)
+        vec = np.concatenate([v * pres[i] for i in kept])
+        assert np.abs(Yk @ vec).max() < 1e-8 * np.abs(Yk).max()
+
+
+def test_lemma2_pattern_equals_single_phase_kron(oracle_lib):
+    """Lemma 2: the block pattern of three-phase Kron equals the pattern of
+    the single-phase Kron reduction of the same topology, also for a node of
+    degree 3 whose elimination creates a clique (Section V)."""
+    parent = [-1, 0, 1, 1, 1, 2]
+    phase = [7, 7, 7, 7, 7, 7]
+    rng = np.random.default_rng(3)
+    zs = [None]
+    for i in range(1, 6):
+        a = rng.uniform(0.5, 1.5, size=(3, 3)) * (0.01 + 0.03j)
+        zs.append(a + a.T + np.eye(3) * (0.02 + 0.06j))
+    f = hand_feeder(parent, phase, zs, np.zeros((1, 6, 3)))
+    for keep in itertools.product([0, 1], repeat=5):
+        keep = np.array((1,) + keep, np.uint8)
+        Yk, K = dc.dense_kron(f, keep)
+        # scalar Laplacian with unit weights, same topology
+        L = np.zeros((6, 6))
+        for i in range(1, 6):
+            p = parent[i]
+            L[i, i] += 1; L[p, p] += 1; L[i, p] -= 1; L[p, i] -= 1
+        k = [i for i in range(6) if keep[i]]
+        r = [i for i in range(6) if not keep[i]]
+        Lk = L[np.ix_(k, k)] - (L[np.ix_(k, r)] @ np.linalg.pinv(L[np.ix_(r, r)]) @ L[np.ix_(r, k)] if r else 0)
+        for a, b in itertools.product(range(len(k)), repeat=2):
+            blk = Yk[3 * a:3 * a + 3, 3 * b:3 * b + 3]
+            assert (np.abs(blk).max() > 1e-12) == (abs(Lk[a, b]) > 1e-12)
+
+
+def test_series_chain_and_leaf_closed_forms(oracle_lib):
+    """Eliminating the middle node of 0-a-b gives the series branch
+    -(z_a + z_b)^-1; eliminating a leaf removes its branch (Section II.B)."""
+    rng = np.random.default_rng(7)
+    zs = [None]
+    for _ in range(3):
+        a = rng.uniform(0.5, 1.5, size=(3, 3)) * (0.01 + 0.03j)
+        zs.append(a + a.T + np.eye(3) * (0.02 + 0.06j))
+    # 0 - 1 - 2, and a leaf 3 hanging off 2; node 2 is two-phase (a, b)
+    phase = [7, 7, 3, 1]
+    zs[2] = zs[2] * np.outer([1, 1, 0], [1, 1, 0])
+    zs[3] = zs[3] * np.outer([1, 0, 0], [1, 0, 0])
+    f = hand_feeder([-1, 0, 1, 2], phase, zs, np.zeros((1, 4, 3)))
+    kp, Ykd, Yko, extra = oracle_lib.kron_blocks(f, np.array([1, 0, 1, 0], np.uint8))
+    zeq = (zs[1] + zs[2])[:2, :2]
+    want = np.zeros((3, 3), complex)
+    want[:2, :2] = -np.linalg.inv(zeq)
+    assert kp[2] == 0
+    np.testing.assert_allclose(Yko[2], want, rtol=1e-12, atol=1e-9)
+    # after removing leaf 3 and node 1, node 2's self block is the series admittance only
+    np.testing.assert_allclose(Ykd[2], -want, rtol=1e-12, atol=1e-9)
+
+
+# ---------------------------------------------------- candidate voltages --
+
+@pytest.mark.parametrize("seed", range(6))
+def test_candidate_voltages_match_dense_routes(oracle_lib, seed):
+    """V^c from the oracle equals (a) the dense pinv Kron route and (b) the
+    full-network solve Y V^c = I^c, for random kept sets."""
+    f = tiny(seed, n=11, snapshots=2, scale=(0.3, 1.0))
+    V, I, st, _ = oracle_lib.powerflow(f)
+    assert st == 0
+    rng = np.random.default_rng(100 + seed)
+    for _ in range(5):
+        keep = random_keep(rng, f["n"])
+        got = oracle_lib.candidate_voltages(f, I, keep)
+        a = dc.vc_kron_route(f, I, keep)
+        b = dc.vc_full_route(f, I, keep)
+        np.testing.assert_allclose(got, a, rtol=0, atol=1e-12)
+        np.testing.assert_allclose(got, b, rtol=0, atol=1e-12)
+
+
+@pytest.mark.parametrize("seed", range(4))
+def test_zero_injection_invariant(oracle_lib, seed):
+    """Kron reduction preserves kept-node voltages when the reduced nodes carry
+    no injection (Section II.C): zero their loads, reduce them, compare."""
+    f = tiny(seed, n=12, snapshots=3, scale=(0.3, 1.0))
+    rng = np.random.default_rng(seed)
+    keep = random_keep(rng, f["n"], 0.4)
+    S = f["S_load"].copy()
+    S[:, keep == 0, :] = 0
+    f = dict(f, S_load=S)
+    V, I, st, _ = oracle_lib.powerflow(f)
+    assert st == 0
+    Vc = oracle_lib.candidate_voltages(f, I, keep)
+    np.testing.assert_allclose(Vc[:, keep == 1], V[:, keep == 1], rtol=0, atol=1e-12)
+
+
+def test_hand_example_three_node_chain(oracle_lib):
+    """Single-phase chain 0-a-b with fixed load currents L_a, L_b:
+    reduce b -> V^c_a = V^_a, V^c_b = V^_a; reduce a -> V^c_a = V0,
+    V^c_b = V0 - (z_a + z_b) L_b; reduce both -> V0 everywhere."""
+    za, zb = 0.01 + 0.03j, 0.02 + 0.05j
+    zs = [None] + [np.diag([z, 0, 0]) for z in (za, zb)]
+    f = hand_feeder([-1, 0, 1], [7, 1, 1], zs, [[[0, 0, 0], [0.3 + 0.1j, 0, 0], [0.5 + 0.2j, 0, 0]]])
+    V, I, st, _ = oracle_lib.powerflow(f)
+    assert st == 0
+    La, Lb = -I[0, 1, 0], -I[0, 2, 0]
+    V0 = f["V0"][0]
+    Va = V0 - za * (La + Lb)
+    Vb = Va - zb * Lb
+    assert abs(V[0, 1, 0] - Va) < 1e-12 and abs(V[0, 2, 0] - Vb) < 1e-12
+    Vc = oracle_lib.candidate_voltages(f, I, np.array([1, 1, 0], np.uint8))[0, :, 0]
+    assert abs(Vc[1] - Va) < 1e-12 and abs(Vc[2] - Va) < 1e-12
+    Vc = oracle_lib.candidate_voltages(f, I, np.array([1, 0, 1], np.uint8))[0, :, 0]
+    assert abs(Vc[1] - V0) < 1e-12 and abs(Vc[2] - (V0 - (za + zb) * Lb)) < 1e-12
+    Vc = oracle_lib.candidate_voltages(f, I, np.array([1, 0, 0], np.uint8))[0, :, 0]
+    assert abs(Vc[1] - V0) < 1e-12 and abs(Vc[2] - V0) < 1e-12
+
+
+# --------------------------------------------------------------- search --
+
+@pytest.mark.parametrize("seed,e_bar", [(0, 3e-4), (1, 1e-4), (2, 3e-4), (3, 1e-3), (4, 2e-4), (5, 3e-3)])
+def test_search_matches_dense_brute_force(oracle_lib, seed, e_bar):
+    """Every mask of every segment of a tiny feeder, scored with the dense
+    full-network route, picks the same aggregation as the oracle."""
+    f = tiny(seed, n=11, snapshots=2, scale=(0.3, 1.0), e_bar=e_bar)
+    V, I, st, _ = oracle_lib.powerflow(f)
+    keep_b, masks_b = dc.brute_search(f, V, I)
+    for mode in (0, 1):
+        keep, dec, st = oracle_lib.search(f, V, I, mode=mode)
+        assert st == 0
+        assert [d["mask"] for d in dec] == masks_b
+        assert not any(d["ambiguous"] for d in dec)
+        np.testing.assert_array_equal(keep, keep_b)
+
+
+def test_masks_leave_errors_outside_omega_unchanged(oracle_lib):
+    """Omega_g holds every node whose error can depend on the mask: outside it
+    the candidate voltages equal those of the empty mask."""
+    f = make_feeder("c1", 1, seg_size=(6, 6), n_eligible=None, snapshots=2, scale=(0.3, 1.0))
+    V, I, st, _ = oracle_lib.powerflow(f)
+    keep = np.ones(f["n"], np.uint8)
+    rng = np.random.default_rng(0)
+    nseg = int(f["segment"].max()) + 1
+    for g in range(nseg):
+        om = dc.omega(f, keep, g)
+        nodes = dc.seg_nodes(f, g)
+        base = oracle_lib.candidate_voltages(f, I, keep)
+        for m in rng.integers(0, 1 << len(nodes), size=4):
+            keep2 = keep.copy()
+            for j, v in enumerate(nodes):
+                if m >> j & 1:
+                    keep2[v] = 0
+            Vc = oracle_lib.candidate_voltages(f, I, keep2)
+            np.testing.assert_allclose(Vc[:, ~om], base[:, ~om], rtol=0, atol=1e-13)
+        # cumulative state: reduce the odd-positioned nodes of this segment
+        for j, v in enumerate(nodes):
+            if j % 2:
+                keep[v] = 0
+
+
+def test_base_out_of_band_warns_and_reduces_nothing(oracle_lib):
+    f = make_feeder("c1", 0, v_min=0.999)
+    V, I, st, _ = oracle_lib.powerflow(f)
+    keep, dec, st = oracle_lib.search(f, V, I)
+    assert st == oracle_lib.W_BASE_OUT_OF_BAND
+    assert keep.all() and all(d["mask"] == 0 for d in dec)
+
+
+def test_score_masks_agrees_with_dense_scores(oracle_lib):
+    f = tiny(2, n=11, snapshots=2, scale=(0.3, 1.0), e_bar=3e-4)
+    V, I, _, _ = oracle_lib.powerflow(f)
+    keep = np.ones(f["n"], np.uint8)
+    nodes = dc.seg_nodes(f, 0)
+    masks = np.arange(1 << len(nodes))
+    got = oracle_lib.score_masks(f, V, I, keep, 0, masks)
+    om = dc.omega(f, keep, 0)
+    for q, m in enumerate(masks):
+        keep2 = keep.copy()
+        for j, v in enumerate(nodes):
+            if m >> j & 1:
+                keep2[v] = 0
+        ref = dc.score(f, V, I, keep2, om)
+        for key in ("e_glob", "e_loc", "slack_glob", "slack_loc"):
+            assert abs(got[key][q] - ref[key]) < 1e-12
+        assert got["feasible"][q] == ref["feasible"]
