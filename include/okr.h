@@ -1,0 +1,190 @@
+/*
+ * okr.h -- C ABI of the MI355X (gfx950) segment-exhaustive Kron-reduction
+ * search ("Opti-KRON" exhaustive aggregation search, arXiv 2510.19608).
+ *
+ * What the library computes (Section IV of the paper, generalised from single
+ * edge moves to every subset of a segment's eligible nodes):
+ *
+ *   for each segment g (increasing id), against the cumulative state left by
+ *   the segments before it:
+ *     for every mask m in [0, 2^k):  reduce the nodes whose bit is set
+ *       - assignment: each reduced node moves its (aggregated) injection to
+ *         its nearest kept ancestor (Section II.C, eq. i_agg; Algorithm 1
+ *         current aggregation);
+ *       - Kron reduction of the network (eq. Y_kron, Schur complement with
+ *         the pseudo-inverse on present phases) and the fixed-current solve
+ *         of the reduced network over every load snapshot (Algorithm 1
+ *         "solve I^c = Y V^c", which gives the same super-node voltages);
+ *       - reduced nodes take their super-node's voltage (Algorithm 1);
+ *       - error e = max over snapshots, nodes, phases of ||V^| - |V^c||
+ *         (eq. iter_obj) and the margins: e <= e_bar (eq. v_abs, inclusive)
+ *         and v_min <= |V^c| <= v_max on every kept node-phase;
+ *     select the feasible mask with the most reduced nodes, then the smallest
+ *     error over the nodes the segment can affect, then the lowest mask
+ *     (errors within tie_tol of the minimum tie).
+ *   The scenario library (V^, I^) comes from an AC load flow of the full
+ *   network with constant-PQ wye loads (Section III, library L), unless the
+ *   caller passes V^.
+ *
+ * Conventions.
+ *   Complex numbers are interleaved double pairs (re, im).  3x3 blocks are
+ *   row-major, phase order a, b, c.  Values are per unit on a per-phase
+ *   line-to-neutral base.  Node 0 is the slack, parent[0] = -1.
+ *   Mask bit j of segment g is the j-th node of g in DFS preorder, children
+ *   visited in increasing node id.
+ *
+ * Memory.  The library allocates no device memory: the caller passes one
+ * device workspace of the size okr_plan() reports.  Pointers marked DEVICE
+ * must be device memory; pointers marked HOST host memory.  Nothing is
+ * retained after a call returns.  Calls on one handle must not overlap.
+ *
+ * Errors.  Every function returns 0 on success, a negative OKR_E_* code on
+ * failure (okr_last_error() gives a message) or a positive OKR_W_* warning.
+ * No exception or abort crosses the ABI.
+ */
+#ifndef OKR_H
+#define OKR_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define OKR_OK 0
+#define OKR_E_ARG (-1)         /* bad argument, size or pointer */
+#define OKR_E_NOT_TREE (-2)    /* parent[] is not a tree rooted at node 0 */
+#define OKR_E_PHASE (-3)       /* child phases not a subset of the parent's, or
+                                  nonzero entries on absent phases */
+#define OKR_E_SINGULAR (-4)    /* a present-phase branch block is singular */
+#define OKR_E_PF_DIVERGED (-5) /* load flow did not converge */
+#define OKR_E_WORKSPACE (-6)   /* workspace missing or smaller than planned */
+#define OKR_E_HIP (-7)         /* a HIP runtime call failed */
+#define OKR_E_UNSUPPORTED (-8) /* shunts / asymmetric blocks, or a segment with
+                                  more than 24 eligible nodes, or an eligible
+                                  node that is the slack or has two children */
+#define OKR_W_BASE_OUT_OF_BAND 1 /* the full network violates the band: nothing
+                                    is reduced (Algorithm 1 stops at once) */
+
+#define OKR_PRECISION_FP64 0   /* complex128 everywhere */
+#define OKR_PRECISION_MIXED 1  /* FP32 difference-form sweep, FP64 refine */
+
+#define OKR_FLAG_TIMING 1u     /* record per-kernel HIP-event timings */
+#define OKR_FLAG_VHAT_GIVEN 2u /* loads->Vhat holds the scenario voltages */
+#define OKR_FLAG_DUMP_SCORES 4u /* keep every mask's (e, slack) of the last
+                                   scored segment for okr_dump_scores() */
+
+typedef struct okr_handle okr_handle;
+
+/* Topology (HOST).  eligible[i] = 1 marks a node the search may reduce: it
+ * must not be the slack and must have at most one child (so reductions never
+ * create meshes, Section V).  segment[i] is the segment id of an eligible
+ * node, -1 otherwise; ids run from 0 without gaps. */
+typedef struct {
+    int32_t n;
+    const int32_t *parent;   /* [n] */
+    const uint8_t *phase;    /* [n] bit0 = a, bit1 = b, bit2 = c */
+    const uint8_t *eligible; /* [n] */
+    const int32_t *segment;  /* [n] */
+} okr_topology;
+
+/* Nodal admittance blocks (DEVICE, complex128 [n][3][3]).
+ * Y_off[i] = Y_{i,parent(i)} for i >= 1 (Y_off[0] ignored); Y_diag[i] = Y_ii.
+ * Blocks must be symmetric, zero on absent phases, and without shunts
+ * (Y_ii = -sum of the incident off-diagonal blocks, 1e-9 relative). */
+typedef struct {
+    const double *Y_diag;
+    const double *Y_off;
+} okr_yblocks;
+
+/* Loads.  S_load (DEVICE, complex128 [S][n][3]) is the consumed power P + jQ
+ * per node-phase and snapshot; V0 (HOST, complex128 [3]) the slack voltage;
+ * Vhat (DEVICE, complex128 [S][n][3], optional) the scenario voltages, used
+ * instead of the load flow when OKR_FLAG_VHAT_GIVEN is set. */
+typedef struct {
+    int32_t S;
+    const double *S_load;
+    const double *V0;
+    const double *Vhat;
+} okr_loads;
+
+typedef struct {
+    double e_bar;     /* voltage-magnitude error bound (p.u.), e.g. 0.003 */
+    double v_min;     /* band, inclusive, e.g. 0.95 */
+    double v_max;     /* e.g. 1.05 */
+    double tie_tol;   /* errors within tie_tol of the minimum tie (1e-11) */
+    double amb_tol;   /* near-boundary window for the ambiguity flag (1e-13) */
+    double pf_tol;    /* load-flow stop: max |dV| <= pf_tol (1e-13) */
+    int32_t pf_maxit; /* load-flow iteration cap (100) */
+    int32_t precision;/* OKR_PRECISION_* */
+    uint32_t flags;   /* OKR_FLAG_* */
+    int32_t reserved;
+} okr_margins;
+
+/* Sizes okr_plan() reports. */
+typedef struct {
+    int32_t n_segments;
+    int32_t k_max;        /* largest segment */
+    int64_t n_candidates; /* sum over segments of 2^k */
+} okr_sizes;
+
+/* Per-segment outcome. */
+typedef struct {
+    int32_t segment, k;
+    uint32_t mask;      /* chosen aggregation of the segment */
+    int32_t popcount;
+    double e_loc;       /* error of the chosen mask over the affected nodes */
+    double e_min;       /* smallest error at the chosen level */
+    int32_t ambiguous;  /* a candidate lay within amb_tol of a decision boundary */
+    int32_t n_scored;   /* masks scored exactly */
+    double flops;       /* algorithmic FP64 flops of the scoring kernel */
+    float score_ms;     /* scoring-kernel time (OKR_FLAG_TIMING) */
+    float pad;
+} okr_segment_result;
+
+/* Outputs (HOST buffers owned by the caller). */
+typedef struct {
+    int32_t *super;          /* [n] aggregation map: super[i] = i when kept */
+    int32_t *kept_parent;    /* [n] reduced-network parent of each kept node, -1 otherwise */
+    double *Yk_diag;         /* [n][3][3] complex128: Y_Kron(i,i), zero rows for reduced nodes */
+    double *Yk_off;          /* [n][3][3] complex128: Y_Kron(i, kept_parent[i]) */
+    double *err_per_snapshot;/* [S] max error over all nodes of the final reduction */
+    double *Vhat;            /* [S][n][3] complex128 scenario voltages, or NULL */
+    okr_segment_result *seg; /* [n_segments] */
+    int32_t n_kept;
+    int32_t warnings;        /* OKR_W_* bits seen */
+    double max_err;
+    /* wall-clock phase times (ms) and summed kernel times (OKR_FLAG_TIMING) */
+    double t_setup_ms, t_pf_ms, t_search_ms, t_final_ms;
+    double score_kernel_ms, algorithmic_flops;
+    int32_t pf_iterations, n_score_launches;
+} okr_result;
+
+/* One handle per HIP stream (hip_stream may be NULL for the null stream).
+ * The handle holds only host metadata. */
+int okr_create(okr_handle **h, void *hip_stream);
+
+/* Validate the topology and report the device workspace size for S
+ * snapshots, plus the output sizes. */
+int okr_plan(okr_handle *h, const okr_topology *topo, const okr_margins *mg,
+             int32_t S, size_t *workspace_bytes, okr_sizes *sizes);
+
+/* The search.  topo must be the planned topology; d_workspace (DEVICE) must
+ * hold workspace_bytes >= the planned size.  Synchronous on the handle's
+ * stream: outputs are complete in `out` on return. */
+int okr_reduce_feeder(okr_handle *h, const okr_yblocks *Y, const okr_topology *topo,
+                      const okr_loads *loads, const okr_margins *mg,
+                      void *d_workspace, size_t workspace_bytes, okr_result *out);
+
+/* With OKR_FLAG_DUMP_SCORES: copy the last scored segment's per-mask error
+ * and band slack (HOST double[2^k] each) and return k through *k. */
+int okr_dump_scores(okr_handle *h, int32_t segment, double *e, double *slack, int32_t *k);
+
+int okr_destroy(okr_handle *h);
+const char *okr_last_error(const okr_handle *h);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* OKR_H */

@@ -1,0 +1,275 @@
+"""ctypes binding of the C ABI in include/okr.h (argument marshalling only).
+
+torch supplies device memory and the HIP stream; every step of the search
+runs in the library's kernels.  The functions named okr_* mirror the C entry
+points one to one; ``Reducer`` and ``reduce_feeder`` are conveniences that
+plan once, keep inputs resident on the device and call okr_reduce_feeder.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_LIB_PATH = os.path.join(_HERE, "libokr.so")
+
+
+class OKR:
+    OK = 0
+    E_ARG = -1
+    E_NOT_TREE = -2
+    E_PHASE = -3
+    E_SINGULAR = -4
+    E_PF_DIVERGED = -5
+    E_WORKSPACE = -6
+    E_HIP = -7
+    E_UNSUPPORTED = -8
+    W_BASE_OUT_OF_BAND = 1
+    PRECISION_FP64 = 0
+    PRECISION_MIXED = 1
+    FLAG_TIMING = 1
+    FLAG_VHAT_GIVEN = 2
+    FLAG_DUMP_SCORES = 4
+
+
+class OkrError(RuntimeError):
+    def __init__(self, code, msg):
+        super().__init__(f"okr error {code}: {msg}")
+        self.code = code
+
+
+class Topology(ctypes.Structure):
+    _fields_ = [("n", ctypes.c_int32), ("parent", ctypes.c_void_p), ("phase", ctypes.c_void_p),
+                ("eligible", ctypes.c_void_p), ("segment", ctypes.c_void_p)]
+
+
+class YBlocks(ctypes.Structure):
+    _fields_ = [("Y_diag", ctypes.c_void_p), ("Y_off", ctypes.c_void_p)]
+
+
+class Loads(ctypes.Structure):
+    _fields_ = [("S", ctypes.c_int32), ("S_load", ctypes.c_void_p), ("V0", ctypes.c_void_p),
+                ("Vhat", ctypes.c_void_p)]
+
+
+class Margins(ctypes.Structure):
+    _fields_ = [("e_bar", ctypes.c_double), ("v_min", ctypes.c_double), ("v_max", ctypes.c_double),
+                ("tie_tol", ctypes.c_double), ("amb_tol", ctypes.c_double), ("pf_tol", ctypes.c_double),
+                ("pf_maxit", ctypes.c_int32), ("precision", ctypes.c_int32), ("flags", ctypes.c_uint32),
+                ("reserved", ctypes.c_int32)]
+
+
+class Sizes(ctypes.Structure):
+    _fields_ = [("n_segments", ctypes.c_int32), ("k_max", ctypes.c_int32), ("n_candidates", ctypes.c_int64)]
+
+
+class SegmentResult(ctypes.Structure):
+    _fields_ = [("segment", ctypes.c_int32), ("k", ctypes.c_int32), ("mask", ctypes.c_uint32),
+                ("popcount", ctypes.c_int32), ("e_loc", ctypes.c_double), ("e_min", ctypes.c_double),
+                ("ambiguous", ctypes.c_int32), ("n_scored", ctypes.c_int32), ("flops", ctypes.c_double),
+                ("score_ms", ctypes.c_float), ("pad", ctypes.c_float)]
+
+
+class Result(ctypes.Structure):
+    _fields_ = [("super", ctypes.c_void_p), ("kept_parent", ctypes.c_void_p), ("Yk_diag", ctypes.c_void_p),
+                ("Yk_off", ctypes.c_void_p), ("err_per_snapshot", ctypes.c_void_p), ("Vhat", ctypes.c_void_p),
+                ("seg", ctypes.c_void_p), ("n_kept", ctypes.c_int32), ("warnings", ctypes.c_int32),
+                ("max_err", ctypes.c_double), ("t_setup_ms", ctypes.c_double), ("t_pf_ms", ctypes.c_double),
+                ("t_search_ms", ctypes.c_double), ("t_final_ms", ctypes.c_double),
+                ("score_kernel_ms", ctypes.c_double), ("algorithmic_flops", ctypes.c_double),
+                ("pf_iterations", ctypes.c_int32), ("n_score_launches", ctypes.c_int32)]
+
+
+_lib = None
+
+
+def lib():
+    """Load libokr.so; raises if it has not been built (no fallback)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(_LIB_PATH):
+            raise OkrError(OKR.E_HIP, f"{_LIB_PATH} is missing: run __graft_entry__.build()")
+        L = ctypes.CDLL(_LIB_PATH)
+        vp = ctypes.c_void_p
+        L.okr_create.argtypes = [ctypes.POINTER(vp), vp]
+        L.okr_plan.argtypes = [vp, ctypes.POINTER(Topology), ctypes.POINTER(Margins), ctypes.c_int32,
+                               ctypes.POINTER(ctypes.c_size_t), ctypes.POINTER(Sizes)]
+        L.okr_reduce_feeder.argtypes = [vp, ctypes.POINTER(YBlocks), ctypes.POINTER(Topology),
+                                        ctypes.POINTER(Loads), ctypes.POINTER(Margins), vp, ctypes.c_size_t,
+                                        ctypes.POINTER(Result)]
+        L.okr_dump_scores.argtypes = [vp, ctypes.c_int32, vp, vp, ctypes.POINTER(ctypes.c_int32)]
+        L.okr_destroy.argtypes = [vp]
+        L.okr_last_error.argtypes = [vp]
+        L.okr_last_error.restype = ctypes.c_char_p
+        for fn in ("okr_create", "okr_plan", "okr_reduce_feeder", "okr_dump_scores", "okr_destroy"):
+            getattr(L, fn).restype = ctypes.c_int
+        _lib = L
+    return _lib
+
+
+# ---- one-to-one wrappers of the C entry points ---------------------------
+
+def okr_create(stream=None):
+    h = ctypes.c_void_p()
+    rc = lib().okr_create(ctypes.byref(h), stream)
+    if rc != 0:
+        raise OkrError(rc, "okr_create failed")
+    return h
+
+
+def okr_last_error(h):
+    return lib().okr_last_error(h).decode()
+
+
+def _check(h, rc):
+    if rc < 0:
+        raise OkrError(rc, okr_last_error(h))
+    return rc
+
+
+def okr_plan(h, topo: Topology, margins: Margins, S: int):
+    ws = ctypes.c_size_t(0)
+    sizes = Sizes()
+    _check(h, lib().okr_plan(h, ctypes.byref(topo), ctypes.byref(margins), S, ctypes.byref(ws),
+                             ctypes.byref(sizes)))
+    return ws.value, sizes
+
+
+def okr_reduce_feeder(h, Y: YBlocks, topo: Topology, loads: Loads, margins: Margins, d_ws, ws_bytes,
+                      out: Result):
+    return _check(h, lib().okr_reduce_feeder(h, ctypes.byref(Y), ctypes.byref(topo), ctypes.byref(loads),
+                                             ctypes.byref(margins), d_ws, ws_bytes, ctypes.byref(out)))
+
+
+def okr_dump_scores(h, segment, nmask):
+    e = np.zeros(nmask)
+    s = np.zeros(nmask)
+    k = ctypes.c_int32(0)
+    _check(h, lib().okr_dump_scores(h, segment, e.ctypes.data, s.ctypes.data, ctypes.byref(k)))
+    return e, s, k.value
+
+
+def okr_destroy(h):
+    return lib().okr_destroy(h)
+
+
+# ---- conveniences ----------------------------------------------------------
+
+def make_margins(f=None, *, e_bar=None, v_min=None, v_max=None, tie_tol=1e-11, amb_tol=1e-13,
+                 precision="fp64", timing=False, dump=False, vhat_given=False, pf_tol=1e-13, pf_maxit=100):
+    f = f or {}
+    flags = (OKR.FLAG_TIMING if timing else 0) | (OKR.FLAG_DUMP_SCORES if dump else 0) | \
+            (OKR.FLAG_VHAT_GIVEN if vhat_given else 0)
+    return Margins(e_bar=f.get("e_bar", 0.003) if e_bar is None else e_bar,
+                   v_min=f.get("v_min", 0.95) if v_min is None else v_min,
+                   v_max=f.get("v_max", 1.05) if v_max is None else v_max,
+                   tie_tol=tie_tol, amb_tol=amb_tol, pf_tol=pf_tol, pf_maxit=pf_maxit,
+                   precision={"fp64": OKR.PRECISION_FP64, "mixed": OKR.PRECISION_MIXED}[precision],
+                   flags=flags, reserved=0)
+
+
+class Reducer:
+    """Plans once, keeps the feeder's inputs resident on the device and runs
+    okr_reduce_feeder on demand (``run``)."""
+
+    def __init__(self, f, device="cuda:0", vhat=None, **margin_kw):
+        import torch
+        if not torch.cuda.is_available():
+            raise OkrError(OKR.E_HIP, "no GPU visible: the search runs only on the HIP device")
+        lib()
+        self.torch = torch
+        self.device = torch.device(device)
+        self.f = f
+        n, S = int(f["n"]), int(np.asarray(f["S_load"]).shape[0])
+        self.n, self.S = n, S
+        self.parent = np.ascontiguousarray(f["parent"], dtype=np.int32)
+        self.phase = np.ascontiguousarray(f["phase"], dtype=np.uint8)
+        self.eligible = np.ascontiguousarray(f["eligible"], dtype=np.uint8)
+        self.segment = np.ascontiguousarray(f["segment"], dtype=np.int32)
+        self.topo = Topology(n, self.parent.ctypes.data, self.phase.ctypes.data, self.eligible.ctypes.data,
+                             self.segment.ctypes.data)
+        self.margins = make_margins(f, vhat_given=vhat is not None, **margin_kw)
+
+        def dev(a):
+            t = torch.from_numpy(np.ascontiguousarray(a, dtype=np.complex128))
+            return torch.view_as_real(t).contiguous().to(self.device)
+
+        with torch.cuda.device(self.device):
+            self.Yd = dev(f["Y_diag"])
+            self.Yo = dev(f["Y_off"])
+            self.Sl = dev(f["S_load"])
+            self.Vh = dev(vhat) if vhat is not None else None
+            self.stream = torch.cuda.current_stream(self.device)
+            self.h = okr_create(ctypes.c_void_p(self.stream.cuda_stream))
+            self.ws_bytes, self.sizes = okr_plan(self.h, self.topo, self.margins, S)
+            self.ws = torch.empty(max(self.ws_bytes, 1), dtype=torch.uint8, device=self.device)
+        self.V0 = np.ascontiguousarray(f["V0"], dtype=np.complex128)
+        self.Y = YBlocks(self.Yd.data_ptr(), self.Yo.data_ptr())
+        self.loads = Loads(S, self.Sl.data_ptr(), self.V0.ctypes.data,
+                           self.Vh.data_ptr() if self.Vh is not None else None)
+        nseg = self.sizes.n_segments
+        self.out_super = np.zeros(n, np.int32)
+        self.out_kp = np.zeros(n, np.int32)
+        self.out_Ykd = np.zeros((n, 3, 3), np.complex128)
+        self.out_Yko = np.zeros((n, 3, 3), np.complex128)
+        self.out_err = np.zeros(S)
+        self.out_Vhat = np.zeros((S, n, 3), np.complex128)
+        self.out_seg = (SegmentResult * max(nseg, 1))()
+        self.res = Result(self.out_super.ctypes.data, self.out_kp.ctypes.data, self.out_Ykd.ctypes.data,
+                          self.out_Yko.ctypes.data, self.out_err.ctypes.data, None,
+                          ctypes.cast(self.out_seg, ctypes.c_void_p))
+
+    def run(self, replan=True, want_vhat=False):
+        """One pass of the whole search (planning included when replan)."""
+        if replan:
+            self.ws_bytes_now, _ = okr_plan(self.h, self.topo, self.margins, self.S)
+        self.res.Vhat = self.out_Vhat.ctypes.data if want_vhat else None
+        rc = okr_reduce_feeder(self.h, self.Y, self.topo, self.loads, self.margins,
+                               ctypes.c_void_p(self.ws.data_ptr()), self.ws_bytes, self.res)
+        return rc
+
+    def result(self):
+        r = self.res
+        segs = [dict(segment=s.segment, k=s.k, mask=s.mask, popcount=s.popcount, e_loc=s.e_loc,
+                     e_min=s.e_min, ambiguous=bool(s.ambiguous), n_scored=s.n_scored, flops=s.flops,
+                     score_ms=s.score_ms) for s in list(self.out_seg)[:self.sizes.n_segments]]
+        return dict(super=self.out_super.copy(), kept_parent=self.out_kp.copy(),
+                    kept=(self.out_super == np.arange(self.n)).astype(np.uint8),
+                    Yk_diag=self.out_Ykd.copy(), Yk_off=self.out_Yko.copy(),
+                    err_per_snapshot=self.out_err.copy(), max_err=r.max_err, n_kept=r.n_kept,
+                    warnings=r.warnings, segments=segs, t_pf_ms=r.t_pf_ms, t_search_ms=r.t_search_ms,
+                    t_final_ms=r.t_final_ms, score_kernel_ms=r.score_kernel_ms,
+                    algorithmic_flops=r.algorithmic_flops, pf_iterations=r.pf_iterations,
+                    n_score_launches=r.n_score_launches, Vhat=self.out_Vhat)
+
+    def dump_scores(self, g):
+        k = self.result()["segments"][g]["k"]
+        return okr_dump_scores(self.h, g, 1 << k)
+
+    def close(self):
+        if getattr(self, "h", None) is not None:
+            okr_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def reduce_feeder(f, device="cuda:0", vhat=None, want_vhat=True, **margin_kw):
+    """Run the search once on a feeder dict and return the result dict."""
+    R = Reducer(f, device=device, vhat=vhat, **margin_kw)
+    try:
+        rc = R.run(replan=False, want_vhat=want_vhat)
+        R.torch.cuda.synchronize(R.device)
+        out = R.result()
+        out["status"] = rc
+        if margin_kw.get("dump"):
+            out["scores"] = {g: R.dump_scores(g) for g in range(R.sizes.n_segments)}
+        return out
+    finally:
+        R.close()

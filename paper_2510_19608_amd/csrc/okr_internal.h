@@ -1,0 +1,69 @@
+// Internal tables shared by the host planner and the gfx950 kernels.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace okr {
+
+constexpr int kMaxK = 24;                    // eligible nodes per segment
+constexpr int kMaxPairs = kMaxK * (kMaxK + 1) / 2;  // (super slot, reduced slot) pairs
+constexpr int kScoreBlock = 64;              // one wave per scoring block
+
+// Index tables of one segment, built on the host from the cumulative kept
+// state and uploaded as one int32 buffer; the offsets below index into it.
+struct SegHdr {
+  int k;          // eligible nodes in the segment
+  int nchains;    // chains of the affected region
+  int nslots;     // == k (every segment node is a slot of exactly one chain)
+  int npairs;     // sum over chains of j(j+1)/2
+  int nz;         // zone entries (kept target node, phase)
+  int nh;         // head-cluster members (constant error part)
+  int nmem;       // cluster member entries (slots then zone entries)
+  int S;          // snapshots
+  // offsets (in int32 units) into the table buffer
+  int o_chain;    // [nchains][kChainInts]
+  int o_nest;     // nesting paths, outermost first, ending with the chain itself
+  int o_slot;     // [nslots][kSlotInts]
+  int o_path;     // chain node paths, top to bottom
+  int o_pair;     // [npairs][kPairInts]
+  int o_zent;     // [nz][2]: node, phase
+  int o_zmemoff;  // [nz + 1] CSR offsets into members
+  int o_smemoff;  // [nslots + 1] CSR offsets into members
+  int o_mem;      // member node ids
+  int o_h;        // [nh][3]: member node, head node, present-phase mask of the member
+  int total_ints;
+};
+
+// chain record
+enum { C_HEAD = 0, C_NSLOT, C_SLOT0, C_NEST_OFF, C_NEST_LEN, C_PATH_OFF, C_PATH_LEN,
+       C_ZOFF0, C_ZOFF1, C_ZOFF2, C_ZCNT0, C_ZCNT1, C_ZCNT2, C_OUTER, kChainInts };
+// slot record
+enum { SL_NODE = 0, SL_BIT, SL_PHASE, SL_PAIRBASE, SL_PATHPOS, SL_CHAIN, kSlotInts };
+// pair record: reduced slot node, first and last path index summed, chain path offset
+enum { PR_RNODE = 0, PR_FROM, PR_TO, PR_PATHOFF, kPairInts };
+
+// Per-slot and per-zone-entry numeric data for one snapshot and phase.
+struct TargetRec {
+  double2 W;   // current voltage of the kept node the entry evaluates
+  double lo;   // min |V^| over the cluster's members on that phase
+  double hi;   // max |V^| over the cluster's members on that phase
+};
+
+// Decision written by the arg-min kernel.
+struct DevDecision {
+  uint32_t mask;
+  int32_t popcount;
+  double e_loc;
+  double e_min;
+  int32_t ambiguous;
+  int32_t found;
+};
+
+// Per-mask partial score: max error and min band slack over a snapshot group.
+struct MaskScore {
+  double e;
+  double slack;
+};
+
+}  // namespace okr

@@ -1,0 +1,616 @@
+// gfx950 kernels of the segment-exhaustive Kron-reduction search.
+//
+// Data layout in HBM (complex values as double2 = (re, im)):
+//   z[n][9]            branch impedance of node i's upstream edge (restricted)
+//   Vhat, Vcur, A      [S][n][3]: scenario voltages, current candidate-state
+//                      voltages of kept nodes, aggregated load current of kept
+//                      nodes (consumed current, = -I^ moved by the assignment)
+//   absV[S][n][3]      |Vhat|
+//   per segment        P[S][npairs][3], slot/zone TargetRec[S][..][3], headV
+//   scores             MaskScore[snapshot group][2^k]
+#include <hip/hip_runtime.h>
+#include <math.h>
+#include <stdint.h>
+
+#include "okr_internal.h"
+
+namespace okr {
+
+// ---------------------------------------------------------------- complex --
+__device__ __forceinline__ double2 cadd(double2 a, double2 b) { return make_double2(a.x + b.x, a.y + b.y); }
+__device__ __forceinline__ double2 csub(double2 a, double2 b) { return make_double2(a.x - b.x, a.y - b.y); }
+__device__ __forceinline__ double2 cmul(double2 a, double2 b) {
+  return make_double2(a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x);
+}
+__device__ __forceinline__ double2 cconj(double2 a) { return make_double2(a.x, -a.y); }
+__device__ __forceinline__ double cabs2(double2 a) { return a.x * a.x + a.y * a.y; }
+__device__ __forceinline__ double2 cdiv(double2 a, double2 b) {
+  const double d = cabs2(b);
+  const double2 t = cmul(a, cconj(b));
+  return make_double2(t.x / d, t.y / d);
+}
+// |v| with the hardware square root (v_sqrt_f64).
+__device__ __forceinline__ double cmag(double2 a) { return __builtin_amdgcn_sqrt(cabs2(a)); }
+
+// Restricted inverse of a 3x3 block on the phases in `mask` (zero-padded):
+// for blocks supported on the present-phase principal submatrix this is the
+// Moore-Penrose pseudo-inverse (Section II.B footnote).  Closed forms for
+// 1x1, 2x2 (adjugate) and 3x3 (cofactors).  Returns false if singular.
+__device__ bool inv_restricted(const double2* A, unsigned mask, double2* out) {
+  int idx[3];
+  int m = 0;
+  for (int p = 0; p < 3; ++p)
+    if (mask >> p & 1u) idx[m++] = p;
+  for (int q = 0; q < 9; ++q) out[q] = make_double2(0.0, 0.0);
+  if (m == 1) {
+    const double2 a = A[idx[0] * 4];
+    if (cabs2(a) == 0.0) return false;
+    out[idx[0] * 4] = cdiv(make_double2(1.0, 0.0), a);
+    return true;
+  }
+  if (m == 2) {
+    const int i = idx[0], j = idx[1];
+    const double2 a = A[i * 3 + i], b = A[i * 3 + j], c = A[j * 3 + i], d = A[j * 3 + j];
+    const double2 det = csub(cmul(a, d), cmul(b, c));
+    if (cabs2(det) == 0.0) return false;
+    out[i * 3 + i] = cdiv(d, det);
+    out[i * 3 + j] = cdiv(make_double2(-b.x, -b.y), det);
+    out[j * 3 + i] = cdiv(make_double2(-c.x, -c.y), det);
+    out[j * 3 + j] = cdiv(a, det);
+    return true;
+  }
+  if (m == 3) {
+    double2 cof[9];
+    for (int r = 0; r < 3; ++r)
+      for (int c = 0; c < 3; ++c) {
+        const int r1 = (r + 1) % 3, r2 = (r + 2) % 3, c1 = (c + 1) % 3, c2 = (c + 2) % 3;
+        cof[r * 3 + c] = csub(cmul(A[r1 * 3 + c1], A[r2 * 3 + c2]), cmul(A[r1 * 3 + c2], A[r2 * 3 + c1]));
+      }
+    const double2 det = cadd(cadd(cmul(A[0], cof[0]), cmul(A[1], cof[1])), cmul(A[2], cof[2]));
+    if (cabs2(det) == 0.0) return false;
+    for (int r = 0; r < 3; ++r)
+      for (int c = 0; c < 3; ++c) out[r * 3 + c] = cdiv(cof[c * 3 + r], det);
+    return true;
+  }
+  return m == 0;
+}
+
+__device__ __forceinline__ double blk_maxabs(const double2* A) {
+  double mx = 0.0;
+  for (int q = 0; q < 9; ++q) mx = fmax(mx, sqrt(cabs2(A[q])));
+  return mx;
+}
+
+// ---------------------------------------------------------- validation + z --
+// One thread per node: branch impedance z_i = (-Y_{i,parent})^+ and checks of
+// the admittance input (symmetry, zero absent-phase entries, no shunts).
+// status bits: 1 singular, 2 absent-phase entry, 4 asymmetric, 8 shunt.
+__global__ void k_branch_z(int n, const int* __restrict__ parent, const uint8_t* __restrict__ phase,
+                           const int* __restrict__ ch_off, const int* __restrict__ ch,
+                           const double2* __restrict__ Ydiag, const double2* __restrict__ Yoff,
+                           double2* __restrict__ z, int* __restrict__ status) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  const unsigned ph = phase[i];
+  int bad = 0;
+  const double2* Yd = Ydiag + (size_t)i * 9;
+  double dscale = blk_maxabs(Yd);
+  // Laplacian row: Y_ii + Y_{i,p} + sum_c Y_{i,c} = 0, with Y_{i,c} = Y_{c,i}^T
+  double2 acc[9];
+  for (int q = 0; q < 9; ++q) acc[q] = Yd[q];
+  if (i > 0) {
+    const double2* Yo = Yoff + (size_t)i * 9;
+    for (int q = 0; q < 9; ++q) acc[q] = cadd(acc[q], Yo[q]);
+    const double oscale = blk_maxabs(Yo);
+    for (int r = 0; r < 3; ++r)
+      for (int c = 0; c < 3; ++c) {
+        const double2 d = csub(Yo[r * 3 + c], Yo[c * 3 + r]);
+        if (sqrt(cabs2(d)) > 1e-12 * oscale) bad |= 4;
+        const bool absent = !((ph >> r) & 1u) || !((ph >> c) & 1u);
+        if (absent && cabs2(Yo[r * 3 + c]) != 0.0) bad |= 2;
+      }
+    double2 y[9];
+    for (int q = 0; q < 9; ++q) y[q] = make_double2(-Yo[q].x, -Yo[q].y);
+    if (!inv_restricted(y, ph, z + (size_t)i * 9)) bad |= 1;
+  } else {
+    for (int q = 0; q < 9; ++q) z[q] = make_double2(0.0, 0.0);
+  }
+  for (int e = ch_off[i]; e < ch_off[i + 1]; ++e) {
+    const double2* Yc = Yoff + (size_t)ch[e] * 9;
+    for (int r = 0; r < 3; ++r)
+      for (int c = 0; c < 3; ++c) acc[r * 3 + c] = cadd(acc[r * 3 + c], Yc[c * 3 + r]);
+  }
+  for (int r = 0; r < 3; ++r)
+    for (int c = 0; c < 3; ++c) {
+      const bool absent = !((ph >> r) & 1u) || !((ph >> c) & 1u);
+      if (absent && cabs2(Yd[r * 3 + c]) != 0.0) bad |= 2;
+    }
+  if (blk_maxabs(acc) > 1e-9 * fmax(dscale, 1e-300)) bad |= 8;
+  if (bad) atomicOr(status, bad);
+}
+
+// ------------------------------------------------------------ block reduce --
+template <typename T, typename Op>
+__device__ T block_reduce(T v, Op op, T* sh) {
+  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6, nw = (blockDim.x + 63) >> 6;
+  for (int o = 32; o > 0; o >>= 1) v = op(v, __shfl_xor(v, o, 64));
+  __syncthreads();
+  if (lane == 0) sh[wid] = v;
+  __syncthreads();
+  T r = sh[0];
+  for (int w = 1; w < nw; ++w) r = op(r, sh[w]);
+  __syncthreads();
+  return r;
+}
+
+// ------------------------------------------------------------- load flow --
+// Scenario library (Section III): constant-PQ wye loads, backward/forward
+// sweep on the radial tree, one block per snapshot, level-synchronous.
+// status bit 16: not converged; bit 32: base network outside the band.
+__global__ __launch_bounds__(256) void k_powerflow(
+    int n, const int* __restrict__ parent, const uint8_t* __restrict__ phase,
+    const int* __restrict__ lvl_off, const int* __restrict__ lvl_nodes, int nlev,
+    const int* __restrict__ ch_off, const int* __restrict__ ch, const double2* __restrict__ z,
+    const double2* __restrict__ Sload, double2 v0a, double2 v0b, double2 v0c, double tol, int maxit,
+    double vmin, double vmax, double2* __restrict__ V, double2* __restrict__ J,
+    double2* __restrict__ A, double* __restrict__ absV, int* __restrict__ iters, int* __restrict__ status) {
+  __shared__ double shd[16];
+  const int l = blockIdx.x;
+  const size_t base = (size_t)l * n * 3;
+  double2* Vl = V + base;
+  double2* Jl = J + base;
+  const double2* Sl = Sload + base;
+  const double2 v0[3] = {v0a, v0b, v0c};
+  for (int i = threadIdx.x; i < n; i += blockDim.x)
+    for (int p = 0; p < 3; ++p) Vl[i * 3 + p] = (phase[i] >> p & 1u) ? v0[p] : make_double2(0.0, 0.0);
+  __syncthreads();
+  int it = 0;
+  bool conv = false;
+  for (it = 1; it <= maxit; ++it) {
+    for (int i = threadIdx.x; i < n; i += blockDim.x)
+      for (int p = 0; p < 3; ++p)
+        Jl[i * 3 + p] = (i > 0 && (phase[i] >> p & 1u)) ? cconj(cdiv(Sl[i * 3 + p], Vl[i * 3 + p]))
+                                                        : make_double2(0.0, 0.0);
+    __syncthreads();
+    for (int lev = nlev - 2; lev >= 0; --lev) {
+      for (int q = lvl_off[lev] + threadIdx.x; q < lvl_off[lev + 1]; q += blockDim.x) {
+        const int i = lvl_nodes[q];
+        double2 s0 = Jl[i * 3], s1 = Jl[i * 3 + 1], s2 = Jl[i * 3 + 2];
+        for (int e = ch_off[i]; e < ch_off[i + 1]; ++e) {
+          const int c = ch[e];
+          s0 = cadd(s0, Jl[c * 3]);
+          s1 = cadd(s1, Jl[c * 3 + 1]);
+          s2 = cadd(s2, Jl[c * 3 + 2]);
+        }
+        Jl[i * 3] = s0; Jl[i * 3 + 1] = s1; Jl[i * 3 + 2] = s2;
+      }
+      __syncthreads();
+    }
+    double dmax = 0.0;
+    for (int lev = 1; lev < nlev; ++lev) {
+      for (int q = lvl_off[lev] + threadIdx.x; q < lvl_off[lev + 1]; q += blockDim.x) {
+        const int i = lvl_nodes[q], pv = parent[i];
+        const double2* zi = z + (size_t)i * 9;
+        const double2 j0 = Jl[i * 3], j1 = Jl[i * 3 + 1], j2 = Jl[i * 3 + 2];
+        for (int p = 0; p < 3; ++p) {
+          if (!(phase[i] >> p & 1u)) continue;
+          const double2 d = cadd(cadd(cmul(zi[p * 3], j0), cmul(zi[p * 3 + 1], j1)), cmul(zi[p * 3 + 2], j2));
+          const double2 nv = csub(Vl[pv * 3 + p], d);
+          const double dd = sqrt(cabs2(csub(nv, Vl[i * 3 + p])));
+          dmax = (dd <= dmax) ? dmax : dd;  // NaN-propagating
+          Vl[i * 3 + p] = nv;
+        }
+      }
+      __syncthreads();
+    }
+    dmax = block_reduce(dmax, [](double a, double b) { return (b <= a) ? a : b; }, shd);
+    if (!(dmax <= 1e3)) break;
+    if (dmax <= tol) { conv = true; break; }
+  }
+  double vlo = 1e300, vhi = -1e300;
+  for (int i = threadIdx.x; i < n; i += blockDim.x)
+    for (int p = 0; p < 3; ++p) {
+      const bool pr = (phase[i] >> p & 1u);
+      const double2 v = Vl[i * 3 + p];
+      A[base + i * 3 + p] = (i > 0 && pr) ? cconj(cdiv(Sl[i * 3 + p], v)) : make_double2(0.0, 0.0);
+      const double m = pr ? sqrt(cabs2(v)) : 0.0;
+      absV[base + i * 3 + p] = m;
+      if (pr) { vlo = fmin(vlo, m); vhi = fmax(vhi, m); }
+    }
+  vlo = block_reduce(vlo, [](double a, double b) { return fmin(a, b); }, shd);
+  vhi = block_reduce(vhi, [](double a, double b) { return fmax(a, b); }, shd);
+  if (threadIdx.x == 0) {
+    iters[l] = it;
+    if (!conv) atomicOr(status, 16);
+    if (vlo < vmin || vhi > vmax) atomicOr(status, 32);
+  }
+}
+
+// Given V^ (caller supplied): load currents and magnitudes, band check.
+__global__ void k_from_vhat(int n, int S, const uint8_t* __restrict__ phase, const double2* __restrict__ Sload,
+                            const double2* __restrict__ V, double vmin, double vmax, double2* __restrict__ A,
+                            double* __restrict__ absV, int* __restrict__ status) {
+  const size_t q = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (q >= (size_t)S * n * 3) return;
+  const int p = q % 3, i = (q / 3) % n;
+  const bool pr = (phase[i] >> p & 1u);
+  A[q] = (i > 0 && pr) ? cconj(cdiv(Sload[q], V[q])) : make_double2(0.0, 0.0);
+  const double m = pr ? sqrt(cabs2(V[q])) : 0.0;
+  absV[q] = m;
+  if (pr && (m < vmin || m > vmax)) atomicOr(status, 32);
+}
+
+// ------------------------------------------------------- segment tables --
+// Numeric tables of one segment from the current state (grid.y = part):
+//   0: P[l][pair] = Z(super -> reduced) A_reduced     (series impedance of the
+//      Kron-eliminated path times the moved aggregated current)
+//   1: slot TargetRec (W = Vcur, lo/hi over the slot's cluster)
+//   2: head voltages, 3: zone TargetRec, 4: constant error of head clusters.
+__global__ void k_seg_fill(const int* __restrict__ tab, SegHdr H, int n, const double2* __restrict__ z,
+                           const double2* __restrict__ Vcur, const double2* __restrict__ A,
+                           const double* __restrict__ absV, double2* __restrict__ P,
+                           TargetRec* __restrict__ srec, double2* __restrict__ headV,
+                           TargetRec* __restrict__ zrec, double* __restrict__ econst) {
+  const int part = blockIdx.y;
+  const int t = blockIdx.x * blockDim.x + threadIdx.x;
+  const int S = H.S;
+  const int* chains = tab + H.o_chain;
+  const int* slots = tab + H.o_slot;
+  const int* path = tab + H.o_path;
+  const int* pairs = tab + H.o_pair;
+  const int* mem = tab + H.o_mem;
+  if (part == 0) {
+    if (t >= S * H.npairs) return;
+    const int l = t / H.npairs, q = t % H.npairs;
+    const int* pr = pairs + q * kPairInts;
+    double2 Z[9];
+    for (int e = 0; e < 9; ++e) Z[e] = make_double2(0.0, 0.0);
+    for (int x = pr[PR_FROM]; x <= pr[PR_TO]; ++x) {
+      const double2* zv = z + (size_t)path[pr[PR_PATHOFF] + x] * 9;
+      for (int e = 0; e < 9; ++e) Z[e] = cadd(Z[e], zv[e]);
+    }
+    const double2* a = A + ((size_t)l * n + pr[PR_RNODE]) * 3;
+    double2* o = P + ((size_t)l * H.npairs + q) * 3;
+    for (int r = 0; r < 3; ++r) o[r] = cadd(cadd(cmul(Z[r * 3], a[0]), cmul(Z[r * 3 + 1], a[1])), cmul(Z[r * 3 + 2], a[2]));
+  } else if (part == 1) {
+    if (t >= S * H.nslots * 3) return;
+    const int l = t / (H.nslots * 3), rem = t % (H.nslots * 3), s = rem / 3, p = rem % 3;
+    const int* sr = slots + s * kSlotInts;
+    const int node = sr[SL_NODE];
+    TargetRec rec;
+    rec.W = Vcur[((size_t)l * n + node) * 3 + p];
+    double lo = INFINITY, hi = -INFINITY;
+    if (sr[SL_PHASE] >> p & 1) {
+      const int* off = tab + H.o_smemoff;
+      for (int e = off[s]; e < off[s + 1]; ++e) {
+        const int v = mem[e];
+        const double m = absV[((size_t)l * n + v) * 3 + p];
+        if (m > 0.0) { lo = fmin(lo, m); hi = fmax(hi, m); }
+      }
+    }
+    rec.lo = lo;
+    rec.hi = hi;
+    srec[((size_t)l * H.nslots + s) * 3 + p] = rec;
+  } else if (part == 2) {
+    if (t >= S * H.nchains) return;
+    const int l = t / H.nchains, c = t % H.nchains;
+    const int head = chains[c * kChainInts + C_HEAD];
+    for (int p = 0; p < 3; ++p) headV[((size_t)l * H.nchains + c) * 3 + p] = Vcur[((size_t)l * n + head) * 3 + p];
+  } else if (part == 3) {
+    if (t >= S * H.nz) return;
+    const int l = t / H.nz, q = t % H.nz;
+    const int* ze = tab + H.o_zent + q * 3;
+    const int node = ze[0], p = ze[1];
+    const int* off = tab + H.o_zmemoff;
+    double lo = INFINITY, hi = -INFINITY;
+    for (int e = off[q]; e < off[q + 1]; ++e) {
+      const double m = absV[((size_t)l * n + mem[e]) * 3 + p];
+      lo = fmin(lo, m);
+      hi = fmax(hi, m);
+    }
+    TargetRec rec;
+    rec.W = Vcur[((size_t)l * n + node) * 3 + p];
+    rec.lo = lo;
+    rec.hi = hi;
+    zrec[(size_t)l * H.nz + q] = rec;
+  } else {
+    if (t >= S) return;
+    const int l = t;
+    double e = 0.0;
+    const int* h = tab + H.o_h;
+    for (int q = 0; q < H.nh; ++q) {
+      const int v = h[q * 3], head = h[q * 3 + 1], pm = h[q * 3 + 2];
+      for (int p = 0; p < 3; ++p) {
+        if (!(pm >> p & 1)) continue;
+        const double d = fabs(sqrt(cabs2(Vcur[((size_t)l * n + head) * 3 + p])) - absV[((size_t)l * n + v) * 3 + p]);
+        e = fmax(e, d);
+      }
+    }
+    econst[l] = e;
+  }
+}
+
+// ---------------------------------------------------------------- scoring --
+// Walk one chain for one mask: super-node slots top to bottom; a reduced slot
+// adds the voltage rise of moving its aggregated current to its current super
+// (P from LDS); a kept slot becomes the super of the slots below it.  With
+// ERR, every slot cluster's error against its super's magnitude and the band
+// of kept slots are folded into (el, slack).
+template <bool ERR>
+__device__ __forceinline__ void walk_chain(const int* __restrict__ cr, const int* __restrict__ slots,
+                                           const double2* Ps, const TargetRec* __restrict__ srec_l,
+                                           const double2* __restrict__ headV_l, int c, uint32_t m,
+                                           double2& B0, double2& B1, double2& B2, double& el,
+                                           double& slack, double vmin, double vmax) {
+  double2 S0 = B0, S1 = B1, S2 = B2;
+  double sm0 = 0.0, sm1 = 0.0, sm2 = 0.0;
+  if (ERR) {
+    const double2* hv = headV_l + c * 3;
+    sm0 = cmag(cadd(hv[0], B0));
+    sm1 = cmag(cadd(hv[1], B1));
+    sm2 = cmag(cadd(hv[2], B2));
+  }
+  const int ns = cr[C_NSLOT], s0 = cr[C_SLOT0];
+  int sidx = 0;
+  for (int r = 0; r < ns; ++r) {
+    const int* sr = slots + (s0 + r) * kSlotInts;
+    const int bit = sr[SL_BIT], pb = sr[SL_PAIRBASE];
+    const bool red = (m >> bit) & 1u;
+    const double rf = red ? 1.0 : 0.0;
+    const double2* pp = Ps + (pb + sidx) * 3;
+    const double2 p0 = pp[0], p1 = pp[1], p2 = pp[2];
+    S0.x = fma(rf, p0.x, S0.x); S0.y = fma(rf, p0.y, S0.y);
+    S1.x = fma(rf, p1.x, S1.x); S1.y = fma(rf, p1.y, S1.y);
+    S2.x = fma(rf, p2.x, S2.x); S2.y = fma(rf, p2.y, S2.y);
+    sidx = red ? sidx : r + 1;
+    if (ERR) {
+      const int ph = sr[SL_PHASE];
+      const TargetRec* tr = srec_l + (s0 + r) * 3;
+#define OKR_SLOT_PHASE(P_, S_, SM_)                                              \
+      if (ph & (1 << P_)) {                                                      \
+        const TargetRec t = tr[P_];                                              \
+        const double mag = cmag(cadd(t.W, S_));                                  \
+        SM_ = red ? SM_ : mag;                                                   \
+        const double sk = fmin(mag - vmin, vmax - mag);                          \
+        slack = red ? slack : fmin(slack, sk);                                   \
+        el = fmax(el, fmax(SM_ - t.lo, t.hi - SM_));                             \
+      }
+      OKR_SLOT_PHASE(0, S0, sm0)
+      OKR_SLOT_PHASE(1, S1, sm1)
+      OKR_SLOT_PHASE(2, S2, sm2)
+#undef OKR_SLOT_PHASE
+    }
+  }
+  B0 = S0; B1 = S1; B2 = S2;
+}
+
+// One lane scores one mask over the block's snapshot group: e = max error
+// over the affected nodes, slack = min band slack over their kept node-phases.
+__global__ __launch_bounds__(kScoreBlock) void k_score_fp64(
+    const int* __restrict__ tab, SegHdr H, const double2* __restrict__ P,
+    const TargetRec* __restrict__ srec, const double2* __restrict__ headV,
+    const TargetRec* __restrict__ zrec, const double* __restrict__ econst, int snaps_per_group,
+    double vmin, double vmax, MaskScore* __restrict__ out) {
+  __shared__ double2 Ps[kMaxPairs * 3];
+  const uint32_t m = blockIdx.x * kScoreBlock + threadIdx.x;
+  const int sg = blockIdx.y;
+  const int l0 = sg * snaps_per_group;
+  const int l1 = min(H.S, l0 + snaps_per_group);
+  const int* chains = tab + H.o_chain;
+  const int* slots = tab + H.o_slot;
+  const int* nest = tab + H.o_nest;
+  double e = 0.0, slack = INFINITY;
+  for (int l = l0; l < l1; ++l) {
+    const double2* Pl = P + (size_t)l * H.npairs * 3;
+    for (int q = threadIdx.x; q < H.npairs * 3; q += kScoreBlock) Ps[q] = Pl[q];
+    __syncthreads();
+    const TargetRec* srec_l = srec + (size_t)l * H.nslots * 3;
+    const double2* headV_l = headV + (size_t)l * H.nchains * 3;
+    const TargetRec* zrec_l = zrec + (size_t)l * H.nz;
+    double el = econst[l];
+    for (int c = 0; c < H.nchains; ++c) {
+      const int* cr = chains + c * kChainInts;
+      double2 B0 = make_double2(0.0, 0.0), B1 = B0, B2 = B0;
+      const int nl = cr[C_NEST_LEN], no = cr[C_NEST_OFF];
+      for (int q = 0; q + 1 < nl; ++q) {
+        const int oc = nest[no + q];
+        walk_chain<false>(chains + oc * kChainInts, slots, Ps, srec_l, headV_l, oc, m, B0, B1, B2, el,
+                          slack, vmin, vmax);
+      }
+      walk_chain<true>(cr, slots, Ps, srec_l, headV_l, c, m, B0, B1, B2, el, slack, vmin, vmax);
+#define OKR_ZONE_PHASE(P_, B_)                                                   \
+      for (int q = cr[C_ZOFF0 + P_], qe = q + cr[C_ZCNT0 + P_]; q < qe; ++q) { \
+        const TargetRec t = zrec_l[q];                                           \
+        const double mag = cmag(cadd(t.W, B_));                                  \
+        el = fmax(el, fmax(mag - t.lo, t.hi - mag));                             \
+        slack = fmin(slack, fmin(mag - vmin, vmax - mag));                       \
+      }
+      OKR_ZONE_PHASE(0, B0)
+      OKR_ZONE_PHASE(1, B1)
+      OKR_ZONE_PHASE(2, B2)
+#undef OKR_ZONE_PHASE
+    }
+    e = fmax(e, el);
+    __syncthreads();
+  }
+  const uint32_t nmask = 1u << H.k;
+  if (m < nmask) {
+    MaskScore r;
+    r.e = e;
+    r.slack = slack;
+    out[(size_t)sg * nmask + m] = r;
+  }
+}
+
+// ----------------------------------------------------------------- argmin --
+// Lexicographic selection: most reduced nodes among feasible masks, then the
+// smallest error, masks within tie_tol of that error tie and the lowest wins.
+// Flags the decision ambiguous when a mask at the chosen level or above lies
+// within amb_tol of the e_bar / band boundary, or a feasible mask at the
+// chosen level lies within amb_tol of e_min + tie_tol.
+__global__ __launch_bounds__(1024) void k_argmin(MaskScore* __restrict__ res, int SG, int k, double e_bar,
+                                                 double tie, double amb, DevDecision* __restrict__ dec) {
+  __shared__ double shd[16];
+  __shared__ int shi[16];
+  __shared__ unsigned shu[16];
+  const uint32_t nm = 1u << k;
+  int best = -1;
+  for (uint32_t m = threadIdx.x; m < nm; m += blockDim.x) {
+    double e = res[m].e, s = res[m].slack;
+    for (int g = 1; g < SG; ++g) {
+      const MaskScore r = res[(size_t)g * nm + m];
+      e = fmax(e, r.e);
+      s = fmin(s, r.slack);
+    }
+    res[m].e = e;
+    res[m].slack = s;
+    if (e <= e_bar && s >= 0.0) best = max(best, __popc(m));
+  }
+  best = block_reduce(best, [](int a, int b) { return max(a, b); }, shi);
+  double emin = INFINITY;
+  for (uint32_t m = threadIdx.x; m < nm; m += blockDim.x) {
+    const MaskScore r = res[m];
+    if (r.e <= e_bar && r.slack >= 0.0 && __popc(m) == best) emin = fmin(emin, r.e);
+  }
+  emin = block_reduce(emin, [](double a, double b) { return fmin(a, b); }, shd);
+  unsigned pick = 0xffffffffu;
+  int amb_flag = 0;
+  for (uint32_t m = threadIdx.x; m < nm; m += blockDim.x) {
+    const MaskScore r = res[m];
+    const int pc = __popc(m);
+    const bool feas = r.e <= e_bar && r.slack >= 0.0;
+    if (best >= 0 && pc >= best) {
+      const bool rin = r.e <= e_bar - amb && r.slack >= amb;
+      const bool rout = r.e > e_bar + amb || r.slack < -amb;
+      if (!rin && !rout) amb_flag = 1;
+    }
+    if (feas && pc == best) {
+      if (fabs(r.e - (emin + tie)) <= amb) amb_flag = 1;
+      if (r.e <= emin + tie) pick = min(pick, m);
+    }
+  }
+  pick = block_reduce(pick, [](unsigned a, unsigned b) { return min(a, b); }, shu);
+  amb_flag = block_reduce(amb_flag, [](int a, int b) { return a | b; }, shi);
+  if (threadIdx.x == 0) {
+    DevDecision d;
+    if (best < 0) {
+      d.mask = 0; d.popcount = 0; d.e_loc = res[0].e; d.e_min = res[0].e; d.ambiguous = 1; d.found = 0;
+    } else {
+      d.mask = pick; d.popcount = best; d.e_loc = res[pick].e; d.e_min = emin; d.ambiguous = amb_flag; d.found = 1;
+    }
+    *dec = d;
+  }
+}
+
+// ------------------------------------------------------------ state update --
+// Apply the chosen mask to the cumulative state (Algorithm 1 state update):
+// aggregated currents move to the new super-nodes, kept slots and zone
+// targets take their candidate voltages (same arithmetic as the scoring).
+__global__ __launch_bounds__(64) void k_apply(const int* __restrict__ tab, SegHdr H, int n,
+                                              const DevDecision* __restrict__ dec, const double2* __restrict__ P,
+                                              const TargetRec* __restrict__ srec, const TargetRec* __restrict__ zrec,
+                                              double2* __restrict__ Vcur, double2* __restrict__ A) {
+  __shared__ double2 Bs[kMaxK * 3];
+  const int l = blockIdx.x;
+  const uint32_t m = dec->mask;
+  const int* chains = tab + H.o_chain;
+  const int* slots = tab + H.o_slot;
+  if (threadIdx.x == 0) {
+    const double2* Pl = P + (size_t)l * H.npairs * 3;
+    const TargetRec* srec_l = srec + (size_t)l * H.nslots * 3;
+    for (int c = 0; c < H.nchains; ++c) {
+      const int* cr = chains + c * kChainInts;
+      const int outer = cr[C_OUTER];
+      double2 S[3];
+      for (int p = 0; p < 3; ++p) S[p] = outer >= 0 ? Bs[outer * 3 + p] : make_double2(0.0, 0.0);
+      int sidx = 0, supnode = cr[C_HEAD];
+      const int ns = cr[C_NSLOT], s0 = cr[C_SLOT0];
+      for (int r = 0; r < ns; ++r) {
+        const int* sr = slots + (s0 + r) * kSlotInts;
+        const int node = sr[SL_NODE];
+        if ((m >> sr[SL_BIT]) & 1u) {
+          const double2* pp = Pl + (sr[SL_PAIRBASE] + sidx) * 3;
+          for (int p = 0; p < 3; ++p) {
+            S[p] = cadd(S[p], pp[p]);
+            const size_t a = ((size_t)l * n + supnode) * 3 + p, b = ((size_t)l * n + node) * 3 + p;
+            A[a] = cadd(A[a], A[b]);
+            A[b] = make_double2(0.0, 0.0);
+          }
+        } else {
+          for (int p = 0; p < 3; ++p)
+            if (sr[SL_PHASE] >> p & 1) Vcur[((size_t)l * n + node) * 3 + p] = cadd(srec_l[(s0 + r) * 3 + p].W, S[p]);
+          sidx = r + 1;
+          supnode = node;
+        }
+      }
+      for (int p = 0; p < 3; ++p) Bs[c * 3 + p] = S[p];
+    }
+  }
+  __syncthreads();
+  for (int q = threadIdx.x; q < H.nz; q += blockDim.x) {
+    const int* ze = tab + H.o_zent + q * 3;
+    const int node = ze[0], p = ze[1], c = ze[2];
+    Vcur[((size_t)l * n + node) * 3 + p] = cadd(zrec[(size_t)l * H.nz + q].W, Bs[c * 3 + p]);
+  }
+}
+
+// ---------------------------------------------------------- final outputs --
+// Per-snapshot max error of the final reduction over every node-phase.
+__global__ __launch_bounds__(256) void k_final_err(int n, const uint8_t* __restrict__ phase,
+                                                   const int* __restrict__ sup, const double2* __restrict__ Vcur,
+                                                   const double* __restrict__ absV, double* __restrict__ err) {
+  __shared__ double shd[16];
+  const int l = blockIdx.x;
+  double e = 0.0;
+  for (int i = threadIdx.x; i < n; i += blockDim.x)
+    for (int p = 0; p < 3; ++p) {
+      if (!(phase[i] >> p & 1u)) continue;
+      const double m = sqrt(cabs2(Vcur[((size_t)l * n + sup[i]) * 3 + p]));
+      e = fmax(e, fabs(m - absV[((size_t)l * n + i) * 3 + p]));
+    }
+  e = block_reduce(e, [](double a, double b) { return fmax(a, b); }, shd);
+  if (threadIdx.x == 0) err[l] = e;
+}
+
+// Kron-reduced branch of every kept node: the eliminated path up to its kept
+// parent is a series chain, so y_eq = (sum of z on the path, restricted to
+// the node's phases)^-1 (eq. Y_kron for degree-2 and leaf eliminations).
+__global__ void k_kron_yeq(int n, const int* __restrict__ parent, const uint8_t* __restrict__ phase,
+                           const int* __restrict__ kp, const double2* __restrict__ z, double2* __restrict__ yeq,
+                           double2* __restrict__ Yk_off, int* __restrict__ status) {
+  const int x = blockIdx.x * blockDim.x + threadIdx.x;
+  if (x >= n) return;
+  double2* yo = Yk_off + (size_t)x * 9;
+  double2* ye = yeq + (size_t)x * 9;
+  for (int q = 0; q < 9; ++q) { yo[q] = make_double2(0.0, 0.0); ye[q] = yo[q]; }
+  if (kp[x] < 0) return;
+  const unsigned ph = phase[x];
+  double2 Z[9];
+  for (int q = 0; q < 9; ++q) Z[q] = make_double2(0.0, 0.0);
+  for (int v = x; v != kp[x]; v = parent[v]) {
+    const double2* zv = z + (size_t)v * 9;
+    for (int r = 0; r < 3; ++r)
+      for (int c = 0; c < 3; ++c)
+        if ((ph >> r & 1u) && (ph >> c & 1u)) Z[r * 3 + c] = cadd(Z[r * 3 + c], zv[r * 3 + c]);
+  }
+  if (!inv_restricted(Z, ph, ye)) { atomicOr(status, 1); return; }
+  for (int q = 0; q < 9; ++q) yo[q] = make_double2(-ye[q].x, -ye[q].y);
+}
+
+__global__ void k_kron_diag(int n, const uint8_t* __restrict__ kept, const int* __restrict__ kp,
+                            const int* __restrict__ kc_off, const int* __restrict__ kc,
+                            const double2* __restrict__ yeq, double2* __restrict__ Yk_diag) {
+  const int x = blockIdx.x * blockDim.x + threadIdx.x;
+  if (x >= n) return;
+  double2 D[9];
+  for (int q = 0; q < 9; ++q) D[q] = make_double2(0.0, 0.0);
+  if (kept[x]) {
+    if (kp[x] >= 0)
+      for (int q = 0; q < 9; ++q) D[q] = yeq[(size_t)x * 9 + q];
+    for (int e = kc_off[x]; e < kc_off[x + 1]; ++e)
+      for (int q = 0; q < 9; ++q) D[q] = cadd(D[q], yeq[(size_t)kc[e] * 9 + q]);
+  }
+  for (int q = 0; q < 9; ++q) Yk_diag[(size_t)x * 9 + q] = D[q];
+}
+
+}  // namespace okr
