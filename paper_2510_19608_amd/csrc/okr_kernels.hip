@@ -29,8 +29,10 @@ __device__ __forceinline__ double2 cdiv(double2 a, double2 b) {
   const double2 t = cmul(a, cconj(b));
   return make_double2(t.x / d, t.y / d);
 }
-// |v| with the hardware square root (v_sqrt_f64).
-__device__ __forceinline__ double cmag(double2 a) { return __builtin_amdgcn_sqrt(cabs2(a)); }
+// |v| with the correctly rounded square root (the raw v_sqrt_f64 instruction
+// alone is accurate to only about 2^-27 relative, far outside the 1e-13
+// decision window).
+__device__ __forceinline__ double cmag(double2 a) { return sqrt(cabs2(a)); }
 
 // Restricted inverse of a 3x3 block on the phases in `mask` (zero-padded):
 // for blocks supported on the present-phase principal submatrix this is the

@@ -88,15 +88,20 @@ def test_c1_every_mask_matches_oracle(okr, seed):
     assert (s[~fin] > 1e300).all()
 
 
-@pytest.mark.parametrize("seed,e_bar,vmin", [(1, 3e-4, 0.95), (2, 1e-4, 0.95), (4, 3e-3, 0.996),
-                                             (5, 2e-4, 0.95), (6, 3e-4, 0.9955)])
-def test_multisegment_cumulative_state(okr, seed, e_bar, vmin):
+@pytest.mark.parametrize("seed,e_bar,band", [(1, 3e-4, None), (2, 1e-4, None), (4, 3e-3, 2e-4),
+                                             (5, 2e-4, None), (6, 3e-4, 5e-4), (7, 3e-3, 5e-5)])
+def test_multisegment_cumulative_state(okr, seed, e_bar, band):
     """Small feeders split into several segments: each segment is scored
     against the state the earlier decisions left; every mask of every segment
-    is compared with the oracle at that state."""
-    _say(f"multiseg seed={seed} e_bar={e_bar} vmin={vmin}")
+    is compared with the oracle at that state.  With `band`, v_min sits that
+    far below the lowest full-network voltage so the band binds."""
+    _say(f"multiseg seed={seed} e_bar={e_bar} band={band}")
     f = make_feeder("c1", seed, n=40, n_eligible=None, seg_size=(4, 7), snapshots=3,
-                    scale=(0.3, 1.0), e_bar=e_bar, v_min=vmin)
+                    scale=(0.3, 1.0), e_bar=e_bar)
+    if band is not None:
+        V, _, _, _ = oracle.powerflow(f)
+        pres = np.array([[(int(m) >> p) & 1 for p in range(3)] for m in f["phase"]], bool)
+        f = dict(f, v_min=float(np.abs(V)[:, pres].min()) - band)
     V, I, keep_final, dec, st = oracle_run(f)
     if st == oracle.W_BASE_OUT_OF_BAND:
         pytest.skip("base network outside the band for this seed")
@@ -163,12 +168,13 @@ def test_vhat_given_matches_powerflow_run(okr):
 def test_input_errors_are_reported(okr):
     f = make_feeder("c1", 1)
     g = dict(f, Y_off=f["Y_off"].copy())
-    g["Y_off"][5, 0, 1] += 1e-3  # asymmetric block
+    g["Y_off"][1, 0, 1] += 1e-3  # asymmetric block (node 1 is three-phase)
     with pytest.raises(okr.OkrError) as ei:
         okr.reduce_feeder(g)
     assert ei.value.code == okr.OKR.E_UNSUPPORTED
     g = dict(f, Y_diag=f["Y_diag"].copy())
-    g["Y_diag"][3] += np.eye(3) * 0.5  # a shunt
+    pres = np.array([(int(f["phase"][3]) >> p) & 1 for p in range(3)], float)
+    g["Y_diag"][3] += np.diag(pres) * 0.5  # a shunt on the present phases
     with pytest.raises(okr.OkrError) as ei:
         okr.reduce_feeder(g)
     assert ei.value.code == okr.OKR.E_UNSUPPORTED
