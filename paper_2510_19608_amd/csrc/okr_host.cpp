@@ -25,8 +25,9 @@ __global__ void k_from_vhat(int, int, const uint8_t*, const double2*, const doub
 __global__ void k_seg_fill(const int*, SegHdr, int, const double2*, const double2*, const double2*, const double*,
                            double2*, TargetRec*, double2*, TargetRec*, double*);
 __global__ void k_score_fp64(const int*, SegHdr, const double2*, const TargetRec*, const double2*, const TargetRec*,
-                             const double*, int, double, double, MaskScore*);
-__global__ void k_argmin(MaskScore*, int, int, double, double, double, DevDecision*);
+                             const double*, int, int, SelParams, MaskScore*, MaskScore*, TileRec*, int*);
+__global__ void k_argmin(const MaskScore*, const TileRec*, int, SelParams, DevDecision*);
+__global__ void k_sqrt_selftest(const double*, double*, int);
 __global__ void k_apply(const int*, SegHdr, int, const DevDecision*, const double2*, const TargetRec*,
                         const TargetRec*, double2*, double2*);
 __global__ void k_final_err(int, const uint8_t*, const int*, const double2*, const double*, double*);
@@ -41,8 +42,8 @@ namespace {
 constexpr int kMaxSnapGroups = 32;
 
 struct Layout {
-  size_t z, Vhat, Vcur, A, J, absV, status, iters, topo, tab, P, srec, headV, zrec, econst, res, dec, fin_int,
-      yeq, Ykd, Yko, err, total;
+  size_t z, Vhat, Vcur, A, J, absV, status, iters, topo, tab, P, srec, headV, zrec, econst, res, fin, tiles,
+      tickets, dec, fin_int, yeq, Ykd, Yko, err, total;
 };
 
 size_t align256(size_t x) { return (x + 255) & ~size_t(255); }
@@ -243,6 +244,12 @@ extern "C" int okr_plan(okr_handle* h, const okr_topology* topo, const okr_margi
       most = std::max(most, (size_t)snap_groups(k, S, &spg) << k);
     }
     L.res = take(sizeof(MaskScore) * most);
+  }
+  {
+    const size_t nm = (size_t)1 << h->kmax, nt = (nm + 63) / 64;
+    L.fin = take(sizeof(MaskScore) * nm);
+    L.tiles = take(sizeof(TileRec) * nt);
+    L.tickets = take(sizeof(int) * nt);
   }
   L.dec = take(sizeof(DevDecision) + 64);
   L.fin_int = take(sizeof(int) * (size_t)(4 * n + 1) + n);
@@ -646,6 +653,9 @@ extern "C" int okr_reduce_feeder(okr_handle* h, const okr_yblocks* Y, const okr_
   TargetRec* zrec = (TargetRec*)dptr(L.zrec);
   double* econst = (double*)dptr(L.econst);
   MaskScore* res = (MaskScore*)dptr(L.res);
+  MaskScore* mfin = (MaskScore*)dptr(L.fin);
+  TileRec* tiles = (TileRec*)dptr(L.tiles);
+  int* tickets = (int*)dptr(L.tickets);
   DevDecision* ddec = (DevDecision*)dptr(L.dec);
   int* fin = (int*)dptr(L.fin_int);
   double2* yeq = (double2*)dptr(L.yeq);
@@ -678,6 +688,7 @@ extern "C" int okr_reduce_feeder(okr_handle* h, const okr_yblocks* Y, const okr_
   const int o_ph = o; std::memcpy(ht + o, h->phase.data(), n); o += (n + 3) / 4;
   OKR_HIP(h, hipMemcpyAsync(dtopo, ht, sizeof(int) * o, hipMemcpyHostToDevice, st));
   OKR_HIP(h, hipMemsetAsync(status, 0, 64, st));
+  OKR_HIP(h, hipMemsetAsync(tickets, 0, sizeof(int) * ((((size_t)1 << h->kmax) + 63) / 64), st));
   const int* d_par = dtopo + o_par;
   const int* d_choff = dtopo + o_choff;
   const int* d_ch = dtopo + o_ch;
@@ -728,6 +739,12 @@ extern "C" int okr_reduce_feeder(okr_handle* h, const okr_yblocks* Y, const okr_
   out->n_score_launches = 0;
   out->warnings = base_out ? OKR_W_BASE_OUT_OF_BAND : 0;
   SegBuild B;
+  SelParams sp;
+  sp.e_bar = mg->e_bar;
+  sp.vmin = mg->v_min;
+  sp.vmax = mg->v_max;
+  sp.tie = mg->tie_tol;
+  sp.amb = mg->amb_tol;
   for (int g = 0; g < h->nseg; ++g) {
     okr_segment_result& R = out->seg[g];
     std::memset(&R, 0, sizeof R);
@@ -754,10 +771,10 @@ extern "C" int okr_reduce_feeder(okr_handle* h, const okr_yblocks* Y, const okr_
     const int SG = snap_groups(H.k, S, &spg);
     if (timing) OKR_HIP(h, hipEventRecord(h->ev0, st));
     hipLaunchKernelGGL(k_score_fp64, dim3(mblocks, SG), dim3(kScoreBlock), 0, st, dtab, H, P, srec, headV, zrec,
-                       econst, spg, mg->v_min, mg->v_max, res);
+                       econst, spg, SG, sp, res, mfin, tiles, tickets);
     OKR_HIP(h, hipGetLastError());
     if (timing) OKR_HIP(h, hipEventRecord(h->ev1, st));
-    hipLaunchKernelGGL(k_argmin, dim3(1), dim3(1024), 0, st, res, SG, H.k, mg->e_bar, mg->tie_tol, mg->amb_tol, ddec);
+    hipLaunchKernelGGL(k_argmin, dim3(1), dim3(1024), 0, st, mfin, tiles, H.k, sp, ddec);
     OKR_HIP(h, hipGetLastError());
     hipLaunchKernelGGL(k_apply, dim3(S), dim3(64), 0, st, dtab, H, n, ddec, P, srec, zrec, Vcur, A);
     OKR_HIP(h, hipGetLastError());
@@ -767,7 +784,7 @@ extern "C" int okr_reduce_feeder(okr_handle* h, const okr_yblocks* Y, const okr_
       h->dump_s[g].resize(nmask);
       h->dump_k[g] = H.k;
       std::vector<MaskScore> tmp(nmask);
-      OKR_HIP(h, hipMemcpyAsync(tmp.data(), res, sizeof(MaskScore) * nmask, hipMemcpyDeviceToHost, st));
+      OKR_HIP(h, hipMemcpyAsync(tmp.data(), mfin, sizeof(MaskScore) * nmask, hipMemcpyDeviceToHost, st));
       OKR_HIP(h, hipStreamSynchronize(st));
       for (uint32_t m = 0; m < nmask; ++m) { h->dump_e[g][m] = tmp[m].e; h->dump_s[g][m] = tmp[m].slack; }
     }
@@ -873,4 +890,12 @@ extern "C" int okr_dump_scores(okr_handle* h, int32_t segment, double* e, double
   if (slack) std::memcpy(slack, h->dump_s[segment].data(), sizeof(double) * nm);
   if (k) *k = h->dump_k[segment];
   return OKR_OK;
+}
+
+// Self-test of the scoring kernel's square root (device pointers, n values).
+extern "C" int okr_selftest_sqrt(const double* d_x, double* d_y, int n, void* stream) {
+  if (!d_x || !d_y || n < 0) return OKR_E_ARG;
+  hipLaunchKernelGGL(k_sqrt_selftest, dim3((n + 255) / 256), dim3(256), 0, static_cast<hipStream_t>(stream), d_x,
+                     d_y, n);
+  return hipGetLastError() == hipSuccess ? OKR_OK : OKR_E_HIP;
 }

@@ -66,4 +66,18 @@ struct MaskScore {
   double slack;
 };
 
+// Per-tile (64 consecutive masks) summary written by the last scoring block
+// of the tile: best feasible level, smallest error at that level, highest
+// level of a near-boundary mask.
+struct TileRec {
+  int32_t best;   // max popcount of a feasible mask, -1 if none
+  int32_t near;   // max popcount of a mask near the e_bar / band boundary, -1 if none
+  double emin;    // min error among feasible masks at `best`
+};
+
+// Selection parameters shared by the scoring epilogue and the arg-min.
+struct SelParams {
+  double e_bar, vmin, vmax, tie, amb;
+};
+
 }  // namespace okr

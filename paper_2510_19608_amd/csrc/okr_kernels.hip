@@ -29,10 +29,9 @@ __device__ __forceinline__ double2 cdiv(double2 a, double2 b) {
   const double2 t = cmul(a, cconj(b));
   return make_double2(t.x / d, t.y / d);
 }
-// |v| with the correctly rounded square root (the raw v_sqrt_f64 instruction
-// alone is accurate to only about 2^-27 relative, far outside the 1e-13
-// decision window).
-__device__ __forceinline__ double cmag(double2 a) { return sqrt(cabs2(a)); }
+// Note: the bare v_sqrt_f64 instruction is accurate to only about 2^-27
+// relative, far outside the 1e-13 decision window; magnitudes in the scoring
+// use sqrt_nr() below, elsewhere the libm sqrt.
 
 // Restricted inverse of a 3x3 block on the phases in `mask` (zero-padded):
 // for blocks supported on the present-phase principal submatrix this is the
@@ -333,24 +332,41 @@ __global__ void k_seg_fill(const int* __restrict__ tab, SegHdr H, int n, const d
 }
 
 // ---------------------------------------------------------------- scoring --
+// sqrt for arguments in the normal range (here |V|^2 of a bus voltage): the
+// hardware reciprocal-square-root estimate refined by Newton-Raphson steps in
+// Goldschmidt form (g -> sqrt(x), h -> 1/(2 sqrt(x))), two residual
+// corrections at the end.  No range scaling: callers pass x in [2^-500, 2^500].
+__device__ __forceinline__ double sqrt_nr(double x) {
+  const double r = __builtin_amdgcn_rsq(x);
+  double g = x * r, h = 0.5 * r;
+  const double e = fma(-h, g, 0.5);
+  g = fma(g, e, g);
+  h = fma(h, e, h);
+  double d = fma(-g, g, x);
+  g = fma(d, h, g);
+  d = fma(-g, g, x);
+  return fma(d, h, g);
+}
+__device__ __forceinline__ double vmag(double2 a) { return sqrt_nr(a.x * a.x + a.y * a.y); }
+
 // Walk one chain for one mask: super-node slots top to bottom; a reduced slot
 // adds the voltage rise of moving its aggregated current to its current super
 // (P from LDS); a kept slot becomes the super of the slots below it.  With
 // ERR, every slot cluster's error against its super's magnitude and the band
-// of kept slots are folded into (el, slack).
+// of kept slots are folded into (el, slack).  Slot records and head voltages
+// of the snapshot come from LDS.
 template <bool ERR>
 __device__ __forceinline__ void walk_chain(const int* __restrict__ cr, const int* __restrict__ slots,
-                                           const double2* Ps, const TargetRec* __restrict__ srec_l,
-                                           const double2* __restrict__ headV_l, int c, uint32_t m,
-                                           double2& B0, double2& B1, double2& B2, double& el,
+                                           const double2* Ps, const TargetRec* Ss, const double2* Hs, int c,
+                                           uint32_t m, double2& B0, double2& B1, double2& B2, double& el,
                                            double& slack, double vmin, double vmax) {
   double2 S0 = B0, S1 = B1, S2 = B2;
   double sm0 = 0.0, sm1 = 0.0, sm2 = 0.0;
   if (ERR) {
-    const double2* hv = headV_l + c * 3;
-    sm0 = cmag(cadd(hv[0], B0));
-    sm1 = cmag(cadd(hv[1], B1));
-    sm2 = cmag(cadd(hv[2], B2));
+    const double2* hv = Hs + c * 3;
+    sm0 = vmag(cadd(hv[0], B0));
+    sm1 = vmag(cadd(hv[1], B1));
+    sm2 = vmag(cadd(hv[2], B2));
   }
   const int ns = cr[C_NSLOT], s0 = cr[C_SLOT0];
   int sidx = 0;
@@ -367,11 +383,11 @@ __device__ __forceinline__ void walk_chain(const int* __restrict__ cr, const int
     sidx = red ? sidx : r + 1;
     if (ERR) {
       const int ph = sr[SL_PHASE];
-      const TargetRec* tr = srec_l + (s0 + r) * 3;
+      const TargetRec* tr = Ss + (s0 + r) * 3;
 #define OKR_SLOT_PHASE(P_, S_, SM_)                                              \
       if (ph & (1 << P_)) {                                                      \
         const TargetRec t = tr[P_];                                              \
-        const double mag = cmag(cadd(t.W, S_));                                  \
+        const double mag = vmag(cadd(t.W, S_));                                  \
         SM_ = red ? SM_ : mag;                                                   \
         const double sk = fmin(mag - vmin, vmax - mag);                          \
         slack = red ? slack : fmin(slack, sk);                                   \
@@ -386,14 +402,27 @@ __device__ __forceinline__ void walk_chain(const int* __restrict__ cr, const int
   B0 = S0; B1 = S1; B2 = S2;
 }
 
+__device__ __forceinline__ bool feasible(const MaskScore& r, double e_bar) { return r.e <= e_bar && r.slack >= 0.0; }
+__device__ __forceinline__ bool near_boundary(const MaskScore& r, double e_bar, double amb) {
+  const bool rin = r.e <= e_bar - amb && r.slack >= amb;
+  const bool rout = r.e > e_bar + amb || r.slack < -amb;
+  return !rin && !rout;
+}
+
 // One lane scores one mask over the block's snapshot group: e = max error
 // over the affected nodes, slack = min band slack over their kept node-phases.
+// The last block of a 64-mask tile to finish (ticket counter) folds the
+// snapshot groups into the final per-mask score and writes the tile record.
 __global__ __launch_bounds__(kScoreBlock) void k_score_fp64(
     const int* __restrict__ tab, SegHdr H, const double2* __restrict__ P,
     const TargetRec* __restrict__ srec, const double2* __restrict__ headV,
-    const TargetRec* __restrict__ zrec, const double* __restrict__ econst, int snaps_per_group,
-    double vmin, double vmax, MaskScore* __restrict__ out) {
+    const TargetRec* __restrict__ zrec, const double* __restrict__ econst, int snaps_per_group, int SG,
+    SelParams sp, MaskScore* __restrict__ part, MaskScore* __restrict__ fin, TileRec* __restrict__ tiles,
+    int* __restrict__ tickets) {
   __shared__ double2 Ps[kMaxPairs * 3];
+  __shared__ TargetRec Ss[kMaxK * 3];
+  __shared__ double2 Hs[kMaxK * 3];
+  __shared__ int ticket;
   const uint32_t m = blockIdx.x * kScoreBlock + threadIdx.x;
   const int sg = blockIdx.y;
   const int l0 = sg * snaps_per_group;
@@ -401,13 +430,16 @@ __global__ __launch_bounds__(kScoreBlock) void k_score_fp64(
   const int* chains = tab + H.o_chain;
   const int* slots = tab + H.o_slot;
   const int* nest = tab + H.o_nest;
+  const double vmin = sp.vmin, vmax = sp.vmax;
   double e = 0.0, slack = INFINITY;
   for (int l = l0; l < l1; ++l) {
     const double2* Pl = P + (size_t)l * H.npairs * 3;
     for (int q = threadIdx.x; q < H.npairs * 3; q += kScoreBlock) Ps[q] = Pl[q];
+    const TargetRec* Sl = srec + (size_t)l * H.nslots * 3;
+    for (int q = threadIdx.x; q < H.nslots * 3; q += kScoreBlock) Ss[q] = Sl[q];
+    const double2* Hl = headV + (size_t)l * H.nchains * 3;
+    for (int q = threadIdx.x; q < H.nchains * 3; q += kScoreBlock) Hs[q] = Hl[q];
     __syncthreads();
-    const TargetRec* srec_l = srec + (size_t)l * H.nslots * 3;
-    const double2* headV_l = headV + (size_t)l * H.nchains * 3;
     const TargetRec* zrec_l = zrec + (size_t)l * H.nz;
     double el = econst[l];
     for (int c = 0; c < H.nchains; ++c) {
@@ -416,14 +448,13 @@ __global__ __launch_bounds__(kScoreBlock) void k_score_fp64(
       const int nl = cr[C_NEST_LEN], no = cr[C_NEST_OFF];
       for (int q = 0; q + 1 < nl; ++q) {
         const int oc = nest[no + q];
-        walk_chain<false>(chains + oc * kChainInts, slots, Ps, srec_l, headV_l, oc, m, B0, B1, B2, el,
-                          slack, vmin, vmax);
+        walk_chain<false>(chains + oc * kChainInts, slots, Ps, Ss, Hs, oc, m, B0, B1, B2, el, slack, vmin, vmax);
       }
-      walk_chain<true>(cr, slots, Ps, srec_l, headV_l, c, m, B0, B1, B2, el, slack, vmin, vmax);
+      walk_chain<true>(cr, slots, Ps, Ss, Hs, c, m, B0, B1, B2, el, slack, vmin, vmax);
 #define OKR_ZONE_PHASE(P_, B_)                                                   \
       for (int q = cr[C_ZOFF0 + P_], qe = q + cr[C_ZCNT0 + P_]; q < qe; ++q) { \
         const TargetRec t = zrec_l[q];                                           \
-        const double mag = cmag(cadd(t.W, B_));                                  \
+        const double mag = vmag(cadd(t.W, B_));                                  \
         el = fmax(el, fmax(mag - t.lo, t.hi - mag));                             \
         slack = fmin(slack, fmin(mag - vmin, vmax - mag));                       \
       }
@@ -436,72 +467,117 @@ __global__ __launch_bounds__(kScoreBlock) void k_score_fp64(
     __syncthreads();
   }
   const uint32_t nmask = 1u << H.k;
-  if (m < nmask) {
+  const bool valid = m < nmask;
+  if (valid) {
     MaskScore r;
     r.e = e;
     r.slack = slack;
-    out[(size_t)sg * nmask + m] = r;
+    part[(size_t)sg * nmask + m] = r;
+  }
+  __threadfence();
+  if (threadIdx.x == 0) ticket = atomicAdd(&tickets[blockIdx.x], 1);
+  __syncthreads();
+  if (ticket != SG - 1) return;
+  // last block of this tile: combine the snapshot groups
+  MaskScore r;
+  r.e = 0.0;
+  r.slack = INFINITY;
+  if (valid) {
+    for (int g = 0; g < SG; ++g) {
+      const volatile MaskScore* q = part + (size_t)g * nmask + m;
+      r.e = fmax(r.e, q->e);
+      r.slack = fmin(r.slack, q->slack);
+    }
+    fin[m] = r;
+  }
+  const int pc = __popc(m);
+  const bool feas = valid && feasible(r, sp.e_bar);
+  int best = feas ? pc : -1;
+  int nearl = (valid && near_boundary(r, sp.e_bar, sp.amb)) ? pc : -1;
+  for (int o = 32; o > 0; o >>= 1) {
+    best = max(best, __shfl_xor(best, o, 64));
+    nearl = max(nearl, __shfl_xor(nearl, o, 64));
+  }
+  double em = (feas && pc == best) ? r.e : INFINITY;
+  for (int o = 32; o > 0; o >>= 1) em = fmin(em, __shfl_xor(em, o, 64));
+  if (threadIdx.x == 0) {
+    TileRec t;
+    t.best = best;
+    t.near = nearl;
+    t.emin = em;
+    tiles[blockIdx.x] = t;
+    tickets[blockIdx.x] = 0;  // ready for the next launch
   }
 }
 
 // ----------------------------------------------------------------- argmin --
-// Lexicographic selection: most reduced nodes among feasible masks, then the
-// smallest error, masks within tie_tol of that error tie and the lowest wins.
-// Flags the decision ambiguous when a mask at the chosen level or above lies
-// within amb_tol of the e_bar / band boundary, or a feasible mask at the
-// chosen level lies within amb_tol of e_min + tie_tol.
-__global__ __launch_bounds__(1024) void k_argmin(MaskScore* __restrict__ res, int SG, int k, double e_bar,
-                                                 double tie, double amb, DevDecision* __restrict__ dec) {
+// Lexicographic selection over the tile records: most reduced nodes among
+// feasible masks, then the smallest error, masks within tie_tol of that error
+// tie and the lowest wins.  Only tiles whose record can hold the winner (or a
+// mask within amb of the tie threshold) are rescanned mask by mask.
+// Ambiguous when a mask at the chosen level or above lies within amb of the
+// e_bar / band boundary, or a feasible mask at the chosen level lies within
+// amb of e_min + tie_tol.
+__global__ __launch_bounds__(1024) void k_argmin(const MaskScore* __restrict__ fin, const TileRec* __restrict__ tiles,
+                                                 int k, SelParams sp, DevDecision* __restrict__ dec) {
   __shared__ double shd[16];
   __shared__ int shi[16];
   __shared__ unsigned shu[16];
+  __shared__ int ncand;
+  __shared__ int cand[1024];
   const uint32_t nm = 1u << k;
+  const int ntiles = (int)((nm + 63) / 64);
   int best = -1;
-  for (uint32_t m = threadIdx.x; m < nm; m += blockDim.x) {
-    double e = res[m].e, s = res[m].slack;
-    for (int g = 1; g < SG; ++g) {
-      const MaskScore r = res[(size_t)g * nm + m];
-      e = fmax(e, r.e);
-      s = fmin(s, r.slack);
-    }
-    res[m].e = e;
-    res[m].slack = s;
-    if (e <= e_bar && s >= 0.0) best = max(best, __popc(m));
-  }
+  for (int t = threadIdx.x; t < ntiles; t += blockDim.x) best = max(best, tiles[t].best);
   best = block_reduce(best, [](int a, int b) { return max(a, b); }, shi);
   double emin = INFINITY;
-  for (uint32_t m = threadIdx.x; m < nm; m += blockDim.x) {
-    const MaskScore r = res[m];
-    if (r.e <= e_bar && r.slack >= 0.0 && __popc(m) == best) emin = fmin(emin, r.e);
+  int amb = 0;
+  for (int t = threadIdx.x; t < ntiles; t += blockDim.x) {
+    const TileRec r = tiles[t];
+    if (best >= 0 && r.best == best) emin = fmin(emin, r.emin);
+    if (best >= 0 && r.near >= best) amb = 1;
   }
   emin = block_reduce(emin, [](double a, double b) { return fmin(a, b); }, shd);
   unsigned pick = 0xffffffffu;
-  int amb_flag = 0;
-  for (uint32_t m = threadIdx.x; m < nm; m += blockDim.x) {
-    const MaskScore r = res[m];
-    const int pc = __popc(m);
-    const bool feas = r.e <= e_bar && r.slack >= 0.0;
-    if (best >= 0 && pc >= best) {
-      const bool rin = r.e <= e_bar - amb && r.slack >= amb;
-      const bool rout = r.e > e_bar + amb || r.slack < -amb;
-      if (!rin && !rout) amb_flag = 1;
+  const double thr = emin + sp.tie;
+  // candidate tiles, processed in chunks of 1024 tiles
+  for (int base = 0; base < ntiles && best >= 0; base += 1024) {
+    if (threadIdx.x == 0) ncand = 0;
+    __syncthreads();
+    const int t = base + threadIdx.x;
+    if (t < ntiles) {
+      const TileRec r = tiles[t];
+      if (r.best == best && r.emin <= thr + sp.amb) cand[atomicAdd(&ncand, 1)] = t;
     }
-    if (feas && pc == best) {
-      if (fabs(r.e - (emin + tie)) <= amb) amb_flag = 1;
-      if (r.e <= emin + tie) pick = min(pick, m);
+    __syncthreads();
+    const int nc = ncand;
+    for (int q = threadIdx.x; q < nc * 64; q += blockDim.x) {
+      const uint32_t mm = (uint32_t)cand[q >> 6] * 64 + (q & 63);
+      if (mm >= nm) continue;
+      const MaskScore r = fin[mm];
+      if (__popc(mm) != best || !feasible(r, sp.e_bar)) continue;
+      if (fabs(r.e - thr) <= sp.amb) amb = 1;
+      if (r.e <= thr) pick = min(pick, mm);
     }
+    __syncthreads();
   }
   pick = block_reduce(pick, [](unsigned a, unsigned b) { return min(a, b); }, shu);
-  amb_flag = block_reduce(amb_flag, [](int a, int b) { return a | b; }, shi);
+  amb = block_reduce(amb, [](int a, int b) { return a | b; }, shi);
   if (threadIdx.x == 0) {
     DevDecision d;
     if (best < 0) {
-      d.mask = 0; d.popcount = 0; d.e_loc = res[0].e; d.e_min = res[0].e; d.ambiguous = 1; d.found = 0;
+      d.mask = 0; d.popcount = 0; d.e_loc = fin[0].e; d.e_min = fin[0].e; d.ambiguous = 1; d.found = 0;
     } else {
-      d.mask = pick; d.popcount = best; d.e_loc = res[pick].e; d.e_min = emin; d.ambiguous = amb_flag; d.found = 1;
+      d.mask = pick; d.popcount = best; d.e_loc = fin[pick].e; d.e_min = emin; d.ambiguous = amb; d.found = 1;
     }
     *dec = d;
   }
+}
+
+// Self-test hook: sqrt_nr on an array (host compares with the libm result).
+__global__ void k_sqrt_selftest(const double* __restrict__ x, double* __restrict__ y, int n) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) y[i] = sqrt_nr(x[i]);
 }
 
 // ------------------------------------------------------------ state update --

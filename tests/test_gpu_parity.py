@@ -182,3 +182,24 @@ def test_input_errors_are_reported(okr):
     with pytest.raises(okr.OkrError) as ei:
         okr.reduce_feeder(g)
     assert ei.value.code == okr.OKR.E_PF_DIVERGED
+
+
+def test_scoring_sqrt_is_correctly_rounded(okr):
+    """The scoring kernel's square root (rsq seed + Newton-Raphson) against
+    libm on |V|^2-range arguments and a wide range: at most 1 ulp, exact for
+    nearly all."""
+    import ctypes
+    import torch
+    rng = np.random.default_rng(0)
+    x = np.concatenate([rng.uniform(0.5, 1.5, 500_000), np.exp(rng.uniform(-40, 40, 100_000))])
+    dx = torch.from_numpy(x).cuda()
+    dy = torch.empty_like(dx)
+    L = okr.lib()
+    L.okr_selftest_sqrt.argtypes = [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int, ctypes.c_void_p]
+    assert L.okr_selftest_sqrt(dx.data_ptr(), dy.data_ptr(), len(x), None) == 0
+    torch.cuda.synchronize()
+    y = dy.cpu().numpy()
+    ref = np.sqrt(x)
+    ulp = np.abs(y - ref) / np.spacing(ref)
+    assert ulp.max() <= 1.0
+    assert (ulp == 0).mean() > 0.999
