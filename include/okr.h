@@ -72,8 +72,12 @@ extern "C" {
 
 #define OKR_FLAG_TIMING 1u     /* record per-kernel HIP-event timings */
 #define OKR_FLAG_VHAT_GIVEN 2u /* loads->Vhat holds the scenario voltages */
-#define OKR_FLAG_DUMP_SCORES 4u /* keep every mask's (e, slack) of the last
-                                   scored segment for okr_dump_scores() */
+#define OKR_FLAG_DUMP_SCORES 4u /* keep every segment's per-mask (e, slack) for
+                                   okr_dump_scores() */
+#define OKR_FLAG_GRAPH 8u      /* capture the whole search (load flow, every
+                                  segment, final outputs) as one hipGraph on
+                                  the first call and replay it afterwards;
+                                  ignored with TIMING or DUMP_SCORES */
 
 typedef struct okr_handle okr_handle;
 
@@ -177,8 +181,8 @@ int okr_reduce_feeder(okr_handle *h, const okr_yblocks *Y, const okr_topology *t
                       const okr_loads *loads, const okr_margins *mg,
                       void *d_workspace, size_t workspace_bytes, okr_result *out);
 
-/* With OKR_FLAG_DUMP_SCORES: copy the last scored segment's per-mask error
- * and band slack (HOST double[2^k] each) and return k through *k. */
+/* With OKR_FLAG_DUMP_SCORES: copy segment `segment`'s per-mask error and band
+ * slack from the last call (HOST double[2^k] each) and return k through *k. */
 int okr_dump_scores(okr_handle *h, int32_t segment, double *e, double *slack, int32_t *k);
 
 int okr_destroy(okr_handle *h);

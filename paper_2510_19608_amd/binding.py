@@ -32,6 +32,7 @@ class OKR:
     FLAG_TIMING = 1
     FLAG_VHAT_GIVEN = 2
     FLAG_DUMP_SCORES = 4
+    FLAG_GRAPH = 8
 
 
 class OkrError(RuntimeError):
@@ -158,10 +159,11 @@ def okr_destroy(h):
 # ---- conveniences ----------------------------------------------------------
 
 def make_margins(f=None, *, e_bar=None, v_min=None, v_max=None, tie_tol=1e-11, amb_tol=1e-13,
-                 precision="fp64", timing=False, dump=False, vhat_given=False, pf_tol=1e-13, pf_maxit=100):
+                 precision="fp64", timing=False, dump=False, vhat_given=False, graph=False, pf_tol=1e-13,
+                 pf_maxit=100):
     f = f or {}
     flags = (OKR.FLAG_TIMING if timing else 0) | (OKR.FLAG_DUMP_SCORES if dump else 0) | \
-            (OKR.FLAG_VHAT_GIVEN if vhat_given else 0)
+            (OKR.FLAG_VHAT_GIVEN if vhat_given else 0) | (OKR.FLAG_GRAPH if graph else 0)
     return Margins(e_bar=f.get("e_bar", 0.003) if e_bar is None else e_bar,
                    v_min=f.get("v_min", 0.95) if v_min is None else v_min,
                    v_max=f.get("v_max", 1.05) if v_max is None else v_max,

@@ -1,0 +1,399 @@
+// Device-side construction of one segment's tables from the cumulative kept
+// state (no host round trip between segments).
+//
+//   k_build_struct  (1 block)  chains, slots, pairs, nesting, Omega ranges,
+//                              zone entries grouped by (chain, phase)
+//   k_build_values  (grid)     P = Z(super -> reduced) A, record voltages,
+//                              min/max initialisation
+//   k_build_members (grid)     cluster min/max |V^| and the constant error of
+//                              clusters whose super-node is outside Omega_g
+//
+// The tables have the layout the scoring kernel reads (okr_internal.h).
+#include <hip/hip_runtime.h>
+#include <math.h>
+#include <stdint.h>
+
+#include "okr_internal.h"
+
+namespace okr {
+
+__device__ __forceinline__ double2 b_cadd(double2 a, double2 b) { return make_double2(a.x + b.x, a.y + b.y); }
+__device__ __forceinline__ double2 b_cmul(double2 a, double2 b) {
+  return make_double2(a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x);
+}
+
+// status bit set when a structural invariant fails (the segment is then
+// skipped by the scoring path and the call reports an error)
+constexpr int kStatusBuild = 64;
+
+__global__ __launch_bounds__(256) void k_build_struct(Topo T, State St, int g, int S, SegHdr* __restrict__ hdrs,
+                                                      int* __restrict__ tab, int tab_cap, int* __restrict__ status) {
+  __shared__ int s_top[kMaxK], s_tops[kMaxK], s_slotnode[kMaxK], s_slotbit[kMaxK], s_slotchain[kMaxK];
+  __shared__ int s_cslot0[kMaxK + 1], s_head[kMaxK], s_outer[kMaxK], s_pathpos[kMaxK];
+  __shared__ int s_rs[kMaxK], s_re[kMaxK], s_rcum[kMaxK + 1];
+  __shared__ int s_keycnt[kMaxK * 3], s_keyoff[kMaxK * 3], s_keycur[kMaxK * 3];
+  __shared__ SegHdr s_h;
+  __shared__ int s_err;
+  const int* parent = T.parent;
+  const int* segment = T.segment;
+  if (threadIdx.x == 0) {
+    // an earlier segment failed: leave every later one invalid (its scratch
+    // maps may be stale)
+    int err = (*status & kStatusBuild) ? 1 : 0;
+    SegHdr H;
+    for (int q = 0; q < (int)(sizeof(SegHdr) / sizeof(int)); ++q) ((int*)&H)[q] = 0;
+    const int o0 = T.seg_off[g];
+    const int k = T.seg_off[g + 1] - o0;
+    if (k < 1 || k > kMaxK) err = 1;
+    H.g = g;
+    H.k = k;
+    H.S = S;
+    // chain tops: highest node above e reachable through segment or reduced nodes
+    int nch = 0;
+    for (int j = 0; j < k && !err; ++j) {
+      int c = T.seg_nodes[o0 + j];
+      while (parent[c] >= 0 && (segment[parent[c]] == g || !St.kept[parent[c]])) c = parent[c];
+      s_top[j] = c;
+      bool seen = false;
+      for (int q = 0; q < nch; ++q) seen |= (s_tops[q] == c);
+      if (!seen) s_tops[nch++] = c;
+    }
+    // chains in preorder of their tops
+    for (int a = 1; a < nch; ++a) {
+      const int v = s_tops[a];
+      int b = a - 1;
+      while (b >= 0 && T.pos[s_tops[b]] > T.pos[v]) { s_tops[b + 1] = s_tops[b]; --b; }
+      s_tops[b + 1] = v;
+    }
+    // slots chain by chain, top to bottom (segment nodes are in preorder)
+    int ns = 0;
+    for (int c = 0; c < nch && !err; ++c) {
+      s_cslot0[c] = ns;
+      for (int j = 0; j < k; ++j)
+        if (s_top[j] == s_tops[c]) {
+          s_slotnode[ns] = T.seg_nodes[o0 + j];
+          s_slotbit[ns] = j;
+          s_slotchain[ns] = c;
+          ++ns;
+        }
+      s_head[c] = parent[s_tops[c]];
+    }
+    s_cslot0[nch] = ns;
+    if (ns != k) err = 1;
+    // outer chain: the chain whose bottom slot is the first segment node above the head
+    for (int c = 0; c < nch && !err; ++c) {
+      int u = s_head[c];
+      while (u >= 0 && segment[u] != g) u = parent[u];
+      s_outer[c] = -1;
+      if (u >= 0) {
+        int s = -1;
+        for (int q = 0; q < ns; ++q)
+          if (s_slotnode[q] == u) s = q;
+        if (s < 0) { err = 1; break; }
+        const int oc = s_slotchain[s];
+        if (s != s_cslot0[oc + 1] - 1 || oc >= c) { err = 1; break; }
+        s_outer[c] = oc;
+      }
+    }
+    // table layout
+    int o = 0;
+    H.o_chain = o; o += nch * kChainInts;
+    H.o_nest = o;
+    if (o + nch * nch > tab_cap) err = 1;
+    int nest_off[kMaxK], nest_len[kMaxK];
+    for (int c = 0; c < nch && !err; ++c) {
+      int d = 0;
+      for (int x = c; x >= 0; x = s_outer[x]) ++d;
+      nest_off[c] = o - H.o_nest;
+      nest_len[c] = d;
+      int q = d - 1;
+      for (int x = c; x >= 0; x = s_outer[x]) tab[o + q--] = x;
+      o += d;
+    }
+    H.o_path = o;
+    int path_off[kMaxK], path_len[kMaxK];
+    for (int c = 0; c < nch && !err; ++c) {
+      const int bottom = s_slotnode[s_cslot0[c + 1] - 1];
+      int len = 1;
+      for (int v = bottom; v != s_tops[c] && v >= 0; v = parent[v]) ++len;
+      if (o + len > tab_cap || len > T.n) { err = 1; break; }
+      path_off[c] = o - H.o_path;
+      path_len[c] = len;
+      int q = len - 1, sl = s_cslot0[c + 1] - 1;
+      for (int v = bottom; v >= 0 && q >= 0; v = parent[v]) {
+        tab[o + q] = v;
+        if (sl >= s_cslot0[c] && s_slotnode[sl] == v) s_pathpos[sl--] = q;
+        if (v == s_tops[c]) break;
+        --q;
+      }
+      if (sl >= s_cslot0[c]) err = 1;
+      o += len;
+    }
+    H.o_slot = o; o += ns * kSlotInts;
+    H.o_pair = o;
+    int npairs = 0, pairbase[kMaxK];
+    for (int c = 0; c < nch && !err; ++c)
+      for (int s = s_cslot0[c]; s < s_cslot0[c + 1]; ++s) {
+        const int r = s - s_cslot0[c];
+        pairbase[s] = npairs;
+        for (int sx = 0; sx <= r; ++sx) {
+          if (npairs >= kMaxPairs || o + kPairInts > tab_cap) { err = 1; break; }
+          tab[o + PR_RNODE] = s_slotnode[s];
+          tab[o + PR_FROM] = (sx == 0) ? 0 : s_pathpos[s_cslot0[c] + sx - 1] + 1;
+          tab[o + PR_TO] = s_pathpos[s];
+          tab[o + PR_PATHOFF] = path_off[c];
+          o += kPairInts;
+          ++npairs;
+        }
+      }
+    // Omega_g ranges in preorder: union of the chain tops' subtrees
+    int nr = 0;
+    for (int c = 0; c < nch && !err; ++c) {
+      const int a = T.pos[s_tops[c]], b = a + T.size[s_tops[c]];
+      int q = nr - 1;
+      while (q >= 0 && s_rs[q] > a) { s_rs[q + 1] = s_rs[q]; s_re[q + 1] = s_re[q]; --q; }
+      s_rs[q + 1] = a;
+      s_re[q + 1] = b;
+      ++nr;
+    }
+    int m = 0;
+    for (int q = 0; q < nr; ++q) {
+      if (m > 0 && s_rs[q] < s_re[m - 1]) {
+        s_re[m - 1] = max(s_re[m - 1], s_re[q]);
+      } else {
+        s_rs[m] = s_rs[q];
+        s_re[m] = s_re[q];
+        ++m;
+      }
+    }
+    nr = m;
+    s_rcum[0] = 0;
+    for (int q = 0; q < nr; ++q) s_rcum[q + 1] = s_rcum[q] + (s_re[q] - s_rs[q]);
+    H.o_range = o;
+    if (o + 3 * nr > tab_cap) err = 1;
+    for (int q = 0; q < nr && !err; ++q) {
+      tab[o + 3 * q] = s_rs[q];
+      tab[o + 3 * q + 1] = s_re[q];
+      tab[o + 3 * q + 2] = s_rcum[q];
+    }
+    o += 3 * nr;
+    H.nrange = nr;
+    H.nomega = s_rcum[nr];
+    H.o_zent = o;
+    H.nchains = nch;
+    H.nslots = ns;
+    H.npairs = npairs;
+    // chain and slot records (zone ranges filled after the zone pass)
+    for (int c = 0; c < nch && !err; ++c) {
+      int* cr = tab + H.o_chain + c * kChainInts;
+      cr[C_HEAD] = s_head[c];
+      cr[C_NSLOT] = s_cslot0[c + 1] - s_cslot0[c];
+      cr[C_SLOT0] = s_cslot0[c];
+      cr[C_NEST_OFF] = nest_off[c];
+      cr[C_NEST_LEN] = nest_len[c];
+      cr[C_PATH_OFF] = path_off[c];
+      cr[C_PATH_LEN] = path_len[c];
+      cr[C_OUTER] = s_outer[c];
+      for (int p = 0; p < 3; ++p) { cr[C_ZOFF0 + p] = 0; cr[C_ZCNT0 + p] = 0; }
+    }
+    for (int s = 0; s < ns && !err; ++s) {
+      int* sr = tab + H.o_slot + s * kSlotInts;
+      sr[SL_NODE] = s_slotnode[s];
+      sr[SL_BIT] = s_slotbit[s];
+      sr[SL_PHASE] = T.phase[s_slotnode[s]];
+      sr[SL_PAIRBASE] = pairbase[s];
+      sr[SL_PATHPOS] = s_pathpos[s];
+      sr[SL_CHAIN] = s_slotchain[s];
+      St.slot_of[s_slotnode[s]] = s;
+    }
+    for (int q = 0; q < kMaxK * 3; ++q) { s_keycnt[q] = 0; s_keycur[q] = 0; }
+    H.valid = err ? 0 : 1;
+    s_h = H;
+    s_err = err;
+  }
+  __syncthreads();
+  SegHdr H = s_h;
+  if (s_err) {
+    if (threadIdx.x == 0) {
+      H.valid = 0;
+      hdrs[g] = H;
+      atomicOr(status, kStatusBuild);
+    }
+    return;
+  }
+  const int nr = H.nrange, nom = H.nomega;
+  const int* rg = tab + H.o_range;
+  // zone targets: kept nodes of Omega_g outside the segment; anchor = chain
+  // whose bottom slot is the first segment node above the target
+  for (int pass = 0; pass < 2; ++pass) {
+    for (int q = threadIdx.x; q < nom; q += blockDim.x) {
+      int r = 0;
+      while (r + 1 < nr && rg[3 * (r + 1) + 2] <= q) ++r;
+      const int i = T.pre[rg[3 * r] + (q - rg[3 * r + 2])];
+      if (segment[i] == g || !St.kept[i]) continue;
+      int u = parent[i];
+      while (u >= 0 && segment[u] != g) u = parent[u];
+      const int s = (u >= 0) ? St.slot_of[u] : -1;
+      if (s < 0) { atomicOr(&s_err, 1); continue; }
+      const int c = tab[H.o_slot + s * kSlotInts + SL_CHAIN];
+      const int* cr = tab + H.o_chain + c * kChainInts;
+      if (s != cr[C_SLOT0] + cr[C_NSLOT] - 1) { atomicOr(&s_err, 1); continue; }  // must be the chain's bottom
+      const unsigned ph = T.phase[i];
+      for (int p = 0; p < 3; ++p) {
+        if (!(ph >> p & 1u)) continue;
+        const int key = c * 3 + p;
+        if (pass == 0) {
+          atomicAdd(&s_keycnt[key], 1);
+        } else {
+          const int idx = s_keyoff[key] + atomicAdd(&s_keycur[key], 1);
+          int* ze = tab + H.o_zent + 3 * idx;
+          ze[0] = i;
+          ze[1] = p;
+          ze[2] = c;
+          St.zent_of[i * 3 + p] = idx;
+        }
+      }
+    }
+    __syncthreads();
+    if (pass == 0 && threadIdx.x == 0) {
+      int acc = 0;
+      for (int key = 0; key < H.nchains * 3; ++key) {
+        s_keyoff[key] = acc;
+        int* cr = tab + H.o_chain + (key / 3) * kChainInts;
+        cr[C_ZOFF0 + key % 3] = acc;
+        cr[C_ZCNT0 + key % 3] = s_keycnt[key];
+        acc += s_keycnt[key];
+      }
+      s_h.nz = acc;
+      s_h.total_ints = H.o_zent + 3 * acc;
+      if (s_h.total_ints > tab_cap) s_err = 1;
+    }
+    __syncthreads();
+    if (s_err) break;
+  }
+  if (threadIdx.x == 0) {
+    H = s_h;
+    if (s_err) {
+      H.valid = 0;
+      atomicOr(status, kStatusBuild);
+    }
+    hdrs[g] = H;
+  }
+}
+
+// Node of Omega_g with flattened index q (ranges: start, end, cumulative).
+__device__ __forceinline__ int omega_node(const Topo& T, const int* rg, int nr, int q) {
+  int r = 0;
+  while (r + 1 < nr && rg[3 * (r + 1) + 2] <= q) ++r;
+  return T.pre[rg[3 * r] + (q - rg[3 * r + 2])];
+}
+
+__global__ __launch_bounds__(256) void k_build_values(const SegHdr* __restrict__ hdrs, int g,
+                                                      const int* __restrict__ tab, int n,
+                                                      const double2* __restrict__ z, const double2* __restrict__ Vcur,
+                                                      const double2* __restrict__ A, double2* __restrict__ P,
+                                                      TargetRec* __restrict__ srec, double2* __restrict__ headV,
+                                                      TargetRec* __restrict__ zrec, double* __restrict__ econst) {
+  const SegHdr H = hdrs[g];
+  if (!H.valid) return;
+  const int part = blockIdx.y;
+  const int S = H.S;
+  const int stride = gridDim.x * blockDim.x;
+  const int* path = tab + H.o_path;
+  if (part == 0) {
+    for (int t = blockIdx.x * blockDim.x + threadIdx.x; t < S * H.npairs; t += stride) {
+      const int l = t / H.npairs, q = t % H.npairs;
+      const int* pr = tab + H.o_pair + q * kPairInts;
+      double2 Z[9];
+      for (int e = 0; e < 9; ++e) Z[e] = make_double2(0.0, 0.0);
+      for (int x = pr[PR_FROM]; x <= pr[PR_TO]; ++x) {
+        const double2* zv = z + (size_t)path[pr[PR_PATHOFF] + x] * 9;
+        for (int e = 0; e < 9; ++e) Z[e] = b_cadd(Z[e], zv[e]);
+      }
+      const double2* a = A + ((size_t)l * n + pr[PR_RNODE]) * 3;
+      double2* o = P + ((size_t)l * H.npairs + q) * 3;
+      for (int r = 0; r < 3; ++r)
+        o[r] = b_cadd(b_cadd(b_cmul(Z[r * 3], a[0]), b_cmul(Z[r * 3 + 1], a[1])), b_cmul(Z[r * 3 + 2], a[2]));
+    }
+  } else if (part == 1) {
+    for (int t = blockIdx.x * blockDim.x + threadIdx.x; t < S * H.nslots * 3; t += stride) {
+      const int l = t / (H.nslots * 3), rem = t % (H.nslots * 3), s = rem / 3, p = rem % 3;
+      const int node = tab[H.o_slot + s * kSlotInts + SL_NODE];
+      TargetRec rec;
+      rec.W = Vcur[((size_t)l * n + node) * 3 + p];
+      rec.lo = INFINITY;
+      rec.hi = 0.0;
+      srec[((size_t)l * H.nslots + s) * 3 + p] = rec;
+    }
+  } else if (part == 2) {
+    for (int t = blockIdx.x * blockDim.x + threadIdx.x; t < S * H.nchains; t += stride) {
+      const int l = t / H.nchains, c = t % H.nchains;
+      const int head = tab[H.o_chain + c * kChainInts + C_HEAD];
+      for (int p = 0; p < 3; ++p) headV[((size_t)l * H.nchains + c) * 3 + p] = Vcur[((size_t)l * n + head) * 3 + p];
+    }
+  } else if (part == 3) {
+    for (int t = blockIdx.x * blockDim.x + threadIdx.x; t < S * H.nz; t += stride) {
+      const int l = t / H.nz, q = t % H.nz;
+      const int* ze = tab + H.o_zent + q * 3;
+      TargetRec rec;
+      rec.W = Vcur[((size_t)l * n + ze[0]) * 3 + ze[1]];
+      rec.lo = INFINITY;
+      rec.hi = 0.0;
+      zrec[(size_t)l * H.nz + q] = rec;
+    }
+  } else {
+    for (int t = blockIdx.x * blockDim.x + threadIdx.x; t < S; t += stride) econst[t] = 0.0;
+  }
+}
+
+__device__ __forceinline__ void atomic_min_nonneg(double* a, double v) {
+  atomicMin((unsigned long long*)a, (unsigned long long)__double_as_longlong(v));
+}
+__device__ __forceinline__ void atomic_max_nonneg(double* a, double v) {
+  atomicMax((unsigned long long*)a, (unsigned long long)__double_as_longlong(v));
+}
+
+// Cluster statistics: every node of Omega_g contributes |V^| to the cluster of
+// its current super-node (a slot, a zone target, or a head outside Omega_g,
+// whose error is mask-independent and folds into econst).
+__global__ __launch_bounds__(256) void k_build_members(const SegHdr* __restrict__ hdrs, int g,
+                                                       const int* __restrict__ tab, Topo T, State St,
+                                                       const double2* __restrict__ Vcur,
+                                                       const double* __restrict__ absV, TargetRec* __restrict__ srec,
+                                                       TargetRec* __restrict__ zrec, double* __restrict__ econst) {
+  const SegHdr H = hdrs[g];
+  if (!H.valid) return;
+  const int n = T.n;
+  const int* rg = tab + H.o_range;
+  const long total = (long)H.nomega * H.S;
+  for (long t = (long)blockIdx.x * blockDim.x + threadIdx.x; t < total; t += (long)gridDim.x * blockDim.x) {
+    const int l = (int)(t / H.nomega), q = (int)(t % H.nomega);
+    const int i = omega_node(T, rg, H.nrange, q);
+    const int sp = St.sup[i];
+    const unsigned ph = T.phase[i];
+    const double* av = absV + ((size_t)l * n + i) * 3;
+    if (T.segment[sp] == g) {
+      const int s = St.slot_of[sp];
+      if (s < 0 || s >= H.nslots) continue;
+      TargetRec* r = srec + ((size_t)l * H.nslots + s) * 3;
+      for (int p = 0; p < 3; ++p)
+        if (ph >> p & 1u) { atomic_min_nonneg(&r[p].lo, av[p]); atomic_max_nonneg(&r[p].hi, av[p]); }
+    } else {
+      for (int p = 0; p < 3; ++p) {
+        if (!(ph >> p & 1u)) continue;
+        const int zi = St.zent_of[sp * 3 + p];
+        if (zi >= H.nz) continue;
+        if (zi >= 0) {
+          TargetRec* r = zrec + (size_t)l * H.nz + zi;
+          atomic_min_nonneg(&r->lo, av[p]);
+          atomic_max_nonneg(&r->hi, av[p]);
+        } else {
+          const double2 v = Vcur[((size_t)l * n + sp) * 3 + p];
+          atomic_max_nonneg(&econst[l], fabs(sqrt(v.x * v.x + v.y * v.y) - av[p]));
+        }
+      }
+    }
+  }
+}
+
+}  // namespace okr

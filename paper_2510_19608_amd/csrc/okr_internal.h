@@ -10,29 +10,50 @@ constexpr int kMaxK = 24;                    // eligible nodes per segment
 constexpr int kMaxPairs = kMaxK * (kMaxK + 1) / 2;  // (super slot, reduced slot) pairs
 constexpr int kScoreBlock = 64;              // one wave per scoring block
 
-// Index tables of one segment, built on the host from the cumulative kept
-// state and uploaded as one int32 buffer; the offsets below index into it.
+// Header of one segment's tables (one per segment, in device memory), written
+// by the device-side builder; offsets index the int32 table buffer.
 struct SegHdr {
+  int g;          // segment id
+  int valid;      // 0 if a structural invariant failed
   int k;          // eligible nodes in the segment
   int nchains;    // chains of the affected region
   int nslots;     // == k (every segment node is a slot of exactly one chain)
   int npairs;     // sum over chains of j(j+1)/2
   int nz;         // zone entries (kept target node, phase)
-  int nh;         // head-cluster members (constant error part)
-  int nmem;       // cluster member entries (slots then zone entries)
   int S;          // snapshots
-  // offsets (in int32 units) into the table buffer
+  int nrange;     // preorder ranges whose union is Omega_g
+  int nomega;     // nodes in Omega_g
   int o_chain;    // [nchains][kChainInts]
   int o_nest;     // nesting paths, outermost first, ending with the chain itself
-  int o_slot;     // [nslots][kSlotInts]
   int o_path;     // chain node paths, top to bottom
+  int o_slot;     // [nslots][kSlotInts]
   int o_pair;     // [npairs][kPairInts]
-  int o_zent;     // [nz][2]: node, phase
-  int o_zmemoff;  // [nz + 1] CSR offsets into members
-  int o_smemoff;  // [nslots + 1] CSR offsets into members
-  int o_mem;      // member node ids
-  int o_h;        // [nh][3]: member node, head node, present-phase mask of the member
+  int o_range;    // [nrange][3]: preorder start, end, cumulative node count
+  int o_zent;     // [nz][3]: node, phase, chain
   int total_ints;
+};
+
+// Static topology on the device.
+struct Topo {
+  int n;
+  const int* parent;
+  const uint8_t* phase;
+  const int* segment;
+  const int* pos;       // DFS preorder position
+  const int* size;      // subtree size
+  const int* pre;       // preorder -> node
+  const int* ch_off;    // children CSR
+  const int* ch;
+  const int* seg_off;   // segment -> first index in seg_nodes
+  const int* seg_nodes; // segment nodes in DFS preorder
+};
+
+// Cumulative search state on the device.
+struct State {
+  uint8_t* kept;  // 1 while the node is kept
+  int* sup;       // nearest kept ancestor (inclusive)
+  int* slot_of;   // node -> slot of the segment being scored, -1 otherwise
+  int* zent_of;   // node*3+phase -> zone entry of the segment being scored, -1 otherwise
 };
 
 // chain record

@@ -241,96 +241,6 @@ __global__ void k_from_vhat(int n, int S, const uint8_t* __restrict__ phase, con
   if (pr && (m < vmin || m > vmax)) atomicOr(status, 32);
 }
 
-// ------------------------------------------------------- segment tables --
-// Numeric tables of one segment from the current state (grid.y = part):
-//   0: P[l][pair] = Z(super -> reduced) A_reduced     (series impedance of the
-//      Kron-eliminated path times the moved aggregated current)
-//   1: slot TargetRec (W = Vcur, lo/hi over the slot's cluster)
-//   2: head voltages, 3: zone TargetRec, 4: constant error of head clusters.
-__global__ void k_seg_fill(const int* __restrict__ tab, SegHdr H, int n, const double2* __restrict__ z,
-                           const double2* __restrict__ Vcur, const double2* __restrict__ A,
-                           const double* __restrict__ absV, double2* __restrict__ P,
-                           TargetRec* __restrict__ srec, double2* __restrict__ headV,
-                           TargetRec* __restrict__ zrec, double* __restrict__ econst) {
-  const int part = blockIdx.y;
-  const int t = blockIdx.x * blockDim.x + threadIdx.x;
-  const int S = H.S;
-  const int* chains = tab + H.o_chain;
-  const int* slots = tab + H.o_slot;
-  const int* path = tab + H.o_path;
-  const int* pairs = tab + H.o_pair;
-  const int* mem = tab + H.o_mem;
-  if (part == 0) {
-    if (t >= S * H.npairs) return;
-    const int l = t / H.npairs, q = t % H.npairs;
-    const int* pr = pairs + q * kPairInts;
-    double2 Z[9];
-    for (int e = 0; e < 9; ++e) Z[e] = make_double2(0.0, 0.0);
-    for (int x = pr[PR_FROM]; x <= pr[PR_TO]; ++x) {
-      const double2* zv = z + (size_t)path[pr[PR_PATHOFF] + x] * 9;
-      for (int e = 0; e < 9; ++e) Z[e] = cadd(Z[e], zv[e]);
-    }
-    const double2* a = A + ((size_t)l * n + pr[PR_RNODE]) * 3;
-    double2* o = P + ((size_t)l * H.npairs + q) * 3;
-    for (int r = 0; r < 3; ++r) o[r] = cadd(cadd(cmul(Z[r * 3], a[0]), cmul(Z[r * 3 + 1], a[1])), cmul(Z[r * 3 + 2], a[2]));
-  } else if (part == 1) {
-    if (t >= S * H.nslots * 3) return;
-    const int l = t / (H.nslots * 3), rem = t % (H.nslots * 3), s = rem / 3, p = rem % 3;
-    const int* sr = slots + s * kSlotInts;
-    const int node = sr[SL_NODE];
-    TargetRec rec;
-    rec.W = Vcur[((size_t)l * n + node) * 3 + p];
-    double lo = INFINITY, hi = -INFINITY;
-    if (sr[SL_PHASE] >> p & 1) {
-      const int* off = tab + H.o_smemoff;
-      for (int e = off[s]; e < off[s + 1]; ++e) {
-        const int v = mem[e];
-        const double m = absV[((size_t)l * n + v) * 3 + p];
-        if (m > 0.0) { lo = fmin(lo, m); hi = fmax(hi, m); }
-      }
-    }
-    rec.lo = lo;
-    rec.hi = hi;
-    srec[((size_t)l * H.nslots + s) * 3 + p] = rec;
-  } else if (part == 2) {
-    if (t >= S * H.nchains) return;
-    const int l = t / H.nchains, c = t % H.nchains;
-    const int head = chains[c * kChainInts + C_HEAD];
-    for (int p = 0; p < 3; ++p) headV[((size_t)l * H.nchains + c) * 3 + p] = Vcur[((size_t)l * n + head) * 3 + p];
-  } else if (part == 3) {
-    if (t >= S * H.nz) return;
-    const int l = t / H.nz, q = t % H.nz;
-    const int* ze = tab + H.o_zent + q * 3;
-    const int node = ze[0], p = ze[1];
-    const int* off = tab + H.o_zmemoff;
-    double lo = INFINITY, hi = -INFINITY;
-    for (int e = off[q]; e < off[q + 1]; ++e) {
-      const double m = absV[((size_t)l * n + mem[e]) * 3 + p];
-      lo = fmin(lo, m);
-      hi = fmax(hi, m);
-    }
-    TargetRec rec;
-    rec.W = Vcur[((size_t)l * n + node) * 3 + p];
-    rec.lo = lo;
-    rec.hi = hi;
-    zrec[(size_t)l * H.nz + q] = rec;
-  } else {
-    if (t >= S) return;
-    const int l = t;
-    double e = 0.0;
-    const int* h = tab + H.o_h;
-    for (int q = 0; q < H.nh; ++q) {
-      const int v = h[q * 3], head = h[q * 3 + 1], pm = h[q * 3 + 2];
-      for (int p = 0; p < 3; ++p) {
-        if (!(pm >> p & 1)) continue;
-        const double d = fabs(sqrt(cabs2(Vcur[((size_t)l * n + head) * 3 + p])) - absV[((size_t)l * n + v) * 3 + p]);
-        e = fmax(e, d);
-      }
-    }
-    econst[l] = e;
-  }
-}
-
 // ---------------------------------------------------------------- scoring --
 // sqrt for arguments in the normal range (here |V|^2 of a bus voltage): the
 // hardware reciprocal-square-root estimate refined by Newton-Raphson steps in
@@ -354,12 +264,14 @@ __device__ __forceinline__ double vmag(double2 a) { return sqrt_nr(a.x * a.x + a
 // (P from LDS); a kept slot becomes the super of the slots below it.  With
 // ERR, every slot cluster's error against its super's magnitude and the band
 // of kept slots are folded into (el, slack).  Slot records and head voltages
-// of the snapshot come from LDS.
+// are wave-uniform and read with scalar loads; P entries depend on the lane's
+// super slot and come from LDS.
 template <bool ERR>
 __device__ __forceinline__ void walk_chain(const int* __restrict__ cr, const int* __restrict__ slots,
-                                           const double2* Ps, const TargetRec* Ss, const double2* Hs, int c,
-                                           uint32_t m, double2& B0, double2& B1, double2& B2, double& el,
-                                           double& slack, double vmin, double vmax) {
+                                           const double2* Ps, const TargetRec* __restrict__ Ss,
+                                           const double2* __restrict__ Hs, int c, uint32_t m, double2& B0,
+                                           double2& B1, double2& B2, double& el, double& slack, double vmin,
+                                           double vmax) {
   double2 S0 = B0, S1 = B1, S2 = B2;
   double sm0 = 0.0, sm1 = 0.0, sm2 = 0.0;
   if (ERR) {
@@ -414,15 +326,15 @@ __device__ __forceinline__ bool near_boundary(const MaskScore& r, double e_bar, 
 // The last block of a 64-mask tile to finish (ticket counter) folds the
 // snapshot groups into the final per-mask score and writes the tile record.
 __global__ __launch_bounds__(kScoreBlock) void k_score_fp64(
-    const int* __restrict__ tab, SegHdr H, const double2* __restrict__ P,
+    const SegHdr* __restrict__ hdrs, int g, const int* __restrict__ tab, const double2* __restrict__ P,
     const TargetRec* __restrict__ srec, const double2* __restrict__ headV,
     const TargetRec* __restrict__ zrec, const double* __restrict__ econst, int snaps_per_group, int SG,
     SelParams sp, MaskScore* __restrict__ part, MaskScore* __restrict__ fin, TileRec* __restrict__ tiles,
     int* __restrict__ tickets) {
   __shared__ double2 Ps[kMaxPairs * 3];
-  __shared__ TargetRec Ss[kMaxK * 3];
-  __shared__ double2 Hs[kMaxK * 3];
   __shared__ int ticket;
+  const SegHdr H = hdrs[g];
+  if (!H.valid) return;
   const uint32_t m = blockIdx.x * kScoreBlock + threadIdx.x;
   const int sg = blockIdx.y;
   const int l0 = sg * snaps_per_group;
@@ -435,10 +347,8 @@ __global__ __launch_bounds__(kScoreBlock) void k_score_fp64(
   for (int l = l0; l < l1; ++l) {
     const double2* Pl = P + (size_t)l * H.npairs * 3;
     for (int q = threadIdx.x; q < H.npairs * 3; q += kScoreBlock) Ps[q] = Pl[q];
-    const TargetRec* Sl = srec + (size_t)l * H.nslots * 3;
-    for (int q = threadIdx.x; q < H.nslots * 3; q += kScoreBlock) Ss[q] = Sl[q];
-    const double2* Hl = headV + (size_t)l * H.nchains * 3;
-    for (int q = threadIdx.x; q < H.nchains * 3; q += kScoreBlock) Hs[q] = Hl[q];
+    const TargetRec* Ss = srec + (size_t)l * H.nslots * 3;
+    const double2* Hs = headV + (size_t)l * H.nchains * 3;
     __syncthreads();
     const TargetRec* zrec_l = zrec + (size_t)l * H.nz;
     double el = econst[l];
@@ -518,13 +428,28 @@ __global__ __launch_bounds__(kScoreBlock) void k_score_fp64(
 // Ambiguous when a mask at the chosen level or above lies within amb of the
 // e_bar / band boundary, or a feasible mask at the chosen level lies within
 // amb of e_min + tie_tol.
-__global__ __launch_bounds__(1024) void k_argmin(const MaskScore* __restrict__ fin, const TileRec* __restrict__ tiles,
-                                                 int k, SelParams sp, DevDecision* __restrict__ dec) {
+__global__ __launch_bounds__(1024) void k_argmin(const SegHdr* __restrict__ hdrs, int g,
+                                                 const MaskScore* __restrict__ fin, const TileRec* __restrict__ tiles,
+                                                 SelParams sp, const int* __restrict__ status,
+                                                 DevDecision* __restrict__ decs) {
   __shared__ double shd[16];
   __shared__ int shi[16];
   __shared__ unsigned shu[16];
   __shared__ int ncand;
   __shared__ int cand[1024];
+  const SegHdr H = hdrs[g];
+  DevDecision* dec = decs + g;
+  // nothing is reduced when the full network violates the band, the load
+  // flow failed, or the segment's tables are inconsistent
+  if (!H.valid || (*status & (16 | 32))) {
+    if (threadIdx.x == 0) {
+      DevDecision d;
+      d.mask = 0; d.popcount = 0; d.e_loc = 0.0; d.e_min = 0.0; d.ambiguous = 0; d.found = 0;
+      *dec = d;
+    }
+    return;
+  }
+  const int k = H.k;
   const uint32_t nm = 1u << k;
   const int ntiles = (int)((nm + 63) / 64);
   int best = -1;
@@ -584,13 +509,19 @@ __global__ void k_sqrt_selftest(const double* __restrict__ x, double* __restrict
 // Apply the chosen mask to the cumulative state (Algorithm 1 state update):
 // aggregated currents move to the new super-nodes, kept slots and zone
 // targets take their candidate voltages (same arithmetic as the scoring).
-__global__ __launch_bounds__(64) void k_apply(const int* __restrict__ tab, SegHdr H, int n,
-                                              const DevDecision* __restrict__ dec, const double2* __restrict__ P,
-                                              const TargetRec* __restrict__ srec, const TargetRec* __restrict__ zrec,
-                                              double2* __restrict__ Vcur, double2* __restrict__ A) {
+// Block 0 then updates the kept flags and super-nodes over Omega_g and clears
+// the node -> slot / zone-entry maps for the next segment.
+__global__ __launch_bounds__(64) void k_apply(const SegHdr* __restrict__ hdrs, int g, const int* __restrict__ tab,
+                                              Topo T, State St, const DevDecision* __restrict__ decs,
+                                              const double2* __restrict__ P, const TargetRec* __restrict__ srec,
+                                              const TargetRec* __restrict__ zrec, double2* __restrict__ Vcur,
+                                              double2* __restrict__ A) {
   __shared__ double2 Bs[kMaxK * 3];
+  const SegHdr H = hdrs[g];
+  if (!H.valid) return;
+  const int n = T.n;
   const int l = blockIdx.x;
-  const uint32_t m = dec->mask;
+  const uint32_t m = decs[g].mask;
   const int* chains = tab + H.o_chain;
   const int* slots = tab + H.o_slot;
   if (threadIdx.x == 0) {
@@ -630,6 +561,48 @@ __global__ __launch_bounds__(64) void k_apply(const int* __restrict__ tab, SegHd
     const int node = ze[0], p = ze[1], c = ze[2];
     Vcur[((size_t)l * n + node) * 3 + p] = cadd(zrec[(size_t)l * H.nz + q].W, Bs[c * 3 + p]);
   }
+  if (blockIdx.x != 0) return;
+  __syncthreads();
+  if (threadIdx.x == 0)
+    for (int s = 0; s < H.nslots; ++s) {
+      const int* sr = slots + s * kSlotInts;
+      if ((m >> sr[SL_BIT]) & 1u) St.kept[sr[SL_NODE]] = 0;
+      St.slot_of[sr[SL_NODE]] = -1;
+    }
+  for (int q = threadIdx.x; q < H.nz; q += blockDim.x) {
+    const int* ze = tab + H.o_zent + q * 3;
+    St.zent_of[ze[0] * 3 + ze[1]] = -1;
+  }
+  __syncthreads();
+  const int* rg = tab + H.o_range;
+  for (int q = threadIdx.x; q < H.nomega; q += blockDim.x) {
+    int r = 0;
+    while (r + 1 < H.nrange && rg[3 * (r + 1) + 2] <= q) ++r;
+    const int i = T.pre[rg[3 * r] + (q - rg[3 * r + 2])];
+    int v = i;
+    while (!St.kept[v]) v = T.parent[v];
+    St.sup[i] = v;
+  }
+}
+
+// Reset of the search state at the start of a call (no memset nodes, so the
+// sequence can be captured in a graph).
+__global__ void k_init_state(int n, State St, int* __restrict__ status, int nstatus, int* __restrict__ tickets,
+                             int ntickets) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) {
+    St.kept[i] = 1;
+    St.sup[i] = i;
+    St.slot_of[i] = -1;
+    St.zent_of[3 * i] = St.zent_of[3 * i + 1] = St.zent_of[3 * i + 2] = -1;
+  }
+  if (i < nstatus) status[i] = 0;
+  if (i < ntickets) tickets[i] = 0;
+}
+
+__global__ void k_copy2(const double2* __restrict__ a, double2* __restrict__ b, size_t count) {
+  for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < count; i += (size_t)gridDim.x * blockDim.x)
+    b[i] = a[i];
 }
 
 // ---------------------------------------------------------- final outputs --
@@ -653,19 +626,20 @@ __global__ __launch_bounds__(256) void k_final_err(int n, const uint8_t* __restr
 // Kron-reduced branch of every kept node: the eliminated path up to its kept
 // parent is a series chain, so y_eq = (sum of z on the path, restricted to
 // the node's phases)^-1 (eq. Y_kron for degree-2 and leaf eliminations).
-__global__ void k_kron_yeq(int n, const int* __restrict__ parent, const uint8_t* __restrict__ phase,
-                           const int* __restrict__ kp, const double2* __restrict__ z, double2* __restrict__ yeq,
-                           double2* __restrict__ Yk_off, int* __restrict__ status) {
+__global__ void k_kron_yeq(Topo T, State St, const double2* __restrict__ z, double2* __restrict__ yeq,
+                           double2* __restrict__ Yk_off, int* __restrict__ kp_out, int* __restrict__ status) {
   const int x = blockIdx.x * blockDim.x + threadIdx.x;
-  if (x >= n) return;
+  if (x >= T.n) return;
   double2* yo = Yk_off + (size_t)x * 9;
   double2* ye = yeq + (size_t)x * 9;
   for (int q = 0; q < 9; ++q) { yo[q] = make_double2(0.0, 0.0); ye[q] = yo[q]; }
-  if (kp[x] < 0) return;
-  const unsigned ph = phase[x];
+  const int kp = (x > 0 && St.kept[x]) ? St.sup[T.parent[x]] : -1;
+  kp_out[x] = kp;
+  if (kp < 0) return;
+  const unsigned ph = T.phase[x];
   double2 Z[9];
   for (int q = 0; q < 9; ++q) Z[q] = make_double2(0.0, 0.0);
-  for (int v = x; v != kp[x]; v = parent[v]) {
+  for (int v = x; v != kp; v = T.parent[v]) {
     const double2* zv = z + (size_t)v * 9;
     for (int r = 0; r < 3; ++r)
       for (int c = 0; c < 3; ++c)
@@ -675,18 +649,23 @@ __global__ void k_kron_yeq(int n, const int* __restrict__ parent, const uint8_t*
   for (int q = 0; q < 9; ++q) yo[q] = make_double2(-ye[q].x, -ye[q].y);
 }
 
-__global__ void k_kron_diag(int n, const uint8_t* __restrict__ kept, const int* __restrict__ kp,
-                            const int* __restrict__ kc_off, const int* __restrict__ kc,
-                            const double2* __restrict__ yeq, double2* __restrict__ Yk_diag) {
+// Y_Kron(x,x) = y_eq of x's own branch plus those of its reduced-network
+// children, found by following each tree child down through reduced nodes
+// (which have at most one child) to the first kept node.
+__global__ void k_kron_diag(Topo T, State St, const double2* __restrict__ yeq, double2* __restrict__ Yk_diag) {
   const int x = blockIdx.x * blockDim.x + threadIdx.x;
-  if (x >= n) return;
+  if (x >= T.n) return;
   double2 D[9];
   for (int q = 0; q < 9; ++q) D[q] = make_double2(0.0, 0.0);
-  if (kept[x]) {
-    if (kp[x] >= 0)
+  if (St.kept[x]) {
+    if (x > 0)
       for (int q = 0; q < 9; ++q) D[q] = yeq[(size_t)x * 9 + q];
-    for (int e = kc_off[x]; e < kc_off[x + 1]; ++e)
-      for (int q = 0; q < 9; ++q) D[q] = cadd(D[q], yeq[(size_t)kc[e] * 9 + q]);
+    for (int e = T.ch_off[x]; e < T.ch_off[x + 1]; ++e) {
+      int v = T.ch[e];
+      while (!St.kept[v] && T.ch_off[v + 1] > T.ch_off[v]) v = T.ch[T.ch_off[v]];
+      if (St.kept[v])
+        for (int q = 0; q < 9; ++q) D[q] = cadd(D[q], yeq[(size_t)v * 9 + q]);
+    }
   }
   for (int q = 0; q < 9; ++q) Yk_diag[(size_t)x * 9 + q] = D[q];
 }

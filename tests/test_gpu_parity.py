@@ -203,3 +203,26 @@ def test_scoring_sqrt_is_correctly_rounded(okr):
     ulp = np.abs(y - ref) / np.spacing(ref)
     assert ulp.max() <= 1.0
     assert (ulp == 0).mean() > 0.999
+
+
+def test_graph_replay_matches_stream_run(okr):
+    """The whole search captured as one hipGraph and replayed gives the same
+    decisions and outputs as the plain stream launch, on every replay, with
+    other GPU work and host synchronisations between replays."""
+    import torch
+    f = make_feeder("c2", 1, e_bar=3e-4)
+    ref = okr.reduce_feeder(f)
+    R = okr.Reducer(f, graph=True)
+    try:
+        for rep in range(3):
+            R.run(replan=False)
+            torch.cuda.synchronize()
+            out = R.result()
+            assert [s["mask"] for s in out["segments"]] == [s["mask"] for s in ref["segments"]]
+            np.testing.assert_array_equal(out["super"], ref["super"])
+            np.testing.assert_array_equal(out["err_per_snapshot"], ref["err_per_snapshot"])
+            np.testing.assert_array_equal(out["Yk_diag"], ref["Yk_diag"])
+            x = torch.randn(1 << 20, device="cuda")
+            (x * 2).sum().item()
+    finally:
+        R.close()
