@@ -142,9 +142,10 @@ typedef struct {
     double e_min;       /* smallest error at the chosen level */
     int32_t ambiguous;  /* a candidate lay within amb_tol of a decision boundary */
     int32_t n_scored;   /* masks scored exactly */
-    double flops;       /* algorithmic FP64 flops of the scoring kernel */
+    double flops;       /* algorithmic flops of the scoring kernel */
     float score_ms;     /* scoring-kernel time (OKR_FLAG_TIMING) */
-    float pad;
+    int32_t n_refined;  /* MIXED: masks rescored in FP64 (shortlists A + B) */
+    double fp32_dev;    /* MIXED: max |e32 - e64| over rescored masks with e64 <= 2 e_bar */
 } okr_segment_result;
 
 /* Outputs (HOST buffers owned by the caller). */

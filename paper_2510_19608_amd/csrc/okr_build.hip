@@ -142,6 +142,8 @@ __global__ __launch_bounds__(256) void k_build_struct(Topo T, State St, int g, i
           tab[o + PR_FROM] = (sx == 0) ? 0 : s_pathpos[s_cslot0[c] + sx - 1] + 1;
           tab[o + PR_TO] = s_pathpos[s];
           tab[o + PR_PATHOFF] = path_off[c];
+          tab[o + PR_SUPER] = (sx == 0) ? s_head[c] : s_slotnode[s_cslot0[c] + sx - 1];
+          tab[o + PR_RSLOT] = s;
           o += kPairInts;
           ++npairs;
         }

@@ -41,6 +41,19 @@ __global__ void k_final_err(int, const uint8_t*, const int*, const double2*, con
 __global__ void k_kron_yeq(Topo, State, const double2*, double2*, double2*, int*, int*);
 __global__ void k_kron_diag(Topo, State, const double2*, double2*);
 __global__ void k_sqrt_selftest(const double*, double*, int);
+__global__ void k_build_mixed(const SegHdr*, int, const int*, int, const double2*, const double2*, const TargetRec*,
+                              const double2*, const TargetRec*, double, double, Pair32*, Rec32*, Head32*, Rec32*);
+__global__ void k_score_fp32(const SegHdr*, int, const int*, const Pair32*, const Rec32*, const Head32*, const Rec32*,
+                             const double*, int, int, SelParams, MaskScore32*, MaskScore32*, TileRec32*, int*);
+__global__ void k_mixed_select_a(const SegHdr*, int, const MaskScore32*, const TileRec32*, SelParams, const int*,
+                                 MixedState*, uint32_t*, int*);
+__global__ void k_refine_fp64(const SegHdr*, int, const int*, const double2*, const TargetRec*, const double2*,
+                              const TargetRec*, const double*, SelParams, const uint32_t*, const int*, MaskScore*);
+__global__ void k_mixed_select_b(const SegHdr*, int, const MaskScore32*, const TileRec32*, SelParams, const int*,
+                                 MixedState*, const uint32_t*, const int*, const MaskScore*, uint32_t*, int*);
+__global__ void k_mixed_final(const SegHdr*, int, SelParams, const int*, MixedState*, const MaskScore32*,
+                              const uint32_t*, const int*, const MaskScore*, const uint32_t*, const int*,
+                              const MaskScore*, DevDecision*);
 }  // namespace okr
 
 using namespace okr;
@@ -49,6 +62,8 @@ namespace {
 
 constexpr int kMaxSnapGroups = 32;
 constexpr int kStatusInts = 16;
+constexpr double kMixedDelta = 1e-8;  // bound on |e32 - e64| used by the shortlist
+constexpr int kRefineBlocks = 256;
 
 size_t align256(size_t x) { return (x + 255) & ~size_t(255); }
 
@@ -64,7 +79,10 @@ int snap_groups(int k, int S, int* spg) {
 
 struct Layout {
   size_t topo, z, Vhat, Vcur, A, J, absV, kept, sup, slot_of, zent_of, status, iters, hdrs, decs, tab, P, srec,
-      headV, zrec, econst, part, fin, tiles, tickets, kp, yeq, Ykd, Yko, err, total;
+      headV, zrec, econst, part, fin, tiles, tickets, kp, yeq, Ykd, Yko, err;
+  // mixed precision
+  size_t P32, S32, H32, Z32, part32, fin32, tiles32, listA, listB, scoreA, scoreB, counts, mstate;
+  size_t total;
 };
 
 // offsets (in int32) of the static topology arrays inside the topology buffer
@@ -91,8 +109,9 @@ struct okr_handle {
   // captured graph of one whole search, and the arguments it was captured with
   hipGraphExec_t gexec = nullptr;
   std::vector<uint64_t> gkey;
-  // per-mask score dumps
+  // per-mask score dumps (FP64 scores, or FP32 screening scores in MIXED)
   std::vector<std::vector<MaskScore>> dump;
+  std::vector<std::vector<MaskScore32>> dump32;
 };
 
 #define OKR_FAIL(h, code, ...)            \
@@ -305,6 +324,27 @@ extern "C" int okr_plan(okr_handle* h, const okr_topology* topo, const okr_margi
     L.tiles = take(sizeof(TileRec) * nt);
     L.tickets = take(sizeof(int) * nt);
   }
+  {
+    size_t most = 1;
+    for (int k = 1; k <= h->kmax; ++k) {
+      int spg;
+      most = std::max(most, (size_t)snap_groups(k, S, &spg) << k);
+    }
+    const size_t nm = (size_t)1 << h->kmax, nt = (nm + 63) / 64;
+    L.P32 = take(sizeof(Pair32) * 3 * (size_t)S * kMaxPairs);
+    L.S32 = take(sizeof(Rec32) * 3 * (size_t)S * kMaxK);
+    L.H32 = take(sizeof(Head32) * 3 * (size_t)S * kMaxK);
+    L.Z32 = take(sizeof(Rec32) * (size_t)S * 3 * n);
+    L.part32 = take(sizeof(MaskScore32) * most);
+    L.fin32 = take(sizeof(MaskScore32) * nm);
+    L.tiles32 = take(sizeof(TileRec32) * nt);
+    L.listA = take(sizeof(uint32_t) * nm);
+    L.listB = take(sizeof(uint32_t) * nm);
+    L.scoreA = take(sizeof(MaskScore) * nm);
+    L.scoreB = take(sizeof(MaskScore) * nm);
+    L.counts = take(sizeof(int) * 4);
+    L.mstate = take(sizeof(MixedState) * std::max(nseg, 1));
+  }
   L.kp = take(sizeof(int) * n);
   L.yeq = take(sizeof(double2) * 9 * n);
   L.Ykd = take(sizeof(double2) * 9 * n);
@@ -336,6 +376,15 @@ struct Ptrs {
   TargetRec *srec, *zrec;
   MaskScore *part, *fin;
   TileRec* tiles;
+  Pair32* P32;
+  Rec32 *S32, *Z32;
+  Head32* H32;
+  MaskScore32 *part32, *fin32;
+  TileRec32* tiles32;
+  uint32_t *listA, *listB;
+  MaskScore *scoreA, *scoreB;
+  int* counts;
+  MixedState* mstate;
 };
 
 Ptrs pointers(okr_handle* h, void* d_workspace) {
@@ -387,6 +436,19 @@ Ptrs pointers(okr_handle* h, void* d_workspace) {
   p.Ykd = (double2*)at(L.Ykd);
   p.Yko = (double2*)at(L.Yko);
   p.err = (double*)at(L.err);
+  p.P32 = (Pair32*)at(L.P32);
+  p.S32 = (Rec32*)at(L.S32);
+  p.H32 = (Head32*)at(L.H32);
+  p.Z32 = (Rec32*)at(L.Z32);
+  p.part32 = (MaskScore32*)at(L.part32);
+  p.fin32 = (MaskScore32*)at(L.fin32);
+  p.tiles32 = (TileRec32*)at(L.tiles32);
+  p.listA = (uint32_t*)at(L.listA);
+  p.listB = (uint32_t*)at(L.listB);
+  p.scoreA = (MaskScore*)at(L.scoreA);
+  p.scoreB = (MaskScore*)at(L.scoreB);
+  p.counts = (int*)at(L.counts);
+  p.mstate = (MixedState*)at(L.mstate);
   return p;
 }
 
@@ -395,7 +457,7 @@ Ptrs pointers(okr_handle* h, void* d_workspace) {
 // `dump` every segment's final per-mask scores are copied out.
 void enqueue_search(okr_handle* h, const Ptrs& p, const okr_yblocks* Y, const okr_loads* loads,
                     const okr_margins* mg, hipStream_t st, const std::vector<hipEvent_t>* ev,
-                    std::vector<std::vector<MaskScore>>* dump) {
+                    std::vector<std::vector<MaskScore>>* dump, std::vector<std::vector<MaskScore32>>* dump32) {
   const int n = h->n, S = h->S;
   const bool vhat_given = (mg->flags & OKR_FLAG_VHAT_GIVEN) != 0;
   const int ntick = (int)((((size_t)1 << h->kmax) + 63) / 64);
@@ -424,6 +486,8 @@ void enqueue_search(okr_handle* h, const Ptrs& p, const okr_yblocks* Y, const ok
   sp.vmax = mg->v_max;
   sp.tie = mg->tie_tol;
   sp.amb = mg->amb_tol;
+  sp.delta = kMixedDelta;
+  const bool mixed = mg->precision == OKR_PRECISION_MIXED;
   const int members_blocks = std::min(2048, std::max(1, (int)(((size_t)n * S + 255) / 256)));
   for (int g = 0; g < h->nseg; ++g) {
     const int k = h->seg_off[g + 1] - h->seg_off[g];
@@ -439,17 +503,55 @@ void enqueue_search(okr_handle* h, const Ptrs& p, const okr_yblocks* Y, const ok
     const int mblocks = (int)((nmask + kScoreBlock - 1) / kScoreBlock);
     int spg;
     const int SG = snap_groups(k, S, &spg);
-    if (ev) (void)hipEventRecord((*ev)[2 * g], st);
-    hipLaunchKernelGGL(k_score_fp64, dim3(mblocks, SG), dim3(kScoreBlock), 0, st, (const SegHdr*)p.hdrs, g,
-                       (const int*)p.tab, (const double2*)p.P, (const TargetRec*)p.srec, (const double2*)p.headV,
-                       (const TargetRec*)p.zrec, (const double*)p.econst, spg, SG, sp, p.part, p.fin, p.tiles,
-                       p.tickets);
-    if (ev) (void)hipEventRecord((*ev)[2 * g + 1], st);
-    hipLaunchKernelGGL(k_argmin, dim3(1), dim3(1024), 0, st, (const SegHdr*)p.hdrs, g, (const MaskScore*)p.fin,
-                       (const TileRec*)p.tiles, sp, (const int*)p.status, p.decs);
-    if (dump) {
-      (*dump)[g].resize(nmask);
-      (void)hipMemcpyAsync((*dump)[g].data(), p.fin, sizeof(MaskScore) * nmask, hipMemcpyDeviceToHost, st);
+    if (!mixed) {
+      if (ev) (void)hipEventRecord((*ev)[2 * g], st);
+      hipLaunchKernelGGL(k_score_fp64, dim3(mblocks, SG), dim3(kScoreBlock), 0, st, (const SegHdr*)p.hdrs, g,
+                         (const int*)p.tab, (const double2*)p.P, (const TargetRec*)p.srec, (const double2*)p.headV,
+                         (const TargetRec*)p.zrec, (const double*)p.econst, spg, SG, sp, p.part, p.fin, p.tiles,
+                         p.tickets);
+      if (ev) (void)hipEventRecord((*ev)[2 * g + 1], st);
+      hipLaunchKernelGGL(k_argmin, dim3(1), dim3(1024), 0, st, (const SegHdr*)p.hdrs, g, (const MaskScore*)p.fin,
+                         (const TileRec*)p.tiles, sp, (const int*)p.status, p.decs);
+      if (dump) {
+        (*dump)[g].resize(nmask);
+        (void)hipMemcpyAsync((*dump)[g].data(), p.fin, sizeof(MaskScore) * nmask, hipMemcpyDeviceToHost, st);
+      }
+    } else {
+      hipLaunchKernelGGL(k_build_mixed, dim3(256, 4), dim3(256), 0, st, (const SegHdr*)p.hdrs, g, (const int*)p.tab,
+                         n, (const double2*)p.Vcur, (const double2*)p.P, (const TargetRec*)p.srec,
+                         (const double2*)p.headV, (const TargetRec*)p.zrec, mg->v_min, mg->v_max, p.P32, p.S32,
+                         p.H32, p.Z32);
+      if (ev) (void)hipEventRecord((*ev)[2 * g], st);
+      hipLaunchKernelGGL(k_score_fp32, dim3(mblocks, SG), dim3(kScoreBlock), 0, st, (const SegHdr*)p.hdrs, g,
+                         (const int*)p.tab, (const Pair32*)p.P32, (const Rec32*)p.S32, (const Head32*)p.H32,
+                         (const Rec32*)p.Z32, (const double*)p.econst, spg, SG, sp, p.part32, p.fin32, p.tiles32,
+                         p.tickets);
+      if (ev) (void)hipEventRecord((*ev)[2 * g + 1], st);
+      int* cA = p.counts;
+      int* cB = p.counts + 1;
+      hipLaunchKernelGGL(k_mixed_select_a, dim3(1), dim3(1024), 0, st, (const SegHdr*)p.hdrs, g,
+                         (const MaskScore32*)p.fin32, (const TileRec32*)p.tiles32, sp, (const int*)p.status,
+                         p.mstate, p.listA, cA);
+      hipLaunchKernelGGL(k_refine_fp64, dim3(kRefineBlocks), dim3(kScoreBlock), 0, st, (const SegHdr*)p.hdrs, g,
+                         (const int*)p.tab, (const double2*)p.P, (const TargetRec*)p.srec, (const double2*)p.headV,
+                         (const TargetRec*)p.zrec, (const double*)p.econst, sp, (const uint32_t*)p.listA,
+                         (const int*)cA, p.scoreA);
+      hipLaunchKernelGGL(k_mixed_select_b, dim3(1), dim3(1024), 0, st, (const SegHdr*)p.hdrs, g,
+                         (const MaskScore32*)p.fin32, (const TileRec32*)p.tiles32, sp, (const int*)p.status,
+                         p.mstate, (const uint32_t*)p.listA, (const int*)cA, (const MaskScore*)p.scoreA, p.listB,
+                         cB);
+      hipLaunchKernelGGL(k_refine_fp64, dim3(kRefineBlocks), dim3(kScoreBlock), 0, st, (const SegHdr*)p.hdrs, g,
+                         (const int*)p.tab, (const double2*)p.P, (const TargetRec*)p.srec, (const double2*)p.headV,
+                         (const TargetRec*)p.zrec, (const double*)p.econst, sp, (const uint32_t*)p.listB,
+                         (const int*)cB, p.scoreB);
+      hipLaunchKernelGGL(k_mixed_final, dim3(1), dim3(1024), 0, st, (const SegHdr*)p.hdrs, g, sp,
+                         (const int*)p.status, p.mstate, (const MaskScore32*)p.fin32, (const uint32_t*)p.listA,
+                         (const int*)cA, (const MaskScore*)p.scoreA, (const uint32_t*)p.listB, (const int*)cB,
+                         (const MaskScore*)p.scoreB, p.decs);
+      if (dump) {
+        (*dump32)[g].resize(nmask);
+        (void)hipMemcpyAsync((*dump32)[g].data(), p.fin32, sizeof(MaskScore32) * nmask, hipMemcpyDeviceToHost, st);
+      }
     }
     hipLaunchKernelGGL(k_apply, dim3(S), dim3(64), 0, st, (const SegHdr*)p.hdrs, g, (const int*)p.tab, p.T, p.St,
                        (const DevDecision*)p.decs, (const double2*)p.P, (const TargetRec*)p.srec,
@@ -499,7 +601,10 @@ extern "C" int okr_reduce_feeder(okr_handle* h, const okr_yblocks* Y, const okr_
   const auto t0 = clk::now();
   OKR_HIP(h, hipMemcpyAsync((void*)p.T.parent, h->topo_host.data(), sizeof(int) * h->TO.total,
                             hipMemcpyHostToDevice, st));
-  if (dump) h->dump.assign(nseg, {});
+  if (dump) {
+    h->dump.assign(nseg, {});
+    h->dump32.assign(nseg, {});
+  }
   if (timing && (int)h->ev.size() < 2 * nseg) {
     drop_events(h);
     h->ev.resize(2 * std::max(nseg, 1), nullptr);
@@ -516,7 +621,7 @@ extern "C" int okr_reduce_feeder(okr_handle* h, const okr_yblocks* Y, const okr_
       drop_graph(h);
       OKR_HIP(h, hipStreamSynchronize(st));
       OKR_HIP(h, hipStreamBeginCapture(st, hipStreamCaptureModeThreadLocal));
-      enqueue_search(h, p, Y, loads, mg, st, nullptr, nullptr);
+      enqueue_search(h, p, Y, loads, mg, st, nullptr, nullptr, nullptr);
       hipGraph_t gobj = nullptr;
       const hipError_t ec = hipStreamEndCapture(st, &gobj);
       if (ec != hipSuccess) OKR_FAIL(h, OKR_E_HIP, "graph capture failed: %s", hipGetErrorString(ec));
@@ -530,16 +635,21 @@ extern "C" int okr_reduce_feeder(okr_handle* h, const okr_yblocks* Y, const okr_
     }
     OKR_HIP(h, hipGraphLaunch(h->gexec, st));
   } else {
-    enqueue_search(h, p, Y, loads, mg, st, timing ? &h->ev : nullptr, dump ? &h->dump : nullptr);
+    enqueue_search(h, p, Y, loads, mg, st, timing ? &h->ev : nullptr, dump ? &h->dump : nullptr,
+                   dump ? &h->dump32 : nullptr);
     OKR_HIP(h, hipGetLastError());
   }
   // results (one synchronisation)
   std::vector<DevDecision> decs(std::max(nseg, 1));
   std::vector<SegHdr> hdrs(std::max(nseg, 1));
+  std::vector<MixedState> mstate(std::max(nseg, 1));
+  const bool mixed = mg->precision == OKR_PRECISION_MIXED;
   std::vector<int> sup(n), kp(n), iters(S, 0), status(kStatusInts, 0);
   if (nseg > 0) {
     OKR_HIP(h, hipMemcpyAsync(decs.data(), p.decs, sizeof(DevDecision) * nseg, hipMemcpyDeviceToHost, st));
     OKR_HIP(h, hipMemcpyAsync(hdrs.data(), p.hdrs, sizeof(SegHdr) * nseg, hipMemcpyDeviceToHost, st));
+    if (mixed)
+      OKR_HIP(h, hipMemcpyAsync(mstate.data(), p.mstate, sizeof(MixedState) * nseg, hipMemcpyDeviceToHost, st));
   }
   OKR_HIP(h, hipMemcpyAsync(sup.data(), p.St.sup, sizeof(int) * n, hipMemcpyDeviceToHost, st));
   OKR_HIP(h, hipMemcpyAsync(kp.data(), p.kp, sizeof(int) * n, hipMemcpyDeviceToHost, st));
@@ -587,6 +697,10 @@ extern "C" int okr_reduce_feeder(okr_handle* h, const okr_yblocks* Y, const okr_
     fl += 14.0 * hdrs[g].nz;
     R.flops = fl * double(int64_t(1) << k) * S;
     out->algorithmic_flops += R.flops;
+    if (mixed) {
+      R.n_refined = mstate[g].nA + mstate[g].nB;
+      R.fp32_dev = mstate[g].max_dev;
+    }
     if (timing) {
       float ms = 0.f;
       OKR_HIP(h, hipEventElapsedTime(&ms, h->ev[2 * g], h->ev[2 * g + 1]));
@@ -614,12 +728,20 @@ extern "C" int okr_reduce_feeder(okr_handle* h, const okr_yblocks* Y, const okr_
 
 extern "C" int okr_dump_scores(okr_handle* h, int32_t segment, double* e, double* slack, int32_t* k) {
   if (!h) return OKR_E_ARG;
-  if (segment < 0 || segment >= (int)h->dump.size() || h->dump[segment].empty())
-    OKR_FAIL(h, OKR_E_ARG, "no scores kept for segment %d (set OKR_FLAG_DUMP_SCORES)", segment);
+  const bool have = segment >= 0 && segment < (int)h->dump.size() &&
+                    (!h->dump[segment].empty() || (segment < (int)h->dump32.size() && !h->dump32[segment].empty()));
+  if (!have) OKR_FAIL(h, OKR_E_ARG, "no scores kept for segment %d (set OKR_FLAG_DUMP_SCORES)", segment);
   const std::vector<MaskScore>& d = h->dump[segment];
   for (size_t m = 0; m < d.size(); ++m) {
     if (e) e[m] = d[m].e;
     if (slack) slack[m] = d[m].slack;
+  }
+  if (d.empty() && segment < (int)h->dump32.size()) {
+    const std::vector<MaskScore32>& d32 = h->dump32[segment];
+    for (size_t m = 0; m < d32.size(); ++m) {
+      if (e) e[m] = d32[m].e;
+      if (slack) slack[m] = d32[m].slack;
+    }
   }
   if (k) *k = h->seg_off[segment + 1] - h->seg_off[segment];
   return OKR_OK;

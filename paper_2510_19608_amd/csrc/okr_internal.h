@@ -61,8 +61,9 @@ enum { C_HEAD = 0, C_NSLOT, C_SLOT0, C_NEST_OFF, C_NEST_LEN, C_PATH_OFF, C_PATH_
        C_ZOFF0, C_ZOFF1, C_ZOFF2, C_ZCNT0, C_ZCNT1, C_ZCNT2, C_OUTER, kChainInts };
 // slot record
 enum { SL_NODE = 0, SL_BIT, SL_PHASE, SL_PAIRBASE, SL_PATHPOS, SL_CHAIN, kSlotInts };
-// pair record: reduced slot node, first and last path index summed, chain path offset
-enum { PR_RNODE = 0, PR_FROM, PR_TO, PR_PATHOFF, kPairInts };
+// pair record: reduced slot node, first and last path index summed, chain path
+// offset, the super-node of the pair and the reduced slot's index
+enum { PR_RNODE = 0, PR_FROM, PR_TO, PR_PATHOFF, PR_SUPER, PR_RSLOT, kPairInts };
 
 // Per-slot and per-zone-entry numeric data for one snapshot and phase.
 struct TargetRec {
@@ -97,8 +98,41 @@ struct TileRec {
 };
 
 // Selection parameters shared by the scoring epilogue and the arg-min.
+// delta bounds |e32 - e64| and |slack32 - slack64| of the FP32 screening pass.
 struct SelParams {
-  double e_bar, vmin, vmax, tie, amb;
+  double e_bar, vmin, vmax, tie, amb, delta;
+};
+
+// ---- mixed precision (FP32 screening in difference form, FP64 refine) ----
+// Every error term is (FP64 difference rounded to FP32) +/- d, where
+// d = |W + S| - |W| = (2 Re(conj(W) S) + |S|^2) / (|W + S| + |W|) is the
+// FP32 voltage-magnitude change; so FP32 rounding acts on small quantities.
+struct Pair32 {      // per (snapshot, pair, phase)
+  float2 P;          // Z(super -> reduced) A_reduced
+  float a, b;        // |W_super| - lo_reduced, hi_reduced - |W_super|  (-inf on absent phases)
+};
+struct Rec32 {       // per (snapshot, slot or zone entry, phase)
+  float2 W;          // current voltage
+  float w;           // |W|
+  float a, b;        // w - lo, hi - w of the node's own cluster (-inf on absent phases)
+  float bmin, bmax;  // w - v_min, v_max - w (+inf on absent phases)
+  float pad;
+};
+struct Head32 {      // per (snapshot, chain, phase)
+  float2 W;
+  float w;
+  float pad;
+};
+struct MaskScore32 {
+  float e, slack;
+};
+struct TileRec32 {   // max popcount of sure-feasible / possibly-feasible / uncertain masks
+  int sure, poss, unc, pad;
+};
+struct MixedState {  // per segment: the screening levels and shortlist sizes
+  int lo_level, hi_level, best, nA, nB, pad;
+  double e_up;
+  double max_dev;    // max |e32 - e64| over refined masks with e64 <= 2 e_bar
 };
 
 }  // namespace okr

@@ -13,25 +13,9 @@
 #include <stdint.h>
 
 #include "okr_internal.h"
+#include "okr_device.h"
 
 namespace okr {
-
-// ---------------------------------------------------------------- complex --
-__device__ __forceinline__ double2 cadd(double2 a, double2 b) { return make_double2(a.x + b.x, a.y + b.y); }
-__device__ __forceinline__ double2 csub(double2 a, double2 b) { return make_double2(a.x - b.x, a.y - b.y); }
-__device__ __forceinline__ double2 cmul(double2 a, double2 b) {
-  return make_double2(a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x);
-}
-__device__ __forceinline__ double2 cconj(double2 a) { return make_double2(a.x, -a.y); }
-__device__ __forceinline__ double cabs2(double2 a) { return a.x * a.x + a.y * a.y; }
-__device__ __forceinline__ double2 cdiv(double2 a, double2 b) {
-  const double d = cabs2(b);
-  const double2 t = cmul(a, cconj(b));
-  return make_double2(t.x / d, t.y / d);
-}
-// Note: the bare v_sqrt_f64 instruction is accurate to only about 2^-27
-// relative, far outside the 1e-13 decision window; magnitudes in the scoring
-// use sqrt_nr() below, elsewhere the libm sqrt.
 
 // Restricted inverse of a 3x3 block on the phases in `mask` (zero-padded):
 // for blocks supported on the present-phase principal submatrix this is the
@@ -242,85 +226,6 @@ __global__ void k_from_vhat(int n, int S, const uint8_t* __restrict__ phase, con
 }
 
 // ---------------------------------------------------------------- scoring --
-// sqrt for arguments in the normal range (here |V|^2 of a bus voltage): the
-// hardware reciprocal-square-root estimate refined by Newton-Raphson steps in
-// Goldschmidt form (g -> sqrt(x), h -> 1/(2 sqrt(x))), two residual
-// corrections at the end.  No range scaling: callers pass x in [2^-500, 2^500].
-__device__ __forceinline__ double sqrt_nr(double x) {
-  const double r = __builtin_amdgcn_rsq(x);
-  double g = x * r, h = 0.5 * r;
-  const double e = fma(-h, g, 0.5);
-  g = fma(g, e, g);
-  h = fma(h, e, h);
-  double d = fma(-g, g, x);
-  g = fma(d, h, g);
-  d = fma(-g, g, x);
-  return fma(d, h, g);
-}
-__device__ __forceinline__ double vmag(double2 a) { return sqrt_nr(a.x * a.x + a.y * a.y); }
-
-// Walk one chain for one mask: super-node slots top to bottom; a reduced slot
-// adds the voltage rise of moving its aggregated current to its current super
-// (P from LDS); a kept slot becomes the super of the slots below it.  With
-// ERR, every slot cluster's error against its super's magnitude and the band
-// of kept slots are folded into (el, slack).  Slot records and head voltages
-// are wave-uniform and read with scalar loads; P entries depend on the lane's
-// super slot and come from LDS.
-template <bool ERR>
-__device__ __forceinline__ void walk_chain(const int* __restrict__ cr, const int* __restrict__ slots,
-                                           const double2* Ps, const TargetRec* __restrict__ Ss,
-                                           const double2* __restrict__ Hs, int c, uint32_t m, double2& B0,
-                                           double2& B1, double2& B2, double& el, double& slack, double vmin,
-                                           double vmax) {
-  double2 S0 = B0, S1 = B1, S2 = B2;
-  double sm0 = 0.0, sm1 = 0.0, sm2 = 0.0;
-  if (ERR) {
-    const double2* hv = Hs + c * 3;
-    sm0 = vmag(cadd(hv[0], B0));
-    sm1 = vmag(cadd(hv[1], B1));
-    sm2 = vmag(cadd(hv[2], B2));
-  }
-  const int ns = cr[C_NSLOT], s0 = cr[C_SLOT0];
-  int sidx = 0;
-  for (int r = 0; r < ns; ++r) {
-    const int* sr = slots + (s0 + r) * kSlotInts;
-    const int bit = sr[SL_BIT], pb = sr[SL_PAIRBASE];
-    const bool red = (m >> bit) & 1u;
-    const double rf = red ? 1.0 : 0.0;
-    const double2* pp = Ps + (pb + sidx) * 3;
-    const double2 p0 = pp[0], p1 = pp[1], p2 = pp[2];
-    S0.x = fma(rf, p0.x, S0.x); S0.y = fma(rf, p0.y, S0.y);
-    S1.x = fma(rf, p1.x, S1.x); S1.y = fma(rf, p1.y, S1.y);
-    S2.x = fma(rf, p2.x, S2.x); S2.y = fma(rf, p2.y, S2.y);
-    sidx = red ? sidx : r + 1;
-    if (ERR) {
-      const int ph = sr[SL_PHASE];
-      const TargetRec* tr = Ss + (s0 + r) * 3;
-#define OKR_SLOT_PHASE(P_, S_, SM_)                                              \
-      if (ph & (1 << P_)) {                                                      \
-        const TargetRec t = tr[P_];                                              \
-        const double mag = vmag(cadd(t.W, S_));                                  \
-        SM_ = red ? SM_ : mag;                                                   \
-        const double sk = fmin(mag - vmin, vmax - mag);                          \
-        slack = red ? slack : fmin(slack, sk);                                   \
-        el = fmax(el, fmax(SM_ - t.lo, t.hi - SM_));                             \
-      }
-      OKR_SLOT_PHASE(0, S0, sm0)
-      OKR_SLOT_PHASE(1, S1, sm1)
-      OKR_SLOT_PHASE(2, S2, sm2)
-#undef OKR_SLOT_PHASE
-    }
-  }
-  B0 = S0; B1 = S1; B2 = S2;
-}
-
-__device__ __forceinline__ bool feasible(const MaskScore& r, double e_bar) { return r.e <= e_bar && r.slack >= 0.0; }
-__device__ __forceinline__ bool near_boundary(const MaskScore& r, double e_bar, double amb) {
-  const bool rin = r.e <= e_bar - amb && r.slack >= amb;
-  const bool rout = r.e > e_bar + amb || r.slack < -amb;
-  return !rin && !rout;
-}
-
 // One lane scores one mask over the block's snapshot group: e = max error
 // over the affected nodes, slack = min band slack over their kept node-phases.
 // The last block of a 64-mask tile to finish (ticket counter) folds the
@@ -352,27 +257,7 @@ __global__ __launch_bounds__(kScoreBlock) void k_score_fp64(
     __syncthreads();
     const TargetRec* zrec_l = zrec + (size_t)l * H.nz;
     double el = econst[l];
-    for (int c = 0; c < H.nchains; ++c) {
-      const int* cr = chains + c * kChainInts;
-      double2 B0 = make_double2(0.0, 0.0), B1 = B0, B2 = B0;
-      const int nl = cr[C_NEST_LEN], no = cr[C_NEST_OFF];
-      for (int q = 0; q + 1 < nl; ++q) {
-        const int oc = nest[no + q];
-        walk_chain<false>(chains + oc * kChainInts, slots, Ps, Ss, Hs, oc, m, B0, B1, B2, el, slack, vmin, vmax);
-      }
-      walk_chain<true>(cr, slots, Ps, Ss, Hs, c, m, B0, B1, B2, el, slack, vmin, vmax);
-#define OKR_ZONE_PHASE(P_, B_)                                                   \
-      for (int q = cr[C_ZOFF0 + P_], qe = q + cr[C_ZCNT0 + P_]; q < qe; ++q) { \
-        const TargetRec t = zrec_l[q];                                           \
-        const double mag = vmag(cadd(t.W, B_));                                  \
-        el = fmax(el, fmax(mag - t.lo, t.hi - mag));                             \
-        slack = fmin(slack, fmin(mag - vmin, vmax - mag));                       \
-      }
-      OKR_ZONE_PHASE(0, B0)
-      OKR_ZONE_PHASE(1, B1)
-      OKR_ZONE_PHASE(2, B2)
-#undef OKR_ZONE_PHASE
-    }
+    score_snapshot(H, chains, slots, nest, Ps, Ss, Hs, zrec_l, m, vmin, vmax, el, slack);
     e = fmax(e, el);
     __syncthreads();
   }

@@ -1,0 +1,483 @@
+// Mixed-precision search of one segment: FP32 screening of every mask in
+// difference form, then FP64 rescoring of a shortlist that provably contains
+// every mask the FP64 decision depends on, so that the decision equals the
+// FP64 path's whenever |e32 - e64| <= delta and |slack32 - slack64| <= delta.
+//
+//   k_build_mixed    FP32 tables from the FP64 ones (P, cluster offsets)
+//   k_score_fp32     every mask, FP32; tile records of sure / possible /
+//                    uncertain feasibility (band delta + amb around e_bar and
+//                    the voltage band)
+//   k_mixed_select_a list A: uncertain masks at or above the best sure level
+//   k_refine_fp64    FP64 scores of a mask list (same arithmetic as the FP64
+//                    scoring kernel)
+//   k_mixed_select_b best level P*; list B: possibly feasible masks at P*
+//                    whose FP32 error is within tie + 2 delta + amb of the
+//                    smallest FP64-confirmed one
+//   k_mixed_final    FP64 arg-min over list B, ambiguity from A and B
+#include <hip/hip_runtime.h>
+#include <math.h>
+#include <stdint.h>
+
+#include "okr_device.h"
+#include "okr_internal.h"
+
+namespace okr {
+
+__global__ __launch_bounds__(256) void k_build_mixed(const SegHdr* __restrict__ hdrs, int g,
+                                                     const int* __restrict__ tab, int n,
+                                                     const double2* __restrict__ Vcur,
+                                                     const double2* __restrict__ P,
+                                                     const TargetRec* __restrict__ srec,
+                                                     const double2* __restrict__ headV,
+                                                     const TargetRec* __restrict__ zrec, double vmin, double vmax,
+                                                     Pair32* __restrict__ P32, Rec32* __restrict__ S32,
+                                                     Head32* __restrict__ H32, Rec32* __restrict__ Z32) {
+  const SegHdr H = hdrs[g];
+  if (!H.valid) return;
+  const int part = blockIdx.y, S = H.S;
+  const int stride = gridDim.x * blockDim.x;
+  const float NEG = -INFINITY, POS = INFINITY;
+  if (part == 0) {
+    for (int t = blockIdx.x * blockDim.x + threadIdx.x; t < S * H.npairs * 3; t += stride) {
+      const int l = t / (H.npairs * 3), rem = t % (H.npairs * 3), q = rem / 3, p = rem % 3;
+      const int* pr = tab + H.o_pair + q * kPairInts;
+      const double2 pv = P[((size_t)l * H.npairs + q) * 3 + p];
+      const TargetRec r = srec[((size_t)l * H.nslots + pr[PR_RSLOT]) * 3 + p];
+      Pair32 o;
+      o.P = make_float2((float)pv.x, (float)pv.y);
+      const int rphase = tab[H.o_slot + pr[PR_RSLOT] * kSlotInts + SL_PHASE];
+      if (rphase >> p & 1) {
+        const double ws = sqrt(cabs2(Vcur[((size_t)l * n + pr[PR_SUPER]) * 3 + p]));
+        o.a = (float)(ws - r.lo);
+        o.b = (float)(r.hi - ws);
+      } else {
+        o.a = NEG;
+        o.b = NEG;
+      }
+      P32[t] = o;
+    }
+  } else if (part == 1) {
+    for (int t = blockIdx.x * blockDim.x + threadIdx.x; t < S * H.nslots * 3; t += stride) {
+      const int s = (t / 3) % H.nslots, p = t % 3;
+      const TargetRec r = srec[t];
+      const int ph = tab[H.o_slot + s * kSlotInts + SL_PHASE];
+      const double w = sqrt(cabs2(r.W));
+      Rec32 o;
+      o.W = make_float2((float)r.W.x, (float)r.W.y);
+      o.w = (float)w;
+      o.pad = 0.f;
+      if (ph >> p & 1) {
+        o.a = (float)(w - r.lo);
+        o.b = (float)(r.hi - w);
+        o.bmin = (float)(w - vmin);
+        o.bmax = (float)(vmax - w);
+      } else {
+        o.a = NEG; o.b = NEG; o.bmin = POS; o.bmax = POS;
+      }
+      S32[t] = o;
+    }
+  } else if (part == 2) {
+    for (int t = blockIdx.x * blockDim.x + threadIdx.x; t < S * H.nchains * 3; t += stride) {
+      const double2 v = headV[t];
+      Head32 o;
+      o.W = make_float2((float)v.x, (float)v.y);
+      o.w = (float)sqrt(cabs2(v));
+      o.pad = 0.f;
+      H32[t] = o;
+    }
+  } else {
+    for (int t = blockIdx.x * blockDim.x + threadIdx.x; t < S * H.nz; t += stride) {
+      const TargetRec r = zrec[t];
+      const double w = sqrt(cabs2(r.W));
+      Rec32 o;
+      o.W = make_float2((float)r.W.x, (float)r.W.y);
+      o.w = (float)w;
+      o.a = (float)(w - r.lo);
+      o.b = (float)(r.hi - w);
+      o.bmin = (float)(w - vmin);
+      o.bmax = (float)(vmax - w);
+      o.pad = 0.f;
+      Z32[t] = o;
+    }
+  }
+}
+
+// d = |W + S| - |W| in difference form (w = |W| given).
+__device__ __forceinline__ float diff32(float2 W, float w, float2 S) {
+  const float vx = W.x + S.x, vy = W.y + S.y;
+  const float m = __builtin_sqrtf(vx * vx + vy * vy);
+  const float num = 2.f * (W.x * S.x + W.y * S.y) + (S.x * S.x + S.y * S.y);
+  return num / (m + w);
+}
+
+template <bool ERR>
+__device__ __forceinline__ void walk32(const int* __restrict__ cr, const int* __restrict__ slots, const Pair32* Ps,
+                                       const Rec32* __restrict__ Ss, const Head32* __restrict__ Hs, int c, uint32_t m,
+                                       float2& B0, float2& B1, float2& B2, float& el, float& slack) {
+  float2 S0 = B0, S1 = B1, S2 = B2;
+  float d0 = 0.f, d1 = 0.f, d2 = 0.f;  // d of the current super on each phase
+  if (ERR) {
+    const Head32* hv = Hs + c * 3;
+    d0 = diff32(hv[0].W, hv[0].w, B0);
+    d1 = diff32(hv[1].W, hv[1].w, B1);
+    d2 = diff32(hv[2].W, hv[2].w, B2);
+  }
+  const int ns = cr[C_NSLOT], s0 = cr[C_SLOT0];
+  int sidx = 0;
+  for (int r = 0; r < ns; ++r) {
+    const int* sr = slots + (s0 + r) * kSlotInts;
+    const int bit = sr[SL_BIT], pb = sr[SL_PAIRBASE];
+    const bool red = (m >> bit) & 1u;
+    const float rf = red ? 1.f : 0.f;
+    const Pair32* pp = Ps + (pb + sidx) * 3;
+    const Pair32 q0 = pp[0], q1 = pp[1], q2 = pp[2];
+    S0.x = fmaf(rf, q0.P.x, S0.x); S0.y = fmaf(rf, q0.P.y, S0.y);
+    S1.x = fmaf(rf, q1.P.x, S1.x); S1.y = fmaf(rf, q1.P.y, S1.y);
+    S2.x = fmaf(rf, q2.P.x, S2.x); S2.y = fmaf(rf, q2.P.y, S2.y);
+    if (ERR) {
+      const int ph = sr[SL_PHASE];
+      const Rec32* tr = Ss + (s0 + r) * 3;
+#define OKR_SLOT32(P_, S_, D_, Q_)                                              \
+      if (ph & (1 << P_)) {                                                     \
+        const Rec32 t = tr[P_];                                                 \
+        const float d = diff32(t.W, t.w, S_);                                   \
+        const float ek = fmaxf(t.a + d, t.b - d);                               \
+        const float er = fmaxf(Q_.a + D_, Q_.b - D_);                           \
+        el = fmaxf(el, red ? er : ek);                                          \
+        slack = red ? slack : fminf(slack, fminf(t.bmin + d, t.bmax - d));      \
+        D_ = red ? D_ : d;                                                      \
+      }
+      OKR_SLOT32(0, S0, d0, q0)
+      OKR_SLOT32(1, S1, d1, q1)
+      OKR_SLOT32(2, S2, d2, q2)
+#undef OKR_SLOT32
+    }
+    sidx = red ? sidx : r + 1;
+  }
+  B0 = S0; B1 = S1; B2 = S2;
+}
+
+__global__ __launch_bounds__(kScoreBlock) void k_score_fp32(
+    const SegHdr* __restrict__ hdrs, int g, const int* __restrict__ tab, const Pair32* __restrict__ P32,
+    const Rec32* __restrict__ S32, const Head32* __restrict__ H32, const Rec32* __restrict__ Z32,
+    const double* __restrict__ econst, int snaps_per_group, int SG, SelParams sp, MaskScore32* __restrict__ part,
+    MaskScore32* __restrict__ fin, TileRec32* __restrict__ tiles, int* __restrict__ tickets) {
+  __shared__ Pair32 Ps[kMaxPairs * 3];
+  __shared__ int ticket;
+  const SegHdr H = hdrs[g];
+  if (!H.valid) return;
+  const uint32_t m = blockIdx.x * kScoreBlock + threadIdx.x;
+  const int sg = blockIdx.y;
+  const int l0 = sg * snaps_per_group;
+  const int l1 = min(H.S, l0 + snaps_per_group);
+  const int* chains = tab + H.o_chain;
+  const int* slots = tab + H.o_slot;
+  const int* nest = tab + H.o_nest;
+  float e = 0.f, slack = INFINITY;
+  for (int l = l0; l < l1; ++l) {
+    const Pair32* Pl = P32 + (size_t)l * H.npairs * 3;
+    for (int q = threadIdx.x; q < H.npairs * 3; q += kScoreBlock) Ps[q] = Pl[q];
+    const Rec32* Ss = S32 + (size_t)l * H.nslots * 3;
+    const Head32* Hs = H32 + (size_t)l * H.nchains * 3;
+    const Rec32* Zl = Z32 + (size_t)l * H.nz;
+    __syncthreads();
+    float el = (float)econst[l];
+    for (int c = 0; c < H.nchains; ++c) {
+      const int* cr = chains + c * kChainInts;
+      float2 B0 = make_float2(0.f, 0.f), B1 = B0, B2 = B0;
+      const int nl = cr[C_NEST_LEN], no = cr[C_NEST_OFF];
+      for (int q = 0; q + 1 < nl; ++q) {
+        const int oc = nest[no + q];
+        walk32<false>(chains + oc * kChainInts, slots, Ps, Ss, Hs, oc, m, B0, B1, B2, el, slack);
+      }
+      walk32<true>(cr, slots, Ps, Ss, Hs, c, m, B0, B1, B2, el, slack);
+#define OKR_ZONE32(P_, B_)                                                       \
+      for (int q = cr[C_ZOFF0 + P_], qe = q + cr[C_ZCNT0 + P_]; q < qe; ++q) { \
+        const Rec32 t = Zl[q];                                                   \
+        const float d = diff32(t.W, t.w, B_);                                    \
+        el = fmaxf(el, fmaxf(t.a + d, t.b - d));                                 \
+        slack = fminf(slack, fminf(t.bmin + d, t.bmax - d));                     \
+      }
+      OKR_ZONE32(0, B0)
+      OKR_ZONE32(1, B1)
+      OKR_ZONE32(2, B2)
+#undef OKR_ZONE32
+    }
+    e = fmaxf(e, el);
+    __syncthreads();
+  }
+  const uint32_t nmask = 1u << H.k;
+  const bool valid = m < nmask;
+  if (valid) {
+    MaskScore32 r;
+    r.e = e;
+    r.slack = slack;
+    part[(size_t)sg * nmask + m] = r;
+  }
+  __threadfence();
+  if (threadIdx.x == 0) ticket = atomicAdd(&tickets[blockIdx.x], 1);
+  __syncthreads();
+  if (ticket != SG - 1) return;
+  MaskScore32 r;
+  r.e = 0.f;
+  r.slack = INFINITY;
+  if (valid) {
+    for (int q = 0; q < SG; ++q) {
+      const volatile MaskScore32* x = part + (size_t)q * nmask + m;
+      r.e = fmaxf(r.e, x->e);
+      r.slack = fminf(r.slack, x->slack);
+    }
+    fin[m] = r;
+  }
+  const double dd = sp.delta + sp.amb;
+  const bool sure = valid && (double)r.e <= sp.e_bar - dd && (double)r.slack >= dd;
+  const bool poss = valid && (double)r.e <= sp.e_bar + dd && (double)r.slack >= -dd;
+  const int pc = __popc(m);
+  int a = sure ? pc : -1, b = poss ? pc : -1, c = (poss && !sure) ? pc : -1;
+  for (int o = 32; o > 0; o >>= 1) {
+    a = max(a, __shfl_xor(a, o, 64));
+    b = max(b, __shfl_xor(b, o, 64));
+    c = max(c, __shfl_xor(c, o, 64));
+  }
+  if (threadIdx.x == 0) {
+    TileRec32 t;
+    t.sure = a;
+    t.poss = b;
+    t.unc = c;
+    t.pad = 0;
+    tiles[blockIdx.x] = t;
+    tickets[blockIdx.x] = 0;
+  }
+}
+
+template <typename T, typename Op>
+__device__ T breduce(T v, Op op, T* sh) {
+  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6, nw = (blockDim.x + 63) >> 6;
+  for (int o = 32; o > 0; o >>= 1) v = op(v, __shfl_xor(v, o, 64));
+  __syncthreads();
+  if (lane == 0) sh[wid] = v;
+  __syncthreads();
+  T r = sh[0];
+  for (int w = 1; w < nw; ++w) r = op(r, sh[w]);
+  __syncthreads();
+  return r;
+}
+
+__device__ __forceinline__ bool skip_segment(const SegHdr& H, const int* status) {
+  return !H.valid || (*status & (16 | 32));
+}
+
+// List A: masks whose FP32 verdict is uncertain, at or above the best level
+// holding a surely feasible mask.
+__global__ __launch_bounds__(1024) void k_mixed_select_a(const SegHdr* __restrict__ hdrs, int g,
+                                                         const MaskScore32* __restrict__ fin,
+                                                         const TileRec32* __restrict__ tiles, SelParams sp,
+                                                         const int* __restrict__ status, MixedState* __restrict__ ms,
+                                                         uint32_t* __restrict__ listA, int* __restrict__ countA) {
+  __shared__ int shi[16];
+  __shared__ int cnt;
+  const SegHdr H = hdrs[g];
+  if (threadIdx.x == 0) cnt = 0;
+  if (skip_segment(H, status)) {
+    if (threadIdx.x == 0) { *countA = 0; ms[g].lo_level = -1; ms[g].hi_level = -1; }
+    return;
+  }
+  const uint32_t nm = 1u << H.k;
+  const int ntiles = (int)((nm + 63) / 64);
+  int lo = -1, hi = -1;
+  for (int t = threadIdx.x; t < ntiles; t += blockDim.x) {
+    lo = max(lo, tiles[t].sure);
+    hi = max(hi, tiles[t].poss);
+  }
+  lo = breduce(lo, [](int a, int b) { return max(a, b); }, shi);
+  hi = breduce(hi, [](int a, int b) { return max(a, b); }, shi);
+  const double dd = sp.delta + sp.amb;
+  for (int t = threadIdx.x; t < ntiles; t += blockDim.x) {
+    if (tiles[t].unc < lo || tiles[t].unc < 0) continue;
+    for (int j = 0; j < 64; ++j) {
+      const uint32_t mm = (uint32_t)t * 64 + j;
+      if (mm >= nm) break;
+      const MaskScore32 r = fin[mm];
+      const bool sure = (double)r.e <= sp.e_bar - dd && (double)r.slack >= dd;
+      const bool poss = (double)r.e <= sp.e_bar + dd && (double)r.slack >= -dd;
+      if (poss && !sure && __popc(mm) >= lo) listA[atomicAdd(&cnt, 1)] = mm;
+    }
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    *countA = cnt;
+    ms[g].lo_level = lo;
+    ms[g].hi_level = hi;
+    ms[g].nA = cnt;
+  }
+}
+
+// FP64 scores of the masks in `list` (all snapshots), with the arithmetic of
+// the FP64 scoring kernel.
+__global__ __launch_bounds__(kScoreBlock) void k_refine_fp64(
+    const SegHdr* __restrict__ hdrs, int g, const int* __restrict__ tab, const double2* __restrict__ P,
+    const TargetRec* __restrict__ srec, const double2* __restrict__ headV, const TargetRec* __restrict__ zrec,
+    const double* __restrict__ econst, SelParams sp, const uint32_t* __restrict__ list,
+    const int* __restrict__ count, MaskScore* __restrict__ out) {
+  __shared__ double2 Ps[kMaxPairs * 3];
+  const SegHdr H = hdrs[g];
+  if (!H.valid) return;
+  const int cnt = *count;
+  const int* chains = tab + H.o_chain;
+  const int* slots = tab + H.o_slot;
+  const int* nest = tab + H.o_nest;
+  for (int base = blockIdx.x * kScoreBlock; base < cnt; base += gridDim.x * kScoreBlock) {
+    const int idx = base + threadIdx.x;
+    const uint32_t m = idx < cnt ? list[idx] : 0u;
+    double e = 0.0, slack = INFINITY;
+    for (int l = 0; l < H.S; ++l) {
+      const double2* Pl = P + (size_t)l * H.npairs * 3;
+      for (int q = threadIdx.x; q < H.npairs * 3; q += kScoreBlock) Ps[q] = Pl[q];
+      __syncthreads();
+      double el = econst[l];
+      score_snapshot(H, chains, slots, nest, Ps, srec + (size_t)l * H.nslots * 3,
+                     headV + (size_t)l * H.nchains * 3, zrec + (size_t)l * H.nz, m, sp.vmin, sp.vmax, el, slack);
+      e = fmax(e, el);
+      __syncthreads();
+    }
+    if (idx < cnt) {
+      MaskScore r;
+      r.e = e;
+      r.slack = slack;
+      out[idx] = r;
+    }
+  }
+}
+
+// Best level P* and list B.
+__global__ __launch_bounds__(1024) void k_mixed_select_b(const SegHdr* __restrict__ hdrs, int g,
+                                                         const MaskScore32* __restrict__ fin,
+                                                         const TileRec32* __restrict__ tiles, SelParams sp,
+                                                         const int* __restrict__ status, MixedState* __restrict__ ms,
+                                                         const uint32_t* __restrict__ listA,
+                                                         const int* __restrict__ countA,
+                                                         const MaskScore* __restrict__ scoreA,
+                                                         uint32_t* __restrict__ listB, int* __restrict__ countB) {
+  __shared__ int shi[16];
+  __shared__ double shd[16];
+  __shared__ int cnt;
+  const SegHdr H = hdrs[g];
+  if (threadIdx.x == 0) cnt = 0;
+  if (skip_segment(H, status)) {
+    if (threadIdx.x == 0) { *countB = 0; ms[g].best = -1; }
+    return;
+  }
+  const uint32_t nm = 1u << H.k;
+  const int ntiles = (int)((nm + 63) / 64);
+  const double dd = sp.delta + sp.amb;
+  const int nA = *countA;
+  int best = ms[g].lo_level;
+  for (int q = threadIdx.x; q < nA; q += blockDim.x)
+    if (feasible(scoreA[q], sp.e_bar)) best = max(best, __popc(listA[q]));
+  best = breduce(best, [](int a, int b) { return max(a, b); }, shi);
+  // upper bound on the smallest FP64 error at level best
+  double eup = INFINITY;
+  if (best >= 0) {
+    for (int t = threadIdx.x; t < ntiles; t += blockDim.x) {
+      if (tiles[t].sure < best) continue;
+      for (int j = 0; j < 64; ++j) {
+        const uint32_t mm = (uint32_t)t * 64 + j;
+        if (mm >= nm) break;
+        const MaskScore32 r = fin[mm];
+        if (__popc(mm) == best && (double)r.e <= sp.e_bar - dd && (double)r.slack >= dd)
+          eup = fmin(eup, (double)r.e + sp.delta);
+      }
+    }
+    for (int q = threadIdx.x; q < nA; q += blockDim.x)
+      if (__popc(listA[q]) == best && feasible(scoreA[q], sp.e_bar)) eup = fmin(eup, scoreA[q].e);
+  }
+  eup = breduce(eup, [](double a, double b) { return fmin(a, b); }, shd);
+  const double bound = eup + sp.tie + sp.delta + sp.amb;
+  if (best >= 0) {
+    for (int t = threadIdx.x; t < ntiles; t += blockDim.x) {
+      if (tiles[t].poss < best) continue;
+      for (int j = 0; j < 64; ++j) {
+        const uint32_t mm = (uint32_t)t * 64 + j;
+        if (mm >= nm) break;
+        const MaskScore32 r = fin[mm];
+        const bool poss = (double)r.e <= sp.e_bar + dd && (double)r.slack >= -dd;
+        if (poss && __popc(mm) == best && (double)r.e <= bound) listB[atomicAdd(&cnt, 1)] = mm;
+      }
+    }
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    *countB = cnt;
+    ms[g].best = best;
+    ms[g].nB = cnt;
+    ms[g].e_up = eup;
+  }
+}
+
+// FP64 arg-min over list B; ambiguity from the FP64 scores of A and B; the
+// largest FP32 deviation seen on refined masks is kept for reporting.
+__global__ __launch_bounds__(1024) void k_mixed_final(const SegHdr* __restrict__ hdrs, int g, SelParams sp,
+                                                      const int* __restrict__ status, MixedState* __restrict__ ms,
+                                                      const MaskScore32* __restrict__ fin,
+                                                      const uint32_t* __restrict__ listA, const int* __restrict__ countA,
+                                                      const MaskScore* __restrict__ scoreA,
+                                                      const uint32_t* __restrict__ listB, const int* __restrict__ countB,
+                                                      const MaskScore* __restrict__ scoreB,
+                                                      DevDecision* __restrict__ decs) {
+  __shared__ double shd[16];
+  __shared__ int shi[16];
+  __shared__ unsigned shu[16];
+  const SegHdr H = hdrs[g];
+  DevDecision* dec = decs + g;
+  const int best = ms[g].best;
+  if (skip_segment(H, status) || best < 0) {
+    if (threadIdx.x == 0) {
+      DevDecision d;
+      d.mask = 0; d.popcount = 0; d.e_loc = 0.0; d.e_min = 0.0; d.ambiguous = skip_segment(H, status) ? 0 : 1;
+      d.found = 0;
+      *dec = d;
+    }
+    return;
+  }
+  const int nA = *countA, nB = *countB;
+  double emin = INFINITY, dev = 0.0;
+  for (int q = threadIdx.x; q < nB; q += blockDim.x) {
+    const MaskScore r = scoreB[q];
+    if (feasible(r, sp.e_bar)) emin = fmin(emin, r.e);
+    if (r.e <= 2.0 * sp.e_bar) dev = fmax(dev, fabs((double)fin[listB[q]].e - r.e));
+  }
+  emin = breduce(emin, [](double a, double b) { return fmin(a, b); }, shd);
+  const double thr = emin + sp.tie;
+  unsigned pick = 0xffffffffu;
+  int amb = 0;
+  for (int q = threadIdx.x; q < nB; q += blockDim.x) {
+    const MaskScore r = scoreB[q];
+    if (!feasible(r, sp.e_bar)) continue;
+    if (fabs(r.e - thr) <= sp.amb) amb = 1;
+    if (r.e <= thr) pick = min(pick, listB[q]);
+  }
+  for (int q = threadIdx.x; q < nA; q += blockDim.x) {
+    const MaskScore r = scoreA[q];
+    if (__popc(listA[q]) >= best && near_boundary(r, sp.e_bar, sp.amb)) amb = 1;
+    if (r.e <= 2.0 * sp.e_bar) dev = fmax(dev, fabs((double)fin[listA[q]].e - r.e));
+  }
+  pick = breduce(pick, [](unsigned a, unsigned b) { return min(a, b); }, shu);
+  amb = breduce(amb, [](int a, int b) { return a | b; }, shi);
+  dev = breduce(dev, [](double a, double b) { return fmax(a, b); }, shd);
+  if (threadIdx.x == 0) {
+    DevDecision d;
+    double epick = 0.0;
+    for (int q = 0; q < nB; ++q)
+      if (listB[q] == pick) epick = scoreB[q].e;
+    d.mask = pick == 0xffffffffu ? 0u : pick;
+    d.popcount = best;
+    d.e_loc = epick;
+    d.e_min = emin;
+    d.ambiguous = amb;
+    d.found = pick != 0xffffffffu;
+    *dec = d;
+    ms[g].max_dev = dev;
+  }
+}
+
+}  // namespace okr

@@ -226,3 +226,55 @@ def test_graph_replay_matches_stream_run(okr):
             (x * 2).sum().item()
     finally:
         R.close()
+
+
+MIXED_DELTA = 1e-8
+
+
+@pytest.mark.parametrize("name,seed,e_bar,band", [("c1", 0, 3e-4, None), ("c1", 3, 1e-4, None),
+                                                  ("c1", 5, 3e-3, None), ("ms", 1, 3e-4, None),
+                                                  ("ms", 4, 3e-3, 2e-4), ("ms", 6, 3e-4, 5e-4),
+                                                  ("c2", 0, 3e-3, None), ("c2", 0, 3e-4, None)])
+def test_mixed_precision_decisions_equal_fp64(okr, name, seed, e_bar, band):
+    """FP32 screening + FP64 refinement of the shortlist: identical decisions
+    and outputs to the FP64 path and the oracle; the FP32 error stays within
+    the shortlist bound."""
+    _say(f"mixed {name} seed={seed} e_bar={e_bar} band={band}")
+    if name == "ms":
+        f = make_feeder("c1", seed, n=40, n_eligible=None, seg_size=(4, 7), snapshots=3,
+                        scale=(0.3, 1.0), e_bar=e_bar)
+    else:
+        f = make_feeder(name, seed, e_bar=e_bar)
+    if band is not None:
+        V, _, _, _ = oracle.powerflow(f)
+        pres = np.array([[(int(m) >> p) & 1 for p in range(3)] for m in f["phase"]], bool)
+        f = dict(f, v_min=float(np.abs(V)[:, pres].min()) - band)
+    V, I, keep, dec, st = oracle_run(f)
+    a = okr.reduce_feeder(f, precision="fp64")
+    b = okr.reduce_feeder(f, precision="mixed")
+    check_outputs(f, b, V, I, keep, dec)
+    assert [s["mask"] for s in a["segments"]] == [s["mask"] for s in b["segments"]]
+    for sa, sb in zip(a["segments"], b["segments"]):
+        assert sa["e_loc"] == sb["e_loc"]  # the decision's error is the FP64 value
+        assert sb["fp32_dev"] <= MIXED_DELTA
+    np.testing.assert_array_equal(a["Yk_diag"], b["Yk_diag"])
+    np.testing.assert_array_equal(a["err_per_snapshot"], b["err_per_snapshot"])
+
+
+@pytest.mark.parametrize("name,seed,e_bar", [("c1", 2, 3e-4), ("c2", 1, 3e-3)])
+def test_fp32_screening_error_bound(okr, name, seed, e_bar):
+    """Every mask's FP32 difference-form error and band slack against the FP64
+    kernel's, for masks with e64 <= 2 e_bar: within the shortlist bound."""
+    f = make_feeder(name, seed, e_bar=e_bar)
+    a = okr.reduce_feeder(f, precision="fp64", dump=True)
+    b = okr.reduce_feeder(f, precision="mixed", dump=True)
+    worst_e = worst_s = 0.0
+    for g in range(len(a["segments"])):
+        e64, s64, _ = a["scores"][g]
+        e32, s32, _ = b["scores"][g]
+        sel = e64 <= 2 * e_bar
+        worst_e = max(worst_e, np.abs(e32[sel] - e64[sel]).max(initial=0.0))
+        fin = sel & np.isfinite(s64)
+        worst_s = max(worst_s, np.abs(s32[fin] - s64[fin]).max(initial=0.0))
+    _say(f"fp32 screening worst |de| = {worst_e:.3e}, |dslack| = {worst_s:.3e}")
+    assert worst_e <= MIXED_DELTA and worst_s <= MIXED_DELTA
