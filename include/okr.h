@@ -123,7 +123,10 @@ typedef struct {
     int32_t pf_maxit; /* load-flow iteration cap (100) */
     int32_t precision;/* OKR_PRECISION_* */
     uint32_t flags;   /* OKR_FLAG_* */
-    int32_t reserved;
+    int32_t top_k;    /* > 0 with `surrogate`: rescore only the top_k masks the
+                         surrogate ranks first (full enumeration as fallback) */
+    const float *surrogate; /* DEVICE FP32 parameters of the surrogate MLP
+                               (layout in okr_train_surrogate), or NULL */
 } okr_margins;
 
 /* Sizes okr_plan() reports. */
@@ -157,6 +160,10 @@ typedef struct {
     double *err_per_snapshot;/* [S] max error over all nodes of the final reduction */
     double *Vhat;            /* [S][n][3] complex128 scenario voltages, or NULL */
     okr_segment_result *seg; /* [n_segments] */
+    float *features;         /* DEVICE [n_candidates][32] or NULL: per-mask surrogate
+                                features of every segment, in segment then mask order */
+    float *targets;          /* DEVICE [n_candidates] or NULL: ln(e_loc + 1e-12) of
+                                every mask (FP64 scores); needs precision FP64 */
     int32_t n_kept;
     int32_t warnings;        /* OKR_W_* bits seen */
     double max_err;
@@ -185,6 +192,36 @@ int okr_reduce_feeder(okr_handle *h, const okr_yblocks *Y, const okr_topology *t
 /* With OKR_FLAG_DUMP_SCORES: copy segment `segment`'s per-mask error and band
  * slack from the last call (HOST double[2^k] each) and return k through *k. */
 int okr_dump_scores(okr_handle *h, int32_t segment, double *e, double *slack, int32_t *k);
+
+/* Surrogate MLP (learned pruning).  Parameters are one FP32 buffer in
+ * [out][in] layout: W1[256][32] b1[256] W2[256][256] b2[256] w3[256] b3[1]
+ * (OKR_SURR_PARAMS floats).  The network maps 32 per-mask features (from
+ * okr_result.features) through two GELU layers to y = ln(e_loc + 1e-12); its
+ * GEMMs run on MFMA with BF16 operands and FP32 accumulation. */
+#define OKR_SURR_FEATURES 32
+#define OKR_SURR_PARAMS (256 * 32 + 256 + 256 * 256 + 256 + 256 + 1)
+
+/* Device workspace bytes for okr_train_surrogate / okr_surrogate_grad /
+ * okr_surrogate_forward with batches of `batch` rows (a multiple of 64). */
+int okr_surrogate_workspace(int32_t batch, size_t *bytes);
+
+/* Train in place (DEVICE params, Adam, mean-squared error) on n rows of
+ * features X (DEVICE float [n][32]) and targets t (DEVICE float [n]) for
+ * `epochs` passes of whole batches in an order drawn from `seed`; writes the
+ * mean loss of each epoch to loss (HOST float [epochs]).  Synchronous. */
+int okr_train_surrogate(const float *X, const float *t, int64_t n, int32_t epochs, int32_t batch, float lr,
+                        uint64_t seed, float *params, void *work, size_t work_bytes, void *hip_stream,
+                        float *loss);
+
+/* Loss gradient of one batch (B rows, a multiple of 64) into grads (DEVICE
+ * float [OKR_SURR_PARAMS]); the batch loss to *loss (HOST).  Synchronous. */
+int okr_surrogate_grad(const float *params, const float *X, const float *t, int32_t B, float *grads,
+                       float *loss, void *work, size_t work_bytes, void *hip_stream);
+
+/* Predictions y (DEVICE float [n]) for features X (DEVICE float [n][32]),
+ * n a multiple of 64 (at most the workspace batch).  Synchronous. */
+int okr_surrogate_forward(const float *params, const float *X, int64_t n, float *y, void *work,
+                          size_t work_bytes, void *hip_stream);
 
 int okr_destroy(okr_handle *h);
 const char *okr_last_error(const okr_handle *h);

@@ -4,8 +4,10 @@ The compute path is the HIP library ``libokr.so`` behind the C ABI declared in
 ``include/okr.h``; ``binding`` marshals arguments into it.  There is no CPU
 fallback: without the built library or a GPU the calls raise.
 """
-from .binding import (OKR, OkrError, Reducer, lib, okr_create, okr_destroy, okr_dump_scores,
-                      okr_last_error, okr_plan, okr_reduce_feeder, reduce_feeder)
+from .binding import (OKR, SURR_FEATURES, SURR_PARAMS, OkrError, Reducer, lib, okr_create, okr_destroy,
+                      okr_dump_scores, okr_last_error, okr_plan, okr_reduce_feeder, okr_surrogate_forward,
+                      okr_surrogate_grad, okr_surrogate_workspace, okr_train_surrogate, reduce_feeder)
 
-__all__ = ["OKR", "OkrError", "Reducer", "lib", "okr_create", "okr_destroy", "okr_dump_scores",
-           "okr_last_error", "okr_plan", "okr_reduce_feeder", "reduce_feeder"]
+__all__ = ["OKR", "SURR_FEATURES", "SURR_PARAMS", "OkrError", "Reducer", "lib", "okr_create", "okr_destroy",
+           "okr_dump_scores", "okr_last_error", "okr_plan", "okr_reduce_feeder", "okr_surrogate_forward",
+           "okr_surrogate_grad", "okr_surrogate_workspace", "okr_train_surrogate", "reduce_feeder"]

@@ -59,7 +59,7 @@ class Margins(ctypes.Structure):
     _fields_ = [("e_bar", ctypes.c_double), ("v_min", ctypes.c_double), ("v_max", ctypes.c_double),
                 ("tie_tol", ctypes.c_double), ("amb_tol", ctypes.c_double), ("pf_tol", ctypes.c_double),
                 ("pf_maxit", ctypes.c_int32), ("precision", ctypes.c_int32), ("flags", ctypes.c_uint32),
-                ("reserved", ctypes.c_int32)]
+                ("top_k", ctypes.c_int32), ("surrogate", ctypes.c_void_p)]
 
 
 class Sizes(ctypes.Structure):
@@ -76,7 +76,8 @@ class SegmentResult(ctypes.Structure):
 class Result(ctypes.Structure):
     _fields_ = [("super", ctypes.c_void_p), ("kept_parent", ctypes.c_void_p), ("Yk_diag", ctypes.c_void_p),
                 ("Yk_off", ctypes.c_void_p), ("err_per_snapshot", ctypes.c_void_p), ("Vhat", ctypes.c_void_p),
-                ("seg", ctypes.c_void_p), ("n_kept", ctypes.c_int32), ("warnings", ctypes.c_int32),
+                ("seg", ctypes.c_void_p), ("features", ctypes.c_void_p), ("targets", ctypes.c_void_p),
+                ("n_kept", ctypes.c_int32), ("warnings", ctypes.c_int32),
                 ("max_err", ctypes.c_double), ("t_setup_ms", ctypes.c_double), ("t_pf_ms", ctypes.c_double),
                 ("t_search_ms", ctypes.c_double), ("t_final_ms", ctypes.c_double),
                 ("score_kernel_ms", ctypes.c_double), ("algorithmic_flops", ctypes.c_double),
@@ -104,7 +105,15 @@ def lib():
         L.okr_destroy.argtypes = [vp]
         L.okr_last_error.argtypes = [vp]
         L.okr_last_error.restype = ctypes.c_char_p
-        for fn in ("okr_create", "okr_plan", "okr_reduce_feeder", "okr_dump_scores", "okr_destroy"):
+        L.okr_surrogate_workspace.argtypes = [ctypes.c_int32, ctypes.POINTER(ctypes.c_size_t)]
+        L.okr_train_surrogate.argtypes = [vp, vp, ctypes.c_int64, ctypes.c_int32, ctypes.c_int32, ctypes.c_float,
+                                          ctypes.c_uint64, vp, vp, ctypes.c_size_t, vp, vp]
+        L.okr_surrogate_grad.argtypes = [vp, vp, vp, ctypes.c_int32, vp, ctypes.POINTER(ctypes.c_float), vp,
+                                         ctypes.c_size_t, vp]
+        L.okr_surrogate_forward.argtypes = [vp, vp, ctypes.c_int64, vp, vp, ctypes.c_size_t, vp]
+        for fn in ("okr_create", "okr_plan", "okr_reduce_feeder", "okr_dump_scores", "okr_destroy",
+                   "okr_surrogate_workspace", "okr_train_surrogate", "okr_surrogate_grad",
+                   "okr_surrogate_forward"):
             getattr(L, fn).restype = ctypes.c_int
         _lib = L
     return _lib
@@ -156,11 +165,62 @@ def okr_destroy(h):
     return lib().okr_destroy(h)
 
 
+SURR_FEATURES = 32
+SURR_HIDDEN = 256
+SURR_PARAMS = 256 * 32 + 256 + 256 * 256 + 256 + 256 + 1
+
+
+def _ptr(t):
+    return ctypes.c_void_p(t.data_ptr())
+
+
+def _stream_of(t):
+    import torch
+    return ctypes.c_void_p(torch.cuda.current_stream(t.device).cuda_stream)
+
+
+def _free_check(rc, what):
+    if rc != 0:
+        raise OkrError(rc, what)
+
+
+def okr_surrogate_workspace(batch):
+    b = ctypes.c_size_t(0)
+    _free_check(lib().okr_surrogate_workspace(batch, ctypes.byref(b)), f"bad surrogate batch {batch}")
+    return b.value
+
+
+def okr_train_surrogate(X, t, epochs, batch, lr, seed, params, work):
+    """Train ``params`` in place (device tensors: X float [n][32], t float [n],
+    params float [SURR_PARAMS], work uint8); returns the per-epoch mean loss."""
+    loss = np.zeros(epochs, np.float32)
+    rc = lib().okr_train_surrogate(_ptr(X), _ptr(t), X.shape[0], epochs, batch, lr, seed, _ptr(params), _ptr(work),
+                                   work.numel(), _stream_of(X), loss.ctypes.data)
+    _free_check(rc, "okr_train_surrogate failed")
+    return loss
+
+
+def okr_surrogate_grad(params, X, t, grads, work):
+    """Loss gradient of one batch into ``grads``; returns the batch loss."""
+    loss = ctypes.c_float(0.0)
+    rc = lib().okr_surrogate_grad(_ptr(params), _ptr(X), _ptr(t), X.shape[0], _ptr(grads), ctypes.byref(loss),
+                                  _ptr(work), work.numel(), _stream_of(X))
+    _free_check(rc, "okr_surrogate_grad failed")
+    return loss.value
+
+
+def okr_surrogate_forward(params, X, y, work):
+    rc = lib().okr_surrogate_forward(_ptr(params), _ptr(X), X.shape[0], _ptr(y), _ptr(work), work.numel(),
+                                     _stream_of(X))
+    _free_check(rc, "okr_surrogate_forward failed")
+    return y
+
+
 # ---- conveniences ----------------------------------------------------------
 
 def make_margins(f=None, *, e_bar=None, v_min=None, v_max=None, tie_tol=1e-11, amb_tol=1e-13,
                  precision="fp64", timing=False, dump=False, vhat_given=False, graph=False, pf_tol=1e-13,
-                 pf_maxit=100):
+                 pf_maxit=100, top_k=0, surrogate=None):
     f = f or {}
     flags = (OKR.FLAG_TIMING if timing else 0) | (OKR.FLAG_DUMP_SCORES if dump else 0) | \
             (OKR.FLAG_VHAT_GIVEN if vhat_given else 0) | (OKR.FLAG_GRAPH if graph else 0)
@@ -169,7 +229,8 @@ def make_margins(f=None, *, e_bar=None, v_min=None, v_max=None, tie_tol=1e-11, a
                    v_max=f.get("v_max", 1.05) if v_max is None else v_max,
                    tie_tol=tie_tol, amb_tol=amb_tol, pf_tol=pf_tol, pf_maxit=pf_maxit,
                    precision={"fp64": OKR.PRECISION_FP64, "mixed": OKR.PRECISION_MIXED}[precision],
-                   flags=flags, reserved=0)
+                   flags=flags, top_k=top_k,
+                   surrogate=None if surrogate is None else surrogate.data_ptr())
 
 
 class Reducer:
@@ -177,6 +238,8 @@ class Reducer:
     okr_reduce_feeder on demand (``run``)."""
 
     def __init__(self, f, device="cuda:0", vhat=None, **margin_kw):
+        """margin_kw: make_margins' keywords; ``surrogate`` (a device tensor of
+        SURR_PARAMS floats) with ``top_k`` enables learned pruning."""
         import torch
         if not torch.cuda.is_available():
             raise OkrError(OKR.E_HIP, "no GPU visible: the search runs only on the HIP device")
@@ -192,6 +255,7 @@ class Reducer:
         self.segment = np.ascontiguousarray(f["segment"], dtype=np.int32)
         self.topo = Topology(n, self.parent.ctypes.data, self.phase.ctypes.data, self.eligible.ctypes.data,
                              self.segment.ctypes.data)
+        self.surrogate = margin_kw.get("surrogate")  # keeps the parameters alive
         self.margins = make_margins(f, vhat_given=vhat is not None, **margin_kw)
 
         def dev(a):
@@ -223,11 +287,31 @@ class Reducer:
                           self.out_Yko.ctypes.data, self.out_err.ctypes.data, None,
                           ctypes.cast(self.out_seg, ctypes.c_void_p))
 
-    def run(self, replan=True, want_vhat=False):
-        """One pass of the whole search (planning included when replan)."""
+    def set_surrogate(self, params, top_k):
+        """Switch learned pruning on (params: device tensor) or off (None);
+        top_k must not exceed the value planned with."""
+        self.surrogate = params
+        self.margins.surrogate = None if params is None else params.data_ptr()
+        self.margins.top_k = top_k if params is not None else 0
+
+    def run(self, replan=True, want_vhat=False, want_features=False):
+        """One pass of the whole search (planning included when replan).  With
+        want_features the per-mask surrogate features and FP64 targets of every
+        segment are left in ``self.features`` / ``self.targets`` (device)."""
         if replan:
             self.ws_bytes_now, _ = okr_plan(self.h, self.topo, self.margins, self.S)
         self.res.Vhat = self.out_Vhat.ctypes.data if want_vhat else None
+        if want_features:
+            nc = int(self.sizes.n_candidates)
+            if getattr(self, "features", None) is None or self.features.shape[0] != nc:
+                self.features = self.torch.zeros((nc, SURR_FEATURES), dtype=self.torch.float32,
+                                                 device=self.device)
+                self.targets = self.torch.zeros(nc, dtype=self.torch.float32, device=self.device)
+            self.res.features = self.features.data_ptr()
+            self.res.targets = self.targets.data_ptr()
+        else:
+            self.res.features = None
+            self.res.targets = None
         rc = okr_reduce_feeder(self.h, self.Y, self.topo, self.loads, self.margins,
                                ctypes.c_void_p(self.ws.data_ptr()), self.ws_bytes, self.res)
         return rc

@@ -5,7 +5,7 @@ import subprocess
 HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libokr.so")
-SOURCES = ["okr_kernels.hip", "okr_build.hip", "okr_mixed.hip", "okr_host.cpp"]
+SOURCES = ["okr_kernels.hip", "okr_build.hip", "okr_mixed.hip", "okr_surrogate.hip", "okr_host.cpp"]
 FLAGS = [
     "--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC", "-shared",
     # no packed-FP32 instructions anywhere in the device code

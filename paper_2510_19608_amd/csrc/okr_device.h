@@ -137,4 +137,34 @@ __device__ __forceinline__ void score_snapshot(const SegHdr& H, const int* __res
   }
 }
 
+// ------------------------------------------------------------ block reduce --
+template <typename T, typename Op>
+__device__ T block_reduce(T v, Op op, T* sh) {
+  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6, nw = (blockDim.x + 63) >> 6;
+  for (int o = 32; o > 0; o >>= 1) v = op(v, __shfl_xor(v, o, 64));
+  __syncthreads();
+  if (lane == 0) sh[wid] = v;
+  __syncthreads();
+  T r = sh[0];
+  for (int w = 1; w < nw; ++w) r = op(r, sh[w]);
+  __syncthreads();
+  return r;
+}
+
+// Exclusive prefix sum of one int per thread over the block (Hillis-Steele in
+// `sh`, which holds blockDim.x ints).
+__device__ __forceinline__ int block_exclusive_scan(int v, int* sh) {
+  sh[threadIdx.x] = v;
+  __syncthreads();
+  for (int o = 1; o < (int)blockDim.x; o <<= 1) {
+    const int x = threadIdx.x >= (unsigned)o ? sh[threadIdx.x - o] : 0;
+    __syncthreads();
+    sh[threadIdx.x] += x;
+    __syncthreads();
+  }
+  const int incl = sh[threadIdx.x];
+  __syncthreads();
+  return incl - v;
+}
+
 }  // namespace okr

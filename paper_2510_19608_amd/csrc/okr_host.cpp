@@ -31,8 +31,9 @@ __global__ void k_build_members(const SegHdr*, int, const int*, Topo, State, con
                                 TargetRec*, TargetRec*, double*);
 __global__ void k_score_fp64(const SegHdr*, int, const int*, const double2*, const TargetRec*, const double2*,
                              const TargetRec*, const double*, int, int, SelParams, MaskScore*, MaskScore*, TileRec*,
-                             int*);
-__global__ void k_argmin(const SegHdr*, int, const MaskScore*, const TileRec*, SelParams, const int*, DevDecision*);
+                             int*, const int*);
+__global__ void k_argmin(const SegHdr*, int, const MaskScore*, const TileRec*, SelParams, const int*, DevDecision*,
+                         const int*);
 __global__ void k_apply(const SegHdr*, int, const int*, Topo, State, const DevDecision*, const double2*,
                         const TargetRec*, const TargetRec*, double2*, double2*);
 __global__ void k_init_state(int, State, int*, int, int*, int);
@@ -54,6 +55,29 @@ __global__ void k_mixed_select_b(const SegHdr*, int, const MaskScore32*, const T
 __global__ void k_mixed_final(const SegHdr*, int, SelParams, const int*, MixedState*, const MaskScore32*,
                               const uint32_t*, const int*, const MaskScore*, const uint32_t*, const int*,
                               const MaskScore*, DevDecision*);
+__global__ void k_surr_tables(const SegHdr*, int, const int*, int, const double2*, const double2*, const double2*,
+                              const TargetRec*, float*, float*, SurrSlot*);
+__global__ void k_surr_features(const SegHdr*, int, const int*, const float*, const float*, const SurrSlot*,
+                                const double*, int, float*, __bf16*);
+__global__ void k_surr_target(const SegHdr*, int, const MaskScore*, float*);
+template <int EPI>
+__global__ void k_gemm_nt(const __bf16*, int, const __bf16*, int, int, float*, int, const float*, float*, __bf16*,
+                          __bf16*, int, const float*, float*);
+__global__ void k_rowdot_finish(const float*, int, int, const float*, float*);
+__global__ void k_batch_cast(const float*, int, __bf16*, __bf16*);
+__global__ void k_loss_dy(const float*, const float*, int, float*, float*);
+__global__ void k_dz2(const float*, const float*, const float*, int, __bf16*, __bf16*);
+__global__ void k_dz1(const float*, const float*, int, __bf16*);
+__global__ void k_colsums(const float*, const float*, const float*, const float*, const float*, int, float*, float*,
+                          float*, float*);
+__global__ void k_copy_cols(const float*, int, float*, int, int);
+__global__ void k_adam(float*, const float*, float*, float*, int, float, float, float);
+__global__ void k_refresh_weights(const float*, __bf16*, __bf16*, __bf16*);
+__global__ void k_surr_keys(const SegHdr*, int, const float*, float, uint32_t*);
+__global__ void k_topk(const SegHdr*, int, const uint32_t*, int, const int*, uint32_t*, int*);
+__global__ void k_surr_decide(const SegHdr*, int, SelParams, const int*, const uint32_t*, const int*,
+                              const MaskScore*, DevDecision*, int*);
+__global__ void k_zero_f32(float*, int);
 }  // namespace okr
 
 using namespace okr;
@@ -82,6 +106,8 @@ struct Layout {
       headV, zrec, econst, part, fin, tiles, tickets, kp, yeq, Ykd, Yko, err;
   // mixed precision
   size_t P32, S32, H32, Z32, part32, fin32, tiles32, listA, listB, scoreA, scoreB, counts, mstate;
+  // surrogate: feature tables (always), ranking buffers (when planned with top_k)
+  size_t spz, szs, sss, sXb, sH1b, spart, sy, skeys, slist, sscore, scount, sgates, sW1b, sW2b, sW2tb;
   size_t total;
 };
 
@@ -97,7 +123,7 @@ struct okr_handle {
   std::string err;
   // plan
   bool planned = false;
-  int n = 0, S = 0, nseg = 0, kmax = 0, nlev = 0, tab_cap = 0;
+  int n = 0, S = 0, nseg = 0, kmax = 0, nlev = 0, tab_cap = 0, topk = 0;
   int64_t ncand = 0;
   std::vector<int> parent, segment, pre, pos, size, ch_off, ch, lvl_off, lvl_nodes, seg_off, seg_nodes;
   std::vector<uint8_t> phase, eligible;
@@ -345,6 +371,25 @@ extern "C" int okr_plan(okr_handle* h, const okr_topology* topo, const okr_margi
     L.counts = take(sizeof(int) * 4);
     L.mstate = take(sizeof(MixedState) * std::max(nseg, 1));
   }
+  {
+    L.spz = take(sizeof(float) * kMaxPairs);
+    L.szs = take(sizeof(float) * kMaxPairs);
+    L.sss = take(sizeof(SurrSlot) * kMaxK);
+    h->topk = (mg->top_k > 0) ? mg->top_k : 0;
+    const size_t mp = h->topk ? std::max((size_t)64, (size_t)1 << h->kmax) : 0;
+    L.sXb = take(sizeof(uint16_t) * kSurrF * mp);
+    L.sH1b = take(sizeof(uint16_t) * kSurrH * mp);
+    L.spart = take(sizeof(float) * (kSurrH / 32) * mp);
+    L.sy = take(sizeof(float) * mp);
+    L.skeys = take(sizeof(uint32_t) * mp);
+    L.slist = take(sizeof(uint32_t) * std::max(h->topk, 1));
+    L.sscore = take(sizeof(MaskScore) * std::max(h->topk, 1));
+    L.scount = take(sizeof(int) * 4);
+    L.sgates = take(sizeof(int) * std::max(nseg, 1));
+    L.sW1b = take(sizeof(uint16_t) * kSurrH * kSurrF * (h->topk ? 1 : 0));
+    L.sW2b = take(sizeof(uint16_t) * kSurrH * kSurrH * (h->topk ? 1 : 0));
+    L.sW2tb = take(8);
+  }
   L.kp = take(sizeof(int) * n);
   L.yeq = take(sizeof(double2) * 9 * n);
   L.Ykd = take(sizeof(double2) * 9 * n);
@@ -385,6 +430,12 @@ struct Ptrs {
   MaskScore *scoreA, *scoreB;
   int* counts;
   MixedState* mstate;
+  float *spz, *szs, *spart, *sy;
+  SurrSlot* sss;
+  __bf16 *sXb, *sH1b, *sW1b, *sW2b, *sW2tb;
+  uint32_t *skeys, *slist;
+  MaskScore* sscore;
+  int *scount, *sgates;
 };
 
 Ptrs pointers(okr_handle* h, void* d_workspace) {
@@ -449,6 +500,21 @@ Ptrs pointers(okr_handle* h, void* d_workspace) {
   p.scoreB = (MaskScore*)at(L.scoreB);
   p.counts = (int*)at(L.counts);
   p.mstate = (MixedState*)at(L.mstate);
+  p.spz = (float*)at(L.spz);
+  p.szs = (float*)at(L.szs);
+  p.sss = (SurrSlot*)at(L.sss);
+  p.sXb = (__bf16*)at(L.sXb);
+  p.sH1b = (__bf16*)at(L.sH1b);
+  p.spart = (float*)at(L.spart);
+  p.sy = (float*)at(L.sy);
+  p.skeys = (uint32_t*)at(L.skeys);
+  p.slist = (uint32_t*)at(L.slist);
+  p.sscore = (MaskScore*)at(L.sscore);
+  p.scount = (int*)at(L.scount);
+  p.sgates = (int*)at(L.sgates);
+  p.sW1b = (__bf16*)at(L.sW1b);
+  p.sW2b = (__bf16*)at(L.sW2b);
+  p.sW2tb = (__bf16*)at(L.sW2tb);
   return p;
 }
 
@@ -457,7 +523,8 @@ Ptrs pointers(okr_handle* h, void* d_workspace) {
 // `dump` every segment's final per-mask scores are copied out.
 void enqueue_search(okr_handle* h, const Ptrs& p, const okr_yblocks* Y, const okr_loads* loads,
                     const okr_margins* mg, hipStream_t st, const std::vector<hipEvent_t>* ev,
-                    std::vector<std::vector<MaskScore>>* dump, std::vector<std::vector<MaskScore32>>* dump32) {
+                    std::vector<std::vector<MaskScore>>* dump, std::vector<std::vector<MaskScore32>>* dump32,
+                    float* feat_out, float* targ_out) {
   const int n = h->n, S = h->S;
   const bool vhat_given = (mg->flags & OKR_FLAG_VHAT_GIVEN) != 0;
   const int ntick = (int)((((size_t)1 << h->kmax) + 63) / 64);
@@ -488,6 +555,11 @@ void enqueue_search(okr_handle* h, const Ptrs& p, const okr_yblocks* Y, const ok
   sp.amb = mg->amb_tol;
   sp.delta = kMixedDelta;
   const bool mixed = mg->precision == OKR_PRECISION_MIXED;
+  const bool surr = mg->top_k > 0 && mg->top_k <= h->topk && mg->surrogate != nullptr && !mixed;
+  if (surr)
+    hipLaunchKernelGGL(k_refresh_weights, dim3((kSurrH * kSurrH + 255) / 256), dim3(256), 0, st, mg->surrogate,
+                       p.sW1b, p.sW2b, (__bf16*)nullptr);
+  size_t feat_off = 0;
   const int members_blocks = std::min(2048, std::max(1, (int)(((size_t)n * S + 255) / 256)));
   for (int g = 0; g < h->nseg; ++g) {
     const int k = h->seg_off[g + 1] - h->seg_off[g];
@@ -503,15 +575,57 @@ void enqueue_search(okr_handle* h, const Ptrs& p, const okr_yblocks* Y, const ok
     const int mblocks = (int)((nmask + kScoreBlock - 1) / kScoreBlock);
     int spg;
     const int SG = snap_groups(k, S, &spg);
+    const int* gate = nullptr;
+    if (surr || feat_out) {
+      hipLaunchKernelGGL(k_surr_tables, dim3((kMaxPairs + kMaxK + 127) / 128), dim3(128), 0, st,
+                         (const SegHdr*)p.hdrs, g, (const int*)p.tab, n, (const double2*)p.z, (const double2*)p.P,
+                         (const double2*)p.A, (const TargetRec*)p.srec, p.spz, p.szs, p.sss);
+    }
+    if (surr) {
+      // rank every mask with the surrogate, rescore the top-k exactly
+      const int Mp = (int)std::max<uint32_t>(64u, nmask);
+      hipLaunchKernelGGL(k_surr_features, dim3((Mp + 255) / 256), dim3(256), 0, st, (const SegHdr*)p.hdrs, g,
+                         (const int*)p.tab, (const float*)p.spz, (const float*)p.szs, (const SurrSlot*)p.sss,
+                         (const double*)p.econst, Mp, (float*)nullptr, p.sXb);
+      hipLaunchKernelGGL(k_gemm_nt<1>, dim3(kSurrH / 64, Mp / 64), dim3(256), 0, st, (const __bf16*)p.sXb, kSurrF,
+                         (const __bf16*)p.sW1b, kSurrF, kSurrF, (float*)nullptr, kSurrH, mg->surrogate + kOffB1,
+                         (float*)nullptr, p.sH1b, (__bf16*)nullptr, Mp, (const float*)nullptr, (float*)nullptr);
+      hipLaunchKernelGGL(k_gemm_nt<2>, dim3(kSurrH / 64, Mp / 64), dim3(256), 0, st, (const __bf16*)p.sH1b, kSurrH,
+                         (const __bf16*)p.sW2b, kSurrH, kSurrH, (float*)nullptr, kSurrH, mg->surrogate + kOffB2,
+                         (float*)nullptr, (__bf16*)nullptr, (__bf16*)nullptr, Mp, mg->surrogate + kOffW3, p.spart);
+      hipLaunchKernelGGL(k_rowdot_finish, dim3((Mp + 255) / 256), dim3(256), 0, st, (const float*)p.spart,
+                         kSurrH / 32, Mp, mg->surrogate + kOffB3, p.sy);
+      hipLaunchKernelGGL(k_surr_keys, dim3((Mp + 255) / 256), dim3(256), 0, st, (const SegHdr*)p.hdrs, g,
+                         (const float*)p.sy, (float)std::log(mg->e_bar), p.skeys);
+      hipLaunchKernelGGL(k_topk, dim3(1), dim3(1024), 0, st, (const SegHdr*)p.hdrs, g, (const uint32_t*)p.skeys,
+                         mg->top_k, (const int*)p.status, p.slist, p.scount);
+      hipLaunchKernelGGL(k_refine_fp64, dim3(kRefineBlocks), dim3(kScoreBlock), 0, st, (const SegHdr*)p.hdrs, g,
+                         (const int*)p.tab, (const double2*)p.P, (const TargetRec*)p.srec, (const double2*)p.headV,
+                         (const TargetRec*)p.zrec, (const double*)p.econst, sp, (const uint32_t*)p.slist,
+                         (const int*)p.scount, p.sscore);
+      hipLaunchKernelGGL(k_surr_decide, dim3(1), dim3(1024), 0, st, (const SegHdr*)p.hdrs, g, sp,
+                         (const int*)p.status, (const uint32_t*)p.slist, (const int*)p.scount,
+                         (const MaskScore*)p.sscore, p.decs, p.sgates + g);
+      gate = p.sgates + g;
+    }
     if (!mixed) {
       if (ev) (void)hipEventRecord((*ev)[2 * g], st);
       hipLaunchKernelGGL(k_score_fp64, dim3(mblocks, SG), dim3(kScoreBlock), 0, st, (const SegHdr*)p.hdrs, g,
                          (const int*)p.tab, (const double2*)p.P, (const TargetRec*)p.srec, (const double2*)p.headV,
                          (const TargetRec*)p.zrec, (const double*)p.econst, spg, SG, sp, p.part, p.fin, p.tiles,
-                         p.tickets);
+                         p.tickets, gate);
       if (ev) (void)hipEventRecord((*ev)[2 * g + 1], st);
       hipLaunchKernelGGL(k_argmin, dim3(1), dim3(1024), 0, st, (const SegHdr*)p.hdrs, g, (const MaskScore*)p.fin,
-                         (const TileRec*)p.tiles, sp, (const int*)p.status, p.decs);
+                         (const TileRec*)p.tiles, sp, (const int*)p.status, p.decs, gate);
+      if (feat_out && !surr) {
+        hipLaunchKernelGGL(k_surr_features, dim3((nmask + 255) / 256), dim3(256), 0, st, (const SegHdr*)p.hdrs, g,
+                           (const int*)p.tab, (const float*)p.spz, (const float*)p.szs, (const SurrSlot*)p.sss,
+                           (const double*)p.econst, (int)nmask, feat_out + feat_off * kSurrF, (__bf16*)nullptr);
+        if (targ_out)
+          hipLaunchKernelGGL(k_surr_target, dim3((nmask + 255) / 256), dim3(256), 0, st, (const SegHdr*)p.hdrs, g,
+                             (const MaskScore*)p.fin, targ_out + feat_off);
+      }
+      feat_off += nmask;
       if (dump) {
         (*dump)[g].resize(nmask);
         (void)hipMemcpyAsync((*dump)[g].data(), p.fin, sizeof(MaskScore) * nmask, hipMemcpyDeviceToHost, st);
@@ -594,7 +708,10 @@ extern "C" int okr_reduce_feeder(okr_handle* h, const okr_yblocks* Y, const okr_
     OKR_FAIL(h, OKR_E_ARG, "bad margins");
   const bool timing = (mg->flags & OKR_FLAG_TIMING) != 0;
   const bool dump = (mg->flags & OKR_FLAG_DUMP_SCORES) != 0;
-  const bool graph = (mg->flags & OKR_FLAG_GRAPH) != 0 && !timing && !dump;
+  const bool graph = (mg->flags & OKR_FLAG_GRAPH) != 0 && !timing && !dump && !out->features;
+  if (mg->top_k > 0 && mg->surrogate && mg->top_k > h->topk)
+    OKR_FAIL(h, OKR_E_ARG, "top_k %d exceeds the planned %d", mg->top_k, h->topk);
+  if (out->targets && mg->precision != OKR_PRECISION_FP64) OKR_FAIL(h, OKR_E_ARG, "targets need precision FP64");
   const int n = h->n, S = h->S, nseg = h->nseg;
   hipStream_t st = h->stream;
   const Ptrs p = pointers(h, d_workspace);
@@ -616,12 +733,13 @@ extern "C" int okr_reduce_feeder(okr_handle* h, const okr_yblocks* Y, const okr_
         (uint64_t)d_workspace, (uint64_t)Y->Y_diag, (uint64_t)Y->Y_off, (uint64_t)loads->S_load,
         (uint64_t)loads->Vhat, (uint64_t)st, (uint64_t)mg->flags, bits(mg->e_bar), bits(mg->v_min),
         bits(mg->v_max), bits(mg->tie_tol), bits(mg->amb_tol), bits(mg->pf_tol), (uint64_t)mg->pf_maxit,
-        bits(V0[0].x), bits(V0[0].y), bits(V0[1].x), bits(V0[1].y), bits(V0[2].x), bits(V0[2].y)};
+        bits(V0[0].x), bits(V0[0].y), bits(V0[1].x), bits(V0[1].y), bits(V0[2].x), bits(V0[2].y),
+        (uint64_t)mg->precision, (uint64_t)(int64_t)mg->top_k, (uint64_t)mg->surrogate};
     if (!h->gexec || key != h->gkey) {
       drop_graph(h);
       OKR_HIP(h, hipStreamSynchronize(st));
       OKR_HIP(h, hipStreamBeginCapture(st, hipStreamCaptureModeThreadLocal));
-      enqueue_search(h, p, Y, loads, mg, st, nullptr, nullptr, nullptr);
+      enqueue_search(h, p, Y, loads, mg, st, nullptr, nullptr, nullptr, nullptr, nullptr);
       hipGraph_t gobj = nullptr;
       const hipError_t ec = hipStreamEndCapture(st, &gobj);
       if (ec != hipSuccess) OKR_FAIL(h, OKR_E_HIP, "graph capture failed: %s", hipGetErrorString(ec));
@@ -636,13 +754,15 @@ extern "C" int okr_reduce_feeder(okr_handle* h, const okr_yblocks* Y, const okr_
     OKR_HIP(h, hipGraphLaunch(h->gexec, st));
   } else {
     enqueue_search(h, p, Y, loads, mg, st, timing ? &h->ev : nullptr, dump ? &h->dump : nullptr,
-                   dump ? &h->dump32 : nullptr);
+                   dump ? &h->dump32 : nullptr, out->features, out->targets);
     OKR_HIP(h, hipGetLastError());
   }
   // results (one synchronisation)
   std::vector<DevDecision> decs(std::max(nseg, 1));
   std::vector<SegHdr> hdrs(std::max(nseg, 1));
   std::vector<MixedState> mstate(std::max(nseg, 1));
+  std::vector<int> gates(std::max(nseg, 1), 1);
+  const bool surr_used = mg->top_k > 0 && mg->top_k <= h->topk && mg->surrogate && mg->precision == OKR_PRECISION_FP64;
   const bool mixed = mg->precision == OKR_PRECISION_MIXED;
   std::vector<int> sup(n), kp(n), iters(S, 0), status(kStatusInts, 0);
   if (nseg > 0) {
@@ -650,6 +770,8 @@ extern "C" int okr_reduce_feeder(okr_handle* h, const okr_yblocks* Y, const okr_
     OKR_HIP(h, hipMemcpyAsync(hdrs.data(), p.hdrs, sizeof(SegHdr) * nseg, hipMemcpyDeviceToHost, st));
     if (mixed)
       OKR_HIP(h, hipMemcpyAsync(mstate.data(), p.mstate, sizeof(MixedState) * nseg, hipMemcpyDeviceToHost, st));
+    if (surr_used)
+      OKR_HIP(h, hipMemcpyAsync(gates.data(), p.sgates, sizeof(int) * nseg, hipMemcpyDeviceToHost, st));
   }
   OKR_HIP(h, hipMemcpyAsync(sup.data(), p.St.sup, sizeof(int) * n, hipMemcpyDeviceToHost, st));
   OKR_HIP(h, hipMemcpyAsync(kp.data(), p.kp, sizeof(int) * n, hipMemcpyDeviceToHost, st));
@@ -700,6 +822,10 @@ extern "C" int okr_reduce_feeder(okr_handle* h, const okr_yblocks* Y, const okr_
     if (mixed) {
       R.n_refined = mstate[g].nA + mstate[g].nB;
       R.fp32_dev = mstate[g].max_dev;
+    }
+    if (surr_used) {
+      R.n_refined = std::min(mg->top_k, 1 << k);
+      R.n_scored = R.n_refined + (gates[g] ? (1 << k) : 0);
     }
     if (timing) {
       float ms = 0.f;
@@ -752,5 +878,179 @@ extern "C" int okr_selftest_sqrt(const double* d_x, double* d_y, int n, void* st
   if (!d_x || !d_y || n < 0) return OKR_E_ARG;
   hipLaunchKernelGGL(k_sqrt_selftest, dim3((n + 255) / 256), dim3(256), 0, static_cast<hipStream_t>(stream), d_x,
                      d_y, n);
+  return hipGetLastError() == hipSuccess ? OKR_OK : OKR_E_HIP;
+}
+
+// ------------------------------------------------------------ surrogate --
+namespace {
+
+struct SurrWork {
+  __bf16 *Xb, *Xt, *H1b, *H1t, *dZ2b, *dZ2t, *dZ1t, *W1b, *W2b, *W2tb;
+  float *Z1, *Z2, *part, *y, *dy, *dH1, *gW1full, *grads, *m, *v, *loss;
+  size_t bytes;
+};
+
+constexpr int kMaxEpochs = 4096;
+
+SurrWork surr_layout(int B, void* base) {
+  SurrWork w{};
+  size_t off = 0;
+  char* b = static_cast<char*>(base);
+  auto take = [&](size_t bytes) {
+    void* p = b ? (void*)(b + off) : nullptr;
+    off = align256(off + bytes);
+    return p;
+  };
+  const size_t bf = sizeof(uint16_t), f4 = sizeof(float);
+  w.Xb = (__bf16*)take(bf * B * kSurrF);
+  w.Xt = (__bf16*)take(bf * 64 * B);
+  w.H1b = (__bf16*)take(bf * B * kSurrH);
+  w.H1t = (__bf16*)take(bf * kSurrH * B);
+  w.dZ2b = (__bf16*)take(bf * B * kSurrH);
+  w.dZ2t = (__bf16*)take(bf * kSurrH * B);
+  w.dZ1t = (__bf16*)take(bf * kSurrH * B);
+  w.W1b = (__bf16*)take(bf * kSurrH * kSurrF);
+  w.W2b = (__bf16*)take(bf * kSurrH * kSurrH);
+  w.W2tb = (__bf16*)take(bf * kSurrH * kSurrH);
+  w.Z1 = (float*)take(f4 * B * kSurrH);
+  w.Z2 = (float*)take(f4 * B * kSurrH);
+  w.part = (float*)take(f4 * (kSurrH / 32) * B);
+  w.y = (float*)take(f4 * B);
+  w.dy = (float*)take(f4 * B);
+  w.dH1 = (float*)take(f4 * B * kSurrH);
+  w.gW1full = (float*)take(f4 * kSurrH * 64);
+  w.grads = (float*)take(f4 * kSurrParams);
+  w.m = (float*)take(f4 * kSurrParams);
+  w.v = (float*)take(f4 * kSurrParams);
+  w.loss = (float*)take(f4 * kMaxEpochs);
+  w.bytes = off;
+  return w;
+}
+
+// Forward of one batch (B rows of FP32 features at X) into w.y; with `train`
+// the pre-activations and the transposed activations are kept for backward.
+void surr_forward(const SurrWork& w, const float* prm, const float* X, int B, bool train, hipStream_t st) {
+  hipLaunchKernelGGL(k_batch_cast, dim3((B * 64 + 255) / 256), dim3(256), 0, st, X, B, w.Xb, w.Xt);
+  hipLaunchKernelGGL(k_gemm_nt<1>, dim3(kSurrH / 64, B / 64), dim3(256), 0, st, (const __bf16*)w.Xb, kSurrF,
+                     (const __bf16*)w.W1b, kSurrF, kSurrF, (float*)nullptr, kSurrH, prm + kOffB1,
+                     train ? w.Z1 : (float*)nullptr, w.H1b, train ? w.H1t : (__bf16*)nullptr, B, (const float*)nullptr,
+                     (float*)nullptr);
+  hipLaunchKernelGGL(k_gemm_nt<2>, dim3(kSurrH / 64, B / 64), dim3(256), 0, st, (const __bf16*)w.H1b, kSurrH,
+                     (const __bf16*)w.W2b, kSurrH, kSurrH, (float*)nullptr, kSurrH, prm + kOffB2,
+                     train ? w.Z2 : (float*)nullptr, (__bf16*)nullptr, (__bf16*)nullptr, B, prm + kOffW3, w.part);
+  hipLaunchKernelGGL(k_rowdot_finish, dim3((B + 255) / 256), dim3(256), 0, st, (const float*)w.part, kSurrH / 32, B,
+                     prm + kOffB3, w.y);
+}
+
+// Loss gradient of one batch into w.grads; the batch loss is added to *loss.
+void surr_backward(const SurrWork& w, const float* prm, const float* t, int B, float* loss, hipStream_t st) {
+  hipLaunchKernelGGL(k_loss_dy, dim3((B + 255) / 256), dim3(256), 0, st, (const float*)w.y, t, B, w.dy, loss);
+  hipLaunchKernelGGL(k_dz2, dim3((B * kSurrH + 255) / 256), dim3(256), 0, st, (const float*)w.Z2, (const float*)w.dy,
+                     prm + kOffW3, B, w.dZ2b, w.dZ2t);
+  // dW2 = dZ2^T H1
+  hipLaunchKernelGGL(k_gemm_nt<0>, dim3(kSurrH / 64, kSurrH / 64), dim3(256), 0, st, (const __bf16*)w.dZ2t, B,
+                     (const __bf16*)w.H1t, B, B, w.grads + kOffW2, kSurrH, (const float*)nullptr, (float*)nullptr,
+                     (__bf16*)nullptr, (__bf16*)nullptr, kSurrH, (const float*)nullptr, (float*)nullptr);
+  // dH1 = dZ2 W2
+  hipLaunchKernelGGL(k_gemm_nt<0>, dim3(kSurrH / 64, B / 64), dim3(256), 0, st, (const __bf16*)w.dZ2b, kSurrH,
+                     (const __bf16*)w.W2tb, kSurrH, kSurrH, w.dH1, kSurrH, (const float*)nullptr, (float*)nullptr,
+                     (__bf16*)nullptr, (__bf16*)nullptr, B, (const float*)nullptr, (float*)nullptr);
+  hipLaunchKernelGGL(k_dz1, dim3((B * kSurrH + 255) / 256), dim3(256), 0, st, (const float*)w.dH1, (const float*)w.Z1,
+                     B, w.dZ1t);
+  // dW1 = dZ1^T X (X^T padded to 64 rows)
+  hipLaunchKernelGGL(k_gemm_nt<0>, dim3(1, kSurrH / 64), dim3(256), 0, st, (const __bf16*)w.dZ1t, B,
+                     (const __bf16*)w.Xt, B, B, w.gW1full, 64, (const float*)nullptr, (float*)nullptr,
+                     (__bf16*)nullptr, (__bf16*)nullptr, kSurrH, (const float*)nullptr, (float*)nullptr);
+  hipLaunchKernelGGL(k_copy_cols, dim3((kSurrH * kSurrF + 255) / 256), dim3(256), 0, st, (const float*)w.gW1full, 64,
+                     w.grads + kOffW1, kSurrH, kSurrF);
+  hipLaunchKernelGGL(k_colsums, dim3((kSurrH + 1 + 255) / 256), dim3(256), 0, st, (const float*)w.Z1,
+                     (const float*)w.dH1, (const float*)w.Z2, (const float*)w.dy, prm + kOffW3, B, w.grads + kOffB1,
+                     w.grads + kOffB2, w.grads + kOffW3, w.grads + kOffB3);
+}
+
+void surr_refresh(const SurrWork& w, const float* prm, hipStream_t st) {
+  hipLaunchKernelGGL(k_refresh_weights, dim3((kSurrH * kSurrH + 255) / 256), dim3(256), 0, st, prm, w.W1b, w.W2b,
+                     w.W2tb);
+}
+
+}  // namespace
+
+extern "C" int okr_surrogate_workspace(int32_t batch, size_t* bytes) {
+  if (!bytes || batch < 64 || batch % 64) return OKR_E_ARG;
+  *bytes = surr_layout(batch, nullptr).bytes;
+  return OKR_OK;
+}
+
+extern "C" int okr_surrogate_grad(const float* params, const float* X, const float* t, int32_t B, float* grads,
+                                  float* loss, void* work, size_t work_bytes, void* stream) {
+  if (!params || !X || !t || !grads || B < 64 || B % 64 || !work) return OKR_E_ARG;
+  const SurrWork w = surr_layout(B, work);
+  if (work_bytes < w.bytes) return OKR_E_WORKSPACE;
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  surr_refresh(w, params, st);
+  hipLaunchKernelGGL(k_zero_f32, dim3(1), dim3(64), 0, st, w.loss, 1);
+  surr_forward(w, params, X, B, true, st);
+  surr_backward(w, params, t, B, w.loss, st);
+  if (hipMemcpyAsync(grads, w.grads, sizeof(float) * kSurrParams, hipMemcpyDeviceToDevice, st) != hipSuccess)
+    return OKR_E_HIP;
+  float l = 0.f;
+  if (hipMemcpyAsync(&l, w.loss, sizeof(float), hipMemcpyDeviceToHost, st) != hipSuccess) return OKR_E_HIP;
+  if (hipStreamSynchronize(st) != hipSuccess) return OKR_E_HIP;
+  if (loss) *loss = l;
+  return hipGetLastError() == hipSuccess ? OKR_OK : OKR_E_HIP;
+}
+
+extern "C" int okr_train_surrogate(const float* X, const float* t, int64_t n, int32_t epochs, int32_t batch, float lr,
+                                   uint64_t seed, float* params, void* work, size_t work_bytes, void* stream,
+                                   float* loss) {
+  if (!X || !t || !params || !work || batch < 64 || batch % 64 || epochs < 1 || epochs > kMaxEpochs ||
+      n < batch)
+    return OKR_E_ARG;
+  const SurrWork w = surr_layout(batch, work);
+  if (work_bytes < w.bytes) return OKR_E_WORKSPACE;
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  const int64_t nb = n / batch;
+  hipLaunchKernelGGL(k_zero_f32, dim3((kSurrParams + 255) / 256), dim3(256), 0, st, w.m, kSurrParams);
+  hipLaunchKernelGGL(k_zero_f32, dim3((kSurrParams + 255) / 256), dim3(256), 0, st, w.v, kSurrParams);
+  hipLaunchKernelGGL(k_zero_f32, dim3((epochs + 255) / 256), dim3(256), 0, st, w.loss, epochs);
+  std::vector<int64_t> order(nb);
+  uint64_t rng = seed * 0x9E3779B97F4A7C15ull + 1;
+  int64_t step = 0;
+  for (int e = 0; e < epochs; ++e) {
+    for (int64_t q = 0; q < nb; ++q) order[q] = q;
+    for (int64_t q = nb - 1; q > 0; --q) {  // Fisher-Yates with a 64-bit LCG
+      rng = rng * 6364136223846793005ull + 1442695040888963407ull;
+      std::swap(order[q], order[(int64_t)((rng >> 33) % (uint64_t)(q + 1))]);
+    }
+    for (int64_t q = 0; q < nb; ++q) {
+      const int64_t off = order[q] * batch;
+      surr_refresh(w, params, st);
+      surr_forward(w, params, X + off * kSurrF, batch, true, st);
+      surr_backward(w, params, t + off, batch, w.loss + e, st);
+      ++step;
+      const float c1 = 1.f - std::pow(0.9f, (float)step), c2 = 1.f - std::pow(0.999f, (float)step);
+      hipLaunchKernelGGL(k_adam, dim3((kSurrParams + 255) / 256), dim3(256), 0, st, params, (const float*)w.grads,
+                         w.m, w.v, kSurrParams, lr, c1, c2);
+    }
+  }
+  std::vector<float> lh(epochs);
+  if (hipMemcpyAsync(lh.data(), w.loss, sizeof(float) * epochs, hipMemcpyDeviceToHost, st) != hipSuccess)
+    return OKR_E_HIP;
+  if (hipStreamSynchronize(st) != hipSuccess) return OKR_E_HIP;
+  if (loss)
+    for (int e = 0; e < epochs; ++e) loss[e] = lh[e] / (float)nb;
+  return hipGetLastError() == hipSuccess ? OKR_OK : OKR_E_HIP;
+}
+
+extern "C" int okr_surrogate_forward(const float* params, const float* X, int64_t n, float* y, void* work,
+                                     size_t work_bytes, void* stream) {
+  if (!params || !X || !y || !work || n < 64 || n % 64) return OKR_E_ARG;
+  const SurrWork w = surr_layout((int)n, work);
+  if (work_bytes < w.bytes) return OKR_E_WORKSPACE;
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  surr_refresh(w, params, st);
+  surr_forward(w, params, X, (int)n, false, st);
+  if (hipMemcpyAsync(y, w.y, sizeof(float) * n, hipMemcpyDeviceToDevice, st) != hipSuccess) return OKR_E_HIP;
+  if (hipStreamSynchronize(st) != hipSuccess) return OKR_E_HIP;
   return hipGetLastError() == hipSuccess ? OKR_OK : OKR_E_HIP;
 }

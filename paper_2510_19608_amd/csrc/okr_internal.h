@@ -129,6 +129,23 @@ struct MaskScore32 {
 struct TileRec32 {   // max popcount of sure-feasible / possibly-feasible / uncertain masks
   int sure, poss, unc, pad;
 };
+// ---- surrogate ----
+constexpr int kSurrF = 32;    // features per mask (16 used, zero padded)
+constexpr int kSurrH = 256;   // hidden width
+constexpr int kOffW1 = 0;
+constexpr int kOffB1 = kOffW1 + kSurrH * kSurrF;
+constexpr int kOffW2 = kOffB1 + kSurrH;
+constexpr int kOffB2 = kOffW2 + kSurrH * kSurrH;
+constexpr int kOffW3 = kOffB2 + kSurrH;
+constexpr int kOffB3 = kOffW3 + kSurrH;
+constexpr int kSurrParams = kOffB3 + 1;
+struct SurrSlot {   // per slot of the segment being ranked
+  float la;         // max over snapshots of the slot's aggregated load current
+  float spread;     // max over snapshots and phases of its cluster's |V^| spread
+  int nph;          // phases
+  int pos;          // position in its chain
+};
+
 struct MixedState {  // per segment: the screening levels and shortlist sizes
   int lo_level, hi_level, best, nA, nB, pad;
   double e_up;

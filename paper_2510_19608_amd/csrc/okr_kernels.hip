@@ -114,20 +114,6 @@ __global__ void k_branch_z(int n, const int* __restrict__ parent, const uint8_t*
   if (bad) atomicOr(status, bad);
 }
 
-// ------------------------------------------------------------ block reduce --
-template <typename T, typename Op>
-__device__ T block_reduce(T v, Op op, T* sh) {
-  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6, nw = (blockDim.x + 63) >> 6;
-  for (int o = 32; o > 0; o >>= 1) v = op(v, __shfl_xor(v, o, 64));
-  __syncthreads();
-  if (lane == 0) sh[wid] = v;
-  __syncthreads();
-  T r = sh[0];
-  for (int w = 1; w < nw; ++w) r = op(r, sh[w]);
-  __syncthreads();
-  return r;
-}
-
 // ------------------------------------------------------------- load flow --
 // Scenario library (Section III): constant-PQ wye loads, backward/forward
 // sweep on the radial tree, one block per snapshot, level-synchronous.
@@ -235,11 +221,11 @@ __global__ __launch_bounds__(kScoreBlock) void k_score_fp64(
     const TargetRec* __restrict__ srec, const double2* __restrict__ headV,
     const TargetRec* __restrict__ zrec, const double* __restrict__ econst, int snaps_per_group, int SG,
     SelParams sp, MaskScore* __restrict__ part, MaskScore* __restrict__ fin, TileRec* __restrict__ tiles,
-    int* __restrict__ tickets) {
+    int* __restrict__ tickets, const int* __restrict__ gate) {
   __shared__ double2 Ps[kMaxPairs * 3];
   __shared__ int ticket;
   const SegHdr H = hdrs[g];
-  if (!H.valid) return;
+  if (!H.valid || (gate && *gate == 0)) return;
   const uint32_t m = blockIdx.x * kScoreBlock + threadIdx.x;
   const int sg = blockIdx.y;
   const int l0 = sg * snaps_per_group;
@@ -316,13 +302,14 @@ __global__ __launch_bounds__(kScoreBlock) void k_score_fp64(
 __global__ __launch_bounds__(1024) void k_argmin(const SegHdr* __restrict__ hdrs, int g,
                                                  const MaskScore* __restrict__ fin, const TileRec* __restrict__ tiles,
                                                  SelParams sp, const int* __restrict__ status,
-                                                 DevDecision* __restrict__ decs) {
+                                                 DevDecision* __restrict__ decs, const int* __restrict__ gate) {
   __shared__ double shd[16];
   __shared__ int shi[16];
   __shared__ unsigned shu[16];
   __shared__ int ncand;
   __shared__ int cand[1024];
   const SegHdr H = hdrs[g];
+  if (gate && *gate == 0) return;  // decided without the full enumeration
   DevDecision* dec = decs + g;
   // nothing is reduced when the full network violates the band, the load
   // flow failed, or the segment's tables are inconsistent

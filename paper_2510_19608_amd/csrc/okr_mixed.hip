@@ -250,19 +250,6 @@ __global__ __launch_bounds__(kScoreBlock) void k_score_fp32(
   }
 }
 
-template <typename T, typename Op>
-__device__ T breduce(T v, Op op, T* sh) {
-  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6, nw = (blockDim.x + 63) >> 6;
-  for (int o = 32; o > 0; o >>= 1) v = op(v, __shfl_xor(v, o, 64));
-  __syncthreads();
-  if (lane == 0) sh[wid] = v;
-  __syncthreads();
-  T r = sh[0];
-  for (int w = 1; w < nw; ++w) r = op(r, sh[w]);
-  __syncthreads();
-  return r;
-}
-
 __device__ __forceinline__ bool skip_segment(const SegHdr& H, const int* status) {
   return !H.valid || (*status & (16 | 32));
 }
@@ -289,8 +276,8 @@ __global__ __launch_bounds__(1024) void k_mixed_select_a(const SegHdr* __restric
     lo = max(lo, tiles[t].sure);
     hi = max(hi, tiles[t].poss);
   }
-  lo = breduce(lo, [](int a, int b) { return max(a, b); }, shi);
-  hi = breduce(hi, [](int a, int b) { return max(a, b); }, shi);
+  lo = block_reduce(lo, [](int a, int b) { return max(a, b); }, shi);
+  hi = block_reduce(hi, [](int a, int b) { return max(a, b); }, shi);
   const double dd = sp.delta + sp.amb;
   for (int t = threadIdx.x; t < ntiles; t += blockDim.x) {
     if (tiles[t].unc < lo || tiles[t].unc < 0) continue;
@@ -374,7 +361,7 @@ __global__ __launch_bounds__(1024) void k_mixed_select_b(const SegHdr* __restric
   int best = ms[g].lo_level;
   for (int q = threadIdx.x; q < nA; q += blockDim.x)
     if (feasible(scoreA[q], sp.e_bar)) best = max(best, __popc(listA[q]));
-  best = breduce(best, [](int a, int b) { return max(a, b); }, shi);
+  best = block_reduce(best, [](int a, int b) { return max(a, b); }, shi);
   // upper bound on the smallest FP64 error at level best
   double eup = INFINITY;
   if (best >= 0) {
@@ -391,7 +378,7 @@ __global__ __launch_bounds__(1024) void k_mixed_select_b(const SegHdr* __restric
     for (int q = threadIdx.x; q < nA; q += blockDim.x)
       if (__popc(listA[q]) == best && feasible(scoreA[q], sp.e_bar)) eup = fmin(eup, scoreA[q].e);
   }
-  eup = breduce(eup, [](double a, double b) { return fmin(a, b); }, shd);
+  eup = block_reduce(eup, [](double a, double b) { return fmin(a, b); }, shd);
   const double bound = eup + sp.tie + sp.delta + sp.amb;
   if (best >= 0) {
     for (int t = threadIdx.x; t < ntiles; t += blockDim.x) {
@@ -446,7 +433,7 @@ __global__ __launch_bounds__(1024) void k_mixed_final(const SegHdr* __restrict__
     if (feasible(r, sp.e_bar)) emin = fmin(emin, r.e);
     if (r.e <= 2.0 * sp.e_bar) dev = fmax(dev, fabs((double)fin[listB[q]].e - r.e));
   }
-  emin = breduce(emin, [](double a, double b) { return fmin(a, b); }, shd);
+  emin = block_reduce(emin, [](double a, double b) { return fmin(a, b); }, shd);
   const double thr = emin + sp.tie;
   unsigned pick = 0xffffffffu;
   int amb = 0;
@@ -461,9 +448,9 @@ __global__ __launch_bounds__(1024) void k_mixed_final(const SegHdr* __restrict__
     if (__popc(listA[q]) >= best && near_boundary(r, sp.e_bar, sp.amb)) amb = 1;
     if (r.e <= 2.0 * sp.e_bar) dev = fmax(dev, fabs((double)fin[listA[q]].e - r.e));
   }
-  pick = breduce(pick, [](unsigned a, unsigned b) { return min(a, b); }, shu);
-  amb = breduce(amb, [](int a, int b) { return a | b; }, shi);
-  dev = breduce(dev, [](double a, double b) { return fmax(a, b); }, shd);
+  pick = block_reduce(pick, [](unsigned a, unsigned b) { return min(a, b); }, shu);
+  amb = block_reduce(amb, [](int a, int b) { return a | b; }, shi);
+  dev = block_reduce(dev, [](double a, double b) { return fmax(a, b); }, shd);
   if (threadIdx.x == 0) {
     DevDecision d;
     double epick = 0.0;

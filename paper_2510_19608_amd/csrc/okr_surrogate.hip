@@ -1,0 +1,482 @@
+// Learned pruning: a 3-layer MLP (F -> 256 -> 256 -> 1, GELU, BF16 operands,
+// FP32 accumulation on MFMA) predicts y = ln(e_loc + 1e-12) of every mask of
+// a segment from per-mask features; the top-k masks by (predicted feasible,
+// most reduced, smallest predicted error) are rescored exactly in FP64, and
+// the full enumeration runs when none of them is feasible with a reduction.
+//
+// Parameters (FP32, one contiguous buffer, [out][in] layout):
+//   W1[256][32] b1[256] W2[256][256] b2[256] w3[256] b3[1]
+#include <hip/hip_runtime.h>
+#include <math.h>
+#include <stdint.h>
+
+#include "okr_device.h"
+#include "okr_internal.h"
+
+namespace okr {
+
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+typedef float f32x16 __attribute__((ext_vector_type(16)));
+
+// ------------------------------------------------------ per-mask features --
+__global__ void k_surr_tables(const SegHdr* __restrict__ hdrs, int g, const int* __restrict__ tab, int n,
+                              const double2* __restrict__ z, const double2* __restrict__ P,
+                              const double2* __restrict__ A, const TargetRec* __restrict__ srec,
+                              float* __restrict__ pz, float* __restrict__ zs, SurrSlot* __restrict__ ss) {
+  const SegHdr H = hdrs[g];
+  if (!H.valid) return;
+  const int t = blockIdx.x * blockDim.x + threadIdx.x;
+  if (t < H.npairs) {
+    const int* pr = tab + H.o_pair + t * kPairInts;
+    double mx = 0.0;
+    for (int l = 0; l < H.S; ++l)
+      for (int p = 0; p < 3; ++p) mx = fmax(mx, sqrt(cabs2(P[((size_t)l * H.npairs + t) * 3 + p])));
+    double zsum = 0.0;
+    for (int x = pr[PR_FROM]; x <= pr[PR_TO]; ++x) {
+      const double2* zv = z + (size_t)tab[H.o_path + pr[PR_PATHOFF] + x] * 9;
+      for (int p = 0; p < 3; ++p) zsum += sqrt(cabs2(zv[p * 4]));
+    }
+    pz[t] = (float)mx;
+    zs[t] = (float)zsum;
+  } else if (t < H.npairs + H.nslots) {
+    const int s = t - H.npairs;
+    const int* sr = tab + H.o_slot + s * kSlotInts;
+    const int node = sr[SL_NODE], ph = sr[SL_PHASE];
+    double la = 0.0, sp = 0.0;
+    for (int l = 0; l < H.S; ++l) {
+      double a = 0.0;
+      for (int p = 0; p < 3; ++p) {
+        a += sqrt(cabs2(A[((size_t)l * n + node) * 3 + p]));
+        if (ph >> p & 1) {
+          const TargetRec r = srec[((size_t)l * H.nslots + s) * 3 + p];
+          sp = fmax(sp, r.hi - r.lo);
+        }
+      }
+      la = fmax(la, a);
+    }
+    const int* cr = tab + H.o_chain + sr[SL_CHAIN] * kChainInts;
+    SurrSlot o;
+    o.la = (float)la;
+    o.spread = (float)sp;
+    o.nph = __popc(ph);
+    o.pos = s - cr[C_SLOT0];
+    ss[s] = o;
+  }
+}
+
+// Features of mask m from a snapshot-free walk of the chains (the moved
+// currents' voltage rises, path impedance sums, load totals, phase counts,
+// run lengths, depth), scaled to O(1).  Rows m >= 2^k are zero padding.
+__global__ void k_surr_features(const SegHdr* __restrict__ hdrs, int g, const int* __restrict__ tab,
+                                const float* __restrict__ pz, const float* __restrict__ zs,
+                                const SurrSlot* __restrict__ ss, const double* __restrict__ econst, int Mp,
+                                float* __restrict__ Xf, __bf16* __restrict__ Xb) {
+  const SegHdr H = hdrs[g];
+  if (!H.valid) return;
+  const uint32_t m = blockIdx.x * blockDim.x + threadIdx.x;
+  if (m >= (uint32_t)Mp) return;
+  float f[kSurrF];
+  for (int q = 0; q < kSurrF; ++q) f[q] = 0.f;
+  if (m < (1u << H.k)) {
+    const int* chains = tab + H.o_chain;
+    const int* slots = tab + H.o_slot;
+    float sum_pz = 0.f, max_pz = 0.f, sum_z = 0.f, sum_la = 0.f, max_sp = 0.f, sum_pos = 0.f;
+    int n1 = 0, n2 = 0, n3 = 0, maxrun = 0, touched = 0, pop = 0;
+    for (int c = 0; c < H.nchains; ++c) {
+      const int* cr = chains + c * kChainInts;
+      int sidx = 0, run = 0, tc = 0;
+      for (int r = 0; r < cr[C_NSLOT]; ++r) {
+        const int s = cr[C_SLOT0] + r;
+        const int* sr = slots + s * kSlotInts;
+        if ((m >> sr[SL_BIT]) & 1u) {
+          const int q = sr[SL_PAIRBASE] + sidx;
+          const SurrSlot o = ss[s];
+          sum_pz += pz[q];
+          max_pz = fmaxf(max_pz, pz[q]);
+          sum_z += zs[q];
+          sum_la += o.la;
+          max_sp = fmaxf(max_sp, o.spread);
+          sum_pos += (float)o.pos;
+          n1 += o.nph == 1;
+          n2 += o.nph == 2;
+          n3 += o.nph == 3;
+          ++pop;
+          maxrun = max(maxrun, ++run);
+          tc = 1;
+        } else {
+          sidx = r + 1;
+          run = 0;
+        }
+      }
+      touched += tc;
+    }
+    double ec = 0.0;
+    for (int l = 0; l < H.S; ++l) ec = fmax(ec, econst[l]);
+    const float k = (float)H.k;
+    f[0] = pop / k;
+    f[1] = sum_pz * 1e3f;
+    f[2] = max_pz * 1e3f;
+    f[3] = sum_z * 1e2f;
+    f[4] = sum_la * 10.f;
+    f[5] = n1 / k;
+    f[6] = n2 / k;
+    f[7] = n3 / k;
+    f[8] = maxrun / k;
+    f[9] = touched / (float)H.nchains;
+    f[10] = sum_pos / k;
+    f[11] = max_sp * 1e3f;
+    f[12] = log10f(max_pz + 1e-9f) / 4.f;
+    f[13] = log10f(sum_pz + 1e-9f) / 4.f;
+    f[14] = (float)ec * 1e3f;
+    f[15] = k / 24.f;
+  }
+  if (Xf)
+    for (int q = 0; q < kSurrF; ++q) Xf[(size_t)m * kSurrF + q] = f[q];
+  if (Xb)
+    for (int q = 0; q < kSurrF; ++q) Xb[(size_t)m * kSurrF + q] = (__bf16)f[q];
+}
+
+// Training target of every mask from the FP64 scores: y = ln(e + 1e-12).
+__global__ void k_surr_target(const SegHdr* __restrict__ hdrs, int g, const MaskScore* __restrict__ fin,
+                              float* __restrict__ t) {
+  const SegHdr H = hdrs[g];
+  const uint32_t m = blockIdx.x * blockDim.x + threadIdx.x;
+  if (!H.valid || m >= (1u << H.k)) return;
+  t[m] = (float)log(fin[m].e + 1e-12);
+}
+
+// --------------------------------------------------------------- BF16 GEMM --
+__device__ __forceinline__ float gelu_f(float x) { return 0.5f * x * (1.f + erff(x * 0.70710678118654752f)); }
+__device__ __forceinline__ float gelu_grad_f(float x) {
+  const float cdf = 0.5f * (1.f + erff(x * 0.70710678118654752f));
+  const float pdf = 0.39894228040143268f * expf(-0.5f * x * x);
+  return cdf + x * pdf;
+}
+
+enum { EPI_STORE = 0, EPI_BIAS_GELU = 1, EPI_BIAS_GELU_DOT = 2 };
+
+// C[M][N] = sum_k A[m][k] * B[n][k] (A, B BF16, K contiguous), FP32 results.
+// 256 threads = 4 waves (2 x 2), block tile 64 x 64, K step 32 through LDS;
+// each wave a 32 x 32 tile with v_mfma_f32_32x32x16_bf16.  M, N multiples of
+// 64, K a multiple of 32.  Epilogues:
+//   STORE          C (ldc)
+//   BIAS_GELU      Z = C + bias (FP32, optional), H = gelu(Z) in BF16 [M][N]
+//                  (optional) and transposed Ht [N][M] (optional)
+//   BIAS_GELU_DOT  as BIAS_GELU, plus per-row partial dot products of
+//                  gelu(Z) with w over each 32-column block: part[N/32][M]
+template <int EPI>
+__global__ __launch_bounds__(256) void k_gemm_nt(const __bf16* __restrict__ A, int lda, const __bf16* __restrict__ B,
+                                                 int ldb, int K, float* __restrict__ C, int ldc,
+                                                 const float* __restrict__ bias, float* __restrict__ Z,
+                                                 __bf16* __restrict__ Hb, __bf16* __restrict__ Ht, int M,
+                                                 const float* __restrict__ w, float* __restrict__ part) {
+  __shared__ __attribute__((aligned(16))) __bf16 As[64][40];
+  __shared__ __attribute__((aligned(16))) __bf16 Bs[64][40];
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int wm = wave >> 1, wn = wave & 1;
+  const int m0 = blockIdx.y * 64, n0 = blockIdx.x * 64;
+  f32x16 acc;
+  for (int v = 0; v < 16; ++v) acc[v] = 0.f;
+  const int lr = tid >> 2, lc = (tid & 3) * 8;
+  for (int k0 = 0; k0 < K; k0 += 32) {
+    *(uint4*)&As[lr][lc] = *(const uint4*)&A[(size_t)(m0 + lr) * lda + k0 + lc];
+    *(uint4*)&Bs[lr][lc] = *(const uint4*)&B[(size_t)(n0 + lr) * ldb + k0 + lc];
+    __syncthreads();
+#pragma unroll
+    for (int kk = 0; kk < 32; kk += 16) {
+      const bf16x8 a = *(const bf16x8*)&As[wm * 32 + (lane & 31)][kk + 8 * (lane >> 5)];
+      const bf16x8 b = *(const bf16x8*)&Bs[wn * 32 + (lane & 31)][kk + 8 * (lane >> 5)];
+      acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a, b, acc, 0, 0, 0);
+    }
+    __syncthreads();
+  }
+  const int col = n0 + wn * 32 + (lane & 31);
+  float dot[16];
+#pragma unroll
+  for (int v = 0; v < 16; ++v) {
+    const int row = m0 + wm * 32 + 8 * (v >> 2) + 4 * (lane >> 5) + (v & 3);
+    float x = acc[v];
+    if (EPI == EPI_STORE) {
+      C[(size_t)row * ldc + col] = x;
+    } else {
+      x += bias[col];
+      if (Z) Z[(size_t)row * ldc + col] = x;
+      const float h = gelu_f(x);
+      if (Hb) Hb[(size_t)row * ldc + col] = (__bf16)h;
+      if (Ht) Ht[(size_t)col * M + row] = (__bf16)h;
+      if (EPI == EPI_BIAS_GELU_DOT) dot[v] = h * w[col];
+    }
+  }
+  if (EPI == EPI_BIAS_GELU_DOT) {
+#pragma unroll
+    for (int v = 0; v < 16; ++v) {
+      float s = dot[v];
+      for (int o = 1; o < 32; o <<= 1) s += __shfl_xor(s, o, 64);
+      const int row = m0 + wm * 32 + 8 * (v >> 2) + 4 * (lane >> 5) + (v & 3);
+      if ((lane & 31) == 0) part[(size_t)((n0 + wn * 32) / 32) * M + row] = s;
+    }
+  }
+}
+
+#define OKR_GEMM_INST(E)                                                                                       \
+  template __global__ void k_gemm_nt<E>(const __bf16*, int, const __bf16*, int, int, float*, int, const float*, \
+                                        float*, __bf16*, __bf16*, int, const float*, float*);
+OKR_GEMM_INST(EPI_STORE)
+OKR_GEMM_INST(EPI_BIAS_GELU)
+OKR_GEMM_INST(EPI_BIAS_GELU_DOT)
+#undef OKR_GEMM_INST
+
+// y[m] = b3 + sum over the column blocks' partial dots, in a fixed order.
+__global__ void k_rowdot_finish(const float* __restrict__ part, int nblk, int M, const float* __restrict__ b3,
+                                float* __restrict__ y) {
+  const int m = blockIdx.x * blockDim.x + threadIdx.x;
+  if (m >= M) return;
+  float s = b3[0];
+  for (int j = 0; j < nblk; ++j) s += part[(size_t)j * M + m];
+  y[m] = s;
+}
+
+// ------------------------------------------------------------- training --
+// Batch rows (FP32 [B][F]) to BF16 [B][F] and the transposed [64][B] (rows
+// F..63 zero) for the weight gradient of layer 1.
+__global__ void k_batch_cast(const float* __restrict__ X, int B, __bf16* __restrict__ Xb, __bf16* __restrict__ Xt) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= B * 64) return;
+  const int b = i / 64, j = i % 64;
+  const float v = j < kSurrF ? X[(size_t)b * kSurrF + j] : 0.f;
+  if (j < kSurrF) Xb[(size_t)b * kSurrF + j] = (__bf16)v;
+  Xt[(size_t)j * B + b] = (__bf16)v;
+}
+
+__global__ void k_loss_dy(const float* __restrict__ y, const float* __restrict__ t, int B, float* __restrict__ dy,
+                          float* __restrict__ loss) {
+  const int b = blockIdx.x * blockDim.x + threadIdx.x;
+  float l = 0.f;
+  if (b < B) {
+    const float d = y[b] - t[b];
+    dy[b] = 2.f * d / B;
+    l = d * d / B;
+  }
+  for (int o = 32; o > 0; o >>= 1) l += __shfl_xor(l, o, 64);
+  if ((threadIdx.x & 63) == 0) atomicAdd(loss, l);
+}
+
+// dZ2 = dy w3^T * gelu'(Z2) as BF16 [B][256] and transposed [256][B]
+__global__ void k_dz2(const float* __restrict__ Z2, const float* __restrict__ dy, const float* __restrict__ w3, int B,
+                      __bf16* __restrict__ dZ2b, __bf16* __restrict__ dZ2t) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= B * kSurrH) return;
+  const int b = i / kSurrH, o = i % kSurrH;
+  const float v = dy[b] * w3[o] * gelu_grad_f(Z2[i]);
+  dZ2b[i] = (__bf16)v;
+  dZ2t[(size_t)o * B + b] = (__bf16)v;
+}
+
+// dZ1 = dH1 * gelu'(Z1), transposed BF16 [256][B]
+__global__ void k_dz1(const float* __restrict__ dH1, const float* __restrict__ Z1, int B, __bf16* __restrict__ dZ1t) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= B * kSurrH) return;
+  const int b = i / kSurrH, o = i % kSurrH;
+  dZ1t[(size_t)o * B + b] = (__bf16)(dH1[i] * gelu_grad_f(Z1[i]));
+}
+
+// Column reductions over the batch (one thread per column, fixed order):
+//   gb2[o] = sum_b dy[b] w3[o] gelu'(Z2[b][o]);  gw3[o] = sum_b gelu(Z2[b][o]) dy[b]
+//   gb1[o] = sum_b dH1[b][o] gelu'(Z1[b][o]);    gb3 = sum_b dy[b]
+__global__ void k_colsums(const float* __restrict__ Z1, const float* __restrict__ dH1, const float* __restrict__ Z2,
+                          const float* __restrict__ dy, const float* __restrict__ w3, int B, float* __restrict__ gb1,
+                          float* __restrict__ gb2, float* __restrict__ gw3, float* __restrict__ gb3) {
+  const int o = blockIdx.x * blockDim.x + threadIdx.x;
+  if (o < kSurrH) {
+    float a = 0.f, c = 0.f, d = 0.f;
+    for (int b = 0; b < B; ++b) {
+      const float z2 = Z2[(size_t)b * kSurrH + o];
+      a += dy[b] * w3[o] * gelu_grad_f(z2);
+      c += gelu_f(z2) * dy[b];
+      d += dH1[(size_t)b * kSurrH + o] * gelu_grad_f(Z1[(size_t)b * kSurrH + o]);
+    }
+    gb2[o] = a;
+    gw3[o] = c;
+    gb1[o] = d;
+  } else if (o == kSurrH) {
+    float s = 0.f;
+    for (int b = 0; b < B; ++b) s += dy[b];
+    gb3[0] = s;
+  }
+}
+
+__global__ void k_copy_cols(const float* __restrict__ src, int lds, float* __restrict__ dst, int rows, int cols) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < rows * cols) dst[i] = src[(size_t)(i / cols) * lds + i % cols];
+}
+
+__global__ void k_adam(float* __restrict__ p, const float* __restrict__ gr, float* __restrict__ m,
+                       float* __restrict__ v, int n, float lr, float c1, float c2) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  const float gi = gr[i];
+  const float mi = 0.9f * m[i] + 0.1f * gi;
+  const float vi = 0.999f * v[i] + 0.001f * gi * gi;
+  m[i] = mi;
+  v[i] = vi;
+  p[i] -= lr * (mi / c1) / (sqrtf(vi / c2) + 1e-8f);
+}
+
+// BF16 copies of the weights: W1 [256][32], W2 [256][256] and W2^T.
+__global__ void k_refresh_weights(const float* __restrict__ prm, __bf16* __restrict__ W1b, __bf16* __restrict__ W2b,
+                                  __bf16* __restrict__ W2tb) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < kSurrH * kSurrF) W1b[i] = (__bf16)prm[kOffW1 + i];
+  if (i < kSurrH * kSurrH) {
+    const float v = prm[kOffW2 + i];
+    W2b[i] = (__bf16)v;
+    if (W2tb) W2tb[(size_t)(i % kSurrH) * kSurrH + i / kSurrH] = (__bf16)v;
+  }
+}
+
+__global__ void k_zero_f32(float* __restrict__ a, int n) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) a[i] = 0.f;
+}
+
+// ---------------------------------------------------- top-k and decision --
+__device__ __forceinline__ uint32_t ordered(float y) {
+  const uint32_t u = __float_as_uint(y);
+  return (u & 0x80000000u) ? ~u : (u | 0x80000000u);
+}
+
+// Rank key of every mask: predicted feasible first, then most reduced, then
+// smallest predicted error (26-bit monotone quantisation), ties by mask.
+__global__ void k_surr_keys(const SegHdr* __restrict__ hdrs, int g, const float* __restrict__ y, float ln_ebar,
+                            uint32_t* __restrict__ keys) {
+  const SegHdr H = hdrs[g];
+  const uint32_t m = blockIdx.x * blockDim.x + threadIdx.x;
+  if (!H.valid || m >= (1u << H.k)) return;
+  const uint32_t pf = y[m] <= ln_ebar ? 0u : 1u;
+  const uint32_t lvl = (uint32_t)(H.k - __popc(m)) & 31u;
+  keys[m] = (pf << 31) | (lvl << 26) | (ordered(y[m]) >> 6);
+}
+
+// The K smallest keys (ties by mask index) in mask order: radix select of the
+// K-th key, then an ordered compaction.  One block.
+__global__ __launch_bounds__(1024) void k_topk(const SegHdr* __restrict__ hdrs, int g,
+                                               const uint32_t* __restrict__ keys, int topk,
+                                               const int* __restrict__ status, uint32_t* __restrict__ list,
+                                               int* __restrict__ count) {
+  __shared__ int hist[256];
+  __shared__ uint32_t s_prefix, s_maskbits;
+  __shared__ int s_need;
+  __shared__ int scan[1024];
+  const SegHdr H = hdrs[g];
+  if (!H.valid || (*status & (16 | 32))) {
+    if (threadIdx.x == 0) *count = 0;
+    return;
+  }
+  const uint32_t nm = 1u << H.k;
+  const int K = (int)min((uint32_t)topk, nm);
+  if (threadIdx.x == 0) { s_prefix = 0; s_maskbits = 0; s_need = K; }
+  __syncthreads();
+  for (int shift = 24; shift >= 0; shift -= 8) {
+    for (int q = threadIdx.x; q < 256; q += blockDim.x) hist[q] = 0;
+    __syncthreads();
+    const uint32_t pre = s_prefix, mb = s_maskbits;
+    for (uint32_t m = threadIdx.x; m < nm; m += blockDim.x)
+      if ((keys[m] & mb) == pre) atomicAdd(&hist[(keys[m] >> shift) & 255u], 1);
+    __syncthreads();
+    if (threadIdx.x == 0) {
+      int need = s_need, cum = 0, d = 0;
+      for (d = 0; d < 256; ++d) {
+        if (cum + hist[d] >= need) break;
+        cum += hist[d];
+      }
+      s_need = need - cum;
+      s_prefix = pre | ((uint32_t)d << shift);
+      s_maskbits = mb | (255u << shift);
+    }
+    __syncthreads();
+  }
+  const uint32_t T = s_prefix;
+  const int need_eq = s_need;  // masks with key == T to take, lowest first
+  int taken = 0, eq_seen = 0;
+  for (uint32_t base = 0; base < nm; base += blockDim.x) {
+    const uint32_t m = base + threadIdx.x;
+    const uint32_t key = m < nm ? keys[m] : 0xffffffffu;
+    const int eq = (m < nm && key == T) ? 1 : 0;
+    const int eq_before = block_exclusive_scan(eq, scan);
+    const int take = (m < nm && (key < T || (eq && eq_seen + eq_before < need_eq))) ? 1 : 0;
+    const int pos = block_exclusive_scan(take, scan);
+    if (take) list[taken + pos] = m;
+    // totals of this chunk (last thread's exclusive value plus its own flag)
+    __shared__ int s_tot_eq, s_tot_take;
+    if (threadIdx.x == blockDim.x - 1) {
+      s_tot_eq = eq_before + eq;
+      s_tot_take = pos + take;
+    }
+    __syncthreads();
+    eq_seen += s_tot_eq;
+    taken += s_tot_take;
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) *count = K;
+}
+
+// Exact (FP64) selection among the top-k: most reduced feasible, smallest
+// error, tie rule, lowest mask.  When no rescored mask is feasible with at
+// least one reduced node, the full enumeration is enabled (gate = 1).
+__global__ __launch_bounds__(1024) void k_surr_decide(const SegHdr* __restrict__ hdrs, int g, SelParams sp,
+                                                      const int* __restrict__ status,
+                                                      const uint32_t* __restrict__ list,
+                                                      const int* __restrict__ count,
+                                                      const MaskScore* __restrict__ sc, DevDecision* __restrict__ decs,
+                                                      int* __restrict__ gate) {
+  __shared__ double shd[16];
+  __shared__ int shi[16];
+  __shared__ unsigned shu[16];
+  const SegHdr H = hdrs[g];
+  if (!H.valid || (*status & (16 | 32))) {
+    if (threadIdx.x == 0) *gate = 1;  // let the full path write its (null) decision
+    return;
+  }
+  const int n = *count;
+  int best = -1;
+  for (int q = threadIdx.x; q < n; q += blockDim.x)
+    if (feasible(sc[q], sp.e_bar)) best = max(best, __popc(list[q]));
+  best = block_reduce(best, [](int a, int b) { return max(a, b); }, shi);
+  if (best < 1) {
+    if (threadIdx.x == 0) *gate = 1;
+    return;
+  }
+  double emin = INFINITY;
+  for (int q = threadIdx.x; q < n; q += blockDim.x)
+    if (feasible(sc[q], sp.e_bar) && __popc(list[q]) == best) emin = fmin(emin, sc[q].e);
+  emin = block_reduce(emin, [](double a, double b) { return fmin(a, b); }, shd);
+  const double thr = emin + sp.tie;
+  unsigned pick = 0xffffffffu;
+  int amb = 0;
+  for (int q = threadIdx.x; q < n; q += blockDim.x) {
+    const MaskScore r = sc[q];
+    const int pc = __popc(list[q]);
+    if (pc >= best && near_boundary(r, sp.e_bar, sp.amb)) amb = 1;
+    if (pc != best || !feasible(r, sp.e_bar)) continue;
+    if (fabs(r.e - thr) <= sp.amb) amb = 1;
+    if (r.e <= thr) pick = min(pick, list[q]);
+  }
+  pick = block_reduce(pick, [](unsigned a, unsigned b) { return min(a, b); }, shu);
+  amb = block_reduce(amb, [](int a, int b) { return a | b; }, shi);
+  if (threadIdx.x == 0) {
+    double epick = 0.0;
+    for (int q = 0; q < n; ++q)
+      if (list[q] == pick) epick = sc[q].e;
+    DevDecision d;
+    d.mask = pick;
+    d.popcount = best;
+    d.e_loc = epick;
+    d.e_min = emin;
+    d.ambiguous = amb;
+    d.found = 1;
+    decs[g] = d;
+    *gate = 0;
+  }
+}
+
+}  // namespace okr
