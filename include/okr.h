@@ -77,7 +77,8 @@ extern "C" {
 #define OKR_FLAG_GRAPH 8u      /* capture the whole search (load flow, every
                                   segment, final outputs) as one hipGraph on
                                   the first call and replay it afterwards;
-                                  ignored with TIMING or DUMP_SCORES */
+                                  ignored with TIMING, DUMP_SCORES or a
+                                  features dump; needs a non-null stream */
 
 typedef struct okr_handle okr_handle;
 

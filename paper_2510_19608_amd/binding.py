@@ -267,7 +267,9 @@ class Reducer:
             self.Yo = dev(f["Y_off"])
             self.Sl = dev(f["S_load"])
             self.Vh = dev(vhat) if vhat is not None else None
-            self.stream = torch.cuda.current_stream(self.device)
+            # a stream of the handle's own (default priority): the null stream
+            # cannot be captured into a graph
+            self.stream = torch.cuda.Stream(device=self.device)
             self.h = okr_create(ctypes.c_void_p(self.stream.cuda_stream))
             self.ws_bytes, self.sizes = okr_plan(self.h, self.topo, self.margins, S)
             self.ws = torch.empty(max(self.ws_bytes, 1), dtype=torch.uint8, device=self.device)
@@ -298,6 +300,8 @@ class Reducer:
         """One pass of the whole search (planning included when replan).  With
         want_features the per-mask surrogate features and FP64 targets of every
         segment are left in ``self.features`` / ``self.targets`` (device)."""
+        # inputs written on the caller's stream are complete before the search
+        self.stream.wait_stream(self.torch.cuda.current_stream(self.device))
         if replan:
             self.ws_bytes_now, _ = okr_plan(self.h, self.topo, self.margins, self.S)
         self.res.Vhat = self.out_Vhat.ctypes.data if want_vhat else None

@@ -727,6 +727,7 @@ extern "C" int okr_reduce_feeder(okr_handle* h, const okr_yblocks* Y, const okr_
     h->ev.resize(2 * std::max(nseg, 1), nullptr);
     for (auto& e : h->ev) OKR_HIP(h, hipEventCreate(&e));
   }
+  if (graph && st == nullptr) OKR_FAIL(h, OKR_E_ARG, "OKR_FLAG_GRAPH needs a non-null stream (the null stream cannot be captured)");
   if (graph) {
     const double2* V0 = (const double2*)loads->V0;
     const std::vector<uint64_t> key = {
