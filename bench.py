@@ -1,15 +1,22 @@
 """Benchmark: candidate reductions scored per second on the 1000-node,
-24-snapshot feeder (whole search per step: planning, load flow, every
-segment's 2^k candidates, arg-min, state update, Y_Kron and final errors).
+24-snapshot feeder, and time-to-optimal of the accelerated forms vs plain.
 
-Prints ONE JSON line.  `value` = candidates scored per second with the inputs
-resident in HBM.  `roofline` describes the dominant kernel (the FP64 scoring
-kernel) from HIP-event timings taken in the timed region; `cpu_baseline` is
-the FP64 CPU oracle on a bounded sample of the same workload.
+One step = one whole search (load flow, every segment's 2^k candidates,
+arg-min, state update, Y_Kron and final errors) with the inputs resident in
+HBM and the topology planned beforehand.
+
+Prints ONE JSON line.  `value` = candidates scored per second by the plain
+FP64 search (every mask scored exactly).  `roofline` describes the dominant
+kernel (the FP64 scoring kernel) from HIP-event timings recorded on the
+library's stream inside the timed region.  `modes` gives the time-to-optimal
+(median of repeated whole searches, graph-captured) of the plain, mixed
+precision and surrogate-pruned forms and their agreement with the plain
+decisions.  `cpu_baseline` is the FP64 CPU oracle on a bounded sample.
 """
 import argparse
 import json
 import os
+import statistics
 import sys
 import time
 
@@ -17,7 +24,6 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 FP64_VECTOR_PEAK_TFLOPS = 78.6   # MI355X FP64 vector (256 CUs x 2.4 GHz x 128 flop/clk)
-FP32_VECTOR_PEAK_TFLOPS = 157.3
 
 
 def cpu_baseline(f, seconds=12.0):
@@ -41,18 +47,77 @@ def cpu_baseline(f, seconds=12.0):
                        f"FP64 Kron elimination + reduced-network solve + scoring per mask, {dt:.1f} s on 1 core")
 
 
+def timed_runs(R, reps):
+    """Median wall time (ms) of `reps` whole searches after one warm-up."""
+    import torch
+    R.run(replan=False)
+    torch.cuda.synchronize()
+    ts = []
+    for _ in range(reps):
+        t0 = time.perf_counter()
+        R.run(replan=False)
+        torch.cuda.synchronize()
+        ts.append((time.perf_counter() - t0) * 1e3)
+    return statistics.median(ts)
+
+
+def decisions(R):
+    res = R.result()
+    return [s["mask"] for s in res["segments"]], [s["popcount"] for s in res["segments"]], res
+
+
+def mode_entry(name, ms, plain_ms, masks, pops, res, ref_masks, ref_pops, ncand, extra=None):
+    d = dict(time_to_optimal_ms=ms, speedup_vs_plain=plain_ms / ms, candidates_per_s=ncand / (ms * 1e-3),
+             agreement=sum(a == b for a, b in zip(masks, ref_masks)) / max(len(ref_masks), 1),
+             reduction_deficit_nodes=sum(ref_pops) - sum(pops), n_kept=int(res["n_kept"]),
+             max_err=res["max_err"])
+    if extra:
+        d.update(extra)
+    return d
+
+
+def surrogate_mode(f, args, plain_ms, ref, ncand):
+    """Train the ranking MLP on the exhaustive search's own (features, error)
+    pairs from other feeders, then run the pruned search on this one."""
+    import torch
+    from paper_2510_19608_amd import Reducer, surrogate
+    from synth_feeders import make_feeder
+    t0 = time.perf_counter()
+    train_feeders = [make_feeder("c2", s) for s in (101, 102)] + [make_feeder("c1", s) for s in range(10)]
+    X, t, _ = surrogate.collect(train_feeders)
+    t_collect = time.perf_counter() - t0
+    t0 = time.perf_counter()
+    params, loss = surrogate.train(X, t, epochs=args.surr_epochs, batch=4096, lr=1e-3, seed=0)
+    torch.cuda.synchronize()
+    t_train = time.perf_counter() - t0
+    n_pairs = int(X.shape[0])
+    del X, t
+    R = Reducer(f, device="cuda:0", graph=True, surrogate=params, top_k=args.top_k)
+    ms = timed_runs(R, args.reps)
+    masks, pops, res = decisions(R)
+    fallback = sum(1 for s in res["segments"] if s["n_scored"] > s["n_refined"])
+    R.close()
+    return mode_entry("surrogate", ms, plain_ms, masks, pops, res, ref[0], ref[1], ncand,
+                      dict(top_k=args.top_k, fallback_segments=fallback, train_pairs=n_pairs,
+                           train_epochs=args.surr_epochs, train_loss_first=float(loss[0]),
+                           train_loss_last=float(loss[-1]), train_s=t_train, collect_s=t_collect))
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--seed", type=int, default=0)
-    ap.add_argument("--precision", default="fp64", choices=["fp64", "mixed"])
+    ap.add_argument("--reps", type=int, default=5, help="searches per mode for the time-to-optimal median")
+    ap.add_argument("--top-k", type=int, default=256)
+    ap.add_argument("--surr-epochs", type=int, default=6)
     ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--no-modes", action="store_true")
     args = ap.parse_args()
     if args.gpus != 1:
         print(json.dumps({"error": "this search runs on one GPU; --gpus above 1 is not supported "
-                                   "(see DESIGN.md for how segments would shard)"}))
+                                   "(segments would shard across GPUs by subtree, see the design notes)"}))
         sys.exit(2)
 
     import torch
@@ -60,21 +125,22 @@ def main():
     from synth_feeders import make_feeder
 
     f = make_feeder("c2", args.seed)
-    R = Reducer(f, device="cuda:0", precision=args.precision, timing=True)
+    R = Reducer(f, device="cuda:0", timing=True)
     ncand = int(R.sizes.n_candidates)
     for _ in range(args.warmup):
-        R.run()
+        R.run(replan=False)
     torch.cuda.synchronize()
     kern_ms, flops = 0.0, 0.0
     t0 = time.perf_counter()
     for _ in range(args.steps):
-        R.run()
+        R.run(replan=False)
         r = R.res
         kern_ms += r.score_kernel_ms
         flops += r.algorithmic_flops
     torch.cuda.synchronize()
     dt = time.perf_counter() - t0
-    out = R.result()
+    ref_masks, ref_pops, out = decisions(R)
+    R.close()
     ms_per_step = dt * 1e3 / args.steps
     launches = out["n_score_launches"] * args.steps
     achieved = flops / (kern_ms * 1e-3) / 1e12 if kern_ms > 0 else None
@@ -89,23 +155,38 @@ def main():
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "f64" if args.precision == "fp64" else "f32+f64",
+        "dtype": "f64",
         "data": "synthetic",
         "config": {"workload": "c2: 1000-node synthetic three-phase feeder, 24 snapshots, "
                                "segments of 16 eligible nodes, exhaustive 2^16 masks per segment",
-                   "seed": args.seed, "n_candidates": ncand, "segments": int(R.sizes.n_segments),
-                   "precision": args.precision, "e_bar": f["e_bar"], "n_kept": int(out["n_kept"]),
-                   "max_err": out["max_err"], "time_to_optimal_ms": ms_per_step,
-                   "parallelism": "single GPU"},
+                   "seed": args.seed, "n_candidates": ncand, "segments": int(out["n_score_launches"]),
+                   "precision": "fp64", "e_bar": f["e_bar"], "n_kept": int(out["n_kept"]),
+                   "max_err": out["max_err"], "parallelism": "single GPU"},
         "roofline": {"bound": "alu", "achieved": achieved, "peak": FP64_VECTOR_PEAK_TFLOPS,
                      "unit": "TFLOP/s", "frac": (achieved / FP64_VECTOR_PEAK_TFLOPS) if achieved else None,
                      "traffic": None, "kernel": "okr::k_score_fp64",
                      "avg_launch_us": kern_ms * 1e3 / max(launches, 1),
                      "flops_per_launch": flops / max(launches, 1)},
     }
+    if not args.no_modes:
+        modes = {}
+        Rg = Reducer(f, device="cuda:0", graph=True)
+        plain_ms = timed_runs(Rg, args.reps)
+        m, p, res = decisions(Rg)
+        Rg.close()
+        modes["plain_fp64"] = mode_entry("plain", plain_ms, plain_ms, m, p, res, ref_masks, ref_pops, ncand)
+        Rm = Reducer(f, device="cuda:0", graph=True, precision="mixed")
+        ms = timed_runs(Rm, args.reps)
+        m, p, res = decisions(Rm)
+        refined = sum(s["n_refined"] for s in res["segments"])
+        dev = max(s["fp32_dev"] for s in res["segments"])
+        Rm.close()
+        modes["mixed"] = mode_entry("mixed", ms, plain_ms, m, p, res, ref_masks, ref_pops, ncand,
+                                    dict(fp64_rescored_masks=refined, max_fp32_vs_fp64_error=dev))
+        modes["surrogate"] = surrogate_mode(f, args, plain_ms, (ref_masks, ref_pops), ncand)
+        line["modes"] = modes
     if not args.no_cpu:
         line["cpu_baseline"] = cpu_baseline(f)
-    R.close()
     print(json.dumps(line))
 
 

@@ -196,6 +196,7 @@ __global__ __launch_bounds__(256) void k_build_struct(Topo T, State St, int g, i
       cr[C_PATH_OFF] = path_off[c];
       cr[C_PATH_LEN] = path_len[c];
       cr[C_OUTER] = s_outer[c];
+      cr[C_PHASE] = T.phase[s_head[c]];
       for (int p = 0; p < 3; ++p) { cr[C_ZOFF0 + p] = 0; cr[C_ZCNT0 + p] = 0; }
     }
     for (int s = 0; s < ns && !err; ++s) {

@@ -47,56 +47,65 @@ __device__ __forceinline__ double vmag(double2 a) { return sqrt_nr(a.x * a.x + a
 // Walk one chain for one mask: super-node slots top to bottom; a reduced slot
 // adds the voltage rise of moving its aggregated current to its current super
 // (P from LDS); a kept slot becomes the super of the slots below it.  With
-// ERR, every slot cluster's error against its super's magnitude and the band
-// of kept slots are folded into (el, slack).  Slot records and head voltages
-// are wave-uniform and read with scalar loads; P entries depend on the lane's
-// super slot and come from LDS.
+// ERR, every slot cluster's error against its super's magnitude is folded
+// into el, and the squared magnitudes of kept slots into (qmin, qmax) for the
+// band (the slack is formed once per mask: sqrt is monotone, so
+// min(|V| - vmin) = sqrt(min |V|^2) - vmin exactly).  Structure records are
+// wave-uniform (scalar loads, uniform phase branches); P entries depend on the
+// lane's super slot.
 template <bool ERR>
 __device__ __forceinline__ void walk_chain(const int* __restrict__ cr, const int* __restrict__ slots,
-                                           const double2* Ps, const TargetRec* __restrict__ Ss,
-                                           const double2* __restrict__ Hs, int c, uint32_t m, double2& B0,
-                                           double2& B1, double2& B2, double& el, double& slack, double vmin,
-                                           double vmax) {
+                                           const double2* Ps, const TargetRec* Ss, const double2* Hs, int c,
+                                           uint32_t m, double2& B0, double2& B1, double2& B2, double& el,
+                                           double& qmin, double& qmax) {
   double2 S0 = B0, S1 = B1, S2 = B2;
   double sm0 = 0.0, sm1 = 0.0, sm2 = 0.0;
   if (ERR) {
+    const int hph = cr[C_PHASE];
     const double2* hv = Hs + c * 3;
-    sm0 = vmag(cadd(hv[0], B0));
-    sm1 = vmag(cadd(hv[1], B1));
-    sm2 = vmag(cadd(hv[2], B2));
+    if (hph & 1) sm0 = vmag(cadd(hv[0], B0));
+    if (hph & 2) sm1 = vmag(cadd(hv[1], B1));
+    if (hph & 4) sm2 = vmag(cadd(hv[2], B2));
   }
   const int ns = cr[C_NSLOT], s0 = cr[C_SLOT0];
   int sidx = 0;
   for (int r = 0; r < ns; ++r) {
     const int* sr = slots + (s0 + r) * kSlotInts;
-    const int bit = sr[SL_BIT], pb = sr[SL_PAIRBASE];
+    const int bit = sr[SL_BIT], pb = sr[SL_PAIRBASE], ph = sr[SL_PHASE];
     const bool red = (m >> bit) & 1u;
     const double rf = red ? 1.0 : 0.0;
     const double2* pp = Ps + (pb + sidx) * 3;
-    const double2 p0 = pp[0], p1 = pp[1], p2 = pp[2];
-    S0.x = fma(rf, p0.x, S0.x); S0.y = fma(rf, p0.y, S0.y);
-    S1.x = fma(rf, p1.x, S1.x); S1.y = fma(rf, p1.y, S1.y);
-    S2.x = fma(rf, p2.x, S2.x); S2.y = fma(rf, p2.y, S2.y);
-    sidx = red ? sidx : r + 1;
-    if (ERR) {
-      const int ph = sr[SL_PHASE];
-      const TargetRec* tr = Ss + (s0 + r) * 3;
+    const TargetRec* tr = Ss + (s0 + r) * 3;
 #define OKR_SLOT_PHASE(P_, S_, SM_)                                              \
-      if (ph & (1 << P_)) {                                                      \
+    if (ph & (1 << P_)) {                                                        \
+      const double2 pv = pp[P_];                                                 \
+      S_.x = fma(rf, pv.x, S_.x);                                                \
+      S_.y = fma(rf, pv.y, S_.y);                                                \
+      if (ERR) {                                                                 \
         const TargetRec t = tr[P_];                                              \
-        const double mag = vmag(cadd(t.W, S_));                                  \
-        SM_ = red ? SM_ : mag;                                                   \
-        const double sk = fmin(mag - vmin, vmax - mag);                          \
-        slack = red ? slack : fmin(slack, sk);                                   \
+        const double vx = t.W.x + S_.x, vy = t.W.y + S_.y;                       \
+        const double q = fma(vx, vx, vy * vy);                                   \
+        if (!red) SM_ = sqrt_nr(q);                                              \
+        qmin = fmin(qmin, red ? INFINITY : q);                                   \
+        qmax = fmax(qmax, red ? -INFINITY : q);                                  \
         el = fmax(el, fmax(SM_ - t.lo, t.hi - SM_));                             \
-      }
-      OKR_SLOT_PHASE(0, S0, sm0)
-      OKR_SLOT_PHASE(1, S1, sm1)
-      OKR_SLOT_PHASE(2, S2, sm2)
-#undef OKR_SLOT_PHASE
+      }                                                                          \
     }
+    OKR_SLOT_PHASE(0, S0, sm0)
+    OKR_SLOT_PHASE(1, S1, sm1)
+    OKR_SLOT_PHASE(2, S2, sm2)
+#undef OKR_SLOT_PHASE
+    sidx = red ? sidx : r + 1;
   }
   B0 = S0; B1 = S1; B2 = S2;
+}
+
+// Band slack of a mask from the extreme squared magnitudes of its kept
+// node-phases: min(|V| - vmin, vmax - |V|) over them (+inf if there are none).
+__device__ __forceinline__ double band_slack(double qmin, double qmax, double vmin, double vmax) {
+  const double a = qmin < INFINITY ? sqrt_nr(qmin) - vmin : INFINITY;
+  const double b = qmax > 0.0 ? vmax - sqrt_nr(qmax) : INFINITY;
+  return fmin(a, b);
 }
 
 __device__ __forceinline__ bool feasible(const MaskScore& r, double e_bar) { return r.e <= e_bar && r.slack >= 0.0; }
@@ -106,29 +115,32 @@ __device__ __forceinline__ bool near_boundary(const MaskScore& r, double e_bar, 
   return !rin && !rout;
 }
 
-// Error and band slack of one mask for one snapshot (max / min folded into
-// el / slack): every chain walked with its nesting path recomputed, then the
-// zone entries anchored below it.
+// Error of one mask for one snapshot folded into el, kept squared magnitudes
+// into (qmin, qmax): every chain walked with its nesting path recomputed, then
+// the zone entries anchored below it.
 __device__ __forceinline__ void score_snapshot(const SegHdr& H, const int* __restrict__ chains,
                                                const int* __restrict__ slots, const int* __restrict__ nest,
-                                               const double2* Ps, const TargetRec* __restrict__ Ss,
-                                               const double2* __restrict__ Hs, const TargetRec* __restrict__ zrec_l,
-                                               uint32_t m, double vmin, double vmax, double& el, double& slack) {
+                                               const double2* Ps, const TargetRec* Ss, const double2* Hs,
+                                               const TargetRec* __restrict__ zrec_l, uint32_t m, double& el,
+                                               double& qmin, double& qmax) {
   for (int c = 0; c < H.nchains; ++c) {
     const int* cr = chains + c * kChainInts;
     double2 B0 = make_double2(0.0, 0.0), B1 = B0, B2 = B0;
     const int nl = cr[C_NEST_LEN], no = cr[C_NEST_OFF];
     for (int q = 0; q + 1 < nl; ++q) {
       const int oc = nest[no + q];
-      walk_chain<false>(chains + oc * kChainInts, slots, Ps, Ss, Hs, oc, m, B0, B1, B2, el, slack, vmin, vmax);
+      walk_chain<false>(chains + oc * kChainInts, slots, Ps, Ss, Hs, oc, m, B0, B1, B2, el, qmin, qmax);
     }
-    walk_chain<true>(cr, slots, Ps, Ss, Hs, c, m, B0, B1, B2, el, slack, vmin, vmax);
+    walk_chain<true>(cr, slots, Ps, Ss, Hs, c, m, B0, B1, B2, el, qmin, qmax);
 #define OKR_ZONE_PHASE(P_, B_)                                                   \
     for (int q = cr[C_ZOFF0 + P_], qe = q + cr[C_ZCNT0 + P_]; q < qe; ++q) {   \
       const TargetRec t = zrec_l[q];                                             \
-      const double mag = vmag(cadd(t.W, B_));                                    \
+      const double vx = t.W.x + B_.x, vy = t.W.y + B_.y;                         \
+      const double q2 = fma(vx, vx, vy * vy);                                    \
+      const double mag = sqrt_nr(q2);                                            \
       el = fmax(el, fmax(mag - t.lo, t.hi - mag));                               \
-      slack = fmin(slack, fmin(mag - vmin, vmax - mag));                         \
+      qmin = fmin(qmin, q2);                                                     \
+      qmax = fmax(qmax, q2);                                                     \
     }
     OKR_ZONE_PHASE(0, B0)
     OKR_ZONE_PHASE(1, B1)

@@ -94,8 +94,8 @@ size_t align256(size_t x) { return (x + 255) & ~size_t(255); }
 // Snapshot groups of a scoring launch: enough blocks to fill the chip (about
 // 8192 waves), each group a contiguous run of snapshots.
 int snap_groups(int k, int S, int* spg) {
-  const int mblocks = (int)((((uint64_t)1 << k) + kScoreBlock - 1) / kScoreBlock);
-  int SG = std::min(S, std::max(1, 8192 / mblocks));
+  const int mblocks = (int)((((uint64_t)1 << k) + kScoreThreads - 1) / kScoreThreads);
+  int SG = std::min(S, std::max(1, 2048 / mblocks));
   SG = std::min(SG, kMaxSnapGroups);
   *spg = (S + SG - 1) / SG;
   return (S + *spg - 1) / *spg;
@@ -572,7 +572,7 @@ void enqueue_search(okr_handle* h, const Ptrs& p, const okr_yblocks* Y, const ok
                        (const int*)p.tab, p.T, p.St, (const double2*)p.Vcur, (const double*)p.absV, p.srec, p.zrec,
                        p.econst);
     const uint32_t nmask = 1u << k;
-    const int mblocks = (int)((nmask + kScoreBlock - 1) / kScoreBlock);
+    const int mblocks = (int)((nmask + kScoreThreads - 1) / kScoreThreads);
     int spg;
     const int SG = snap_groups(k, S, &spg);
     const int* gate = nullptr;
@@ -610,7 +610,7 @@ void enqueue_search(okr_handle* h, const Ptrs& p, const okr_yblocks* Y, const ok
     }
     if (!mixed) {
       if (ev) (void)hipEventRecord((*ev)[2 * g], st);
-      hipLaunchKernelGGL(k_score_fp64, dim3(mblocks, SG), dim3(kScoreBlock), 0, st, (const SegHdr*)p.hdrs, g,
+      hipLaunchKernelGGL(k_score_fp64, dim3(mblocks, SG), dim3(kScoreThreads), 0, st, (const SegHdr*)p.hdrs, g,
                          (const int*)p.tab, (const double2*)p.P, (const TargetRec*)p.srec, (const double2*)p.headV,
                          (const TargetRec*)p.zrec, (const double*)p.econst, spg, SG, sp, p.part, p.fin, p.tiles,
                          p.tickets, gate);
@@ -636,7 +636,7 @@ void enqueue_search(okr_handle* h, const Ptrs& p, const okr_yblocks* Y, const ok
                          (const double2*)p.headV, (const TargetRec*)p.zrec, mg->v_min, mg->v_max, p.P32, p.S32,
                          p.H32, p.Z32);
       if (ev) (void)hipEventRecord((*ev)[2 * g], st);
-      hipLaunchKernelGGL(k_score_fp32, dim3(mblocks, SG), dim3(kScoreBlock), 0, st, (const SegHdr*)p.hdrs, g,
+      hipLaunchKernelGGL(k_score_fp32, dim3(mblocks, SG), dim3(kScoreThreads), 0, st, (const SegHdr*)p.hdrs, g,
                          (const int*)p.tab, (const Pair32*)p.P32, (const Rec32*)p.S32, (const Head32*)p.H32,
                          (const Rec32*)p.Z32, (const double*)p.econst, spg, SG, sp, p.part32, p.fin32, p.tiles32,
                          p.tickets);

@@ -8,7 +8,8 @@ namespace okr {
 
 constexpr int kMaxK = 24;                    // eligible nodes per segment
 constexpr int kMaxPairs = kMaxK * (kMaxK + 1) / 2;  // (super slot, reduced slot) pairs
-constexpr int kScoreBlock = 64;              // one wave per scoring block
+constexpr int kScoreBlock = 64;              // masks per tile record (one wave)
+constexpr int kScoreThreads = 256;           // scoring block: 4 waves, one mask per lane
 
 // Header of one segment's tables (one per segment, in device memory), written
 // by the device-side builder; offsets index the int32 table buffer.
@@ -58,7 +59,7 @@ struct State {
 
 // chain record
 enum { C_HEAD = 0, C_NSLOT, C_SLOT0, C_NEST_OFF, C_NEST_LEN, C_PATH_OFF, C_PATH_LEN,
-       C_ZOFF0, C_ZOFF1, C_ZOFF2, C_ZCNT0, C_ZCNT1, C_ZCNT2, C_OUTER, kChainInts };
+       C_ZOFF0, C_ZOFF1, C_ZOFF2, C_ZCNT0, C_ZCNT1, C_ZCNT2, C_OUTER, C_PHASE, kChainInts };
 // slot record
 enum { SL_NODE = 0, SL_BIT, SL_PHASE, SL_PAIRBASE, SL_PATHPOS, SL_CHAIN, kSlotInts };
 // pair record: reduced slot node, first and last path index summed, chain path

@@ -214,36 +214,41 @@ __global__ void k_from_vhat(int n, int S, const uint8_t* __restrict__ phase, con
 // ---------------------------------------------------------------- scoring --
 // One lane scores one mask over the block's snapshot group: e = max error
 // over the affected nodes, slack = min band slack over their kept node-phases.
-// The last block of a 64-mask tile to finish (ticket counter) folds the
-// snapshot groups into the final per-mask score and writes the tile record.
-__global__ __launch_bounds__(kScoreBlock) void k_score_fp64(
+// A block is 4 waves (256 masks) sharing the snapshot's LDS stage: the pair
+// table P, the slot targets and the chain heads.  The last block of a
+// 256-mask range to finish (ticket counter) folds the snapshot groups into
+// the final per-mask score and writes one tile record per wave.
+__global__ __launch_bounds__(kScoreThreads) void k_score_fp64(
     const SegHdr* __restrict__ hdrs, int g, const int* __restrict__ tab, const double2* __restrict__ P,
     const TargetRec* __restrict__ srec, const double2* __restrict__ headV,
     const TargetRec* __restrict__ zrec, const double* __restrict__ econst, int snaps_per_group, int SG,
     SelParams sp, MaskScore* __restrict__ part, MaskScore* __restrict__ fin, TileRec* __restrict__ tiles,
     int* __restrict__ tickets, const int* __restrict__ gate) {
   __shared__ double2 Ps[kMaxPairs * 3];
+  __shared__ TargetRec Ts[kMaxK * 3];
+  __shared__ double2 Hv[kMaxK * 3];
   __shared__ int ticket;
   const SegHdr H = hdrs[g];
   if (!H.valid || (gate && *gate == 0)) return;
-  const uint32_t m = blockIdx.x * kScoreBlock + threadIdx.x;
+  const int tid = threadIdx.x;
+  const uint32_t m = blockIdx.x * kScoreThreads + tid;
   const int sg = blockIdx.y;
   const int l0 = sg * snaps_per_group;
   const int l1 = min(H.S, l0 + snaps_per_group);
   const int* chains = tab + H.o_chain;
   const int* slots = tab + H.o_slot;
   const int* nest = tab + H.o_nest;
-  const double vmin = sp.vmin, vmax = sp.vmax;
-  double e = 0.0, slack = INFINITY;
+  double e = 0.0, qmin = INFINITY, qmax = -INFINITY;
   for (int l = l0; l < l1; ++l) {
     const double2* Pl = P + (size_t)l * H.npairs * 3;
-    for (int q = threadIdx.x; q < H.npairs * 3; q += kScoreBlock) Ps[q] = Pl[q];
-    const TargetRec* Ss = srec + (size_t)l * H.nslots * 3;
-    const double2* Hs = headV + (size_t)l * H.nchains * 3;
+    for (int q = tid; q < H.npairs * 3; q += kScoreThreads) Ps[q] = Pl[q];
+    const TargetRec* Sl = srec + (size_t)l * H.nslots * 3;
+    for (int q = tid; q < H.nslots * 3; q += kScoreThreads) Ts[q] = Sl[q];
+    const double2* Hl = headV + (size_t)l * H.nchains * 3;
+    for (int q = tid; q < H.nchains * 3; q += kScoreThreads) Hv[q] = Hl[q];
     __syncthreads();
-    const TargetRec* zrec_l = zrec + (size_t)l * H.nz;
     double el = econst[l];
-    score_snapshot(H, chains, slots, nest, Ps, Ss, Hs, zrec_l, m, vmin, vmax, el, slack);
+    score_snapshot(H, chains, slots, nest, Ps, Ts, Hv, zrec + (size_t)l * H.nz, m, el, qmin, qmax);
     e = fmax(e, el);
     __syncthreads();
   }
@@ -252,22 +257,22 @@ __global__ __launch_bounds__(kScoreBlock) void k_score_fp64(
   if (valid) {
     MaskScore r;
     r.e = e;
-    r.slack = slack;
+    r.slack = band_slack(qmin, qmax, sp.vmin, sp.vmax);
     part[(size_t)sg * nmask + m] = r;
   }
   __threadfence();
-  if (threadIdx.x == 0) ticket = atomicAdd(&tickets[blockIdx.x], 1);
+  if (tid == 0) ticket = atomicAdd(&tickets[blockIdx.x], 1);
   __syncthreads();
   if (ticket != SG - 1) return;
-  // last block of this tile: combine the snapshot groups
+  // last block of this mask range: combine the snapshot groups
   MaskScore r;
   r.e = 0.0;
   r.slack = INFINITY;
   if (valid) {
-    for (int g = 0; g < SG; ++g) {
-      const volatile MaskScore* q = part + (size_t)g * nmask + m;
-      r.e = fmax(r.e, q->e);
-      r.slack = fmin(r.slack, q->slack);
+    for (int q = 0; q < SG; ++q) {
+      const volatile MaskScore* x = part + (size_t)q * nmask + m;
+      r.e = fmax(r.e, x->e);
+      r.slack = fmin(r.slack, x->slack);
     }
     fin[m] = r;
   }
@@ -281,14 +286,15 @@ __global__ __launch_bounds__(kScoreBlock) void k_score_fp64(
   }
   double em = (feas && pc == best) ? r.e : INFINITY;
   for (int o = 32; o > 0; o >>= 1) em = fmin(em, __shfl_xor(em, o, 64));
-  if (threadIdx.x == 0) {
+  const uint32_t tile = m / kScoreBlock;
+  if ((tid & 63) == 0 && tile * kScoreBlock < nmask) {
     TileRec t;
     t.best = best;
     t.near = nearl;
     t.emin = em;
-    tiles[blockIdx.x] = t;
-    tickets[blockIdx.x] = 0;  // ready for the next launch
+    tiles[tile] = t;
   }
+  if (tid == 0) tickets[blockIdx.x] = 0;  // ready for the next launch
 }
 
 // ----------------------------------------------------------------- argmin --
