@@ -114,6 +114,9 @@ def main():
     ap.add_argument("--surr-epochs", type=int, default=6)
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-modes", action="store_true")
+    ap.add_argument("--copy-probe-mib", type=int, default=0,
+                    help="first run one device-to-device copy of this many MiB (a known-size reference "
+                         "for hardware byte counters)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(json.dumps({"error": "this search runs on one GPU; --gpus above 1 is not supported "
@@ -124,6 +127,12 @@ def main():
     from paper_2510_19608_amd import Reducer
     from synth_feeders import make_feeder
 
+    if args.copy_probe_mib:
+        src = torch.ones(args.copy_probe_mib << 18, dtype=torch.float32, device="cuda:0")
+        dst = torch.empty_like(src)
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst
     f = make_feeder("c2", args.seed)
     R = Reducer(f, device="cuda:0", timing=True)
     ncand = int(R.sizes.n_candidates)

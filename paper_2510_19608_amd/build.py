@@ -1,23 +1,43 @@
-"""Build step of the HIP library (gfx950): hipcc -> libokr.so in this package."""
+"""Build step of the HIP library (gfx950): hipcc -> libokr.so in this package.
+
+Each source is compiled to an object of its own (in parallel), then linked.
+The candidate-scoring unit is compiled with NaNs excluded and the IEEE mode
+bit off: its max/min reductions then need no NaN canonicalisation, and no
+value it handles is a NaN.  Every other unit keeps IEEE semantics (the load
+flow detects divergence through NaN-safe comparisons).
+"""
 import os
 import subprocess
+from concurrent.futures import ThreadPoolExecutor
 
 HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
+OBJ = os.path.join(HERE, "_build")
 LIB = os.path.join(HERE, "libokr.so")
-SOURCES = ["okr_kernels.hip", "okr_build.hip", "okr_mixed.hip", "okr_surrogate.hip", "okr_host.cpp"]
+SOURCES = ["okr_kernels.hip", "okr_build.hip", "okr_score.hip", "okr_mixed.hip", "okr_surrogate.hip",
+           "okr_host.cpp"]
 FLAGS = [
-    "--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC", "-shared",
+    "--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC",
     # no packed-FP32 instructions anywhere in the device code
     "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
 ]
+EXTRA = {"okr_score.hip": ["-fno-honor-nans", "-mno-amdgpu-ieee"]}
 
 
 def build() -> str:
     hipcc = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
+    os.makedirs(OBJ, exist_ok=True)
+
+    def compile_one(src):
+        obj = os.path.join(OBJ, os.path.splitext(src)[0] + ".o")
+        cmd = [hipcc] + FLAGS + EXTRA.get(src, []) + ["-c", "-o", obj, os.path.join(CSRC, src)]
+        subprocess.run(cmd, check=True, cwd=CSRC)
+        return obj
+
+    with ThreadPoolExecutor(max_workers=min(len(SOURCES), 6)) as ex:
+        objs = list(ex.map(compile_one, SOURCES))
     tmp = LIB + ".tmp"
-    cmd = [hipcc] + FLAGS + ["-o", tmp] + [os.path.join(CSRC, s) for s in SOURCES]
-    subprocess.run(cmd, check=True, cwd=CSRC)
+    subprocess.run([hipcc, "--offload-arch=gfx950", "-shared", "-fPIC", "-o", tmp] + objs, check=True, cwd=CSRC)
     os.replace(tmp, LIB)
     return LIB
 

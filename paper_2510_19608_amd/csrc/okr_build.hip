@@ -26,34 +26,62 @@ __device__ __forceinline__ double2 b_cmul(double2 a, double2 b) {
 // skipped by the scoring path and the call reports an error)
 constexpr int kStatusBuild = 64;
 
+// Child of kept node h on the tree path down to its descendant v.
+__device__ __forceinline__ int child_toward(const Topo& T, int h, int v) {
+  const int pv = T.pos[v];
+  for (int q = T.ch_off[h]; q < T.ch_off[h + 1]; ++q) {
+    const int x = T.ch[q];
+    if (T.pos[x] <= pv && pv < T.pos[x] + T.size[x]) return x;
+  }
+  return -1;
+}
+
 __global__ __launch_bounds__(256) void k_build_struct(Topo T, State St, int g, int S, SegHdr* __restrict__ hdrs,
                                                       int* __restrict__ tab, int tab_cap, int* __restrict__ status) {
   __shared__ int s_top[kMaxK], s_tops[kMaxK], s_slotnode[kMaxK], s_slotbit[kMaxK], s_slotchain[kMaxK];
   __shared__ int s_cslot0[kMaxK + 1], s_head[kMaxK], s_outer[kMaxK], s_pathpos[kMaxK];
+  __shared__ int s_spos[kMaxK], s_ssize[kMaxK];
   __shared__ int s_rs[kMaxK], s_re[kMaxK], s_rcum[kMaxK + 1];
   __shared__ int s_keycnt[kMaxK * 3], s_keyoff[kMaxK * 3], s_keycur[kMaxK * 3];
   __shared__ SegHdr s_h;
-  __shared__ int s_err;
+  __shared__ int s_err, s_nch;
   const int* parent = T.parent;
   const int* segment = T.segment;
-  if (threadIdx.x == 0) {
+  const int tid = threadIdx.x;
+  const int o0 = T.seg_off[g];
+  const int k = T.seg_off[g + 1] - o0;
+  if (tid == 0) {
     // an earlier segment failed: leave every later one invalid (its scratch
     // maps may be stale)
-    int err = (*status & kStatusBuild) ? 1 : 0;
-    SegHdr H;
-    for (int q = 0; q < (int)(sizeof(SegHdr) / sizeof(int)); ++q) ((int*)&H)[q] = 0;
-    const int o0 = T.seg_off[g];
-    const int k = T.seg_off[g + 1] - o0;
-    if (k < 1 || k > kMaxK) err = 1;
-    H.g = g;
-    H.k = k;
-    H.S = S;
-    // chain tops: highest node above e reachable through segment or reduced nodes
+    s_err = ((*status & kStatusBuild) || k < 1 || k > kMaxK) ? 1 : 0;
+    s_nch = 0;
+  }
+  __syncthreads();
+  // chain top of every segment node: the highest node above it reachable
+  // through segment or reduced nodes (runs of reduced nodes are crossed in
+  // one step: their nearest kept ancestor is known)
+  if (!s_err && tid < k) {
+    const int e = T.seg_nodes[o0 + tid];
+    int c = e, guard = 0;
+    for (;;) {
+      const int p = parent[c];
+      if (p < 0 || ++guard > T.n) break;
+      if (segment[p] == g) { c = p; continue; }
+      if (St.kept[p]) break;
+      const int h = St.sup[p];
+      const int x = (h >= 0 && h != p) ? child_toward(T, h, p) : -1;
+      if (x < 0) { atomicOr(&s_err, 1); break; }
+      c = x;
+    }
+    s_top[tid] = c;
+    s_spos[tid] = T.pos[e];
+    s_ssize[tid] = T.size[e];
+  }
+  __syncthreads();
+  if (tid == 0 && !s_err) {
     int nch = 0;
-    for (int j = 0; j < k && !err; ++j) {
-      int c = T.seg_nodes[o0 + j];
-      while (parent[c] >= 0 && (segment[parent[c]] == g || !St.kept[parent[c]])) c = parent[c];
-      s_top[j] = c;
+    for (int j = 0; j < k; ++j) {
+      const int c = s_top[j];
       bool seen = false;
       for (int q = 0; q < nch; ++q) seen |= (s_tops[q] == c);
       if (!seen) s_tops[nch++] = c;
@@ -67,7 +95,7 @@ __global__ __launch_bounds__(256) void k_build_struct(Topo T, State St, int g, i
     }
     // slots chain by chain, top to bottom (segment nodes are in preorder)
     int ns = 0;
-    for (int c = 0; c < nch && !err; ++c) {
+    for (int c = 0; c < nch; ++c) {
       s_cslot0[c] = ns;
       for (int j = 0; j < k; ++j)
         if (s_top[j] == s_tops[c]) {
@@ -79,22 +107,39 @@ __global__ __launch_bounds__(256) void k_build_struct(Topo T, State St, int g, i
       s_head[c] = parent[s_tops[c]];
     }
     s_cslot0[nch] = ns;
-    if (ns != k) err = 1;
-    // outer chain: the chain whose bottom slot is the first segment node above the head
-    for (int c = 0; c < nch && !err; ++c) {
-      int u = s_head[c];
-      while (u >= 0 && segment[u] != g) u = parent[u];
-      s_outer[c] = -1;
-      if (u >= 0) {
-        int s = -1;
-        for (int q = 0; q < ns; ++q)
-          if (s_slotnode[q] == u) s = q;
-        if (s < 0) { err = 1; break; }
-        const int oc = s_slotchain[s];
-        if (s != s_cslot0[oc + 1] - 1 || oc >= c) { err = 1; break; }
-        s_outer[c] = oc;
-      }
+    if (ns != k) s_err = 1;
+    s_nch = nch;
+  }
+  __syncthreads();
+  // outer chain: the chain whose bottom slot is the deepest segment node
+  // above the head (a subtree test against every segment node)
+  if (!s_err && tid < s_nch) {
+    const int c = tid, hd = s_head[c];
+    const int ph = hd >= 0 ? T.pos[hd] : -1;
+    int best = -1;
+    for (int j = 0; j < k; ++j)
+      if (hd >= 0 && s_spos[j] <= ph && ph < s_spos[j] + s_ssize[j] && (best < 0 || s_spos[j] > s_spos[best]))
+        best = j;
+    s_outer[c] = -1;
+    if (best >= 0) {
+      const int u = T.seg_nodes[o0 + best];
+      int s = -1;
+      for (int q = 0; q < k; ++q)
+        if (s_slotnode[q] == u) s = q;
+      const int oc = s >= 0 ? s_slotchain[s] : -1;
+      if (s < 0 || s != s_cslot0[oc + 1] - 1 || oc >= c) atomicOr(&s_err, 1);
+      else s_outer[c] = oc;
     }
+  }
+  __syncthreads();
+  if (tid == 0) {
+    int err = s_err;
+    const int nch = s_nch, ns = k;
+    SegHdr H;
+    for (int q = 0; q < (int)(sizeof(SegHdr) / sizeof(int)); ++q) ((int*)&H)[q] = 0;
+    H.g = g;
+    H.k = k;
+    H.S = S;
     // table layout
     int o = 0;
     H.o_chain = o; o += nch * kChainInts;

@@ -211,92 +211,6 @@ __global__ void k_from_vhat(int n, int S, const uint8_t* __restrict__ phase, con
   if (pr && (m < vmin || m > vmax)) atomicOr(status, 32);
 }
 
-// ---------------------------------------------------------------- scoring --
-// One lane scores one mask over the block's snapshot group: e = max error
-// over the affected nodes, slack = min band slack over their kept node-phases.
-// A block is 4 waves (256 masks) sharing the snapshot's LDS stage: the pair
-// table P, the slot targets and the chain heads.  The last block of a
-// 256-mask range to finish (ticket counter) folds the snapshot groups into
-// the final per-mask score and writes one tile record per wave.
-__global__ __launch_bounds__(kScoreThreads) void k_score_fp64(
-    const SegHdr* __restrict__ hdrs, int g, const int* __restrict__ tab, const double2* __restrict__ P,
-    const TargetRec* __restrict__ srec, const double2* __restrict__ headV,
-    const TargetRec* __restrict__ zrec, const double* __restrict__ econst, int snaps_per_group, int SG,
-    SelParams sp, MaskScore* __restrict__ part, MaskScore* __restrict__ fin, TileRec* __restrict__ tiles,
-    int* __restrict__ tickets, const int* __restrict__ gate) {
-  __shared__ double2 Ps[kMaxPairs * 3];
-  __shared__ TargetRec Ts[kMaxK * 3];
-  __shared__ double2 Hv[kMaxK * 3];
-  __shared__ int ticket;
-  const SegHdr H = hdrs[g];
-  if (!H.valid || (gate && *gate == 0)) return;
-  const int tid = threadIdx.x;
-  const uint32_t m = blockIdx.x * kScoreThreads + tid;
-  const int sg = blockIdx.y;
-  const int l0 = sg * snaps_per_group;
-  const int l1 = min(H.S, l0 + snaps_per_group);
-  const int* chains = tab + H.o_chain;
-  const int* slots = tab + H.o_slot;
-  const int* nest = tab + H.o_nest;
-  double e = 0.0, qmin = INFINITY, qmax = -INFINITY;
-  for (int l = l0; l < l1; ++l) {
-    const double2* Pl = P + (size_t)l * H.npairs * 3;
-    for (int q = tid; q < H.npairs * 3; q += kScoreThreads) Ps[q] = Pl[q];
-    const TargetRec* Sl = srec + (size_t)l * H.nslots * 3;
-    for (int q = tid; q < H.nslots * 3; q += kScoreThreads) Ts[q] = Sl[q];
-    const double2* Hl = headV + (size_t)l * H.nchains * 3;
-    for (int q = tid; q < H.nchains * 3; q += kScoreThreads) Hv[q] = Hl[q];
-    __syncthreads();
-    double el = econst[l];
-    score_snapshot(H, chains, slots, nest, Ps, Ts, Hv, zrec + (size_t)l * H.nz, m, el, qmin, qmax);
-    e = fmax(e, el);
-    __syncthreads();
-  }
-  const uint32_t nmask = 1u << H.k;
-  const bool valid = m < nmask;
-  if (valid) {
-    MaskScore r;
-    r.e = e;
-    r.slack = band_slack(qmin, qmax, sp.vmin, sp.vmax);
-    part[(size_t)sg * nmask + m] = r;
-  }
-  __threadfence();
-  if (tid == 0) ticket = atomicAdd(&tickets[blockIdx.x], 1);
-  __syncthreads();
-  if (ticket != SG - 1) return;
-  // last block of this mask range: combine the snapshot groups
-  MaskScore r;
-  r.e = 0.0;
-  r.slack = INFINITY;
-  if (valid) {
-    for (int q = 0; q < SG; ++q) {
-      const volatile MaskScore* x = part + (size_t)q * nmask + m;
-      r.e = fmax(r.e, x->e);
-      r.slack = fmin(r.slack, x->slack);
-    }
-    fin[m] = r;
-  }
-  const int pc = __popc(m);
-  const bool feas = valid && feasible(r, sp.e_bar);
-  int best = feas ? pc : -1;
-  int nearl = (valid && near_boundary(r, sp.e_bar, sp.amb)) ? pc : -1;
-  for (int o = 32; o > 0; o >>= 1) {
-    best = max(best, __shfl_xor(best, o, 64));
-    nearl = max(nearl, __shfl_xor(nearl, o, 64));
-  }
-  double em = (feas && pc == best) ? r.e : INFINITY;
-  for (int o = 32; o > 0; o >>= 1) em = fmin(em, __shfl_xor(em, o, 64));
-  const uint32_t tile = m / kScoreBlock;
-  if ((tid & 63) == 0 && tile * kScoreBlock < nmask) {
-    TileRec t;
-    t.best = best;
-    t.near = nearl;
-    t.emin = em;
-    tiles[tile] = t;
-  }
-  if (tid == 0) tickets[blockIdx.x] = 0;  // ready for the next launch
-}
-
 // ----------------------------------------------------------------- argmin --
 // Lexicographic selection over the tile records: most reduced nodes among
 // feasible masks, then the smallest error, masks within tie_tol of that error
@@ -402,35 +316,31 @@ __global__ __launch_bounds__(64) void k_apply(const SegHdr* __restrict__ hdrs, i
   const uint32_t m = decs[g].mask;
   const int* chains = tab + H.o_chain;
   const int* slots = tab + H.o_slot;
-  if (threadIdx.x == 0) {
+  if (threadIdx.x < 3) {  // phases are independent: one thread each
+    const int p = threadIdx.x;
     const double2* Pl = P + (size_t)l * H.npairs * 3;
     const TargetRec* srec_l = srec + (size_t)l * H.nslots * 3;
     for (int c = 0; c < H.nchains; ++c) {
       const int* cr = chains + c * kChainInts;
       const int outer = cr[C_OUTER];
-      double2 S[3];
-      for (int p = 0; p < 3; ++p) S[p] = outer >= 0 ? Bs[outer * 3 + p] : make_double2(0.0, 0.0);
+      double2 S = outer >= 0 ? Bs[outer * 3 + p] : make_double2(0.0, 0.0);
       int sidx = 0, supnode = cr[C_HEAD];
       const int ns = cr[C_NSLOT], s0 = cr[C_SLOT0];
       for (int r = 0; r < ns; ++r) {
         const int* sr = slots + (s0 + r) * kSlotInts;
         const int node = sr[SL_NODE];
         if ((m >> sr[SL_BIT]) & 1u) {
-          const double2* pp = Pl + (sr[SL_PAIRBASE] + sidx) * 3;
-          for (int p = 0; p < 3; ++p) {
-            S[p] = cadd(S[p], pp[p]);
-            const size_t a = ((size_t)l * n + supnode) * 3 + p, b = ((size_t)l * n + node) * 3 + p;
-            A[a] = cadd(A[a], A[b]);
-            A[b] = make_double2(0.0, 0.0);
-          }
+          S = cadd(S, Pl[(sr[SL_PAIRBASE] + sidx) * 3 + p]);
+          const size_t a = ((size_t)l * n + supnode) * 3 + p, b = ((size_t)l * n + node) * 3 + p;
+          A[a] = cadd(A[a], A[b]);
+          A[b] = make_double2(0.0, 0.0);
         } else {
-          for (int p = 0; p < 3; ++p)
-            if (sr[SL_PHASE] >> p & 1) Vcur[((size_t)l * n + node) * 3 + p] = cadd(srec_l[(s0 + r) * 3 + p].W, S[p]);
+          if (sr[SL_PHASE] >> p & 1) Vcur[((size_t)l * n + node) * 3 + p] = cadd(srec_l[(s0 + r) * 3 + p].W, S);
           sidx = r + 1;
           supnode = node;
         }
       }
-      for (int p = 0; p < 3; ++p) Bs[c * 3 + p] = S[p];
+      Bs[c * 3 + p] = S;
     }
   }
   __syncthreads();
@@ -457,8 +367,13 @@ __global__ __launch_bounds__(64) void k_apply(const SegHdr* __restrict__ hdrs, i
     int r = 0;
     while (r + 1 < H.nrange && rg[3 * (r + 1) + 2] <= q) ++r;
     const int i = T.pre[rg[3 * r] + (q - rg[3 * r + 2])];
+    // up through reduced nodes; a reduced node's recorded super (before or
+    // after this update) is an ancestor with only reduced nodes in between
     int v = i;
-    while (!St.kept[v]) v = T.parent[v];
+    while (!St.kept[v]) {
+      const int s = St.sup[v];
+      v = (s >= 0 && s != v) ? s : T.parent[v];
+    }
     St.sup[i] = v;
   }
 }

@@ -1,0 +1,295 @@
+// Candidate scoring kernels: every mask of a segment (FP64, and the FP32
+// difference-form screen of the mixed-precision search) and FP64 rescoring of
+// a mask list.  Built with NaNs excluded (no input or intermediate here is
+// NaN), which lets max/min compile to single instructions.
+#include <hip/hip_runtime.h>
+#include <math.h>
+#include <stdint.h>
+
+#include "okr_device.h"
+#include "okr_internal.h"
+
+namespace okr {
+
+// ---------------------------------------------------------------- scoring --
+// One lane scores one mask over the block's snapshot group: e = max error
+// over the affected nodes, slack = min band slack over their kept node-phases.
+// A block is 4 waves (256 masks) sharing the snapshot's LDS stage: the pair
+// table P, the slot targets and the chain heads.  The last block of a
+// 256-mask range to finish (ticket counter) folds the snapshot groups into
+// the final per-mask score and writes one tile record per wave.
+__global__ __launch_bounds__(kScoreThreads) void k_score_fp64(
+    const SegHdr* __restrict__ hdrs, int g, const int* __restrict__ tab, const double2* __restrict__ P,
+    const TargetRec* __restrict__ srec, const double2* __restrict__ headV,
+    const TargetRec* __restrict__ zrec, const double* __restrict__ econst, int snaps_per_group, int SG,
+    SelParams sp, MaskScore* __restrict__ part, MaskScore* __restrict__ fin, TileRec* __restrict__ tiles,
+    int* __restrict__ tickets, const int* __restrict__ gate) {
+  __shared__ double2 Ps[kMaxPairs * 3];
+  __shared__ TargetRec Ts[kMaxK * 3];
+  __shared__ double2 Hv[kMaxK * 3];
+  __shared__ int ticket;
+  const SegHdr H = hdrs[g];
+  if (!H.valid || (gate && *gate == 0)) return;
+  const int tid = threadIdx.x;
+  const uint32_t m = blockIdx.x * kScoreThreads + tid;
+  const int sg = blockIdx.y;
+  const int l0 = sg * snaps_per_group;
+  const int l1 = min(H.S, l0 + snaps_per_group);
+  const int* chains = tab + H.o_chain;
+  const int* slots = tab + H.o_slot;
+  const int* nest = tab + H.o_nest;
+  double e = 0.0, qmin = INFINITY, qmax = -INFINITY;
+  for (int l = l0; l < l1; ++l) {
+    const double2* Pl = P + (size_t)l * H.npairs * 3;
+    for (int q = tid; q < H.npairs * 3; q += kScoreThreads) Ps[q] = Pl[q];
+    const TargetRec* Sl = srec + (size_t)l * H.nslots * 3;
+    for (int q = tid; q < H.nslots * 3; q += kScoreThreads) Ts[q] = Sl[q];
+    const double2* Hl = headV + (size_t)l * H.nchains * 3;
+    for (int q = tid; q < H.nchains * 3; q += kScoreThreads) Hv[q] = Hl[q];
+    __syncthreads();
+    double el = econst[l];
+    score_snapshot(H, chains, slots, nest, Ps, Ts, Hv, zrec + (size_t)l * H.nz, m, el, qmin, qmax);
+    e = fmax(e, el);
+    __syncthreads();
+  }
+  const uint32_t nmask = 1u << H.k;
+  const bool valid = m < nmask;
+  if (valid) {
+    MaskScore r;
+    r.e = e;
+    r.slack = band_slack(qmin, qmax, sp.vmin, sp.vmax);
+    part[(size_t)sg * nmask + m] = r;
+  }
+  __threadfence();
+  if (tid == 0) ticket = atomicAdd(&tickets[blockIdx.x], 1);
+  __syncthreads();
+  if (ticket != SG - 1) return;
+  // last block of this mask range: combine the snapshot groups
+  MaskScore r;
+  r.e = 0.0;
+  r.slack = INFINITY;
+  if (valid) {
+    for (int q = 0; q < SG; ++q) {
+      const volatile MaskScore* x = part + (size_t)q * nmask + m;
+      r.e = fmax(r.e, x->e);
+      r.slack = fmin(r.slack, x->slack);
+    }
+    fin[m] = r;
+  }
+  const int pc = __popc(m);
+  const bool feas = valid && feasible(r, sp.e_bar);
+  int best = feas ? pc : -1;
+  int nearl = (valid && near_boundary(r, sp.e_bar, sp.amb)) ? pc : -1;
+  for (int o = 32; o > 0; o >>= 1) {
+    best = max(best, __shfl_xor(best, o, 64));
+    nearl = max(nearl, __shfl_xor(nearl, o, 64));
+  }
+  double em = (feas && pc == best) ? r.e : INFINITY;
+  for (int o = 32; o > 0; o >>= 1) em = fmin(em, __shfl_xor(em, o, 64));
+  const uint32_t tile = m / kScoreBlock;
+  if ((tid & 63) == 0 && tile * kScoreBlock < nmask) {
+    TileRec t;
+    t.best = best;
+    t.near = nearl;
+    t.emin = em;
+    tiles[tile] = t;
+  }
+  if (tid == 0) tickets[blockIdx.x] = 0;  // ready for the next launch
+}
+
+// FP64 scores of the masks in `list` (all snapshots), with the arithmetic of
+// the FP64 scoring kernel.
+__global__ __launch_bounds__(kScoreBlock) void k_refine_fp64(
+    const SegHdr* __restrict__ hdrs, int g, const int* __restrict__ tab, const double2* __restrict__ P,
+    const TargetRec* __restrict__ srec, const double2* __restrict__ headV, const TargetRec* __restrict__ zrec,
+    const double* __restrict__ econst, SelParams sp, const uint32_t* __restrict__ list,
+    const int* __restrict__ count, MaskScore* __restrict__ out) {
+  __shared__ double2 Ps[kMaxPairs * 3];
+  __shared__ TargetRec Ts[kMaxK * 3];
+  __shared__ double2 Hv[kMaxK * 3];
+  const SegHdr H = hdrs[g];
+  if (!H.valid) return;
+  const int cnt = *count;
+  const int* chains = tab + H.o_chain;
+  const int* slots = tab + H.o_slot;
+  const int* nest = tab + H.o_nest;
+  for (int base = blockIdx.x * kScoreBlock; base < cnt; base += gridDim.x * kScoreBlock) {
+    const int idx = base + threadIdx.x;
+    const uint32_t m = idx < cnt ? list[idx] : 0u;
+    double e = 0.0, qmin = INFINITY, qmax = -INFINITY;
+    for (int l = 0; l < H.S; ++l) {
+      const double2* Pl = P + (size_t)l * H.npairs * 3;
+      for (int q = threadIdx.x; q < H.npairs * 3; q += kScoreBlock) Ps[q] = Pl[q];
+      const TargetRec* Sl = srec + (size_t)l * H.nslots * 3;
+      for (int q = threadIdx.x; q < H.nslots * 3; q += kScoreBlock) Ts[q] = Sl[q];
+      const double2* Hl = headV + (size_t)l * H.nchains * 3;
+      for (int q = threadIdx.x; q < H.nchains * 3; q += kScoreBlock) Hv[q] = Hl[q];
+      __syncthreads();
+      double el = econst[l];
+      score_snapshot(H, chains, slots, nest, Ps, Ts, Hv, zrec + (size_t)l * H.nz, m, el, qmin, qmax);
+      e = fmax(e, el);
+      __syncthreads();
+    }
+    if (idx < cnt) {
+      MaskScore r;
+      r.e = e;
+      r.slack = band_slack(qmin, qmax, sp.vmin, sp.vmax);
+      out[idx] = r;
+    }
+  }
+}
+
+// d = |W + S| - |W| in difference form (w = |W| given).
+__device__ __forceinline__ float diff32(float2 W, float w, float2 S) {
+  const float vx = W.x + S.x, vy = W.y + S.y;
+  const float m = __builtin_sqrtf(vx * vx + vy * vy);
+  const float num = 2.f * (W.x * S.x + W.y * S.y) + (S.x * S.x + S.y * S.y);
+  return num / (m + w);
+}
+
+template <bool ERR>
+__device__ __forceinline__ void walk32(const int* __restrict__ cr, const int* __restrict__ slots, const Pair32* Ps,
+                                       const Rec32* Ss, const Head32* Hs, int c, uint32_t m, float2& B0, float2& B1,
+                                       float2& B2, float& el, float& slack) {
+  float2 S0 = B0, S1 = B1, S2 = B2;
+  float d0 = 0.f, d1 = 0.f, d2 = 0.f;  // d of the current super on each phase
+  if (ERR) {
+    const int hph = cr[C_PHASE];
+    const Head32* hv = Hs + c * 3;
+    if (hph & 1) d0 = diff32(hv[0].W, hv[0].w, B0);
+    if (hph & 2) d1 = diff32(hv[1].W, hv[1].w, B1);
+    if (hph & 4) d2 = diff32(hv[2].W, hv[2].w, B2);
+  }
+  const int ns = cr[C_NSLOT], s0 = cr[C_SLOT0];
+  int sidx = 0;
+  for (int r = 0; r < ns; ++r) {
+    const int* sr = slots + (s0 + r) * kSlotInts;
+    const int bit = sr[SL_BIT], pb = sr[SL_PAIRBASE], ph = sr[SL_PHASE];
+    const bool red = (m >> bit) & 1u;
+    const float rf = red ? 1.f : 0.f;
+    const Pair32* pp = Ps + (pb + sidx) * 3;
+    const Rec32* tr = Ss + (s0 + r) * 3;
+#define OKR_SLOT32(P_, S_, D_)                                                  \
+    if (ph & (1 << P_)) {                                                       \
+      const Pair32 q = pp[P_];                                                  \
+      S_.x = fmaf(rf, q.P.x, S_.x);                                             \
+      S_.y = fmaf(rf, q.P.y, S_.y);                                             \
+      if (ERR) {                                                                \
+        const Rec32 t = tr[P_];                                                 \
+        const float d = diff32(t.W, t.w, S_);                                   \
+        const float ek = fmaxf(t.a + d, t.b - d);                               \
+        const float er = fmaxf(q.a + D_, q.b - D_);                             \
+        el = fmaxf(el, red ? er : ek);                                          \
+        slack = red ? slack : fminf(slack, fminf(t.bmin + d, t.bmax - d));      \
+        D_ = red ? D_ : d;                                                      \
+      }                                                                         \
+    }
+    OKR_SLOT32(0, S0, d0)
+    OKR_SLOT32(1, S1, d1)
+    OKR_SLOT32(2, S2, d2)
+#undef OKR_SLOT32
+    sidx = red ? sidx : r + 1;
+  }
+  B0 = S0; B1 = S1; B2 = S2;
+}
+
+__global__ __launch_bounds__(kScoreThreads) void k_score_fp32(
+    const SegHdr* __restrict__ hdrs, int g, const int* __restrict__ tab, const Pair32* __restrict__ P32,
+    const Rec32* __restrict__ S32, const Head32* __restrict__ H32, const Rec32* __restrict__ Z32,
+    const double* __restrict__ econst, int snaps_per_group, int SG, SelParams sp, MaskScore32* __restrict__ part,
+    MaskScore32* __restrict__ fin, TileRec32* __restrict__ tiles, int* __restrict__ tickets) {
+  __shared__ Pair32 Ps[kMaxPairs * 3];
+  __shared__ Rec32 Ts[kMaxK * 3];
+  __shared__ Head32 Hv[kMaxK * 3];
+  __shared__ int ticket;
+  const SegHdr H = hdrs[g];
+  if (!H.valid) return;
+  const int tid = threadIdx.x;
+  const uint32_t m = blockIdx.x * kScoreThreads + tid;
+  const int sg = blockIdx.y;
+  const int l0 = sg * snaps_per_group;
+  const int l1 = min(H.S, l0 + snaps_per_group);
+  const int* chains = tab + H.o_chain;
+  const int* slots = tab + H.o_slot;
+  const int* nest = tab + H.o_nest;
+  float e = 0.f, slack = INFINITY;
+  for (int l = l0; l < l1; ++l) {
+    const Pair32* Pl = P32 + (size_t)l * H.npairs * 3;
+    for (int q = tid; q < H.npairs * 3; q += kScoreThreads) Ps[q] = Pl[q];
+    const Rec32* Sl = S32 + (size_t)l * H.nslots * 3;
+    for (int q = tid; q < H.nslots * 3; q += kScoreThreads) Ts[q] = Sl[q];
+    const Head32* Hl = H32 + (size_t)l * H.nchains * 3;
+    for (int q = tid; q < H.nchains * 3; q += kScoreThreads) Hv[q] = Hl[q];
+    const Rec32* Zl = Z32 + (size_t)l * H.nz;
+    __syncthreads();
+    float el = (float)econst[l];
+    for (int c = 0; c < H.nchains; ++c) {
+      const int* cr = chains + c * kChainInts;
+      float2 B0 = make_float2(0.f, 0.f), B1 = B0, B2 = B0;
+      const int nl = cr[C_NEST_LEN], no = cr[C_NEST_OFF];
+      for (int q = 0; q + 1 < nl; ++q) {
+        const int oc = nest[no + q];
+        walk32<false>(chains + oc * kChainInts, slots, Ps, Ts, Hv, oc, m, B0, B1, B2, el, slack);
+      }
+      walk32<true>(cr, slots, Ps, Ts, Hv, c, m, B0, B1, B2, el, slack);
+#define OKR_ZONE32(P_, B_)                                                       \
+      for (int q = cr[C_ZOFF0 + P_], qe = q + cr[C_ZCNT0 + P_]; q < qe; ++q) { \
+        const Rec32 t = Zl[q];                                                   \
+        const float d = diff32(t.W, t.w, B_);                                    \
+        el = fmaxf(el, fmaxf(t.a + d, t.b - d));                                 \
+        slack = fminf(slack, fminf(t.bmin + d, t.bmax - d));                     \
+      }
+      OKR_ZONE32(0, B0)
+      OKR_ZONE32(1, B1)
+      OKR_ZONE32(2, B2)
+#undef OKR_ZONE32
+    }
+    e = fmaxf(e, el);
+    __syncthreads();
+  }
+  const uint32_t nmask = 1u << H.k;
+  const bool valid = m < nmask;
+  if (valid) {
+    MaskScore32 r;
+    r.e = e;
+    r.slack = slack;
+    part[(size_t)sg * nmask + m] = r;
+  }
+  __threadfence();
+  if (tid == 0) ticket = atomicAdd(&tickets[blockIdx.x], 1);
+  __syncthreads();
+  if (ticket != SG - 1) return;
+  MaskScore32 r;
+  r.e = 0.f;
+  r.slack = INFINITY;
+  if (valid) {
+    for (int q = 0; q < SG; ++q) {
+      const volatile MaskScore32* x = part + (size_t)q * nmask + m;
+      r.e = fmaxf(r.e, x->e);
+      r.slack = fminf(r.slack, x->slack);
+    }
+    fin[m] = r;
+  }
+  const double dd = sp.delta + sp.amb;
+  const bool sure = valid && (double)r.e <= sp.e_bar - dd && (double)r.slack >= dd;
+  const bool poss = valid && (double)r.e <= sp.e_bar + dd && (double)r.slack >= -dd;
+  const int pc = __popc(m);
+  int a = sure ? pc : -1, b = poss ? pc : -1, c = (poss && !sure) ? pc : -1;
+  for (int o = 32; o > 0; o >>= 1) {
+    a = max(a, __shfl_xor(a, o, 64));
+    b = max(b, __shfl_xor(b, o, 64));
+    c = max(c, __shfl_xor(c, o, 64));
+  }
+  const uint32_t tile = m / kScoreBlock;
+  if ((tid & 63) == 0 && tile * kScoreBlock < nmask) {
+    TileRec32 t;
+    t.sure = a;
+    t.poss = b;
+    t.unc = c;
+    t.pad = 0;
+    tiles[tile] = t;
+  }
+  if (tid == 0) tickets[blockIdx.x] = 0;
+}
+
+}  // namespace okr
