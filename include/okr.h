@@ -224,6 +224,11 @@ int okr_surrogate_grad(const float *params, const float *X, const float *t, int3
 int okr_surrogate_forward(const float *params, const float *X, int64_t n, float *y, void *work,
                           size_t work_bytes, void *hip_stream);
 
+/* Self-test of the square root the FP64 scoring kernels use for voltage
+ * magnitudes: y[i] = sqrt(x[i]) for n DEVICE doubles.  Synchronous on
+ * hip_stream.  For tests of its rounding; not part of the search. */
+int okr_selftest_sqrt(const double *x, double *y, int32_t n, void *hip_stream);
+
 int okr_destroy(okr_handle *h);
 const char *okr_last_error(const okr_handle *h);
 

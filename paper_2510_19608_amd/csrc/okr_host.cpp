@@ -58,12 +58,14 @@ __global__ void k_mixed_final(const SegHdr*, int, SelParams, const int*, MixedSt
 __global__ void k_surr_tables(const SegHdr*, int, const int*, int, const double2*, const double2*, const double2*,
                               const TargetRec*, float*, float*, SurrSlot*);
 __global__ void k_surr_features(const SegHdr*, int, const int*, const float*, const float*, const SurrSlot*,
-                                const double*, int, float*, __bf16*);
+                                const double*, const uint32_t*, int, int, float*, __bf16*, const int*, int);
+__global__ void k_level_masks(int, int, int, int, uint32_t*);
+__global__ void k_surr_stage(const SegHdr*, int, const uint32_t*, int, int, int*);
 __global__ void k_surr_target(const SegHdr*, int, const MaskScore*, float*);
 template <int EPI>
 __global__ void k_gemm_nt(const __bf16*, int, const __bf16*, int, int, float*, int, const float*, float*, __bf16*,
-                          __bf16*, int, const float*, float*);
-__global__ void k_rowdot_finish(const float*, int, int, const float*, float*);
+                          __bf16*, int, const float*, float*, const int*, int);
+__global__ void k_rowdot_finish(const float*, int, int, const float*, float*, const int*, int);
 __global__ void k_batch_cast(const float*, int, __bf16*, __bf16*);
 __global__ void k_loss_dy(const float*, const float*, int, float*, float*);
 __global__ void k_dz2(const float*, const float*, const float*, int, __bf16*, __bf16*);
@@ -73,8 +75,10 @@ __global__ void k_colsums(const float*, const float*, const float*, const float*
 __global__ void k_copy_cols(const float*, int, float*, int, int);
 __global__ void k_adam(float*, const float*, float*, float*, int, float, float, float);
 __global__ void k_refresh_weights(const float*, __bf16*, __bf16*, __bf16*);
-__global__ void k_surr_keys(const SegHdr*, int, const float*, float, uint32_t*);
-__global__ void k_topk(const SegHdr*, int, const uint32_t*, int, const int*, uint32_t*, int*);
+__global__ void k_surr_keys(const SegHdr*, int, const float*, float, const uint32_t*, int, uint32_t*, const int*,
+                            int);
+__global__ void k_topk(const SegHdr*, int, const uint32_t*, const uint32_t*, int, int, const int*, uint32_t*, int*,
+                       const int*, int);
 __global__ void k_surr_decide(const SegHdr*, int, SelParams, const int*, const uint32_t*, const int*,
                               const MaskScore*, DevDecision*, int*);
 __global__ void k_zero_f32(float*, int);
@@ -107,7 +111,8 @@ struct Layout {
   // mixed precision
   size_t P32, S32, H32, Z32, part32, fin32, tiles32, listA, listB, scoreA, scoreB, counts, mstate;
   // surrogate: feature tables (always), ranking buffers (when planned with top_k)
-  size_t spz, szs, sss, sXb, sH1b, spart, sy, skeys, slist, sscore, scount, sgates, sW1b, sW2b, sW2tb;
+  size_t spz, szs, sss, sXb, sH1b, spart, sy, skeys, slist, sscore, scount, sgates, sW1b, sW2b, sW2tb, slevel,
+      sstage;
   size_t total;
 };
 
@@ -382,6 +387,8 @@ extern "C" int okr_plan(okr_handle* h, const okr_topology* topo, const okr_margi
     L.spart = take(sizeof(float) * (kSurrH / 32) * mp);
     L.sy = take(sizeof(float) * mp);
     L.skeys = take(sizeof(uint32_t) * mp);
+    L.slevel = take(sizeof(uint32_t) * mp);
+    L.sstage = take(sizeof(int) * std::max(nseg, 1));
     L.slist = take(sizeof(uint32_t) * std::max(h->topk, 1));
     L.sscore = take(sizeof(MaskScore) * std::max(h->topk, 1));
     L.scount = take(sizeof(int) * 4);
@@ -433,9 +440,9 @@ struct Ptrs {
   float *spz, *szs, *spart, *sy;
   SurrSlot* sss;
   __bf16 *sXb, *sH1b, *sW1b, *sW2b, *sW2tb;
-  uint32_t *skeys, *slist;
+  uint32_t *skeys, *slist, *slevel;
   MaskScore* sscore;
-  int *scount, *sgates;
+  int *scount, *sgates, *sstage;
 };
 
 Ptrs pointers(okr_handle* h, void* d_workspace) {
@@ -512,6 +519,8 @@ Ptrs pointers(okr_handle* h, void* d_workspace) {
   p.sscore = (MaskScore*)at(L.sscore);
   p.scount = (int*)at(L.scount);
   p.sgates = (int*)at(L.sgates);
+  p.slevel = (uint32_t*)at(L.slevel);
+  p.sstage = (int*)at(L.sstage);
   p.sW1b = (__bf16*)at(L.sW1b);
   p.sW2b = (__bf16*)at(L.sW2b);
   p.sW2tb = (__bf16*)at(L.sW2tb);
@@ -582,23 +591,60 @@ void enqueue_search(okr_handle* h, const Ptrs& p, const okr_yblocks* Y, const ok
                          (const double2*)p.A, (const TargetRec*)p.srec, p.spz, p.szs, p.sss);
     }
     if (surr) {
-      // rank every mask with the surrogate, rescore the top-k exactly
-      const int Mp = (int)std::max<uint32_t>(64u, nmask);
-      hipLaunchKernelGGL(k_surr_features, dim3((Mp + 255) / 256), dim3(256), 0, st, (const SegHdr*)p.hdrs, g,
-                         (const int*)p.tab, (const float*)p.spz, (const float*)p.szs, (const SurrSlot*)p.sss,
-                         (const double*)p.econst, Mp, (float*)nullptr, p.sXb);
-      hipLaunchKernelGGL(k_gemm_nt<1>, dim3(kSurrH / 64, Mp / 64), dim3(256), 0, st, (const __bf16*)p.sXb, kSurrF,
-                         (const __bf16*)p.sW1b, kSurrF, kSurrF, (float*)nullptr, kSurrH, mg->surrogate + kOffB1,
-                         (float*)nullptr, p.sH1b, (__bf16*)nullptr, Mp, (const float*)nullptr, (float*)nullptr);
-      hipLaunchKernelGGL(k_gemm_nt<2>, dim3(kSurrH / 64, Mp / 64), dim3(256), 0, st, (const __bf16*)p.sH1b, kSurrH,
-                         (const __bf16*)p.sW2b, kSurrH, kSurrH, (float*)nullptr, kSurrH, mg->surrogate + kOffB2,
-                         (float*)nullptr, (__bf16*)nullptr, (__bf16*)nullptr, Mp, mg->surrogate + kOffW3, p.spart);
-      hipLaunchKernelGGL(k_rowdot_finish, dim3((Mp + 255) / 256), dim3(256), 0, st, (const float*)p.spart,
-                         kSurrH / 32, Mp, mg->surrogate + kOffB3, p.sy);
-      hipLaunchKernelGGL(k_surr_keys, dim3((Mp + 255) / 256), dim3(256), 0, st, (const SegHdr*)p.hdrs, g,
-                         (const float*)p.sy, (float)std::log(mg->e_bar), p.skeys);
-      hipLaunchKernelGGL(k_topk, dim3(1), dim3(1024), 0, st, (const SegHdr*)p.hdrs, g, (const uint32_t*)p.skeys,
-                         mg->top_k, (const int*)p.status, p.slist, p.scount);
+      // Rank the masks with the surrogate and rescore the top-k exactly.
+      // Stage 1 ranks only the top levels (popcount >= L1, at least 4 top_k
+      // masks); when they hold top_k masks predicted feasible, those are the
+      // top_k of the full ranking (predicted-feasible masks rank by level
+      // first) and stage 2, the ranking of every mask, is skipped on device.
+      const int K = mg->top_k;
+      const float ln_ebar = (float)std::log(mg->e_bar);
+      int L1 = k;
+      uint64_t N1 = 1;
+      while (L1 > 0 && N1 < (uint64_t)4 * K) {
+        --L1;
+        uint64_t c = 1;
+        for (int q = 1; q <= L1; ++q) c = c * (uint64_t)(k - L1 + q) / (uint64_t)q;
+        N1 += c;
+      }
+      const bool staged = N1 < nmask;
+      int* stage = p.sstage + g;
+      auto rank = [&](const uint32_t* masks, int nrow, const int* flag, int skip_if) {
+        const int Mp = std::max(64, (nrow + 63) / 64 * 64);
+        hipLaunchKernelGGL(k_surr_features, dim3((Mp + 255) / 256), dim3(256), 0, st, (const SegHdr*)p.hdrs, g,
+                           (const int*)p.tab, (const float*)p.spz, (const float*)p.szs, (const SurrSlot*)p.sss,
+                           (const double*)p.econst, masks, nrow, Mp, (float*)nullptr, p.sXb, flag, skip_if);
+        hipLaunchKernelGGL(k_gemm_nt<1>, dim3(kSurrH / 64, Mp / 64), dim3(256), 0, st, (const __bf16*)p.sXb, kSurrF,
+                           (const __bf16*)p.sW1b, kSurrF, kSurrF, (float*)nullptr, kSurrH, mg->surrogate + kOffB1,
+                           (float*)nullptr, p.sH1b, (__bf16*)nullptr, Mp, (const float*)nullptr, (float*)nullptr,
+                           flag, skip_if);
+        hipLaunchKernelGGL(k_gemm_nt<2>, dim3(kSurrH / 64, Mp / 64), dim3(256), 0, st, (const __bf16*)p.sH1b, kSurrH,
+                           (const __bf16*)p.sW2b, kSurrH, kSurrH, (float*)nullptr, kSurrH, mg->surrogate + kOffB2,
+                           (float*)nullptr, (__bf16*)nullptr, (__bf16*)nullptr, Mp, mg->surrogate + kOffW3, p.spart,
+                           flag, skip_if);
+        hipLaunchKernelGGL(k_rowdot_finish, dim3((Mp + 255) / 256), dim3(256), 0, st, (const float*)p.spart,
+                           kSurrH / 32, Mp, mg->surrogate + kOffB3, p.sy, flag, skip_if);
+        hipLaunchKernelGGL(k_surr_keys, dim3((nrow + 255) / 256), dim3(256), 0, st, (const SegHdr*)p.hdrs, g,
+                           (const float*)p.sy, ln_ebar, masks, nrow, p.skeys, flag, skip_if);
+      };
+      if (staged) {
+        hipLaunchKernelGGL(k_level_masks, dim3(((int)N1 + 63) / 64 * 64 / 64), dim3(64), 0, st, k, L1, (int)N1,
+                           ((int)N1 + 63) / 64 * 64, p.slevel);
+        rank(p.slevel, (int)N1, (const int*)nullptr, 0);
+        hipLaunchKernelGGL(k_surr_stage, dim3(1), dim3(256), 0, st, (const SegHdr*)p.hdrs, g,
+                           (const uint32_t*)p.skeys, (int)N1, K, stage);
+        hipLaunchKernelGGL(k_topk, dim3(1), dim3(1024), 0, st, (const SegHdr*)p.hdrs, g, (const uint32_t*)p.skeys,
+                           (const uint32_t*)p.slevel, (int)N1, K, (const int*)p.status, p.slist, p.scount,
+                           (const int*)stage, 0);
+        rank((const uint32_t*)nullptr, (int)nmask, (const int*)stage, 1);
+        hipLaunchKernelGGL(k_topk, dim3(1), dim3(1024), 0, st, (const SegHdr*)p.hdrs, g, (const uint32_t*)p.skeys,
+                           (const uint32_t*)nullptr, (int)nmask, K, (const int*)p.status, p.slist, p.scount,
+                           (const int*)stage, 1);
+      } else {
+        rank((const uint32_t*)nullptr, (int)nmask, (const int*)nullptr, 0);
+        hipLaunchKernelGGL(k_topk, dim3(1), dim3(1024), 0, st, (const SegHdr*)p.hdrs, g, (const uint32_t*)p.skeys,
+                           (const uint32_t*)nullptr, (int)nmask, K, (const int*)p.status, p.slist, p.scount,
+                           (const int*)nullptr, 0);
+      }
       hipLaunchKernelGGL(k_refine_fp64, dim3(kRefineBlocks), dim3(kScoreBlock), 0, st, (const SegHdr*)p.hdrs, g,
                          (const int*)p.tab, (const double2*)p.P, (const TargetRec*)p.srec, (const double2*)p.headV,
                          (const TargetRec*)p.zrec, (const double*)p.econst, sp, (const uint32_t*)p.slist,
@@ -620,7 +666,8 @@ void enqueue_search(okr_handle* h, const Ptrs& p, const okr_yblocks* Y, const ok
       if (feat_out && !surr) {
         hipLaunchKernelGGL(k_surr_features, dim3((nmask + 255) / 256), dim3(256), 0, st, (const SegHdr*)p.hdrs, g,
                            (const int*)p.tab, (const float*)p.spz, (const float*)p.szs, (const SurrSlot*)p.sss,
-                           (const double*)p.econst, (int)nmask, feat_out + feat_off * kSurrF, (__bf16*)nullptr);
+                           (const double*)p.econst, (const uint32_t*)nullptr, (int)nmask, (int)nmask,
+                           feat_out + feat_off * kSurrF, (__bf16*)nullptr, (const int*)nullptr, 0);
         if (targ_out)
           hipLaunchKernelGGL(k_surr_target, dim3((nmask + 255) / 256), dim3(256), 0, st, (const SegHdr*)p.hdrs, g,
                              (const MaskScore*)p.fin, targ_out + feat_off);
@@ -935,12 +982,13 @@ void surr_forward(const SurrWork& w, const float* prm, const float* X, int B, bo
   hipLaunchKernelGGL(k_gemm_nt<1>, dim3(kSurrH / 64, B / 64), dim3(256), 0, st, (const __bf16*)w.Xb, kSurrF,
                      (const __bf16*)w.W1b, kSurrF, kSurrF, (float*)nullptr, kSurrH, prm + kOffB1,
                      train ? w.Z1 : (float*)nullptr, w.H1b, train ? w.H1t : (__bf16*)nullptr, B, (const float*)nullptr,
-                     (float*)nullptr);
+                     (float*)nullptr, (const int*)nullptr, 0);
   hipLaunchKernelGGL(k_gemm_nt<2>, dim3(kSurrH / 64, B / 64), dim3(256), 0, st, (const __bf16*)w.H1b, kSurrH,
                      (const __bf16*)w.W2b, kSurrH, kSurrH, (float*)nullptr, kSurrH, prm + kOffB2,
-                     train ? w.Z2 : (float*)nullptr, (__bf16*)nullptr, (__bf16*)nullptr, B, prm + kOffW3, w.part);
+                     train ? w.Z2 : (float*)nullptr, (__bf16*)nullptr, (__bf16*)nullptr, B, prm + kOffW3, w.part,
+                     (const int*)nullptr, 0);
   hipLaunchKernelGGL(k_rowdot_finish, dim3((B + 255) / 256), dim3(256), 0, st, (const float*)w.part, kSurrH / 32, B,
-                     prm + kOffB3, w.y);
+                     prm + kOffB3, w.y, (const int*)nullptr, 0);
 }
 
 // Loss gradient of one batch into w.grads; the batch loss is added to *loss.
@@ -951,17 +999,20 @@ void surr_backward(const SurrWork& w, const float* prm, const float* t, int B, f
   // dW2 = dZ2^T H1
   hipLaunchKernelGGL(k_gemm_nt<0>, dim3(kSurrH / 64, kSurrH / 64), dim3(256), 0, st, (const __bf16*)w.dZ2t, B,
                      (const __bf16*)w.H1t, B, B, w.grads + kOffW2, kSurrH, (const float*)nullptr, (float*)nullptr,
-                     (__bf16*)nullptr, (__bf16*)nullptr, kSurrH, (const float*)nullptr, (float*)nullptr);
+                     (__bf16*)nullptr, (__bf16*)nullptr, kSurrH, (const float*)nullptr, (float*)nullptr,
+                     (const int*)nullptr, 0);
   // dH1 = dZ2 W2
   hipLaunchKernelGGL(k_gemm_nt<0>, dim3(kSurrH / 64, B / 64), dim3(256), 0, st, (const __bf16*)w.dZ2b, kSurrH,
                      (const __bf16*)w.W2tb, kSurrH, kSurrH, w.dH1, kSurrH, (const float*)nullptr, (float*)nullptr,
-                     (__bf16*)nullptr, (__bf16*)nullptr, B, (const float*)nullptr, (float*)nullptr);
+                     (__bf16*)nullptr, (__bf16*)nullptr, B, (const float*)nullptr, (float*)nullptr,
+                     (const int*)nullptr, 0);
   hipLaunchKernelGGL(k_dz1, dim3((B * kSurrH + 255) / 256), dim3(256), 0, st, (const float*)w.dH1, (const float*)w.Z1,
                      B, w.dZ1t);
   // dW1 = dZ1^T X (X^T padded to 64 rows)
   hipLaunchKernelGGL(k_gemm_nt<0>, dim3(1, kSurrH / 64), dim3(256), 0, st, (const __bf16*)w.dZ1t, B,
                      (const __bf16*)w.Xt, B, B, w.gW1full, 64, (const float*)nullptr, (float*)nullptr,
-                     (__bf16*)nullptr, (__bf16*)nullptr, kSurrH, (const float*)nullptr, (float*)nullptr);
+                     (__bf16*)nullptr, (__bf16*)nullptr, kSurrH, (const float*)nullptr, (float*)nullptr,
+                     (const int*)nullptr, 0);
   hipLaunchKernelGGL(k_copy_cols, dim3((kSurrH * kSurrF + 255) / 256), dim3(256), 0, st, (const float*)w.gW1full, 64,
                      w.grads + kOffW1, kSurrH, kSurrF);
   hipLaunchKernelGGL(k_colsums, dim3((kSurrH + 1 + 255) / 256), dim3(256), 0, st, (const float*)w.Z1,

@@ -69,15 +69,17 @@ __global__ void k_surr_tables(const SegHdr* __restrict__ hdrs, int g, const int*
 // run lengths, depth), scaled to O(1).  Rows m >= 2^k are zero padding.
 __global__ void k_surr_features(const SegHdr* __restrict__ hdrs, int g, const int* __restrict__ tab,
                                 const float* __restrict__ pz, const float* __restrict__ zs,
-                                const SurrSlot* __restrict__ ss, const double* __restrict__ econst, int Mp,
-                                float* __restrict__ Xf, __bf16* __restrict__ Xb) {
+                                const SurrSlot* __restrict__ ss, const double* __restrict__ econst,
+                                const uint32_t* __restrict__ masks, int n, int Mp, float* __restrict__ Xf,
+                                __bf16* __restrict__ Xb, const int* __restrict__ flag, int skip_if) {
   const SegHdr H = hdrs[g];
-  if (!H.valid) return;
-  const uint32_t m = blockIdx.x * blockDim.x + threadIdx.x;
-  if (m >= (uint32_t)Mp) return;
+  if (!H.valid || (flag && *flag == skip_if)) return;
+  const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= (uint32_t)Mp) return;
+  const uint32_t m = (masks && i < (uint32_t)n) ? masks[i] : i;
   float f[kSurrF];
   for (int q = 0; q < kSurrF; ++q) f[q] = 0.f;
-  if (m < (1u << H.k)) {
+  if (i < (uint32_t)n && m < (1u << H.k)) {
     const int* chains = tab + H.o_chain;
     const int* slots = tab + H.o_slot;
     float sum_pz = 0.f, max_pz = 0.f, sum_z = 0.f, sum_la = 0.f, max_sp = 0.f, sum_pos = 0.f;
@@ -131,9 +133,44 @@ __global__ void k_surr_features(const SegHdr* __restrict__ hdrs, int g, const in
     f[15] = k / 24.f;
   }
   if (Xf)
-    for (int q = 0; q < kSurrF; ++q) Xf[(size_t)m * kSurrF + q] = f[q];
+    for (int q = 0; q < kSurrF; ++q) Xf[(size_t)i * kSurrF + q] = f[q];
   if (Xb)
-    for (int q = 0; q < kSurrF; ++q) Xb[(size_t)m * kSurrF + q] = (__bf16)f[q];
+    for (int q = 0; q < kSurrF; ++q) Xb[(size_t)i * kSurrF + q] = (__bf16)f[q];
+}
+
+// Masks of popcount >= L1 over k bits, level by level from the top, each
+// level in colexicographic order (combinatorial number system); rows
+// [N1, M1) are padding.
+__device__ __forceinline__ uint32_t binom(int n, int r) {
+  if (r < 0 || r > n) return 0u;
+  uint64_t c = 1;
+  for (int q = 1; q <= r; ++q) c = c * (uint64_t)(n - r + q) / (uint64_t)q;
+  return (uint32_t)c;
+}
+
+__global__ void k_level_masks(int k, int L1, int N1, int M1, uint32_t* __restrict__ masks) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= M1) return;
+  if (i >= N1) {
+    masks[i] = 0u;
+    return;
+  }
+  int j = k;
+  uint32_t r = (uint32_t)i;
+  while (j > L1 && r >= binom(k, j)) {
+    r -= binom(k, j);
+    --j;
+  }
+  uint32_t m = 0u;
+  for (int pos = k - 1; pos >= 0 && j > 0; --pos) {
+    const uint32_t c = binom(pos, j);
+    if (c <= r) {
+      m |= 1u << pos;
+      r -= c;
+      --j;
+    }
+  }
+  masks[i] = m;
 }
 
 // Training target of every mask from the FP64 scores: y = ln(e + 1e-12).
@@ -169,8 +206,10 @@ __global__ __launch_bounds__(256) void k_gemm_nt(const __bf16* __restrict__ A, i
                                                  int ldb, int K, float* __restrict__ C, int ldc,
                                                  const float* __restrict__ bias, float* __restrict__ Z,
                                                  __bf16* __restrict__ Hb, __bf16* __restrict__ Ht, int M,
-                                                 const float* __restrict__ w, float* __restrict__ part) {
+                                                 const float* __restrict__ w, float* __restrict__ part,
+                                                 const int* __restrict__ flag, int skip_if) {
   __shared__ __attribute__((aligned(16))) __bf16 As[64][40];
+  if (flag && *flag == skip_if) return;
   __shared__ __attribute__((aligned(16))) __bf16 Bs[64][40];
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int wm = wave >> 1, wn = wave & 1;
@@ -220,7 +259,7 @@ __global__ __launch_bounds__(256) void k_gemm_nt(const __bf16* __restrict__ A, i
 
 #define OKR_GEMM_INST(E)                                                                                       \
   template __global__ void k_gemm_nt<E>(const __bf16*, int, const __bf16*, int, int, float*, int, const float*, \
-                                        float*, __bf16*, __bf16*, int, const float*, float*);
+                                        float*, __bf16*, __bf16*, int, const float*, float*, const int*, int);
 OKR_GEMM_INST(EPI_STORE)
 OKR_GEMM_INST(EPI_BIAS_GELU)
 OKR_GEMM_INST(EPI_BIAS_GELU_DOT)
@@ -228,9 +267,9 @@ OKR_GEMM_INST(EPI_BIAS_GELU_DOT)
 
 // y[m] = b3 + sum over the column blocks' partial dots, in a fixed order.
 __global__ void k_rowdot_finish(const float* __restrict__ part, int nblk, int M, const float* __restrict__ b3,
-                                float* __restrict__ y) {
+                                float* __restrict__ y, const int* __restrict__ flag, int skip_if) {
   const int m = blockIdx.x * blockDim.x + threadIdx.x;
-  if (m >= M) return;
+  if (m >= M || (flag && *flag == skip_if)) return;
   float s = b3[0];
   for (int j = 0; j < nblk; ++j) s += part[(size_t)j * M + m];
   y[m] = s;
@@ -348,40 +387,64 @@ __device__ __forceinline__ uint32_t ordered(float y) {
 // Rank key of every mask: predicted feasible first, then most reduced, then
 // smallest predicted error (26-bit monotone quantisation), ties by mask.
 __global__ void k_surr_keys(const SegHdr* __restrict__ hdrs, int g, const float* __restrict__ y, float ln_ebar,
-                            uint32_t* __restrict__ keys) {
+                            const uint32_t* __restrict__ masks, int n, uint32_t* __restrict__ keys,
+                            const int* __restrict__ flag, int skip_if) {
   const SegHdr H = hdrs[g];
-  const uint32_t m = blockIdx.x * blockDim.x + threadIdx.x;
-  if (!H.valid || m >= (1u << H.k)) return;
-  const uint32_t pf = y[m] <= ln_ebar ? 0u : 1u;
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (!H.valid || i >= n || (flag && *flag == skip_if)) return;
+  const uint32_t m = masks ? masks[i] : (uint32_t)i;
+  const uint32_t pf = y[i] <= ln_ebar ? 0u : 1u;
   const uint32_t lvl = (uint32_t)(H.k - __popc(m)) & 31u;
-  keys[m] = (pf << 31) | (lvl << 26) | (ordered(y[m]) >> 6);
+  keys[i] = (pf << 31) | (lvl << 26) | (ordered(y[i]) >> 6);
 }
 
-// The K smallest keys (ties by mask index) in mask order: radix select of the
-// K-th key, then an ordered compaction.  One block.
+// Whether the first ranking stage (the top levels) holds at least K masks
+// predicted feasible: then the K best keys overall are among them, since
+// predicted-feasible masks rank by level first.
+__global__ __launch_bounds__(256) void k_surr_stage(const SegHdr* __restrict__ hdrs, int g,
+                                                    const uint32_t* __restrict__ keys, int n, int K,
+                                                    int* __restrict__ flag) {
+  __shared__ int shi[4];
+  const SegHdr H = hdrs[g];
+  int c = 0;
+  if (H.valid)
+    for (int i = threadIdx.x; i < n; i += blockDim.x) c += (keys[i] >> 31) == 0u;
+  c = block_reduce(c, [](int a, int b) { return a + b; }, shi);
+  if (threadIdx.x == 0) *flag = (H.valid && c >= K) ? 1 : 0;
+}
+
+// The K smallest keys, ties at the K-th key broken by the lowest mask index:
+// a radix select of the K-th key, a radix select over the mask indices of
+// the masks holding that key, then one collection pass (list order is not
+// meaningful; its content is).  One block.
 __global__ __launch_bounds__(1024) void k_topk(const SegHdr* __restrict__ hdrs, int g,
-                                               const uint32_t* __restrict__ keys, int topk,
+                                               const uint32_t* __restrict__ keys,
+                                               const uint32_t* __restrict__ masks, int n, int topk,
                                                const int* __restrict__ status, uint32_t* __restrict__ list,
-                                               int* __restrict__ count) {
+                                               int* __restrict__ count, const int* __restrict__ flag,
+                                               int skip_if) {
   __shared__ int hist[256];
-  __shared__ uint32_t s_prefix, s_maskbits;
-  __shared__ int s_need;
-  __shared__ int scan[1024];
+  __shared__ uint32_t s_prefix, s_maskbits, s_mprefix, s_mmaskbits;
+  __shared__ int s_need, s_eq, s_n;
+  if (flag && *flag == skip_if) return;
   const SegHdr H = hdrs[g];
   if (!H.valid || (*status & (16 | 32))) {
     if (threadIdx.x == 0) *count = 0;
     return;
   }
-  const uint32_t nm = 1u << H.k;
+  const uint32_t nm = (uint32_t)n;
   const int K = (int)min((uint32_t)topk, nm);
-  if (threadIdx.x == 0) { s_prefix = 0; s_maskbits = 0; s_need = K; }
+  if (threadIdx.x == 0) { s_prefix = 0; s_maskbits = 0; s_need = K; s_eq = 0; s_n = 0; }
   __syncthreads();
+  // K-th smallest key T; s_need = how many masks holding T belong to the top K
   for (int shift = 24; shift >= 0; shift -= 8) {
     for (int q = threadIdx.x; q < 256; q += blockDim.x) hist[q] = 0;
     __syncthreads();
     const uint32_t pre = s_prefix, mb = s_maskbits;
-    for (uint32_t m = threadIdx.x; m < nm; m += blockDim.x)
-      if ((keys[m] & mb) == pre) atomicAdd(&hist[(keys[m] >> shift) & 255u], 1);
+    for (uint32_t i = threadIdx.x; i < nm; i += blockDim.x) {
+      const uint32_t key = keys[i];
+      if ((key & mb) == pre) atomicAdd(&hist[(key >> shift) & 255u], 1);
+    }
     __syncthreads();
     if (threadIdx.x == 0) {
       int need = s_need, cum = 0, d = 0;
@@ -392,32 +455,51 @@ __global__ __launch_bounds__(1024) void k_topk(const SegHdr* __restrict__ hdrs, 
       s_need = need - cum;
       s_prefix = pre | ((uint32_t)d << shift);
       s_maskbits = mb | (255u << shift);
+      if (shift == 0) s_eq = hist[d];  // masks holding T
     }
     __syncthreads();
   }
   const uint32_t T = s_prefix;
-  const int need_eq = s_need;  // masks with key == T to take, lowest first
-  int taken = 0, eq_seen = 0;
-  for (uint32_t base = 0; base < nm; base += blockDim.x) {
-    const uint32_t m = base + threadIdx.x;
-    const uint32_t key = m < nm ? keys[m] : 0xffffffffu;
-    const int eq = (m < nm && key == T) ? 1 : 0;
-    const int eq_before = block_exclusive_scan(eq, scan);
-    const int take = (m < nm && (key < T || (eq && eq_seen + eq_before < need_eq))) ? 1 : 0;
-    const int pos = block_exclusive_scan(take, scan);
-    if (take) list[taken + pos] = m;
-    // totals of this chunk (last thread's exclusive value plus its own flag)
-    __shared__ int s_tot_eq, s_tot_take;
-    if (threadIdx.x == blockDim.x - 1) {
-      s_tot_eq = eq_before + eq;
-      s_tot_take = pos + take;
+  // the s_need lowest mask indices among the s_eq masks holding T
+  if (threadIdx.x == 0) { s_mprefix = 0; s_mmaskbits = 0; }
+  __syncthreads();
+  if (s_need < s_eq) {
+    for (int shift = 16; shift >= 0; shift -= 8) {
+      for (int q = threadIdx.x; q < 256; q += blockDim.x) hist[q] = 0;
+      __syncthreads();
+      const uint32_t pre = s_mprefix, mb = s_mmaskbits;
+      for (uint32_t i = threadIdx.x; i < nm; i += blockDim.x) {
+        const uint32_t m = masks ? masks[i] : i;
+        if (keys[i] == T && (m & mb) == pre) atomicAdd(&hist[(m >> shift) & 255u], 1);
+      }
+      __syncthreads();
+      if (threadIdx.x == 0) {
+        int need = s_need, cum = 0, d = 0;
+        for (d = 0; d < 256; ++d) {
+          if (cum + hist[d] >= need) break;
+          cum += hist[d];
+        }
+        s_need = need - cum;
+        s_mprefix = pre | ((uint32_t)d << shift);
+        s_mmaskbits = mb | (255u << shift);
+      }
+      __syncthreads();
     }
-    __syncthreads();
-    eq_seen += s_tot_eq;
-    taken += s_tot_take;
-    __syncthreads();
+  } else if (threadIdx.x == 0) {
+    s_mprefix = 0xffffffffu;  // every mask holding T
   }
-  if (threadIdx.x == 0) *count = K;
+  __syncthreads();
+  const uint32_t Mt = s_mprefix;
+  for (uint32_t i = threadIdx.x; i < nm; i += blockDim.x) {
+    const uint32_t key = keys[i];
+    const uint32_t m = masks ? masks[i] : i;
+    if (key < T || (key == T && m <= Mt)) {
+      const int pos = atomicAdd(&s_n, 1);
+      if (pos < K) list[pos] = m;
+    }
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) *count = min(s_n, K);
 }
 
 // Exact (FP64) selection among the top-k: most reduced feasible, smallest
