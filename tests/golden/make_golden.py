@@ -1,0 +1,47 @@
+"""Writes the oracle's full-size decisions for the 6000- and 8400-node
+workloads (TEST INFRASTRUCTURE: calls only oracle/ and the input generator).
+
+For each case: per-segment chosen mask, popcount, e_loc and ambiguity flag,
+the final per-snapshot errors and the kept count, as JSON next to this
+script.  The oracle runs its descending-popcount search (every mask of a
+level scored before the next lower level; the first level holding a feasible
+mask decides), which selects the same mask as scoring all 2^k masks.
+
+    python tests/golden/make_golden.py
+"""
+import json
+import os
+import sys
+import time
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, os.path.dirname(os.path.dirname(HERE)))
+
+import numpy as np  # noqa: E402
+
+import oracle  # noqa: E402
+from synth_feeders import make_feeder  # noqa: E402
+
+CASES = [("c3", 0, 3e-3), ("c4", 0, 3e-3)]
+
+
+def main():
+    for cfg, seed, e_bar in CASES:
+        t0 = time.time()
+        f = make_feeder(cfg, seed, e_bar=e_bar)
+        V, I, st, _ = oracle.powerflow(f)
+        assert st == 0, f"load flow status {st}"
+        keep, dec, st = oracle.search(f, V, I)
+        err, _ = oracle.final_errors(f, V, I, keep)
+        out = dict(workload=cfg, seed=seed, e_bar=e_bar, status=int(st), n_kept=int(keep.sum()),
+                   err_per_snapshot=[float(x) for x in err],
+                   segments=[dict(mask=int(d["mask"]), popcount=int(d["popcount"]), e_loc=float(d["e_loc"]),
+                                  ambiguous=int(d["ambiguous"])) for d in dec])
+        name = os.path.join(HERE, f"oracle_{cfg}_seed{seed}.json")
+        with open(name, "w") as fh:
+            json.dump(out, fh)
+        print(f"{name}: {len(dec)} segments, kept {out['n_kept']}, {time.time() - t0:.0f} s", flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,95 @@
+"""Full-size parity on the 6000-node (96 snapshots, segments of 8-18) and
+8400-node (288 snapshots, segments of 8-20) workloads, in the graph-captured
+launch configuration and in mixed precision.
+
+Expected decisions and final errors come from tests/golden/make_golden.py
+(oracle only).  Per-mask scores are checked on sampled masks of sampled
+segments, each scored by the oracle at the state the earlier (golden)
+decisions leave.
+"""
+import json
+import os
+import sys
+
+import numpy as np
+import pytest
+
+import oracle
+from synth_feeders import dfs_preorder, make_feeder
+
+pytestmark = pytest.mark.gpu
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+TOL = 1e-9
+
+
+def _say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def okr():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.fail("GPU tests need a visible MI355X")
+    import paper_2510_19608_amd as okr
+    okr.lib()
+    return okr
+
+
+def golden(cfg):
+    with open(os.path.join(HERE, "golden", f"oracle_{cfg}_seed0.json")) as fh:
+        return json.load(fh)
+
+
+def check_against_golden(out, G):
+    assert not any(s["ambiguous"] for s in G["segments"]), "golden case holds a near-tie"
+    got = [s["mask"] for s in out["segments"]]
+    want = [s["mask"] for s in G["segments"]]
+    assert got == want
+    assert int(out["n_kept"]) == G["n_kept"]
+    for s, d in zip(out["segments"], G["segments"]):
+        assert abs(s["e_loc"] - d["e_loc"]) < TOL
+    np.testing.assert_allclose(out["err_per_snapshot"], G["err_per_snapshot"], rtol=0, atol=TOL)
+
+
+@pytest.mark.parametrize("cfg", ["c3", "c4"])
+@pytest.mark.parametrize("precision", ["fp64", "mixed"])
+def test_fullsize_decisions_graph(okr, cfg, precision):
+    _say(f"{cfg} seed 0 {precision} graph")
+    G = golden(cfg)
+    f = make_feeder(cfg, 0, e_bar=G["e_bar"])
+    out = okr.reduce_feeder(f, graph=True, precision=precision, want_vhat=False)
+    check_against_golden(out, G)
+
+
+@pytest.mark.parametrize("cfg", ["c3", "c4"])
+def test_fullsize_sampled_masks(okr, cfg):
+    """Every mask's FP64 score is dumped; sampled masks of three segments
+    (first, middle, last) are compared with the oracle at the golden state."""
+    _say(f"{cfg} seed 0 sampled masks")
+    G = golden(cfg)
+    f = make_feeder(cfg, 0, e_bar=G["e_bar"])
+    out = okr.reduce_feeder(f, dump=True, want_vhat=False)
+    check_against_golden(out, G)
+    V, I, st, _ = oracle.powerflow(f)
+    assert st == 0
+    pre = dfs_preorder(f["parent"])
+    nseg = len(G["segments"])
+    picks = sorted({0, nseg // 2, nseg - 1})
+    rng = np.random.default_rng(7)
+    keep = np.ones(f["n"], np.uint8)
+    for g in range(nseg):
+        order = [int(v) for v in pre if f["segment"][v] == g]
+        if g in picks:
+            e, s, k = out["scores"][g]
+            masks = np.unique(np.concatenate([rng.integers(0, 1 << k, 6), [0, (1 << k) - 1,
+                                                                            G["segments"][g]["mask"]]]))
+            ref = oracle.score_masks(f, V, I, keep, g, masks.astype(np.uint32))
+            np.testing.assert_allclose(e[masks], ref["e_loc"], rtol=0, atol=TOL)
+            fin = np.isfinite(ref["slack_loc"])
+            np.testing.assert_allclose(s[masks][fin], ref["slack_loc"][fin], rtol=0, atol=TOL)
+        for j, v in enumerate(order):
+            if G["segments"][g]["mask"] >> j & 1:
+                keep[v] = 0
