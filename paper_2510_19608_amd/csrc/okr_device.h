@@ -43,6 +43,9 @@ __device__ __forceinline__ double sqrt_nr(double x) {
   return fma(d, h, g);
 }
 __device__ __forceinline__ double vmag(double2 a) { return sqrt_nr(a.x * a.x + a.y * a.y); }
+// Magnitude of a chain head's voltage (mask-independent for chains that are
+// not nested below another chain), one fixed evaluation order.
+__device__ __forceinline__ double hmag(double2 a) { return sqrt_nr(fma(a.x, a.x, a.y * a.y)); }
 
 // Walk one chain for one mask: super-node slots top to bottom; a reduced slot
 // adds the voltage rise of moving its aggregated current to its current super
@@ -55,17 +58,29 @@ __device__ __forceinline__ double vmag(double2 a) { return sqrt_nr(a.x * a.x + a
 // lane's super slot.
 template <bool ERR>
 __device__ __forceinline__ void walk_chain(const int* __restrict__ cr, const int* __restrict__ slots,
-                                           const double2* Ps, const TargetRec* Ss, const double2* Hs, int c,
-                                           uint32_t m, double2& B0, double2& B1, double2& B2, double& el,
-                                           double& qmin, double& qmax) {
+                                           const double2* Ps, const TargetRec* Ss, const double2* Hs,
+                                           const double* Hm, int c, uint32_t m, double2& B0, double2& B1,
+                                           double2& B2, double& el, double& qmin, double& qmax) {
   double2 S0 = B0, S1 = B1, S2 = B2;
   double sm0 = 0.0, sm1 = 0.0, sm2 = 0.0;
   if (ERR) {
     const int hph = cr[C_PHASE];
     const double2* hv = Hs + c * 3;
-    if (hph & 1) sm0 = vmag(cadd(hv[0], B0));
-    if (hph & 2) sm1 = vmag(cadd(hv[1], B1));
-    if (hph & 4) sm2 = vmag(cadd(hv[2], B2));
+    if (cr[C_OUTER] < 0) {  // head unaffected by the mask
+      if (Hm) {
+        sm0 = Hm[c * 3];
+        sm1 = Hm[c * 3 + 1];
+        sm2 = Hm[c * 3 + 2];
+      } else {
+        if (hph & 1) sm0 = hmag(hv[0]);
+        if (hph & 2) sm1 = hmag(hv[1]);
+        if (hph & 4) sm2 = hmag(hv[2]);
+      }
+    } else {
+      if (hph & 1) sm0 = vmag(cadd(hv[0], B0));
+      if (hph & 2) sm1 = vmag(cadd(hv[1], B1));
+      if (hph & 4) sm2 = vmag(cadd(hv[2], B2));
+    }
   }
   const int ns = cr[C_NSLOT], s0 = cr[C_SLOT0];
   int sidx = 0;
@@ -121,17 +136,17 @@ __device__ __forceinline__ bool near_boundary(const MaskScore& r, double e_bar, 
 __device__ __forceinline__ void score_snapshot(const SegHdr& H, const int* __restrict__ chains,
                                                const int* __restrict__ slots, const int* __restrict__ nest,
                                                const double2* Ps, const TargetRec* Ss, const double2* Hs,
-                                               const TargetRec* __restrict__ zrec_l, uint32_t m, double& el,
-                                               double& qmin, double& qmax) {
+                                               const double* Hm, const TargetRec* __restrict__ zrec_l, uint32_t m,
+                                               double& el, double& qmin, double& qmax) {
   for (int c = 0; c < H.nchains; ++c) {
     const int* cr = chains + c * kChainInts;
     double2 B0 = make_double2(0.0, 0.0), B1 = B0, B2 = B0;
     const int nl = cr[C_NEST_LEN], no = cr[C_NEST_OFF];
     for (int q = 0; q + 1 < nl; ++q) {
       const int oc = nest[no + q];
-      walk_chain<false>(chains + oc * kChainInts, slots, Ps, Ss, Hs, oc, m, B0, B1, B2, el, qmin, qmax);
+      walk_chain<false>(chains + oc * kChainInts, slots, Ps, Ss, Hs, Hm, oc, m, B0, B1, B2, el, qmin, qmax);
     }
-    walk_chain<true>(cr, slots, Ps, Ss, Hs, c, m, B0, B1, B2, el, qmin, qmax);
+    walk_chain<true>(cr, slots, Ps, Ss, Hs, Hm, c, m, B0, B1, B2, el, qmin, qmax);
 #define OKR_ZONE_PHASE(P_, B_)                                                   \
     for (int q = cr[C_ZOFF0 + P_], qe = q + cr[C_ZCNT0 + P_]; q < qe; ++q) {   \
       const TargetRec t = zrec_l[q];                                             \

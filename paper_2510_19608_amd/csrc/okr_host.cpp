@@ -70,9 +70,10 @@ __global__ void k_batch_cast(const float*, int, __bf16*, __bf16*);
 __global__ void k_loss_dy(const float*, const float*, int, float*, float*);
 __global__ void k_dz2(const float*, const float*, const float*, int, __bf16*, __bf16*);
 __global__ void k_dz1(const float*, const float*, int, __bf16*);
-__global__ void k_colsums(const float*, const float*, const float*, const float*, const float*, int, float*, float*,
-                          float*, float*);
+__global__ void k_colsums_part(const float*, const float*, const float*, const float*, const float*, int, float*);
+__global__ void k_colsums_final(const float*, int, float*, float*, float*, float*);
 __global__ void k_copy_cols(const float*, int, float*, int, int);
+__global__ void k_sum_splits(const float*, int, int, float*);
 __global__ void k_adam(float*, const float*, float*, float*, int, float, float, float);
 __global__ void k_refresh_weights(const float*, __bf16*, __bf16*, __bf16*);
 __global__ void k_surr_keys(const SegHdr*, int, const float*, float, const uint32_t*, int, uint32_t*, const int*,
@@ -934,11 +935,16 @@ namespace {
 
 struct SurrWork {
   __bf16 *Xb, *Xt, *H1b, *H1t, *dZ2b, *dZ2t, *dZ1t, *W1b, *W2b, *W2tb;
-  float *Z1, *Z2, *part, *y, *dy, *dH1, *gW1full, *grads, *m, *v, *loss;
+  float *Z1, *Z2, *part, *y, *dy, *dH1, *gW1full, *grads, *m, *v, *loss, *colpart, *gpart;
   size_t bytes;
 };
 
 constexpr int kMaxEpochs = 4096;
+constexpr int kColChunkHost = 256;  // rows per partial column sum (k_colsums_part)
+constexpr int kSplitK = 256;        // batch rows per K slice of the weight-gradient GEMMs
+
+// K slices of the weight-gradient GEMMs for a batch of B rows (B % 64 == 0).
+int surr_splits(int B) { return (B % kSplitK == 0) ? B / kSplitK : 1; }
 
 SurrWork surr_layout(int B, void* base) {
   SurrWork w{};
@@ -971,6 +977,8 @@ SurrWork surr_layout(int B, void* base) {
   w.m = (float*)take(f4 * kSurrParams);
   w.v = (float*)take(f4 * kSurrParams);
   w.loss = (float*)take(f4 * kMaxEpochs);
+  w.colpart = (float*)take(f4 * (3 * kSurrH + 1) * ((B + kColChunkHost - 1) / kColChunkHost));
+  w.gpart = (float*)take(f4 * kSurrH * kSurrH * surr_splits(B));
   w.bytes = off;
   return w;
 }
@@ -996,11 +1004,14 @@ void surr_backward(const SurrWork& w, const float* prm, const float* t, int B, f
   hipLaunchKernelGGL(k_loss_dy, dim3((B + 255) / 256), dim3(256), 0, st, (const float*)w.y, t, B, w.dy, loss);
   hipLaunchKernelGGL(k_dz2, dim3((B * kSurrH + 255) / 256), dim3(256), 0, st, (const float*)w.Z2, (const float*)w.dy,
                      prm + kOffW3, B, w.dZ2b, w.dZ2t);
-  // dW2 = dZ2^T H1
-  hipLaunchKernelGGL(k_gemm_nt<0>, dim3(kSurrH / 64, kSurrH / 64), dim3(256), 0, st, (const __bf16*)w.dZ2t, B,
-                     (const __bf16*)w.H1t, B, B, w.grads + kOffW2, kSurrH, (const float*)nullptr, (float*)nullptr,
+  // dW2 = dZ2^T H1, K = B split into slices of kSplitK rows
+  const int splits = surr_splits(B);
+  hipLaunchKernelGGL(k_gemm_nt<0>, dim3(kSurrH / 64, kSurrH / 64, splits), dim3(256), 0, st, (const __bf16*)w.dZ2t,
+                     B, (const __bf16*)w.H1t, B, B, w.gpart, kSurrH, (const float*)nullptr, (float*)nullptr,
                      (__bf16*)nullptr, (__bf16*)nullptr, kSurrH, (const float*)nullptr, (float*)nullptr,
                      (const int*)nullptr, 0);
+  hipLaunchKernelGGL(k_sum_splits, dim3(kSurrH * kSurrH / 256), dim3(256), 0, st, (const float*)w.gpart, splits,
+                     kSurrH * kSurrH, w.grads + kOffW2);
   // dH1 = dZ2 W2
   hipLaunchKernelGGL(k_gemm_nt<0>, dim3(kSurrH / 64, B / 64), dim3(256), 0, st, (const __bf16*)w.dZ2b, kSurrH,
                      (const __bf16*)w.W2tb, kSurrH, kSurrH, w.dH1, kSurrH, (const float*)nullptr, (float*)nullptr,
@@ -1008,16 +1019,20 @@ void surr_backward(const SurrWork& w, const float* prm, const float* t, int B, f
                      (const int*)nullptr, 0);
   hipLaunchKernelGGL(k_dz1, dim3((B * kSurrH + 255) / 256), dim3(256), 0, st, (const float*)w.dH1, (const float*)w.Z1,
                      B, w.dZ1t);
-  // dW1 = dZ1^T X (X^T padded to 64 rows)
-  hipLaunchKernelGGL(k_gemm_nt<0>, dim3(1, kSurrH / 64), dim3(256), 0, st, (const __bf16*)w.dZ1t, B,
-                     (const __bf16*)w.Xt, B, B, w.gW1full, 64, (const float*)nullptr, (float*)nullptr,
+  // dW1 = dZ1^T X (X^T padded to 64 rows), split like dW2
+  hipLaunchKernelGGL(k_gemm_nt<0>, dim3(1, kSurrH / 64, splits), dim3(256), 0, st, (const __bf16*)w.dZ1t, B,
+                     (const __bf16*)w.Xt, B, B, w.gpart, 64, (const float*)nullptr, (float*)nullptr,
                      (__bf16*)nullptr, (__bf16*)nullptr, kSurrH, (const float*)nullptr, (float*)nullptr,
                      (const int*)nullptr, 0);
+  hipLaunchKernelGGL(k_sum_splits, dim3(kSurrH * 64 / 256), dim3(256), 0, st, (const float*)w.gpart, splits,
+                     kSurrH * 64, w.gW1full);
   hipLaunchKernelGGL(k_copy_cols, dim3((kSurrH * kSurrF + 255) / 256), dim3(256), 0, st, (const float*)w.gW1full, 64,
                      w.grads + kOffW1, kSurrH, kSurrF);
-  hipLaunchKernelGGL(k_colsums, dim3((kSurrH + 1 + 255) / 256), dim3(256), 0, st, (const float*)w.Z1,
-                     (const float*)w.dH1, (const float*)w.Z2, (const float*)w.dy, prm + kOffW3, B, w.grads + kOffB1,
-                     w.grads + kOffB2, w.grads + kOffW3, w.grads + kOffB3);
+  const int nchunk = (B + kColChunkHost - 1) / kColChunkHost;
+  hipLaunchKernelGGL(k_colsums_part, dim3(nchunk), dim3(kSurrH + 1), 0, st, (const float*)w.Z1, (const float*)w.dH1,
+                     (const float*)w.Z2, (const float*)w.dy, prm + kOffW3, B, w.colpart);
+  hipLaunchKernelGGL(k_colsums_final, dim3((3 * kSurrH + 1 + 255) / 256), dim3(256), 0, st, (const float*)w.colpart,
+                     nchunk, w.grads + kOffB1, w.grads + kOffB2, w.grads + kOffW3, w.grads + kOffB3);
 }
 
 void surr_refresh(const SurrWork& w, const float* prm, hipStream_t st) {

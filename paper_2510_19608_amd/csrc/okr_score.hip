@@ -27,6 +27,7 @@ __global__ __launch_bounds__(kScoreThreads) void k_score_fp64(
   __shared__ double2 Ps[kMaxPairs * 3];
   __shared__ TargetRec Ts[kMaxK * 3];
   __shared__ double2 Hv[kMaxK * 3];
+  __shared__ double Hm[kMaxK * 3];
   __shared__ int ticket;
   const SegHdr H = hdrs[g];
   if (!H.valid || (gate && *gate == 0)) return;
@@ -45,10 +46,14 @@ __global__ __launch_bounds__(kScoreThreads) void k_score_fp64(
     const TargetRec* Sl = srec + (size_t)l * H.nslots * 3;
     for (int q = tid; q < H.nslots * 3; q += kScoreThreads) Ts[q] = Sl[q];
     const double2* Hl = headV + (size_t)l * H.nchains * 3;
-    for (int q = tid; q < H.nchains * 3; q += kScoreThreads) Hv[q] = Hl[q];
+    for (int q = tid; q < H.nchains * 3; q += kScoreThreads) {
+      const double2 hv = Hl[q];
+      Hv[q] = hv;
+      Hm[q] = (hv.x != 0.0 || hv.y != 0.0) ? hmag(hv) : 0.0;  // absent phases stay 0
+    }
     __syncthreads();
     double el = econst[l];
-    score_snapshot(H, chains, slots, nest, Ps, Ts, Hv, zrec + (size_t)l * H.nz, m, el, qmin, qmax);
+    score_snapshot(H, chains, slots, nest, Ps, Ts, Hv, Hm, zrec + (size_t)l * H.nz, m, el, qmin, qmax);
     e = fmax(e, el);
     __syncthreads();
   }
@@ -120,7 +125,8 @@ __global__ __launch_bounds__(kScoreBlock) void k_refine_fp64(
     for (int l = lane; l < H.S; l += kScoreBlock) {
       double el = econst[l];
       score_snapshot(H, chains, slots, nest, P + (size_t)l * H.npairs * 3, srec + (size_t)l * H.nslots * 3,
-                     headV + (size_t)l * H.nchains * 3, zrec + (size_t)l * H.nz, m, el, qmin, qmax);
+                     headV + (size_t)l * H.nchains * 3, (const double*)nullptr, zrec + (size_t)l * H.nz, m, el,
+                     qmin, qmax);
       e = fmax(e, el);
     }
     for (int o = 32; o > 0; o >>= 1) {

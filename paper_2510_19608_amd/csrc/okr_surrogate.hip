@@ -217,7 +217,11 @@ __global__ __launch_bounds__(256) void k_gemm_nt(const __bf16* __restrict__ A, i
   f32x16 acc;
   for (int v = 0; v < 16; ++v) acc[v] = 0.f;
   const int lr = tid >> 2, lc = (tid & 3) * 8;
-  for (int k0 = 0; k0 < K; k0 += 32) {
+  // split K over grid.z (STORE only): slice z writes its partial product to
+  // C + z * M * ldc
+  const int kspan = K / (int)gridDim.z, kb = (int)blockIdx.z * kspan;
+  if (EPI == EPI_STORE) C += (size_t)blockIdx.z * M * ldc;
+  for (int k0 = kb; k0 < kb + kspan; k0 += 32) {
     *(uint4*)&As[lr][lc] = *(const uint4*)&A[(size_t)(m0 + lr) * lda + k0 + lc];
     *(uint4*)&Bs[lr][lc] = *(const uint4*)&B[(size_t)(n0 + lr) * ldb + k0 + lc];
     __syncthreads();
@@ -264,6 +268,15 @@ OKR_GEMM_INST(EPI_STORE)
 OKR_GEMM_INST(EPI_BIAS_GELU)
 OKR_GEMM_INST(EPI_BIAS_GELU_DOT)
 #undef OKR_GEMM_INST
+
+// out[i] = sum over the K slices' partial products, in slice order.
+__global__ void k_sum_splits(const float* __restrict__ part, int splits, int n, float* __restrict__ out) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  float t = 0.f;
+  for (int z = 0; z < splits; ++z) t += part[(size_t)z * n + i];
+  out[i] = t;
+}
 
 // y[m] = b3 + sum over the column blocks' partial dots, in a fixed order.
 __global__ void k_rowdot_finish(const float* __restrict__ part, int nblk, int M, const float* __restrict__ b3,
@@ -319,29 +332,47 @@ __global__ void k_dz1(const float* __restrict__ dH1, const float* __restrict__ Z
   dZ1t[(size_t)o * B + b] = (__bf16)(dH1[i] * gelu_grad_f(Z1[i]));
 }
 
-// Column reductions over the batch (one thread per column, fixed order):
+// Column reductions over the batch, in two passes with a fixed order (no
+// atomics): partial sums over row chunks of kColChunk, then their sum.
 //   gb2[o] = sum_b dy[b] w3[o] gelu'(Z2[b][o]);  gw3[o] = sum_b gelu(Z2[b][o]) dy[b]
 //   gb1[o] = sum_b dH1[b][o] gelu'(Z1[b][o]);    gb3 = sum_b dy[b]
-__global__ void k_colsums(const float* __restrict__ Z1, const float* __restrict__ dH1, const float* __restrict__ Z2,
-                          const float* __restrict__ dy, const float* __restrict__ w3, int B, float* __restrict__ gb1,
-                          float* __restrict__ gb2, float* __restrict__ gw3, float* __restrict__ gb3) {
-  const int o = blockIdx.x * blockDim.x + threadIdx.x;
+constexpr int kColChunk = 256;
+constexpr int kColVals = 3 * kSurrH + 1;  // gb2, gw3, gb1 per column, then gb3
+
+__global__ void k_colsums_part(const float* __restrict__ Z1, const float* __restrict__ dH1,
+                               const float* __restrict__ Z2, const float* __restrict__ dy,
+                               const float* __restrict__ w3, int B, float* __restrict__ part) {
+  const int o = threadIdx.x;  // blockDim = kSurrH + 1
+  const int b0 = blockIdx.x * kColChunk, b1 = min(B, b0 + kColChunk);
+  float* out = part + (size_t)blockIdx.x * kColVals;
   if (o < kSurrH) {
     float a = 0.f, c = 0.f, d = 0.f;
-    for (int b = 0; b < B; ++b) {
+    for (int b = b0; b < b1; ++b) {
       const float z2 = Z2[(size_t)b * kSurrH + o];
       a += dy[b] * w3[o] * gelu_grad_f(z2);
       c += gelu_f(z2) * dy[b];
       d += dH1[(size_t)b * kSurrH + o] * gelu_grad_f(Z1[(size_t)b * kSurrH + o]);
     }
-    gb2[o] = a;
-    gw3[o] = c;
-    gb1[o] = d;
+    out[o] = a;
+    out[kSurrH + o] = c;
+    out[2 * kSurrH + o] = d;
   } else if (o == kSurrH) {
-    float s = 0.f;
-    for (int b = 0; b < B; ++b) s += dy[b];
-    gb3[0] = s;
+    float t = 0.f;
+    for (int b = b0; b < b1; ++b) t += dy[b];
+    out[3 * kSurrH] = t;
   }
+}
+
+__global__ void k_colsums_final(const float* __restrict__ part, int nchunk, float* __restrict__ gb1,
+                                float* __restrict__ gb2, float* __restrict__ gw3, float* __restrict__ gb3) {
+  const int q = blockIdx.x * blockDim.x + threadIdx.x;
+  if (q >= kColVals) return;
+  float t = 0.f;
+  for (int c = 0; c < nchunk; ++c) t += part[(size_t)c * kColVals + q];
+  if (q < kSurrH) gb2[q] = t;
+  else if (q < 2 * kSurrH) gw3[q - kSurrH] = t;
+  else if (q < 3 * kSurrH) gb1[q - 2 * kSurrH] = t;
+  else gb3[0] = t;
 }
 
 __global__ void k_copy_cols(const float* __restrict__ src, int lds, float* __restrict__ dst, int rows, int cols) {
