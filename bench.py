@@ -47,9 +47,11 @@ def cpu_baseline(f, seconds=12.0):
                        f"FP64 Kron elimination + reduced-network solve + scoring per mask, {dt:.1f} s on 1 core")
 
 
-def timed_runs(R, reps):
-    """Median wall time (ms) of `reps` whole searches after one warm-up."""
+def timed_runs(R, reps, autotune=True):
+    """Median wall time (ms) of `reps` whole searches after one warm-up (the
+    warm-up tunes the scoring launch shape unless autotune is off)."""
     import torch
+    R.run(replan=False, autotune=autotune)
     R.run(replan=False)
     torch.cuda.synchronize()
     ts = []
@@ -93,7 +95,7 @@ def surrogate_mode(f, args, plain_ms, ref, ncand):
     n_pairs = int(X.shape[0])
     del X, t
     R = Reducer(f, device="cuda:0", graph=True, surrogate=params, top_k=args.top_k)
-    ms = timed_runs(R, args.reps)
+    ms = timed_runs(R, args.reps, not args.no_autotune)
     masks, pops, res = decisions(R)
     fallback = sum(1 for s in res["segments"] if s["n_scored"] > s["n_refined"])
     R.close()
@@ -114,6 +116,8 @@ def main():
     ap.add_argument("--surr-epochs", type=int, default=6)
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-modes", action="store_true")
+    ap.add_argument("--no-autotune", action="store_true",
+                    help="keep the default scoring launch shape (no tuning run before the warm-up)")
     ap.add_argument("--copy-probe-mib", type=int, default=0,
                     help="first run one device-to-device copy of this many MiB (a known-size reference "
                          "for hardware byte counters)")
@@ -136,6 +140,8 @@ def main():
     f = make_feeder("c2", args.seed)
     R = Reducer(f, device="cuda:0", timing=True)
     ncand = int(R.sizes.n_candidates)
+    if not args.no_autotune:
+        R.run(replan=False, autotune=True)
     for _ in range(args.warmup):
         R.run(replan=False)
     torch.cuda.synchronize()
@@ -180,12 +186,12 @@ def main():
     if not args.no_modes:
         modes = {}
         Rg = Reducer(f, device="cuda:0", graph=True)
-        plain_ms = timed_runs(Rg, args.reps)
+        plain_ms = timed_runs(Rg, args.reps, not args.no_autotune)
         m, p, res = decisions(Rg)
         Rg.close()
         modes["plain_fp64"] = mode_entry("plain", plain_ms, plain_ms, m, p, res, ref_masks, ref_pops, ncand)
         Rm = Reducer(f, device="cuda:0", graph=True, precision="mixed")
-        ms = timed_runs(Rm, args.reps)
+        ms = timed_runs(Rm, args.reps, not args.no_autotune)
         m, p, res = decisions(Rm)
         refined = sum(s["n_refined"] for s in res["segments"])
         dev = max(s["fp32_dev"] for s in res["segments"])

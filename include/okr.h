@@ -74,6 +74,12 @@ extern "C" {
 #define OKR_FLAG_VHAT_GIVEN 2u /* loads->Vhat holds the scenario voltages */
 #define OKR_FLAG_DUMP_SCORES 4u /* keep every segment's per-mask (e, slack) for
                                    okr_dump_scores() */
+#define OKR_FLAG_AUTOTUNE 16u  /* before this call's search, run the search
+                                  once per candidate snapshot-group count
+                                  of the scoring launch (1, 2, 4, ... 32,
+                                  within the planned workspace), keep the
+                                  fastest per segment size in the handle for
+                                  this and later calls */
 #define OKR_FLAG_GRAPH 8u      /* capture the whole search (load flow, every
                                   segment, final outputs) as one hipGraph on
                                   the first call and replay it afterwards;

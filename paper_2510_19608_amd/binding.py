@@ -33,6 +33,7 @@ class OKR:
     FLAG_VHAT_GIVEN = 2
     FLAG_DUMP_SCORES = 4
     FLAG_GRAPH = 8
+    FLAG_AUTOTUNE = 16
 
 
 class OkrError(RuntimeError):
@@ -296,10 +297,12 @@ class Reducer:
         self.margins.surrogate = None if params is None else params.data_ptr()
         self.margins.top_k = top_k if params is not None else 0
 
-    def run(self, replan=True, want_vhat=False, want_features=False):
+    def run(self, replan=True, want_vhat=False, want_features=False, autotune=False):
         """One pass of the whole search (planning included when replan).  With
         want_features the per-mask surrogate features and FP64 targets of every
-        segment are left in ``self.features`` / ``self.targets`` (device)."""
+        segment are left in ``self.features`` / ``self.targets`` (device).
+        With autotune the scoring launch shape is tuned first (kept in the
+        handle for later runs)."""
         # inputs written on the caller's stream are complete before the search
         self.stream.wait_stream(self.torch.cuda.current_stream(self.device))
         if replan:
@@ -316,8 +319,14 @@ class Reducer:
         else:
             self.res.features = None
             self.res.targets = None
-        rc = okr_reduce_feeder(self.h, self.Y, self.topo, self.loads, self.margins,
-                               ctypes.c_void_p(self.ws.data_ptr()), self.ws_bytes, self.res)
+        flags = self.margins.flags
+        if autotune:
+            self.margins.flags = flags | OKR.FLAG_AUTOTUNE
+        try:
+            rc = okr_reduce_feeder(self.h, self.Y, self.topo, self.loads, self.margins,
+                                   ctypes.c_void_p(self.ws.data_ptr()), self.ws_bytes, self.res)
+        finally:
+            self.margins.flags = flags
         return rc
 
     def result(self):

@@ -98,7 +98,7 @@ size_t align256(size_t x) { return (x + 255) & ~size_t(255); }
 
 // Snapshot groups of a scoring launch: enough blocks to fill the chip (about
 // 8192 waves), each group a contiguous run of snapshots.
-int snap_groups(int k, int S, int* spg) {
+int snap_groups_default(int k, int S, int* spg) {
   const int mblocks = (int)((((uint64_t)1 << k) + kScoreThreads - 1) / kScoreThreads);
   int SG = std::min(S, std::max(1, 2048 / mblocks));
   SG = std::min(SG, kMaxSnapGroups);
@@ -144,7 +144,28 @@ struct okr_handle {
   // per-mask score dumps (FP64 scores, or FP32 screening scores in MIXED)
   std::vector<std::vector<MaskScore>> dump;
   std::vector<std::vector<MaskScore32>> dump32;
+  // snapshot groups of the scoring launches: autotuned per segment size
+  // (0 = the default rule), a value forced while tuning, and the partial
+  // score capacity (masks x groups) the workspace was planned with
+  std::vector<int> sg_tuned;
+  int sg_force = 0;
+  size_t part_cap = 0;
 };
+
+namespace {
+// Snapshot groups of the scoring launch for a segment of k nodes: the forced
+// or tuned count, else the default rule, within the planned partial-score
+// capacity; spg = snapshots per group.
+int snap_groups(const okr_handle* h, int k, int* spg) {
+  const int S = h->S;
+  int SG = h->sg_force ? h->sg_force : ((int)h->sg_tuned.size() > k && h->sg_tuned[k] ? h->sg_tuned[k] : 0);
+  if (SG <= 0) return snap_groups_default(k, S, spg);
+  SG = std::min(std::min(SG, S), kMaxSnapGroups);
+  while (SG > 1 && ((size_t)SG << k) > h->part_cap) --SG;
+  *spg = (S + SG - 1) / SG;
+  return (S + *spg - 1) / *spg;
+}
+}  // namespace
 
 #define OKR_FAIL(h, code, ...)            \
   do {                                    \
@@ -348,9 +369,11 @@ extern "C" int okr_plan(okr_handle* h, const okr_topology* topo, const okr_margi
     size_t most = 1;
     for (int k = 1; k <= h->kmax; ++k) {
       int spg;
-      most = std::max(most, (size_t)snap_groups(k, S, &spg) << k);
+      most = std::max(most, (size_t)snap_groups_default(k, S, &spg) << k);
     }
     L.part = take(sizeof(MaskScore) * most);
+    h->part_cap = most;
+    if ((int)h->sg_tuned.size() != h->kmax + 1) h->sg_tuned.assign(h->kmax + 1, 0);  // tuning survives a re-plan
     const size_t nm = (size_t)1 << h->kmax, nt = (nm + 63) / 64;
     L.fin = take(sizeof(MaskScore) * nm);
     L.tiles = take(sizeof(TileRec) * nt);
@@ -360,7 +383,7 @@ extern "C" int okr_plan(okr_handle* h, const okr_topology* topo, const okr_margi
     size_t most = 1;
     for (int k = 1; k <= h->kmax; ++k) {
       int spg;
-      most = std::max(most, (size_t)snap_groups(k, S, &spg) << k);
+      most = std::max(most, (size_t)snap_groups_default(k, S, &spg) << k);
     }
     const size_t nm = (size_t)1 << h->kmax, nt = (nm + 63) / 64;
     L.P32 = take(sizeof(Pair32) * 3 * (size_t)S * kMaxPairs);
@@ -584,7 +607,7 @@ void enqueue_search(okr_handle* h, const Ptrs& p, const okr_yblocks* Y, const ok
     const uint32_t nmask = 1u << k;
     const int mblocks = (int)((nmask + kScoreThreads - 1) / kScoreThreads);
     int spg;
-    const int SG = snap_groups(k, S, &spg);
+    const int SG = snap_groups(h, k, &spg);
     const int* gate = nullptr;
     if (surr || feat_out) {
       hipLaunchKernelGGL(k_surr_tables, dim3((kMaxPairs + kMaxK + 127) / 128), dim3(128), 0, st,
@@ -774,6 +797,41 @@ extern "C" int okr_reduce_feeder(okr_handle* h, const okr_yblocks* Y, const okr_
     drop_events(h);
     h->ev.resize(2 * std::max(nseg, 1), nullptr);
     for (auto& e : h->ev) OKR_HIP(h, hipEventCreate(&e));
+  }
+  if (mg->flags & OKR_FLAG_AUTOTUNE) {
+    // time the scoring launches of a whole search once per candidate group
+    // count; keep the fastest per segment size
+    if ((int)h->ev.size() < 2 * nseg) {
+      drop_events(h);
+      h->ev.resize(2 * std::max(nseg, 1), nullptr);
+      for (auto& e : h->ev) OKR_HIP(h, hipEventCreate(&e));
+    }
+    std::vector<std::vector<double>> tsum(h->kmax + 1, std::vector<double>(kMaxSnapGroups + 1, 0.0));
+    for (int c = 1; c <= std::min(S, kMaxSnapGroups); c *= 2) {
+      h->sg_force = c;
+      enqueue_search(h, p, Y, loads, mg, st, &h->ev, nullptr, nullptr, nullptr, nullptr);
+      const hipError_t e1 = hipGetLastError(), e2 = hipStreamSynchronize(st);
+      h->sg_force = 0;
+      if (e1 != hipSuccess || e2 != hipSuccess)
+        OKR_FAIL(h, OKR_E_HIP, "autotune run failed: %s", hipGetErrorString(e1 != hipSuccess ? e1 : e2));
+      for (int g = 0; g < nseg; ++g) {
+        const int k = h->seg_off[g + 1] - h->seg_off[g];
+        h->sg_force = c;
+        int spg;
+        const int used = snap_groups(h, k, &spg);
+        h->sg_force = 0;
+        float ms = 0.f;
+        OKR_HIP(h, hipEventElapsedTime(&ms, h->ev[2 * g], h->ev[2 * g + 1]));
+        if (used == c) tsum[k][c] += ms;
+      }
+    }
+    for (int k = 1; k <= h->kmax; ++k) {
+      int best = 0;
+      for (int c = 1; c <= kMaxSnapGroups; c *= 2)
+        if (tsum[k][c] > 0.0 && (best == 0 || tsum[k][c] < tsum[k][best])) best = c;
+      h->sg_tuned[k] = best;
+    }
+    drop_graph(h);  // a captured search used the earlier group counts
   }
   if (graph && st == nullptr) OKR_FAIL(h, OKR_E_ARG, "OKR_FLAG_GRAPH needs a non-null stream (the null stream cannot be captured)");
   if (graph) {

@@ -278,3 +278,25 @@ def test_fp32_screening_error_bound(okr, name, seed, e_bar):
         worst_s = max(worst_s, np.abs(s32[fin] - s64[fin]).max(initial=0.0))
     _say(f"fp32 screening worst |de| = {worst_e:.3e}, |dslack| = {worst_s:.3e}")
     assert worst_e <= MIXED_DELTA and worst_s <= MIXED_DELTA
+
+
+def test_autotuned_launch_shape_gives_identical_results(okr):
+    """Tuning the scoring launch (snapshot groups per segment size) changes
+    only the schedule: decisions, per-segment errors and outputs are the same
+    as with the default shape, on the tuning call and after it."""
+    import torch
+    _say("autotune c2 seed 2")
+    f = make_feeder("c2", 2, e_bar=3e-4)
+    ref = okr.reduce_feeder(f, want_vhat=False)
+    R = okr.Reducer(f)
+    try:
+        for autotune in (True, False, False):
+            R.run(replan=False, autotune=autotune)
+            torch.cuda.synchronize()
+            out = R.result()
+            assert [s["mask"] for s in out["segments"]] == [s["mask"] for s in ref["segments"]]
+            assert [s["e_loc"] for s in out["segments"]] == [s["e_loc"] for s in ref["segments"]]
+            np.testing.assert_array_equal(out["err_per_snapshot"], ref["err_per_snapshot"])
+            np.testing.assert_array_equal(out["Yk_diag"], ref["Yk_diag"])
+    finally:
+        R.close()
