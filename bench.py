@@ -116,6 +116,8 @@ def main():
     ap.add_argument("--surr-epochs", type=int, default=6)
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-modes", action="store_true")
+    ap.add_argument("--modes", default="plain,mixed,surrogate",
+                    help="comma-separated forms timed for time-to-optimal (plain is always timed)")
     ap.add_argument("--no-autotune", action="store_true",
                     help="keep the default scoring launch shape (no tuning run before the warm-up)")
     ap.add_argument("--copy-probe-mib", type=int, default=0,
@@ -190,15 +192,18 @@ def main():
         m, p, res = decisions(Rg)
         Rg.close()
         modes["plain_fp64"] = mode_entry("plain", plain_ms, plain_ms, m, p, res, ref_masks, ref_pops, ncand)
-        Rm = Reducer(f, device="cuda:0", graph=True, precision="mixed")
-        ms = timed_runs(Rm, args.reps, not args.no_autotune)
-        m, p, res = decisions(Rm)
-        refined = sum(s["n_refined"] for s in res["segments"])
-        dev = max(s["fp32_dev"] for s in res["segments"])
-        Rm.close()
-        modes["mixed"] = mode_entry("mixed", ms, plain_ms, m, p, res, ref_masks, ref_pops, ncand,
-                                    dict(fp64_rescored_masks=refined, max_fp32_vs_fp64_error=dev))
-        modes["surrogate"] = surrogate_mode(f, args, plain_ms, (ref_masks, ref_pops), ncand)
+        wanted = set(args.modes.split(","))
+        if "mixed" in wanted:
+            Rm = Reducer(f, device="cuda:0", graph=True, precision="mixed")
+            ms = timed_runs(Rm, args.reps, not args.no_autotune)
+            m, p, res = decisions(Rm)
+            refined = sum(s["n_refined"] for s in res["segments"])
+            dev = max(s["fp32_dev"] for s in res["segments"])
+            Rm.close()
+            modes["mixed"] = mode_entry("mixed", ms, plain_ms, m, p, res, ref_masks, ref_pops, ncand,
+                                        dict(fp64_rescored_masks=refined, max_fp32_vs_fp64_error=dev))
+        if "surrogate" in wanted:
+            modes["surrogate"] = surrogate_mode(f, args, plain_ms, (ref_masks, ref_pops), ncand)
         line["modes"] = modes
     if not args.no_cpu:
         line["cpu_baseline"] = cpu_baseline(f)

@@ -39,8 +39,10 @@ __device__ __forceinline__ int child_toward(const Topo& T, int h, int v) {
 __global__ __launch_bounds__(256) void k_build_struct(Topo T, State St, int g, int S, SegHdr* __restrict__ hdrs,
                                                       int* __restrict__ tab, int tab_cap, int* __restrict__ status) {
   __shared__ int s_top[kMaxK], s_tops[kMaxK], s_slotnode[kMaxK], s_slotbit[kMaxK], s_slotchain[kMaxK];
-  __shared__ int s_cslot0[kMaxK + 1], s_head[kMaxK], s_outer[kMaxK], s_pathpos[kMaxK];
-  __shared__ int s_spos[kMaxK], s_ssize[kMaxK];
+  __shared__ int s_cslot0[kMaxK + 1], s_head[kMaxK], s_outer[kMaxK], s_jslot[kMaxK];
+  __shared__ int s_spos[kMaxK], s_ssize[kMaxK], s_sph[kMaxK];           // segment node j
+  __shared__ int s_tpos[kMaxK], s_tsize[kMaxK], s_thead[kMaxK], s_thph[kMaxK];  // its chain top
+  __shared__ int s_cpos[kMaxK], s_csize[kMaxK], s_chph[kMaxK];          // chain c: top pos/size, head phase
   __shared__ int s_rs[kMaxK], s_re[kMaxK], s_rcum[kMaxK + 1];
   __shared__ int s_keycnt[kMaxK * 3], s_keyoff[kMaxK * 3], s_keycur[kMaxK * 3];
   __shared__ SegHdr s_h;
@@ -76,22 +78,42 @@ __global__ __launch_bounds__(256) void k_build_struct(Topo T, State St, int g, i
     s_top[tid] = c;
     s_spos[tid] = T.pos[e];
     s_ssize[tid] = T.size[e];
+    s_sph[tid] = T.phase[e];
+    const int hd = parent[c];
+    s_tpos[tid] = T.pos[c];
+    s_tsize[tid] = T.size[c];
+    s_thead[tid] = hd;
+    s_thph[tid] = hd >= 0 ? T.phase[hd] : 0;
   }
   __syncthreads();
   if (tid == 0 && !s_err) {
-    int nch = 0;
+    // distinct chain tops (shared-memory data only from here on)
+    int nch = 0, tj[kMaxK];
     for (int j = 0; j < k; ++j) {
       const int c = s_top[j];
       bool seen = false;
       for (int q = 0; q < nch; ++q) seen |= (s_tops[q] == c);
-      if (!seen) s_tops[nch++] = c;
+      if (!seen) {
+        tj[nch] = j;
+        s_tops[nch++] = c;
+      }
     }
     // chains in preorder of their tops
     for (int a = 1; a < nch; ++a) {
-      const int v = s_tops[a];
+      const int v = s_tops[a], vj = tj[a];
       int b = a - 1;
-      while (b >= 0 && T.pos[s_tops[b]] > T.pos[v]) { s_tops[b + 1] = s_tops[b]; --b; }
+      while (b >= 0 && s_tpos[tj[b]] > s_tpos[vj]) {
+        s_tops[b + 1] = s_tops[b];
+        tj[b + 1] = tj[b];
+        --b;
+      }
       s_tops[b + 1] = v;
+      tj[b + 1] = vj;
+    }
+    for (int c = 0; c < nch; ++c) {
+      s_cpos[c] = s_tpos[tj[c]];
+      s_csize[c] = s_tsize[tj[c]];
+      s_chph[c] = s_thph[tj[c]];
     }
     // slots chain by chain, top to bottom (segment nodes are in preorder)
     int ns = 0;
@@ -102,9 +124,10 @@ __global__ __launch_bounds__(256) void k_build_struct(Topo T, State St, int g, i
           s_slotnode[ns] = T.seg_nodes[o0 + j];
           s_slotbit[ns] = j;
           s_slotchain[ns] = c;
+          s_jslot[j] = ns;
           ++ns;
         }
-      s_head[c] = parent[s_tops[c]];
+      s_head[c] = s_thead[tj[c]];
     }
     s_cslot0[nch] = ns;
     if (ns != k) s_err = 1;
@@ -155,24 +178,16 @@ __global__ __launch_bounds__(256) void k_build_struct(Topo T, State St, int g, i
       for (int x = c; x >= 0; x = s_outer[x]) tab[o + q--] = x;
       o += d;
     }
-    H.o_path = o;
-    int path_off[kMaxK], path_len[kMaxK];
+    // every chain is a path: each slot lies below the previous one (the
+    // first below the chain top)
     for (int c = 0; c < nch && !err; ++c) {
-      const int bottom = s_slotnode[s_cslot0[c + 1] - 1];
-      int len = 1;
-      for (int v = bottom; v != s_tops[c] && v >= 0; v = parent[v]) ++len;
-      if (o + len > tab_cap || len > T.n) { err = 1; break; }
-      path_off[c] = o - H.o_path;
-      path_len[c] = len;
-      int q = len - 1, sl = s_cslot0[c + 1] - 1;
-      for (int v = bottom; v >= 0 && q >= 0; v = parent[v]) {
-        tab[o + q] = v;
-        if (sl >= s_cslot0[c] && s_slotnode[sl] == v) s_pathpos[sl--] = q;
-        if (v == s_tops[c]) break;
-        --q;
+      int pu = s_cpos[c], su = s_csize[c];
+      for (int s = s_cslot0[c]; s < s_cslot0[c + 1]; ++s) {
+        const int j = s_slotbit[s], pv = s_spos[j];
+        if (!(pu <= pv && pv < pu + su) || (s > s_cslot0[c] && pv == pu)) { err = 1; break; }
+        pu = pv;
+        su = s_ssize[j];
       }
-      if (sl >= s_cslot0[c]) err = 1;
-      o += len;
     }
     H.o_slot = o; o += ns * kSlotInts;
     H.o_pair = o;
@@ -184,9 +199,6 @@ __global__ __launch_bounds__(256) void k_build_struct(Topo T, State St, int g, i
         for (int sx = 0; sx <= r; ++sx) {
           if (npairs >= kMaxPairs || o + kPairInts > tab_cap) { err = 1; break; }
           tab[o + PR_RNODE] = s_slotnode[s];
-          tab[o + PR_FROM] = (sx == 0) ? 0 : s_pathpos[s_cslot0[c] + sx - 1] + 1;
-          tab[o + PR_TO] = s_pathpos[s];
-          tab[o + PR_PATHOFF] = path_off[c];
           tab[o + PR_SUPER] = (sx == 0) ? s_head[c] : s_slotnode[s_cslot0[c] + sx - 1];
           tab[o + PR_RSLOT] = s;
           o += kPairInts;
@@ -196,7 +208,7 @@ __global__ __launch_bounds__(256) void k_build_struct(Topo T, State St, int g, i
     // Omega_g ranges in preorder: union of the chain tops' subtrees
     int nr = 0;
     for (int c = 0; c < nch && !err; ++c) {
-      const int a = T.pos[s_tops[c]], b = a + T.size[s_tops[c]];
+      const int a = s_cpos[c], b = a + s_csize[c];
       int q = nr - 1;
       while (q >= 0 && s_rs[q] > a) { s_rs[q + 1] = s_rs[q]; s_re[q + 1] = s_re[q]; --q; }
       s_rs[q + 1] = a;
@@ -238,19 +250,29 @@ __global__ __launch_bounds__(256) void k_build_struct(Topo T, State St, int g, i
       cr[C_SLOT0] = s_cslot0[c];
       cr[C_NEST_OFF] = nest_off[c];
       cr[C_NEST_LEN] = nest_len[c];
-      cr[C_PATH_OFF] = path_off[c];
-      cr[C_PATH_LEN] = path_len[c];
       cr[C_OUTER] = s_outer[c];
-      cr[C_PHASE] = T.phase[s_head[c]];
+      cr[C_PHASE] = s_chph[c];
+      cr[C_BIT0] = s_slotbit[s_cslot0[c]];
+      cr[C_PAIR0] = pairbase[s_cslot0[c]];
+      int phw[3] = {0, 0, 0};
+      for (int s = s_cslot0[c]; s < s_cslot0[c + 1]; ++s) {
+        const int r = s - s_cslot0[c];
+        phw[r >> 3] |= s_sph[s_slotbit[s]] << (3 * (r & 7));
+        // a chain's nodes have at most one child, so its slots are consecutive
+        // segment nodes in preorder: consecutive mask bits
+        if (s_slotbit[s] != s_slotbit[s_cslot0[c]] + r) err = 1;
+      }
+      cr[C_PHW0] = phw[0];
+      cr[C_PHW1] = phw[1];
+      cr[C_PHW2] = phw[2];
       for (int p = 0; p < 3; ++p) { cr[C_ZOFF0 + p] = 0; cr[C_ZCNT0 + p] = 0; }
     }
     for (int s = 0; s < ns && !err; ++s) {
       int* sr = tab + H.o_slot + s * kSlotInts;
       sr[SL_NODE] = s_slotnode[s];
       sr[SL_BIT] = s_slotbit[s];
-      sr[SL_PHASE] = T.phase[s_slotnode[s]];
+      sr[SL_PHASE] = s_sph[s_slotbit[s]];
       sr[SL_PAIRBASE] = pairbase[s];
-      sr[SL_PATHPOS] = s_pathpos[s];
       sr[SL_CHAIN] = s_slotchain[s];
       St.slot_of[s_slotnode[s]] = s;
     }
@@ -279,9 +301,12 @@ __global__ __launch_bounds__(256) void k_build_struct(Topo T, State St, int g, i
       while (r + 1 < nr && rg[3 * (r + 1) + 2] <= q) ++r;
       const int i = T.pre[rg[3 * r] + (q - rg[3 * r + 2])];
       if (segment[i] == g || !St.kept[i]) continue;
-      int u = parent[i];
-      while (u >= 0 && segment[u] != g) u = parent[u];
-      const int s = (u >= 0) ? St.slot_of[u] : -1;
+      // anchor: the deepest segment node whose subtree holds i
+      const int pi = T.pos[i];
+      int best = -1;
+      for (int j = 0; j < k; ++j)
+        if (s_spos[j] < pi && pi < s_spos[j] + s_ssize[j] && (best < 0 || s_spos[j] > s_spos[best])) best = j;
+      const int s = (best >= 0) ? s_jslot[best] : -1;
       if (s < 0) { atomicOr(&s_err, 1); continue; }
       const int c = tab[H.o_slot + s * kSlotInts + SL_CHAIN];
       const int* cr = tab + H.o_chain + c * kChainInts;
@@ -338,7 +363,8 @@ __device__ __forceinline__ int omega_node(const Topo& T, const int* rg, int nr, 
 
 __global__ __launch_bounds__(256) void k_build_values(const SegHdr* __restrict__ hdrs, int g,
                                                       const int* __restrict__ tab, int n,
-                                                      const double2* __restrict__ z, const double2* __restrict__ Vcur,
+                                                      const double2* __restrict__ Zroot,
+                                                      const double2* __restrict__ Vcur,
                                                       const double2* __restrict__ A, double2* __restrict__ P,
                                                       TargetRec* __restrict__ srec, double2* __restrict__ headV,
                                                       TargetRec* __restrict__ zrec, double* __restrict__ econst) {
@@ -347,17 +373,16 @@ __global__ __launch_bounds__(256) void k_build_values(const SegHdr* __restrict__
   const int part = blockIdx.y;
   const int S = H.S;
   const int stride = gridDim.x * blockDim.x;
-  const int* path = tab + H.o_path;
   if (part == 0) {
+    // P = Z(super -> reduced) A_reduced with Z(s -> r) = Zroot(r) - Zroot(s),
+    // the series impedance of the path between them
     for (int t = blockIdx.x * blockDim.x + threadIdx.x; t < S * H.npairs; t += stride) {
       const int l = t / H.npairs, q = t % H.npairs;
       const int* pr = tab + H.o_pair + q * kPairInts;
+      const double2* zr = Zroot + (size_t)pr[PR_RNODE] * 9;
+      const double2* zs = Zroot + (size_t)pr[PR_SUPER] * 9;
       double2 Z[9];
-      for (int e = 0; e < 9; ++e) Z[e] = make_double2(0.0, 0.0);
-      for (int x = pr[PR_FROM]; x <= pr[PR_TO]; ++x) {
-        const double2* zv = z + (size_t)path[pr[PR_PATHOFF] + x] * 9;
-        for (int e = 0; e < 9; ++e) Z[e] = b_cadd(Z[e], zv[e]);
-      }
+      for (int e = 0; e < 9; ++e) Z[e] = make_double2(zr[e].x - zs[e].x, zr[e].y - zs[e].y);
       const double2* a = A + ((size_t)l * n + pr[PR_RNODE]) * 3;
       double2* o = P + ((size_t)l * H.npairs + q) * 3;
       for (int r = 0; r < 3; ++r)

@@ -47,72 +47,101 @@ __device__ __forceinline__ double vmag(double2 a) { return sqrt_nr(a.x * a.x + a
 // not nested below another chain), one fixed evaluation order.
 __device__ __forceinline__ double hmag(double2 a) { return sqrt_nr(fma(a.x, a.x, a.y * a.y)); }
 
-// Walk one chain for one mask: super-node slots top to bottom; a reduced slot
-// adds the voltage rise of moving its aggregated current to its current super
-// (P from LDS); a kept slot becomes the super of the slots below it.  With
-// ERR, every slot cluster's error against its super's magnitude is folded
-// into el, and the squared magnitudes of kept slots into (qmin, qmax) for the
-// band (the slack is formed once per mask: sqrt is monotone, so
-// min(|V| - vmin) = sqrt(min |V|^2) - vmin exactly).  Structure records are
-// wave-uniform (scalar loads, uniform phase branches); P entries depend on the
-// lane's super slot.
-template <bool ERR>
-__device__ __forceinline__ void walk_chain(const int* __restrict__ cr, const int* __restrict__ slots,
-                                           const double2* Ps, const TargetRec* Ss, const double2* Hs,
-                                           const double* Hm, int c, uint32_t m, double2& B0, double2& B1,
-                                           double2& B2, double& el, double& qmin, double& qmax) {
-  double2 S0 = B0, S1 = B1, S2 = B2;
-  double sm0 = 0.0, sm1 = 0.0, sm2 = 0.0;
+// Walk one chain for M masks at once (one lane holds M masks; every
+// wave-uniform quantity -- chain record, slot records, targets, head
+// magnitude -- is shared by the M independent arithmetic chains): super-node
+// slots top to bottom; a reduced slot adds the voltage rise of moving its
+// aggregated current to its current super (P from LDS); a kept slot becomes
+// the super of the slots below it.  With ERR, every slot cluster's error
+// against its super's magnitude is folded into el, and the squared
+// magnitudes of kept slots into (qmin, qmax) for the band (the slack is
+// formed once per mask: sqrt is monotone, so min(|V| - vmin) =
+// sqrt(min |V|^2) - vmin exactly).  Slot r of the chain has mask bit
+// C_BIT0 + r, pairs from C_PAIR0 + r(r+1)/2 and its phases in the C_PHW
+// words, so the slot loop issues no scalar loads.  The arithmetic of each
+// mask is the same whatever M.
+template <bool ERR, int M>
+__device__ __forceinline__ void walk_chain(const int* __restrict__ cr, const double2* Ps, const TargetRec* Ss,
+                                           const double2* Hs, const double* Hm, int c, const uint32_t (&m)[M],
+                                           double2 (&B)[M][3], double (&el)[M], double (&qmin)[M],
+                                           double (&qmax)[M]) {
+  double2 S[M][3];
+  double sm[M][3];
+#pragma unroll
+  for (int i = 0; i < M; ++i)
+#pragma unroll
+    for (int p = 0; p < 3; ++p) {
+      S[i][p] = B[i][p];
+      sm[i][p] = 0.0;
+    }
   if (ERR) {
     const int hph = cr[C_PHASE];
     const double2* hv = Hs + c * 3;
     if (cr[C_OUTER] < 0) {  // head unaffected by the mask
-      if (Hm) {
-        sm0 = Hm[c * 3];
-        sm1 = Hm[c * 3 + 1];
-        sm2 = Hm[c * 3 + 2];
-      } else {
-        if (hph & 1) sm0 = hmag(hv[0]);
-        if (hph & 2) sm1 = hmag(hv[1]);
-        if (hph & 4) sm2 = hmag(hv[2]);
+#pragma unroll
+      for (int p = 0; p < 3; ++p) {
+        double h = 0.0;
+        if (Hm) h = Hm[c * 3 + p];
+        else if (hph >> p & 1) h = hmag(hv[p]);
+#pragma unroll
+        for (int i = 0; i < M; ++i) sm[i][p] = h;
       }
     } else {
-      if (hph & 1) sm0 = vmag(cadd(hv[0], B0));
-      if (hph & 2) sm1 = vmag(cadd(hv[1], B1));
-      if (hph & 4) sm2 = vmag(cadd(hv[2], B2));
+#pragma unroll
+      for (int p = 0; p < 3; ++p)
+        if (hph >> p & 1) {
+          const double2 h = hv[p];
+#pragma unroll
+          for (int i = 0; i < M; ++i) sm[i][p] = vmag(cadd(h, B[i][p]));
+        }
     }
   }
-  const int ns = cr[C_NSLOT], s0 = cr[C_SLOT0];
-  int sidx = 0;
+  const int ns = cr[C_NSLOT], s0 = cr[C_SLOT0], pair0 = cr[C_PAIR0], bit0 = cr[C_BIT0];
+  const int phw0 = cr[C_PHW0], phw1 = cr[C_PHW1], phw2 = cr[C_PHW2];
+  int sidx[M];
+#pragma unroll
+  for (int i = 0; i < M; ++i) sidx[i] = 0;
   for (int r = 0; r < ns; ++r) {
-    const int* sr = slots + (s0 + r) * kSlotInts;
-    const int bit = sr[SL_BIT], pb = sr[SL_PAIRBASE], ph = sr[SL_PHASE];
-    const bool red = (m >> bit) & 1u;
-    const double rf = red ? 1.0 : 0.0;
-    const double2* pp = Ps + (pb + sidx) * 3;
+    const int w = r < 8 ? phw0 : (r < 16 ? phw1 : phw2);
+    const int ph = (w >> (3 * (r & 7))) & 7;
+    const int prow = pair0 + ((r * (r + 1)) >> 1);
     const TargetRec* tr = Ss + (s0 + r) * 3;
-#define OKR_SLOT_PHASE(P_, S_, SM_)                                              \
-    if (ph & (1 << P_)) {                                                        \
-      const double2 pv = pp[P_];                                                 \
-      S_.x = fma(rf, pv.x, S_.x);                                                \
-      S_.y = fma(rf, pv.y, S_.y);                                                \
-      if (ERR) {                                                                 \
-        const TargetRec t = tr[P_];                                              \
-        const double vx = t.W.x + S_.x, vy = t.W.y + S_.y;                       \
-        const double q = fma(vx, vx, vy * vy);                                   \
-        if (!red) SM_ = sqrt_nr(q);                                              \
-        qmin = fmin(qmin, red ? INFINITY : q);                                   \
-        qmax = fmax(qmax, red ? -INFINITY : q);                                  \
-        el = fmax(el, fmax(SM_ - t.lo, t.hi - SM_));                             \
-      }                                                                          \
+    bool red[M];
+    double rf[M];
+    const double2* pp[M];
+#pragma unroll
+    for (int i = 0; i < M; ++i) {
+      red[i] = (m[i] >> (bit0 + r)) & 1u;
+      rf[i] = red[i] ? 1.0 : 0.0;
+      pp[i] = Ps + (prow + sidx[i]) * 3;
     }
-    OKR_SLOT_PHASE(0, S0, sm0)
-    OKR_SLOT_PHASE(1, S1, sm1)
-    OKR_SLOT_PHASE(2, S2, sm2)
-#undef OKR_SLOT_PHASE
-    sidx = red ? sidx : r + 1;
+#pragma unroll
+    for (int p = 0; p < 3; ++p) {
+      if (!(ph >> p & 1)) continue;
+      TargetRec t;
+      if (ERR) t = tr[p];
+#pragma unroll
+      for (int i = 0; i < M; ++i) {
+        const double2 pv = pp[i][p];
+        S[i][p].x = fma(rf[i], pv.x, S[i][p].x);
+        S[i][p].y = fma(rf[i], pv.y, S[i][p].y);
+        if (ERR) {
+          const double vx = t.W.x + S[i][p].x, vy = t.W.y + S[i][p].y;
+          const double q = fma(vx, vx, vy * vy);
+          if (!red[i]) sm[i][p] = sqrt_nr(q);
+          qmin[i] = fmin(qmin[i], red[i] ? INFINITY : q);
+          qmax[i] = fmax(qmax[i], red[i] ? -INFINITY : q);
+          el[i] = fmax(el[i], fmax(sm[i][p] - t.lo, t.hi - sm[i][p]));
+        }
+      }
+    }
+#pragma unroll
+    for (int i = 0; i < M; ++i) sidx[i] = red[i] ? sidx[i] : r + 1;
   }
-  B0 = S0; B1 = S1; B2 = S2;
+#pragma unroll
+  for (int i = 0; i < M; ++i)
+#pragma unroll
+    for (int p = 0; p < 3; ++p) B[i][p] = S[i][p];
 }
 
 // Band slack of a mask from the extreme squared magnitudes of its kept
@@ -130,37 +159,99 @@ __device__ __forceinline__ bool near_boundary(const MaskScore& r, double e_bar, 
   return !rin && !rout;
 }
 
-// Error of one mask for one snapshot folded into el, kept squared magnitudes
+// Per-snapshot LDS stage of the scoring kernels, in 16-byte chunks: pair
+// table, slot records (2 chunks each), chain heads, then the first kZoneLds
+// zone records (2 chunks each; later ones are read from global memory).
+constexpr int kZoneLds = 256;
+
+struct Stage {
+  int cP, cT, cH, cZ, total;
+};
+
+__device__ __forceinline__ Stage stage_sizes(const SegHdr& H) {
+  Stage z;
+  z.cP = H.npairs * 3;
+  z.cT = H.nslots * 6;
+  z.cH = H.nchains * 3;
+  z.cZ = min(H.nz, kZoneLds) * 2;
+  z.total = z.cP + z.cT + z.cH + z.cZ;
+  return z;
+}
+
+__device__ __forceinline__ uint4 stage_src(const Stage& z, int i, const uint4* __restrict__ P_l,
+                                           const uint4* __restrict__ S_l, const uint4* __restrict__ H_l,
+                                           const uint4* __restrict__ Z_l) {
+  if (i < z.cP) return P_l[i];
+  i -= z.cP;
+  if (i < z.cT) return S_l[i];
+  i -= z.cT;
+  if (i < z.cH) return H_l[i];
+  return Z_l[i - z.cH];
+}
+
+// Store chunk i; with Hm (FP64 heads) also the head magnitude (absent phases 0).
+__device__ __forceinline__ void stage_put(const Stage& z, int i, const uint4& v, uint4* Pd, uint4* Sd, uint4* Hd,
+                                          double* Hm, uint4* Zd) {
+  if (i < z.cP) {
+    Pd[i] = v;
+    return;
+  }
+  i -= z.cP;
+  if (i < z.cT) {
+    Sd[i] = v;
+    return;
+  }
+  i -= z.cT;
+  if (i < z.cH) {
+    Hd[i] = v;
+    if (Hm) {
+      const double2 hv = make_double2(__hiloint2double((int)v.y, (int)v.x), __hiloint2double((int)v.w, (int)v.z));
+      Hm[i] = (hv.x != 0.0 || hv.y != 0.0) ? hmag(hv) : 0.0;
+    }
+    return;
+  }
+  Zd[i - z.cH] = v;
+}
+
+// Error of M masks for one snapshot folded into el, kept squared magnitudes
 // into (qmin, qmax): every chain walked with its nesting path recomputed, then
-// the zone entries anchored below it.
+// the zone entries anchored below it (the first zcap of them from the LDS
+// stage Zs when STAGED, the rest from global memory).
+template <bool STAGED, int M>
 __device__ __forceinline__ void score_snapshot(const SegHdr& H, const int* __restrict__ chains,
-                                               const int* __restrict__ slots, const int* __restrict__ nest,
-                                               const double2* Ps, const TargetRec* Ss, const double2* Hs,
-                                               const double* Hm, const TargetRec* __restrict__ zrec_l, uint32_t m,
-                                               double& el, double& qmin, double& qmax) {
+                                               const int* __restrict__ nest, const double2* Ps, const TargetRec* Ss,
+                                               const double2* Hs, const double* Hm, const TargetRec* Zs, int zcap,
+                                               const TargetRec* __restrict__ zrec_l, const uint32_t (&m)[M],
+                                               double (&el)[M], double (&qmin)[M], double (&qmax)[M]) {
   for (int c = 0; c < H.nchains; ++c) {
     const int* cr = chains + c * kChainInts;
-    double2 B0 = make_double2(0.0, 0.0), B1 = B0, B2 = B0;
+    double2 B[M][3];
+#pragma unroll
+    for (int i = 0; i < M; ++i)
+#pragma unroll
+      for (int p = 0; p < 3; ++p) B[i][p] = make_double2(0.0, 0.0);
     const int nl = cr[C_NEST_LEN], no = cr[C_NEST_OFF];
     for (int q = 0; q + 1 < nl; ++q) {
       const int oc = nest[no + q];
-      walk_chain<false>(chains + oc * kChainInts, slots, Ps, Ss, Hs, Hm, oc, m, B0, B1, B2, el, qmin, qmax);
+      walk_chain<false, M>(chains + oc * kChainInts, Ps, Ss, Hs, Hm, oc, m, B, el, qmin, qmax);
     }
-    walk_chain<true>(cr, slots, Ps, Ss, Hs, Hm, c, m, B0, B1, B2, el, qmin, qmax);
-#define OKR_ZONE_PHASE(P_, B_)                                                   \
-    for (int q = cr[C_ZOFF0 + P_], qe = q + cr[C_ZCNT0 + P_]; q < qe; ++q) {   \
-      const TargetRec t = zrec_l[q];                                             \
-      const double vx = t.W.x + B_.x, vy = t.W.y + B_.y;                         \
-      const double q2 = fma(vx, vx, vy * vy);                                    \
-      const double mag = sqrt_nr(q2);                                            \
-      el = fmax(el, fmax(mag - t.lo, t.hi - mag));                               \
-      qmin = fmin(qmin, q2);                                                     \
-      qmax = fmax(qmax, q2);                                                     \
-    }
-    OKR_ZONE_PHASE(0, B0)
-    OKR_ZONE_PHASE(1, B1)
-    OKR_ZONE_PHASE(2, B2)
-#undef OKR_ZONE_PHASE
+    walk_chain<true, M>(cr, Ps, Ss, Hs, Hm, c, m, B, el, qmin, qmax);
+#pragma unroll
+    for (int p = 0; p < 3; ++p)
+      for (int q = cr[C_ZOFF0 + p], qe = q + cr[C_ZCNT0 + p]; q < qe; ++q) {
+        TargetRec t;
+        if (STAGED && q < zcap) t = Zs[q];
+        else t = zrec_l[q];
+#pragma unroll
+        for (int i = 0; i < M; ++i) {
+          const double vx = t.W.x + B[i][p].x, vy = t.W.y + B[i][p].y;
+          const double q2 = fma(vx, vx, vy * vy);
+          const double mag = sqrt_nr(q2);
+          el[i] = fmax(el[i], fmax(mag - t.lo, t.hi - mag));
+          qmin[i] = fmin(qmin[i], q2);
+          qmax[i] = fmax(qmax[i], q2);
+        }
+      }
   }
 }
 

@@ -25,10 +25,12 @@ __global__ void k_powerflow(int, const int*, const uint8_t*, const int*, const i
 __global__ void k_from_vhat(int, int, const uint8_t*, const double2*, const double2*, double, double, double2*,
                             double*, int*);
 __global__ void k_build_struct(Topo, State, int, int, SegHdr*, int*, int, int*);
+__global__ void k_zroot(int, const int*, const int*, const int*, int, const double2*, double2*);
 __global__ void k_build_values(const SegHdr*, int, const int*, int, const double2*, const double2*, const double2*,
                                double2*, TargetRec*, double2*, TargetRec*, double*);
 __global__ void k_build_members(const SegHdr*, int, const int*, Topo, State, const double2*, const double*,
                                 TargetRec*, TargetRec*, double*);
+template <int M>
 __global__ void k_score_fp64(const SegHdr*, int, const int*, const double2*, const TargetRec*, const double2*,
                              const TargetRec*, const double*, int, int, SelParams, MaskScore*, MaskScore*, TileRec*,
                              int*, const int*);
@@ -96,10 +98,11 @@ constexpr int kRefineBlocks = 256;
 
 size_t align256(size_t x) { return (x + 255) & ~size_t(255); }
 
-// Snapshot groups of a scoring launch: enough blocks to fill the chip (about
-// 8192 waves), each group a contiguous run of snapshots.
-int snap_groups_default(int k, int S, int* spg) {
-  const int mblocks = (int)((((uint64_t)1 << k) + kScoreThreads - 1) / kScoreThreads);
+// Snapshot groups of a scoring launch with mpl masks per lane: enough blocks
+// to fill the chip (about 2048 blocks of 4 waves), each group a contiguous
+// run of snapshots.
+int snap_groups_default(int k, int S, int* spg, int mpl = 1) {
+  const int mblocks = (int)((((uint64_t)1 << k) + kScoreThreads * mpl - 1) / (kScoreThreads * mpl));
   int SG = std::min(S, std::max(1, 2048 / mblocks));
   SG = std::min(SG, kMaxSnapGroups);
   *spg = (S + SG - 1) / SG;
@@ -107,7 +110,7 @@ int snap_groups_default(int k, int S, int* spg) {
 }
 
 struct Layout {
-  size_t topo, z, Vhat, Vcur, A, J, absV, kept, sup, slot_of, zent_of, status, iters, hdrs, decs, tab, P, srec,
+  size_t topo, z, Zroot, Vhat, Vcur, A, J, absV, kept, sup, slot_of, zent_of, status, iters, hdrs, decs, tab, P, srec,
       headV, zrec, econst, part, fin, tiles, tickets, kp, yeq, Ykd, Yko, err;
   // mixed precision
   size_t P32, S32, H32, Z32, part32, fin32, tiles32, listA, listB, scoreA, scoreB, counts, mstate;
@@ -144,22 +147,31 @@ struct okr_handle {
   // per-mask score dumps (FP64 scores, or FP32 screening scores in MIXED)
   std::vector<std::vector<MaskScore>> dump;
   std::vector<std::vector<MaskScore32>> dump32;
-  // snapshot groups of the scoring launches: autotuned per segment size
-  // (0 = the default rule), a value forced while tuning, and the partial
-  // score capacity (masks x groups) the workspace was planned with
-  std::vector<int> sg_tuned;
-  int sg_force = 0;
+  // shape of the FP64 scoring launches, autotuned per segment size (0 = the
+  // default rule): snapshot groups and masks per lane; values forced while
+  // tuning; the partial-score capacity (masks x groups) of the workspace
+  std::vector<int> sg_tuned, mpl_tuned;
+  int sg_force = 0, mpl_force = 0;
   size_t part_cap = 0;
 };
 
 namespace {
-// Snapshot groups of the scoring launch for a segment of k nodes: the forced
-// or tuned count, else the default rule, within the planned partial-score
-// capacity; spg = snapshots per group.
+constexpr int kDefaultMpl = 2;
+
+// Masks per lane of the FP64 scoring launch for a segment of k nodes.
+int score_mpl(const okr_handle* h, int k) {
+  if (h->mpl_force) return h->mpl_force;
+  if ((int)h->mpl_tuned.size() > k && h->mpl_tuned[k]) return h->mpl_tuned[k];
+  return kDefaultMpl;
+}
+
+// Snapshot groups of the FP64 scoring launch for a segment of k nodes: the
+// forced or tuned count, else the default rule, within the planned
+// partial-score capacity; spg = snapshots per group.
 int snap_groups(const okr_handle* h, int k, int* spg) {
   const int S = h->S;
   int SG = h->sg_force ? h->sg_force : ((int)h->sg_tuned.size() > k && h->sg_tuned[k] ? h->sg_tuned[k] : 0);
-  if (SG <= 0) return snap_groups_default(k, S, spg);
+  if (SG <= 0) SG = snap_groups_default(k, S, spg, score_mpl(h, k));
   SG = std::min(std::min(SG, S), kMaxSnapGroups);
   while (SG > 1 && ((size_t)SG << k) > h->part_cap) --SG;
   *spg = (S + SG - 1) / SG;
@@ -346,6 +358,7 @@ extern "C" int okr_plan(okr_handle* h, const okr_topology* topo, const okr_margi
   };
   L.topo = take(sizeof(int) * TO.total);
   L.z = take(sizeof(double2) * 9 * n);
+  L.Zroot = take(sizeof(double2) * 9 * n);
   L.Vhat = take(sizeof(double2) * c3);
   L.Vcur = take(sizeof(double2) * c3);
   L.A = take(sizeof(double2) * c3);
@@ -366,14 +379,20 @@ extern "C" int okr_plan(okr_handle* h, const okr_topology* topo, const okr_margi
   L.zrec = take(sizeof(TargetRec) * (size_t)S * 3 * n);
   L.econst = take(sizeof(double) * S);
   {
-    size_t most = 1;
-    for (int k = 1; k <= h->kmax; ++k) {
-      int spg;
-      most = std::max(most, (size_t)snap_groups_default(k, S, &spg) << k);
-    }
+    // partial scores: every default shape, and room to tune up to 32 groups
+    // for segments of up to 16 nodes
+    size_t most = (size_t)std::min(S, kMaxSnapGroups) << std::min(h->kmax, 16);
+    for (int k = 1; k <= h->kmax; ++k)
+      for (int mpl = 1; mpl <= 4; mpl *= 2) {
+        int spg;
+        most = std::max(most, (size_t)snap_groups_default(k, S, &spg, mpl) << k);
+      }
     L.part = take(sizeof(MaskScore) * most);
     h->part_cap = most;
-    if ((int)h->sg_tuned.size() != h->kmax + 1) h->sg_tuned.assign(h->kmax + 1, 0);  // tuning survives a re-plan
+    if ((int)h->sg_tuned.size() != h->kmax + 1) {  // tuning survives a re-plan of the same sizes
+      h->sg_tuned.assign(h->kmax + 1, 0);
+      h->mpl_tuned.assign(h->kmax + 1, 0);
+    }
     const size_t nm = (size_t)1 << h->kmax, nt = (nm + 63) / 64;
     L.fin = take(sizeof(MaskScore) * nm);
     L.tiles = take(sizeof(TileRec) * nt);
@@ -444,7 +463,7 @@ struct Ptrs {
   Topo T;
   State St;
   const int *lvl_off, *lvl_nodes;
-  double2 *z, *Vhat, *Vcur, *A, *J, *P, *headV, *yeq, *Ykd, *Yko;
+  double2 *z, *Zroot, *Vhat, *Vcur, *A, *J, *P, *headV, *yeq, *Ykd, *Yko;
   double *absV, *econst, *err;
   int *status, *iters, *tab, *tickets, *kp;
   SegHdr* hdrs;
@@ -494,6 +513,7 @@ Ptrs pointers(okr_handle* h, void* d_workspace) {
   p.St.slot_of = (int*)at(L.slot_of);
   p.St.zent_of = (int*)at(L.zent_of);
   p.z = (double2*)at(L.z);
+  p.Zroot = (double2*)at(L.Zroot);
   p.Vhat = (double2*)at(L.Vhat);
   p.Vcur = (double2*)at(L.Vcur);
   p.A = (double2*)at(L.A);
@@ -566,6 +586,8 @@ void enqueue_search(okr_handle* h, const Ptrs& p, const okr_yblocks* Y, const ok
                      p.tickets, ntick);
   hipLaunchKernelGGL(k_branch_z, dim3((n + 127) / 128), dim3(128), 0, st, n, p.T.parent, p.T.phase, p.T.ch_off,
                      p.T.ch, (const double2*)Y->Y_diag, (const double2*)Y->Y_off, p.z, p.status);
+  hipLaunchKernelGGL(k_zroot, dim3(1), dim3(256), 0, st, n, p.T.parent, p.lvl_off, p.lvl_nodes, h->nlev,
+                     (const double2*)p.z, p.Zroot);
   const size_t c3 = (size_t)S * n * 3;
   if (vhat_given) {
     hipLaunchKernelGGL(k_copy2, dim3(1024), dim3(256), 0, st, (const double2*)loads->Vhat, p.Vhat, c3);
@@ -599,19 +621,24 @@ void enqueue_search(okr_handle* h, const Ptrs& p, const okr_yblocks* Y, const ok
     hipLaunchKernelGGL(k_build_struct, dim3(1), dim3(256), 0, st, p.T, p.St, g, S, p.hdrs, p.tab, h->tab_cap,
                        p.status);
     hipLaunchKernelGGL(k_build_values, dim3(256, 5), dim3(256), 0, st, (const SegHdr*)p.hdrs, g, (const int*)p.tab,
-                       n, (const double2*)p.z, (const double2*)p.Vcur, (const double2*)p.A, p.P, p.srec, p.headV,
+                       n, (const double2*)p.Zroot, (const double2*)p.Vcur, (const double2*)p.A, p.P, p.srec, p.headV,
                        p.zrec, p.econst);
     hipLaunchKernelGGL(k_build_members, dim3(members_blocks), dim3(256), 0, st, (const SegHdr*)p.hdrs, g,
                        (const int*)p.tab, p.T, p.St, (const double2*)p.Vcur, (const double*)p.absV, p.srec, p.zrec,
                        p.econst);
     const uint32_t nmask = 1u << k;
-    const int mblocks = (int)((nmask + kScoreThreads - 1) / kScoreThreads);
+    const int mpl = score_mpl(h, k);
+    const int mblocks = (int)((nmask + kScoreThreads * mpl - 1) / (kScoreThreads * mpl));
     int spg;
     const int SG = snap_groups(h, k, &spg);
+    // the FP32 screen keeps one mask per lane and the default group rule
+    const int mblocks32 = (int)((nmask + kScoreThreads - 1) / kScoreThreads);
+    int spg32;
+    const int SG32 = snap_groups_default(k, S, &spg32);
     const int* gate = nullptr;
     if (surr || feat_out) {
-      hipLaunchKernelGGL(k_surr_tables, dim3((kMaxPairs + kMaxK + 127) / 128), dim3(128), 0, st,
-                         (const SegHdr*)p.hdrs, g, (const int*)p.tab, n, (const double2*)p.z, (const double2*)p.P,
+      hipLaunchKernelGGL(k_surr_tables, dim3(kMaxPairs + kMaxK), dim3(64), 0, st,
+                         (const SegHdr*)p.hdrs, g, (const int*)p.tab, n, (const double2*)p.Zroot, (const double2*)p.P,
                          (const double2*)p.A, (const TargetRec*)p.srec, p.spz, p.szs, p.sss);
     }
     if (surr) {
@@ -680,10 +707,15 @@ void enqueue_search(okr_handle* h, const Ptrs& p, const okr_yblocks* Y, const ok
     }
     if (!mixed) {
       if (ev) (void)hipEventRecord((*ev)[2 * g], st);
-      hipLaunchKernelGGL(k_score_fp64, dim3(mblocks, SG), dim3(kScoreThreads), 0, st, (const SegHdr*)p.hdrs, g,
-                         (const int*)p.tab, (const double2*)p.P, (const TargetRec*)p.srec, (const double2*)p.headV,
-                         (const TargetRec*)p.zrec, (const double*)p.econst, spg, SG, sp, p.part, p.fin, p.tiles,
-                         p.tickets, gate);
+#define OKR_SCORE64(M_)                                                                                      \
+  hipLaunchKernelGGL(k_score_fp64<M_>, dim3(mblocks, SG), dim3(kScoreThreads), 0, st, (const SegHdr*)p.hdrs, g, \
+                     (const int*)p.tab, (const double2*)p.P, (const TargetRec*)p.srec, (const double2*)p.headV, \
+                     (const TargetRec*)p.zrec, (const double*)p.econst, spg, SG, sp, p.part, p.fin, p.tiles,   \
+                     p.tickets, gate)
+      if (mpl == 4) OKR_SCORE64(4);
+      else if (mpl == 2) OKR_SCORE64(2);
+      else OKR_SCORE64(1);
+#undef OKR_SCORE64
       if (ev) (void)hipEventRecord((*ev)[2 * g + 1], st);
       hipLaunchKernelGGL(k_argmin, dim3(1), dim3(1024), 0, st, (const SegHdr*)p.hdrs, g, (const MaskScore*)p.fin,
                          (const TileRec*)p.tiles, sp, (const int*)p.status, p.decs, gate);
@@ -707,9 +739,9 @@ void enqueue_search(okr_handle* h, const Ptrs& p, const okr_yblocks* Y, const ok
                          (const double2*)p.headV, (const TargetRec*)p.zrec, mg->v_min, mg->v_max, p.P32, p.S32,
                          p.H32, p.Z32);
       if (ev) (void)hipEventRecord((*ev)[2 * g], st);
-      hipLaunchKernelGGL(k_score_fp32, dim3(mblocks, SG), dim3(kScoreThreads), 0, st, (const SegHdr*)p.hdrs, g,
+      hipLaunchKernelGGL(k_score_fp32, dim3(mblocks32, SG32), dim3(kScoreThreads), 0, st, (const SegHdr*)p.hdrs, g,
                          (const int*)p.tab, (const Pair32*)p.P32, (const Rec32*)p.S32, (const Head32*)p.H32,
-                         (const Rec32*)p.Z32, (const double*)p.econst, spg, SG, sp, p.part32, p.fin32, p.tiles32,
+                         (const Rec32*)p.Z32, (const double*)p.econst, spg32, SG32, sp, p.part32, p.fin32, p.tiles32,
                          p.tickets);
       if (ev) (void)hipEventRecord((*ev)[2 * g + 1], st);
       int* cA = p.counts;
@@ -806,30 +838,48 @@ extern "C" int okr_reduce_feeder(okr_handle* h, const okr_yblocks* Y, const okr_
       h->ev.resize(2 * std::max(nseg, 1), nullptr);
       for (auto& e : h->ev) OKR_HIP(h, hipEventCreate(&e));
     }
-    std::vector<std::vector<double>> tsum(h->kmax + 1, std::vector<double>(kMaxSnapGroups + 1, 0.0));
-    for (int c = 1; c <= std::min(S, kMaxSnapGroups); c *= 2) {
-      h->sg_force = c;
-      enqueue_search(h, p, Y, loads, mg, st, &h->ev, nullptr, nullptr, nullptr, nullptr);
-      const hipError_t e1 = hipGetLastError(), e2 = hipStreamSynchronize(st);
-      h->sg_force = 0;
-      if (e1 != hipSuccess || e2 != hipSuccess)
-        OKR_FAIL(h, OKR_E_HIP, "autotune run failed: %s", hipGetErrorString(e1 != hipSuccess ? e1 : e2));
-      for (int g = 0; g < nseg; ++g) {
-        const int k = h->seg_off[g + 1] - h->seg_off[g];
+    // (the FP64 scoring kernel is tuned whatever the call's precision)
+    okr_margins mt = *mg;
+    mt.precision = OKR_PRECISION_FP64;
+    mt.top_k = 0;
+    mt.surrogate = nullptr;
+    // tsum[k][mpl index][groups]
+    std::vector<double> tsum((size_t)(h->kmax + 1) * 3 * (kMaxSnapGroups + 1), 0.0);
+    auto T_ = [&](int k, int mi, int c) -> double& { return tsum[((size_t)k * 3 + mi) * (kMaxSnapGroups + 1) + c]; };
+    for (int mi = 0; mi < 3; ++mi)
+      for (int c = 1; c <= std::min(S, kMaxSnapGroups); c *= 2) {
         h->sg_force = c;
-        int spg;
-        const int used = snap_groups(h, k, &spg);
-        h->sg_force = 0;
-        float ms = 0.f;
-        OKR_HIP(h, hipEventElapsedTime(&ms, h->ev[2 * g], h->ev[2 * g + 1]));
-        if (used == c) tsum[k][c] += ms;
+        h->mpl_force = 1 << mi;
+        enqueue_search(h, p, Y, loads, &mt, st, &h->ev, nullptr, nullptr, nullptr, nullptr);
+        const hipError_t e1 = hipGetLastError(), e2 = hipStreamSynchronize(st);
+        if (e1 != hipSuccess || e2 != hipSuccess) {
+          h->sg_force = h->mpl_force = 0;
+          OKR_FAIL(h, OKR_E_HIP, "autotune run failed: %s", hipGetErrorString(e1 != hipSuccess ? e1 : e2));
+        }
+        for (int g = 0; g < nseg; ++g) {
+          const int k = h->seg_off[g + 1] - h->seg_off[g];
+          int spg;
+          const int used = snap_groups(h, k, &spg);
+          float ms = 0.f;
+          const hipError_t ee = hipEventElapsedTime(&ms, h->ev[2 * g], h->ev[2 * g + 1]);
+          if (ee != hipSuccess) {
+            h->sg_force = h->mpl_force = 0;
+            OKR_FAIL(h, OKR_E_HIP, "autotune timing failed: %s", hipGetErrorString(ee));
+          }
+          if (used == c) T_(k, mi, c) += ms;
+        }
+        h->sg_force = h->mpl_force = 0;
       }
-    }
     for (int k = 1; k <= h->kmax; ++k) {
-      int best = 0;
-      for (int c = 1; c <= kMaxSnapGroups; c *= 2)
-        if (tsum[k][c] > 0.0 && (best == 0 || tsum[k][c] < tsum[k][best])) best = c;
-      h->sg_tuned[k] = best;
+      int bc = 0, bm = 0;
+      for (int mi = 0; mi < 3; ++mi)
+        for (int c = 1; c <= kMaxSnapGroups; c *= 2)
+          if (T_(k, mi, c) > 0.0 && (bc == 0 || T_(k, mi, c) < T_(k, bm, bc))) {
+            bc = c;
+            bm = mi;
+          }
+      h->sg_tuned[k] = bc;
+      h->mpl_tuned[k] = bc ? 1 << bm : 0;
     }
     drop_graph(h);  // a captured search used the earlier group counts
   }

@@ -26,7 +26,6 @@ struct SegHdr {
   int nomega;     // nodes in Omega_g
   int o_chain;    // [nchains][kChainInts]
   int o_nest;     // nesting paths, outermost first, ending with the chain itself
-  int o_path;     // chain node paths, top to bottom
   int o_slot;     // [nslots][kSlotInts]
   int o_pair;     // [npairs][kPairInts]
   int o_range;    // [nrange][3]: preorder start, end, cumulative node count
@@ -58,13 +57,17 @@ struct State {
 };
 
 // chain record
-enum { C_HEAD = 0, C_NSLOT, C_SLOT0, C_NEST_OFF, C_NEST_LEN, C_PATH_OFF, C_PATH_LEN,
-       C_ZOFF0, C_ZOFF1, C_ZOFF2, C_ZCNT0, C_ZCNT1, C_ZCNT2, C_OUTER, C_PHASE, kChainInts };
+enum { C_HEAD = 0, C_NSLOT, C_SLOT0, C_NEST_OFF, C_NEST_LEN,
+       C_ZOFF0, C_ZOFF1, C_ZOFF2, C_ZCNT0, C_ZCNT1, C_ZCNT2, C_OUTER, C_PHASE,
+       C_BIT0,   // mask bit of the first slot; slot r has bit C_BIT0 + r
+       C_PAIR0,  // first pair of the chain; slot r's pairs start at C_PAIR0 + r(r+1)/2
+       C_PHW0, C_PHW1, C_PHW2,  // phase masks of slots 8w..8w+7, 3 bits each
+       kChainInts };
 // slot record
-enum { SL_NODE = 0, SL_BIT, SL_PHASE, SL_PAIRBASE, SL_PATHPOS, SL_CHAIN, kSlotInts };
-// pair record: reduced slot node, first and last path index summed, chain path
-// offset, the super-node of the pair and the reduced slot's index
-enum { PR_RNODE = 0, PR_FROM, PR_TO, PR_PATHOFF, PR_SUPER, PR_RSLOT, kPairInts };
+enum { SL_NODE = 0, SL_BIT, SL_PHASE, SL_PAIRBASE, SL_CHAIN, kSlotInts };
+// pair record: reduced slot node, its super-node for this pair, and the
+// reduced slot's index
+enum { PR_RNODE = 0, PR_SUPER, PR_RSLOT, kPairInts };
 
 // Per-slot and per-zone-entry numeric data for one snapshot and phase.
 struct TargetRec {

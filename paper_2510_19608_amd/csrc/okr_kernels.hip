@@ -197,6 +197,26 @@ __global__ __launch_bounds__(256) void k_powerflow(
   }
 }
 
+// Cumulative series impedance from the root, Zroot(v) = Zroot(parent) + z(v)
+// (3x3 blocks, zero on absent phases), level by level; the impedance of the
+// path between an ancestor s and r is Zroot(r) - Zroot(s).  One block.
+__global__ __launch_bounds__(256) void k_zroot(int n, const int* __restrict__ parent,
+                                               const int* __restrict__ lvl_off, const int* __restrict__ lvl_nodes,
+                                               int nlev, const double2* __restrict__ z, double2* __restrict__ Zroot) {
+  for (int e = threadIdx.x; e < 9; e += blockDim.x) Zroot[e] = make_double2(0.0, 0.0);  // node 0, level 0
+  __syncthreads();
+  for (int L = 1; L < nlev; ++L) {
+    const int a = lvl_off[L], b = lvl_off[L + 1];
+    for (int t = a * 9 + threadIdx.x; t < b * 9; t += blockDim.x) {
+      const int v = lvl_nodes[t / 9], e = t % 9;
+      const double2 up = Zroot[(size_t)parent[v] * 9 + e], zv = z[(size_t)v * 9 + e];
+      Zroot[(size_t)v * 9 + e] = make_double2(up.x + zv.x, up.y + zv.y);
+    }
+    __threadfence_block();
+    __syncthreads();
+  }
+}
+
 // Given V^ (caller supplied): load currents and magnitudes, band check.
 __global__ void k_from_vhat(int n, int S, const uint8_t* __restrict__ phase, const double2* __restrict__ Sload,
                             const double2* __restrict__ V, double vmin, double vmax, double2* __restrict__ A,

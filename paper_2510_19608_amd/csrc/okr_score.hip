@@ -12,12 +12,15 @@
 namespace okr {
 
 // ---------------------------------------------------------------- scoring --
-// One lane scores one mask over the block's snapshot group: e = max error
-// over the affected nodes, slack = min band slack over their kept node-phases.
-// A block is 4 waves (256 masks) sharing the snapshot's LDS stage: the pair
-// table P, the slot targets and the chain heads.  The last block of a
-// 256-mask range to finish (ticket counter) folds the snapshot groups into
-// the final per-mask score and writes one tile record per wave.
+// Every mask of a segment over the block's snapshot group: e = max error over
+// the affected nodes, slack = min band slack over their kept node-phases.  A
+// block is 4 waves; a lane holds M masks (mask i of the lane is
+// blockIdx.x * 256M + 256 i + tid, so each wave covers 64 consecutive masks
+// per i) and the 4 waves share the snapshot's LDS stage (pair table, slot
+// targets, chain heads and their magnitudes, zone targets).  The last block
+// of a 256M-mask range to finish (ticket counter) folds the snapshot groups
+// into the final per-mask score and writes the 64-mask tile records.
+template <int M>
 __global__ __launch_bounds__(kScoreThreads) void k_score_fp64(
     const SegHdr* __restrict__ hdrs, int g, const int* __restrict__ tab, const double2* __restrict__ P,
     const TargetRec* __restrict__ srec, const double2* __restrict__ headV,
@@ -28,79 +31,106 @@ __global__ __launch_bounds__(kScoreThreads) void k_score_fp64(
   __shared__ TargetRec Ts[kMaxK * 3];
   __shared__ double2 Hv[kMaxK * 3];
   __shared__ double Hm[kMaxK * 3];
+  __shared__ TargetRec Zs[kZoneLds];
+  __shared__ double s_ec;
   __shared__ int ticket;
   const SegHdr H = hdrs[g];
   if (!H.valid || (gate && *gate == 0)) return;
   const int tid = threadIdx.x;
-  const uint32_t m = blockIdx.x * kScoreThreads + tid;
+  uint32_t m[M];
+#pragma unroll
+  for (int i = 0; i < M; ++i) m[i] = blockIdx.x * (kScoreThreads * M) + i * kScoreThreads + tid;
   const int sg = blockIdx.y;
   const int l0 = sg * snaps_per_group;
   const int l1 = min(H.S, l0 + snaps_per_group);
   const int* chains = tab + H.o_chain;
-  const int* slots = tab + H.o_slot;
   const int* nest = tab + H.o_nest;
-  double e = 0.0, qmin = INFINITY, qmax = -INFINITY;
+  const Stage z = stage_sizes(H);
+  double e[M], qmin[M], qmax[M];
+#pragma unroll
+  for (int i = 0; i < M; ++i) {
+    e[i] = 0.0;
+    qmin[i] = INFINITY;
+    qmax[i] = -INFINITY;
+  }
   for (int l = l0; l < l1; ++l) {
-    const double2* Pl = P + (size_t)l * H.npairs * 3;
-    for (int q = tid; q < H.npairs * 3; q += kScoreThreads) Ps[q] = Pl[q];
-    const TargetRec* Sl = srec + (size_t)l * H.nslots * 3;
-    for (int q = tid; q < H.nslots * 3; q += kScoreThreads) Ts[q] = Sl[q];
-    const double2* Hl = headV + (size_t)l * H.nchains * 3;
-    for (int q = tid; q < H.nchains * 3; q += kScoreThreads) {
-      const double2 hv = Hl[q];
-      Hv[q] = hv;
-      Hm[q] = (hv.x != 0.0 || hv.y != 0.0) ? hmag(hv) : 0.0;  // absent phases stay 0
-    }
+    const uint4* P_l = (const uint4*)(P + (size_t)l * H.npairs * 3);
+    const uint4* S_l = (const uint4*)(srec + (size_t)l * H.nslots * 3);
+    const uint4* H_l = (const uint4*)(headV + (size_t)l * H.nchains * 3);
+    const uint4* Z_l = (const uint4*)(zrec + (size_t)l * H.nz);
+    for (int i = tid; i < z.total; i += kScoreThreads)
+      stage_put(z, i, stage_src(z, i, P_l, S_l, H_l, Z_l), (uint4*)Ps, (uint4*)Ts, (uint4*)Hv, Hm, (uint4*)Zs);
+    if (tid == 0) s_ec = econst[l];
     __syncthreads();
-    double el = econst[l];
-    score_snapshot(H, chains, slots, nest, Ps, Ts, Hv, Hm, zrec + (size_t)l * H.nz, m, el, qmin, qmax);
-    e = fmax(e, el);
+    double el[M];
+    const double ec = s_ec;
+#pragma unroll
+    for (int i = 0; i < M; ++i) el[i] = ec;
+    score_snapshot<true, M>(H, chains, nest, Ps, Ts, Hv, Hm, Zs, kZoneLds, zrec + (size_t)l * H.nz, m, el, qmin,
+                            qmax);
+#pragma unroll
+    for (int i = 0; i < M; ++i) e[i] = fmax(e[i], el[i]);
     __syncthreads();
   }
   const uint32_t nmask = 1u << H.k;
-  const bool valid = m < nmask;
-  if (valid) {
-    MaskScore r;
-    r.e = e;
-    r.slack = band_slack(qmin, qmax, sp.vmin, sp.vmax);
-    part[(size_t)sg * nmask + m] = r;
-  }
+#pragma unroll
+  for (int i = 0; i < M; ++i)
+    if (m[i] < nmask) {
+      MaskScore r;
+      r.e = e[i];
+      r.slack = band_slack(qmin[i], qmax[i], sp.vmin, sp.vmax);
+      part[(size_t)sg * nmask + m[i]] = r;
+    }
   __threadfence();
   if (tid == 0) ticket = atomicAdd(&tickets[blockIdx.x], 1);
   __syncthreads();
   if (ticket != SG - 1) return;
   // last block of this mask range: combine the snapshot groups
-  MaskScore r;
-  r.e = 0.0;
-  r.slack = INFINITY;
-  if (valid) {
-    for (int q = 0; q < SG; ++q) {
-      const volatile MaskScore* x = part + (size_t)q * nmask + m;
-      r.e = fmax(r.e, x->e);
-      r.slack = fmin(r.slack, x->slack);
+#pragma unroll
+  for (int i = 0; i < M; ++i) {
+    const bool valid = m[i] < nmask;
+    MaskScore r;
+    r.e = 0.0;
+    r.slack = INFINITY;
+    if (valid) {
+      for (int q = 0; q < SG; ++q) {
+        const volatile MaskScore* x = part + (size_t)q * nmask + m[i];
+        r.e = fmax(r.e, x->e);
+        r.slack = fmin(r.slack, x->slack);
+      }
+      fin[m[i]] = r;
     }
-    fin[m] = r;
-  }
-  const int pc = __popc(m);
-  const bool feas = valid && feasible(r, sp.e_bar);
-  int best = feas ? pc : -1;
-  int nearl = (valid && near_boundary(r, sp.e_bar, sp.amb)) ? pc : -1;
-  for (int o = 32; o > 0; o >>= 1) {
-    best = max(best, __shfl_xor(best, o, 64));
-    nearl = max(nearl, __shfl_xor(nearl, o, 64));
-  }
-  double em = (feas && pc == best) ? r.e : INFINITY;
-  for (int o = 32; o > 0; o >>= 1) em = fmin(em, __shfl_xor(em, o, 64));
-  const uint32_t tile = m / kScoreBlock;
-  if ((tid & 63) == 0 && tile * kScoreBlock < nmask) {
-    TileRec t;
-    t.best = best;
-    t.near = nearl;
-    t.emin = em;
-    tiles[tile] = t;
+    const int pc = __popc(m[i]);
+    const bool feas = valid && feasible(r, sp.e_bar);
+    int best = feas ? pc : -1;
+    int nearl = (valid && near_boundary(r, sp.e_bar, sp.amb)) ? pc : -1;
+    for (int o = 32; o > 0; o >>= 1) {
+      best = max(best, __shfl_xor(best, o, 64));
+      nearl = max(nearl, __shfl_xor(nearl, o, 64));
+    }
+    double em = (feas && pc == best) ? r.e : INFINITY;
+    for (int o = 32; o > 0; o >>= 1) em = fmin(em, __shfl_xor(em, o, 64));
+    const uint32_t tile = m[i] / kScoreBlock;
+    if ((tid & 63) == 0 && tile * kScoreBlock < nmask) {
+      TileRec t;
+      t.best = best;
+      t.near = nearl;
+      t.emin = em;
+      tiles[tile] = t;
+    }
   }
   if (tid == 0) tickets[blockIdx.x] = 0;  // ready for the next launch
 }
+
+template __global__ void k_score_fp64<1>(const SegHdr*, int, const int*, const double2*, const TargetRec*,
+                                         const double2*, const TargetRec*, const double*, int, int, SelParams,
+                                         MaskScore*, MaskScore*, TileRec*, int*, const int*);
+template __global__ void k_score_fp64<2>(const SegHdr*, int, const int*, const double2*, const TargetRec*,
+                                         const double2*, const TargetRec*, const double*, int, int, SelParams,
+                                         MaskScore*, MaskScore*, TileRec*, int*, const int*);
+template __global__ void k_score_fp64<4>(const SegHdr*, int, const int*, const double2*, const TargetRec*,
+                                         const double2*, const TargetRec*, const double*, int, int, SelParams,
+                                         MaskScore*, MaskScore*, TileRec*, int*, const int*);
 
 // FP64 scores of the masks in `list` (all snapshots), with the arithmetic of
 // the FP64 scoring kernel: one wave per mask, its lanes over the snapshots
@@ -123,11 +153,14 @@ __global__ __launch_bounds__(kScoreBlock) void k_refine_fp64(
     const uint32_t m = list[idx];
     double e = 0.0, qmin = INFINITY, qmax = -INFINITY;
     for (int l = lane; l < H.S; l += kScoreBlock) {
-      double el = econst[l];
-      score_snapshot(H, chains, slots, nest, P + (size_t)l * H.npairs * 3, srec + (size_t)l * H.nslots * 3,
-                     headV + (size_t)l * H.nchains * 3, (const double*)nullptr, zrec + (size_t)l * H.nz, m, el,
-                     qmin, qmax);
-      e = fmax(e, el);
+      double el[1] = {econst[l]}, qn[1] = {qmin}, qx[1] = {qmax};
+      const uint32_t mm[1] = {m};
+      score_snapshot<false, 1>(H, chains, nest, P + (size_t)l * H.npairs * 3, srec + (size_t)l * H.nslots * 3,
+                               headV + (size_t)l * H.nchains * 3, (const double*)nullptr, (const TargetRec*)nullptr,
+                               0, zrec + (size_t)l * H.nz, mm, el, qn, qx);
+      qmin = qn[0];
+      qmax = qx[0];
+      e = fmax(e, el[0]);
     }
     for (int o = 32; o > 0; o >>= 1) {
       e = fmax(e, __shfl_xor(e, o, 64));
@@ -167,14 +200,16 @@ __device__ __forceinline__ void walk32(const int* __restrict__ cr, const int* __
     if (hph & 2) d1 = diff32(hv[1].W, hv[1].w, B1);
     if (hph & 4) d2 = diff32(hv[2].W, hv[2].w, B2);
   }
-  const int ns = cr[C_NSLOT], s0 = cr[C_SLOT0];
+  const int ns = cr[C_NSLOT], s0 = cr[C_SLOT0], pair0 = cr[C_PAIR0];
+  const int phw0 = cr[C_PHW0], phw1 = cr[C_PHW1], phw2 = cr[C_PHW2];
+  const uint32_t mb = m >> cr[C_BIT0];
   int sidx = 0;
   for (int r = 0; r < ns; ++r) {
-    const int* sr = slots + (s0 + r) * kSlotInts;
-    const int bit = sr[SL_BIT], pb = sr[SL_PAIRBASE], ph = sr[SL_PHASE];
-    const bool red = (m >> bit) & 1u;
+    const int w = r < 8 ? phw0 : (r < 16 ? phw1 : phw2);
+    const int ph = (w >> (3 * (r & 7))) & 7;
+    const bool red = (mb >> r) & 1u;
     const float rf = red ? 1.f : 0.f;
-    const Pair32* pp = Ps + (pb + sidx) * 3;
+    const Pair32* pp = Ps + (pair0 + ((r * (r + 1)) >> 1) + sidx) * 3;
     const Rec32* tr = Ss + (s0 + r) * 3;
 #define OKR_SLOT32(P_, S_, D_)                                                  \
     if (ph & (1 << P_)) {                                                       \
@@ -208,6 +243,8 @@ __global__ __launch_bounds__(kScoreThreads) void k_score_fp32(
   __shared__ Pair32 Ps[kMaxPairs * 3];
   __shared__ Rec32 Ts[kMaxK * 3];
   __shared__ Head32 Hv[kMaxK * 3];
+  __shared__ Rec32 Zs[kZoneLds];
+  __shared__ double s_ec;
   __shared__ int ticket;
   const SegHdr H = hdrs[g];
   if (!H.valid) return;
@@ -219,17 +256,22 @@ __global__ __launch_bounds__(kScoreThreads) void k_score_fp32(
   const int* chains = tab + H.o_chain;
   const int* slots = tab + H.o_slot;
   const int* nest = tab + H.o_nest;
+  const Stage z = stage_sizes(H);
   float e = 0.f, slack = INFINITY;
   for (int l = l0; l < l1; ++l) {
-    const Pair32* Pl = P32 + (size_t)l * H.npairs * 3;
-    for (int q = tid; q < H.npairs * 3; q += kScoreThreads) Ps[q] = Pl[q];
-    const Rec32* Sl = S32 + (size_t)l * H.nslots * 3;
-    for (int q = tid; q < H.nslots * 3; q += kScoreThreads) Ts[q] = Sl[q];
-    const Head32* Hl = H32 + (size_t)l * H.nchains * 3;
-    for (int q = tid; q < H.nchains * 3; q += kScoreThreads) Hv[q] = Hl[q];
+    {
+      const uint4* P_l = (const uint4*)(P32 + (size_t)l * H.npairs * 3);
+      const uint4* S_l = (const uint4*)(S32 + (size_t)l * H.nslots * 3);
+      const uint4* H_l = (const uint4*)(H32 + (size_t)l * H.nchains * 3);
+      const uint4* Z_l = (const uint4*)(Z32 + (size_t)l * H.nz);
+      for (int i = tid; i < z.total; i += kScoreThreads)
+        stage_put(z, i, stage_src(z, i, P_l, S_l, H_l, Z_l), (uint4*)Ps, (uint4*)Ts, (uint4*)Hv, (double*)nullptr,
+                  (uint4*)Zs);
+      if (tid == 0) s_ec = econst[l];
+      __syncthreads();
+    }
     const Rec32* Zl = Z32 + (size_t)l * H.nz;
-    __syncthreads();
-    float el = (float)econst[l];
+    float el = (float)s_ec;
     for (int c = 0; c < H.nchains; ++c) {
       const int* cr = chains + c * kChainInts;
       float2 B0 = make_float2(0.f, 0.f), B1 = B0, B2 = B0;
@@ -241,7 +283,9 @@ __global__ __launch_bounds__(kScoreThreads) void k_score_fp32(
       walk32<true>(cr, slots, Ps, Ts, Hv, c, m, B0, B1, B2, el, slack);
 #define OKR_ZONE32(P_, B_)                                                       \
       for (int q = cr[C_ZOFF0 + P_], qe = q + cr[C_ZCNT0 + P_]; q < qe; ++q) { \
-        const Rec32 t = Zl[q];                                                   \
+        Rec32 t;                                                                 \
+        if (q < kZoneLds) t = Zs[q];                                             \
+        else t = Zl[q];                                                          \
         const float d = diff32(t.W, t.w, B_);                                    \
         el = fmaxf(el, fmaxf(t.a + d, t.b - d));                                 \
         slack = fminf(slack, fminf(t.bmin + d, t.bmax - d));                     \

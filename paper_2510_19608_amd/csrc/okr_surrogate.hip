@@ -19,31 +19,38 @@ typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
 typedef float f32x16 __attribute__((ext_vector_type(16)));
 
 // ------------------------------------------------------ per-mask features --
-__global__ void k_surr_tables(const SegHdr* __restrict__ hdrs, int g, const int* __restrict__ tab, int n,
-                              const double2* __restrict__ z, const double2* __restrict__ P,
-                              const double2* __restrict__ A, const TargetRec* __restrict__ srec,
-                              float* __restrict__ pz, float* __restrict__ zs, SurrSlot* __restrict__ ss) {
+// Per-pair and per-slot feature tables (maxima over the snapshots): one wave
+// per pair or slot, lanes over the snapshots, a wave reduction.
+__global__ __launch_bounds__(64) void k_surr_tables(const SegHdr* __restrict__ hdrs, int g,
+                                                    const int* __restrict__ tab, int n,
+                                                    const double2* __restrict__ Zroot, const double2* __restrict__ P,
+                                                    const double2* __restrict__ A,
+                                                    const TargetRec* __restrict__ srec, float* __restrict__ pz,
+                                                    float* __restrict__ zs, SurrSlot* __restrict__ ss) {
   const SegHdr H = hdrs[g];
   if (!H.valid) return;
-  const int t = blockIdx.x * blockDim.x + threadIdx.x;
+  const int t = blockIdx.x, lane = threadIdx.x;
   if (t < H.npairs) {
     const int* pr = tab + H.o_pair + t * kPairInts;
     double mx = 0.0;
-    for (int l = 0; l < H.S; ++l)
+    for (int l = lane; l < H.S; l += 64)
       for (int p = 0; p < 3; ++p) mx = fmax(mx, sqrt(cabs2(P[((size_t)l * H.npairs + t) * 3 + p])));
-    double zsum = 0.0;
-    for (int x = pr[PR_FROM]; x <= pr[PR_TO]; ++x) {
-      const double2* zv = z + (size_t)tab[H.o_path + pr[PR_PATHOFF] + x] * 9;
-      for (int p = 0; p < 3; ++p) zsum += sqrt(cabs2(zv[p * 4]));
+    for (int o = 32; o > 0; o >>= 1) mx = fmax(mx, __shfl_xor(mx, o, 64));
+    if (lane == 0) {
+      // sum of |Z(s -> r)| over the diagonal, Z(s -> r) = Zroot(r) - Zroot(s)
+      double zsum = 0.0;
+      const double2* zr = Zroot + (size_t)pr[PR_RNODE] * 9;
+      const double2* zs0 = Zroot + (size_t)pr[PR_SUPER] * 9;
+      for (int p = 0; p < 3; ++p) zsum += sqrt(cabs2(csub(zr[p * 4], zs0[p * 4])));
+      pz[t] = (float)mx;
+      zs[t] = (float)zsum;
     }
-    pz[t] = (float)mx;
-    zs[t] = (float)zsum;
   } else if (t < H.npairs + H.nslots) {
     const int s = t - H.npairs;
     const int* sr = tab + H.o_slot + s * kSlotInts;
     const int node = sr[SL_NODE], ph = sr[SL_PHASE];
     double la = 0.0, sp = 0.0;
-    for (int l = 0; l < H.S; ++l) {
+    for (int l = lane; l < H.S; l += 64) {
       double a = 0.0;
       for (int p = 0; p < 3; ++p) {
         a += sqrt(cabs2(A[((size_t)l * n + node) * 3 + p]));
@@ -54,13 +61,19 @@ __global__ void k_surr_tables(const SegHdr* __restrict__ hdrs, int g, const int*
       }
       la = fmax(la, a);
     }
-    const int* cr = tab + H.o_chain + sr[SL_CHAIN] * kChainInts;
-    SurrSlot o;
-    o.la = (float)la;
-    o.spread = (float)sp;
-    o.nph = __popc(ph);
-    o.pos = s - cr[C_SLOT0];
-    ss[s] = o;
+    for (int o = 32; o > 0; o >>= 1) {
+      la = fmax(la, __shfl_xor(la, o, 64));
+      sp = fmax(sp, __shfl_xor(sp, o, 64));
+    }
+    if (lane == 0) {
+      const int* cr = tab + H.o_chain + sr[SL_CHAIN] * kChainInts;
+      SurrSlot o;
+      o.la = (float)la;
+      o.spread = (float)sp;
+      o.nph = __popc(ph);
+      o.pos = s - cr[C_SLOT0];
+      ss[s] = o;
+    }
   }
 }
 
@@ -141,12 +154,20 @@ __global__ void k_surr_features(const SegHdr* __restrict__ hdrs, int g, const in
 // Masks of popcount >= L1 over k bits, level by level from the top, each
 // level in colexicographic order (combinatorial number system); rows
 // [N1, M1) are padding.
-__device__ __forceinline__ uint32_t binom(int n, int r) {
-  if (r < 0 || r > n) return 0u;
-  uint64_t c = 1;
-  for (int q = 1; q <= r; ++q) c = c * (uint64_t)(n - r + q) / (uint64_t)q;
-  return (uint32_t)c;
+struct BinomTable {
+  uint32_t v[kMaxK + 1][kMaxK + 1];
+};
+constexpr BinomTable make_binom() {
+  BinomTable t{};
+  for (int n = 0; n <= kMaxK; ++n) {
+    t.v[n][0] = 1u;
+    for (int r = 1; r <= n; ++r) t.v[n][r] = t.v[n - 1][r - 1] + (r <= n - 1 ? t.v[n - 1][r] : 0u);
+  }
+  return t;
 }
+__constant__ BinomTable kBinom = make_binom();  // Pascal's triangle, C(n, r) for n <= 24
+
+__device__ __forceinline__ uint32_t binom(int n, int r) { return (r < 0 || r > n) ? 0u : kBinom.v[n][r]; }
 
 __global__ void k_level_masks(int k, int L1, int N1, int M1, uint32_t* __restrict__ masks) {
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
