@@ -134,6 +134,10 @@ typedef struct {
                          surrogate ranks first (full enumeration as fallback) */
     const float *surrogate; /* DEVICE FP32 parameters of the surrogate MLP
                                (layout in okr_train_surrogate), or NULL */
+    int32_t lanes;    /* segments searched concurrently (0 = 4, at most 8):
+                         a segment waits only for earlier segments whose
+                         affected regions (or chain heads) it can share;
+                         read by okr_plan (each lane has its own scratch) */
 } okr_margins;
 
 /* Sizes okr_plan() reports. */

@@ -60,7 +60,7 @@ class Margins(ctypes.Structure):
     _fields_ = [("e_bar", ctypes.c_double), ("v_min", ctypes.c_double), ("v_max", ctypes.c_double),
                 ("tie_tol", ctypes.c_double), ("amb_tol", ctypes.c_double), ("pf_tol", ctypes.c_double),
                 ("pf_maxit", ctypes.c_int32), ("precision", ctypes.c_int32), ("flags", ctypes.c_uint32),
-                ("top_k", ctypes.c_int32), ("surrogate", ctypes.c_void_p)]
+                ("top_k", ctypes.c_int32), ("surrogate", ctypes.c_void_p), ("lanes", ctypes.c_int32)]
 
 
 class Sizes(ctypes.Structure):
@@ -221,7 +221,7 @@ def okr_surrogate_forward(params, X, y, work):
 
 def make_margins(f=None, *, e_bar=None, v_min=None, v_max=None, tie_tol=1e-11, amb_tol=1e-13,
                  precision="fp64", timing=False, dump=False, vhat_given=False, graph=False, pf_tol=1e-13,
-                 pf_maxit=100, top_k=0, surrogate=None):
+                 pf_maxit=100, top_k=0, surrogate=None, lanes=0):
     f = f or {}
     flags = (OKR.FLAG_TIMING if timing else 0) | (OKR.FLAG_DUMP_SCORES if dump else 0) | \
             (OKR.FLAG_VHAT_GIVEN if vhat_given else 0) | (OKR.FLAG_GRAPH if graph else 0)
@@ -231,7 +231,7 @@ def make_margins(f=None, *, e_bar=None, v_min=None, v_max=None, tie_tol=1e-11, a
                    tie_tol=tie_tol, amb_tol=amb_tol, pf_tol=pf_tol, pf_maxit=pf_maxit,
                    precision={"fp64": OKR.PRECISION_FP64, "mixed": OKR.PRECISION_MIXED}[precision],
                    flags=flags, top_k=top_k,
-                   surrogate=None if surrogate is None else surrogate.data_ptr())
+                   surrogate=None if surrogate is None else surrogate.data_ptr(), lanes=lanes)
 
 
 class Reducer:

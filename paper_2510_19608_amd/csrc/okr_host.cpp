@@ -117,6 +117,7 @@ struct Layout {
   // surrogate: feature tables (always), ranking buffers (when planned with top_k)
   size_t spz, szs, sss, sXb, sH1b, spart, sy, skeys, slist, sscore, scount, sgates, sW1b, sW2b, sW2tb, slevel,
       sstage;
+  size_t lane0, lane_stride;  // per-lane scratch block (tab .. scount)
   size_t total;
 };
 
@@ -153,6 +154,15 @@ struct okr_handle {
   std::vector<int> sg_tuned, mpl_tuned;
   int sg_force = 0, mpl_force = 0;
   size_t part_cap = 0;
+  // concurrent segment lanes: a stream each (lane 0 is the handle's stream
+  // when there is one lane), the lane of every segment, the earlier segments
+  // it must wait for, and one event per segment plus fork/join events
+  int nlanes = 1;
+  std::vector<hipStream_t> lane_st;
+  std::vector<int> lane_of;
+  std::vector<std::vector<int>> deps;
+  std::vector<hipEvent_t> seg_ev, join_ev;
+  hipEvent_t fork_ev = nullptr;
 };
 
 namespace {
@@ -204,6 +214,18 @@ static void drop_events(okr_handle* h) {
   h->ev.clear();
 }
 
+static void drop_lanes(okr_handle* h) {
+  for (hipEvent_t e : h->seg_ev) (void)hipEventDestroy(e);
+  for (hipEvent_t e : h->join_ev) (void)hipEventDestroy(e);
+  if (h->fork_ev) (void)hipEventDestroy(h->fork_ev);
+  for (hipStream_t s : h->lane_st)
+    if (s != h->stream) (void)hipStreamDestroy(s);
+  h->seg_ev.clear();
+  h->join_ev.clear();
+  h->fork_ev = nullptr;
+  h->lane_st.clear();
+}
+
 extern "C" int okr_create(okr_handle** h, void* hip_stream) {
   if (!h) return OKR_E_ARG;
   okr_handle* H = new (std::nothrow) okr_handle();
@@ -217,6 +239,7 @@ extern "C" int okr_destroy(okr_handle* h) {
   if (!h) return OKR_E_ARG;
   drop_graph(h);
   drop_events(h);
+  drop_lanes(h);
   delete h;
   return OKR_OK;
 }
@@ -320,6 +343,69 @@ extern "C" int okr_plan(okr_handle* h, const okr_topology* topo, const okr_margi
     h->seg_nodes.insert(h->seg_nodes.end(), seg_nodes[g].begin(), seg_nodes[g].end());
   }
   h->nseg = nseg;
+  // Concurrent lanes.  A segment's search reads and writes state only inside
+  // the subtrees of its possible chain tops (climb from each node through
+  // segment nodes of any segment: every node that a chain of the segment can
+  // ever pass lies there) and at the heads above them (moved currents land
+  // there).  Segments that share none of that are independent; a segment
+  // waits for the latest conflicting earlier segment of every lane.
+  {
+    const int want = mg->lanes > 0 ? std::min(mg->lanes, 8) : 4;
+    h->nlanes = std::max(1, std::min(want, nseg));
+    std::vector<std::vector<std::pair<int, int>>> iv(nseg);
+    std::vector<std::vector<int>> heads(nseg);
+    for (int g = 0; g < nseg; ++g) {
+      for (int q = h->seg_off[g]; q < h->seg_off[g + 1]; ++q) {
+        int c = h->seg_nodes[q];
+        while (h->parent[c] >= 0 && h->segment[h->parent[c]] >= 0) c = h->parent[c];
+        iv[g].push_back({h->pos[c], h->pos[c] + h->size[c]});
+        heads[g].push_back(h->parent[c]);
+      }
+      std::sort(iv[g].begin(), iv[g].end());
+      std::vector<std::pair<int, int>> mgd;
+      for (auto& r : iv[g]) {
+        if (!mgd.empty() && r.first < mgd.back().second) mgd.back().second = std::max(mgd.back().second, r.second);
+        else mgd.push_back(r);
+      }
+      iv[g] = mgd;
+      std::sort(heads[g].begin(), heads[g].end());
+      heads[g].erase(std::unique(heads[g].begin(), heads[g].end()), heads[g].end());
+    }
+    auto inside = [&](int v, const std::vector<std::pair<int, int>>& R) {
+      if (v < 0) return false;
+      const int pv = h->pos[v];
+      for (auto& r : R)
+        if (r.first <= pv && pv < r.second) return true;
+      return false;
+    };
+    auto conflict = [&](int a, int b) {
+      size_t i = 0, j = 0;
+      while (i < iv[a].size() && j < iv[b].size()) {
+        if (iv[a][i].first < iv[b][j].second && iv[b][j].first < iv[a][i].second) return true;
+        if (iv[a][i].second <= iv[b][j].second) ++i;
+        else ++j;
+      }
+      for (int x : heads[a])
+        if (inside(x, iv[b]) || std::binary_search(heads[b].begin(), heads[b].end(), x)) return true;
+      for (int x : heads[b])
+        if (inside(x, iv[a])) return true;
+      return false;
+    };
+    h->lane_of.assign(nseg, 0);
+    h->deps.assign(nseg, {});
+    for (int g = 0; g < nseg; ++g) {
+      h->lane_of[g] = g % h->nlanes;
+      std::vector<int> last(h->nlanes, -1);
+      for (int b = g - 1; b >= 0; --b) {
+        const int lb = h->lane_of[b];
+        if (lb == h->lane_of[g] || last[lb] >= 0) continue;  // same lane: in order anyway
+        if (conflict(g, b)) last[lb] = b;
+      }
+      for (int l = 0; l < h->nlanes; ++l)
+        if (last[l] >= 0) h->deps[g].push_back(last[l]);
+    }
+    drop_lanes(h);  // streams and events are created by the first search after a plan
+  }
   // packed static topology
   TopoOffsets& TO = h->TO;
   std::vector<int>& tp = h->topo_host;
@@ -372,6 +458,8 @@ extern "C" int okr_plan(okr_handle* h, const okr_topology* topo, const okr_margi
   L.iters = take(sizeof(int) * S);
   L.hdrs = take(sizeof(SegHdr) * std::max(nseg, 1));
   L.decs = take(sizeof(DevDecision) * std::max(nseg, 1));
+  // per-lane scratch (one block per concurrent lane, lane l at + l * lane_stride)
+  L.lane0 = off;
   L.tab = take(sizeof(int) * h->tab_cap);
   L.P = take(sizeof(double2) * 3 * (size_t)S * kMaxPairs);
   L.srec = take(sizeof(TargetRec) * 3 * (size_t)S * kMaxK);
@@ -417,13 +505,12 @@ extern "C" int okr_plan(okr_handle* h, const okr_topology* topo, const okr_margi
     L.scoreA = take(sizeof(MaskScore) * nm);
     L.scoreB = take(sizeof(MaskScore) * nm);
     L.counts = take(sizeof(int) * 4);
-    L.mstate = take(sizeof(MixedState) * std::max(nseg, 1));
   }
+  h->topk = (mg->top_k > 0) ? mg->top_k : 0;
   {
     L.spz = take(sizeof(float) * kMaxPairs);
     L.szs = take(sizeof(float) * kMaxPairs);
     L.sss = take(sizeof(SurrSlot) * kMaxK);
-    h->topk = (mg->top_k > 0) ? mg->top_k : 0;
     const size_t mp = h->topk ? std::max((size_t)64, (size_t)1 << h->kmax) : 0;
     L.sXb = take(sizeof(uint16_t) * kSurrF * mp);
     L.sH1b = take(sizeof(uint16_t) * kSurrH * mp);
@@ -431,15 +518,19 @@ extern "C" int okr_plan(okr_handle* h, const okr_topology* topo, const okr_margi
     L.sy = take(sizeof(float) * mp);
     L.skeys = take(sizeof(uint32_t) * mp);
     L.slevel = take(sizeof(uint32_t) * mp);
-    L.sstage = take(sizeof(int) * std::max(nseg, 1));
     L.slist = take(sizeof(uint32_t) * std::max(h->topk, 1));
     L.sscore = take(sizeof(MaskScore) * std::max(h->topk, 1));
     L.scount = take(sizeof(int) * 4);
-    L.sgates = take(sizeof(int) * std::max(nseg, 1));
-    L.sW1b = take(sizeof(uint16_t) * kSurrH * kSurrF * (h->topk ? 1 : 0));
-    L.sW2b = take(sizeof(uint16_t) * kSurrH * kSurrH * (h->topk ? 1 : 0));
-    L.sW2tb = take(8);
   }
+  L.lane_stride = off - L.lane0;
+  off = L.lane0 + L.lane_stride * (size_t)h->nlanes;
+  // per-segment records and shared weights
+  L.mstate = take(sizeof(MixedState) * std::max(nseg, 1));
+  L.sstage = take(sizeof(int) * std::max(nseg, 1));
+  L.sgates = take(sizeof(int) * std::max(nseg, 1));
+  L.sW1b = take(sizeof(uint16_t) * kSurrH * kSurrF * (h->topk ? 1 : 0));
+  L.sW2b = take(sizeof(uint16_t) * kSurrH * kSurrH * (h->topk ? 1 : 0));
+  L.sW2tb = take(8);
   L.kp = take(sizeof(int) * n);
   L.yeq = take(sizeof(double2) * 9 * n);
   L.Ykd = take(sizeof(double2) * 9 * n);
@@ -488,10 +579,15 @@ struct Ptrs {
   int *scount, *sgates, *sstage;
 };
 
-Ptrs pointers(okr_handle* h, void* d_workspace) {
+// Device pointers, with the per-lane scratch of lane `lane`.
+Ptrs pointers(okr_handle* h, void* d_workspace, int lane = 0) {
   const Layout& L = h->L;
   char* ws = static_cast<char*>(d_workspace);
-  auto at = [&](size_t o) { return static_cast<void*>(ws + o); };
+  const size_t lo = L.lane_stride * (size_t)lane;
+  auto at = [&](size_t o) {
+    const bool lane_scoped = o >= L.lane0 && o < L.lane0 + L.lane_stride;
+    return static_cast<void*>(ws + o + (lane_scoped ? lo : 0));
+  };
   Ptrs p{};
   int* tp = (int*)at(L.topo);
   const TopoOffsets& TO = h->TO;
@@ -574,16 +670,25 @@ Ptrs pointers(okr_handle* h, void* d_workspace) {
 // Enqueue one whole search on `st` without host synchronisation.  With `ev`
 // (2 events per segment) the scoring launches are bracketed by events; with
 // `dump` every segment's final per-mask scores are copied out.
-void enqueue_search(okr_handle* h, const Ptrs& p, const okr_yblocks* Y, const okr_loads* loads,
+void enqueue_search(okr_handle* h, void* ws, const okr_yblocks* Y, const okr_loads* loads,
                     const okr_margins* mg, hipStream_t st, const std::vector<hipEvent_t>* ev,
                     std::vector<std::vector<MaskScore>>* dump, std::vector<std::vector<MaskScore32>>* dump32,
-                    float* feat_out, float* targ_out) {
+                    float* feat_out, float* targ_out, bool use_lanes) {
   const int n = h->n, S = h->S;
+  const Ptrs p = pointers(h, ws);
+  // lanes run concurrently on streams of their own; without use_lanes every
+  // segment runs in order on st (one scratch block)
+  const int nl = use_lanes ? h->nlanes : 1;
+  std::vector<Ptrs> lp(h->nlanes);
+  for (int l = 0; l < h->nlanes; ++l) lp[l] = pointers(h, ws, l);
   const bool vhat_given = (mg->flags & OKR_FLAG_VHAT_GIVEN) != 0;
   const int ntick = (int)((((size_t)1 << h->kmax) + 63) / 64);
   const int ninit = std::max(n, std::max(kStatusInts, ntick));
   hipLaunchKernelGGL(k_init_state, dim3((ninit + 255) / 256), dim3(256), 0, st, n, p.St, p.status, kStatusInts,
                      p.tickets, ntick);
+  for (int l = 1; l < h->nlanes; ++l)  // the other lanes' ticket counters
+    hipLaunchKernelGGL(k_init_state, dim3((ntick + 255) / 256), dim3(256), 0, st, 0, p.St, p.status, 0,
+                       lp[l].tickets, ntick);
   hipLaunchKernelGGL(k_branch_z, dim3((n + 127) / 128), dim3(128), 0, st, n, p.T.parent, p.T.phase, p.T.ch_off,
                      p.T.ch, (const double2*)Y->Y_diag, (const double2*)Y->Y_off, p.z, p.status);
   hipLaunchKernelGGL(k_zroot, dim3(1), dim3(256), 0, st, n, p.T.parent, p.lvl_off, p.lvl_nodes, h->nlev,
@@ -616,16 +721,26 @@ void enqueue_search(okr_handle* h, const Ptrs& p, const okr_yblocks* Y, const ok
                        p.sW1b, p.sW2b, (__bf16*)nullptr);
   size_t feat_off = 0;
   const int members_blocks = std::min(2048, std::max(1, (int)(((size_t)n * S + 255) / 256)));
+  // segments run on their lanes, each after the earlier segments it conflicts with
+  if (nl > 1) {
+    (void)hipEventRecord(h->fork_ev, st);
+    for (int l = 0; l < nl; ++l) (void)hipStreamWaitEvent(h->lane_st[l], h->fork_ev, 0);
+  }
   for (int g = 0; g < h->nseg; ++g) {
     const int k = h->seg_off[g + 1] - h->seg_off[g];
-    hipLaunchKernelGGL(k_build_struct, dim3(1), dim3(256), 0, st, p.T, p.St, g, S, p.hdrs, p.tab, h->tab_cap,
-                       p.status);
-    hipLaunchKernelGGL(k_build_values, dim3(256, 5), dim3(256), 0, st, (const SegHdr*)p.hdrs, g, (const int*)p.tab,
-                       n, (const double2*)p.Zroot, (const double2*)p.Vcur, (const double2*)p.A, p.P, p.srec, p.headV,
-                       p.zrec, p.econst);
-    hipLaunchKernelGGL(k_build_members, dim3(members_blocks), dim3(256), 0, st, (const SegHdr*)p.hdrs, g,
-                       (const int*)p.tab, p.T, p.St, (const double2*)p.Vcur, (const double*)p.absV, p.srec, p.zrec,
-                       p.econst);
+    const int lane = nl > 1 ? h->lane_of[g] : 0;
+    hipStream_t ls = nl > 1 ? h->lane_st[lane] : st;
+    const Ptrs& q = lp[lane];
+    if (nl > 1)
+      for (int d : h->deps[g]) (void)hipStreamWaitEvent(ls, h->seg_ev[d], 0);
+    hipLaunchKernelGGL(k_build_struct, dim3(1), dim3(256), 0, ls, q.T, q.St, g, S, q.hdrs, q.tab, h->tab_cap,
+                       q.status);
+    hipLaunchKernelGGL(k_build_values, dim3(256, 5), dim3(256), 0, ls, (const SegHdr*)q.hdrs, g, (const int*)q.tab,
+                       n, (const double2*)q.Zroot, (const double2*)q.Vcur, (const double2*)q.A, q.P, q.srec, q.headV,
+                       q.zrec, q.econst);
+    hipLaunchKernelGGL(k_build_members, dim3(members_blocks), dim3(256), 0, ls, (const SegHdr*)q.hdrs, g,
+                       (const int*)q.tab, q.T, q.St, (const double2*)q.Vcur, (const double*)q.absV, q.srec, q.zrec,
+                       q.econst);
     const uint32_t nmask = 1u << k;
     const int mpl = score_mpl(h, k);
     const int mblocks = (int)((nmask + kScoreThreads * mpl - 1) / (kScoreThreads * mpl));
@@ -637,9 +752,9 @@ void enqueue_search(okr_handle* h, const Ptrs& p, const okr_yblocks* Y, const ok
     const int SG32 = snap_groups_default(k, S, &spg32);
     const int* gate = nullptr;
     if (surr || feat_out) {
-      hipLaunchKernelGGL(k_surr_tables, dim3(kMaxPairs + kMaxK), dim3(64), 0, st,
-                         (const SegHdr*)p.hdrs, g, (const int*)p.tab, n, (const double2*)p.Zroot, (const double2*)p.P,
-                         (const double2*)p.A, (const TargetRec*)p.srec, p.spz, p.szs, p.sss);
+      hipLaunchKernelGGL(k_surr_tables, dim3(kMaxPairs + kMaxK), dim3(64), 0, ls,
+                         (const SegHdr*)q.hdrs, g, (const int*)q.tab, n, (const double2*)q.Zroot, (const double2*)q.P,
+                         (const double2*)q.A, (const TargetRec*)q.srec, q.spz, q.szs, q.sss);
     }
     if (surr) {
       // Rank the masks with the surrogate and rescore the top-k exactly.
@@ -658,122 +773,128 @@ void enqueue_search(okr_handle* h, const Ptrs& p, const okr_yblocks* Y, const ok
         N1 += c;
       }
       const bool staged = N1 < nmask;
-      int* stage = p.sstage + g;
+      int* stage = q.sstage + g;
       auto rank = [&](const uint32_t* masks, int nrow, const int* flag, int skip_if) {
         const int Mp = std::max(64, (nrow + 63) / 64 * 64);
-        hipLaunchKernelGGL(k_surr_features, dim3((Mp + 255) / 256), dim3(256), 0, st, (const SegHdr*)p.hdrs, g,
-                           (const int*)p.tab, (const float*)p.spz, (const float*)p.szs, (const SurrSlot*)p.sss,
-                           (const double*)p.econst, masks, nrow, Mp, (float*)nullptr, p.sXb, flag, skip_if);
-        hipLaunchKernelGGL(k_gemm_nt<1>, dim3(kSurrH / 64, Mp / 64), dim3(256), 0, st, (const __bf16*)p.sXb, kSurrF,
-                           (const __bf16*)p.sW1b, kSurrF, kSurrF, (float*)nullptr, kSurrH, mg->surrogate + kOffB1,
-                           (float*)nullptr, p.sH1b, (__bf16*)nullptr, Mp, (const float*)nullptr, (float*)nullptr,
+        hipLaunchKernelGGL(k_surr_features, dim3((Mp + 255) / 256), dim3(256), 0, ls, (const SegHdr*)q.hdrs, g,
+                           (const int*)q.tab, (const float*)q.spz, (const float*)q.szs, (const SurrSlot*)q.sss,
+                           (const double*)q.econst, masks, nrow, Mp, (float*)nullptr, q.sXb, flag, skip_if);
+        hipLaunchKernelGGL(k_gemm_nt<1>, dim3(kSurrH / 64, Mp / 64), dim3(256), 0, ls, (const __bf16*)q.sXb, kSurrF,
+                           (const __bf16*)q.sW1b, kSurrF, kSurrF, (float*)nullptr, kSurrH, mg->surrogate + kOffB1,
+                           (float*)nullptr, q.sH1b, (__bf16*)nullptr, Mp, (const float*)nullptr, (float*)nullptr,
                            flag, skip_if);
-        hipLaunchKernelGGL(k_gemm_nt<2>, dim3(kSurrH / 64, Mp / 64), dim3(256), 0, st, (const __bf16*)p.sH1b, kSurrH,
-                           (const __bf16*)p.sW2b, kSurrH, kSurrH, (float*)nullptr, kSurrH, mg->surrogate + kOffB2,
-                           (float*)nullptr, (__bf16*)nullptr, (__bf16*)nullptr, Mp, mg->surrogate + kOffW3, p.spart,
+        hipLaunchKernelGGL(k_gemm_nt<2>, dim3(kSurrH / 64, Mp / 64), dim3(256), 0, ls, (const __bf16*)q.sH1b, kSurrH,
+                           (const __bf16*)q.sW2b, kSurrH, kSurrH, (float*)nullptr, kSurrH, mg->surrogate + kOffB2,
+                           (float*)nullptr, (__bf16*)nullptr, (__bf16*)nullptr, Mp, mg->surrogate + kOffW3, q.spart,
                            flag, skip_if);
-        hipLaunchKernelGGL(k_rowdot_finish, dim3((Mp + 255) / 256), dim3(256), 0, st, (const float*)p.spart,
-                           kSurrH / 32, Mp, mg->surrogate + kOffB3, p.sy, flag, skip_if);
-        hipLaunchKernelGGL(k_surr_keys, dim3((nrow + 255) / 256), dim3(256), 0, st, (const SegHdr*)p.hdrs, g,
-                           (const float*)p.sy, ln_ebar, masks, nrow, p.skeys, flag, skip_if);
+        hipLaunchKernelGGL(k_rowdot_finish, dim3((Mp + 255) / 256), dim3(256), 0, ls, (const float*)q.spart,
+                           kSurrH / 32, Mp, mg->surrogate + kOffB3, q.sy, flag, skip_if);
+        hipLaunchKernelGGL(k_surr_keys, dim3((nrow + 255) / 256), dim3(256), 0, ls, (const SegHdr*)q.hdrs, g,
+                           (const float*)q.sy, ln_ebar, masks, nrow, q.skeys, flag, skip_if);
       };
       if (staged) {
-        hipLaunchKernelGGL(k_level_masks, dim3(((int)N1 + 63) / 64 * 64 / 64), dim3(64), 0, st, k, L1, (int)N1,
-                           ((int)N1 + 63) / 64 * 64, p.slevel);
-        rank(p.slevel, (int)N1, (const int*)nullptr, 0);
-        hipLaunchKernelGGL(k_surr_stage, dim3(1), dim3(256), 0, st, (const SegHdr*)p.hdrs, g,
-                           (const uint32_t*)p.skeys, (int)N1, K, stage);
-        hipLaunchKernelGGL(k_topk, dim3(1), dim3(1024), 0, st, (const SegHdr*)p.hdrs, g, (const uint32_t*)p.skeys,
-                           (const uint32_t*)p.slevel, (int)N1, K, (const int*)p.status, p.slist, p.scount,
+        hipLaunchKernelGGL(k_level_masks, dim3(((int)N1 + 63) / 64 * 64 / 64), dim3(64), 0, ls, k, L1, (int)N1,
+                           ((int)N1 + 63) / 64 * 64, q.slevel);
+        rank(q.slevel, (int)N1, (const int*)nullptr, 0);
+        hipLaunchKernelGGL(k_surr_stage, dim3(1), dim3(256), 0, ls, (const SegHdr*)q.hdrs, g,
+                           (const uint32_t*)q.skeys, (int)N1, K, stage);
+        hipLaunchKernelGGL(k_topk, dim3(1), dim3(1024), 0, ls, (const SegHdr*)q.hdrs, g, (const uint32_t*)q.skeys,
+                           (const uint32_t*)q.slevel, (int)N1, K, (const int*)q.status, q.slist, q.scount,
                            (const int*)stage, 0);
         rank((const uint32_t*)nullptr, (int)nmask, (const int*)stage, 1);
-        hipLaunchKernelGGL(k_topk, dim3(1), dim3(1024), 0, st, (const SegHdr*)p.hdrs, g, (const uint32_t*)p.skeys,
-                           (const uint32_t*)nullptr, (int)nmask, K, (const int*)p.status, p.slist, p.scount,
+        hipLaunchKernelGGL(k_topk, dim3(1), dim3(1024), 0, ls, (const SegHdr*)q.hdrs, g, (const uint32_t*)q.skeys,
+                           (const uint32_t*)nullptr, (int)nmask, K, (const int*)q.status, q.slist, q.scount,
                            (const int*)stage, 1);
       } else {
         rank((const uint32_t*)nullptr, (int)nmask, (const int*)nullptr, 0);
-        hipLaunchKernelGGL(k_topk, dim3(1), dim3(1024), 0, st, (const SegHdr*)p.hdrs, g, (const uint32_t*)p.skeys,
-                           (const uint32_t*)nullptr, (int)nmask, K, (const int*)p.status, p.slist, p.scount,
+        hipLaunchKernelGGL(k_topk, dim3(1), dim3(1024), 0, ls, (const SegHdr*)q.hdrs, g, (const uint32_t*)q.skeys,
+                           (const uint32_t*)nullptr, (int)nmask, K, (const int*)q.status, q.slist, q.scount,
                            (const int*)nullptr, 0);
       }
-      hipLaunchKernelGGL(k_refine_fp64, dim3(kRefineBlocks), dim3(kScoreBlock), 0, st, (const SegHdr*)p.hdrs, g,
-                         (const int*)p.tab, (const double2*)p.P, (const TargetRec*)p.srec, (const double2*)p.headV,
-                         (const TargetRec*)p.zrec, (const double*)p.econst, sp, (const uint32_t*)p.slist,
-                         (const int*)p.scount, p.sscore);
-      hipLaunchKernelGGL(k_surr_decide, dim3(1), dim3(1024), 0, st, (const SegHdr*)p.hdrs, g, sp,
-                         (const int*)p.status, (const uint32_t*)p.slist, (const int*)p.scount,
-                         (const MaskScore*)p.sscore, p.decs, p.sgates + g);
-      gate = p.sgates + g;
+      hipLaunchKernelGGL(k_refine_fp64, dim3(kRefineBlocks), dim3(kScoreBlock), 0, ls, (const SegHdr*)q.hdrs, g,
+                         (const int*)q.tab, (const double2*)q.P, (const TargetRec*)q.srec, (const double2*)q.headV,
+                         (const TargetRec*)q.zrec, (const double*)q.econst, sp, (const uint32_t*)q.slist,
+                         (const int*)q.scount, q.sscore);
+      hipLaunchKernelGGL(k_surr_decide, dim3(1), dim3(1024), 0, ls, (const SegHdr*)q.hdrs, g, sp,
+                         (const int*)q.status, (const uint32_t*)q.slist, (const int*)q.scount,
+                         (const MaskScore*)q.sscore, q.decs, q.sgates + g);
+      gate = q.sgates + g;
     }
     if (!mixed) {
-      if (ev) (void)hipEventRecord((*ev)[2 * g], st);
+      if (ev) (void)hipEventRecord((*ev)[2 * g], ls);
 #define OKR_SCORE64(M_)                                                                                      \
-  hipLaunchKernelGGL(k_score_fp64<M_>, dim3(mblocks, SG), dim3(kScoreThreads), 0, st, (const SegHdr*)p.hdrs, g, \
-                     (const int*)p.tab, (const double2*)p.P, (const TargetRec*)p.srec, (const double2*)p.headV, \
-                     (const TargetRec*)p.zrec, (const double*)p.econst, spg, SG, sp, p.part, p.fin, p.tiles,   \
-                     p.tickets, gate)
+  hipLaunchKernelGGL(k_score_fp64<M_>, dim3(mblocks, SG), dim3(kScoreThreads), 0, ls, (const SegHdr*)q.hdrs, g, \
+                     (const int*)q.tab, (const double2*)q.P, (const TargetRec*)q.srec, (const double2*)q.headV, \
+                     (const TargetRec*)q.zrec, (const double*)q.econst, spg, SG, sp, q.part, q.fin, q.tiles,   \
+                     q.tickets, gate)
       if (mpl == 4) OKR_SCORE64(4);
       else if (mpl == 2) OKR_SCORE64(2);
       else OKR_SCORE64(1);
 #undef OKR_SCORE64
-      if (ev) (void)hipEventRecord((*ev)[2 * g + 1], st);
-      hipLaunchKernelGGL(k_argmin, dim3(1), dim3(1024), 0, st, (const SegHdr*)p.hdrs, g, (const MaskScore*)p.fin,
-                         (const TileRec*)p.tiles, sp, (const int*)p.status, p.decs, gate);
+      if (ev) (void)hipEventRecord((*ev)[2 * g + 1], ls);
+      hipLaunchKernelGGL(k_argmin, dim3(1), dim3(1024), 0, ls, (const SegHdr*)q.hdrs, g, (const MaskScore*)q.fin,
+                         (const TileRec*)q.tiles, sp, (const int*)q.status, q.decs, gate);
       if (feat_out && !surr) {
-        hipLaunchKernelGGL(k_surr_features, dim3((nmask + 255) / 256), dim3(256), 0, st, (const SegHdr*)p.hdrs, g,
-                           (const int*)p.tab, (const float*)p.spz, (const float*)p.szs, (const SurrSlot*)p.sss,
-                           (const double*)p.econst, (const uint32_t*)nullptr, (int)nmask, (int)nmask,
+        hipLaunchKernelGGL(k_surr_features, dim3((nmask + 255) / 256), dim3(256), 0, ls, (const SegHdr*)q.hdrs, g,
+                           (const int*)q.tab, (const float*)q.spz, (const float*)q.szs, (const SurrSlot*)q.sss,
+                           (const double*)q.econst, (const uint32_t*)nullptr, (int)nmask, (int)nmask,
                            feat_out + feat_off * kSurrF, (__bf16*)nullptr, (const int*)nullptr, 0);
         if (targ_out)
-          hipLaunchKernelGGL(k_surr_target, dim3((nmask + 255) / 256), dim3(256), 0, st, (const SegHdr*)p.hdrs, g,
-                             (const MaskScore*)p.fin, targ_out + feat_off);
+          hipLaunchKernelGGL(k_surr_target, dim3((nmask + 255) / 256), dim3(256), 0, ls, (const SegHdr*)q.hdrs, g,
+                             (const MaskScore*)q.fin, targ_out + feat_off);
       }
       feat_off += nmask;
       if (dump) {
         (*dump)[g].resize(nmask);
-        (void)hipMemcpyAsync((*dump)[g].data(), p.fin, sizeof(MaskScore) * nmask, hipMemcpyDeviceToHost, st);
+        (void)hipMemcpyAsync((*dump)[g].data(), q.fin, sizeof(MaskScore) * nmask, hipMemcpyDeviceToHost, ls);
       }
     } else {
-      hipLaunchKernelGGL(k_build_mixed, dim3(256, 4), dim3(256), 0, st, (const SegHdr*)p.hdrs, g, (const int*)p.tab,
-                         n, (const double2*)p.Vcur, (const double2*)p.P, (const TargetRec*)p.srec,
-                         (const double2*)p.headV, (const TargetRec*)p.zrec, mg->v_min, mg->v_max, p.P32, p.S32,
-                         p.H32, p.Z32);
-      if (ev) (void)hipEventRecord((*ev)[2 * g], st);
-      hipLaunchKernelGGL(k_score_fp32, dim3(mblocks32, SG32), dim3(kScoreThreads), 0, st, (const SegHdr*)p.hdrs, g,
-                         (const int*)p.tab, (const Pair32*)p.P32, (const Rec32*)p.S32, (const Head32*)p.H32,
-                         (const Rec32*)p.Z32, (const double*)p.econst, spg32, SG32, sp, p.part32, p.fin32, p.tiles32,
-                         p.tickets);
-      if (ev) (void)hipEventRecord((*ev)[2 * g + 1], st);
-      int* cA = p.counts;
-      int* cB = p.counts + 1;
-      hipLaunchKernelGGL(k_mixed_select_a, dim3(1), dim3(1024), 0, st, (const SegHdr*)p.hdrs, g,
-                         (const MaskScore32*)p.fin32, (const TileRec32*)p.tiles32, sp, (const int*)p.status,
-                         p.mstate, p.listA, cA);
-      hipLaunchKernelGGL(k_refine_fp64, dim3(kRefineBlocks), dim3(kScoreBlock), 0, st, (const SegHdr*)p.hdrs, g,
-                         (const int*)p.tab, (const double2*)p.P, (const TargetRec*)p.srec, (const double2*)p.headV,
-                         (const TargetRec*)p.zrec, (const double*)p.econst, sp, (const uint32_t*)p.listA,
-                         (const int*)cA, p.scoreA);
-      hipLaunchKernelGGL(k_mixed_select_b, dim3(1), dim3(1024), 0, st, (const SegHdr*)p.hdrs, g,
-                         (const MaskScore32*)p.fin32, (const TileRec32*)p.tiles32, sp, (const int*)p.status,
-                         p.mstate, (const uint32_t*)p.listA, (const int*)cA, (const MaskScore*)p.scoreA, p.listB,
+      hipLaunchKernelGGL(k_build_mixed, dim3(256, 4), dim3(256), 0, ls, (const SegHdr*)q.hdrs, g, (const int*)q.tab,
+                         n, (const double2*)q.Vcur, (const double2*)q.P, (const TargetRec*)q.srec,
+                         (const double2*)q.headV, (const TargetRec*)q.zrec, mg->v_min, mg->v_max, q.P32, q.S32,
+                         q.H32, q.Z32);
+      if (ev) (void)hipEventRecord((*ev)[2 * g], ls);
+      hipLaunchKernelGGL(k_score_fp32, dim3(mblocks32, SG32), dim3(kScoreThreads), 0, ls, (const SegHdr*)q.hdrs, g,
+                         (const int*)q.tab, (const Pair32*)q.P32, (const Rec32*)q.S32, (const Head32*)q.H32,
+                         (const Rec32*)q.Z32, (const double*)q.econst, spg32, SG32, sp, q.part32, q.fin32, q.tiles32,
+                         q.tickets);
+      if (ev) (void)hipEventRecord((*ev)[2 * g + 1], ls);
+      int* cA = q.counts;
+      int* cB = q.counts + 1;
+      hipLaunchKernelGGL(k_mixed_select_a, dim3(1), dim3(1024), 0, ls, (const SegHdr*)q.hdrs, g,
+                         (const MaskScore32*)q.fin32, (const TileRec32*)q.tiles32, sp, (const int*)q.status,
+                         q.mstate, q.listA, cA);
+      hipLaunchKernelGGL(k_refine_fp64, dim3(kRefineBlocks), dim3(kScoreBlock), 0, ls, (const SegHdr*)q.hdrs, g,
+                         (const int*)q.tab, (const double2*)q.P, (const TargetRec*)q.srec, (const double2*)q.headV,
+                         (const TargetRec*)q.zrec, (const double*)q.econst, sp, (const uint32_t*)q.listA,
+                         (const int*)cA, q.scoreA);
+      hipLaunchKernelGGL(k_mixed_select_b, dim3(1), dim3(1024), 0, ls, (const SegHdr*)q.hdrs, g,
+                         (const MaskScore32*)q.fin32, (const TileRec32*)q.tiles32, sp, (const int*)q.status,
+                         q.mstate, (const uint32_t*)q.listA, (const int*)cA, (const MaskScore*)q.scoreA, q.listB,
                          cB);
-      hipLaunchKernelGGL(k_refine_fp64, dim3(kRefineBlocks), dim3(kScoreBlock), 0, st, (const SegHdr*)p.hdrs, g,
-                         (const int*)p.tab, (const double2*)p.P, (const TargetRec*)p.srec, (const double2*)p.headV,
-                         (const TargetRec*)p.zrec, (const double*)p.econst, sp, (const uint32_t*)p.listB,
-                         (const int*)cB, p.scoreB);
-      hipLaunchKernelGGL(k_mixed_final, dim3(1), dim3(1024), 0, st, (const SegHdr*)p.hdrs, g, sp,
-                         (const int*)p.status, p.mstate, (const MaskScore32*)p.fin32, (const uint32_t*)p.listA,
-                         (const int*)cA, (const MaskScore*)p.scoreA, (const uint32_t*)p.listB, (const int*)cB,
-                         (const MaskScore*)p.scoreB, p.decs);
+      hipLaunchKernelGGL(k_refine_fp64, dim3(kRefineBlocks), dim3(kScoreBlock), 0, ls, (const SegHdr*)q.hdrs, g,
+                         (const int*)q.tab, (const double2*)q.P, (const TargetRec*)q.srec, (const double2*)q.headV,
+                         (const TargetRec*)q.zrec, (const double*)q.econst, sp, (const uint32_t*)q.listB,
+                         (const int*)cB, q.scoreB);
+      hipLaunchKernelGGL(k_mixed_final, dim3(1), dim3(1024), 0, ls, (const SegHdr*)q.hdrs, g, sp,
+                         (const int*)q.status, q.mstate, (const MaskScore32*)q.fin32, (const uint32_t*)q.listA,
+                         (const int*)cA, (const MaskScore*)q.scoreA, (const uint32_t*)q.listB, (const int*)cB,
+                         (const MaskScore*)q.scoreB, q.decs);
       if (dump) {
         (*dump32)[g].resize(nmask);
-        (void)hipMemcpyAsync((*dump32)[g].data(), p.fin32, sizeof(MaskScore32) * nmask, hipMemcpyDeviceToHost, st);
+        (void)hipMemcpyAsync((*dump32)[g].data(), q.fin32, sizeof(MaskScore32) * nmask, hipMemcpyDeviceToHost, ls);
       }
     }
-    hipLaunchKernelGGL(k_apply, dim3(S), dim3(64), 0, st, (const SegHdr*)p.hdrs, g, (const int*)p.tab, p.T, p.St,
-                       (const DevDecision*)p.decs, (const double2*)p.P, (const TargetRec*)p.srec,
-                       (const TargetRec*)p.zrec, p.Vcur, p.A);
+    hipLaunchKernelGGL(k_apply, dim3(S), dim3(64), 0, ls, (const SegHdr*)q.hdrs, g, (const int*)q.tab, q.T, q.St,
+                       (const DevDecision*)q.decs, (const double2*)q.P, (const TargetRec*)q.srec,
+                       (const TargetRec*)q.zrec, q.Vcur, q.A);
+    if (nl > 1) (void)hipEventRecord(h->seg_ev[g], ls);
   }
+  if (nl > 1)
+    for (int l = 0; l < nl; ++l) {
+      (void)hipEventRecord(h->join_ev[l], h->lane_st[l]);
+      (void)hipStreamWaitEvent(st, h->join_ev[l], 0);
+    }
   hipLaunchKernelGGL(k_kron_yeq, dim3((n + 127) / 128), dim3(128), 0, st, p.T, p.St, (const double2*)p.z, p.yeq,
                      p.Yko, p.kp, p.status);
   hipLaunchKernelGGL(k_kron_diag, dim3((n + 127) / 128), dim3(128), 0, st, p.T, p.St, (const double2*)p.yeq, p.Ykd);
@@ -830,6 +951,19 @@ extern "C" int okr_reduce_feeder(okr_handle* h, const okr_yblocks* Y, const okr_
     h->ev.resize(2 * std::max(nseg, 1), nullptr);
     for (auto& e : h->ev) OKR_HIP(h, hipEventCreate(&e));
   }
+  if ((int)h->lane_st.size() != h->nlanes || (int)h->seg_ev.size() != nseg) {
+    drop_lanes(h);
+    for (int l = 0; l < h->nlanes; ++l) {
+      hipStream_t ls = h->stream;
+      if (h->nlanes > 1) OKR_HIP(h, hipStreamCreateWithFlags(&ls, hipStreamNonBlocking));
+      h->lane_st.push_back(ls);
+    }
+    h->seg_ev.assign(nseg, nullptr);
+    for (auto& e : h->seg_ev) OKR_HIP(h, hipEventCreateWithFlags(&e, hipEventDisableTiming));
+    h->join_ev.assign(h->nlanes, nullptr);
+    for (auto& e : h->join_ev) OKR_HIP(h, hipEventCreateWithFlags(&e, hipEventDisableTiming));
+    OKR_HIP(h, hipEventCreateWithFlags(&h->fork_ev, hipEventDisableTiming));
+  }
   if (mg->flags & OKR_FLAG_AUTOTUNE) {
     // time the scoring launches of a whole search once per candidate group
     // count; keep the fastest per segment size
@@ -850,7 +984,7 @@ extern "C" int okr_reduce_feeder(okr_handle* h, const okr_yblocks* Y, const okr_
       for (int c = 1; c <= std::min(S, kMaxSnapGroups); c *= 2) {
         h->sg_force = c;
         h->mpl_force = 1 << mi;
-        enqueue_search(h, p, Y, loads, &mt, st, &h->ev, nullptr, nullptr, nullptr, nullptr);
+        enqueue_search(h, d_workspace, Y, loads, &mt, st, &h->ev, nullptr, nullptr, nullptr, nullptr, true);
         const hipError_t e1 = hipGetLastError(), e2 = hipStreamSynchronize(st);
         if (e1 != hipSuccess || e2 != hipSuccess) {
           h->sg_force = h->mpl_force = 0;
@@ -896,7 +1030,8 @@ extern "C" int okr_reduce_feeder(okr_handle* h, const okr_yblocks* Y, const okr_
       drop_graph(h);
       OKR_HIP(h, hipStreamSynchronize(st));
       OKR_HIP(h, hipStreamBeginCapture(st, hipStreamCaptureModeThreadLocal));
-      enqueue_search(h, p, Y, loads, mg, st, nullptr, nullptr, nullptr, nullptr, nullptr);
+      // one stream inside the capture (segments in order)
+      enqueue_search(h, d_workspace, Y, loads, mg, st, nullptr, nullptr, nullptr, nullptr, nullptr, false);
       hipGraph_t gobj = nullptr;
       const hipError_t ec = hipStreamEndCapture(st, &gobj);
       if (ec != hipSuccess) OKR_FAIL(h, OKR_E_HIP, "graph capture failed: %s", hipGetErrorString(ec));
@@ -910,8 +1045,8 @@ extern "C" int okr_reduce_feeder(okr_handle* h, const okr_yblocks* Y, const okr_
     }
     OKR_HIP(h, hipGraphLaunch(h->gexec, st));
   } else {
-    enqueue_search(h, p, Y, loads, mg, st, timing ? &h->ev : nullptr, dump ? &h->dump : nullptr,
-                   dump ? &h->dump32 : nullptr, out->features, out->targets);
+    enqueue_search(h, d_workspace, Y, loads, mg, st, timing ? &h->ev : nullptr, dump ? &h->dump : nullptr,
+                   dump ? &h->dump32 : nullptr, out->features, out->targets, true);
     OKR_HIP(h, hipGetLastError());
   }
   // results (one synchronisation)

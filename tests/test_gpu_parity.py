@@ -300,3 +300,18 @@ def test_autotuned_launch_shape_gives_identical_results(okr):
             np.testing.assert_array_equal(out["Yk_diag"], ref["Yk_diag"])
     finally:
         R.close()
+
+
+@pytest.mark.parametrize("cfg,lanes", [("c2", 4), ("c3", 8)])
+def test_concurrent_lanes_give_identical_results(okr, cfg, lanes):
+    """Independent segments searched concurrently (lanes > 1) give bit-identical
+    decisions, per-segment errors and outputs to the in-order search."""
+    _say(f"lanes {cfg} seed 3 lanes={lanes}")
+    f = make_feeder(cfg, 3)
+    ref = okr.reduce_feeder(f, lanes=1, want_vhat=False)
+    out = okr.reduce_feeder(f, lanes=lanes, want_vhat=False)
+    assert [s["mask"] for s in out["segments"]] == [s["mask"] for s in ref["segments"]]
+    assert [s["e_loc"] for s in out["segments"]] == [s["e_loc"] for s in ref["segments"]]
+    np.testing.assert_array_equal(out["err_per_snapshot"], ref["err_per_snapshot"])
+    np.testing.assert_array_equal(out["Yk_diag"], ref["Yk_diag"])
+    np.testing.assert_array_equal(out["kept"], ref["kept"])
