@@ -25,6 +25,24 @@ sys.path.insert(0, ROOT)
 
 FP64_VECTOR_PEAK_TFLOPS = 78.6   # MI355X FP64 vector (256 CUs x 2.4 GHz x 128 flop/clk)
 
+# HBM bytes per launch of the FP64 scoring kernel on this workload, from the
+# FETCH_SIZE / WRITE_SIZE counters scaled by a known-size copy (see
+# profiles/k_score_fp64_c2_1000node_24snap.md), valid only for the sources
+# they were taken with: any change to them reports null.
+TRAFFIC_SOURCES = ["paper_2510_19608_amd/csrc/okr_score.hip", "paper_2510_19608_amd/csrc/okr_device.h",
+                   "paper_2510_19608_amd/csrc/okr_internal.h", "paper_2510_19608_amd/csrc/okr_host.cpp"]
+TRAFFIC_SHA1 = "a2e49002624b674099b1f17ad11b860f6a31362c"
+TRAFFIC_BYTES_PER_LAUNCH = 18632768
+
+
+def measured_traffic():
+    import hashlib
+    h = hashlib.sha1()
+    for rel in TRAFFIC_SOURCES:
+        with open(os.path.join(ROOT, rel), "rb") as fh:
+            h.update(fh.read())
+    return TRAFFIC_BYTES_PER_LAUNCH if h.hexdigest() == TRAFFIC_SHA1 else None
+
 
 def cpu_baseline(f, seconds=12.0):
     """FP64 oracle scoring masks of the first segment (initial state), as many
@@ -95,7 +113,7 @@ def surrogate_mode(f, args, plain_ms, ref, ncand):
     n_pairs = int(X.shape[0])
     del X, t
     R = Reducer(f, device="cuda:0", graph=True, surrogate=params, top_k=args.top_k)
-    ms = timed_runs(R, args.reps, not args.no_autotune)
+    ms = timed_runs(R, args.reps, args.autotune)
     masks, pops, res = decisions(R)
     fallback = sum(1 for s in res["segments"] if s["n_scored"] > s["n_refined"])
     R.close()
@@ -118,8 +136,9 @@ def main():
     ap.add_argument("--no-modes", action="store_true")
     ap.add_argument("--modes", default="plain,mixed,surrogate",
                     help="comma-separated forms timed for time-to-optimal (plain is always timed)")
-    ap.add_argument("--no-autotune", action="store_true",
-                    help="keep the default scoring launch shape (no tuning run before the warm-up)")
+    ap.add_argument("--lanes", type=int, default=1, help="concurrent segment lanes of the timed searches")
+    ap.add_argument("--autotune", action="store_true",
+                    help="tune the scoring launch shape before the warm-up (default: the library's default shape)")
     ap.add_argument("--copy-probe-mib", type=int, default=0,
                     help="first run one device-to-device copy of this many MiB (a known-size reference "
                          "for hardware byte counters)")
@@ -140,9 +159,12 @@ def main():
         torch.cuda.synchronize()
         del src, dst
     f = make_feeder("c2", args.seed)
-    R = Reducer(f, device="cuda:0", timing=True)
+    # one lane: on this workload the scoring launches fill the GPU, concurrent
+    # segment lanes add no throughput, and with one lane the per-launch event
+    # times of the scoring kernel are not stretched by overlap
+    R = Reducer(f, device="cuda:0", timing=True, lanes=args.lanes)
     ncand = int(R.sizes.n_candidates)
-    if not args.no_autotune:
+    if args.autotune:
         R.run(replan=False, autotune=True)
     for _ in range(args.warmup):
         R.run(replan=False)
@@ -158,6 +180,7 @@ def main():
     dt = time.perf_counter() - t0
     ref_masks, ref_pops, out = decisions(R)
     R.close()
+    shapes = sorted({(s["k"], s["score_groups"], s["score_mpl"]) for s in out["segments"]})
     ms_per_step = dt * 1e3 / args.steps
     launches = out["n_score_launches"] * args.steps
     achieved = flops / (kern_ms * 1e-3) / 1e12 if kern_ms > 0 else None
@@ -181,21 +204,22 @@ def main():
                    "max_err": out["max_err"], "parallelism": "single GPU"},
         "roofline": {"bound": "alu", "achieved": achieved, "peak": FP64_VECTOR_PEAK_TFLOPS,
                      "unit": "TFLOP/s", "frac": (achieved / FP64_VECTOR_PEAK_TFLOPS) if achieved else None,
-                     "traffic": None, "kernel": "okr::k_score_fp64",
+                     "traffic": measured_traffic(), "kernel": "okr::k_score_fp64",
                      "avg_launch_us": kern_ms * 1e3 / max(launches, 1),
-                     "flops_per_launch": flops / max(launches, 1)},
+                     "flops_per_launch": flops / max(launches, 1),
+                     "launch_shapes_k_groups_mpl": shapes},
     }
     if not args.no_modes:
         modes = {}
         Rg = Reducer(f, device="cuda:0", graph=True)
-        plain_ms = timed_runs(Rg, args.reps, not args.no_autotune)
+        plain_ms = timed_runs(Rg, args.reps, args.autotune)
         m, p, res = decisions(Rg)
         Rg.close()
         modes["plain_fp64"] = mode_entry("plain", plain_ms, plain_ms, m, p, res, ref_masks, ref_pops, ncand)
         wanted = set(args.modes.split(","))
         if "mixed" in wanted:
             Rm = Reducer(f, device="cuda:0", graph=True, precision="mixed")
-            ms = timed_runs(Rm, args.reps, not args.no_autotune)
+            ms = timed_runs(Rm, args.reps, args.autotune)
             m, p, res = decisions(Rm)
             refined = sum(s["n_refined"] for s in res["segments"])
             dev = max(s["fp32_dev"] for s in res["segments"])

@@ -160,6 +160,8 @@ typedef struct {
     float score_ms;     /* scoring-kernel time (OKR_FLAG_TIMING) */
     int32_t n_refined;  /* MIXED: masks rescored in FP64 (shortlists A + B) */
     double fp32_dev;    /* MIXED: max |e32 - e64| over rescored masks with e64 <= 2 e_bar */
+    int32_t score_groups;   /* FP64 scoring launch shape: snapshot groups ... */
+    int32_t score_mpl;      /* ... and masks per lane (default rule or autotuned) */
 } okr_segment_result;
 
 /* Outputs (HOST buffers owned by the caller). */

@@ -98,12 +98,13 @@ constexpr int kRefineBlocks = 256;
 
 size_t align256(size_t x) { return (x + 255) & ~size_t(255); }
 
-// Snapshot groups of a scoring launch with mpl masks per lane: enough blocks
-// to fill the chip (about 2048 blocks of 4 waves), each group a contiguous
-// run of snapshots.
-int snap_groups_default(int k, int S, int* spg, int mpl = 1) {
+// Snapshot groups of a scoring launch with mpl masks per lane: about 512
+// blocks of 4 waves (two waves per SIMD, each with mpl independent masks per
+// lane; measured faster on MI355X than more, thinner waves), each group a
+// contiguous run of snapshots.
+int snap_groups_default(int k, int S, int* spg, int mpl = 1, int target_blocks = 512) {
   const int mblocks = (int)((((uint64_t)1 << k) + kScoreThreads * mpl - 1) / (kScoreThreads * mpl));
-  int SG = std::min(S, std::max(1, 2048 / mblocks));
+  int SG = std::min(S, std::max(1, target_blocks / mblocks));
   SG = std::min(SG, kMaxSnapGroups);
   *spg = (S + SG - 1) / SG;
   return (S + *spg - 1) / *spg;
@@ -166,13 +167,13 @@ struct okr_handle {
 };
 
 namespace {
-constexpr int kDefaultMpl = 2;
-
-// Masks per lane of the FP64 scoring launch for a segment of k nodes.
+// Masks per lane of the FP64 scoring launch for a segment of k nodes: forced,
+// tuned, else 4 for large segments, fewer for small ones (each lane must
+// still get masks).
 int score_mpl(const okr_handle* h, int k) {
   if (h->mpl_force) return h->mpl_force;
   if ((int)h->mpl_tuned.size() > k && h->mpl_tuned[k]) return h->mpl_tuned[k];
-  return kDefaultMpl;
+  return k >= 12 ? 4 : (k >= 10 ? 2 : 1);
 }
 
 // Snapshot groups of the FP64 scoring launch for a segment of k nodes: the
@@ -490,7 +491,7 @@ extern "C" int okr_plan(okr_handle* h, const okr_topology* topo, const okr_margi
     size_t most = 1;
     for (int k = 1; k <= h->kmax; ++k) {
       int spg;
-      most = std::max(most, (size_t)snap_groups_default(k, S, &spg) << k);
+      most = std::max(most, (size_t)snap_groups_default(k, S, &spg, 1, 2048) << k);
     }
     const size_t nm = (size_t)1 << h->kmax, nt = (nm + 63) / 64;
     L.P32 = take(sizeof(Pair32) * 3 * (size_t)S * kMaxPairs);
@@ -746,10 +747,10 @@ void enqueue_search(okr_handle* h, void* ws, const okr_yblocks* Y, const okr_loa
     const int mblocks = (int)((nmask + kScoreThreads * mpl - 1) / (kScoreThreads * mpl));
     int spg;
     const int SG = snap_groups(h, k, &spg);
-    // the FP32 screen keeps one mask per lane and the default group rule
+    // the FP32 screen keeps one mask per lane and about 2048 blocks
     const int mblocks32 = (int)((nmask + kScoreThreads - 1) / kScoreThreads);
     int spg32;
-    const int SG32 = snap_groups_default(k, S, &spg32);
+    const int SG32 = snap_groups_default(k, S, &spg32, 1, 2048);
     const int* gate = nullptr;
     if (surr || feat_out) {
       hipLaunchKernelGGL(k_surr_tables, dim3(kMaxPairs + kMaxK), dim3(64), 0, ls,
@@ -1101,6 +1102,11 @@ extern "C" int okr_reduce_feeder(okr_handle* h, const okr_yblocks* Y, const okr_
     R.e_min = decs[g].e_min;
     R.ambiguous = decs[g].ambiguous;
     R.n_scored = 1 << k;
+    {
+      int spg;
+      R.score_groups = snap_groups(h, k, &spg);
+      R.score_mpl = score_mpl(h, k);
+    }
     // algorithmic FP64 flops: per slot and mask, reduced -> 6 + 4|phi|,
     // kept -> 14|phi| (half the masks each); per zone entry 14
     double fl = 0.0;
