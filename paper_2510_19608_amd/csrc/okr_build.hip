@@ -25,6 +25,9 @@ __device__ __forceinline__ double2 b_cmul(double2 a, double2 b) {
 // status bit set when a structural invariant fails (the segment is then
 // skipped by the scoring path and the call reports an error)
 constexpr int kStatusBuild = 64;
+constexpr int kOmegaLds = 4096;  // Omega_g nodes whose zone classification is kept in shared memory
+// structural part of a segment's tables (chains, nesting, slots, pairs, ranges)
+constexpr int kTabLds = kMaxK * kChainInts + kMaxK * kMaxK + kMaxK * kSlotInts + kMaxPairs * kPairInts + 3 * kMaxK;
 
 // Child of kept node h on the tree path down to its descendant v.
 __device__ __forceinline__ int child_toward(const Topo& T, int h, int v) {
@@ -38,15 +41,20 @@ __device__ __forceinline__ int child_toward(const Topo& T, int h, int v) {
 
 __global__ __launch_bounds__(256) void k_build_struct(Topo T, State St, int g, int S, SegHdr* __restrict__ hdrs,
                                                       int* __restrict__ tab, int tab_cap, int* __restrict__ status) {
-  __shared__ int s_top[kMaxK], s_tops[kMaxK], s_slotnode[kMaxK], s_slotbit[kMaxK], s_slotchain[kMaxK];
+  __shared__ int s_top[kMaxK], s_slotnode[kMaxK], s_slotbit[kMaxK], s_slotchain[kMaxK];
   __shared__ int s_cslot0[kMaxK + 1], s_head[kMaxK], s_outer[kMaxK], s_jslot[kMaxK];
   __shared__ int s_spos[kMaxK], s_ssize[kMaxK], s_sph[kMaxK];           // segment node j
   __shared__ int s_tpos[kMaxK], s_tsize[kMaxK], s_thead[kMaxK], s_thph[kMaxK];  // its chain top
   __shared__ int s_cpos[kMaxK], s_csize[kMaxK], s_chph[kMaxK];          // chain c: top pos/size, head phase
-  __shared__ int s_rs[kMaxK], s_re[kMaxK], s_rcum[kMaxK + 1];
+  __shared__ int s_rs[kMaxK], s_rcum[kMaxK + 1];                       // Omega_g ranges: start, cumulative size
+  __shared__ int s_seg[kMaxK], s_thpos[kMaxK], s_first[kMaxK];          // segment node j, its top's head position,
+                                                                        // first segment node with its top
+  __shared__ int s_chpos[kMaxK], s_rkeep[kMaxK], s_depth[kMaxK];        // chain c: head position, new range, nesting
   __shared__ int s_keycnt[kMaxK * 3], s_keyoff[kMaxK * 3], s_keycur[kMaxK * 3];
   __shared__ SegHdr s_h;
   __shared__ int s_err, s_nch;
+  __shared__ int s_zi[kOmegaLds], s_zk[kOmegaLds];  // zone pass: node and key of Omega index q
+  __shared__ int s_tab[kTabLds];                     // structural tables before they are written out
   const int* parent = T.parent;
   const int* segment = T.segment;
   const int tid = threadIdx.x;
@@ -84,266 +92,294 @@ __global__ __launch_bounds__(256) void k_build_struct(Topo T, State St, int g, i
     s_tsize[tid] = T.size[c];
     s_thead[tid] = hd;
     s_thph[tid] = hd >= 0 ? T.phase[hd] : 0;
+    s_thpos[tid] = hd >= 0 ? T.pos[hd] : -1;
+    s_seg[tid] = e;
   }
   __syncthreads();
-  if (tid == 0 && !s_err) {
-    // distinct chain tops (shared-memory data only from here on)
-    int nch = 0, tj[kMaxK];
-    for (int j = 0; j < k; ++j) {
-      const int c = s_top[j];
-      bool seen = false;
-      for (int q = 0; q < nch; ++q) seen |= (s_tops[q] == c);
-      if (!seen) {
-        tj[nch] = j;
-        s_tops[nch++] = c;
-      }
-    }
-    // chains in preorder of their tops
-    for (int a = 1; a < nch; ++a) {
-      const int v = s_tops[a], vj = tj[a];
-      int b = a - 1;
-      while (b >= 0 && s_tpos[tj[b]] > s_tpos[vj]) {
-        s_tops[b + 1] = s_tops[b];
-        tj[b + 1] = tj[b];
-        --b;
-      }
-      s_tops[b + 1] = v;
-      tj[b + 1] = vj;
-    }
-    for (int c = 0; c < nch; ++c) {
-      s_cpos[c] = s_tpos[tj[c]];
-      s_csize[c] = s_tsize[tj[c]];
-      s_chph[c] = s_thph[tj[c]];
-    }
-    // slots chain by chain, top to bottom (segment nodes are in preorder)
-    int ns = 0;
-    for (int c = 0; c < nch; ++c) {
-      s_cslot0[c] = ns;
-      for (int j = 0; j < k; ++j)
-        if (s_top[j] == s_tops[c]) {
-          s_slotnode[ns] = T.seg_nodes[o0 + j];
-          s_slotbit[ns] = j;
-          s_slotchain[ns] = c;
-          s_jslot[j] = ns;
-          ++ns;
-        }
-      s_head[c] = s_thead[tj[c]];
-    }
-    s_cslot0[nch] = ns;
-    if (ns != k) s_err = 1;
-    s_nch = nch;
+  // chains: one per distinct chain top, ordered by the tops' preorder
+  // positions (distinct nodes, so the order is strict); slots chain by chain,
+  // top to bottom (segment nodes are in preorder).  One thread per segment
+  // node, shared-memory data only from here on.
+  if (!s_err && tid < k) {
+    const int top = s_top[tid];
+    int j0 = tid;  // first segment node with this chain top
+    for (int q = tid - 1; q >= 0; --q)
+      if (s_top[q] == top) j0 = q;
+    s_first[tid] = j0;
   }
   __syncthreads();
-  // outer chain: the chain whose bottom slot is the deepest segment node
-  // above the head (a subtree test against every segment node)
-  if (!s_err && tid < s_nch) {
-    const int c = tid, hd = s_head[c];
-    const int ph = hd >= 0 ? T.pos[hd] : -1;
+  if (!s_err && tid < k) {
+    const int j = tid, j0 = s_first[j], tp = s_tpos[j];
+    int c = 0, before = 0, within = 0, nch = 0;
+    for (int q = 0; q < k; ++q) {
+      const bool lower = s_tpos[q] < tp;  // q's chain comes before j's
+      const bool opens = s_first[q] == q;
+      nch += opens;
+      c += opens && lower;
+      before += lower;
+      within += (s_first[q] == j0) && q < j;
+    }
+    const int s = before + within;
+    s_jslot[j] = s;
+    s_slotnode[s] = s_seg[j];
+    s_slotbit[s] = j;
+    s_slotchain[s] = c;
+    if (j0 == j) {
+      s_cpos[c] = tp;
+      s_csize[c] = s_tsize[j];
+      s_chph[c] = s_thph[j];
+      s_head[c] = s_thead[j];
+      s_chpos[c] = s_thpos[j];
+      s_cslot0[c] = before;
+    }
+    if (j == 0) {
+      s_nch = nch;
+      s_cslot0[nch] = k;
+    }
+  }
+  __syncthreads();
+  // per chain: the outer chain (whose bottom slot is the deepest segment node
+  // above the head), the path and consecutive-bit invariants, and whether its
+  // top's subtree starts a new Omega_g range (laminar intervals in preorder:
+  // a top inside an earlier top's subtree adds nothing)
+  const int nch = s_nch;
+  if (!s_err && tid < nch) {
+    const int c = tid, ph = s_chpos[c];
     int best = -1;
     for (int j = 0; j < k; ++j)
-      if (hd >= 0 && s_spos[j] <= ph && ph < s_spos[j] + s_ssize[j] && (best < 0 || s_spos[j] > s_spos[best]))
+      if (ph >= 0 && s_spos[j] <= ph && ph < s_spos[j] + s_ssize[j] && (best < 0 || s_spos[j] > s_spos[best]))
         best = j;
-    s_outer[c] = -1;
+    int oc = -1;
     if (best >= 0) {
-      const int u = T.seg_nodes[o0 + best];
-      int s = -1;
-      for (int q = 0; q < k; ++q)
-        if (s_slotnode[q] == u) s = q;
-      const int oc = s >= 0 ? s_slotchain[s] : -1;
-      if (s < 0 || s != s_cslot0[oc + 1] - 1 || oc >= c) atomicOr(&s_err, 1);
-      else s_outer[c] = oc;
+      const int s = s_jslot[best];
+      oc = s_slotchain[s];
+      if (s != s_cslot0[oc + 1] - 1 || oc >= c) atomicOr(&s_err, 1);
     }
+    s_outer[c] = oc;
+    // every chain is a path: each slot lies below the previous one (the first
+    // below the chain top); its nodes have at most one child, so its slots
+    // are consecutive segment nodes in preorder: consecutive mask bits
+    int pu = s_cpos[c], su = s_csize[c];
+    const int s0 = s_cslot0[c], s1 = s_cslot0[c + 1];
+    for (int s = s0; s < s1; ++s) {
+      const int j = s_slotbit[s], pv = s_spos[j];
+      if (!(pu <= pv && pv < pu + su) || (s > s0 && pv == pu) || j != s_slotbit[s0] + (s - s0))
+        atomicOr(&s_err, 1);
+      pu = pv;
+      su = s_ssize[j];
+    }
+    int keep = 1;
+    for (int q = 0; q < c; ++q)
+      if (s_cpos[q] <= s_cpos[c] && s_cpos[c] < s_cpos[q] + s_csize[q]) keep = 0;
+    s_rkeep[c] = keep;
   }
   __syncthreads();
+  if (tid < nch) {
+    int d = 0;  // nesting depth (outer chains have smaller indices)
+    if (!s_err)
+      for (int x = tid; x >= 0; x = s_outer[x]) ++d;
+    s_depth[tid] = d;
+  }
+  __syncthreads();
+  // table layout: every thread forms the same sums from shared memory
+  int nest_tot = 0, npairs = 0, nr = 0, nom = 0;
+  for (int c = 0; c < nch; ++c) {
+    const int n = s_cslot0[c + 1] - s_cslot0[c];
+    nest_tot += s_depth[c];
+    npairs += n * (n + 1) / 2;
+    nr += s_rkeep[c];
+    nom += s_rkeep[c] ? s_csize[c] : 0;
+  }
+  const int o_nest = nch * kChainInts, o_slot = o_nest + nest_tot, o_pair = o_slot + k * kSlotInts;
+  const int o_range = o_pair + npairs * kPairInts, o_zent = o_range + 3 * nr;
   if (tid == 0) {
-    int err = s_err;
-    const int nch = s_nch, ns = k;
     SegHdr H;
     for (int q = 0; q < (int)(sizeof(SegHdr) / sizeof(int)); ++q) ((int*)&H)[q] = 0;
     H.g = g;
     H.k = k;
     H.S = S;
-    // table layout
-    int o = 0;
-    H.o_chain = o; o += nch * kChainInts;
-    H.o_nest = o;
-    if (o + nch * nch > tab_cap) err = 1;
-    int nest_off[kMaxK], nest_len[kMaxK];
-    for (int c = 0; c < nch && !err; ++c) {
-      int d = 0;
-      for (int x = c; x >= 0; x = s_outer[x]) ++d;
-      nest_off[c] = o - H.o_nest;
-      nest_len[c] = d;
-      int q = d - 1;
-      for (int x = c; x >= 0; x = s_outer[x]) tab[o + q--] = x;
-      o += d;
-    }
-    // every chain is a path: each slot lies below the previous one (the
-    // first below the chain top)
-    for (int c = 0; c < nch && !err; ++c) {
-      int pu = s_cpos[c], su = s_csize[c];
-      for (int s = s_cslot0[c]; s < s_cslot0[c + 1]; ++s) {
-        const int j = s_slotbit[s], pv = s_spos[j];
-        if (!(pu <= pv && pv < pu + su) || (s > s_cslot0[c] && pv == pu)) { err = 1; break; }
-        pu = pv;
-        su = s_ssize[j];
-      }
-    }
-    H.o_slot = o; o += ns * kSlotInts;
-    H.o_pair = o;
-    int npairs = 0, pairbase[kMaxK];
-    for (int c = 0; c < nch && !err; ++c)
-      for (int s = s_cslot0[c]; s < s_cslot0[c + 1]; ++s) {
-        const int r = s - s_cslot0[c];
-        pairbase[s] = npairs;
-        for (int sx = 0; sx <= r; ++sx) {
-          if (npairs >= kMaxPairs || o + kPairInts > tab_cap) { err = 1; break; }
-          tab[o + PR_RNODE] = s_slotnode[s];
-          tab[o + PR_SUPER] = (sx == 0) ? s_head[c] : s_slotnode[s_cslot0[c] + sx - 1];
-          tab[o + PR_RSLOT] = s;
-          o += kPairInts;
-          ++npairs;
-        }
-      }
-    // Omega_g ranges in preorder: union of the chain tops' subtrees
-    int nr = 0;
-    for (int c = 0; c < nch && !err; ++c) {
-      const int a = s_cpos[c], b = a + s_csize[c];
-      int q = nr - 1;
-      while (q >= 0 && s_rs[q] > a) { s_rs[q + 1] = s_rs[q]; s_re[q + 1] = s_re[q]; --q; }
-      s_rs[q + 1] = a;
-      s_re[q + 1] = b;
-      ++nr;
-    }
-    int m = 0;
-    for (int q = 0; q < nr; ++q) {
-      if (m > 0 && s_rs[q] < s_re[m - 1]) {
-        s_re[m - 1] = max(s_re[m - 1], s_re[q]);
-      } else {
-        s_rs[m] = s_rs[q];
-        s_re[m] = s_re[q];
-        ++m;
-      }
-    }
-    nr = m;
-    s_rcum[0] = 0;
-    for (int q = 0; q < nr; ++q) s_rcum[q + 1] = s_rcum[q] + (s_re[q] - s_rs[q]);
-    H.o_range = o;
-    if (o + 3 * nr > tab_cap) err = 1;
-    for (int q = 0; q < nr && !err; ++q) {
-      tab[o + 3 * q] = s_rs[q];
-      tab[o + 3 * q + 1] = s_re[q];
-      tab[o + 3 * q + 2] = s_rcum[q];
-    }
-    o += 3 * nr;
+    H.o_chain = 0;
+    H.o_nest = o_nest;
+    H.o_slot = o_slot;
+    H.o_pair = o_pair;
+    H.o_range = o_range;
+    H.o_zent = o_zent;
     H.nrange = nr;
-    H.nomega = s_rcum[nr];
-    H.o_zent = o;
+    H.nomega = nom;
     H.nchains = nch;
-    H.nslots = ns;
+    H.nslots = k;
     H.npairs = npairs;
-    // chain and slot records (zone ranges filled after the zone pass)
-    for (int c = 0; c < nch && !err; ++c) {
-      int* cr = tab + H.o_chain + c * kChainInts;
-      cr[C_HEAD] = s_head[c];
-      cr[C_NSLOT] = s_cslot0[c + 1] - s_cslot0[c];
-      cr[C_SLOT0] = s_cslot0[c];
-      cr[C_NEST_OFF] = nest_off[c];
-      cr[C_NEST_LEN] = nest_len[c];
-      cr[C_OUTER] = s_outer[c];
-      cr[C_PHASE] = s_chph[c];
-      cr[C_BIT0] = s_slotbit[s_cslot0[c]];
-      cr[C_PAIR0] = pairbase[s_cslot0[c]];
-      int phw[3] = {0, 0, 0};
-      for (int s = s_cslot0[c]; s < s_cslot0[c + 1]; ++s) {
-        const int r = s - s_cslot0[c];
-        phw[r >> 3] |= s_sph[s_slotbit[s]] << (3 * (r & 7));
-        // a chain's nodes have at most one child, so its slots are consecutive
-        // segment nodes in preorder: consecutive mask bits
-        if (s_slotbit[s] != s_slotbit[s_cslot0[c]] + r) err = 1;
-      }
-      cr[C_PHW0] = phw[0];
-      cr[C_PHW1] = phw[1];
-      cr[C_PHW2] = phw[2];
-      for (int p = 0; p < 3; ++p) { cr[C_ZOFF0 + p] = 0; cr[C_ZCNT0 + p] = 0; }
-    }
-    for (int s = 0; s < ns && !err; ++s) {
-      int* sr = tab + H.o_slot + s * kSlotInts;
-      sr[SL_NODE] = s_slotnode[s];
-      sr[SL_BIT] = s_slotbit[s];
-      sr[SL_PHASE] = s_sph[s_slotbit[s]];
-      sr[SL_PAIRBASE] = pairbase[s];
-      sr[SL_CHAIN] = s_slotchain[s];
-      St.slot_of[s_slotnode[s]] = s;
-    }
-    for (int q = 0; q < kMaxK * 3; ++q) { s_keycnt[q] = 0; s_keycur[q] = 0; }
-    H.valid = err ? 0 : 1;
+    // the structural part must fit the segment's table (and the shared image,
+    // which holds the largest possible one)
+    if (o_zent > tab_cap || o_zent > kTabLds) s_err = 1;
+    H.valid = s_err ? 0 : 1;
     s_h = H;
-    s_err = err;
+  }
+  if (tid < kMaxK * 3) {
+    s_keycnt[tid] = 0;
+    s_keycur[tid] = 0;
   }
   __syncthreads();
-  SegHdr H = s_h;
   if (s_err) {
-    if (threadIdx.x == 0) {
+    if (tid == 0) {
+      SegHdr H = s_h;
       H.valid = 0;
       hdrs[g] = H;
       atomicOr(status, kStatusBuild);
     }
     return;
   }
-  const int nr = H.nrange, nom = H.nomega;
-  const int* rg = tab + H.o_range;
-  // zone targets: kept nodes of Omega_g outside the segment; anchor = chain
-  // whose bottom slot is the first segment node above the target
-  for (int pass = 0; pass < 2; ++pass) {
-    for (int q = threadIdx.x; q < nom; q += blockDim.x) {
-      int r = 0;
-      while (r + 1 < nr && rg[3 * (r + 1) + 2] <= q) ++r;
-      const int i = T.pre[rg[3 * r] + (q - rg[3 * r + 2])];
-      if (segment[i] == g || !St.kept[i]) continue;
-      // anchor: the deepest segment node whose subtree holds i
-      const int pi = T.pos[i];
-      int best = -1;
-      for (int j = 0; j < k; ++j)
-        if (s_spos[j] < pi && pi < s_spos[j] + s_ssize[j] && (best < 0 || s_spos[j] > s_spos[best])) best = j;
-      const int s = (best >= 0) ? s_jslot[best] : -1;
-      if (s < 0) { atomicOr(&s_err, 1); continue; }
-      const int c = tab[H.o_slot + s * kSlotInts + SL_CHAIN];
-      const int* cr = tab + H.o_chain + c * kChainInts;
-      if (s != cr[C_SLOT0] + cr[C_NSLOT] - 1) { atomicOr(&s_err, 1); continue; }  // must be the chain's bottom
-      const unsigned ph = T.phase[i];
-      for (int p = 0; p < 3; ++p) {
-        if (!(ph >> p & 1u)) continue;
-        const int key = c * 3 + p;
-        if (pass == 0) {
-          atomicAdd(&s_keycnt[key], 1);
-        } else {
-          const int idx = s_keyoff[key] + atomicAdd(&s_keycur[key], 1);
-          int* ze = tab + H.o_zent + 3 * idx;
-          ze[0] = i;
-          ze[1] = p;
-          ze[2] = c;
-          St.zent_of[i * 3 + p] = idx;
-        }
-      }
+  // records: one thread per chain, one per slot
+  if (tid < nch) {
+    const int c = tid, s0 = s_cslot0[c], n = s_cslot0[c + 1] - s0;
+    int nest_off = 0, pair0 = 0, ridx = 0, rcum = 0;
+    for (int q = 0; q < c; ++q) {
+      const int nq = s_cslot0[q + 1] - s_cslot0[q];
+      nest_off += s_depth[q];
+      pair0 += nq * (nq + 1) / 2;
+      ridx += s_rkeep[q];
+      rcum += s_rkeep[q] ? s_csize[q] : 0;
     }
-    __syncthreads();
-    if (pass == 0 && threadIdx.x == 0) {
-      int acc = 0;
-      for (int key = 0; key < H.nchains * 3; ++key) {
-        s_keyoff[key] = acc;
-        int* cr = tab + H.o_chain + (key / 3) * kChainInts;
-        cr[C_ZOFF0 + key % 3] = acc;
-        cr[C_ZCNT0 + key % 3] = s_keycnt[key];
-        acc += s_keycnt[key];
-      }
-      s_h.nz = acc;
-      s_h.total_ints = H.o_zent + 3 * acc;
+    const int d = s_depth[c];
+    int q = d - 1;
+    for (int x = c; x >= 0; x = s_outer[x]) s_tab[o_nest + nest_off + q--] = x;
+    if (s_rkeep[c]) {
+      s_tab[o_range + 3 * ridx] = s_cpos[c];
+      s_tab[o_range + 3 * ridx + 1] = s_cpos[c] + s_csize[c];
+      s_tab[o_range + 3 * ridx + 2] = rcum;
+    }
+    int phw[3] = {0, 0, 0};
+    for (int r = 0; r < n; ++r) phw[r >> 3] |= s_sph[s_slotbit[s0 + r]] << (3 * (r & 7));
+    int* cr = s_tab + c * kChainInts;
+    cr[C_HEAD] = s_head[c];
+    cr[C_NSLOT] = n;
+    cr[C_SLOT0] = s0;
+    cr[C_NEST_OFF] = nest_off;
+    cr[C_NEST_LEN] = d;
+    cr[C_OUTER] = s_outer[c];
+    cr[C_PHASE] = s_chph[c];
+    cr[C_BIT0] = s_slotbit[s0];
+    cr[C_PAIR0] = pair0;
+    cr[C_PHW0] = phw[0];
+    cr[C_PHW1] = phw[1];
+    cr[C_PHW2] = phw[2];
+    for (int p = 0; p < 3; ++p) {
+      cr[C_ZOFF0 + p] = 0;  // zone ranges filled after the zone pass
+      cr[C_ZCNT0 + p] = 0;
+    }
+  }
+  if (tid < k) {
+    // slot s = r-th slot of chain c: pairs (super, reduced) with the super
+    // node the head or one of the r slots above it
+    const int s = tid, c = s_slotchain[s], s0 = s_cslot0[c], r = s - s0;
+    int pair0 = 0;
+    for (int q = 0; q < c; ++q) {
+      const int nq = s_cslot0[q + 1] - s_cslot0[q];
+      pair0 += nq * (nq + 1) / 2;
+    }
+    const int pb = pair0 + r * (r + 1) / 2;
+    int* sr = s_tab + o_slot + s * kSlotInts;
+    sr[SL_NODE] = s_slotnode[s];
+    sr[SL_BIT] = s_slotbit[s];
+    sr[SL_PHASE] = s_sph[s_slotbit[s]];
+    sr[SL_PAIRBASE] = pb;
+    sr[SL_CHAIN] = c;
+    for (int sx = 0; sx <= r; ++sx) {
+      int* pr = s_tab + o_pair + (pb + sx) * kPairInts;
+      pr[PR_RNODE] = s_slotnode[s];
+      pr[PR_SUPER] = (sx == 0) ? s_head[c] : s_slotnode[s0 + sx - 1];
+      pr[PR_RSLOT] = s;
+    }
+    St.slot_of[s_slotnode[s]] = s;
+  }
+  __syncthreads();
+  // the structural tables, built in shared memory, written out by all threads
+  for (int q = tid; q < o_zent; q += blockDim.x) tab[q] = s_tab[q];
+  // Omega_g ranges for the zone pass (shared copy)
+  if (tid < nch && s_rkeep[tid]) {
+    int ridx = 0, rcum = 0;
+    for (int q = 0; q < tid; ++q) {
+      ridx += s_rkeep[q];
+      rcum += s_rkeep[q] ? s_csize[q] : 0;
+    }
+    s_rs[ridx] = s_cpos[tid];
+    s_rcum[ridx] = rcum;
+  }
+  if (tid == 0) s_rcum[nr] = nom;
+  __syncthreads();
+  SegHdr H = s_h;
+  // zone targets: kept nodes of Omega_g outside the segment; anchor = chain
+  // whose bottom slot is the first segment node above the target.  The
+  // counting pass keeps what it found for the first kOmegaLds nodes in
+  // shared memory, so the placing pass re-reads nothing for them; ranges,
+  // slot chains and chain bottoms come from shared memory throughout.
+  auto classify = [&](int q, int& node, int& key) {  // key = chain * 8 | phase bits, -1: not a target
+    int r = 0;
+    while (r + 1 < nr && s_rcum[r + 1] <= q) ++r;
+    const int i = T.pre[s_rs[r] + (q - s_rcum[r])];
+    node = i;
+    key = -1;
+    if (segment[i] == g || !St.kept[i]) return;
+    const int pi = T.pos[i];
+    int best = -1;
+    for (int j = 0; j < k; ++j)
+      if (s_spos[j] < pi && pi < s_spos[j] + s_ssize[j] && (best < 0 || s_spos[j] > s_spos[best])) best = j;
+    const int s = (best >= 0) ? s_jslot[best] : -1;
+    if (s < 0) { atomicOr(&s_err, 1); return; }
+    const int c = s_slotchain[s];
+    if (s != s_cslot0[c + 1] - 1) { atomicOr(&s_err, 1); return; }  // must be the chain's bottom
+    key = c * 8 + (int)T.phase[i];
+  };
+  for (int q = threadIdx.x; q < nom; q += blockDim.x) {
+    int i, key;
+    classify(q, i, key);
+    if (q < kOmegaLds) {
+      s_zi[q] = i;
+      s_zk[q] = key;
+    }
+    if (key < 0) continue;
+    for (int p = 0; p < 3; ++p)
+      if (key >> p & 1) atomicAdd(&s_keycnt[(key >> 3) * 3 + p], 1);
+  }
+  __syncthreads();
+  // zone entries grouped by key (chain, phase): offsets by an exclusive sum
+  if (!s_err && tid < nch * 3) {
+    int acc = 0;
+    for (int q = 0; q < tid; ++q) acc += s_keycnt[q];
+    const int cnt = s_keycnt[tid];
+    s_keyoff[tid] = acc;
+    int* cr = tab + H.o_chain + (tid / 3) * kChainInts;
+    cr[C_ZOFF0 + tid % 3] = acc;
+    cr[C_ZCNT0 + tid % 3] = cnt;
+    if (tid == nch * 3 - 1) {
+      s_h.nz = acc + cnt;
+      s_h.total_ints = H.o_zent + 3 * (acc + cnt);
       if (s_h.total_ints > tab_cap) s_err = 1;
     }
-    __syncthreads();
-    if (s_err) break;
   }
+  __syncthreads();
+  if (!s_err)
+    for (int q = threadIdx.x; q < nom; q += blockDim.x) {
+      int i, key;
+      if (q < kOmegaLds) {
+        i = s_zi[q];
+        key = s_zk[q];
+      } else {
+        classify(q, i, key);
+      }
+      if (key < 0) continue;
+      const int c = key >> 3;
+      for (int p = 0; p < 3; ++p) {
+        if (!(key >> p & 1)) continue;
+        const int idx = s_keyoff[c * 3 + p] + atomicAdd(&s_keycur[c * 3 + p], 1);
+        int* ze = tab + H.o_zent + 3 * idx;
+        ze[0] = i;
+        ze[1] = p;
+        ze[2] = c;
+        St.zent_of[i * 3 + p] = idx;
+      }
+    }
+  __syncthreads();
   if (threadIdx.x == 0) {
     H = s_h;
     if (s_err) {

@@ -46,6 +46,7 @@ __global__ void k_kron_diag(Topo, State, const double2*, double2*);
 __global__ void k_sqrt_selftest(const double*, double*, int);
 __global__ void k_build_mixed(const SegHdr*, int, const int*, int, const double2*, const double2*, const TargetRec*,
                               const double2*, const TargetRec*, double, double, Pair32*, Rec32*, Head32*, Rec32*);
+template <int M>
 __global__ void k_score_fp32(const SegHdr*, int, const int*, const Pair32*, const Rec32*, const Head32*, const Rec32*,
                              const double*, int, int, SelParams, MaskScore32*, MaskScore32*, TileRec32*, int*);
 __global__ void k_mixed_select_a(const SegHdr*, int, const MaskScore32*, const TileRec32*, SelParams, const int*,
@@ -491,7 +492,7 @@ extern "C" int okr_plan(okr_handle* h, const okr_topology* topo, const okr_margi
     size_t most = 1;
     for (int k = 1; k <= h->kmax; ++k) {
       int spg;
-      most = std::max(most, (size_t)snap_groups_default(k, S, &spg, 1, 2048) << k);
+      for (int mpl = 1; mpl <= 4; mpl *= 2) most = std::max(most, (size_t)snap_groups_default(k, S, &spg, mpl) << k);
     }
     const size_t nm = (size_t)1 << h->kmax, nt = (nm + 63) / 64;
     L.P32 = take(sizeof(Pair32) * 3 * (size_t)S * kMaxPairs);
@@ -747,10 +748,11 @@ void enqueue_search(okr_handle* h, void* ws, const okr_yblocks* Y, const okr_loa
     const int mblocks = (int)((nmask + kScoreThreads * mpl - 1) / (kScoreThreads * mpl));
     int spg;
     const int SG = snap_groups(h, k, &spg);
-    // the FP32 screen keeps one mask per lane and about 2048 blocks
-    const int mblocks32 = (int)((nmask + kScoreThreads - 1) / kScoreThreads);
+    // the FP32 screen: masks per lane and groups by the default rule
+    const int mpl32 = k >= 12 ? 4 : (k >= 10 ? 2 : 1);
+    const int mblocks32 = (int)((nmask + kScoreThreads * mpl32 - 1) / (kScoreThreads * mpl32));
     int spg32;
-    const int SG32 = snap_groups_default(k, S, &spg32, 1, 2048);
+    const int SG32 = snap_groups_default(k, S, &spg32, mpl32);
     const int* gate = nullptr;
     if (surr || feat_out) {
       hipLaunchKernelGGL(k_surr_tables, dim3(kMaxPairs + kMaxK), dim3(64), 0, ls,
@@ -855,10 +857,15 @@ void enqueue_search(okr_handle* h, void* ws, const okr_yblocks* Y, const okr_loa
                          (const double2*)q.headV, (const TargetRec*)q.zrec, mg->v_min, mg->v_max, q.P32, q.S32,
                          q.H32, q.Z32);
       if (ev) (void)hipEventRecord((*ev)[2 * g], ls);
-      hipLaunchKernelGGL(k_score_fp32, dim3(mblocks32, SG32), dim3(kScoreThreads), 0, ls, (const SegHdr*)q.hdrs, g,
-                         (const int*)q.tab, (const Pair32*)q.P32, (const Rec32*)q.S32, (const Head32*)q.H32,
-                         (const Rec32*)q.Z32, (const double*)q.econst, spg32, SG32, sp, q.part32, q.fin32, q.tiles32,
-                         q.tickets);
+#define OKR_SCORE32(M_)                                                                                       \
+  hipLaunchKernelGGL(k_score_fp32<M_>, dim3(mblocks32, SG32), dim3(kScoreThreads), 0, ls, (const SegHdr*)q.hdrs, g, \
+                     (const int*)q.tab, (const Pair32*)q.P32, (const Rec32*)q.S32, (const Head32*)q.H32,         \
+                     (const Rec32*)q.Z32, (const double*)q.econst, spg32, SG32, sp, q.part32, q.fin32, q.tiles32, \
+                     q.tickets)
+      if (mpl32 == 4) OKR_SCORE32(4);
+      else if (mpl32 == 2) OKR_SCORE32(2);
+      else OKR_SCORE32(1);
+#undef OKR_SCORE32
       if (ev) (void)hipEventRecord((*ev)[2 * g + 1], ls);
       int* cA = q.counts;
       int* cB = q.counts + 1;

@@ -187,54 +187,83 @@ __device__ __forceinline__ float diff32(float2 W, float w, float2 S) {
   return num * __builtin_amdgcn_rcpf(m + w);
 }
 
-template <bool ERR>
-__device__ __forceinline__ void walk32(const int* __restrict__ cr, const int* __restrict__ slots, const Pair32* Ps,
-                                       const Rec32* Ss, const Head32* Hs, int c, uint32_t m, float2& B0, float2& B1,
-                                       float2& B2, float& el, float& slack) {
-  float2 S0 = B0, S1 = B1, S2 = B2;
-  float d0 = 0.f, d1 = 0.f, d2 = 0.f;  // d of the current super on each phase
-  if (ERR) {
+// FP32 chain walk for M masks per lane (as walk_chain): d is the difference
+// |W + S| - |W| of a slot's voltage; a non-nested head is unaffected (d = 0).
+template <bool ERR, int M>
+__device__ __forceinline__ void walk32(const int* __restrict__ cr, const Pair32* Ps, const Rec32* Ss,
+                                       const Head32* Hs, int c, const uint32_t (&m)[M], float2 (&B)[M][3],
+                                       float (&el)[M], float (&slack)[M]) {
+  float2 S[M][3];
+  float dd[M][3];  // d of the current super on each phase
+#pragma unroll
+  for (int i = 0; i < M; ++i)
+#pragma unroll
+    for (int p = 0; p < 3; ++p) {
+      S[i][p] = B[i][p];
+      dd[i][p] = 0.f;
+    }
+  if (ERR && cr[C_OUTER] >= 0) {
     const int hph = cr[C_PHASE];
     const Head32* hv = Hs + c * 3;
-    if (hph & 1) d0 = diff32(hv[0].W, hv[0].w, B0);
-    if (hph & 2) d1 = diff32(hv[1].W, hv[1].w, B1);
-    if (hph & 4) d2 = diff32(hv[2].W, hv[2].w, B2);
+#pragma unroll
+    for (int p = 0; p < 3; ++p)
+      if (hph >> p & 1) {
+        const Head32 h = hv[p];
+#pragma unroll
+        for (int i = 0; i < M; ++i) dd[i][p] = diff32(h.W, h.w, B[i][p]);
+      }
   }
-  const int ns = cr[C_NSLOT], s0 = cr[C_SLOT0], pair0 = cr[C_PAIR0];
+  const int ns = cr[C_NSLOT], s0 = cr[C_SLOT0], pair0 = cr[C_PAIR0], bit0 = cr[C_BIT0];
   const int phw0 = cr[C_PHW0], phw1 = cr[C_PHW1], phw2 = cr[C_PHW2];
-  const uint32_t mb = m >> cr[C_BIT0];
-  int sidx = 0;
+  int sidx[M];
+#pragma unroll
+  for (int i = 0; i < M; ++i) sidx[i] = 0;
   for (int r = 0; r < ns; ++r) {
     const int w = r < 8 ? phw0 : (r < 16 ? phw1 : phw2);
     const int ph = (w >> (3 * (r & 7))) & 7;
-    const bool red = (mb >> r) & 1u;
-    const float rf = red ? 1.f : 0.f;
-    const Pair32* pp = Ps + (pair0 + ((r * (r + 1)) >> 1) + sidx) * 3;
+    const int prow = pair0 + ((r * (r + 1)) >> 1);
     const Rec32* tr = Ss + (s0 + r) * 3;
-#define OKR_SLOT32(P_, S_, D_)                                                  \
-    if (ph & (1 << P_)) {                                                       \
-      const Pair32 q = pp[P_];                                                  \
-      S_.x = fmaf(rf, q.P.x, S_.x);                                             \
-      S_.y = fmaf(rf, q.P.y, S_.y);                                             \
-      if (ERR) {                                                                \
-        const Rec32 t = tr[P_];                                                 \
-        const float d = diff32(t.W, t.w, S_);                                   \
-        const float ek = fmaxf(t.a + d, t.b - d);                               \
-        const float er = fmaxf(q.a + D_, q.b - D_);                             \
-        el = fmaxf(el, red ? er : ek);                                          \
-        slack = red ? slack : fminf(slack, fminf(t.bmin + d, t.bmax - d));      \
-        D_ = red ? D_ : d;                                                      \
-      }                                                                         \
+    bool red[M];
+    float rf[M];
+    const Pair32* pp[M];
+#pragma unroll
+    for (int i = 0; i < M; ++i) {
+      red[i] = (m[i] >> (bit0 + r)) & 1u;
+      rf[i] = red[i] ? 1.f : 0.f;
+      pp[i] = Ps + (prow + sidx[i]) * 3;
     }
-    OKR_SLOT32(0, S0, d0)
-    OKR_SLOT32(1, S1, d1)
-    OKR_SLOT32(2, S2, d2)
-#undef OKR_SLOT32
-    sidx = red ? sidx : r + 1;
+#pragma unroll
+    for (int p = 0; p < 3; ++p) {
+      if (!(ph >> p & 1)) continue;
+      Rec32 t;
+      if (ERR) t = tr[p];
+#pragma unroll
+      for (int i = 0; i < M; ++i) {
+        const Pair32 q = pp[i][p];
+        S[i][p].x = fmaf(rf[i], q.P.x, S[i][p].x);
+        S[i][p].y = fmaf(rf[i], q.P.y, S[i][p].y);
+        if (ERR) {
+          const float d = diff32(t.W, t.w, S[i][p]);
+          const float ek = fmaxf(t.a + d, t.b - d);
+          const float er = fmaxf(q.a + dd[i][p], q.b - dd[i][p]);
+          el[i] = fmaxf(el[i], red[i] ? er : ek);
+          slack[i] = red[i] ? slack[i] : fminf(slack[i], fminf(t.bmin + d, t.bmax - d));
+          dd[i][p] = red[i] ? dd[i][p] : d;
+        }
+      }
+    }
+#pragma unroll
+    for (int i = 0; i < M; ++i) sidx[i] = red[i] ? sidx[i] : r + 1;
   }
-  B0 = S0; B1 = S1; B2 = S2;
+#pragma unroll
+  for (int i = 0; i < M; ++i)
+#pragma unroll
+    for (int p = 0; p < 3; ++p) B[i][p] = S[i][p];
 }
 
+// FP32 screen of every mask (M masks per lane, layout as in k_score_fp64):
+// tile records of sure / possible / uncertain feasibility.
+template <int M>
 __global__ __launch_bounds__(kScoreThreads) void k_score_fp32(
     const SegHdr* __restrict__ hdrs, int g, const int* __restrict__ tab, const Pair32* __restrict__ P32,
     const Rec32* __restrict__ S32, const Head32* __restrict__ H32, const Rec32* __restrict__ Z32,
@@ -249,15 +278,21 @@ __global__ __launch_bounds__(kScoreThreads) void k_score_fp32(
   const SegHdr H = hdrs[g];
   if (!H.valid) return;
   const int tid = threadIdx.x;
-  const uint32_t m = blockIdx.x * kScoreThreads + tid;
+  uint32_t m[M];
+#pragma unroll
+  for (int i = 0; i < M; ++i) m[i] = blockIdx.x * (kScoreThreads * M) + i * kScoreThreads + tid;
   const int sg = blockIdx.y;
   const int l0 = sg * snaps_per_group;
   const int l1 = min(H.S, l0 + snaps_per_group);
   const int* chains = tab + H.o_chain;
-  const int* slots = tab + H.o_slot;
   const int* nest = tab + H.o_nest;
   const Stage z = stage_sizes(H);
-  float e = 0.f, slack = INFINITY;
+  float e[M], slack[M];
+#pragma unroll
+  for (int i = 0; i < M; ++i) {
+    e[i] = 0.f;
+    slack[i] = INFINITY;
+  }
   for (int l = l0; l < l1; ++l) {
     {
       const uint4* P_l = (const uint4*)(P32 + (size_t)l * H.npairs * 3);
@@ -271,76 +306,98 @@ __global__ __launch_bounds__(kScoreThreads) void k_score_fp32(
       __syncthreads();
     }
     const Rec32* Zl = Z32 + (size_t)l * H.nz;
-    float el = (float)s_ec;
+    float el[M];
+    const float ec = (float)s_ec;
+#pragma unroll
+    for (int i = 0; i < M; ++i) el[i] = ec;
     for (int c = 0; c < H.nchains; ++c) {
       const int* cr = chains + c * kChainInts;
-      float2 B0 = make_float2(0.f, 0.f), B1 = B0, B2 = B0;
+      float2 B[M][3];
+#pragma unroll
+      for (int i = 0; i < M; ++i)
+#pragma unroll
+        for (int p = 0; p < 3; ++p) B[i][p] = make_float2(0.f, 0.f);
       const int nl = cr[C_NEST_LEN], no = cr[C_NEST_OFF];
       for (int q = 0; q + 1 < nl; ++q) {
         const int oc = nest[no + q];
-        walk32<false>(chains + oc * kChainInts, slots, Ps, Ts, Hv, oc, m, B0, B1, B2, el, slack);
+        walk32<false, M>(chains + oc * kChainInts, Ps, Ts, Hv, oc, m, B, el, slack);
       }
-      walk32<true>(cr, slots, Ps, Ts, Hv, c, m, B0, B1, B2, el, slack);
-#define OKR_ZONE32(P_, B_)                                                       \
-      for (int q = cr[C_ZOFF0 + P_], qe = q + cr[C_ZCNT0 + P_]; q < qe; ++q) { \
-        Rec32 t;                                                                 \
-        if (q < kZoneLds) t = Zs[q];                                             \
-        else t = Zl[q];                                                          \
-        const float d = diff32(t.W, t.w, B_);                                    \
-        el = fmaxf(el, fmaxf(t.a + d, t.b - d));                                 \
-        slack = fminf(slack, fminf(t.bmin + d, t.bmax - d));                     \
-      }
-      OKR_ZONE32(0, B0)
-      OKR_ZONE32(1, B1)
-      OKR_ZONE32(2, B2)
-#undef OKR_ZONE32
+      walk32<true, M>(cr, Ps, Ts, Hv, c, m, B, el, slack);
+#pragma unroll
+      for (int p = 0; p < 3; ++p)
+        for (int q = cr[C_ZOFF0 + p], qe = q + cr[C_ZCNT0 + p]; q < qe; ++q) {
+          Rec32 t;
+          if (q < kZoneLds) t = Zs[q];
+          else t = Zl[q];
+#pragma unroll
+          for (int i = 0; i < M; ++i) {
+            const float d = diff32(t.W, t.w, B[i][p]);
+            el[i] = fmaxf(el[i], fmaxf(t.a + d, t.b - d));
+            slack[i] = fminf(slack[i], fminf(t.bmin + d, t.bmax - d));
+          }
+        }
     }
-    e = fmaxf(e, el);
+#pragma unroll
+    for (int i = 0; i < M; ++i) e[i] = fmaxf(e[i], el[i]);
     __syncthreads();
   }
   const uint32_t nmask = 1u << H.k;
-  const bool valid = m < nmask;
-  if (valid) {
-    MaskScore32 r;
-    r.e = e;
-    r.slack = slack;
-    part[(size_t)sg * nmask + m] = r;
-  }
+#pragma unroll
+  for (int i = 0; i < M; ++i)
+    if (m[i] < nmask) {
+      MaskScore32 r;
+      r.e = e[i];
+      r.slack = slack[i];
+      part[(size_t)sg * nmask + m[i]] = r;
+    }
   __threadfence();
   if (tid == 0) ticket = atomicAdd(&tickets[blockIdx.x], 1);
   __syncthreads();
   if (ticket != SG - 1) return;
-  MaskScore32 r;
-  r.e = 0.f;
-  r.slack = INFINITY;
-  if (valid) {
-    for (int q = 0; q < SG; ++q) {
-      const volatile MaskScore32* x = part + (size_t)q * nmask + m;
-      r.e = fmaxf(r.e, x->e);
-      r.slack = fminf(r.slack, x->slack);
+  const double dlt = sp.delta + sp.amb;
+#pragma unroll
+  for (int i = 0; i < M; ++i) {
+    const bool valid = m[i] < nmask;
+    MaskScore32 r;
+    r.e = 0.f;
+    r.slack = INFINITY;
+    if (valid) {
+      for (int q = 0; q < SG; ++q) {
+        const volatile MaskScore32* x = part + (size_t)q * nmask + m[i];
+        r.e = fmaxf(r.e, x->e);
+        r.slack = fminf(r.slack, x->slack);
+      }
+      fin[m[i]] = r;
     }
-    fin[m] = r;
-  }
-  const double dd = sp.delta + sp.amb;
-  const bool sure = valid && (double)r.e <= sp.e_bar - dd && (double)r.slack >= dd;
-  const bool poss = valid && (double)r.e <= sp.e_bar + dd && (double)r.slack >= -dd;
-  const int pc = __popc(m);
-  int a = sure ? pc : -1, b = poss ? pc : -1, c = (poss && !sure) ? pc : -1;
-  for (int o = 32; o > 0; o >>= 1) {
-    a = max(a, __shfl_xor(a, o, 64));
-    b = max(b, __shfl_xor(b, o, 64));
-    c = max(c, __shfl_xor(c, o, 64));
-  }
-  const uint32_t tile = m / kScoreBlock;
-  if ((tid & 63) == 0 && tile * kScoreBlock < nmask) {
-    TileRec32 t;
-    t.sure = a;
-    t.poss = b;
-    t.unc = c;
-    t.pad = 0;
-    tiles[tile] = t;
+    const bool sure = valid && (double)r.e <= sp.e_bar - dlt && (double)r.slack >= dlt;
+    const bool poss = valid && (double)r.e <= sp.e_bar + dlt && (double)r.slack >= -dlt;
+    const int pc = __popc(m[i]);
+    int a = sure ? pc : -1, b = poss ? pc : -1, c = (poss && !sure) ? pc : -1;
+    for (int o = 32; o > 0; o >>= 1) {
+      a = max(a, __shfl_xor(a, o, 64));
+      b = max(b, __shfl_xor(b, o, 64));
+      c = max(c, __shfl_xor(c, o, 64));
+    }
+    const uint32_t tile = m[i] / kScoreBlock;
+    if ((tid & 63) == 0 && tile * kScoreBlock < nmask) {
+      TileRec32 t;
+      t.sure = a;
+      t.poss = b;
+      t.unc = c;
+      t.pad = 0;
+      tiles[tile] = t;
+    }
   }
   if (tid == 0) tickets[blockIdx.x] = 0;
 }
+
+#define OKR_SCORE32_INST(M_)                                                                                   \
+  template __global__ void k_score_fp32<M_>(const SegHdr*, int, const int*, const Pair32*, const Rec32*,       \
+                                            const Head32*, const Rec32*, const double*, int, int, SelParams,  \
+                                            MaskScore32*, MaskScore32*, TileRec32*, int*);
+OKR_SCORE32_INST(1)
+OKR_SCORE32_INST(2)
+OKR_SCORE32_INST(4)
+#undef OKR_SCORE32_INST
 
 }  // namespace okr
