@@ -134,7 +134,7 @@ def main():
     ap.add_argument("--surr-epochs", type=int, default=6)
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-modes", action="store_true")
-    ap.add_argument("--modes", default="plain,mixed,surrogate",
+    ap.add_argument("--modes", default="plain,mixed,surrogate,factored",
                     help="comma-separated forms timed for time-to-optimal (plain is always timed)")
     ap.add_argument("--lanes", type=int, default=1, help="concurrent segment lanes of the timed searches")
     ap.add_argument("--autotune", action="store_true",
@@ -228,6 +228,13 @@ def main():
                                         dict(fp64_rescored_masks=refined, max_fp32_vs_fp64_error=dev))
         if "surrogate" in wanted:
             modes["surrogate"] = surrogate_mode(f, args, plain_ms, (ref_masks, ref_pops), ncand)
+        if "factored" in wanted:
+            # exact per-mask scores assembled from per-chain pattern tables
+            Rf = Reducer(f, device="cuda:0", graph=True, precision="factored")
+            ms = timed_runs(Rf, args.reps, False)
+            m, p, res = decisions(Rf)
+            Rf.close()
+            modes["factored_fp64"] = mode_entry("factored", ms, plain_ms, m, p, res, ref_masks, ref_pops, ncand)
         line["modes"] = modes
     if not args.no_cpu:
         line["cpu_baseline"] = cpu_baseline(f)

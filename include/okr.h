@@ -69,6 +69,12 @@ extern "C" {
 
 #define OKR_PRECISION_FP64 0   /* complex128 everywhere */
 #define OKR_PRECISION_MIXED 1  /* FP32 difference-form sweep, FP64 refine */
+#define OKR_PRECISION_FP64_FACTORED 2 /* complex128; every mask's score assembled
+                                  from per-chain pattern tables (a chain's
+                                  terms depend only on its own and its nesting
+                                  path's mask bits; max and min are exact), so
+                                  the scores equal OKR_PRECISION_FP64's bit for
+                                  bit */
 
 #define OKR_FLAG_TIMING 1u     /* record per-kernel HIP-event timings */
 #define OKR_FLAG_VHAT_GIVEN 2u /* loads->Vhat holds the scenario voltages */
@@ -156,7 +162,8 @@ typedef struct {
     double e_min;       /* smallest error at the chosen level */
     int32_t ambiguous;  /* a candidate lay within amb_tol of a decision boundary */
     int32_t n_scored;   /* masks scored exactly */
-    double flops;       /* algorithmic flops of the scoring kernel */
+    double flops;       /* algorithmic flops of the per-mask scoring kernel
+                           (0 with OKR_PRECISION_FP64_FACTORED) */
     float score_ms;     /* scoring-kernel time (OKR_FLAG_TIMING) */
     int32_t n_refined;  /* MIXED: masks rescored in FP64 (shortlists A + B) */
     double fp32_dev;    /* MIXED: max |e32 - e64| over rescored masks with e64 <= 2 e_bar */

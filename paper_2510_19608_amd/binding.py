@@ -29,6 +29,7 @@ class OKR:
     W_BASE_OUT_OF_BAND = 1
     PRECISION_FP64 = 0
     PRECISION_MIXED = 1
+    PRECISION_FP64_FACTORED = 2
     FLAG_TIMING = 1
     FLAG_VHAT_GIVEN = 2
     FLAG_DUMP_SCORES = 4
@@ -230,7 +231,8 @@ def make_margins(f=None, *, e_bar=None, v_min=None, v_max=None, tie_tol=1e-11, a
                    v_min=f.get("v_min", 0.95) if v_min is None else v_min,
                    v_max=f.get("v_max", 1.05) if v_max is None else v_max,
                    tie_tol=tie_tol, amb_tol=amb_tol, pf_tol=pf_tol, pf_maxit=pf_maxit,
-                   precision={"fp64": OKR.PRECISION_FP64, "mixed": OKR.PRECISION_MIXED}[precision],
+                   precision={"fp64": OKR.PRECISION_FP64, "mixed": OKR.PRECISION_MIXED,
+                              "factored": OKR.PRECISION_FP64_FACTORED}[precision],
                    flags=flags, top_k=top_k,
                    surrogate=None if surrogate is None else surrogate.data_ptr(), lanes=lanes)
 

@@ -50,6 +50,7 @@ __global__ __launch_bounds__(256) void k_build_struct(Topo T, State St, int g, i
   __shared__ int s_seg[kMaxK], s_thpos[kMaxK], s_first[kMaxK];          // segment node j, its top's head position,
                                                                         // first segment node with its top
   __shared__ int s_chpos[kMaxK], s_rkeep[kMaxK], s_depth[kMaxK];        // chain c: head position, new range, nesting
+  __shared__ int s_pmask[kMaxK];                                        // chain c: mask bits of its nesting path
   __shared__ int s_keycnt[kMaxK * 3], s_keyoff[kMaxK * 3], s_keycur[kMaxK * 3];
   __shared__ SegHdr s_h;
   __shared__ int s_err, s_nch;
@@ -175,16 +176,23 @@ __global__ __launch_bounds__(256) void k_build_struct(Topo T, State St, int g, i
   }
   __syncthreads();
   if (tid < nch) {
-    int d = 0;  // nesting depth (outer chains have smaller indices)
+    // nesting depth (outer chains have smaller indices) and the mask bits of
+    // the chains on the nesting path, the chain itself included
+    int d = 0, pm = 0;
     if (!s_err)
-      for (int x = tid; x >= 0; x = s_outer[x]) ++d;
+      for (int x = tid; x >= 0; x = s_outer[x]) {
+        ++d;
+        pm |= ((1 << (s_cslot0[x + 1] - s_cslot0[x])) - 1) << s_slotbit[s_cslot0[x]];
+      }
     s_depth[tid] = d;
+    s_pmask[tid] = pm;
   }
   __syncthreads();
   // table layout: every thread forms the same sums from shared memory
-  int nest_tot = 0, npairs = 0, nr = 0, nom = 0;
+  int nest_tot = 0, npairs = 0, nr = 0, nom = 0, npat = 0;
   for (int c = 0; c < nch; ++c) {
     const int n = s_cslot0[c + 1] - s_cslot0[c];
+    npat += 1 << __popc(s_pmask[c]);
     nest_tot += s_depth[c];
     npairs += n * (n + 1) / 2;
     nr += s_rkeep[c];
@@ -209,9 +217,13 @@ __global__ __launch_bounds__(256) void k_build_struct(Topo T, State St, int g, i
     H.nchains = nch;
     H.nslots = k;
     H.npairs = npairs;
+    H.npat = npat;
     // the structural part must fit the segment's table (and the shared image,
     // which holds the largest possible one)
     if (o_zent > tab_cap || o_zent > kTabLds) s_err = 1;
+    // the chain patterns number at most 2^(k+1) (a nesting forest whose
+    // chains hold k bits in all): the pattern table's capacity
+    if (npat > (2 << k)) s_err = 1;
     H.valid = s_err ? 0 : 1;
     s_h = H;
   }
@@ -232,9 +244,10 @@ __global__ __launch_bounds__(256) void k_build_struct(Topo T, State St, int g, i
   // records: one thread per chain, one per slot
   if (tid < nch) {
     const int c = tid, s0 = s_cslot0[c], n = s_cslot0[c + 1] - s0;
-    int nest_off = 0, pair0 = 0, ridx = 0, rcum = 0;
+    int nest_off = 0, pair0 = 0, ridx = 0, rcum = 0, pbase = 0;
     for (int q = 0; q < c; ++q) {
       const int nq = s_cslot0[q + 1] - s_cslot0[q];
+      pbase += 1 << __popc(s_pmask[q]);
       nest_off += s_depth[q];
       pair0 += nq * (nq + 1) / 2;
       ridx += s_rkeep[q];
@@ -263,6 +276,8 @@ __global__ __launch_bounds__(256) void k_build_struct(Topo T, State St, int g, i
     cr[C_PHW0] = phw[0];
     cr[C_PHW1] = phw[1];
     cr[C_PHW2] = phw[2];
+    cr[C_PMASK] = s_pmask[c];
+    cr[C_PBASE] = pbase;
     for (int p = 0; p < 3; ++p) {
       cr[C_ZOFF0 + p] = 0;  // zone ranges filled after the zone pass
       cr[C_ZCNT0 + p] = 0;

@@ -213,46 +213,57 @@ __device__ __forceinline__ void stage_put(const Stage& z, int i, const uint4& v,
   Zd[i - z.cH] = v;
 }
 
+// Terms of chain c for M masks and one snapshot folded into el, kept squared
+// magnitudes into (qmin, qmax): the nesting path walked to the chain's head
+// (voltage rises only), the chain's own slots, then the zone entries anchored
+// below it (the first zcap of them from the LDS stage Zs when STAGED, the
+// rest from global memory).  They depend on the mask bits in C_PMASK only.
+template <bool STAGED, int M>
+__device__ __forceinline__ void score_chain(const int* __restrict__ chains, const int* __restrict__ nest, int c,
+                                            const double2* Ps, const TargetRec* Ss, const double2* Hs,
+                                            const double* Hm, const TargetRec* Zs, int zcap,
+                                            const TargetRec* __restrict__ zrec_l, const uint32_t (&m)[M],
+                                            double (&el)[M], double (&qmin)[M], double (&qmax)[M]) {
+  const int* cr = chains + c * kChainInts;
+  double2 B[M][3];
+#pragma unroll
+  for (int i = 0; i < M; ++i)
+#pragma unroll
+    for (int p = 0; p < 3; ++p) B[i][p] = make_double2(0.0, 0.0);
+  const int nl = cr[C_NEST_LEN], no = cr[C_NEST_OFF];
+  for (int q = 0; q + 1 < nl; ++q) {
+    const int oc = nest[no + q];
+    walk_chain<false, M>(chains + oc * kChainInts, Ps, Ss, Hs, Hm, oc, m, B, el, qmin, qmax);
+  }
+  walk_chain<true, M>(cr, Ps, Ss, Hs, Hm, c, m, B, el, qmin, qmax);
+#pragma unroll
+  for (int p = 0; p < 3; ++p)
+    for (int q = cr[C_ZOFF0 + p], qe = q + cr[C_ZCNT0 + p]; q < qe; ++q) {
+      TargetRec t;
+      if (STAGED && q < zcap) t = Zs[q];
+      else t = zrec_l[q];
+#pragma unroll
+      for (int i = 0; i < M; ++i) {
+        const double vx = t.W.x + B[i][p].x, vy = t.W.y + B[i][p].y;
+        const double q2 = fma(vx, vx, vy * vy);
+        const double mag = sqrt_nr(q2);
+        el[i] = fmax(el[i], fmax(mag - t.lo, t.hi - mag));
+        qmin[i] = fmin(qmin[i], q2);
+        qmax[i] = fmax(qmax[i], q2);
+      }
+    }
+}
+
 // Error of M masks for one snapshot folded into el, kept squared magnitudes
-// into (qmin, qmax): every chain walked with its nesting path recomputed, then
-// the zone entries anchored below it (the first zcap of them from the LDS
-// stage Zs when STAGED, the rest from global memory).
+// into (qmin, qmax): every chain's terms in turn.
 template <bool STAGED, int M>
 __device__ __forceinline__ void score_snapshot(const SegHdr& H, const int* __restrict__ chains,
                                                const int* __restrict__ nest, const double2* Ps, const TargetRec* Ss,
                                                const double2* Hs, const double* Hm, const TargetRec* Zs, int zcap,
                                                const TargetRec* __restrict__ zrec_l, const uint32_t (&m)[M],
                                                double (&el)[M], double (&qmin)[M], double (&qmax)[M]) {
-  for (int c = 0; c < H.nchains; ++c) {
-    const int* cr = chains + c * kChainInts;
-    double2 B[M][3];
-#pragma unroll
-    for (int i = 0; i < M; ++i)
-#pragma unroll
-      for (int p = 0; p < 3; ++p) B[i][p] = make_double2(0.0, 0.0);
-    const int nl = cr[C_NEST_LEN], no = cr[C_NEST_OFF];
-    for (int q = 0; q + 1 < nl; ++q) {
-      const int oc = nest[no + q];
-      walk_chain<false, M>(chains + oc * kChainInts, Ps, Ss, Hs, Hm, oc, m, B, el, qmin, qmax);
-    }
-    walk_chain<true, M>(cr, Ps, Ss, Hs, Hm, c, m, B, el, qmin, qmax);
-#pragma unroll
-    for (int p = 0; p < 3; ++p)
-      for (int q = cr[C_ZOFF0 + p], qe = q + cr[C_ZCNT0 + p]; q < qe; ++q) {
-        TargetRec t;
-        if (STAGED && q < zcap) t = Zs[q];
-        else t = zrec_l[q];
-#pragma unroll
-        for (int i = 0; i < M; ++i) {
-          const double vx = t.W.x + B[i][p].x, vy = t.W.y + B[i][p].y;
-          const double q2 = fma(vx, vx, vy * vy);
-          const double mag = sqrt_nr(q2);
-          el[i] = fmax(el[i], fmax(mag - t.lo, t.hi - mag));
-          qmin[i] = fmin(qmin[i], q2);
-          qmax[i] = fmax(qmax[i], q2);
-        }
-      }
-  }
+  for (int c = 0; c < H.nchains; ++c)
+    score_chain<STAGED, M>(chains, nest, c, Ps, Ss, Hs, Hm, Zs, zcap, zrec_l, m, el, qmin, qmax);
 }
 
 // ------------------------------------------------------------ block reduce --

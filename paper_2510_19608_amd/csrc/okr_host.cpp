@@ -34,6 +34,10 @@ template <int M>
 __global__ void k_score_fp64(const SegHdr*, int, const int*, const double2*, const TargetRec*, const double2*,
                              const TargetRec*, const double*, int, int, SelParams, MaskScore*, MaskScore*, TileRec*,
                              int*, const int*);
+__global__ void k_fac_tables(const SegHdr*, int, const int*, const double2*, const TargetRec*, const double2*,
+                             const TargetRec*, const double*, PatScore*, double*);
+__global__ void k_fac_combine(const SegHdr*, int, const int*, const PatScore*, const double*, SelParams, MaskScore*,
+                              TileRec*);
 __global__ void k_argmin(const SegHdr*, int, const MaskScore*, const TileRec*, SelParams, const int*, DevDecision*,
                          const int*);
 __global__ void k_apply(const SegHdr*, int, const int*, Topo, State, const DevDecision*, const double2*,
@@ -114,6 +118,8 @@ int snap_groups_default(int k, int S, int* spg, int mpl = 1, int target_blocks =
 struct Layout {
   size_t topo, z, Zroot, Vhat, Vcur, A, J, absV, kept, sup, slot_of, zent_of, status, iters, hdrs, decs, tab, P, srec,
       headV, zrec, econst, part, fin, tiles, tickets, kp, yeq, Ykd, Yko, err;
+  // factored FP64 scoring: chain-pattern table, largest constant error
+  size_t pat, ecmax;
   // mixed precision
   size_t P32, S32, H32, Z32, part32, fin32, tiles32, listA, listB, scoreA, scoreB, counts, mstate;
   // surrogate: feature tables (always), ranking buffers (when planned with top_k)
@@ -487,6 +493,8 @@ extern "C" int okr_plan(okr_handle* h, const okr_topology* topo, const okr_margi
     L.fin = take(sizeof(MaskScore) * nm);
     L.tiles = take(sizeof(TileRec) * nt);
     L.tickets = take(sizeof(int) * nt);
+    L.pat = take(sizeof(PatScore) * 2 * nm);
+    L.ecmax = take(sizeof(double));
   }
   {
     size_t most = 1;
@@ -564,6 +572,8 @@ struct Ptrs {
   TargetRec *srec, *zrec;
   MaskScore *part, *fin;
   TileRec* tiles;
+  PatScore* pat;
+  double* ecmax;
   Pair32* P32;
   Rec32 *S32, *Z32;
   Head32* H32;
@@ -630,6 +640,8 @@ Ptrs pointers(okr_handle* h, void* d_workspace, int lane = 0) {
   p.part = (MaskScore*)at(L.part);
   p.fin = (MaskScore*)at(L.fin);
   p.tiles = (TileRec*)at(L.tiles);
+  p.pat = (PatScore*)at(L.pat);
+  p.ecmax = (double*)at(L.ecmax);
   p.tickets = (int*)at(L.tickets);
   p.kp = (int*)at(L.kp);
   p.yeq = (double2*)at(L.yeq);
@@ -717,7 +729,9 @@ void enqueue_search(okr_handle* h, void* ws, const okr_yblocks* Y, const okr_loa
   sp.amb = mg->amb_tol;
   sp.delta = kMixedDelta;
   const bool mixed = mg->precision == OKR_PRECISION_MIXED;
-  const bool surr = mg->top_k > 0 && mg->top_k <= h->topk && mg->surrogate != nullptr && !mixed;
+  const bool factored = mg->precision == OKR_PRECISION_FP64_FACTORED;
+  const bool surr = mg->top_k > 0 && mg->top_k <= h->topk && mg->surrogate != nullptr &&
+                    mg->precision == OKR_PRECISION_FP64;
   if (surr)
     hipLaunchKernelGGL(k_refresh_weights, dim3((kSurrH * kSurrH + 255) / 256), dim3(256), 0, st, mg->surrogate,
                        p.sW1b, p.sW2b, (__bf16*)nullptr);
@@ -830,7 +844,15 @@ void enqueue_search(okr_handle* h, void* ws, const okr_yblocks* Y, const okr_loa
                      (const int*)q.tab, (const double2*)q.P, (const TargetRec*)q.srec, (const double2*)q.headV, \
                      (const TargetRec*)q.zrec, (const double*)q.econst, spg, SG, sp, q.part, q.fin, q.tiles,   \
                      q.tickets, gate)
-      if (mpl == 4) OKR_SCORE64(4);
+      if (factored) {
+        // pattern table (grid-stride waves: up to 2^(k+1) patterns), then every mask
+        const int tblocks = (int)std::min<uint64_t>(1024, std::max<uint64_t>(4, ((uint64_t)2 << k) / 32));
+        hipLaunchKernelGGL(k_fac_tables, dim3(tblocks), dim3(256), 0, ls, (const SegHdr*)q.hdrs, g,
+                           (const int*)q.tab, (const double2*)q.P, (const TargetRec*)q.srec, (const double2*)q.headV,
+                           (const TargetRec*)q.zrec, (const double*)q.econst, q.pat, q.ecmax);
+        hipLaunchKernelGGL(k_fac_combine, dim3((nmask + 255) / 256), dim3(256), 0, ls, (const SegHdr*)q.hdrs, g,
+                           (const int*)q.tab, (const PatScore*)q.pat, (const double*)q.ecmax, sp, q.fin, q.tiles);
+      } else if (mpl == 4) OKR_SCORE64(4);
       else if (mpl == 2) OKR_SCORE64(2);
       else OKR_SCORE64(1);
 #undef OKR_SCORE64
@@ -934,7 +956,8 @@ extern "C" int okr_reduce_feeder(okr_handle* h, const okr_yblocks* Y, const okr_
   const bool vhat_given = (mg->flags & OKR_FLAG_VHAT_GIVEN) != 0;
   if (!loads->S_load) OKR_FAIL(h, OKR_E_ARG, "S_load is required (load currents)");
   if (vhat_given && !loads->Vhat) OKR_FAIL(h, OKR_E_ARG, "OKR_FLAG_VHAT_GIVEN without Vhat");
-  if (mg->precision != OKR_PRECISION_FP64 && mg->precision != OKR_PRECISION_MIXED)
+  if (mg->precision != OKR_PRECISION_FP64 && mg->precision != OKR_PRECISION_MIXED &&
+      mg->precision != OKR_PRECISION_FP64_FACTORED)
     OKR_FAIL(h, OKR_E_ARG, "unknown precision %d", mg->precision);
   if (!(mg->v_min < mg->v_max) || !(mg->e_bar >= 0) || !(mg->tie_tol >= 0) || !(mg->amb_tol >= 0))
     OKR_FAIL(h, OKR_E_ARG, "bad margins");
@@ -943,7 +966,7 @@ extern "C" int okr_reduce_feeder(okr_handle* h, const okr_yblocks* Y, const okr_
   const bool graph = (mg->flags & OKR_FLAG_GRAPH) != 0 && !timing && !dump && !out->features;
   if (mg->top_k > 0 && mg->surrogate && mg->top_k > h->topk)
     OKR_FAIL(h, OKR_E_ARG, "top_k %d exceeds the planned %d", mg->top_k, h->topk);
-  if (out->targets && mg->precision != OKR_PRECISION_FP64) OKR_FAIL(h, OKR_E_ARG, "targets need precision FP64");
+  if (out->targets && mg->precision == OKR_PRECISION_MIXED) OKR_FAIL(h, OKR_E_ARG, "targets need FP64 scores");
   const int n = h->n, S = h->S, nseg = h->nseg;
   hipStream_t st = h->stream;
   const Ptrs p = pointers(h, d_workspace);
@@ -1122,7 +1145,8 @@ extern "C" int okr_reduce_feeder(okr_handle* h, const okr_yblocks* Y, const okr_
       fl += 0.5 * (6.0 + 4.0 * np) + 0.5 * (14.0 * np);
     }
     fl += 14.0 * hdrs[g].nz;
-    R.flops = fl * double(int64_t(1) << k) * S;
+    // (the per-mask form's count; the factored form does not do this work)
+    R.flops = mg->precision == OKR_PRECISION_FP64_FACTORED ? 0.0 : fl * double(int64_t(1) << k) * S;
     out->algorithmic_flops += R.flops;
     if (mixed) {
       R.n_refined = mstate[g].nA + mstate[g].nB;

@@ -31,6 +31,7 @@ struct SegHdr {
   int o_range;    // [nrange][3]: preorder start, end, cumulative node count
   int o_zent;     // [nz][3]: node, phase, chain
   int total_ints;
+  int npat;       // chain patterns: sum over chains of 2^popcount(C_PMASK)
 };
 
 // Static topology on the device.
@@ -62,6 +63,8 @@ enum { C_HEAD = 0, C_NSLOT, C_SLOT0, C_NEST_OFF, C_NEST_LEN,
        C_BIT0,   // mask bit of the first slot; slot r has bit C_BIT0 + r
        C_PAIR0,  // first pair of the chain; slot r's pairs start at C_PAIR0 + r(r+1)/2
        C_PHW0, C_PHW1, C_PHW2,  // phase masks of slots 8w..8w+7, 3 bits each
+       C_PMASK,  // mask bits the chain's terms depend on: its slots and those of its nesting path
+       C_PBASE,  // first entry of the chain's patterns in the segment's pattern table
        kChainInts };
 // slot record
 enum { SL_NODE = 0, SL_BIT, SL_PHASE, SL_PAIRBASE, SL_CHAIN, kSlotInts };
@@ -90,6 +93,13 @@ struct DevDecision {
 struct MaskScore {
   double e;
   double slack;
+};
+
+// Chain-pattern score: max error and extreme kept squared magnitudes of one
+// chain's terms (its slots and zone entries) over every snapshot, for one
+// assignment of the mask bits in C_PMASK.
+struct PatScore {
+  double e, qmin, qmax;
 };
 
 // Per-tile (64 consecutive masks) summary written by the last scoring block

@@ -12,6 +12,31 @@
 namespace okr {
 
 // ---------------------------------------------------------------- scoring --
+// Tile record of one wave's 64 consecutive masks (lane i holds mask
+// tile * 64 + i, final score r): highest feasible level, smallest error at
+// that level, highest level of a mask near the e_bar / band boundary.
+__device__ __forceinline__ void tile_record(const MaskScore& r, uint32_t m, bool valid, uint32_t nmask,
+                                            const SelParams& sp, TileRec* __restrict__ tiles) {
+  const int pc = __popc(m);
+  const bool feas = valid && feasible(r, sp.e_bar);
+  int best = feas ? pc : -1;
+  int nearl = (valid && near_boundary(r, sp.e_bar, sp.amb)) ? pc : -1;
+  for (int o = 32; o > 0; o >>= 1) {
+    best = max(best, __shfl_xor(best, o, 64));
+    nearl = max(nearl, __shfl_xor(nearl, o, 64));
+  }
+  double em = (feas && pc == best) ? r.e : INFINITY;
+  for (int o = 32; o > 0; o >>= 1) em = fmin(em, __shfl_xor(em, o, 64));
+  const uint32_t tile = m / kScoreBlock;
+  if ((threadIdx.x & 63) == 0 && tile * kScoreBlock < nmask) {
+    TileRec t;
+    t.best = best;
+    t.near = nearl;
+    t.emin = em;
+    tiles[tile] = t;
+  }
+}
+
 // Every mask of a segment over the block's snapshot group: e = max error over
 // the affected nodes, slack = min band slack over their kept node-phases.  A
 // block is 4 waves; a lane holds M masks (mask i of the lane is
@@ -100,24 +125,7 @@ __global__ __launch_bounds__(kScoreThreads) void k_score_fp64(
       }
       fin[m[i]] = r;
     }
-    const int pc = __popc(m[i]);
-    const bool feas = valid && feasible(r, sp.e_bar);
-    int best = feas ? pc : -1;
-    int nearl = (valid && near_boundary(r, sp.e_bar, sp.amb)) ? pc : -1;
-    for (int o = 32; o > 0; o >>= 1) {
-      best = max(best, __shfl_xor(best, o, 64));
-      nearl = max(nearl, __shfl_xor(nearl, o, 64));
-    }
-    double em = (feas && pc == best) ? r.e : INFINITY;
-    for (int o = 32; o > 0; o >>= 1) em = fmin(em, __shfl_xor(em, o, 64));
-    const uint32_t tile = m[i] / kScoreBlock;
-    if ((tid & 63) == 0 && tile * kScoreBlock < nmask) {
-      TileRec t;
-      t.best = best;
-      t.near = nearl;
-      t.emin = em;
-      tiles[tile] = t;
-    }
+    tile_record(r, m[i], valid, nmask, sp, tiles);
   }
   if (tid == 0) tickets[blockIdx.x] = 0;  // ready for the next launch
 }
@@ -174,6 +182,124 @@ __global__ __launch_bounds__(kScoreBlock) void k_refine_fp64(
       out[idx] = r;
     }
   }
+}
+
+// ------------------------------------------------------- factored scoring --
+// A mask's error is the largest of its chains' terms (and of the snapshot's
+// constant error), over every snapshot; the extreme kept squared magnitudes
+// likewise.  Chain c's terms depend only on the mask bits in C_PMASK (its own
+// slots and those of its nesting path), so every mask's exact score can be
+// assembled from one table entry per chain: for each chain and each
+// assignment u of its C_PMASK bits (bit j of u at the j-th lowest set bit),
+// the chain's terms reduced over the snapshots.  Max and min are exact, so
+// the assembled scores equal the per-mask kernel's bit for bit.
+constexpr int kPatLds = 1024;  // pattern-table entries staged in LDS by the combine kernel
+
+// The pattern table: one wave per pattern, lanes over snapshots, the chain's
+// per-snapshot arithmetic of the FP64 scoring kernel, a wave reduction.  Wave 0
+// also stores the largest constant error over the snapshots.
+__global__ __launch_bounds__(256) void k_fac_tables(const SegHdr* __restrict__ hdrs, int g,
+                                                    const int* __restrict__ tab, const double2* __restrict__ P,
+                                                    const TargetRec* __restrict__ srec,
+                                                    const double2* __restrict__ headV,
+                                                    const TargetRec* __restrict__ zrec,
+                                                    const double* __restrict__ econst, PatScore* __restrict__ pat,
+                                                    double* __restrict__ ecmax) {
+  const SegHdr H = hdrs[g];
+  if (!H.valid) return;
+  const int lane = threadIdx.x & 63;
+  const int wave = blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6);
+  const int nwaves = gridDim.x * (blockDim.x >> 6);
+  const int* chains = tab + H.o_chain;
+  const int* nest = tab + H.o_nest;
+  if (wave == 0) {
+    double e = -INFINITY;
+    for (int l = lane; l < H.S; l += 64) e = fmax(e, econst[l]);
+    for (int o = 32; o > 0; o >>= 1) e = fmax(e, __shfl_xor(e, o, 64));
+    if (lane == 0) *ecmax = e;
+  }
+  for (int t = wave; t < H.npat; t += nwaves) {
+    int c = 0;
+    while (c + 1 < H.nchains && chains[(c + 1) * kChainInts + C_PBASE] <= t) ++c;
+    const int* cr = chains + c * kChainInts;
+    const uint32_t u = (uint32_t)(t - cr[C_PBASE]);
+    uint32_t pm = (uint32_t)cr[C_PMASK], mu = 0;
+    for (int j = 0; pm; ++j) {  // deposit bit j of u at the j-th lowest bit of C_PMASK
+      const uint32_t low = pm & (0u - pm);
+      if (u >> j & 1u) mu |= low;
+      pm ^= low;
+    }
+    const uint32_t mm[1] = {mu};
+    double el[1] = {-INFINITY}, qn[1] = {INFINITY}, qx[1] = {-INFINITY};
+    for (int l = lane; l < H.S; l += 64)
+      score_chain<false, 1>(chains, nest, c, P + (size_t)l * H.npairs * 3, srec + (size_t)l * H.nslots * 3,
+                            headV + (size_t)l * H.nchains * 3, (const double*)nullptr, (const TargetRec*)nullptr, 0,
+                            zrec + (size_t)l * H.nz, mm, el, qn, qx);
+    double e = el[0], a = qn[0], b = qx[0];
+    for (int o = 32; o > 0; o >>= 1) {
+      e = fmax(e, __shfl_xor(e, o, 64));
+      a = fmin(a, __shfl_xor(a, o, 64));
+      b = fmax(b, __shfl_xor(b, o, 64));
+    }
+    if (lane == 0) {
+      PatScore r;
+      r.e = e;
+      r.qmin = a;
+      r.qmax = b;
+      pat[t] = r;
+    }
+  }
+}
+
+// Every mask's score from the pattern table (one thread per mask): the
+// largest constant error and each chain's entry for the mask's bits, then
+// the band slack; per-mask scores and 64-mask tile records as the FP64
+// scoring kernel writes them.
+__global__ __launch_bounds__(256) void k_fac_combine(const SegHdr* __restrict__ hdrs, int g,
+                                                     const int* __restrict__ tab, const PatScore* __restrict__ pat,
+                                                     const double* __restrict__ ecmax, SelParams sp,
+                                                     MaskScore* __restrict__ fin, TileRec* __restrict__ tiles) {
+  __shared__ int s_pm[kMaxK], s_pb[kMaxK];
+  __shared__ PatScore s_pat[kPatLds];
+  const SegHdr H = hdrs[g];
+  if (!H.valid) return;
+  const int tid = threadIdx.x;
+  const int nch = H.nchains;
+  if (tid < nch) {
+    s_pm[tid] = tab[H.o_chain + tid * kChainInts + C_PMASK];
+    s_pb[tid] = tab[H.o_chain + tid * kChainInts + C_PBASE];
+  }
+  const int np = min(H.npat, kPatLds);
+  for (int i = tid; i < np; i += blockDim.x) s_pat[i] = pat[i];
+  __syncthreads();
+  const uint32_t nmask = 1u << H.k;
+  const uint32_t m = blockIdx.x * blockDim.x + tid;
+  const bool valid = m < nmask;
+  double e = *ecmax, qn = INFINITY, qx = -INFINITY;
+  for (int c = 0; c < nch; ++c) {
+    uint32_t pm = (uint32_t)__builtin_amdgcn_readfirstlane(s_pm[c]);
+    const int pb = __builtin_amdgcn_readfirstlane(s_pb[c]);
+    uint32_t u = 0;
+    int j = 0;
+    while (pm) {  // gather the mask's bits at C_PMASK's positions, run by run
+      const int b = __builtin_ctz(pm);
+      const int run = __builtin_ctz(~(pm >> b));
+      const uint32_t ones = (1u << run) - 1u;
+      u |= ((m >> b) & ones) << j;
+      j += run;
+      pm &= ~(ones << b);
+    }
+    const int idx = pb + (int)u;
+    const PatScore r = idx < kPatLds ? s_pat[idx] : pat[idx];
+    e = fmax(e, r.e);
+    qn = fmin(qn, r.qmin);
+    qx = fmax(qx, r.qmax);
+  }
+  MaskScore r;
+  r.e = e;
+  r.slack = band_slack(qn, qx, sp.vmin, sp.vmax);
+  if (valid) fin[m] = r;
+  tile_record(r, m, valid, nmask, sp, tiles);
 }
 
 // d = |W + S| - |W| in difference form (w = |W| given):

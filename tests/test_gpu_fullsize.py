@@ -55,7 +55,7 @@ def check_against_golden(out, G):
 
 
 @pytest.mark.parametrize("cfg", ["c3", "c4"])
-@pytest.mark.parametrize("precision", ["fp64", "mixed"])
+@pytest.mark.parametrize("precision", ["fp64", "mixed", "factored"])
 def test_fullsize_decisions_graph(okr, cfg, precision):
     _say(f"{cfg} seed 0 {precision} graph")
     G = golden(cfg)
