@@ -136,7 +136,8 @@ def main():
     ap.add_argument("--no-modes", action="store_true")
     ap.add_argument("--modes", default="plain,mixed,surrogate,factored",
                     help="comma-separated forms timed for time-to-optimal (plain is always timed)")
-    ap.add_argument("--lanes", type=int, default=1, help="concurrent segment lanes of the timed searches")
+    ap.add_argument("--lanes", type=int, default=0,
+                    help="segments per launch chunk of the timed searches (0 = the library default, 8)")
     ap.add_argument("--autotune", action="store_true",
                     help="tune the scoring launch shape before the warm-up (default: the library's default shape)")
     ap.add_argument("--copy-probe-mib", type=int, default=0,
@@ -159,9 +160,6 @@ def main():
         torch.cuda.synchronize()
         del src, dst
     f = make_feeder("c2", args.seed)
-    # one lane: on this workload the scoring launches fill the GPU, concurrent
-    # segment lanes add no throughput, and with one lane the per-launch event
-    # times of the scoring kernel are not stretched by overlap
     R = Reducer(f, device="cuda:0", timing=True, lanes=args.lanes)
     ncand = int(R.sizes.n_candidates)
     if args.autotune:

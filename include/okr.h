@@ -140,10 +140,12 @@ typedef struct {
                          surrogate ranks first (full enumeration as fallback) */
     const float *surrogate; /* DEVICE FP32 parameters of the surrogate MLP
                                (layout in okr_train_surrogate), or NULL */
-    int32_t lanes;    /* segments searched concurrently (0 = 4, at most 8):
-                         a segment waits only for earlier segments whose
-                         affected regions (or chain heads) it can share;
-                         read by okr_plan (each lane has its own scratch) */
+    int32_t lanes;    /* segments per launch chunk (0 = 8, at most 8): each
+                         search step is launched once over a chunk of
+                         mutually independent segments (no shared affected
+                         region or chain head), conflicting segments keep
+                         their order; read by okr_plan (each chunk position
+                         has its own scratch block) */
 } okr_margins;
 
 /* Sizes okr_plan() reports. */
@@ -164,11 +166,13 @@ typedef struct {
     int32_t n_scored;   /* masks scored exactly */
     double flops;       /* algorithmic flops of the per-mask scoring kernel
                            (0 with OKR_PRECISION_FP64_FACTORED) */
-    float score_ms;     /* scoring-kernel time (OKR_FLAG_TIMING) */
+    float score_ms;     /* scoring-kernel time of the segment's chunk divided
+                           by the chunk's segments (OKR_FLAG_TIMING) */
     int32_t n_refined;  /* MIXED: masks rescored in FP64 (shortlists A + B) */
     double fp32_dev;    /* MIXED: max |e32 - e64| over rescored masks with e64 <= 2 e_bar */
     int32_t score_groups;   /* FP64 scoring launch shape: snapshot groups ... */
     int32_t score_mpl;      /* ... and masks per lane (default rule or autotuned) */
+    int32_t chunk;          /* index of the launch chunk the segment ran in */
 } okr_segment_result;
 
 /* Outputs (HOST buffers owned by the caller). */
@@ -183,14 +187,14 @@ typedef struct {
     float *features;         /* DEVICE [n_candidates][32] or NULL: per-mask surrogate
                                 features of every segment, in segment then mask order */
     float *targets;          /* DEVICE [n_candidates] or NULL: ln(e_loc + 1e-12) of
-                                every mask (FP64 scores); needs precision FP64 */
+                                every mask (FP64 scores); needs precision FP64 or FP64_FACTORED */
     int32_t n_kept;
     int32_t warnings;        /* OKR_W_* bits seen */
     double max_err;
     /* wall-clock phase times (ms) and summed kernel times (OKR_FLAG_TIMING) */
     double t_setup_ms, t_pf_ms, t_search_ms, t_final_ms;
     double score_kernel_ms, algorithmic_flops;
-    int32_t pf_iterations, n_score_launches;
+    int32_t pf_iterations, n_score_launches; /* scoring launches: one per chunk */
 } okr_result;
 
 /* One handle per HIP stream (hip_stream may be NULL for the null stream).

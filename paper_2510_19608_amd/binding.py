@@ -73,7 +73,7 @@ class SegmentResult(ctypes.Structure):
                 ("popcount", ctypes.c_int32), ("e_loc", ctypes.c_double), ("e_min", ctypes.c_double),
                 ("ambiguous", ctypes.c_int32), ("n_scored", ctypes.c_int32), ("flops", ctypes.c_double),
                 ("score_ms", ctypes.c_float), ("n_refined", ctypes.c_int32), ("fp32_dev", ctypes.c_double),
-                ("score_groups", ctypes.c_int32), ("score_mpl", ctypes.c_int32)]
+                ("score_groups", ctypes.c_int32), ("score_mpl", ctypes.c_int32), ("chunk", ctypes.c_int32)]
 
 
 class Result(ctypes.Structure):
@@ -337,7 +337,7 @@ class Reducer:
         segs = [dict(segment=s.segment, k=s.k, mask=s.mask, popcount=s.popcount, e_loc=s.e_loc,
                      e_min=s.e_min, ambiguous=bool(s.ambiguous), n_scored=s.n_scored, flops=s.flops,
                      score_ms=s.score_ms, n_refined=s.n_refined, fp32_dev=s.fp32_dev,
-                     score_groups=s.score_groups, score_mpl=s.score_mpl)
+                     score_groups=s.score_groups, score_mpl=s.score_mpl, chunk=s.chunk)
                 for s in list(self.out_seg)[:self.sizes.n_segments]]
         return dict(super=self.out_super.copy(), kept_parent=self.out_kp.copy(),
                     kept=(self.out_super == np.arange(self.n)).astype(np.uint8),

@@ -39,8 +39,9 @@ __device__ __forceinline__ int child_toward(const Topo& T, int h, int v) {
   return -1;
 }
 
-__global__ __launch_bounds__(256) void k_build_struct(Topo T, State St, int g, int S, SegHdr* __restrict__ hdrs,
-                                                      int* __restrict__ tab, int tab_cap, int* __restrict__ status) {
+__global__ __launch_bounds__(256) void k_build_struct(Topo T, State St, const int* __restrict__ segs, size_t lstride,
+                                                      int S, SegHdr* __restrict__ hdrs, int* __restrict__ tab,
+                                                      int tab_cap, int* __restrict__ status) {
   __shared__ int s_top[kMaxK], s_slotnode[kMaxK], s_slotbit[kMaxK], s_slotchain[kMaxK];
   __shared__ int s_cslot0[kMaxK + 1], s_head[kMaxK], s_outer[kMaxK], s_jslot[kMaxK];
   __shared__ int s_spos[kMaxK], s_ssize[kMaxK], s_sph[kMaxK];           // segment node j
@@ -56,6 +57,8 @@ __global__ __launch_bounds__(256) void k_build_struct(Topo T, State St, int g, i
   __shared__ int s_err, s_nch;
   __shared__ int s_zi[kOmegaLds], s_zk[kOmegaLds];  // zone pass: node and key of Omega index q
   __shared__ int s_tab[kTabLds];                     // structural tables before they are written out
+  const int g = segs[blockIdx.z];
+  tab = lane_ptr(tab, lstride);
   const int* parent = T.parent;
   const int* segment = T.segment;
   const int tid = threadIdx.x;
@@ -412,15 +415,21 @@ __device__ __forceinline__ int omega_node(const Topo& T, const int* rg, int nr, 
   return T.pre[rg[3 * r] + (q - rg[3 * r + 2])];
 }
 
-__global__ __launch_bounds__(256) void k_build_values(const SegHdr* __restrict__ hdrs, int g,
-                                                      const int* __restrict__ tab, int n,
+__global__ __launch_bounds__(256) void k_build_values(const SegHdr* __restrict__ hdrs, const int* __restrict__ segs,
+                                                      size_t lstride, const int* __restrict__ tab, int n,
                                                       const double2* __restrict__ Zroot,
                                                       const double2* __restrict__ Vcur,
                                                       const double2* __restrict__ A, double2* __restrict__ P,
                                                       TargetRec* __restrict__ srec, double2* __restrict__ headV,
                                                       TargetRec* __restrict__ zrec, double* __restrict__ econst) {
-  const SegHdr H = hdrs[g];
+  const SegHdr H = hdrs[segs[blockIdx.z]];
   if (!H.valid) return;
+  tab = lane_ptr(tab, lstride);
+  P = lane_ptr(P, lstride);
+  srec = lane_ptr(srec, lstride);
+  headV = lane_ptr(headV, lstride);
+  zrec = lane_ptr(zrec, lstride);
+  econst = lane_ptr(econst, lstride);
   const int part = blockIdx.y;
   const int S = H.S;
   const int stride = gridDim.x * blockDim.x;
@@ -480,13 +489,18 @@ __device__ __forceinline__ void atomic_max_nonneg(double* a, double v) {
 // Cluster statistics: every node of Omega_g contributes |V^| to the cluster of
 // its current super-node (a slot, a zone target, or a head outside Omega_g,
 // whose error is mask-independent and folds into econst).
-__global__ __launch_bounds__(256) void k_build_members(const SegHdr* __restrict__ hdrs, int g,
-                                                       const int* __restrict__ tab, Topo T, State St,
+__global__ __launch_bounds__(256) void k_build_members(const SegHdr* __restrict__ hdrs, const int* __restrict__ segs,
+                                                       size_t lstride, const int* __restrict__ tab, Topo T, State St,
                                                        const double2* __restrict__ Vcur,
                                                        const double* __restrict__ absV, TargetRec* __restrict__ srec,
                                                        TargetRec* __restrict__ zrec, double* __restrict__ econst) {
+  const int g = segs[blockIdx.z];
   const SegHdr H = hdrs[g];
   if (!H.valid) return;
+  tab = lane_ptr(tab, lstride);
+  srec = lane_ptr(srec, lstride);
+  zrec = lane_ptr(zrec, lstride);
+  econst = lane_ptr(econst, lstride);
   const int n = T.n;
   const int* rg = tab + H.o_range;
   const long total = (long)H.nomega * H.S;

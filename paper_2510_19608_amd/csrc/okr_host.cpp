@@ -24,24 +24,24 @@ __global__ void k_powerflow(int, const int*, const uint8_t*, const int*, const i
                             double2*, double2*, double2*, double*, int*, int*);
 __global__ void k_from_vhat(int, int, const uint8_t*, const double2*, const double2*, double, double, double2*,
                             double*, int*);
-__global__ void k_build_struct(Topo, State, int, int, SegHdr*, int*, int, int*);
+__global__ void k_build_struct(Topo, State, const int*, size_t, int, SegHdr*, int*, int, int*);
 __global__ void k_zroot(int, const int*, const int*, const int*, int, const double2*, double2*);
-__global__ void k_build_values(const SegHdr*, int, const int*, int, const double2*, const double2*, const double2*,
-                               double2*, TargetRec*, double2*, TargetRec*, double*);
-__global__ void k_build_members(const SegHdr*, int, const int*, Topo, State, const double2*, const double*,
-                                TargetRec*, TargetRec*, double*);
+__global__ void k_build_values(const SegHdr*, const int*, size_t, const int*, int, const double2*, const double2*,
+                               const double2*, double2*, TargetRec*, double2*, TargetRec*, double*);
+__global__ void k_build_members(const SegHdr*, const int*, size_t, const int*, Topo, State, const double2*,
+                                const double*, TargetRec*, TargetRec*, double*);
 template <int M>
-__global__ void k_score_fp64(const SegHdr*, int, const int*, const double2*, const TargetRec*, const double2*,
-                             const TargetRec*, const double*, int, int, SelParams, MaskScore*, MaskScore*, TileRec*,
-                             int*, const int*);
-__global__ void k_fac_tables(const SegHdr*, int, const int*, const double2*, const TargetRec*, const double2*,
-                             const TargetRec*, const double*, PatScore*, double*);
-__global__ void k_fac_combine(const SegHdr*, int, const int*, const PatScore*, const double*, SelParams, MaskScore*,
-                              TileRec*);
-__global__ void k_argmin(const SegHdr*, int, const MaskScore*, const TileRec*, SelParams, const int*, DevDecision*,
-                         const int*);
-__global__ void k_apply(const SegHdr*, int, const int*, Topo, State, const DevDecision*, const double2*,
-                        const TargetRec*, const TargetRec*, double2*, double2*);
+__global__ void k_score_fp64(const SegHdr*, const int*, size_t, const int*, const double2*, const TargetRec*,
+                             const double2*, const TargetRec*, const double*, int, int, SelParams, MaskScore*,
+                             MaskScore*, TileRec*, int*, const int*);
+__global__ void k_fac_tables(const SegHdr*, const int*, size_t, const int*, const double2*, const TargetRec*,
+                             const double2*, const TargetRec*, const double*, PatScore*, double*);
+__global__ void k_fac_combine(const SegHdr*, const int*, size_t, const int*, const PatScore*, const double*, SelParams,
+                              MaskScore*, TileRec*);
+__global__ void k_argmin(const SegHdr*, const int*, size_t, const MaskScore*, const TileRec*, SelParams, const int*,
+                         DevDecision*, const int*);
+__global__ void k_apply(const SegHdr*, const int*, size_t, const int*, Topo, State, const DevDecision*,
+                        const double2*, const TargetRec*, const TargetRec*, double2*, double2*);
 __global__ void k_init_state(int, State, int*, int, int*, int);
 __global__ void k_copy2(const double2*, double2*, size_t);
 __global__ void k_final_err(int, const uint8_t*, const int*, const double2*, const double*, double*);
@@ -97,6 +97,8 @@ using namespace okr;
 namespace {
 
 constexpr int kMaxSnapGroups = 32;
+constexpr int kMaxLanes = 8;      // segments per chunk (each needs a scratch block)
+constexpr int kDefaultLanes = 8;
 constexpr int kStatusInts = 16;
 constexpr double kMixedDelta = 1e-8;  // bound on |e32 - e64| used by the shortlist
 constexpr int kRefineBlocks = 256;
@@ -131,7 +133,7 @@ struct Layout {
 
 // offsets (in int32) of the static topology arrays inside the topology buffer
 struct TopoOffsets {
-  int parent, phase, segment, pos, size, pre, ch_off, ch, lvl_off, lvl_nodes, seg_off, seg_nodes, total;
+  int parent, phase, segment, pos, size, pre, ch_off, ch, lvl_off, lvl_nodes, seg_off, seg_nodes, chunks, total;
 };
 
 }  // namespace
@@ -162,15 +164,12 @@ struct okr_handle {
   std::vector<int> sg_tuned, mpl_tuned;
   int sg_force = 0, mpl_force = 0;
   size_t part_cap = 0;
-  // concurrent segment lanes: a stream each (lane 0 is the handle's stream
-  // when there is one lane), the lane of every segment, the earlier segments
-  // it must wait for, and one event per segment plus fork/join events
+  // segment chunks: every search step is one launch over a chunk of
+  // mutually independent segments (chunk c = chunk_segs[chunk_off[c] ..
+  // chunk_off[c + 1]), at most nlanes of them, each with its own scratch
+  // block); chunk_k = the chunk's largest segment size
   int nlanes = 1;
-  std::vector<hipStream_t> lane_st;
-  std::vector<int> lane_of;
-  std::vector<std::vector<int>> deps;
-  std::vector<hipEvent_t> seg_ev, join_ev;
-  hipEvent_t fork_ev = nullptr;
+  std::vector<int> chunk_off, chunk_segs, chunk_k;
 };
 
 namespace {
@@ -222,18 +221,6 @@ static void drop_events(okr_handle* h) {
   h->ev.clear();
 }
 
-static void drop_lanes(okr_handle* h) {
-  for (hipEvent_t e : h->seg_ev) (void)hipEventDestroy(e);
-  for (hipEvent_t e : h->join_ev) (void)hipEventDestroy(e);
-  if (h->fork_ev) (void)hipEventDestroy(h->fork_ev);
-  for (hipStream_t s : h->lane_st)
-    if (s != h->stream) (void)hipStreamDestroy(s);
-  h->seg_ev.clear();
-  h->join_ev.clear();
-  h->fork_ev = nullptr;
-  h->lane_st.clear();
-}
-
 extern "C" int okr_create(okr_handle** h, void* hip_stream) {
   if (!h) return OKR_E_ARG;
   okr_handle* H = new (std::nothrow) okr_handle();
@@ -247,7 +234,6 @@ extern "C" int okr_destroy(okr_handle* h) {
   if (!h) return OKR_E_ARG;
   drop_graph(h);
   drop_events(h);
-  drop_lanes(h);
   delete h;
   return OKR_OK;
 }
@@ -351,14 +337,17 @@ extern "C" int okr_plan(okr_handle* h, const okr_topology* topo, const okr_margi
     h->seg_nodes.insert(h->seg_nodes.end(), seg_nodes[g].begin(), seg_nodes[g].end());
   }
   h->nseg = nseg;
-  // Concurrent lanes.  A segment's search reads and writes state only inside
+  // Segment chunks.  A segment's search reads and writes state only inside
   // the subtrees of its possible chain tops (climb from each node through
   // segment nodes of any segment: every node that a chain of the segment can
   // ever pass lies there) and at the heads above them (moved currents land
-  // there).  Segments that share none of that are independent; a segment
-  // waits for the latest conflicting earlier segment of every lane.
+  // there).  Segments that share none of that are independent, so their
+  // order does not matter.  Every segment gets a level one above the highest
+  // level of the earlier segments it conflicts with; each level's segments
+  // (largest first) are cut into chunks of at most nlanes, and the chunks
+  // run level by level: conflicting segments keep their order.
   {
-    const int want = mg->lanes > 0 ? std::min(mg->lanes, 8) : 4;
+    const int want = mg->lanes > 0 ? std::min(mg->lanes, kMaxLanes) : kDefaultLanes;
     h->nlanes = std::max(1, std::min(want, nseg));
     std::vector<std::vector<std::pair<int, int>>> iv(nseg);
     std::vector<std::vector<int>> heads(nseg);
@@ -399,20 +388,37 @@ extern "C" int okr_plan(okr_handle* h, const okr_topology* topo, const okr_margi
         if (inside(x, iv[a])) return true;
       return false;
     };
-    h->lane_of.assign(nseg, 0);
-    h->deps.assign(nseg, {});
+    std::vector<int> level(nseg, 0);
+    int nlev_seg = 0;
     for (int g = 0; g < nseg; ++g) {
-      h->lane_of[g] = g % h->nlanes;
-      std::vector<int> last(h->nlanes, -1);
-      for (int b = g - 1; b >= 0; --b) {
-        const int lb = h->lane_of[b];
-        if (lb == h->lane_of[g] || last[lb] >= 0) continue;  // same lane: in order anyway
-        if (conflict(g, b)) last[lb] = b;
-      }
-      for (int l = 0; l < h->nlanes; ++l)
-        if (last[l] >= 0) h->deps[g].push_back(last[l]);
+      for (int b = g - 1; b >= 0; --b)
+        if (level[b] + 1 > level[g] && conflict(g, b)) level[g] = level[b] + 1;
+      nlev_seg = std::max(nlev_seg, level[g] + 1);
     }
-    drop_lanes(h);  // streams and events are created by the first search after a plan
+    std::vector<int> order(nseg);
+    for (int g = 0; g < nseg; ++g) order[g] = g;
+    auto ksz = [&](int g) { return h->seg_off[g + 1] - h->seg_off[g]; };
+    std::stable_sort(order.begin(), order.end(), [&](int a, int b) {
+      if (level[a] != level[b]) return level[a] < level[b];
+      if (ksz(a) != ksz(b)) return ksz(a) > ksz(b);
+      return a < b;
+    });
+    h->chunk_off.assign(1, 0);
+    h->chunk_segs.clear();
+    h->chunk_k.clear();
+    for (int i = 0; i < nseg; ++i) {
+      const int g = order[i];
+      const int c0 = h->chunk_off.back();
+      const int m = (int)h->chunk_segs.size() - c0;
+      if (m > 0 && (m == h->nlanes || level[h->chunk_segs[c0]] != level[g])) {
+        h->chunk_off.push_back((int)h->chunk_segs.size());
+        h->chunk_k.push_back(0);
+      }
+      if (h->chunk_k.empty()) h->chunk_k.push_back(0);
+      h->chunk_segs.push_back(g);
+      h->chunk_k.back() = std::max(h->chunk_k.back(), ksz(g));
+    }
+    if (!h->chunk_segs.empty()) h->chunk_off.push_back((int)h->chunk_segs.size());
   }
   // packed static topology
   TopoOffsets& TO = h->TO;
@@ -434,6 +440,7 @@ extern "C" int okr_plan(okr_handle* h, const okr_topology* topo, const okr_margi
   TO.lvl_nodes = put(h->lvl_nodes);
   TO.seg_off = put(h->seg_off);
   TO.seg_nodes = put(h->seg_nodes.empty() ? std::vector<int>{0} : h->seg_nodes);
+  TO.chunks = put(h->chunk_segs.empty() ? std::vector<int>{0} : h->chunk_segs);
   TO.phase = (int)tp.size();
   tp.resize(tp.size() + (n + 3) / 4, 0);
   std::memcpy(tp.data() + TO.phase, h->phase.data(), n);
@@ -466,7 +473,7 @@ extern "C" int okr_plan(okr_handle* h, const okr_topology* topo, const okr_margi
   L.iters = take(sizeof(int) * S);
   L.hdrs = take(sizeof(SegHdr) * std::max(nseg, 1));
   L.decs = take(sizeof(DevDecision) * std::max(nseg, 1));
-  // per-lane scratch (one block per concurrent lane, lane l at + l * lane_stride)
+  // per-segment scratch (one block per chunk position z, at + z * lane_stride)
   L.lane0 = off;
   L.tab = take(sizeof(int) * h->tab_cap);
   L.P = take(sizeof(double2) * 3 * (size_t)S * kMaxPairs);
@@ -563,7 +570,7 @@ namespace {
 struct Ptrs {
   Topo T;
   State St;
-  const int *lvl_off, *lvl_nodes;
+  const int *lvl_off, *lvl_nodes, *chunks;
   double2 *z, *Zroot, *Vhat, *Vcur, *A, *J, *P, *headV, *yeq, *Ykd, *Yko;
   double *absV, *econst, *err;
   int *status, *iters, *tab, *tickets, *kp;
@@ -591,7 +598,7 @@ struct Ptrs {
   int *scount, *sgates, *sstage;
 };
 
-// Device pointers, with the per-lane scratch of lane `lane`.
+// Device pointers, with the scratch block of chunk position `lane`.
 Ptrs pointers(okr_handle* h, void* d_workspace, int lane = 0) {
   const Layout& L = h->L;
   char* ws = static_cast<char*>(d_workspace);
@@ -616,6 +623,7 @@ Ptrs pointers(okr_handle* h, void* d_workspace, int lane = 0) {
   p.T.seg_nodes = tp + TO.seg_nodes;
   p.lvl_off = tp + TO.lvl_off;
   p.lvl_nodes = tp + TO.lvl_nodes;
+  p.chunks = tp + TO.chunks;
   p.St.kept = (uint8_t*)at(L.kept);
   p.St.sup = (int*)at(L.sup);
   p.St.slot_of = (int*)at(L.slot_of);
@@ -682,17 +690,14 @@ Ptrs pointers(okr_handle* h, void* d_workspace, int lane = 0) {
 }
 
 // Enqueue one whole search on `st` without host synchronisation.  With `ev`
-// (2 events per segment) the scoring launches are bracketed by events; with
+// (2 events per chunk) the scoring launches are bracketed by events; with
 // `dump` every segment's final per-mask scores are copied out.
 void enqueue_search(okr_handle* h, void* ws, const okr_yblocks* Y, const okr_loads* loads,
                     const okr_margins* mg, hipStream_t st, const std::vector<hipEvent_t>* ev,
                     std::vector<std::vector<MaskScore>>* dump, std::vector<std::vector<MaskScore32>>* dump32,
-                    float* feat_out, float* targ_out, bool use_lanes) {
+                    float* feat_out, float* targ_out) {
   const int n = h->n, S = h->S;
   const Ptrs p = pointers(h, ws);
-  // lanes run concurrently on streams of their own; without use_lanes every
-  // segment runs in order on st (one scratch block)
-  const int nl = use_lanes ? h->nlanes : 1;
   std::vector<Ptrs> lp(h->nlanes);
   for (int l = 0; l < h->nlanes; ++l) lp[l] = pointers(h, ws, l);
   const bool vhat_given = (mg->flags & OKR_FLAG_VHAT_GIVEN) != 0;
@@ -735,45 +740,42 @@ void enqueue_search(okr_handle* h, void* ws, const okr_yblocks* Y, const okr_loa
   if (surr)
     hipLaunchKernelGGL(k_refresh_weights, dim3((kSurrH * kSurrH + 255) / 256), dim3(256), 0, st, mg->surrogate,
                        p.sW1b, p.sW2b, (__bf16*)nullptr);
-  size_t feat_off = 0;
   const int members_blocks = std::min(2048, std::max(1, (int)(((size_t)n * S + 255) / 256)));
-  // segments run on their lanes, each after the earlier segments it conflicts with
-  if (nl > 1) {
-    (void)hipEventRecord(h->fork_ev, st);
-    for (int l = 0; l < nl; ++l) (void)hipStreamWaitEvent(h->lane_st[l], h->fork_ev, 0);
-  }
-  for (int g = 0; g < h->nseg; ++g) {
-    const int k = h->seg_off[g + 1] - h->seg_off[g];
-    const int lane = nl > 1 ? h->lane_of[g] : 0;
-    hipStream_t ls = nl > 1 ? h->lane_st[lane] : st;
-    const Ptrs& q = lp[lane];
-    if (nl > 1)
-      for (int d : h->deps[g]) (void)hipStreamWaitEvent(ls, h->seg_ev[d], 0);
-    hipLaunchKernelGGL(k_build_struct, dim3(1), dim3(256), 0, ls, q.T, q.St, g, S, q.hdrs, q.tab, h->tab_cap,
-                       q.status);
-    hipLaunchKernelGGL(k_build_values, dim3(256, 5), dim3(256), 0, ls, (const SegHdr*)q.hdrs, g, (const int*)q.tab,
-                       n, (const double2*)q.Zroot, (const double2*)q.Vcur, (const double2*)q.A, q.P, q.srec, q.headV,
+  // per-mask feature rows of segment g start at foff[g] (segments in id order)
+  std::vector<size_t> foff(h->nseg + 1, 0);
+  for (int g = 0; g < h->nseg; ++g) foff[g + 1] = foff[g] + ((size_t)1 << (h->seg_off[g + 1] - h->seg_off[g]));
+  const size_t lstride = h->L.lane_stride;
+  const int nchunk = (int)h->chunk_k.size();
+  for (int c = 0; c < nchunk; ++c) {
+    const int c0 = h->chunk_off[c], nz = h->chunk_off[c + 1] - c0;
+    const int* segs = p.chunks + c0;  // device copy of this chunk's segment ids
+    const int kc = h->chunk_k[c];
+    const Ptrs& q = lp[0];  // scratch of chunk position 0; position z is z * lstride further
+    hipLaunchKernelGGL(k_build_struct, dim3(1, 1, nz), dim3(256), 0, st, q.T, q.St, segs, lstride, S, q.hdrs, q.tab,
+                       h->tab_cap, q.status);
+    hipLaunchKernelGGL(k_build_values, dim3(256, 5, nz), dim3(256), 0, st, (const SegHdr*)q.hdrs, segs, lstride,
+                       (const int*)q.tab, n, (const double2*)q.Zroot, (const double2*)q.Vcur, (const double2*)q.A, q.P,
+                       q.srec, q.headV, q.zrec, q.econst);
+    hipLaunchKernelGGL(k_build_members, dim3(members_blocks, 1, nz), dim3(256), 0, st, (const SegHdr*)q.hdrs, segs,
+                       lstride, (const int*)q.tab, q.T, q.St, (const double2*)q.Vcur, (const double*)q.absV, q.srec,
                        q.zrec, q.econst);
-    hipLaunchKernelGGL(k_build_members, dim3(members_blocks), dim3(256), 0, ls, (const SegHdr*)q.hdrs, g,
-                       (const int*)q.tab, q.T, q.St, (const double2*)q.Vcur, (const double*)q.absV, q.srec, q.zrec,
-                       q.econst);
-    const uint32_t nmask = 1u << k;
-    const int mpl = score_mpl(h, k);
+    const uint32_t nmask = 1u << kc;
+    const int mpl = score_mpl(h, kc);
     const int mblocks = (int)((nmask + kScoreThreads * mpl - 1) / (kScoreThreads * mpl));
     int spg;
-    const int SG = snap_groups(h, k, &spg);
-    // the FP32 screen: masks per lane and groups by the default rule
-    const int mpl32 = k >= 12 ? 4 : (k >= 10 ? 2 : 1);
-    const int mblocks32 = (int)((nmask + kScoreThreads * mpl32 - 1) / (kScoreThreads * mpl32));
-    int spg32;
-    const int SG32 = snap_groups_default(k, S, &spg32, mpl32);
-    const int* gate = nullptr;
-    if (surr || feat_out) {
-      hipLaunchKernelGGL(k_surr_tables, dim3(kMaxPairs + kMaxK), dim3(64), 0, ls,
-                         (const SegHdr*)q.hdrs, g, (const int*)q.tab, n, (const double2*)q.Zroot, (const double2*)q.P,
-                         (const double2*)q.A, (const TargetRec*)q.srec, q.spz, q.szs, q.sss);
-    }
-    if (surr) {
+    const int SG = snap_groups(h, kc, &spg);
+    const int* gates = surr ? q.sgates : nullptr;
+    for (int z = 0; z < nz; ++z) {
+      const int g = h->chunk_segs[c0 + z];
+      const int k = h->seg_off[g + 1] - h->seg_off[g];
+      const uint32_t nm = 1u << k;
+      const Ptrs& w = lp[z];
+      if (surr || feat_out) {
+        hipLaunchKernelGGL(k_surr_tables, dim3(kMaxPairs + kMaxK), dim3(64), 0, st, (const SegHdr*)w.hdrs, g,
+                           (const int*)w.tab, n, (const double2*)w.Zroot, (const double2*)w.P, (const double2*)w.A,
+                           (const TargetRec*)w.srec, w.spz, w.szs, w.sss);
+      }
+      if (!surr) continue;
       // Rank the masks with the surrogate and rescore the top-k exactly.
       // Stage 1 ranks only the top levels (popcount >= L1, at least 4 top_k
       // masks); when they hold top_k masks predicted feasible, those are the
@@ -785,146 +787,166 @@ void enqueue_search(okr_handle* h, void* ws, const okr_yblocks* Y, const okr_loa
       uint64_t N1 = 1;
       while (L1 > 0 && N1 < (uint64_t)4 * K) {
         --L1;
-        uint64_t c = 1;
-        for (int q = 1; q <= L1; ++q) c = c * (uint64_t)(k - L1 + q) / (uint64_t)q;
-        N1 += c;
+        uint64_t cb = 1;
+        for (int r = 1; r <= L1; ++r) cb = cb * (uint64_t)(k - L1 + r) / (uint64_t)r;
+        N1 += cb;
       }
-      const bool staged = N1 < nmask;
-      int* stage = q.sstage + g;
+      const bool staged = N1 < nm;
+      int* stage = w.sstage + g;
       auto rank = [&](const uint32_t* masks, int nrow, const int* flag, int skip_if) {
         const int Mp = std::max(64, (nrow + 63) / 64 * 64);
-        hipLaunchKernelGGL(k_surr_features, dim3((Mp + 255) / 256), dim3(256), 0, ls, (const SegHdr*)q.hdrs, g,
-                           (const int*)q.tab, (const float*)q.spz, (const float*)q.szs, (const SurrSlot*)q.sss,
-                           (const double*)q.econst, masks, nrow, Mp, (float*)nullptr, q.sXb, flag, skip_if);
-        hipLaunchKernelGGL(k_gemm_nt<1>, dim3(kSurrH / 64, Mp / 64), dim3(256), 0, ls, (const __bf16*)q.sXb, kSurrF,
-                           (const __bf16*)q.sW1b, kSurrF, kSurrF, (float*)nullptr, kSurrH, mg->surrogate + kOffB1,
-                           (float*)nullptr, q.sH1b, (__bf16*)nullptr, Mp, (const float*)nullptr, (float*)nullptr,
+        hipLaunchKernelGGL(k_surr_features, dim3((Mp + 255) / 256), dim3(256), 0, st, (const SegHdr*)w.hdrs, g,
+                           (const int*)w.tab, (const float*)w.spz, (const float*)w.szs, (const SurrSlot*)w.sss,
+                           (const double*)w.econst, masks, nrow, Mp, (float*)nullptr, w.sXb, flag, skip_if);
+        hipLaunchKernelGGL(k_gemm_nt<1>, dim3(kSurrH / 64, Mp / 64), dim3(256), 0, st, (const __bf16*)w.sXb, kSurrF,
+                           (const __bf16*)w.sW1b, kSurrF, kSurrF, (float*)nullptr, kSurrH, mg->surrogate + kOffB1,
+                           (float*)nullptr, w.sH1b, (__bf16*)nullptr, Mp, (const float*)nullptr, (float*)nullptr,
                            flag, skip_if);
-        hipLaunchKernelGGL(k_gemm_nt<2>, dim3(kSurrH / 64, Mp / 64), dim3(256), 0, ls, (const __bf16*)q.sH1b, kSurrH,
-                           (const __bf16*)q.sW2b, kSurrH, kSurrH, (float*)nullptr, kSurrH, mg->surrogate + kOffB2,
-                           (float*)nullptr, (__bf16*)nullptr, (__bf16*)nullptr, Mp, mg->surrogate + kOffW3, q.spart,
+        hipLaunchKernelGGL(k_gemm_nt<2>, dim3(kSurrH / 64, Mp / 64), dim3(256), 0, st, (const __bf16*)w.sH1b, kSurrH,
+                           (const __bf16*)w.sW2b, kSurrH, kSurrH, (float*)nullptr, kSurrH, mg->surrogate + kOffB2,
+                           (float*)nullptr, (__bf16*)nullptr, (__bf16*)nullptr, Mp, mg->surrogate + kOffW3, w.spart,
                            flag, skip_if);
-        hipLaunchKernelGGL(k_rowdot_finish, dim3((Mp + 255) / 256), dim3(256), 0, ls, (const float*)q.spart,
-                           kSurrH / 32, Mp, mg->surrogate + kOffB3, q.sy, flag, skip_if);
-        hipLaunchKernelGGL(k_surr_keys, dim3((nrow + 255) / 256), dim3(256), 0, ls, (const SegHdr*)q.hdrs, g,
-                           (const float*)q.sy, ln_ebar, masks, nrow, q.skeys, flag, skip_if);
+        hipLaunchKernelGGL(k_rowdot_finish, dim3((Mp + 255) / 256), dim3(256), 0, st, (const float*)w.spart,
+                           kSurrH / 32, Mp, mg->surrogate + kOffB3, w.sy, flag, skip_if);
+        hipLaunchKernelGGL(k_surr_keys, dim3((nrow + 255) / 256), dim3(256), 0, st, (const SegHdr*)w.hdrs, g,
+                           (const float*)w.sy, ln_ebar, masks, nrow, w.skeys, flag, skip_if);
       };
       if (staged) {
-        hipLaunchKernelGGL(k_level_masks, dim3(((int)N1 + 63) / 64 * 64 / 64), dim3(64), 0, ls, k, L1, (int)N1,
-                           ((int)N1 + 63) / 64 * 64, q.slevel);
-        rank(q.slevel, (int)N1, (const int*)nullptr, 0);
-        hipLaunchKernelGGL(k_surr_stage, dim3(1), dim3(256), 0, ls, (const SegHdr*)q.hdrs, g,
-                           (const uint32_t*)q.skeys, (int)N1, K, stage);
-        hipLaunchKernelGGL(k_topk, dim3(1), dim3(1024), 0, ls, (const SegHdr*)q.hdrs, g, (const uint32_t*)q.skeys,
-                           (const uint32_t*)q.slevel, (int)N1, K, (const int*)q.status, q.slist, q.scount,
+        hipLaunchKernelGGL(k_level_masks, dim3(((int)N1 + 63) / 64 * 64 / 64), dim3(64), 0, st, k, L1, (int)N1,
+                           ((int)N1 + 63) / 64 * 64, w.slevel);
+        rank(w.slevel, (int)N1, (const int*)nullptr, 0);
+        hipLaunchKernelGGL(k_surr_stage, dim3(1), dim3(256), 0, st, (const SegHdr*)w.hdrs, g,
+                           (const uint32_t*)w.skeys, (int)N1, K, stage);
+        hipLaunchKernelGGL(k_topk, dim3(1), dim3(1024), 0, st, (const SegHdr*)w.hdrs, g, (const uint32_t*)w.skeys,
+                           (const uint32_t*)w.slevel, (int)N1, K, (const int*)w.status, w.slist, w.scount,
                            (const int*)stage, 0);
-        rank((const uint32_t*)nullptr, (int)nmask, (const int*)stage, 1);
-        hipLaunchKernelGGL(k_topk, dim3(1), dim3(1024), 0, ls, (const SegHdr*)q.hdrs, g, (const uint32_t*)q.skeys,
-                           (const uint32_t*)nullptr, (int)nmask, K, (const int*)q.status, q.slist, q.scount,
+        rank((const uint32_t*)nullptr, (int)nm, (const int*)stage, 1);
+        hipLaunchKernelGGL(k_topk, dim3(1), dim3(1024), 0, st, (const SegHdr*)w.hdrs, g, (const uint32_t*)w.skeys,
+                           (const uint32_t*)nullptr, (int)nm, K, (const int*)w.status, w.slist, w.scount,
                            (const int*)stage, 1);
       } else {
-        rank((const uint32_t*)nullptr, (int)nmask, (const int*)nullptr, 0);
-        hipLaunchKernelGGL(k_topk, dim3(1), dim3(1024), 0, ls, (const SegHdr*)q.hdrs, g, (const uint32_t*)q.skeys,
-                           (const uint32_t*)nullptr, (int)nmask, K, (const int*)q.status, q.slist, q.scount,
+        rank((const uint32_t*)nullptr, (int)nm, (const int*)nullptr, 0);
+        hipLaunchKernelGGL(k_topk, dim3(1), dim3(1024), 0, st, (const SegHdr*)w.hdrs, g, (const uint32_t*)w.skeys,
+                           (const uint32_t*)nullptr, (int)nm, K, (const int*)w.status, w.slist, w.scount,
                            (const int*)nullptr, 0);
       }
-      hipLaunchKernelGGL(k_refine_fp64, dim3(kRefineBlocks), dim3(kScoreBlock), 0, ls, (const SegHdr*)q.hdrs, g,
-                         (const int*)q.tab, (const double2*)q.P, (const TargetRec*)q.srec, (const double2*)q.headV,
-                         (const TargetRec*)q.zrec, (const double*)q.econst, sp, (const uint32_t*)q.slist,
-                         (const int*)q.scount, q.sscore);
-      hipLaunchKernelGGL(k_surr_decide, dim3(1), dim3(1024), 0, ls, (const SegHdr*)q.hdrs, g, sp,
-                         (const int*)q.status, (const uint32_t*)q.slist, (const int*)q.scount,
-                         (const MaskScore*)q.sscore, q.decs, q.sgates + g);
-      gate = q.sgates + g;
+      hipLaunchKernelGGL(k_refine_fp64, dim3(kRefineBlocks), dim3(kScoreBlock), 0, st, (const SegHdr*)w.hdrs, g,
+                         (const int*)w.tab, (const double2*)w.P, (const TargetRec*)w.srec, (const double2*)w.headV,
+                         (const TargetRec*)w.zrec, (const double*)w.econst, sp, (const uint32_t*)w.slist,
+                         (const int*)w.scount, w.sscore);
+      hipLaunchKernelGGL(k_surr_decide, dim3(1), dim3(1024), 0, st, (const SegHdr*)w.hdrs, g, sp,
+                         (const int*)w.status, (const uint32_t*)w.slist, (const int*)w.scount,
+                         (const MaskScore*)w.sscore, w.decs, w.sgates + g);
     }
     if (!mixed) {
-      if (ev) (void)hipEventRecord((*ev)[2 * g], ls);
-#define OKR_SCORE64(M_)                                                                                      \
-  hipLaunchKernelGGL(k_score_fp64<M_>, dim3(mblocks, SG), dim3(kScoreThreads), 0, ls, (const SegHdr*)q.hdrs, g, \
-                     (const int*)q.tab, (const double2*)q.P, (const TargetRec*)q.srec, (const double2*)q.headV, \
-                     (const TargetRec*)q.zrec, (const double*)q.econst, spg, SG, sp, q.part, q.fin, q.tiles,   \
-                     q.tickets, gate)
+      if (ev) (void)hipEventRecord((*ev)[2 * c], st);
       if (factored) {
         // pattern table (grid-stride waves: up to 2^(k+1) patterns), then every mask
-        const int tblocks = (int)std::min<uint64_t>(1024, std::max<uint64_t>(4, ((uint64_t)2 << k) / 32));
-        hipLaunchKernelGGL(k_fac_tables, dim3(tblocks), dim3(256), 0, ls, (const SegHdr*)q.hdrs, g,
+        const int tblocks = (int)std::min<uint64_t>(1024, std::max<uint64_t>(4, ((uint64_t)2 << kc) / 32));
+        hipLaunchKernelGGL(k_fac_tables, dim3(tblocks, 1, nz), dim3(256), 0, st, (const SegHdr*)q.hdrs, segs, lstride,
                            (const int*)q.tab, (const double2*)q.P, (const TargetRec*)q.srec, (const double2*)q.headV,
                            (const TargetRec*)q.zrec, (const double*)q.econst, q.pat, q.ecmax);
-        hipLaunchKernelGGL(k_fac_combine, dim3((nmask + 255) / 256), dim3(256), 0, ls, (const SegHdr*)q.hdrs, g,
-                           (const int*)q.tab, (const PatScore*)q.pat, (const double*)q.ecmax, sp, q.fin, q.tiles);
-      } else if (mpl == 4) OKR_SCORE64(4);
-      else if (mpl == 2) OKR_SCORE64(2);
-      else OKR_SCORE64(1);
+        hipLaunchKernelGGL(k_fac_combine, dim3((nmask + 255) / 256, 1, nz), dim3(256), 0, st, (const SegHdr*)q.hdrs,
+                           segs, lstride, (const int*)q.tab, (const PatScore*)q.pat, (const double*)q.ecmax, sp, q.fin,
+                           q.tiles);
+      } else {
+#define OKR_SCORE64(M_)                                                                                             \
+  hipLaunchKernelGGL(k_score_fp64<M_>, dim3(mblocks, SG, nz), dim3(kScoreThreads), 0, st, (const SegHdr*)q.hdrs, segs, \
+                     lstride, (const int*)q.tab, (const double2*)q.P, (const TargetRec*)q.srec,                      \
+                     (const double2*)q.headV, (const TargetRec*)q.zrec, (const double*)q.econst, spg, SG, sp, q.part, \
+                     q.fin, q.tiles, q.tickets, gates)
+        if (mpl == 4) OKR_SCORE64(4);
+        else if (mpl == 2) OKR_SCORE64(2);
+        else OKR_SCORE64(1);
 #undef OKR_SCORE64
-      if (ev) (void)hipEventRecord((*ev)[2 * g + 1], ls);
-      hipLaunchKernelGGL(k_argmin, dim3(1), dim3(1024), 0, ls, (const SegHdr*)q.hdrs, g, (const MaskScore*)q.fin,
-                         (const TileRec*)q.tiles, sp, (const int*)q.status, q.decs, gate);
-      if (feat_out && !surr) {
-        hipLaunchKernelGGL(k_surr_features, dim3((nmask + 255) / 256), dim3(256), 0, ls, (const SegHdr*)q.hdrs, g,
-                           (const int*)q.tab, (const float*)q.spz, (const float*)q.szs, (const SurrSlot*)q.sss,
-                           (const double*)q.econst, (const uint32_t*)nullptr, (int)nmask, (int)nmask,
-                           feat_out + feat_off * kSurrF, (__bf16*)nullptr, (const int*)nullptr, 0);
-        if (targ_out)
-          hipLaunchKernelGGL(k_surr_target, dim3((nmask + 255) / 256), dim3(256), 0, ls, (const SegHdr*)q.hdrs, g,
-                             (const MaskScore*)q.fin, targ_out + feat_off);
       }
-      feat_off += nmask;
-      if (dump) {
-        (*dump)[g].resize(nmask);
-        (void)hipMemcpyAsync((*dump)[g].data(), q.fin, sizeof(MaskScore) * nmask, hipMemcpyDeviceToHost, ls);
+      if (ev) (void)hipEventRecord((*ev)[2 * c + 1], st);
+      hipLaunchKernelGGL(k_argmin, dim3(1, 1, nz), dim3(1024), 0, st, (const SegHdr*)q.hdrs, segs, lstride,
+                         (const MaskScore*)q.fin, (const TileRec*)q.tiles, sp, (const int*)q.status, q.decs, gates);
+      for (int z = 0; z < nz; ++z) {
+        const int g = h->chunk_segs[c0 + z];
+        const uint32_t nm = 1u << (h->seg_off[g + 1] - h->seg_off[g]);
+        const Ptrs& w = lp[z];
+        if (feat_out && !surr) {
+          hipLaunchKernelGGL(k_surr_features, dim3((nm + 255) / 256), dim3(256), 0, st, (const SegHdr*)w.hdrs, g,
+                             (const int*)w.tab, (const float*)w.spz, (const float*)w.szs, (const SurrSlot*)w.sss,
+                             (const double*)w.econst, (const uint32_t*)nullptr, (int)nm, (int)nm,
+                             feat_out + foff[g] * kSurrF, (__bf16*)nullptr, (const int*)nullptr, 0);
+          if (targ_out)
+            hipLaunchKernelGGL(k_surr_target, dim3((nm + 255) / 256), dim3(256), 0, st, (const SegHdr*)w.hdrs, g,
+                               (const MaskScore*)w.fin, targ_out + foff[g]);
+        }
+        if (dump) {
+          (*dump)[g].resize(nm);
+          (void)hipMemcpyAsync((*dump)[g].data(), w.fin, sizeof(MaskScore) * nm, hipMemcpyDeviceToHost, st);
+        }
       }
     } else {
-      hipLaunchKernelGGL(k_build_mixed, dim3(256, 4), dim3(256), 0, ls, (const SegHdr*)q.hdrs, g, (const int*)q.tab,
-                         n, (const double2*)q.Vcur, (const double2*)q.P, (const TargetRec*)q.srec,
-                         (const double2*)q.headV, (const TargetRec*)q.zrec, mg->v_min, mg->v_max, q.P32, q.S32,
-                         q.H32, q.Z32);
-      if (ev) (void)hipEventRecord((*ev)[2 * g], ls);
+      // the FP32 screen: masks per lane and groups by the default rule
+      const int mpl32 = kc >= 12 ? 4 : (kc >= 10 ? 2 : 1);
+      int spg32;
+      const int SG32 = snap_groups_default(kc, S, &spg32, mpl32);
+      for (int z = 0; z < nz; ++z) {
+        const int g = h->chunk_segs[c0 + z];
+        const Ptrs& w = lp[z];
+        hipLaunchKernelGGL(k_build_mixed, dim3(256, 4), dim3(256), 0, st, (const SegHdr*)w.hdrs, g, (const int*)w.tab,
+                           n, (const double2*)w.Vcur, (const double2*)w.P, (const TargetRec*)w.srec,
+                           (const double2*)w.headV, (const TargetRec*)w.zrec, mg->v_min, mg->v_max, w.P32, w.S32,
+                           w.H32, w.Z32);
+      }
+      if (ev) (void)hipEventRecord((*ev)[2 * c], st);
+      for (int z = 0; z < nz; ++z) {
+        const int g = h->chunk_segs[c0 + z];
+        const int k = h->seg_off[g + 1] - h->seg_off[g];
+        const Ptrs& w = lp[z];
+        const uint32_t nm = 1u << k;
+        const int mblocks32 = (int)((nm + kScoreThreads * mpl32 - 1) / (kScoreThreads * mpl32));
 #define OKR_SCORE32(M_)                                                                                       \
-  hipLaunchKernelGGL(k_score_fp32<M_>, dim3(mblocks32, SG32), dim3(kScoreThreads), 0, ls, (const SegHdr*)q.hdrs, g, \
-                     (const int*)q.tab, (const Pair32*)q.P32, (const Rec32*)q.S32, (const Head32*)q.H32,         \
-                     (const Rec32*)q.Z32, (const double*)q.econst, spg32, SG32, sp, q.part32, q.fin32, q.tiles32, \
-                     q.tickets)
-      if (mpl32 == 4) OKR_SCORE32(4);
-      else if (mpl32 == 2) OKR_SCORE32(2);
-      else OKR_SCORE32(1);
+  hipLaunchKernelGGL(k_score_fp32<M_>, dim3(mblocks32, SG32), dim3(kScoreThreads), 0, st, (const SegHdr*)w.hdrs, g, \
+                     (const int*)w.tab, (const Pair32*)w.P32, (const Rec32*)w.S32, (const Head32*)w.H32,         \
+                     (const Rec32*)w.Z32, (const double*)w.econst, spg32, SG32, sp, w.part32, w.fin32, w.tiles32, \
+                     w.tickets)
+        if (mpl32 == 4) OKR_SCORE32(4);
+        else if (mpl32 == 2) OKR_SCORE32(2);
+        else OKR_SCORE32(1);
 #undef OKR_SCORE32
-      if (ev) (void)hipEventRecord((*ev)[2 * g + 1], ls);
-      int* cA = q.counts;
-      int* cB = q.counts + 1;
-      hipLaunchKernelGGL(k_mixed_select_a, dim3(1), dim3(1024), 0, ls, (const SegHdr*)q.hdrs, g,
-                         (const MaskScore32*)q.fin32, (const TileRec32*)q.tiles32, sp, (const int*)q.status,
-                         q.mstate, q.listA, cA);
-      hipLaunchKernelGGL(k_refine_fp64, dim3(kRefineBlocks), dim3(kScoreBlock), 0, ls, (const SegHdr*)q.hdrs, g,
-                         (const int*)q.tab, (const double2*)q.P, (const TargetRec*)q.srec, (const double2*)q.headV,
-                         (const TargetRec*)q.zrec, (const double*)q.econst, sp, (const uint32_t*)q.listA,
-                         (const int*)cA, q.scoreA);
-      hipLaunchKernelGGL(k_mixed_select_b, dim3(1), dim3(1024), 0, ls, (const SegHdr*)q.hdrs, g,
-                         (const MaskScore32*)q.fin32, (const TileRec32*)q.tiles32, sp, (const int*)q.status,
-                         q.mstate, (const uint32_t*)q.listA, (const int*)cA, (const MaskScore*)q.scoreA, q.listB,
-                         cB);
-      hipLaunchKernelGGL(k_refine_fp64, dim3(kRefineBlocks), dim3(kScoreBlock), 0, ls, (const SegHdr*)q.hdrs, g,
-                         (const int*)q.tab, (const double2*)q.P, (const TargetRec*)q.srec, (const double2*)q.headV,
-                         (const TargetRec*)q.zrec, (const double*)q.econst, sp, (const uint32_t*)q.listB,
-                         (const int*)cB, q.scoreB);
-      hipLaunchKernelGGL(k_mixed_final, dim3(1), dim3(1024), 0, ls, (const SegHdr*)q.hdrs, g, sp,
-                         (const int*)q.status, q.mstate, (const MaskScore32*)q.fin32, (const uint32_t*)q.listA,
-                         (const int*)cA, (const MaskScore*)q.scoreA, (const uint32_t*)q.listB, (const int*)cB,
-                         (const MaskScore*)q.scoreB, q.decs);
-      if (dump) {
-        (*dump32)[g].resize(nmask);
-        (void)hipMemcpyAsync((*dump32)[g].data(), q.fin32, sizeof(MaskScore32) * nmask, hipMemcpyDeviceToHost, ls);
+      }
+      if (ev) (void)hipEventRecord((*ev)[2 * c + 1], st);
+      for (int z = 0; z < nz; ++z) {
+        const int g = h->chunk_segs[c0 + z];
+        const uint32_t nm = 1u << (h->seg_off[g + 1] - h->seg_off[g]);
+        const Ptrs& w = lp[z];
+        int* cA = w.counts;
+        int* cB = w.counts + 1;
+        hipLaunchKernelGGL(k_mixed_select_a, dim3(1), dim3(1024), 0, st, (const SegHdr*)w.hdrs, g,
+                           (const MaskScore32*)w.fin32, (const TileRec32*)w.tiles32, sp, (const int*)w.status,
+                           w.mstate, w.listA, cA);
+        hipLaunchKernelGGL(k_refine_fp64, dim3(kRefineBlocks), dim3(kScoreBlock), 0, st, (const SegHdr*)w.hdrs, g,
+                           (const int*)w.tab, (const double2*)w.P, (const TargetRec*)w.srec, (const double2*)w.headV,
+                           (const TargetRec*)w.zrec, (const double*)w.econst, sp, (const uint32_t*)w.listA,
+                           (const int*)cA, w.scoreA);
+        hipLaunchKernelGGL(k_mixed_select_b, dim3(1), dim3(1024), 0, st, (const SegHdr*)w.hdrs, g,
+                           (const MaskScore32*)w.fin32, (const TileRec32*)w.tiles32, sp, (const int*)w.status,
+                           w.mstate, (const uint32_t*)w.listA, (const int*)cA, (const MaskScore*)w.scoreA, w.listB,
+                           cB);
+        hipLaunchKernelGGL(k_refine_fp64, dim3(kRefineBlocks), dim3(kScoreBlock), 0, st, (const SegHdr*)w.hdrs, g,
+                           (const int*)w.tab, (const double2*)w.P, (const TargetRec*)w.srec, (const double2*)w.headV,
+                           (const TargetRec*)w.zrec, (const double*)w.econst, sp, (const uint32_t*)w.listB,
+                           (const int*)cB, w.scoreB);
+        hipLaunchKernelGGL(k_mixed_final, dim3(1), dim3(1024), 0, st, (const SegHdr*)w.hdrs, g, sp,
+                           (const int*)w.status, w.mstate, (const MaskScore32*)w.fin32, (const uint32_t*)w.listA,
+                           (const int*)cA, (const MaskScore*)w.scoreA, (const uint32_t*)w.listB, (const int*)cB,
+                           (const MaskScore*)w.scoreB, w.decs);
+        if (dump) {
+          (*dump32)[g].resize(nm);
+          (void)hipMemcpyAsync((*dump32)[g].data(), w.fin32, sizeof(MaskScore32) * nm, hipMemcpyDeviceToHost, st);
+        }
       }
     }
-    hipLaunchKernelGGL(k_apply, dim3(S), dim3(64), 0, ls, (const SegHdr*)q.hdrs, g, (const int*)q.tab, q.T, q.St,
-                       (const DevDecision*)q.decs, (const double2*)q.P, (const TargetRec*)q.srec,
-                       (const TargetRec*)q.zrec, q.Vcur, q.A);
-    if (nl > 1) (void)hipEventRecord(h->seg_ev[g], ls);
+    hipLaunchKernelGGL(k_apply, dim3(S, 1, nz), dim3(64), 0, st, (const SegHdr*)q.hdrs, segs, lstride,
+                       (const int*)q.tab, q.T, q.St, (const DevDecision*)q.decs, (const double2*)q.P,
+                       (const TargetRec*)q.srec, (const TargetRec*)q.zrec, q.Vcur, q.A);
   }
-  if (nl > 1)
-    for (int l = 0; l < nl; ++l) {
-      (void)hipEventRecord(h->join_ev[l], h->lane_st[l]);
-      (void)hipStreamWaitEvent(st, h->join_ev[l], 0);
-    }
   hipLaunchKernelGGL(k_kron_yeq, dim3((n + 127) / 128), dim3(128), 0, st, p.T, p.St, (const double2*)p.z, p.yeq,
                      p.Yko, p.kp, p.status);
   hipLaunchKernelGGL(k_kron_diag, dim3((n + 127) / 128), dim3(128), 0, st, p.T, p.St, (const double2*)p.yeq, p.Ykd);
@@ -982,19 +1004,6 @@ extern "C" int okr_reduce_feeder(okr_handle* h, const okr_yblocks* Y, const okr_
     h->ev.resize(2 * std::max(nseg, 1), nullptr);
     for (auto& e : h->ev) OKR_HIP(h, hipEventCreate(&e));
   }
-  if ((int)h->lane_st.size() != h->nlanes || (int)h->seg_ev.size() != nseg) {
-    drop_lanes(h);
-    for (int l = 0; l < h->nlanes; ++l) {
-      hipStream_t ls = h->stream;
-      if (h->nlanes > 1) OKR_HIP(h, hipStreamCreateWithFlags(&ls, hipStreamNonBlocking));
-      h->lane_st.push_back(ls);
-    }
-    h->seg_ev.assign(nseg, nullptr);
-    for (auto& e : h->seg_ev) OKR_HIP(h, hipEventCreateWithFlags(&e, hipEventDisableTiming));
-    h->join_ev.assign(h->nlanes, nullptr);
-    for (auto& e : h->join_ev) OKR_HIP(h, hipEventCreateWithFlags(&e, hipEventDisableTiming));
-    OKR_HIP(h, hipEventCreateWithFlags(&h->fork_ev, hipEventDisableTiming));
-  }
   if (mg->flags & OKR_FLAG_AUTOTUNE) {
     // time the scoring launches of a whole search once per candidate group
     // count; keep the fastest per segment size
@@ -1015,18 +1024,18 @@ extern "C" int okr_reduce_feeder(okr_handle* h, const okr_yblocks* Y, const okr_
       for (int c = 1; c <= std::min(S, kMaxSnapGroups); c *= 2) {
         h->sg_force = c;
         h->mpl_force = 1 << mi;
-        enqueue_search(h, d_workspace, Y, loads, &mt, st, &h->ev, nullptr, nullptr, nullptr, nullptr, true);
+        enqueue_search(h, d_workspace, Y, loads, &mt, st, &h->ev, nullptr, nullptr, nullptr, nullptr);
         const hipError_t e1 = hipGetLastError(), e2 = hipStreamSynchronize(st);
         if (e1 != hipSuccess || e2 != hipSuccess) {
           h->sg_force = h->mpl_force = 0;
           OKR_FAIL(h, OKR_E_HIP, "autotune run failed: %s", hipGetErrorString(e1 != hipSuccess ? e1 : e2));
         }
-        for (int g = 0; g < nseg; ++g) {
-          const int k = h->seg_off[g + 1] - h->seg_off[g];
+        for (int cc = 0; cc < (int)h->chunk_k.size(); ++cc) {
+          const int k = h->chunk_k[cc];
           int spg;
           const int used = snap_groups(h, k, &spg);
           float ms = 0.f;
-          const hipError_t ee = hipEventElapsedTime(&ms, h->ev[2 * g], h->ev[2 * g + 1]);
+          const hipError_t ee = hipEventElapsedTime(&ms, h->ev[2 * cc], h->ev[2 * cc + 1]);
           if (ee != hipSuccess) {
             h->sg_force = h->mpl_force = 0;
             OKR_FAIL(h, OKR_E_HIP, "autotune timing failed: %s", hipGetErrorString(ee));
@@ -1062,7 +1071,7 @@ extern "C" int okr_reduce_feeder(okr_handle* h, const okr_yblocks* Y, const okr_
       OKR_HIP(h, hipStreamSynchronize(st));
       OKR_HIP(h, hipStreamBeginCapture(st, hipStreamCaptureModeThreadLocal));
       // one stream inside the capture (segments in order)
-      enqueue_search(h, d_workspace, Y, loads, mg, st, nullptr, nullptr, nullptr, nullptr, nullptr, false);
+      enqueue_search(h, d_workspace, Y, loads, mg, st, nullptr, nullptr, nullptr, nullptr, nullptr);
       hipGraph_t gobj = nullptr;
       const hipError_t ec = hipStreamEndCapture(st, &gobj);
       if (ec != hipSuccess) OKR_FAIL(h, OKR_E_HIP, "graph capture failed: %s", hipGetErrorString(ec));
@@ -1077,7 +1086,7 @@ extern "C" int okr_reduce_feeder(okr_handle* h, const okr_yblocks* Y, const okr_
     OKR_HIP(h, hipGraphLaunch(h->gexec, st));
   } else {
     enqueue_search(h, d_workspace, Y, loads, mg, st, timing ? &h->ev : nullptr, dump ? &h->dump : nullptr,
-                   dump ? &h->dump32 : nullptr, out->features, out->targets, true);
+                   dump ? &h->dump32 : nullptr, out->features, out->targets);
     OKR_HIP(h, hipGetLastError());
   }
   // results (one synchronisation)
@@ -1119,7 +1128,17 @@ extern "C" int okr_reduce_feeder(okr_handle* h, const okr_yblocks* Y, const okr_
   out->warnings = base_out ? OKR_W_BASE_OUT_OF_BAND : 0;
   out->score_kernel_ms = 0.0;
   out->algorithmic_flops = 0.0;
-  out->n_score_launches = nseg;
+  const int nchunk = (int)h->chunk_k.size();
+  out->n_score_launches = nchunk;
+  std::vector<int> chunk_of(std::max(nseg, 1), 0);
+  for (int c = 0; c < nchunk; ++c)
+    for (int i = h->chunk_off[c]; i < h->chunk_off[c + 1]; ++i) chunk_of[h->chunk_segs[i]] = c;
+  std::vector<float> chunk_ms(std::max(nchunk, 1), 0.f);
+  if (timing)
+    for (int c = 0; c < nchunk; ++c) {
+      OKR_HIP(h, hipEventElapsedTime(&chunk_ms[c], h->ev[2 * c], h->ev[2 * c + 1]));
+      out->score_kernel_ms += chunk_ms[c];
+    }
   for (int g = 0; g < nseg; ++g) {
     okr_segment_result& R = out->seg[g];
     std::memset(&R, 0, sizeof R);
@@ -1133,9 +1152,12 @@ extern "C" int okr_reduce_feeder(okr_handle* h, const okr_yblocks* Y, const okr_
     R.ambiguous = decs[g].ambiguous;
     R.n_scored = 1 << k;
     {
+      // launch shape of the segment's chunk (set by its largest segment)
+      const int kc = h->chunk_k[chunk_of[g]];
       int spg;
-      R.score_groups = snap_groups(h, k, &spg);
-      R.score_mpl = score_mpl(h, k);
+      R.score_groups = snap_groups(h, kc, &spg);
+      R.score_mpl = score_mpl(h, kc);
+      R.chunk = chunk_of[g];
     }
     // algorithmic FP64 flops: per slot and mask, reduced -> 6 + 4|phi|,
     // kept -> 14|phi| (half the masks each); per zone entry 14
@@ -1156,11 +1178,9 @@ extern "C" int okr_reduce_feeder(okr_handle* h, const okr_yblocks* Y, const okr_
       R.n_refined = std::min(mg->top_k, 1 << k);
       R.n_scored = R.n_refined + (gates[g] ? (1 << k) : 0);
     }
-    if (timing) {
-      float ms = 0.f;
-      OKR_HIP(h, hipEventElapsedTime(&ms, h->ev[2 * g], h->ev[2 * g + 1]));
-      R.score_ms = ms;
-      out->score_kernel_ms += ms;
+    if (timing) {  // the chunk's scoring time, split evenly over its segments
+      const int c = chunk_of[g];
+      R.score_ms = chunk_ms[c] / (float)(h->chunk_off[c + 1] - h->chunk_off[c]);
     }
   }
   int nk = 0;

@@ -34,6 +34,15 @@ struct SegHdr {
   int npat;       // chain patterns: sum over chains of 2^popcount(C_PMASK)
 };
 
+// A search step launched over a chunk of mutually independent segments:
+// blockIdx.z picks the segment (segs[blockIdx.z]) and its scratch block; each
+// per-segment scratch buffer of chunk position z lies z * lstride bytes after
+// position 0's.
+template <typename T>
+__device__ __forceinline__ T* lane_ptr(T* p, size_t lstride) {
+  return p ? (T*)((char*)p + (size_t)blockIdx.z * lstride) : p;
+}
+
 // Static topology on the device.
 struct Topo {
   int n;

@@ -239,17 +239,21 @@ __global__ void k_from_vhat(int n, int S, const uint8_t* __restrict__ phase, con
 // Ambiguous when a mask at the chosen level or above lies within amb of the
 // e_bar / band boundary, or a feasible mask at the chosen level lies within
 // amb of e_min + tie_tol.
-__global__ __launch_bounds__(1024) void k_argmin(const SegHdr* __restrict__ hdrs, int g,
-                                                 const MaskScore* __restrict__ fin, const TileRec* __restrict__ tiles,
-                                                 SelParams sp, const int* __restrict__ status,
-                                                 DevDecision* __restrict__ decs, const int* __restrict__ gate) {
+__global__ __launch_bounds__(1024) void k_argmin(const SegHdr* __restrict__ hdrs, const int* __restrict__ segs,
+                                                 size_t lstride, const MaskScore* __restrict__ fin,
+                                                 const TileRec* __restrict__ tiles, SelParams sp,
+                                                 const int* __restrict__ status, DevDecision* __restrict__ decs,
+                                                 const int* __restrict__ gates) {
   __shared__ double shd[16];
   __shared__ int shi[16];
   __shared__ unsigned shu[16];
   __shared__ int ncand;
   __shared__ int cand[1024];
+  const int g = segs[blockIdx.z];
   const SegHdr H = hdrs[g];
-  if (gate && *gate == 0) return;  // decided without the full enumeration
+  if (gates && gates[g] == 0) return;  // decided without the full enumeration
+  fin = lane_ptr(fin, lstride);
+  tiles = lane_ptr(tiles, lstride);
   DevDecision* dec = decs + g;
   // nothing is reduced when the full network violates the band, the load
   // flow failed, or the segment's tables are inconsistent
@@ -323,14 +327,20 @@ __global__ void k_sqrt_selftest(const double* __restrict__ x, double* __restrict
 // targets take their candidate voltages (same arithmetic as the scoring).
 // Block 0 then updates the kept flags and super-nodes over Omega_g and clears
 // the node -> slot / zone-entry maps for the next segment.
-__global__ __launch_bounds__(64) void k_apply(const SegHdr* __restrict__ hdrs, int g, const int* __restrict__ tab,
+__global__ __launch_bounds__(64) void k_apply(const SegHdr* __restrict__ hdrs, const int* __restrict__ segs,
+                                              size_t lstride, const int* __restrict__ tab,
                                               Topo T, State St, const DevDecision* __restrict__ decs,
                                               const double2* __restrict__ P, const TargetRec* __restrict__ srec,
                                               const TargetRec* __restrict__ zrec, double2* __restrict__ Vcur,
                                               double2* __restrict__ A) {
   __shared__ double2 Bs[kMaxK * 3];
+  const int g = segs[blockIdx.z];
   const SegHdr H = hdrs[g];
   if (!H.valid) return;
+  tab = lane_ptr(tab, lstride);
+  P = lane_ptr(P, lstride);
+  srec = lane_ptr(srec, lstride);
+  zrec = lane_ptr(zrec, lstride);
   const int n = T.n;
   const int l = blockIdx.x;
   const uint32_t m = decs[g].mask;

@@ -47,11 +47,11 @@ __device__ __forceinline__ void tile_record(const MaskScore& r, uint32_t m, bool
 // into the final per-mask score and writes the 64-mask tile records.
 template <int M>
 __global__ __launch_bounds__(kScoreThreads) void k_score_fp64(
-    const SegHdr* __restrict__ hdrs, int g, const int* __restrict__ tab, const double2* __restrict__ P,
-    const TargetRec* __restrict__ srec, const double2* __restrict__ headV,
+    const SegHdr* __restrict__ hdrs, const int* __restrict__ segs, size_t lstride, const int* __restrict__ tab,
+    const double2* __restrict__ P, const TargetRec* __restrict__ srec, const double2* __restrict__ headV,
     const TargetRec* __restrict__ zrec, const double* __restrict__ econst, int snaps_per_group, int SG,
     SelParams sp, MaskScore* __restrict__ part, MaskScore* __restrict__ fin, TileRec* __restrict__ tiles,
-    int* __restrict__ tickets, const int* __restrict__ gate) {
+    int* __restrict__ tickets, const int* __restrict__ gates) {
   __shared__ double2 Ps[kMaxPairs * 3];
   __shared__ TargetRec Ts[kMaxK * 3];
   __shared__ double2 Hv[kMaxK * 3];
@@ -59,8 +59,21 @@ __global__ __launch_bounds__(kScoreThreads) void k_score_fp64(
   __shared__ TargetRec Zs[kZoneLds];
   __shared__ double s_ec;
   __shared__ int ticket;
+  const int g = segs[blockIdx.z];
   const SegHdr H = hdrs[g];
-  if (!H.valid || (gate && *gate == 0)) return;
+  if (!H.valid || (gates && gates[g] == 0)) return;
+  // blocks past this segment's masks (a chunk's launch covers its largest segment)
+  if ((uint64_t)blockIdx.x * (kScoreThreads * M) >= ((uint64_t)1 << H.k)) return;
+  tab = lane_ptr(tab, lstride);
+  P = lane_ptr(P, lstride);
+  srec = lane_ptr(srec, lstride);
+  headV = lane_ptr(headV, lstride);
+  zrec = lane_ptr(zrec, lstride);
+  econst = lane_ptr(econst, lstride);
+  part = lane_ptr(part, lstride);
+  fin = lane_ptr(fin, lstride);
+  tiles = lane_ptr(tiles, lstride);
+  tickets = lane_ptr(tickets, lstride);
   const int tid = threadIdx.x;
   uint32_t m[M];
 #pragma unroll
@@ -130,15 +143,15 @@ __global__ __launch_bounds__(kScoreThreads) void k_score_fp64(
   if (tid == 0) tickets[blockIdx.x] = 0;  // ready for the next launch
 }
 
-template __global__ void k_score_fp64<1>(const SegHdr*, int, const int*, const double2*, const TargetRec*,
-                                         const double2*, const TargetRec*, const double*, int, int, SelParams,
-                                         MaskScore*, MaskScore*, TileRec*, int*, const int*);
-template __global__ void k_score_fp64<2>(const SegHdr*, int, const int*, const double2*, const TargetRec*,
-                                         const double2*, const TargetRec*, const double*, int, int, SelParams,
-                                         MaskScore*, MaskScore*, TileRec*, int*, const int*);
-template __global__ void k_score_fp64<4>(const SegHdr*, int, const int*, const double2*, const TargetRec*,
-                                         const double2*, const TargetRec*, const double*, int, int, SelParams,
-                                         MaskScore*, MaskScore*, TileRec*, int*, const int*);
+template __global__ void k_score_fp64<1>(const SegHdr*, const int*, size_t, const int*, const double2*,
+                                         const TargetRec*, const double2*, const TargetRec*, const double*, int,
+                                         int, SelParams, MaskScore*, MaskScore*, TileRec*, int*, const int*);
+template __global__ void k_score_fp64<2>(const SegHdr*, const int*, size_t, const int*, const double2*,
+                                         const TargetRec*, const double2*, const TargetRec*, const double*, int,
+                                         int, SelParams, MaskScore*, MaskScore*, TileRec*, int*, const int*);
+template __global__ void k_score_fp64<4>(const SegHdr*, const int*, size_t, const int*, const double2*,
+                                         const TargetRec*, const double2*, const TargetRec*, const double*, int,
+                                         int, SelParams, MaskScore*, MaskScore*, TileRec*, int*, const int*);
 
 // FP64 scores of the masks in `list` (all snapshots), with the arithmetic of
 // the FP64 scoring kernel: one wave per mask, its lanes over the snapshots
@@ -198,15 +211,24 @@ constexpr int kPatLds = 1024;  // pattern-table entries staged in LDS by the com
 // The pattern table: one wave per pattern, lanes over snapshots, the chain's
 // per-snapshot arithmetic of the FP64 scoring kernel, a wave reduction.  Wave 0
 // also stores the largest constant error over the snapshots.
-__global__ __launch_bounds__(256) void k_fac_tables(const SegHdr* __restrict__ hdrs, int g,
-                                                    const int* __restrict__ tab, const double2* __restrict__ P,
+__global__ __launch_bounds__(256) void k_fac_tables(const SegHdr* __restrict__ hdrs, const int* __restrict__ segs,
+                                                    size_t lstride, const int* __restrict__ tab,
+                                                    const double2* __restrict__ P,
                                                     const TargetRec* __restrict__ srec,
                                                     const double2* __restrict__ headV,
                                                     const TargetRec* __restrict__ zrec,
                                                     const double* __restrict__ econst, PatScore* __restrict__ pat,
                                                     double* __restrict__ ecmax) {
-  const SegHdr H = hdrs[g];
+  const SegHdr H = hdrs[segs[blockIdx.z]];
   if (!H.valid) return;
+  tab = lane_ptr(tab, lstride);
+  P = lane_ptr(P, lstride);
+  srec = lane_ptr(srec, lstride);
+  headV = lane_ptr(headV, lstride);
+  zrec = lane_ptr(zrec, lstride);
+  econst = lane_ptr(econst, lstride);
+  pat = lane_ptr(pat, lstride);
+  ecmax = lane_ptr(ecmax, lstride);
   const int lane = threadIdx.x & 63;
   const int wave = blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6);
   const int nwaves = gridDim.x * (blockDim.x >> 6);
@@ -255,14 +277,21 @@ __global__ __launch_bounds__(256) void k_fac_tables(const SegHdr* __restrict__ h
 // largest constant error and each chain's entry for the mask's bits, then
 // the band slack; per-mask scores and 64-mask tile records as the FP64
 // scoring kernel writes them.
-__global__ __launch_bounds__(256) void k_fac_combine(const SegHdr* __restrict__ hdrs, int g,
-                                                     const int* __restrict__ tab, const PatScore* __restrict__ pat,
+__global__ __launch_bounds__(256) void k_fac_combine(const SegHdr* __restrict__ hdrs, const int* __restrict__ segs,
+                                                     size_t lstride, const int* __restrict__ tab,
+                                                     const PatScore* __restrict__ pat,
                                                      const double* __restrict__ ecmax, SelParams sp,
                                                      MaskScore* __restrict__ fin, TileRec* __restrict__ tiles) {
   __shared__ int s_pm[kMaxK], s_pb[kMaxK];
   __shared__ PatScore s_pat[kPatLds];
-  const SegHdr H = hdrs[g];
+  const SegHdr H = hdrs[segs[blockIdx.z]];
   if (!H.valid) return;
+  if ((uint64_t)blockIdx.x * blockDim.x >= ((uint64_t)1 << H.k)) return;  // past this segment's masks
+  tab = lane_ptr(tab, lstride);
+  pat = lane_ptr(pat, lstride);
+  ecmax = lane_ptr(ecmax, lstride);
+  fin = lane_ptr(fin, lstride);
+  tiles = lane_ptr(tiles, lstride);
   const int tid = threadIdx.x;
   const int nch = H.nchains;
   if (tid < nch) {

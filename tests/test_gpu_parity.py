@@ -302,14 +302,17 @@ def test_autotuned_launch_shape_gives_identical_results(okr):
         R.close()
 
 
-@pytest.mark.parametrize("cfg,lanes", [("c2", 4), ("c3", 8)])
-def test_concurrent_lanes_give_identical_results(okr, cfg, lanes):
-    """Independent segments searched concurrently (lanes > 1) give bit-identical
-    decisions, per-segment errors and outputs to the in-order search."""
-    _say(f"lanes {cfg} seed 3 lanes={lanes}")
+@pytest.mark.parametrize("cfg,lanes,precision,graph", [("c2", 4, "fp64", False), ("c3", 8, "fp64", True),
+                                                       ("c3", 8, "mixed", False), ("c2", 8, "mixed", True)])
+def test_concurrent_lanes_give_identical_results(okr, cfg, lanes, precision, graph):
+    """Independent segments searched together (chunks of up to `lanes`
+    segments per launch, level by level) give bit-identical decisions,
+    per-segment errors and outputs to one segment per launch, in stream
+    launches and in the captured graph."""
+    _say(f"lanes {cfg} seed 3 lanes={lanes} {precision} graph={graph}")
     f = make_feeder(cfg, 3)
-    ref = okr.reduce_feeder(f, lanes=1, want_vhat=False)
-    out = okr.reduce_feeder(f, lanes=lanes, want_vhat=False)
+    ref = okr.reduce_feeder(f, lanes=1, precision=precision, want_vhat=False)
+    out = okr.reduce_feeder(f, lanes=lanes, precision=precision, graph=graph, want_vhat=False)
     assert [s["mask"] for s in out["segments"]] == [s["mask"] for s in ref["segments"]]
     assert [s["e_loc"] for s in out["segments"]] == [s["e_loc"] for s in ref["segments"]]
     np.testing.assert_array_equal(out["err_per_snapshot"], ref["err_per_snapshot"])
