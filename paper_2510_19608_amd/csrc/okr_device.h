@@ -144,6 +144,129 @@ __device__ __forceinline__ void walk_chain(const int* __restrict__ cr, const dou
     for (int p = 0; p < 3; ++p) B[i][p] = S[i][p];
 }
 
+// Snapshot-vectorised chain walk: one mask, M snapshots at once, with the
+// per-snapshot arithmetic of walk_chain.  The mask-dependent control (reduced
+// or kept, current super) is shared by the M snapshots, so each side of the
+// branch carries M independent chains, and on mask bits above the lane bits
+// a whole wave takes one side.  el, qmin and qmax are folded over the M
+// snapshots (max and min are exact).  LDS layout, snapshot fastest:
+// P[(pair * 3 + p) * M + j], T[(slot * 3 + p) * M + j], H and Hm
+// [(chain * 3 + p) * M + j].
+template <bool ERR, int M>
+__device__ __forceinline__ void walk_chain_sv(const int* __restrict__ cr, const double2* Ps, const TargetRec* Ts,
+                                              const double2* Hs, const double* Hm, int c, uint32_t m,
+                                              double2 (&B)[M][3], double& el, double& qmin, double& qmax) {
+  double2 S[M][3];
+  double sm[M][3];
+#pragma unroll
+  for (int j = 0; j < M; ++j)
+#pragma unroll
+    for (int p = 0; p < 3; ++p) {
+      S[j][p] = B[j][p];
+      sm[j][p] = 0.0;
+    }
+  if (ERR) {
+    const int hph = cr[C_PHASE];
+    if (cr[C_OUTER] < 0) {  // head unaffected by the mask: staged magnitude (0 on absent phases)
+#pragma unroll
+      for (int p = 0; p < 3; ++p)
+#pragma unroll
+        for (int j = 0; j < M; ++j) sm[j][p] = Hm[(c * 3 + p) * M + j];
+    } else {
+#pragma unroll
+      for (int p = 0; p < 3; ++p)
+        if (hph >> p & 1)
+#pragma unroll
+          for (int j = 0; j < M; ++j) sm[j][p] = vmag(cadd(Hs[(c * 3 + p) * M + j], B[j][p]));
+    }
+  }
+  const int ns = cr[C_NSLOT], s0 = cr[C_SLOT0], pair0 = cr[C_PAIR0], bit0 = cr[C_BIT0];
+  const int phw0 = cr[C_PHW0], phw1 = cr[C_PHW1], phw2 = cr[C_PHW2];
+  int sidx = 0;
+  for (int r = 0; r < ns; ++r) {
+    const int w = r < 8 ? phw0 : (r < 16 ? phw1 : phw2);
+    const int ph = (w >> (3 * (r & 7))) & 7;
+    const int prow = pair0 + ((r * (r + 1)) >> 1);
+    const TargetRec* tr = Ts + (s0 + r) * 3 * M;
+    if ((m >> (bit0 + r)) & 1u) {  // reduced: the moved current's rise; cluster error against the super
+      const double2* pr = Ps + (prow + sidx) * 3 * M;
+#pragma unroll
+      for (int p = 0; p < 3; ++p) {
+        if (!(ph >> p & 1)) continue;
+#pragma unroll
+        for (int j = 0; j < M; ++j) {
+          const double2 pv = pr[p * M + j];
+          S[j][p].x += pv.x;
+          S[j][p].y += pv.y;
+          if (ERR) {
+            const TargetRec t = tr[p * M + j];
+            el = fmax(el, fmax(sm[j][p] - t.lo, t.hi - sm[j][p]));
+          }
+        }
+      }
+    } else {  // kept: a new super
+      if (ERR) {
+#pragma unroll
+        for (int p = 0; p < 3; ++p) {
+          if (!(ph >> p & 1)) continue;
+#pragma unroll
+          for (int j = 0; j < M; ++j) {
+            const TargetRec t = tr[p * M + j];
+            const double vx = t.W.x + S[j][p].x, vy = t.W.y + S[j][p].y;
+            const double q = fma(vx, vx, vy * vy);
+            sm[j][p] = sqrt_nr(q);
+            qmin = fmin(qmin, q);
+            qmax = fmax(qmax, q);
+            el = fmax(el, fmax(sm[j][p] - t.lo, t.hi - sm[j][p]));
+          }
+        }
+      }
+      sidx = r + 1;
+    }
+  }
+#pragma unroll
+  for (int j = 0; j < M; ++j)
+#pragma unroll
+    for (int p = 0; p < 3; ++p) B[j][p] = S[j][p];
+}
+
+// Terms of chain c for one mask over M snapshots (snapshot-vectorised
+// score_chain): the nesting path, the chain, then its zone entries (the first
+// zcap from the LDS stage Zs[q * M + j], the rest from global memory, where
+// snapshot j's records start at zg[j]).
+template <int M>
+__device__ __forceinline__ void score_chain_sv(const int* __restrict__ chains, const int* __restrict__ nest, int c,
+                                               const double2* Ps, const TargetRec* Ts, const double2* Hs,
+                                               const double* Hm, const TargetRec* Zs, int zcap,
+                                               const TargetRec* const (&zg)[M], uint32_t m, double& el,
+                                               double& qmin, double& qmax) {
+  const int* cr = chains + c * kChainInts;
+  double2 B[M][3];
+#pragma unroll
+  for (int j = 0; j < M; ++j)
+#pragma unroll
+    for (int p = 0; p < 3; ++p) B[j][p] = make_double2(0.0, 0.0);
+  const int nl = cr[C_NEST_LEN], no = cr[C_NEST_OFF];
+  for (int q = 0; q + 1 < nl; ++q) {
+    const int oc = nest[no + q];
+    walk_chain_sv<false, M>(chains + oc * kChainInts, Ps, Ts, Hs, Hm, oc, m, B, el, qmin, qmax);
+  }
+  walk_chain_sv<true, M>(cr, Ps, Ts, Hs, Hm, c, m, B, el, qmin, qmax);
+#pragma unroll
+  for (int p = 0; p < 3; ++p)
+    for (int q = cr[C_ZOFF0 + p], qe = q + cr[C_ZCNT0 + p]; q < qe; ++q)
+#pragma unroll
+      for (int j = 0; j < M; ++j) {
+        const TargetRec t = q < zcap ? Zs[q * M + j] : zg[j][q];
+        const double vx = t.W.x + B[j][p].x, vy = t.W.y + B[j][p].y;
+        const double q2 = fma(vx, vx, vy * vy);
+        const double mag = sqrt_nr(q2);
+        el = fmax(el, fmax(mag - t.lo, t.hi - mag));
+        qmin = fmin(qmin, q2);
+        qmax = fmax(qmax, q2);
+      }
+}
+
 // Band slack of a mask from the extreme squared magnitudes of its kept
 // node-phases: min(|V| - vmin, vmax - |V|) over them (+inf if there are none).
 __device__ __forceinline__ double band_slack(double qmin, double qmax, double vmin, double vmax) {

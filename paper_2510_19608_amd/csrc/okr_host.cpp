@@ -32,8 +32,8 @@ __global__ void k_build_members(const SegHdr*, const int*, size_t, const int*, T
                                 const double*, TargetRec*, TargetRec*, double*);
 template <int M>
 __global__ void k_score_fp64(const SegHdr*, const int*, size_t, const int*, const double2*, const TargetRec*,
-                             const double2*, const TargetRec*, const double*, int, int, SelParams, MaskScore*,
-                             MaskScore*, TileRec*, int*, const int*);
+                           const double2*, const TargetRec*, const double*, int, int, int, int, int, SelParams,
+                           MaskScore*, MaskScore*, TileRec*, int*, const int*);
 __global__ void k_fac_tables(const SegHdr*, const int*, size_t, const int*, const double2*, const TargetRec*,
                              const double2*, const TargetRec*, const double*, PatScore*, double*);
 __global__ void k_fac_combine(const SegHdr*, const int*, size_t, const int*, const PatScore*, const double*, SelParams,
@@ -179,16 +179,34 @@ namespace {
 int score_mpl(const okr_handle* h, int k) {
   if (h->mpl_force) return h->mpl_force;
   if ((int)h->mpl_tuned.size() > k && h->mpl_tuned[k]) return h->mpl_tuned[k];
-  return k >= 12 ? 4 : (k >= 10 ? 2 : 1);
+  return 4;
 }
 
 // Snapshot groups of the FP64 scoring launch for a segment of k nodes: the
 // forced or tuned count, else the default rule, within the planned
 // partial-score capacity; spg = snapshots per group.
+// LDS of the snapshot-vectorised FP64 scoring kernel: spp snapshots of
+// pairs, slot records, chain heads and their magnitudes, the first kSvZone
+// zone records, and the constant errors.
+constexpr int kSvZone = 128;
+constexpr size_t kSvLdsMax = 60 * 1024;
+size_t sv_lds_bytes(int spp, int k) {
+  const size_t pcap = (size_t)k * (k + 1) / 2;
+  return (size_t)spp * (pcap * 3 * sizeof(double2) + (size_t)k * 3 * (sizeof(TargetRec) + sizeof(double2) + sizeof(double)) +
+                        kSvZone * sizeof(TargetRec) + sizeof(double));
+}
+// Snapshots per pass: the wanted count (1, 2 or 4), at most the group's
+// snapshots, within the LDS budget.
+int sv_spp(int want, int k, int spg) {
+  int spp = want >= 4 ? 4 : (want >= 2 ? 2 : 1);
+  while (spp > 1 && (spp > spg || sv_lds_bytes(spp, k) > kSvLdsMax)) spp /= 2;
+  return spp;
+}
+
 int snap_groups(const okr_handle* h, int k, int* spg) {
   const int S = h->S;
   int SG = h->sg_force ? h->sg_force : ((int)h->sg_tuned.size() > k && h->sg_tuned[k] ? h->sg_tuned[k] : 0);
-  if (SG <= 0) SG = snap_groups_default(k, S, spg, score_mpl(h, k));
+  if (SG <= 0) SG = snap_groups_default(k, S, spg);
   SG = std::min(std::min(SG, S), kMaxSnapGroups);
   while (SG > 1 && ((size_t)SG << k) > h->part_cap) --SG;
   *spg = (S + SG - 1) / SG;
@@ -760,10 +778,13 @@ void enqueue_search(okr_handle* h, void* ws, const okr_yblocks* Y, const okr_loa
                        lstride, (const int*)q.tab, q.T, q.St, (const double2*)q.Vcur, (const double*)q.absV, q.srec,
                        q.zrec, q.econst);
     const uint32_t nmask = 1u << kc;
-    const int mpl = score_mpl(h, kc);
-    const int mblocks = (int)((nmask + kScoreThreads * mpl - 1) / (kScoreThreads * mpl));
     int spg;
     const int SG = snap_groups(h, kc, &spg);
+    // per-mask FP64 launch: one mask per lane, spp snapshots per pass, LDS for spp snapshots
+    const int mblocks = (int)((nmask + kScoreThreads - 1) / kScoreThreads);
+    const int pcap = kc * (kc + 1) / 2;
+    const int spp = sv_spp(score_mpl(h, kc), kc, spg);
+    const size_t lds = sv_lds_bytes(spp, kc);
     const int* gates = surr ? q.sgates : nullptr;
     for (int z = 0; z < nz; ++z) {
       const int g = h->chunk_segs[c0 + z];
@@ -851,12 +872,12 @@ void enqueue_search(okr_handle* h, void* ws, const okr_yblocks* Y, const okr_loa
                            q.tiles);
       } else {
 #define OKR_SCORE64(M_)                                                                                             \
-  hipLaunchKernelGGL(k_score_fp64<M_>, dim3(mblocks, SG, nz), dim3(kScoreThreads), 0, st, (const SegHdr*)q.hdrs, segs, \
+  hipLaunchKernelGGL(k_score_fp64<M_>, dim3(mblocks, SG, nz), dim3(kScoreThreads), lds, st, (const SegHdr*)q.hdrs, segs, \
                      lstride, (const int*)q.tab, (const double2*)q.P, (const TargetRec*)q.srec,                      \
-                     (const double2*)q.headV, (const TargetRec*)q.zrec, (const double*)q.econst, spg, SG, sp, q.part, \
-                     q.fin, q.tiles, q.tickets, gates)
-        if (mpl == 4) OKR_SCORE64(4);
-        else if (mpl == 2) OKR_SCORE64(2);
+                     (const double2*)q.headV, (const TargetRec*)q.zrec, (const double*)q.econst, spg, SG, pcap, kc,   \
+                     kSvZone, sp, q.part, q.fin, q.tiles, q.tickets, gates)
+        if (spp == 4) OKR_SCORE64(4);
+        else if (spp == 2) OKR_SCORE64(2);
         else OKR_SCORE64(1);
 #undef OKR_SCORE64
       }
@@ -1156,7 +1177,7 @@ extern "C" int okr_reduce_feeder(okr_handle* h, const okr_yblocks* Y, const okr_
       const int kc = h->chunk_k[chunk_of[g]];
       int spg;
       R.score_groups = snap_groups(h, kc, &spg);
-      R.score_mpl = score_mpl(h, kc);
+      R.score_mpl = sv_spp(score_mpl(h, kc), kc, spg);
       R.chunk = chunk_of[g];
     }
     // algorithmic FP64 flops: per slot and mask, reduced -> 6 + 4|phi|,

@@ -37,33 +37,29 @@ __device__ __forceinline__ void tile_record(const MaskScore& r, uint32_t m, bool
   }
 }
 
-// Every mask of a segment over the block's snapshot group: e = max error over
-// the affected nodes, slack = min band slack over their kept node-phases.  A
-// block is 4 waves; a lane holds M masks (mask i of the lane is
-// blockIdx.x * 256M + 256 i + tid, so each wave covers 64 consecutive masks
-// per i) and the 4 waves share the snapshot's LDS stage (pair table, slot
-// targets, chain heads and their magnitudes, zone targets).  The last block
-// of a 256M-mask range to finish (ticket counter) folds the snapshot groups
-// into the final per-mask score and writes the 64-mask tile records.
+// Per-mask FP64 scoring, snapshot-vectorised: one mask per lane (a block is
+// 4 waves, 256 consecutive masks), the block's snapshot group in passes of M
+// snapshots staged together in LDS (snapshot fastest), every chain's terms
+// for the M snapshots at once (score_chain_sv).  A pass past the group's
+// last snapshot repeats it (max / min unchanged).  The last block of a mask
+// range to finish (ticket counter) folds the snapshot groups into the final
+// per-mask score and writes the 64-mask tile records.  Dynamic LDS per
+// snapshot: pcap pairs, kcap slots and chains, zcap zone records (later
+// zone records are read from global memory).
 template <int M>
 __global__ __launch_bounds__(kScoreThreads) void k_score_fp64(
     const SegHdr* __restrict__ hdrs, const int* __restrict__ segs, size_t lstride, const int* __restrict__ tab,
     const double2* __restrict__ P, const TargetRec* __restrict__ srec, const double2* __restrict__ headV,
-    const TargetRec* __restrict__ zrec, const double* __restrict__ econst, int snaps_per_group, int SG,
-    SelParams sp, MaskScore* __restrict__ part, MaskScore* __restrict__ fin, TileRec* __restrict__ tiles,
-    int* __restrict__ tickets, const int* __restrict__ gates) {
-  __shared__ double2 Ps[kMaxPairs * 3];
-  __shared__ TargetRec Ts[kMaxK * 3];
-  __shared__ double2 Hv[kMaxK * 3];
-  __shared__ double Hm[kMaxK * 3];
-  __shared__ TargetRec Zs[kZoneLds];
-  __shared__ double s_ec;
+    const TargetRec* __restrict__ zrec, const double* __restrict__ econst, int snaps_per_group, int SG, int pcap,
+    int kcap, int zcap, SelParams sp, MaskScore* __restrict__ part, MaskScore* __restrict__ fin,
+    TileRec* __restrict__ tiles, int* __restrict__ tickets, const int* __restrict__ gates) {
+  extern __shared__ __align__(16) unsigned char sv_lds[];
   __shared__ int ticket;
   const int g = segs[blockIdx.z];
   const SegHdr H = hdrs[g];
   if (!H.valid || (gates && gates[g] == 0)) return;
   // blocks past this segment's masks (a chunk's launch covers its largest segment)
-  if ((uint64_t)blockIdx.x * (kScoreThreads * M) >= ((uint64_t)1 << H.k)) return;
+  if ((uint64_t)blockIdx.x * kScoreThreads >= ((uint64_t)1 << H.k)) return;
   tab = lane_ptr(tab, lstride);
   P = lane_ptr(P, lstride);
   srec = lane_ptr(srec, lstride);
@@ -74,84 +70,97 @@ __global__ __launch_bounds__(kScoreThreads) void k_score_fp64(
   fin = lane_ptr(fin, lstride);
   tiles = lane_ptr(tiles, lstride);
   tickets = lane_ptr(tickets, lstride);
+  double2* Ps = (double2*)sv_lds;
+  TargetRec* Ts = (TargetRec*)(Ps + (size_t)pcap * 3 * M);
+  double2* Hv = (double2*)(Ts + (size_t)kcap * 3 * M);
+  TargetRec* Zs = (TargetRec*)(Hv + (size_t)kcap * 3 * M);
+  double* Hm = (double*)(Zs + (size_t)zcap * M);
+  double* Ec = Hm + (size_t)kcap * 3 * M;
   const int tid = threadIdx.x;
-  uint32_t m[M];
-#pragma unroll
-  for (int i = 0; i < M; ++i) m[i] = blockIdx.x * (kScoreThreads * M) + i * kScoreThreads + tid;
+  const uint32_t m = blockIdx.x * kScoreThreads + tid;
   const int sg = blockIdx.y;
   const int l0 = sg * snaps_per_group;
   const int l1 = min(H.S, l0 + snaps_per_group);
   const int* chains = tab + H.o_chain;
   const int* nest = tab + H.o_nest;
-  const Stage z = stage_sizes(H);
-  double e[M], qmin[M], qmax[M];
-#pragma unroll
-  for (int i = 0; i < M; ++i) {
-    e[i] = 0.0;
-    qmin[i] = INFINITY;
-    qmax[i] = -INFINITY;
-  }
-  for (int l = l0; l < l1; ++l) {
-    const uint4* P_l = (const uint4*)(P + (size_t)l * H.npairs * 3);
-    const uint4* S_l = (const uint4*)(srec + (size_t)l * H.nslots * 3);
-    const uint4* H_l = (const uint4*)(headV + (size_t)l * H.nchains * 3);
-    const uint4* Z_l = (const uint4*)(zrec + (size_t)l * H.nz);
-    for (int i = tid; i < z.total; i += kScoreThreads)
-      stage_put(z, i, stage_src(z, i, P_l, S_l, H_l, Z_l), (uint4*)Ps, (uint4*)Ts, (uint4*)Hv, Hm, (uint4*)Zs);
-    if (tid == 0) s_ec = econst[l];
+  const int zst = min(H.nz, zcap);
+  const int cP = H.npairs * 3, cT = H.nslots * 6, cH = H.nchains * 3, cZ = zst * 2;
+  const int tot = cP + cT + cH + cZ;
+  double e = 0.0, qmin = INFINITY, qmax = -INFINITY;
+  for (int l = l0; l < l1; l += M) {
+    for (int i = tid; i < M * tot; i += kScoreThreads) {
+      const int j = i / tot;
+      int r = i - j * tot;
+      const int lj = min(l + j, l1 - 1);
+      if (r < cP) {
+        ((uint4*)Ps)[r * M + j] = ((const uint4*)(P + (size_t)lj * H.npairs * 3))[r];
+        continue;
+      }
+      r -= cP;
+      if (r < cT) {
+        ((uint4*)Ts)[((r >> 1) * M + j) * 2 + (r & 1)] = ((const uint4*)(srec + (size_t)lj * H.nslots * 3))[r];
+        continue;
+      }
+      r -= cT;
+      if (r < cH) {
+        const uint4 v = ((const uint4*)(headV + (size_t)lj * H.nchains * 3))[r];
+        ((uint4*)Hv)[r * M + j] = v;
+        const double2 hv = make_double2(__hiloint2double((int)v.y, (int)v.x), __hiloint2double((int)v.w, (int)v.z));
+        Hm[r * M + j] = (hv.x != 0.0 || hv.y != 0.0) ? hmag(hv) : 0.0;
+        continue;
+      }
+      r -= cH;
+      ((uint4*)Zs)[((r >> 1) * M + j) * 2 + (r & 1)] = ((const uint4*)(zrec + (size_t)lj * H.nz))[r];
+    }
+    if (tid < M) Ec[tid] = econst[min(l + tid, l1 - 1)];
     __syncthreads();
-    double el[M];
-    const double ec = s_ec;
+    double el = Ec[0];
 #pragma unroll
-    for (int i = 0; i < M; ++i) el[i] = ec;
-    score_snapshot<true, M>(H, chains, nest, Ps, Ts, Hv, Hm, Zs, kZoneLds, zrec + (size_t)l * H.nz, m, el, qmin,
-                            qmax);
+    for (int j = 1; j < M; ++j) el = fmax(el, Ec[j]);
+    const TargetRec* zg[M];
 #pragma unroll
-    for (int i = 0; i < M; ++i) e[i] = fmax(e[i], el[i]);
+    for (int j = 0; j < M; ++j) zg[j] = zrec + (size_t)min(l + j, l1 - 1) * H.nz;
+    for (int c = 0; c < H.nchains; ++c)
+      score_chain_sv<M>(chains, nest, c, Ps, Ts, Hv, Hm, Zs, zst, zg, m, el, qmin, qmax);
+    e = fmax(e, el);
     __syncthreads();
   }
   const uint32_t nmask = 1u << H.k;
-#pragma unroll
-  for (int i = 0; i < M; ++i)
-    if (m[i] < nmask) {
-      MaskScore r;
-      r.e = e[i];
-      r.slack = band_slack(qmin[i], qmax[i], sp.vmin, sp.vmax);
-      part[(size_t)sg * nmask + m[i]] = r;
-    }
+  const bool valid = m < nmask;
+  if (valid) {
+    MaskScore r;
+    r.e = e;
+    r.slack = band_slack(qmin, qmax, sp.vmin, sp.vmax);
+    part[(size_t)sg * nmask + m] = r;
+  }
   __threadfence();
   if (tid == 0) ticket = atomicAdd(&tickets[blockIdx.x], 1);
   __syncthreads();
   if (ticket != SG - 1) return;
   // last block of this mask range: combine the snapshot groups
-#pragma unroll
-  for (int i = 0; i < M; ++i) {
-    const bool valid = m[i] < nmask;
-    MaskScore r;
-    r.e = 0.0;
-    r.slack = INFINITY;
-    if (valid) {
-      for (int q = 0; q < SG; ++q) {
-        const volatile MaskScore* x = part + (size_t)q * nmask + m[i];
-        r.e = fmax(r.e, x->e);
-        r.slack = fmin(r.slack, x->slack);
-      }
-      fin[m[i]] = r;
+  MaskScore r;
+  r.e = 0.0;
+  r.slack = INFINITY;
+  if (valid) {
+    for (int q = 0; q < SG; ++q) {
+      const volatile MaskScore* x = part + (size_t)q * nmask + m;
+      r.e = fmax(r.e, x->e);
+      r.slack = fmin(r.slack, x->slack);
     }
-    tile_record(r, m[i], valid, nmask, sp, tiles);
+    fin[m] = r;
   }
+  tile_record(r, m, valid, nmask, sp, tiles);
   if (tid == 0) tickets[blockIdx.x] = 0;  // ready for the next launch
 }
 
-template __global__ void k_score_fp64<1>(const SegHdr*, const int*, size_t, const int*, const double2*,
-                                         const TargetRec*, const double2*, const TargetRec*, const double*, int,
-                                         int, SelParams, MaskScore*, MaskScore*, TileRec*, int*, const int*);
-template __global__ void k_score_fp64<2>(const SegHdr*, const int*, size_t, const int*, const double2*,
-                                         const TargetRec*, const double2*, const TargetRec*, const double*, int,
-                                         int, SelParams, MaskScore*, MaskScore*, TileRec*, int*, const int*);
-template __global__ void k_score_fp64<4>(const SegHdr*, const int*, size_t, const int*, const double2*,
-                                         const TargetRec*, const double2*, const TargetRec*, const double*, int,
-                                         int, SelParams, MaskScore*, MaskScore*, TileRec*, int*, const int*);
+#define OKR_SCORE64_INST(M_)                                                                                               \
+  template __global__ void k_score_fp64<M_>(const SegHdr*, const int*, size_t, const int*, const double2*,              \
+                                          const TargetRec*, const double2*, const TargetRec*, const double*, int, int, \
+                                          int, int, int, SelParams, MaskScore*, MaskScore*, TileRec*, int*, const int*);
+OKR_SCORE64_INST(1)
+OKR_SCORE64_INST(2)
+OKR_SCORE64_INST(4)
+#undef OKR_SCORE64_INST
 
 // FP64 scores of the masks in `list` (all snapshots), with the arithmetic of
 // the FP64 scoring kernel: one wave per mask, its lanes over the snapshots
