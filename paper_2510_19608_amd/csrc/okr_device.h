@@ -42,7 +42,10 @@ __device__ __forceinline__ double sqrt_nr(double x) {
   d = fma(-g, g, x);
   return fma(d, h, g);
 }
-__device__ __forceinline__ double vmag(double2 a) { return sqrt_nr(a.x * a.x + a.y * a.y); }
+// |a|^2 in one fixed evaluation order (every magnitude of the scoring goes
+// through it, so all scoring forms round alike).
+__device__ __forceinline__ double mag2(double2 a) { return fma(a.x, a.x, a.y * a.y); }
+__device__ __forceinline__ double vmag(double2 a) { return sqrt_nr(mag2(a)); }
 // Magnitude of a chain head's voltage (mask-independent for chains that are
 // not nested below another chain), one fixed evaluation order.
 __device__ __forceinline__ double hmag(double2 a) { return sqrt_nr(fma(a.x, a.x, a.y * a.y)); }
@@ -144,18 +147,47 @@ __device__ __forceinline__ void walk_chain(const int* __restrict__ cr, const dou
     for (int p = 0; p < 3; ++p) B[i][p] = S[i][p];
 }
 
+// sqrt_nr of M independent values, step by step across them, so the M
+// dependency chains interleave (each result equals sqrt_nr of its input).
+template <int M>
+__device__ __forceinline__ void sqrt_nr_v(const double (&x)[M], double (&y)[M]) {
+  double g[M], h[M], e[M];
+#pragma unroll
+  for (int j = 0; j < M; ++j) {
+    const double r = __builtin_amdgcn_rsq(x[j]);
+    g[j] = x[j] * r;
+    h[j] = 0.5 * r;
+  }
+#pragma unroll
+  for (int j = 0; j < M; ++j) e[j] = fma(-h[j], g[j], 0.5);
+#pragma unroll
+  for (int j = 0; j < M; ++j) {
+    g[j] = fma(g[j], e[j], g[j]);
+    h[j] = fma(h[j], e[j], h[j]);
+  }
+#pragma unroll
+  for (int j = 0; j < M; ++j) e[j] = fma(-g[j], g[j], x[j]);
+#pragma unroll
+  for (int j = 0; j < M; ++j) g[j] = fma(e[j], h[j], g[j]);
+#pragma unroll
+  for (int j = 0; j < M; ++j) e[j] = fma(-g[j], g[j], x[j]);
+#pragma unroll
+  for (int j = 0; j < M; ++j) y[j] = fma(e[j], h[j], g[j]);
+}
+
 // Snapshot-vectorised chain walk: one mask, M snapshots at once, with the
 // per-snapshot arithmetic of walk_chain.  The mask-dependent control (reduced
 // or kept, current super) is shared by the M snapshots, so each side of the
-// branch carries M independent chains, and on mask bits above the lane bits
-// a whole wave takes one side.  el, qmin and qmax are folded over the M
-// snapshots (max and min are exact).  LDS layout, snapshot fastest:
-// P[(pair * 3 + p) * M + j], T[(slot * 3 + p) * M + j], H and Hm
-// [(chain * 3 + p) * M + j].
+// branch carries M independent chains, evaluated in lock-step, and on mask
+// bits above the lane bits a whole wave takes one side.  el, qmin and qmax
+// are per snapshot (folded later: max and min are exact).  LDS layout,
+// snapshot fastest: P[(pair * 3 + p) * M + j], T[(slot * 3 + p) * M + j],
+// H and Hm [(chain * 3 + p) * M + j].
 template <bool ERR, int M>
 __device__ __forceinline__ void walk_chain_sv(const int* __restrict__ cr, const double2* Ps, const TargetRec* Ts,
                                               const double2* Hs, const double* Hm, int c, uint32_t m,
-                                              double2 (&B)[M][3], double& el, double& qmin, double& qmax) {
+                                              double2 (&B)[M][3], double (&el)[M], double (&qmin)[M],
+                                              double (&qmax)[M]) {
   double2 S[M][3];
   double sm[M][3];
 #pragma unroll
@@ -175,9 +207,16 @@ __device__ __forceinline__ void walk_chain_sv(const int* __restrict__ cr, const 
     } else {
 #pragma unroll
       for (int p = 0; p < 3; ++p)
-        if (hph >> p & 1)
+        if (hph >> p & 1) {
+          double x[M], y[M];
 #pragma unroll
-          for (int j = 0; j < M; ++j) sm[j][p] = vmag(cadd(Hs[(c * 3 + p) * M + j], B[j][p]));
+          for (int j = 0; j < M; ++j) {
+            x[j] = mag2(cadd(Hs[(c * 3 + p) * M + j], B[j][p]));
+          }
+          sqrt_nr_v<M>(x, y);
+#pragma unroll
+          for (int j = 0; j < M; ++j) sm[j][p] = y[j];
+        }
     }
   }
   const int ns = cr[C_NSLOT], s0 = cr[C_SLOT0], pair0 = cr[C_PAIR0], bit0 = cr[C_BIT0];
@@ -185,7 +224,7 @@ __device__ __forceinline__ void walk_chain_sv(const int* __restrict__ cr, const 
   int sidx = 0;
   for (int r = 0; r < ns; ++r) {
     const int w = r < 8 ? phw0 : (r < 16 ? phw1 : phw2);
-    const int ph = (w >> (3 * (r & 7))) & 7;
+    const int ph = __builtin_amdgcn_readfirstlane((w >> (3 * (r & 7))) & 7);  // same for every lane
     const int prow = pair0 + ((r * (r + 1)) >> 1);
     const TargetRec* tr = Ts + (s0 + r) * 3 * M;
     if ((m >> (bit0 + r)) & 1u) {  // reduced: the moved current's rise; cluster error against the super
@@ -200,7 +239,7 @@ __device__ __forceinline__ void walk_chain_sv(const int* __restrict__ cr, const 
           S[j][p].y += pv.y;
           if (ERR) {
             const TargetRec t = tr[p * M + j];
-            el = fmax(el, fmax(sm[j][p] - t.lo, t.hi - sm[j][p]));
+            el[j] = fmax(el[j], fmax(sm[j][p] - t.lo, t.hi - sm[j][p]));
           }
         }
       }
@@ -209,15 +248,22 @@ __device__ __forceinline__ void walk_chain_sv(const int* __restrict__ cr, const 
 #pragma unroll
         for (int p = 0; p < 3; ++p) {
           if (!(ph >> p & 1)) continue;
+          double q[M], mg[M], lo[M], hi[M];
 #pragma unroll
           for (int j = 0; j < M; ++j) {
             const TargetRec t = tr[p * M + j];
             const double vx = t.W.x + S[j][p].x, vy = t.W.y + S[j][p].y;
-            const double q = fma(vx, vx, vy * vy);
-            sm[j][p] = sqrt_nr(q);
-            qmin = fmin(qmin, q);
-            qmax = fmax(qmax, q);
-            el = fmax(el, fmax(sm[j][p] - t.lo, t.hi - sm[j][p]));
+            q[j] = fma(vx, vx, vy * vy);
+            lo[j] = t.lo;
+            hi[j] = t.hi;
+          }
+          sqrt_nr_v<M>(q, mg);
+#pragma unroll
+          for (int j = 0; j < M; ++j) {
+            sm[j][p] = mg[j];
+            qmin[j] = fmin(qmin[j], q[j]);
+            qmax[j] = fmax(qmax[j], q[j]);
+            el[j] = fmax(el[j], fmax(mg[j] - lo[j], hi[j] - mg[j]));
           }
         }
       }
@@ -238,8 +284,8 @@ template <int M>
 __device__ __forceinline__ void score_chain_sv(const int* __restrict__ chains, const int* __restrict__ nest, int c,
                                                const double2* Ps, const TargetRec* Ts, const double2* Hs,
                                                const double* Hm, const TargetRec* Zs, int zcap,
-                                               const TargetRec* const (&zg)[M], uint32_t m, double& el,
-                                               double& qmin, double& qmax) {
+                                               const TargetRec* const (&zg)[M], uint32_t m, double (&el)[M],
+                                               double (&qmin)[M], double (&qmax)[M]) {
   const int* cr = chains + c * kChainInts;
   double2 B[M][3];
 #pragma unroll
@@ -254,17 +300,24 @@ __device__ __forceinline__ void score_chain_sv(const int* __restrict__ chains, c
   walk_chain_sv<true, M>(cr, Ps, Ts, Hs, Hm, c, m, B, el, qmin, qmax);
 #pragma unroll
   for (int p = 0; p < 3; ++p)
-    for (int q = cr[C_ZOFF0 + p], qe = q + cr[C_ZCNT0 + p]; q < qe; ++q)
+    for (int q = cr[C_ZOFF0 + p], qe = q + cr[C_ZCNT0 + p]; q < qe; ++q) {
+      double q2[M], mag[M], lo[M], hi[M];
 #pragma unroll
       for (int j = 0; j < M; ++j) {
         const TargetRec t = q < zcap ? Zs[q * M + j] : zg[j][q];
         const double vx = t.W.x + B[j][p].x, vy = t.W.y + B[j][p].y;
-        const double q2 = fma(vx, vx, vy * vy);
-        const double mag = sqrt_nr(q2);
-        el = fmax(el, fmax(mag - t.lo, t.hi - mag));
-        qmin = fmin(qmin, q2);
-        qmax = fmax(qmax, q2);
+        q2[j] = fma(vx, vx, vy * vy);
+        lo[j] = t.lo;
+        hi[j] = t.hi;
       }
+      sqrt_nr_v<M>(q2, mag);
+#pragma unroll
+      for (int j = 0; j < M; ++j) {
+        el[j] = fmax(el[j], fmax(mag[j] - lo[j], hi[j] - mag[j]));
+        qmin[j] = fmin(qmin[j], q2[j]);
+        qmax[j] = fmax(qmax[j], q2[j]);
+      }
+    }
 }
 
 // Band slack of a mask from the extreme squared magnitudes of its kept

@@ -86,7 +86,12 @@ __global__ __launch_bounds__(kScoreThreads) void k_score_fp64(
   const int zst = min(H.nz, zcap);
   const int cP = H.npairs * 3, cT = H.nslots * 6, cH = H.nchains * 3, cZ = zst * 2;
   const int tot = cP + cT + cH + cZ;
-  double e = 0.0, qmin = INFINITY, qmax = -INFINITY;
+  double e = 0.0, qmn[M], qmx[M];
+#pragma unroll
+  for (int j = 0; j < M; ++j) {
+    qmn[j] = INFINITY;
+    qmx[j] = -INFINITY;
+  }
   for (int l = l0; l < l1; l += M) {
     for (int i = tid; i < M * tot; i += kScoreThreads) {
       const int j = i / tot;
@@ -114,16 +119,24 @@ __global__ __launch_bounds__(kScoreThreads) void k_score_fp64(
     }
     if (tid < M) Ec[tid] = econst[min(l + tid, l1 - 1)];
     __syncthreads();
-    double el = Ec[0];
-#pragma unroll
-    for (int j = 1; j < M; ++j) el = fmax(el, Ec[j]);
+    double el[M];
     const TargetRec* zg[M];
 #pragma unroll
-    for (int j = 0; j < M; ++j) zg[j] = zrec + (size_t)min(l + j, l1 - 1) * H.nz;
+    for (int j = 0; j < M; ++j) {
+      el[j] = Ec[j];
+      zg[j] = zrec + (size_t)min(l + j, l1 - 1) * H.nz;
+    }
     for (int c = 0; c < H.nchains; ++c)
-      score_chain_sv<M>(chains, nest, c, Ps, Ts, Hv, Hm, Zs, zst, zg, m, el, qmin, qmax);
-    e = fmax(e, el);
+      score_chain_sv<M>(chains, nest, c, Ps, Ts, Hv, Hm, Zs, zst, zg, m, el, qmn, qmx);
+#pragma unroll
+    for (int j = 0; j < M; ++j) e = fmax(e, el[j]);
     __syncthreads();
+  }
+  double qmin = qmn[0], qmax = qmx[0];
+#pragma unroll
+  for (int j = 1; j < M; ++j) {
+    qmin = fmin(qmin, qmn[j]);
+    qmax = fmax(qmax, qmx[j]);
   }
   const uint32_t nmask = 1u << H.k;
   const bool valid = m < nmask;
