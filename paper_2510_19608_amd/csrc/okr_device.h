@@ -430,18 +430,6 @@ __device__ __forceinline__ void score_chain(const int* __restrict__ chains, cons
     }
 }
 
-// Error of M masks for one snapshot folded into el, kept squared magnitudes
-// into (qmin, qmax): every chain's terms in turn.
-template <bool STAGED, int M>
-__device__ __forceinline__ void score_snapshot(const SegHdr& H, const int* __restrict__ chains,
-                                               const int* __restrict__ nest, const double2* Ps, const TargetRec* Ss,
-                                               const double2* Hs, const double* Hm, const TargetRec* Zs, int zcap,
-                                               const TargetRec* __restrict__ zrec_l, const uint32_t (&m)[M],
-                                               double (&el)[M], double (&qmin)[M], double (&qmax)[M]) {
-  for (int c = 0; c < H.nchains; ++c)
-    score_chain<STAGED, M>(chains, nest, c, Ps, Ss, Hs, Hm, Zs, zcap, zrec_l, m, el, qmin, qmax);
-}
-
 // ------------------------------------------------------------ block reduce --
 template <typename T, typename Op>
 __device__ T block_reduce(T v, Op op, T* sh) {

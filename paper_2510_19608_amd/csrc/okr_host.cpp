@@ -34,10 +34,14 @@ template <int M>
 __global__ void k_score_fp64(const SegHdr*, const int*, size_t, const int*, const double2*, const TargetRec*,
                            const double2*, const TargetRec*, const double*, int, int, int, int, int, SelParams,
                            MaskScore*, MaskScore*, TileRec*, int*, const int*);
-__global__ void k_fac_tables(const SegHdr*, const int*, size_t, const int*, const double2*, const TargetRec*,
-                             const double2*, const TargetRec*, const double*, PatScore*, double*);
-__global__ void k_fac_combine(const SegHdr*, const int*, size_t, const int*, const PatScore*, const double*, SelParams,
-                              MaskScore*, TileRec*);
+__global__ void k_terms_init(const SegHdr*, const int*, size_t, int, const int*, int, const double*,
+                             unsigned long long*, unsigned long long*);
+__global__ void k_chain_terms(const SegHdr*, const int*, size_t, int, const int*, const double2*, const TargetRec*,
+                              const double2*, const TargetRec*, const double*, const uint32_t*, const int*, int, int,
+                              int, unsigned long long*, unsigned long long*);
+__global__ void k_list_finish(const int*, const unsigned long long*, int, SelParams, MaskScore*);
+__global__ void k_fac_combine(const SegHdr*, const int*, size_t, const int*, const unsigned long long*,
+                              const unsigned long long*, SelParams, MaskScore*, TileRec*);
 __global__ void k_argmin(const SegHdr*, const int*, size_t, const MaskScore*, const TileRec*, SelParams, const int*,
                          DevDecision*, const int*);
 __global__ void k_apply(const SegHdr*, const int*, size_t, const int*, Topo, State, const DevDecision*,
@@ -55,8 +59,6 @@ __global__ void k_score_fp32(const SegHdr*, int, const int*, const Pair32*, cons
                              const double*, int, int, SelParams, MaskScore32*, MaskScore32*, TileRec32*, int*);
 __global__ void k_mixed_select_a(const SegHdr*, int, const MaskScore32*, const TileRec32*, SelParams, const int*,
                                  MixedState*, uint32_t*, int*);
-__global__ void k_refine_fp64(const SegHdr*, int, const int*, const double2*, const TargetRec*, const double2*,
-                              const TargetRec*, const double*, SelParams, const uint32_t*, const int*, MaskScore*);
 __global__ void k_mixed_select_b(const SegHdr*, int, const MaskScore32*, const TileRec32*, SelParams, const int*,
                                  MixedState*, const uint32_t*, const int*, const MaskScore*, uint32_t*, int*);
 __global__ void k_mixed_final(const SegHdr*, int, SelParams, const int*, MixedState*, const MaskScore32*,
@@ -101,7 +103,6 @@ constexpr int kMaxLanes = 8;      // segments per chunk (each needs a scratch bl
 constexpr int kDefaultLanes = 8;
 constexpr int kStatusInts = 16;
 constexpr double kMixedDelta = 1e-8;  // bound on |e32 - e64| used by the shortlist
-constexpr int kRefineBlocks = 256;
 
 size_t align256(size_t x) { return (x + 255) & ~size_t(255); }
 
@@ -120,8 +121,9 @@ int snap_groups_default(int k, int S, int* spg, int mpl = 1, int target_blocks =
 struct Layout {
   size_t topo, z, Zroot, Vhat, Vcur, A, J, absV, kept, sup, slot_of, zent_of, status, iters, hdrs, decs, tab, P, srec,
       headV, zrec, econst, part, fin, tiles, tickets, kp, yeq, Ykd, Yko, err;
-  // factored FP64 scoring: chain-pattern table, largest constant error
-  size_t pat, ecmax;
+  // factored FP64 scoring: chain-pattern table, largest constant error;
+  // accumulators of the short-list scoring
+  size_t pat, ecmax, lacc;
   // mixed precision
   size_t P32, S32, H32, Z32, part32, fin32, tiles32, listA, listB, scoreA, scoreB, counts, mstate;
   // surrogate: feature tables (always), ranking buffers (when planned with top_k)
@@ -195,6 +197,17 @@ size_t sv_lds_bytes(int spp, int k) {
   return (size_t)spp * (pcap * 3 * sizeof(double2) + (size_t)k * 3 * (sizeof(TargetRec) + sizeof(double2) + sizeof(double)) +
                         kSvZone * sizeof(TargetRec) + sizeof(double));
 }
+// LDS of the chain-term kernel for segments of up to k nodes: chain records
+// and nesting paths, one snapshot's pairs, slot and head records, and the
+// first kTermsZone zone records.
+constexpr int kTermsZone = 256;
+int terms_icap(int k) { return k * kChainInts + k * k; }
+size_t terms_lds_bytes(int k) {
+  const size_t pcap = (size_t)k * (k + 1) / 2;
+  return ((size_t)terms_icap(k) * 4 + 15) / 16 * 16 + pcap * 3 * sizeof(double2) +
+         (size_t)k * 3 * (sizeof(TargetRec) + sizeof(double2)) + kTermsZone * sizeof(TargetRec);
+}
+
 // Snapshots per pass: the wanted count (1, 2 or 4), at most the group's
 // snapshots, within the LDS budget.
 int sv_spp(int want, int k, int spg) {
@@ -520,6 +533,7 @@ extern "C" int okr_plan(okr_handle* h, const okr_topology* topo, const okr_margi
     L.tickets = take(sizeof(int) * nt);
     L.pat = take(sizeof(PatScore) * 2 * nm);
     L.ecmax = take(sizeof(double));
+    L.lacc = take(sizeof(unsigned long long) * 3 * nm);
   }
   {
     size_t most = 1;
@@ -597,8 +611,7 @@ struct Ptrs {
   TargetRec *srec, *zrec;
   MaskScore *part, *fin;
   TileRec* tiles;
-  PatScore* pat;
-  double* ecmax;
+  unsigned long long *pat, *ecmax, *lacc;
   Pair32* P32;
   Rec32 *S32, *Z32;
   Head32* H32;
@@ -666,8 +679,9 @@ Ptrs pointers(okr_handle* h, void* d_workspace, int lane = 0) {
   p.part = (MaskScore*)at(L.part);
   p.fin = (MaskScore*)at(L.fin);
   p.tiles = (TileRec*)at(L.tiles);
-  p.pat = (PatScore*)at(L.pat);
-  p.ecmax = (double*)at(L.ecmax);
+  p.pat = (unsigned long long*)at(L.pat);
+  p.ecmax = (unsigned long long*)at(L.ecmax);
+  p.lacc = (unsigned long long*)at(L.lacc);
   p.tickets = (int*)at(L.tickets);
   p.kp = (int*)at(L.kp);
   p.yeq = (double2*)at(L.yeq);
@@ -705,6 +719,23 @@ Ptrs pointers(okr_handle* h, void* d_workspace, int lane = 0) {
   p.sW2b = (__bf16*)at(L.sW2b);
   p.sW2tb = (__bf16*)at(L.sW2tb);
   return p;
+}
+
+// FP64 scores of list[0 .. *count) (at most cap masks) of one segment into
+// out: one lane per (listed mask, chain, snapshot), folded by atomics.  w
+// holds the segment's scratch pointers and segp its id in device memory.
+void list_score(const okr_handle* h, const Ptrs& w, const int* segp, int k, const uint32_t* list, const int* count,
+                int cap, MaskScore* out, const SelParams& sp, hipStream_t st) {
+  const int fb = std::max(1, std::min(64, (cap + 255) / 256));
+  const int cb = std::max(1, std::min(16, (int)(((size_t)cap * k + 255) / 256)));
+  hipLaunchKernelGGL(k_terms_init, dim3(fb), dim3(256), 0, st, (const SegHdr*)w.hdrs, segp, (size_t)0, (int)0, count,
+                     cap, (const double*)w.econst, w.lacc, (unsigned long long*)nullptr);
+  hipLaunchKernelGGL(k_chain_terms, dim3(cb, h->S), dim3(256), terms_lds_bytes(k), st, (const SegHdr*)w.hdrs, segp,
+                     (size_t)0, (int)0, (const int*)w.tab, (const double2*)w.P, (const TargetRec*)w.srec,
+                     (const double2*)w.headV, (const TargetRec*)w.zrec, (const double*)w.econst, list, count, cap,
+                     terms_icap(k), kTermsZone, w.lacc, (unsigned long long*)nullptr);
+  hipLaunchKernelGGL(k_list_finish, dim3(fb), dim3(256), 0, st, count, (const unsigned long long*)w.lacc, cap, sp,
+                     out);
 }
 
 // Enqueue one whole search on `st` without host synchronisation.  With `ev`
@@ -851,10 +882,7 @@ void enqueue_search(okr_handle* h, void* ws, const okr_yblocks* Y, const okr_loa
                            (const uint32_t*)nullptr, (int)nm, K, (const int*)w.status, w.slist, w.scount,
                            (const int*)nullptr, 0);
       }
-      hipLaunchKernelGGL(k_refine_fp64, dim3(kRefineBlocks), dim3(kScoreBlock), 0, st, (const SegHdr*)w.hdrs, g,
-                         (const int*)w.tab, (const double2*)w.P, (const TargetRec*)w.srec, (const double2*)w.headV,
-                         (const TargetRec*)w.zrec, (const double*)w.econst, sp, (const uint32_t*)w.slist,
-                         (const int*)w.scount, w.sscore);
+      list_score(h, w, p.chunks + c0 + z, k, w.slist, w.scount, K, w.sscore, sp, st);
       hipLaunchKernelGGL(k_surr_decide, dim3(1), dim3(1024), 0, st, (const SegHdr*)w.hdrs, g, sp,
                          (const int*)w.status, (const uint32_t*)w.slist, (const int*)w.scount,
                          (const MaskScore*)w.sscore, w.decs, w.sgates + g);
@@ -862,14 +890,18 @@ void enqueue_search(okr_handle* h, void* ws, const okr_yblocks* Y, const okr_loa
     if (!mixed) {
       if (ev) (void)hipEventRecord((*ev)[2 * c], st);
       if (factored) {
-        // pattern table (grid-stride waves: up to 2^(k+1) patterns), then every mask
-        const int tblocks = (int)std::min<uint64_t>(1024, std::max<uint64_t>(4, ((uint64_t)2 << kc) / 32));
-        hipLaunchKernelGGL(k_fac_tables, dim3(tblocks, 1, nz), dim3(256), 0, st, (const SegHdr*)q.hdrs, segs, lstride,
-                           (const int*)q.tab, (const double2*)q.P, (const TargetRec*)q.srec, (const double2*)q.headV,
-                           (const TargetRec*)q.zrec, (const double*)q.econst, q.pat, q.ecmax);
+        // pattern table (up to 2^(k+1) patterns; one block column per snapshot), then every mask
+        const int pb = (int)std::min<uint64_t>(16, std::max<uint64_t>(1, ((uint64_t)2 << kc) / 256));
+        hipLaunchKernelGGL(k_terms_init, dim3(pb, 1, nz), dim3(256), 0, st, (const SegHdr*)q.hdrs, segs, lstride, (int)1,
+                           (const int*)nullptr, 0, (const double*)q.econst, q.pat, q.ecmax);
+        hipLaunchKernelGGL(k_chain_terms, dim3(pb, S, nz), dim3(256), terms_lds_bytes(kc), st, (const SegHdr*)q.hdrs,
+                           segs, lstride, (int)1, (const int*)q.tab, (const double2*)q.P, (const TargetRec*)q.srec,
+                           (const double2*)q.headV, (const TargetRec*)q.zrec, (const double*)q.econst,
+                           (const uint32_t*)nullptr, (const int*)nullptr, 0, terms_icap(kc), kTermsZone, q.pat,
+                           q.ecmax);
         hipLaunchKernelGGL(k_fac_combine, dim3((nmask + 255) / 256, 1, nz), dim3(256), 0, st, (const SegHdr*)q.hdrs,
-                           segs, lstride, (const int*)q.tab, (const PatScore*)q.pat, (const double*)q.ecmax, sp, q.fin,
-                           q.tiles);
+                           segs, lstride, (const int*)q.tab, (const unsigned long long*)q.pat,
+                           (const unsigned long long*)q.ecmax, sp, q.fin, q.tiles);
       } else {
 #define OKR_SCORE64(M_)                                                                                             \
   hipLaunchKernelGGL(k_score_fp64<M_>, dim3(mblocks, SG, nz), dim3(kScoreThreads), lds, st, (const SegHdr*)q.hdrs, segs, \
@@ -935,25 +967,20 @@ void enqueue_search(okr_handle* h, void* ws, const okr_yblocks* Y, const okr_loa
       if (ev) (void)hipEventRecord((*ev)[2 * c + 1], st);
       for (int z = 0; z < nz; ++z) {
         const int g = h->chunk_segs[c0 + z];
-        const uint32_t nm = 1u << (h->seg_off[g + 1] - h->seg_off[g]);
+        const int k = h->seg_off[g + 1] - h->seg_off[g];
+        const uint32_t nm = 1u << k;
         const Ptrs& w = lp[z];
         int* cA = w.counts;
         int* cB = w.counts + 1;
         hipLaunchKernelGGL(k_mixed_select_a, dim3(1), dim3(1024), 0, st, (const SegHdr*)w.hdrs, g,
                            (const MaskScore32*)w.fin32, (const TileRec32*)w.tiles32, sp, (const int*)w.status,
                            w.mstate, w.listA, cA);
-        hipLaunchKernelGGL(k_refine_fp64, dim3(kRefineBlocks), dim3(kScoreBlock), 0, st, (const SegHdr*)w.hdrs, g,
-                           (const int*)w.tab, (const double2*)w.P, (const TargetRec*)w.srec, (const double2*)w.headV,
-                           (const TargetRec*)w.zrec, (const double*)w.econst, sp, (const uint32_t*)w.listA,
-                           (const int*)cA, w.scoreA);
+        list_score(h, w, p.chunks + c0 + z, k, w.listA, cA, (int)nm, w.scoreA, sp, st);
         hipLaunchKernelGGL(k_mixed_select_b, dim3(1), dim3(1024), 0, st, (const SegHdr*)w.hdrs, g,
                            (const MaskScore32*)w.fin32, (const TileRec32*)w.tiles32, sp, (const int*)w.status,
                            w.mstate, (const uint32_t*)w.listA, (const int*)cA, (const MaskScore*)w.scoreA, w.listB,
                            cB);
-        hipLaunchKernelGGL(k_refine_fp64, dim3(kRefineBlocks), dim3(kScoreBlock), 0, st, (const SegHdr*)w.hdrs, g,
-                           (const int*)w.tab, (const double2*)w.P, (const TargetRec*)w.srec, (const double2*)w.headV,
-                           (const TargetRec*)w.zrec, (const double*)w.econst, sp, (const uint32_t*)w.listB,
-                           (const int*)cB, w.scoreB);
+        list_score(h, w, p.chunks + c0 + z, k, w.listB, cB, (int)nm, w.scoreB, sp, st);
         hipLaunchKernelGGL(k_mixed_final, dim3(1), dim3(1024), 0, st, (const SegHdr*)w.hdrs, g, sp,
                            (const int*)w.status, w.mstate, (const MaskScore32*)w.fin32, (const uint32_t*)w.listA,
                            (const int*)cA, (const MaskScore*)w.scoreA, (const uint32_t*)w.listB, (const int*)cB,

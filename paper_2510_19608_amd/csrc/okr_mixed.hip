@@ -8,8 +8,8 @@
 //                    uncertain feasibility (band delta + amb around e_bar and
 //                    the voltage band)                      [okr_score.hip]
 //   k_mixed_select_a list A: uncertain masks at or above the best sure level
-//   k_refine_fp64    FP64 scores of a mask list (same arithmetic as the FP64
-//                    scoring kernel)                        [okr_score.hip]
+//   k_score_fp64     (list mode) FP64 scores of a mask list, the per-mask
+//                    FP64 scoring kernel itself             [okr_score.hip]
 //   k_mixed_select_b best level P*; list B: possibly feasible masks at P*
 //                    whose FP32 error is within tie + 2 delta + amb of the
 //                    smallest FP64-confirmed one

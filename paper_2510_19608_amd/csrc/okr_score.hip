@@ -59,7 +59,8 @@ __global__ __launch_bounds__(kScoreThreads) void k_score_fp64(
   const SegHdr H = hdrs[g];
   if (!H.valid || (gates && gates[g] == 0)) return;
   // blocks past this segment's masks (a chunk's launch covers its largest segment)
-  if ((uint64_t)blockIdx.x * kScoreThreads >= ((uint64_t)1 << H.k)) return;
+  const uint32_t nmask = 1u << H.k;
+  if ((uint64_t)blockIdx.x * kScoreThreads >= nmask) return;
   tab = lane_ptr(tab, lstride);
   P = lane_ptr(P, lstride);
   srec = lane_ptr(srec, lstride);
@@ -78,6 +79,7 @@ __global__ __launch_bounds__(kScoreThreads) void k_score_fp64(
   double* Ec = Hm + (size_t)kcap * 3 * M;
   const int tid = threadIdx.x;
   const uint32_t m = blockIdx.x * kScoreThreads + tid;
+  const bool valid = m < nmask;
   const int sg = blockIdx.y;
   const int l0 = sg * snaps_per_group;
   const int l1 = min(H.S, l0 + snaps_per_group);
@@ -138,8 +140,6 @@ __global__ __launch_bounds__(kScoreThreads) void k_score_fp64(
     qmin = fmin(qmin, qmn[j]);
     qmax = fmax(qmax, qmx[j]);
   }
-  const uint32_t nmask = 1u << H.k;
-  const bool valid = m < nmask;
   if (valid) {
     MaskScore r;
     r.e = e;
@@ -175,72 +175,57 @@ OKR_SCORE64_INST(2)
 OKR_SCORE64_INST(4)
 #undef OKR_SCORE64_INST
 
-// FP64 scores of the masks in `list` (all snapshots), with the arithmetic of
-// the FP64 scoring kernel: one wave per mask, its lanes over the snapshots
-// (per-snapshot tables read from global memory, no LDS stage), a wave
-// reduction per mask.  Lists are short (shortlists, top-k), so the latency
-// of one snapshot replaces that of a serial snapshot loop.
-__global__ __launch_bounds__(kScoreBlock) void k_refine_fp64(
-    const SegHdr* __restrict__ hdrs, int g, const int* __restrict__ tab, const double2* __restrict__ P,
-    const TargetRec* __restrict__ srec, const double2* __restrict__ headV, const TargetRec* __restrict__ zrec,
-    const double* __restrict__ econst, SelParams sp, const uint32_t* __restrict__ list,
-    const int* __restrict__ count, MaskScore* __restrict__ out) {
-  const SegHdr H = hdrs[g];
+// ------------------------------------------------- chain-term kernels --
+// Exact FP64 terms of chains for given mask bits, one lane per (item,
+// snapshot), folded into per-item accumulators by 64-bit atomics on the IEEE
+// bit patterns.  Items are either (listed mask, chain) pairs -- the scores of
+// a short mask list -- or chain patterns -- the factored form's table: for
+// chain c and assignment u of its C_PMASK bits (bit j of u at the j-th lowest
+// set bit), the chain's terms.  Every folded value is a non-negative double
+// (errors max(|V| - lo, hi - |V|) with lo <= hi, squared magnitudes), and for
+// those the bit patterns order like the values; max and min are exact, so the
+// results equal the per-mask kernel's.  qmax starts at +0 instead of -inf:
+// band_slack treats both alike (no kept node-phase).
+//
+// A block serves one snapshot (blockIdx.y) of one segment (blockIdx.z of a
+// chunk): it first stages the chain records and nesting paths and the
+// snapshot's pair, slot, head and first zcap zone records in LDS (one
+// coalesced round trip), then walks every item's chain from there.
+enum { kTermsList = 0, kTermsPatterns = 1 };
+constexpr int kTermsBlock = 256;  // threads of a chain-term block
+
+__device__ __forceinline__ int terms_count(int mode, const SegHdr& H, const int* count, int cap) {
+  return mode == kTermsList ? min(*count, cap) * H.nchains : H.npat;
+}
+
+__global__ void k_terms_init(const SegHdr* __restrict__ hdrs, const int* __restrict__ segs, size_t lstride, int mode,
+                             const int* __restrict__ count, int cap, const double* __restrict__ econst,
+                             unsigned long long* __restrict__ acc, unsigned long long* __restrict__ ecmax) {
+  const SegHdr H = hdrs[segs[blockIdx.z]];
   if (!H.valid) return;
-  const int cnt = *count;
-  const int lane = threadIdx.x;
-  const int* chains = tab + H.o_chain;
-  const int* slots = tab + H.o_slot;
-  const int* nest = tab + H.o_nest;
-  for (int idx = blockIdx.x; idx < cnt; idx += gridDim.x) {
-    const uint32_t m = list[idx];
-    double e = 0.0, qmin = INFINITY, qmax = -INFINITY;
-    for (int l = lane; l < H.S; l += kScoreBlock) {
-      double el[1] = {econst[l]}, qn[1] = {qmin}, qx[1] = {qmax};
-      const uint32_t mm[1] = {m};
-      score_snapshot<false, 1>(H, chains, nest, P + (size_t)l * H.npairs * 3, srec + (size_t)l * H.nslots * 3,
-                               headV + (size_t)l * H.nchains * 3, (const double*)nullptr, (const TargetRec*)nullptr,
-                               0, zrec + (size_t)l * H.nz, mm, el, qn, qx);
-      qmin = qn[0];
-      qmax = qx[0];
-      e = fmax(e, el[0]);
-    }
-    for (int o = 32; o > 0; o >>= 1) {
-      e = fmax(e, __shfl_xor(e, o, 64));
-      qmin = fmin(qmin, __shfl_xor(qmin, o, 64));
-      qmax = fmax(qmax, __shfl_xor(qmax, o, 64));
-    }
-    if (lane == 0) {
-      MaskScore r;
-      r.e = e;
-      r.slack = band_slack(qmin, qmax, sp.vmin, sp.vmax);
-      out[idx] = r;
-    }
+  count = lane_ptr(count, lstride);
+  econst = lane_ptr(econst, lstride);
+  acc = lane_ptr(acc, lstride);
+  ecmax = lane_ptr(ecmax, lstride);
+  const int n = mode == kTermsList ? min(*count, cap) : H.npat;
+  const int t0 = blockIdx.x * blockDim.x + threadIdx.x, stride = gridDim.x * blockDim.x;
+  for (int q = t0; q < n; q += stride) {
+    acc[3 * q] = 0ull;
+    acc[3 * q + 1] = (unsigned long long)__double_as_longlong(INFINITY);
+    acc[3 * q + 2] = 0ull;
+  }
+  if (mode == kTermsPatterns && ecmax) {
+    if (t0 == 0) *ecmax = 0ull;
   }
 }
 
-// ------------------------------------------------------- factored scoring --
-// A mask's error is the largest of its chains' terms (and of the snapshot's
-// constant error), over every snapshot; the extreme kept squared magnitudes
-// likewise.  Chain c's terms depend only on the mask bits in C_PMASK (its own
-// slots and those of its nesting path), so every mask's exact score can be
-// assembled from one table entry per chain: for each chain and each
-// assignment u of its C_PMASK bits (bit j of u at the j-th lowest set bit),
-// the chain's terms reduced over the snapshots.  Max and min are exact, so
-// the assembled scores equal the per-mask kernel's bit for bit.
-constexpr int kPatLds = 1024;  // pattern-table entries staged in LDS by the combine kernel
-
-// The pattern table: one wave per pattern, lanes over snapshots, the chain's
-// per-snapshot arithmetic of the FP64 scoring kernel, a wave reduction.  Wave 0
-// also stores the largest constant error over the snapshots.
-__global__ __launch_bounds__(256) void k_fac_tables(const SegHdr* __restrict__ hdrs, const int* __restrict__ segs,
-                                                    size_t lstride, const int* __restrict__ tab,
-                                                    const double2* __restrict__ P,
-                                                    const TargetRec* __restrict__ srec,
-                                                    const double2* __restrict__ headV,
-                                                    const TargetRec* __restrict__ zrec,
-                                                    const double* __restrict__ econst, PatScore* __restrict__ pat,
-                                                    double* __restrict__ ecmax) {
+__global__ __launch_bounds__(kTermsBlock) void k_chain_terms(
+    const SegHdr* __restrict__ hdrs, const int* __restrict__ segs, size_t lstride, int mode,
+    const int* __restrict__ tab, const double2* __restrict__ P, const TargetRec* __restrict__ srec,
+    const double2* __restrict__ headV, const TargetRec* __restrict__ zrec, const double* __restrict__ econst,
+    const uint32_t* __restrict__ list, const int* __restrict__ count, int cap, int icap, int zcap,
+    unsigned long long* __restrict__ acc, unsigned long long* __restrict__ ecmax) {
+  extern __shared__ __align__(16) unsigned char ct_lds[];
   const SegHdr H = hdrs[segs[blockIdx.z]];
   if (!H.valid) return;
   tab = lane_ptr(tab, lstride);
@@ -249,63 +234,123 @@ __global__ __launch_bounds__(256) void k_fac_tables(const SegHdr* __restrict__ h
   headV = lane_ptr(headV, lstride);
   zrec = lane_ptr(zrec, lstride);
   econst = lane_ptr(econst, lstride);
-  pat = lane_ptr(pat, lstride);
+  list = lane_ptr(list, lstride);
+  count = lane_ptr(count, lstride);
+  acc = lane_ptr(acc, lstride);
   ecmax = lane_ptr(ecmax, lstride);
-  const int lane = threadIdx.x & 63;
-  const int wave = blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6);
-  const int nwaves = gridDim.x * (blockDim.x >> 6);
-  const int* chains = tab + H.o_chain;
-  const int* nest = tab + H.o_nest;
-  if (wave == 0) {
-    double e = -INFINITY;
-    for (int l = lane; l < H.S; l += 64) e = fmax(e, econst[l]);
-    for (int o = 32; o > 0; o >>= 1) e = fmax(e, __shfl_xor(e, o, 64));
-    if (lane == 0) *ecmax = e;
+  const int items = terms_count(mode, H, count, cap);
+  const int l = blockIdx.y;
+  if (mode == kTermsPatterns && ecmax && blockIdx.x == 0 && threadIdx.x == 0)
+    atomicMax(ecmax, (unsigned long long)__double_as_longlong(econst[l]));
+  if ((int)(blockIdx.x * blockDim.x) >= items) return;  // whole block idle
+  // stage: chain records and nesting paths (ints [0, o_slot)), then this
+  // snapshot's pairs, slot records, heads and first zone records
+  const int nint = H.o_slot;
+  const int zst = min(H.nz, zcap);
+  int* si = (int*)ct_lds;
+  double2* sP = (double2*)(ct_lds + (size_t)((icap * 4 + 15) / 16) * 16);
+  TargetRec* sS = (TargetRec*)(sP + (size_t)H.npairs * 3);
+  double2* sH = (double2*)(sS + (size_t)H.nslots * 3);
+  TargetRec* sZ = (TargetRec*)(sH + (size_t)H.nchains * 3);
+  const uint4* gP = (const uint4*)(P + (size_t)l * H.npairs * 3);
+  const uint4* gS = (const uint4*)(srec + (size_t)l * H.nslots * 3);
+  const uint4* gH = (const uint4*)(headV + (size_t)l * H.nchains * 3);
+  const uint4* gZ = (const uint4*)(zrec + (size_t)l * H.nz);
+  const int cP = H.npairs * 3, cS = H.nslots * 6, cH = H.nchains * 3, cZ = zst * 2;
+  for (int i = threadIdx.x; i < nint; i += blockDim.x) si[i] = tab[i];
+  for (int i = threadIdx.x; i < cP + cS + cH + cZ; i += blockDim.x) {
+    if (i < cP) ((uint4*)sP)[i] = gP[i];
+    else if (i < cP + cS) ((uint4*)sS)[i - cP] = gS[i - cP];
+    else if (i < cP + cS + cH) ((uint4*)sH)[i - cP - cS] = gH[i - cP - cS];
+    else ((uint4*)sZ)[i - cP - cS - cH] = gZ[i - cP - cS - cH];
   }
-  for (int t = wave; t < H.npat; t += nwaves) {
+  __syncthreads();
+  const int* chains = si + H.o_chain;
+  const int* nest = si + H.o_nest;
+  const int nch = H.nchains;
+  const double ec = econst[l];
+  if (mode == kTermsList) {
+    // a block's items cover consecutive listed masks (each with all its
+    // chains): fold them in LDS first, then one global atomic per mask
+    __shared__ unsigned long long s_acc[3 * (kTermsBlock + 2)];
+    for (int base = blockIdx.x * blockDim.x; base < items; base += gridDim.x * blockDim.x) {
+      const int q0 = base / nch, q1 = min(items - 1, base + (int)blockDim.x - 1) / nch;
+      for (int i = threadIdx.x; i <= q1 - q0; i += blockDim.x) {
+        s_acc[3 * i] = 0ull;
+        s_acc[3 * i + 1] = (unsigned long long)__double_as_longlong(INFINITY);
+        s_acc[3 * i + 2] = 0ull;
+      }
+      __syncthreads();
+      const int it = base + threadIdx.x;
+      if (it < items) {
+        const int q = it / nch, c = it - q * nch;
+        const uint32_t mm[1] = {list[q]};
+        double el[1] = {ec}, qn[1] = {INFINITY}, qx[1] = {0.0};
+        score_chain<true, 1>(chains, nest, c, sP, sS, sH, (const double*)nullptr, sZ, zst, zrec + (size_t)l * H.nz,
+                             mm, el, qn, qx);
+        unsigned long long* a = s_acc + 3 * (q - q0);
+        atomicMax(&a[0], (unsigned long long)__double_as_longlong(el[0]));
+        if (qn[0] < INFINITY) atomicMin(&a[1], (unsigned long long)__double_as_longlong(qn[0]));
+        if (qx[0] > 0.0) atomicMax(&a[2], (unsigned long long)__double_as_longlong(qx[0]));
+      }
+      __syncthreads();
+      for (int i = threadIdx.x; i <= q1 - q0; i += blockDim.x) {
+        const int q = q0 + i;
+        atomicMax(&acc[3 * q], s_acc[3 * i]);
+        if (s_acc[3 * i + 1] != (unsigned long long)__double_as_longlong(INFINITY))
+          atomicMin(&acc[3 * q + 1], s_acc[3 * i + 1]);
+        if (s_acc[3 * i + 2] != 0ull) atomicMax(&acc[3 * q + 2], s_acc[3 * i + 2]);
+      }
+      __syncthreads();
+    }
+    return;
+  }
+  for (int it = blockIdx.x * blockDim.x + threadIdx.x; it < items; it += gridDim.x * blockDim.x) {
     int c = 0;
-    while (c + 1 < H.nchains && chains[(c + 1) * kChainInts + C_PBASE] <= t) ++c;
-    const int* cr = chains + c * kChainInts;
-    const uint32_t u = (uint32_t)(t - cr[C_PBASE]);
-    uint32_t pm = (uint32_t)cr[C_PMASK], mu = 0;
+    while (c + 1 < nch && chains[(c + 1) * kChainInts + C_PBASE] <= it) ++c;
+    const uint32_t u = (uint32_t)(it - chains[c * kChainInts + C_PBASE]);
+    uint32_t pm = (uint32_t)chains[c * kChainInts + C_PMASK], mask = 0;
     for (int j = 0; pm; ++j) {  // deposit bit j of u at the j-th lowest bit of C_PMASK
       const uint32_t low = pm & (0u - pm);
-      if (u >> j & 1u) mu |= low;
+      if (u >> j & 1u) mask |= low;
       pm ^= low;
     }
-    const uint32_t mm[1] = {mu};
-    double el[1] = {-INFINITY}, qn[1] = {INFINITY}, qx[1] = {-INFINITY};
-    for (int l = lane; l < H.S; l += 64)
-      score_chain<false, 1>(chains, nest, c, P + (size_t)l * H.npairs * 3, srec + (size_t)l * H.nslots * 3,
-                            headV + (size_t)l * H.nchains * 3, (const double*)nullptr, (const TargetRec*)nullptr, 0,
-                            zrec + (size_t)l * H.nz, mm, el, qn, qx);
-    double e = el[0], a = qn[0], b = qx[0];
-    for (int o = 32; o > 0; o >>= 1) {
-      e = fmax(e, __shfl_xor(e, o, 64));
-      a = fmin(a, __shfl_xor(a, o, 64));
-      b = fmax(b, __shfl_xor(b, o, 64));
-    }
-    if (lane == 0) {
-      PatScore r;
-      r.e = e;
-      r.qmin = a;
-      r.qmax = b;
-      pat[t] = r;
-    }
+    const uint32_t mm[1] = {mask};
+    double el[1] = {0.0}, qn[1] = {INFINITY}, qx[1] = {0.0};
+    score_chain<true, 1>(chains, nest, c, sP, sS, sH, (const double*)nullptr, sZ, zst, zrec + (size_t)l * H.nz, mm,
+                         el, qn, qx);
+    atomicMax(&acc[3 * it], (unsigned long long)__double_as_longlong(el[0]));
+    if (qn[0] < INFINITY) atomicMin(&acc[3 * it + 1], (unsigned long long)__double_as_longlong(qn[0]));
+    if (qx[0] > 0.0) atomicMax(&acc[3 * it + 2], (unsigned long long)__double_as_longlong(qx[0]));
+  }
+}
+
+// Scores of a short mask list from its accumulators.
+__global__ void k_list_finish(const int* __restrict__ count, const unsigned long long* __restrict__ acc, int cap,
+                              SelParams sp, MaskScore* __restrict__ out) {
+  const int n = min(*count, cap);
+  for (int q = blockIdx.x * blockDim.x + threadIdx.x; q < n; q += gridDim.x * blockDim.x) {
+    MaskScore r;
+    r.e = __longlong_as_double((long long)acc[3 * q]);
+    r.slack = band_slack(__longlong_as_double((long long)acc[3 * q + 1]),
+                         __longlong_as_double((long long)acc[3 * q + 2]), sp.vmin, sp.vmax);
+    out[q] = r;
   }
 }
 
 // Every mask's score from the pattern table (one thread per mask): the
 // largest constant error and each chain's entry for the mask's bits, then
-// the band slack; per-mask scores and 64-mask tile records as the FP64
+// the band slack; per-mask scores and 64-mask tile records as the per-mask
 // scoring kernel writes them.
+constexpr int kPatLds = 1024;  // pattern-table entries staged in LDS
+
 __global__ __launch_bounds__(256) void k_fac_combine(const SegHdr* __restrict__ hdrs, const int* __restrict__ segs,
                                                      size_t lstride, const int* __restrict__ tab,
-                                                     const PatScore* __restrict__ pat,
-                                                     const double* __restrict__ ecmax, SelParams sp,
+                                                     const unsigned long long* __restrict__ pat,
+                                                     const unsigned long long* __restrict__ ecmax, SelParams sp,
                                                      MaskScore* __restrict__ fin, TileRec* __restrict__ tiles) {
   __shared__ int s_pm[kMaxK], s_pb[kMaxK];
-  __shared__ PatScore s_pat[kPatLds];
+  __shared__ double s_pat[3 * kPatLds];
   const SegHdr H = hdrs[segs[blockIdx.z]];
   if (!H.valid) return;
   if ((uint64_t)blockIdx.x * blockDim.x >= ((uint64_t)1 << H.k)) return;  // past this segment's masks
@@ -321,12 +366,12 @@ __global__ __launch_bounds__(256) void k_fac_combine(const SegHdr* __restrict__ 
     s_pb[tid] = tab[H.o_chain + tid * kChainInts + C_PBASE];
   }
   const int np = min(H.npat, kPatLds);
-  for (int i = tid; i < np; i += blockDim.x) s_pat[i] = pat[i];
+  for (int i = tid; i < 3 * np; i += blockDim.x) s_pat[i] = __longlong_as_double((long long)pat[i]);
   __syncthreads();
   const uint32_t nmask = 1u << H.k;
   const uint32_t m = blockIdx.x * blockDim.x + tid;
   const bool valid = m < nmask;
-  double e = *ecmax, qn = INFINITY, qx = -INFINITY;
+  double e = __longlong_as_double((long long)*ecmax), qn = INFINITY, qx = 0.0;
   for (int c = 0; c < nch; ++c) {
     uint32_t pm = (uint32_t)__builtin_amdgcn_readfirstlane(s_pm[c]);
     const int pb = __builtin_amdgcn_readfirstlane(s_pb[c]);
@@ -341,10 +386,19 @@ __global__ __launch_bounds__(256) void k_fac_combine(const SegHdr* __restrict__ 
       pm &= ~(ones << b);
     }
     const int idx = pb + (int)u;
-    const PatScore r = idx < kPatLds ? s_pat[idx] : pat[idx];
-    e = fmax(e, r.e);
-    qn = fmin(qn, r.qmin);
-    qx = fmax(qx, r.qmax);
+    double pe, pn, px;
+    if (idx < kPatLds) {
+      pe = s_pat[3 * idx];
+      pn = s_pat[3 * idx + 1];
+      px = s_pat[3 * idx + 2];
+    } else {
+      pe = __longlong_as_double((long long)pat[3 * idx]);
+      pn = __longlong_as_double((long long)pat[3 * idx + 1]);
+      px = __longlong_as_double((long long)pat[3 * idx + 2]);
+    }
+    e = fmax(e, pe);
+    qn = fmin(qn, pn);
+    qx = fmax(qx, px);
   }
   MaskScore r;
   r.e = e;

@@ -469,6 +469,44 @@ __global__ __launch_bounds__(256) void k_surr_stage(const SegHdr* __restrict__ h
 // a radix select of the K-th key, a radix select over the mask indices of
 // the masks holding that key, then one collection pass (list order is not
 // meaningful; its content is).  One block.
+// Radix-select step, run by the first wave: the digit d holding the need-th
+// smallest element of a 256-bin histogram, the count below it and its own
+// count (lane l scans bins 4l..4l+3; a wave prefix sum and a ballot find d).
+__device__ __forceinline__ void select_digit(const int* hist, int need, int& d, int& below, int& cnt) {
+  const int lane = threadIdx.x & 63;
+  const int h0 = hist[4 * lane], h1 = hist[4 * lane + 1], h2 = hist[4 * lane + 2], h3 = hist[4 * lane + 3];
+  const int own = h0 + h1 + h2 + h3;
+  int incl = own;
+  for (int o = 1; o < 64; o <<= 1) {
+    const int v = __shfl_up(incl, o, 64);
+    if (lane >= o) incl += v;
+  }
+  const uint64_t hit = __ballot(incl >= need);
+  const int src = hit ? __ffsll((unsigned long long)hit) - 1 : 63;
+  int base = __shfl(incl - own, src, 64);
+  const int c0 = __shfl(h0, src, 64), c1 = __shfl(h1, src, 64), c2 = __shfl(h2, src, 64),
+            c3 = __shfl(h3, src, 64);
+  int j = 0, c = c0;
+  if (base + c0 < need) {
+    base += c0;
+    j = 1;
+    c = c1;
+    if (base + c1 < need) {
+      base += c1;
+      j = 2;
+      c = c2;
+      if (base + c2 < need) {
+        base += c2;
+        j = 3;
+        c = c3;
+      }
+    }
+  }
+  d = 4 * src + j;
+  below = base;
+  cnt = c;
+}
+
 __global__ __launch_bounds__(1024) void k_topk(const SegHdr* __restrict__ hdrs, int g,
                                                const uint32_t* __restrict__ keys,
                                                const uint32_t* __restrict__ masks, int n, int topk,
@@ -498,16 +536,15 @@ __global__ __launch_bounds__(1024) void k_topk(const SegHdr* __restrict__ hdrs, 
       if ((key & mb) == pre) atomicAdd(&hist[(key >> shift) & 255u], 1);
     }
     __syncthreads();
-    if (threadIdx.x == 0) {
-      int need = s_need, cum = 0, d = 0;
-      for (d = 0; d < 256; ++d) {
-        if (cum + hist[d] >= need) break;
-        cum += hist[d];
+    if (threadIdx.x < 64) {
+      int d, below, cnt;
+      select_digit(hist, s_need, d, below, cnt);
+      if (threadIdx.x == 0) {
+        s_need -= below;
+        s_prefix = pre | ((uint32_t)d << shift);
+        s_maskbits = mb | (255u << shift);
+        if (shift == 0) s_eq = cnt;  // masks holding T
       }
-      s_need = need - cum;
-      s_prefix = pre | ((uint32_t)d << shift);
-      s_maskbits = mb | (255u << shift);
-      if (shift == 0) s_eq = hist[d];  // masks holding T
     }
     __syncthreads();
   }
@@ -525,15 +562,14 @@ __global__ __launch_bounds__(1024) void k_topk(const SegHdr* __restrict__ hdrs, 
         if (keys[i] == T && (m & mb) == pre) atomicAdd(&hist[(m >> shift) & 255u], 1);
       }
       __syncthreads();
-      if (threadIdx.x == 0) {
-        int need = s_need, cum = 0, d = 0;
-        for (d = 0; d < 256; ++d) {
-          if (cum + hist[d] >= need) break;
-          cum += hist[d];
+      if (threadIdx.x < 64) {
+        int d, below, cnt;
+        select_digit(hist, s_need, d, below, cnt);
+        if (threadIdx.x == 0) {
+          s_need -= below;
+          s_mprefix = pre | ((uint32_t)d << shift);
+          s_mmaskbits = mb | (255u << shift);
         }
-        s_need = need - cum;
-        s_mprefix = pre | ((uint32_t)d << shift);
-        s_mmaskbits = mb | (255u << shift);
       }
       __syncthreads();
     }
@@ -597,10 +633,11 @@ __global__ __launch_bounds__(1024) void k_surr_decide(const SegHdr* __restrict__
   }
   pick = block_reduce(pick, [](unsigned a, unsigned b) { return min(a, b); }, shu);
   amb = block_reduce(amb, [](int a, int b) { return a | b; }, shi);
+  for (int q = threadIdx.x; q < n; q += blockDim.x)  // masks in the list are distinct
+    if (list[q] == pick) shd[0] = sc[q].e;
+  __syncthreads();
   if (threadIdx.x == 0) {
-    double epick = 0.0;
-    for (int q = 0; q < n; ++q)
-      if (list[q] == pick) epick = sc[q].e;
+    const double epick = shd[0];
     DevDecision d;
     d.mask = pick;
     d.popcount = best;
