@@ -1,10 +1,13 @@
 """Build step of the HIP library (gfx950): hipcc -> libokr.so in this package.
 
 Each source is compiled to an object of its own (in parallel), then linked.
-The candidate-scoring unit is compiled with NaNs excluded and the IEEE mode
-bit off: its max/min reductions then need no NaN canonicalisation, and no
-value it handles is a NaN.  Every other unit keeps IEEE semantics (the load
-flow detects divergence through NaN-safe comparisons).
+The candidate-scoring unit is compiled with NaNs excluded: its max/min
+reductions then need no NaN canonicalisation, and no value it handles is a
+NaN.  (The IEEE mode bit stays on: turning it off makes the device library's
+work-item and work-group id functions non-inlinable, and block indices
+then reach the kernels as per-lane values, which turns every wave-uniform
+table read into a per-lane vector load.)  Every other unit keeps IEEE
+semantics (the load flow detects divergence through NaN-safe comparisons).
 """
 import os
 import subprocess
@@ -21,7 +24,7 @@ FLAGS = [
     # no packed-FP32 instructions anywhere in the device code
     "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
 ]
-EXTRA = {"okr_score.hip": ["-fno-honor-nans", "-mno-amdgpu-ieee"]}
+EXTRA = {"okr_score.hip": ["-fno-honor-nans"]}
 
 
 def build() -> str:

@@ -184,7 +184,7 @@ __device__ __forceinline__ void sqrt_nr_v(const double (&x)[M], double (&y)[M]) 
 // snapshot fastest: P[(pair * 3 + p) * M + j], T[(slot * 3 + p) * M + j],
 // H and Hm [(chain * 3 + p) * M + j].
 template <bool ERR, int M>
-__device__ __forceinline__ void walk_chain_sv(const int* __restrict__ cr, const double2* Ps, const TargetRec* Ts,
+__device__ __forceinline__ void walk_chain_sv(const cint* cr, const double2* Ps, const TargetRec* Ts,
                                               const double2* Hs, const double* Hm, int c, uint32_t m,
                                               double2 (&B)[M][3], double (&el)[M], double (&qmin)[M],
                                               double (&qmax)[M]) {
@@ -281,12 +281,12 @@ __device__ __forceinline__ void walk_chain_sv(const int* __restrict__ cr, const 
 // zcap from the LDS stage Zs[q * M + j], the rest from global memory, where
 // snapshot j's records start at zg[j]).
 template <int M>
-__device__ __forceinline__ void score_chain_sv(const int* __restrict__ chains, const int* __restrict__ nest, int c,
+__device__ __forceinline__ void score_chain_sv(const cint* chains, const cint* nest, int c,
                                                const double2* Ps, const TargetRec* Ts, const double2* Hs,
                                                const double* Hm, const TargetRec* Zs, int zcap,
                                                const TargetRec* const (&zg)[M], uint32_t m, double (&el)[M],
                                                double (&qmin)[M], double (&qmax)[M]) {
-  const int* cr = chains + c * kChainInts;
+  const cint* cr = chains + c * kChainInts;
   double2 B[M][3];
 #pragma unroll
   for (int j = 0; j < M; ++j)
@@ -304,7 +304,9 @@ __device__ __forceinline__ void score_chain_sv(const int* __restrict__ chains, c
       double q2[M], mag[M], lo[M], hi[M];
 #pragma unroll
       for (int j = 0; j < M; ++j) {
-        const TargetRec t = q < zcap ? Zs[q * M + j] : zg[j][q];
+        TargetRec t;
+        if (q < zcap) t = Zs[q * M + j];
+        else t = zg[j][q];
         const double vx = t.W.x + B[j][p].x, vy = t.W.y + B[j][p].y;
         q2[j] = fma(vx, vx, vy * vy);
         lo[j] = t.lo;

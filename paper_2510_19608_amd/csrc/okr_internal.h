@@ -43,6 +43,23 @@ __device__ __forceinline__ T* lane_ptr(T* p, size_t lstride) {
   return p ? (T*)((char*)p + (size_t)blockIdx.z * lstride) : p;
 }
 
+// Read-only int tables (segment structure) in the constant address space:
+// kernels never write them while reading, so wave-uniform reads compile to
+// scalar loads through the scalar cache instead of per-lane vector loads.
+typedef __attribute__((address_space(4))) const int cint;
+__device__ __forceinline__ const cint* as_cint(const int* p) { return (const cint*)p; }
+// The header of the segment at chunk position blockIdx.z, by scalar loads
+// (only for kernels that do not write headers or segment ids).
+__device__ __forceinline__ SegHdr load_hdr(const SegHdr* hdrs, const int* segs) {
+  const int g = *as_cint(segs + blockIdx.z);
+  const cint* src = as_cint((const int*)(hdrs + g));
+  SegHdr H;
+  int* dst = (int*)&H;
+#pragma unroll
+  for (int q = 0; q < (int)(sizeof(SegHdr) / sizeof(int)); ++q) dst[q] = src[q];
+  return H;
+}
+
 // Static topology on the device.
 struct Topo {
   int n;

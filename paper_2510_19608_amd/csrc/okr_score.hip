@@ -55,8 +55,8 @@ __global__ __launch_bounds__(kScoreThreads) void k_score_fp64(
     TileRec* __restrict__ tiles, int* __restrict__ tickets, const int* __restrict__ gates) {
   extern __shared__ __align__(16) unsigned char sv_lds[];
   __shared__ int ticket;
-  const int g = segs[blockIdx.z];
-  const SegHdr H = hdrs[g];
+  const int g = *as_cint(segs + blockIdx.z);
+  const SegHdr H = load_hdr(hdrs, segs);
   if (!H.valid || (gates && gates[g] == 0)) return;
   // blocks past this segment's masks (a chunk's launch covers its largest segment)
   const uint32_t nmask = 1u << H.k;
@@ -83,8 +83,8 @@ __global__ __launch_bounds__(kScoreThreads) void k_score_fp64(
   const int sg = blockIdx.y;
   const int l0 = sg * snaps_per_group;
   const int l1 = min(H.S, l0 + snaps_per_group);
-  const int* chains = tab + H.o_chain;
-  const int* nest = tab + H.o_nest;
+  const cint* chains = as_cint(tab + H.o_chain);
+  const cint* nest = as_cint(tab + H.o_nest);
   const int zst = min(H.nz, zcap);
   const int cP = H.npairs * 3, cT = H.nslots * 6, cH = H.nchains * 3, cZ = zst * 2;
   const int tot = cP + cT + cH + cZ;
