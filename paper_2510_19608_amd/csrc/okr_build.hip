@@ -422,7 +422,7 @@ __global__ __launch_bounds__(256) void k_build_values(const SegHdr* __restrict__
                                                       const double2* __restrict__ A, double2* __restrict__ P,
                                                       TargetRec* __restrict__ srec, double2* __restrict__ headV,
                                                       TargetRec* __restrict__ zrec, double* __restrict__ econst) {
-  const SegHdr H = hdrs[segs[blockIdx.z]];
+  const SegHdr H = load_hdr(hdrs, segs);
   if (!H.valid) return;
   tab = lane_ptr(tab, lstride);
   P = lane_ptr(P, lstride);
@@ -495,7 +495,7 @@ __global__ __launch_bounds__(256) void k_build_members(const SegHdr* __restrict_
                                                        const double* __restrict__ absV, TargetRec* __restrict__ srec,
                                                        TargetRec* __restrict__ zrec, double* __restrict__ econst) {
   const int g = segs[blockIdx.z];
-  const SegHdr H = hdrs[g];
+  const SegHdr H = load_hdr_g(hdrs, g);
   if (!H.valid) return;
   tab = lane_ptr(tab, lstride);
   srec = lane_ptr(srec, lstride);

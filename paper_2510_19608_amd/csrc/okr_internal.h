@@ -50,14 +50,16 @@ typedef __attribute__((address_space(4))) const int cint;
 __device__ __forceinline__ const cint* as_cint(const int* p) { return (const cint*)p; }
 // The header of the segment at chunk position blockIdx.z, by scalar loads
 // (only for kernels that do not write headers or segment ids).
-__device__ __forceinline__ SegHdr load_hdr(const SegHdr* hdrs, const int* segs) {
-  const int g = *as_cint(segs + blockIdx.z);
+__device__ __forceinline__ SegHdr load_hdr_g(const SegHdr* hdrs, int g) {
   const cint* src = as_cint((const int*)(hdrs + g));
   SegHdr H;
   int* dst = (int*)&H;
 #pragma unroll
   for (int q = 0; q < (int)(sizeof(SegHdr) / sizeof(int)); ++q) dst[q] = src[q];
   return H;
+}
+__device__ __forceinline__ SegHdr load_hdr(const SegHdr* hdrs, const int* segs) {
+  return load_hdr_g(hdrs, *as_cint(segs + blockIdx.z));
 }
 
 // Static topology on the device.

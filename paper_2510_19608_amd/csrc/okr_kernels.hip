@@ -250,7 +250,7 @@ __global__ __launch_bounds__(1024) void k_argmin(const SegHdr* __restrict__ hdrs
   __shared__ int ncand;
   __shared__ int cand[1024];
   const int g = segs[blockIdx.z];
-  const SegHdr H = hdrs[g];
+  const SegHdr H = load_hdr_g(hdrs, g);
   if (gates && gates[g] == 0) return;  // decided without the full enumeration
   fin = lane_ptr(fin, lstride);
   tiles = lane_ptr(tiles, lstride);
@@ -335,7 +335,7 @@ __global__ __launch_bounds__(64) void k_apply(const SegHdr* __restrict__ hdrs, c
                                               double2* __restrict__ A) {
   __shared__ double2 Bs[kMaxK * 3];
   const int g = segs[blockIdx.z];
-  const SegHdr H = hdrs[g];
+  const SegHdr H = load_hdr_g(hdrs, g);
   if (!H.valid) return;
   tab = lane_ptr(tab, lstride);
   P = lane_ptr(P, lstride);

@@ -32,7 +32,7 @@ __global__ __launch_bounds__(256) void k_build_mixed(const SegHdr* __restrict__ 
                                                      const TargetRec* __restrict__ zrec, double vmin, double vmax,
                                                      Pair32* __restrict__ P32, Rec32* __restrict__ S32,
                                                      Head32* __restrict__ H32, Rec32* __restrict__ Z32) {
-  const SegHdr H = hdrs[g];
+  const SegHdr H = load_hdr_g(hdrs, g);
   if (!H.valid) return;
   const int part = blockIdx.y, S = H.S;
   const int stride = gridDim.x * blockDim.x;
@@ -115,7 +115,7 @@ __global__ __launch_bounds__(1024) void k_mixed_select_a(const SegHdr* __restric
                                                          uint32_t* __restrict__ listA, int* __restrict__ countA) {
   __shared__ int shi[16];
   __shared__ int cnt;
-  const SegHdr H = hdrs[g];
+  const SegHdr H = load_hdr_g(hdrs, g);
   if (threadIdx.x == 0) cnt = 0;
   if (skip_segment(H, status)) {
     if (threadIdx.x == 0) { *countA = 0; ms[g].lo_level = -1; ms[g].hi_level = -1; }
@@ -163,7 +163,7 @@ __global__ __launch_bounds__(1024) void k_mixed_select_b(const SegHdr* __restric
   __shared__ int shi[16];
   __shared__ double shd[16];
   __shared__ int cnt;
-  const SegHdr H = hdrs[g];
+  const SegHdr H = load_hdr_g(hdrs, g);
   if (threadIdx.x == 0) cnt = 0;
   if (skip_segment(H, status)) {
     if (threadIdx.x == 0) { *countB = 0; ms[g].best = -1; }
@@ -229,7 +229,7 @@ __global__ __launch_bounds__(1024) void k_mixed_final(const SegHdr* __restrict__
   __shared__ double shd[16];
   __shared__ int shi[16];
   __shared__ unsigned shu[16];
-  const SegHdr H = hdrs[g];
+  const SegHdr H = load_hdr_g(hdrs, g);
   DevDecision* dec = decs + g;
   const int best = ms[g].best;
   if (skip_segment(H, status) || best < 0) {

@@ -201,7 +201,7 @@ __device__ __forceinline__ int terms_count(int mode, const SegHdr& H, const int*
 __global__ void k_terms_init(const SegHdr* __restrict__ hdrs, const int* __restrict__ segs, size_t lstride, int mode,
                              const int* __restrict__ count, int cap, const double* __restrict__ econst,
                              unsigned long long* __restrict__ acc, unsigned long long* __restrict__ ecmax) {
-  const SegHdr H = hdrs[segs[blockIdx.z]];
+  const SegHdr H = load_hdr(hdrs, segs);
   if (!H.valid) return;
   count = lane_ptr(count, lstride);
   econst = lane_ptr(econst, lstride);
@@ -226,7 +226,7 @@ __global__ __launch_bounds__(kTermsBlock) void k_chain_terms(
     const uint32_t* __restrict__ list, const int* __restrict__ count, int cap, int icap, int zcap,
     unsigned long long* __restrict__ acc, unsigned long long* __restrict__ ecmax) {
   extern __shared__ __align__(16) unsigned char ct_lds[];
-  const SegHdr H = hdrs[segs[blockIdx.z]];
+  const SegHdr H = load_hdr(hdrs, segs);
   if (!H.valid) return;
   tab = lane_ptr(tab, lstride);
   P = lane_ptr(P, lstride);
@@ -351,7 +351,7 @@ __global__ __launch_bounds__(256) void k_fac_combine(const SegHdr* __restrict__ 
                                                      MaskScore* __restrict__ fin, TileRec* __restrict__ tiles) {
   __shared__ int s_pm[kMaxK], s_pb[kMaxK];
   __shared__ double s_pat[3 * kPatLds];
-  const SegHdr H = hdrs[segs[blockIdx.z]];
+  const SegHdr H = load_hdr(hdrs, segs);
   if (!H.valid) return;
   if ((uint64_t)blockIdx.x * blockDim.x >= ((uint64_t)1 << H.k)) return;  // past this segment's masks
   tab = lane_ptr(tab, lstride);
@@ -506,7 +506,7 @@ __global__ __launch_bounds__(kScoreThreads) void k_score_fp32(
   __shared__ Rec32 Zs[kZoneLds];
   __shared__ double s_ec;
   __shared__ int ticket;
-  const SegHdr H = hdrs[g];
+  const SegHdr H = load_hdr_g(hdrs, g);
   if (!H.valid) return;
   const int tid = threadIdx.x;
   uint32_t m[M];

@@ -27,7 +27,7 @@ __global__ __launch_bounds__(64) void k_surr_tables(const SegHdr* __restrict__ h
                                                     const double2* __restrict__ A,
                                                     const TargetRec* __restrict__ srec, float* __restrict__ pz,
                                                     float* __restrict__ zs, SurrSlot* __restrict__ ss) {
-  const SegHdr H = hdrs[g];
+  const SegHdr H = load_hdr_g(hdrs, g);
   if (!H.valid) return;
   const int t = blockIdx.x, lane = threadIdx.x;
   if (t < H.npairs) {
@@ -85,7 +85,7 @@ __global__ void k_surr_features(const SegHdr* __restrict__ hdrs, int g, const in
                                 const SurrSlot* __restrict__ ss, const double* __restrict__ econst,
                                 const uint32_t* __restrict__ masks, int n, int Mp, float* __restrict__ Xf,
                                 __bf16* __restrict__ Xb, const int* __restrict__ flag, int skip_if) {
-  const SegHdr H = hdrs[g];
+  const SegHdr H = load_hdr_g(hdrs, g);
   if (!H.valid || (flag && *flag == skip_if)) return;
   const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= (uint32_t)Mp) return;
@@ -197,7 +197,7 @@ __global__ void k_level_masks(int k, int L1, int N1, int M1, uint32_t* __restric
 // Training target of every mask from the FP64 scores: y = ln(e + 1e-12).
 __global__ void k_surr_target(const SegHdr* __restrict__ hdrs, int g, const MaskScore* __restrict__ fin,
                               float* __restrict__ t) {
-  const SegHdr H = hdrs[g];
+  const SegHdr H = load_hdr_g(hdrs, g);
   const uint32_t m = blockIdx.x * blockDim.x + threadIdx.x;
   if (!H.valid || m >= (1u << H.k)) return;
   t[m] = (float)log(fin[m].e + 1e-12);
@@ -441,7 +441,7 @@ __device__ __forceinline__ uint32_t ordered(float y) {
 __global__ void k_surr_keys(const SegHdr* __restrict__ hdrs, int g, const float* __restrict__ y, float ln_ebar,
                             const uint32_t* __restrict__ masks, int n, uint32_t* __restrict__ keys,
                             const int* __restrict__ flag, int skip_if) {
-  const SegHdr H = hdrs[g];
+  const SegHdr H = load_hdr_g(hdrs, g);
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
   if (!H.valid || i >= n || (flag && *flag == skip_if)) return;
   const uint32_t m = masks ? masks[i] : (uint32_t)i;
@@ -457,7 +457,7 @@ __global__ __launch_bounds__(256) void k_surr_stage(const SegHdr* __restrict__ h
                                                     const uint32_t* __restrict__ keys, int n, int K,
                                                     int* __restrict__ flag) {
   __shared__ int shi[4];
-  const SegHdr H = hdrs[g];
+  const SegHdr H = load_hdr_g(hdrs, g);
   int c = 0;
   if (H.valid)
     for (int i = threadIdx.x; i < n; i += blockDim.x) c += (keys[i] >> 31) == 0u;
@@ -517,7 +517,7 @@ __global__ __launch_bounds__(1024) void k_topk(const SegHdr* __restrict__ hdrs, 
   __shared__ uint32_t s_prefix, s_maskbits, s_mprefix, s_mmaskbits;
   __shared__ int s_need, s_eq, s_n;
   if (flag && *flag == skip_if) return;
-  const SegHdr H = hdrs[g];
+  const SegHdr H = load_hdr_g(hdrs, g);
   if (!H.valid || (*status & (16 | 32))) {
     if (threadIdx.x == 0) *count = 0;
     return;
@@ -602,7 +602,7 @@ __global__ __launch_bounds__(1024) void k_surr_decide(const SegHdr* __restrict__
   __shared__ double shd[16];
   __shared__ int shi[16];
   __shared__ unsigned shu[16];
-  const SegHdr H = hdrs[g];
+  const SegHdr H = load_hdr_g(hdrs, g);
   if (!H.valid || (*status & (16 | 32))) {
     if (threadIdx.x == 0) *gate = 1;  // let the full path write its (null) decision
     return;
