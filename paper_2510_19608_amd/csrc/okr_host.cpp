@@ -40,6 +40,9 @@ __global__ void k_chain_terms(const SegHdr*, const int*, size_t, int, const int*
                               const double2*, const TargetRec*, const double*, const uint32_t*, const int*, int, int,
                               int, unsigned long long*, unsigned long long*);
 __global__ void k_list_finish(const int*, const unsigned long long*, int, SelParams, MaskScore*);
+__global__ void k_surr_rank(const SegHdr*, int, const int*, const float*, const float*, const SurrSlot*, const double*,
+                            const uint32_t*, int, const __bf16*, const __bf16*, const float*, float, uint32_t*,
+                            const int*, int);
 __global__ void k_fac_combine(const SegHdr*, const int*, size_t, const int*, const unsigned long long*,
                               const unsigned long long*, SelParams, MaskScore*, TileRec*);
 __global__ void k_argmin(const SegHdr*, const int*, size_t, const MaskScore*, const TileRec*, SelParams, const int*,
@@ -85,8 +88,6 @@ __global__ void k_copy_cols(const float*, int, float*, int, int);
 __global__ void k_sum_splits(const float*, int, int, float*);
 __global__ void k_adam(float*, const float*, float*, float*, int, float, float, float);
 __global__ void k_refresh_weights(const float*, __bf16*, __bf16*, __bf16*);
-__global__ void k_surr_keys(const SegHdr*, int, const float*, float, const uint32_t*, int, uint32_t*, const int*,
-                            int);
 __global__ void k_topk(const SegHdr*, int, const uint32_t*, const uint32_t*, int, int, const int*, uint32_t*, int*,
                        const int*, int);
 __global__ void k_surr_decide(const SegHdr*, int, SelParams, const int*, const uint32_t*, const int*,
@@ -127,7 +128,7 @@ struct Layout {
   // mixed precision
   size_t P32, S32, H32, Z32, part32, fin32, tiles32, listA, listB, scoreA, scoreB, counts, mstate;
   // surrogate: feature tables (always), ranking buffers (when planned with top_k)
-  size_t spz, szs, sss, sXb, sH1b, spart, sy, skeys, slist, sscore, scount, sgates, sW1b, sW2b, sW2tb, slevel,
+  size_t spz, szs, sss, skeys, slist, sscore, scount, sgates, sW1b, sW2b, sW2tb, slevel,
       sstage;
   size_t lane0, lane_stride;  // per-lane scratch block (tab .. scount)
   size_t total;
@@ -561,10 +562,6 @@ extern "C" int okr_plan(okr_handle* h, const okr_topology* topo, const okr_margi
     L.szs = take(sizeof(float) * kMaxPairs);
     L.sss = take(sizeof(SurrSlot) * kMaxK);
     const size_t mp = h->topk ? std::max((size_t)64, (size_t)1 << h->kmax) : 0;
-    L.sXb = take(sizeof(uint16_t) * kSurrF * mp);
-    L.sH1b = take(sizeof(uint16_t) * kSurrH * mp);
-    L.spart = take(sizeof(float) * (kSurrH / 32) * mp);
-    L.sy = take(sizeof(float) * mp);
     L.skeys = take(sizeof(uint32_t) * mp);
     L.slevel = take(sizeof(uint32_t) * mp);
     L.slist = take(sizeof(uint32_t) * std::max(h->topk, 1));
@@ -621,9 +618,9 @@ struct Ptrs {
   MaskScore *scoreA, *scoreB;
   int* counts;
   MixedState* mstate;
-  float *spz, *szs, *spart, *sy;
+  float *spz, *szs;
   SurrSlot* sss;
-  __bf16 *sXb, *sH1b, *sW1b, *sW2b, *sW2tb;
+  __bf16 *sW1b, *sW2b, *sW2tb;
   uint32_t *skeys, *slist, *slevel;
   MaskScore* sscore;
   int *scount, *sgates, *sstage;
@@ -704,10 +701,6 @@ Ptrs pointers(okr_handle* h, void* d_workspace, int lane = 0) {
   p.spz = (float*)at(L.spz);
   p.szs = (float*)at(L.szs);
   p.sss = (SurrSlot*)at(L.sss);
-  p.sXb = (__bf16*)at(L.sXb);
-  p.sH1b = (__bf16*)at(L.sH1b);
-  p.spart = (float*)at(L.spart);
-  p.sy = (float*)at(L.sy);
   p.skeys = (uint32_t*)at(L.skeys);
   p.slist = (uint32_t*)at(L.slist);
   p.sscore = (MaskScore*)at(L.sscore);
@@ -846,22 +839,10 @@ void enqueue_search(okr_handle* h, void* ws, const okr_yblocks* Y, const okr_loa
       const bool staged = N1 < nm;
       int* stage = w.sstage + g;
       auto rank = [&](const uint32_t* masks, int nrow, const int* flag, int skip_if) {
-        const int Mp = std::max(64, (nrow + 63) / 64 * 64);
-        hipLaunchKernelGGL(k_surr_features, dim3((Mp + 255) / 256), dim3(256), 0, st, (const SegHdr*)w.hdrs, g,
+        hipLaunchKernelGGL(k_surr_rank, dim3((nrow + 63) / 64), dim3(256), 0, st, (const SegHdr*)w.hdrs, g,
                            (const int*)w.tab, (const float*)w.spz, (const float*)w.szs, (const SurrSlot*)w.sss,
-                           (const double*)w.econst, masks, nrow, Mp, (float*)nullptr, w.sXb, flag, skip_if);
-        hipLaunchKernelGGL(k_gemm_nt<1>, dim3(kSurrH / 64, Mp / 64), dim3(256), 0, st, (const __bf16*)w.sXb, kSurrF,
-                           (const __bf16*)w.sW1b, kSurrF, kSurrF, (float*)nullptr, kSurrH, mg->surrogate + kOffB1,
-                           (float*)nullptr, w.sH1b, (__bf16*)nullptr, Mp, (const float*)nullptr, (float*)nullptr,
-                           flag, skip_if);
-        hipLaunchKernelGGL(k_gemm_nt<2>, dim3(kSurrH / 64, Mp / 64), dim3(256), 0, st, (const __bf16*)w.sH1b, kSurrH,
-                           (const __bf16*)w.sW2b, kSurrH, kSurrH, (float*)nullptr, kSurrH, mg->surrogate + kOffB2,
-                           (float*)nullptr, (__bf16*)nullptr, (__bf16*)nullptr, Mp, mg->surrogate + kOffW3, w.spart,
-                           flag, skip_if);
-        hipLaunchKernelGGL(k_rowdot_finish, dim3((Mp + 255) / 256), dim3(256), 0, st, (const float*)w.spart,
-                           kSurrH / 32, Mp, mg->surrogate + kOffB3, w.sy, flag, skip_if);
-        hipLaunchKernelGGL(k_surr_keys, dim3((nrow + 255) / 256), dim3(256), 0, st, (const SegHdr*)w.hdrs, g,
-                           (const float*)w.sy, ln_ebar, masks, nrow, w.skeys, flag, skip_if);
+                           (const double*)w.econst, masks, nrow, (const __bf16*)w.sW1b, (const __bf16*)w.sW2b,
+                           mg->surrogate, ln_ebar, w.skeys, flag, skip_if);
       };
       if (staged) {
         hipLaunchKernelGGL(k_level_masks, dim3(((int)N1 + 63) / 64 * 64 / 64), dim3(64), 0, st, k, L1, (int)N1,

@@ -79,7 +79,63 @@ __global__ __launch_bounds__(64) void k_surr_tables(const SegHdr* __restrict__ h
 
 // Features of mask m from a snapshot-free walk of the chains (the moved
 // currents' voltage rises, path impedance sums, load totals, phase counts,
-// run lengths, depth), scaled to O(1).  Rows m >= 2^k are zero padding.
+// run lengths, depth), scaled to O(1); ec = the largest constant error over
+// the snapshots.  Table pointers may point to global memory or to an LDS copy.
+__device__ __forceinline__ void surr_features(const SegHdr& H, const int* chains, const int* slots, const float* pz,
+                                              const float* zs, const SurrSlot* ss, double ec, uint32_t m,
+                                              float (&f)[kSurrF]) {
+  for (int q = 0; q < kSurrF; ++q) f[q] = 0.f;
+  float sum_pz = 0.f, max_pz = 0.f, sum_z = 0.f, sum_la = 0.f, max_sp = 0.f, sum_pos = 0.f;
+  int n1 = 0, n2 = 0, n3 = 0, maxrun = 0, touched = 0, pop = 0;
+  for (int c = 0; c < H.nchains; ++c) {
+    const int* cr = chains + c * kChainInts;
+    int sidx = 0, run = 0, tc = 0;
+    for (int r = 0; r < cr[C_NSLOT]; ++r) {
+      const int s = cr[C_SLOT0] + r;
+      const int* sr = slots + s * kSlotInts;
+      if ((m >> sr[SL_BIT]) & 1u) {
+        const int q = sr[SL_PAIRBASE] + sidx;
+        const SurrSlot o = ss[s];
+        sum_pz += pz[q];
+        max_pz = fmaxf(max_pz, pz[q]);
+        sum_z += zs[q];
+        sum_la += o.la;
+        max_sp = fmaxf(max_sp, o.spread);
+        sum_pos += (float)o.pos;
+        n1 += o.nph == 1;
+        n2 += o.nph == 2;
+        n3 += o.nph == 3;
+        ++pop;
+        maxrun = max(maxrun, ++run);
+        tc = 1;
+      } else {
+        sidx = r + 1;
+        run = 0;
+      }
+    }
+    touched += tc;
+  }
+  const float k = (float)H.k;
+  f[0] = pop / k;
+  f[1] = sum_pz * 1e3f;
+  f[2] = max_pz * 1e3f;
+  f[3] = sum_z * 1e2f;
+  f[4] = sum_la * 10.f;
+  f[5] = n1 / k;
+  f[6] = n2 / k;
+  f[7] = n3 / k;
+  f[8] = maxrun / k;
+  f[9] = touched / (float)H.nchains;
+  f[10] = sum_pos / k;
+  f[11] = max_sp * 1e3f;
+  f[12] = log10f(max_pz + 1e-9f) / 4.f;
+  f[13] = log10f(sum_pz + 1e-9f) / 4.f;
+  f[14] = (float)ec * 1e3f;
+  f[15] = k / 24.f;
+}
+
+// Features of every listed mask (or mask = row); rows >= n or masks >= 2^k
+// are zero padding.
 __global__ void k_surr_features(const SegHdr* __restrict__ hdrs, int g, const int* __restrict__ tab,
                                 const float* __restrict__ pz, const float* __restrict__ zs,
                                 const SurrSlot* __restrict__ ss, const double* __restrict__ econst,
@@ -93,57 +149,9 @@ __global__ void k_surr_features(const SegHdr* __restrict__ hdrs, int g, const in
   float f[kSurrF];
   for (int q = 0; q < kSurrF; ++q) f[q] = 0.f;
   if (i < (uint32_t)n && m < (1u << H.k)) {
-    const int* chains = tab + H.o_chain;
-    const int* slots = tab + H.o_slot;
-    float sum_pz = 0.f, max_pz = 0.f, sum_z = 0.f, sum_la = 0.f, max_sp = 0.f, sum_pos = 0.f;
-    int n1 = 0, n2 = 0, n3 = 0, maxrun = 0, touched = 0, pop = 0;
-    for (int c = 0; c < H.nchains; ++c) {
-      const int* cr = chains + c * kChainInts;
-      int sidx = 0, run = 0, tc = 0;
-      for (int r = 0; r < cr[C_NSLOT]; ++r) {
-        const int s = cr[C_SLOT0] + r;
-        const int* sr = slots + s * kSlotInts;
-        if ((m >> sr[SL_BIT]) & 1u) {
-          const int q = sr[SL_PAIRBASE] + sidx;
-          const SurrSlot o = ss[s];
-          sum_pz += pz[q];
-          max_pz = fmaxf(max_pz, pz[q]);
-          sum_z += zs[q];
-          sum_la += o.la;
-          max_sp = fmaxf(max_sp, o.spread);
-          sum_pos += (float)o.pos;
-          n1 += o.nph == 1;
-          n2 += o.nph == 2;
-          n3 += o.nph == 3;
-          ++pop;
-          maxrun = max(maxrun, ++run);
-          tc = 1;
-        } else {
-          sidx = r + 1;
-          run = 0;
-        }
-      }
-      touched += tc;
-    }
     double ec = 0.0;
     for (int l = 0; l < H.S; ++l) ec = fmax(ec, econst[l]);
-    const float k = (float)H.k;
-    f[0] = pop / k;
-    f[1] = sum_pz * 1e3f;
-    f[2] = max_pz * 1e3f;
-    f[3] = sum_z * 1e2f;
-    f[4] = sum_la * 10.f;
-    f[5] = n1 / k;
-    f[6] = n2 / k;
-    f[7] = n3 / k;
-    f[8] = maxrun / k;
-    f[9] = touched / (float)H.nchains;
-    f[10] = sum_pos / k;
-    f[11] = max_sp * 1e3f;
-    f[12] = log10f(max_pz + 1e-9f) / 4.f;
-    f[13] = log10f(sum_pz + 1e-9f) / 4.f;
-    f[14] = (float)ec * 1e3f;
-    f[15] = k / 24.f;
+    surr_features(H, tab + H.o_chain, tab + H.o_slot, pz, zs, ss, ec, m, f);
   }
   if (Xf)
     for (int q = 0; q < kSurrF; ++q) Xf[(size_t)i * kSurrF + q] = f[q];
@@ -438,17 +446,6 @@ __device__ __forceinline__ uint32_t ordered(float y) {
 
 // Rank key of every mask: predicted feasible first, then most reduced, then
 // smallest predicted error (26-bit monotone quantisation), ties by mask.
-__global__ void k_surr_keys(const SegHdr* __restrict__ hdrs, int g, const float* __restrict__ y, float ln_ebar,
-                            const uint32_t* __restrict__ masks, int n, uint32_t* __restrict__ keys,
-                            const int* __restrict__ flag, int skip_if) {
-  const SegHdr H = load_hdr_g(hdrs, g);
-  const int i = blockIdx.x * blockDim.x + threadIdx.x;
-  if (!H.valid || i >= n || (flag && *flag == skip_if)) return;
-  const uint32_t m = masks ? masks[i] : (uint32_t)i;
-  const uint32_t pf = y[i] <= ln_ebar ? 0u : 1u;
-  const uint32_t lvl = (uint32_t)(H.k - __popc(m)) & 31u;
-  keys[i] = (pf << 31) | (lvl << 26) | (ordered(y[i]) >> 6);
-}
 
 // Whether the first ranking stage (the top levels) holds at least K masks
 // predicted feasible: then the K best keys overall are among them, since
@@ -647,6 +644,125 @@ __global__ __launch_bounds__(1024) void k_surr_decide(const SegHdr* __restrict__
     d.found = 1;
     decs[g] = d;
     *gate = 0;
+  }
+}
+
+// ------------------------------------------------------- fused ranking --
+// Ranking keys of 64 masks per block (masks[row], or mask = row), with the
+// arithmetic of k_surr_features -> k_gemm_nt<1> -> k_gemm_nt<2> ->
+// k_rowdot_finish -> k_surr_keys: the segment's feature tables are staged in
+// LDS, the 64 feature rows, the first hidden layer (64 x 256, BF16) and the
+// per-row partial products stay on chip, and both layers run on MFMA in the
+// GEMM kernel's order (K in steps of 16, the same operand layouts), so the
+// keys equal the unfused path's.  4 waves: wave w owns row tile w & 1 and
+// column tiles 4 (w >> 1) .. 4 (w >> 1) + 3 of each layer.
+constexpr int kRankRows = 64;
+constexpr int kRankInts = kMaxK * kChainInts + kMaxK * kMaxK + kMaxK * kSlotInts;  // chains, nesting, slots
+// LDS: H1 [64][256 + 8] BF16; the feature tables and rows.
+constexpr int kRankH1 = kRankRows * (kSurrH + 8) * 2;
+constexpr int kRankU = kRankInts * 4 + 2 * kMaxPairs * 4 + kMaxK * (int)sizeof(SurrSlot) + kRankRows * (kSurrF + 8) * 2;
+
+__global__ __launch_bounds__(256) void k_surr_rank(const SegHdr* __restrict__ hdrs, int g,
+                                                   const int* __restrict__ tab, const float* __restrict__ pz,
+                                                   const float* __restrict__ zs, const SurrSlot* __restrict__ ss,
+                                                   const double* __restrict__ econst,
+                                                   const uint32_t* __restrict__ masks, int n,
+                                                   const __bf16* __restrict__ W1b, const __bf16* __restrict__ W2b,
+                                                   const float* __restrict__ params, float ln_ebar,
+                                                   uint32_t* __restrict__ keys, const int* __restrict__ flag,
+                                                   int skip_if) {
+  __shared__ __attribute__((aligned(16))) unsigned char lds_h1[kRankH1];
+  __shared__ __attribute__((aligned(16))) unsigned char lds_u[kRankU];
+  __shared__ float part[kSurrH / 32][kRankRows];
+  __shared__ double s_ec;
+  const SegHdr H = load_hdr_g(hdrs, g);
+  if (!H.valid || (flag && *flag == skip_if)) return;
+  const int i0 = blockIdx.x * kRankRows;
+  if (i0 >= n) return;
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  __bf16 (*H1)[kSurrH + 8] = (__bf16(*)[kSurrH + 8])lds_h1;
+  int* s_int = (int*)lds_u;
+  float* s_pz = (float*)(s_int + kRankInts);
+  float* s_zs = s_pz + kMaxPairs;
+  SurrSlot* s_ss = (SurrSlot*)(s_zs + kMaxPairs);
+  __bf16 (*X)[kSurrF + 8] = (__bf16(*)[kSurrF + 8])(s_ss + kMaxK);
+  // stage the feature tables (chains, nesting and slots: ints [0, o_pair))
+  const int nint = min(H.o_pair, kRankInts);
+  for (int q = tid; q < nint; q += blockDim.x) s_int[q] = tab[q];
+  for (int q = tid; q < H.npairs; q += blockDim.x) {
+    s_pz[q] = pz[q];
+    s_zs[q] = zs[q];
+  }
+  for (int q = tid; q < H.nslots; q += blockDim.x) s_ss[q] = ss[q];
+  if (wave == 0) {
+    double ec = 0.0;
+    for (int l = lane; l < H.S; l += 64) ec = fmax(ec, econst[l]);
+    for (int o = 32; o > 0; o >>= 1) ec = fmax(ec, __shfl_xor(ec, o, 64));
+    if (lane == 0) s_ec = ec;
+  }
+  __syncthreads();
+  if (tid < kRankRows) {
+    const int i = i0 + tid;
+    const uint32_t m = (masks && i < n) ? masks[i] : (uint32_t)i;
+    float f[kSurrF];
+    for (int q = 0; q < kSurrF; ++q) f[q] = 0.f;
+    if (i < n && m < (1u << H.k) && H.o_pair <= kRankInts)
+      surr_features(H, s_int + H.o_chain, s_int + H.o_slot, s_pz, s_zs, s_ss, s_ec, m, f);
+    for (int q = 0; q < kSurrF; ++q) X[tid][q] = (__bf16)f[q];
+  }
+  __syncthreads();
+  const int rt = wave & 1, ct0 = (wave >> 1) * 4;
+  const int arow = rt * 32 + (lane & 31), koff = 8 * (lane >> 5);
+  // layer 1: H1 = gelu(X W1^T + b1), K = 32
+  for (int ct = ct0; ct < ct0 + 4; ++ct) {
+    f32x16 acc;
+    for (int v = 0; v < 16; ++v) acc[v] = 0.f;
+    const int bcol = ct * 32 + (lane & 31);
+#pragma unroll
+    for (int kk = 0; kk < kSurrF; kk += 16) {
+      const bf16x8 a = *(const bf16x8*)&X[arow][kk + koff];
+      const bf16x8 b = *(const bf16x8*)&W1b[(size_t)bcol * kSurrF + kk + koff];
+      acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a, b, acc, 0, 0, 0);
+    }
+#pragma unroll
+    for (int v = 0; v < 16; ++v) {
+      const int row = rt * 32 + 8 * (v >> 2) + 4 * (lane >> 5) + (v & 3);
+      H1[row][bcol] = (__bf16)gelu_f(acc[v] + params[kOffB1 + bcol]);
+    }
+  }
+  __syncthreads();
+  // layer 2: gelu(H1 W2^T + b2) . w3, K = 256; per output tile all 16 W2
+  // fragments are fetched first (one round trip), then the 16 MFMAs
+  for (int ct = ct0; ct < ct0 + 4; ++ct) {
+    const int bcol = ct * 32 + (lane & 31);
+    bf16x8 bw[kSurrH / 16];
+#pragma unroll
+    for (int q = 0; q < kSurrH / 16; ++q) bw[q] = *(const bf16x8*)&W2b[(size_t)bcol * kSurrH + 16 * q + koff];
+    f32x16 acc;
+    for (int v = 0; v < 16; ++v) acc[v] = 0.f;
+#pragma unroll
+    for (int q = 0; q < kSurrH / 16; ++q) {
+      const bf16x8 a = *(const bf16x8*)&H1[arow][16 * q + koff];
+      acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a, bw[q], acc, 0, 0, 0);
+    }
+    const float bias = params[kOffB2 + bcol], w3 = params[kOffW3 + bcol];
+#pragma unroll
+    for (int v = 0; v < 16; ++v) {
+      float sdot = gelu_f(acc[v] + bias) * w3;
+      for (int o = 1; o < 32; o <<= 1) sdot += __shfl_xor(sdot, o, 64);
+      const int row = rt * 32 + 8 * (v >> 2) + 4 * (lane >> 5) + (v & 3);
+      if ((lane & 31) == 0) part[ct][row] = sdot;
+    }
+  }
+  __syncthreads();
+  if (tid < kRankRows && i0 + tid < n) {
+    const int i = i0 + tid;
+    float y = params[kOffB3];
+    for (int j = 0; j < kSurrH / 32; ++j) y += part[j][tid];
+    const uint32_t m = masks ? masks[i] : (uint32_t)i;
+    const uint32_t pf = y <= ln_ebar ? 0u : 1u;
+    const uint32_t lvl = (uint32_t)(H.k - __popc(m)) & 31u;
+    keys[i] = (pf << 31) | (lvl << 26) | (ordered(y) >> 6);
   }
 }
 
