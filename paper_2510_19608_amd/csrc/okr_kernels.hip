@@ -343,33 +343,40 @@ __global__ __launch_bounds__(64) void k_apply(const SegHdr* __restrict__ hdrs, c
   zrec = lane_ptr(zrec, lstride);
   const int n = T.n;
   const int l = blockIdx.x;
-  const uint32_t m = decs[g].mask;
-  const int* chains = tab + H.o_chain;
-  const int* slots = tab + H.o_slot;
+  const uint32_t m = *as_cint((const int*)&decs[g].mask);
+  const cint* chains = as_cint(tab + H.o_chain);
+  const cint* slots = as_cint(tab + H.o_slot);
   if (threadIdx.x < 3) {  // phases are independent: one thread each
     const int p = threadIdx.x;
     const double2* Pl = P + (size_t)l * H.npairs * 3;
     const TargetRec* srec_l = srec + (size_t)l * H.nslots * 3;
     for (int c = 0; c < H.nchains; ++c) {
-      const int* cr = chains + c * kChainInts;
+      const cint* cr = chains + c * kChainInts;
       const int outer = cr[C_OUTER];
       double2 S = outer >= 0 ? Bs[outer * 3 + p] : make_double2(0.0, 0.0);
-      int sidx = 0, supnode = cr[C_HEAD];
+      int sidx = 0;
+      // the current super-node's aggregated current, kept in a register
+      // while reduced slots add theirs (the same additions, in order)
+      size_t a = ((size_t)l * n + cr[C_HEAD]) * 3 + p;
+      double2 acc = A[a];
       const int ns = cr[C_NSLOT], s0 = cr[C_SLOT0];
       for (int r = 0; r < ns; ++r) {
-        const int* sr = slots + (s0 + r) * kSlotInts;
+        const cint* sr = slots + (s0 + r) * kSlotInts;
         const int node = sr[SL_NODE];
         if ((m >> sr[SL_BIT]) & 1u) {
           S = cadd(S, Pl[(sr[SL_PAIRBASE] + sidx) * 3 + p]);
-          const size_t a = ((size_t)l * n + supnode) * 3 + p, b = ((size_t)l * n + node) * 3 + p;
-          A[a] = cadd(A[a], A[b]);
+          const size_t b = ((size_t)l * n + node) * 3 + p;
+          acc = cadd(acc, A[b]);
           A[b] = make_double2(0.0, 0.0);
         } else {
           if (sr[SL_PHASE] >> p & 1) Vcur[((size_t)l * n + node) * 3 + p] = cadd(srec_l[(s0 + r) * 3 + p].W, S);
           sidx = r + 1;
-          supnode = node;
+          A[a] = acc;
+          a = ((size_t)l * n + node) * 3 + p;
+          acc = A[a];
         }
       }
+      A[a] = acc;
       Bs[c * 3 + p] = S;
     }
   }
@@ -381,12 +388,11 @@ __global__ __launch_bounds__(64) void k_apply(const SegHdr* __restrict__ hdrs, c
   }
   if (blockIdx.x != 0) return;
   __syncthreads();
-  if (threadIdx.x == 0)
-    for (int s = 0; s < H.nslots; ++s) {
-      const int* sr = slots + s * kSlotInts;
-      if ((m >> sr[SL_BIT]) & 1u) St.kept[sr[SL_NODE]] = 0;
-      St.slot_of[sr[SL_NODE]] = -1;
-    }
+  if (threadIdx.x < H.nslots) {
+    const cint* sr = slots + threadIdx.x * kSlotInts;
+    if ((m >> sr[SL_BIT]) & 1u) St.kept[sr[SL_NODE]] = 0;
+    St.slot_of[sr[SL_NODE]] = -1;
+  }
   for (int q = threadIdx.x; q < H.nz; q += blockDim.x) {
     const int* ze = tab + H.o_zent + q * 3;
     St.zent_of[ze[0] * 3 + ze[1]] = -1;
