@@ -107,13 +107,16 @@ constexpr double kMixedDelta = 1e-8;  // bound on |e32 - e64| used by the shortl
 
 size_t align256(size_t x) { return (x + 255) & ~size_t(255); }
 
-// Snapshot groups of a scoring launch with mpl masks per lane: about 512
-// blocks of 4 waves (two waves per SIMD, each with mpl independent masks per
-// lane; measured faster on MI355X than more, thinner waves), each group a
-// contiguous run of snapshots.
-int snap_groups_default(int k, int S, int* spg, int mpl = 1, int target_blocks = 512) {
+// Snapshot groups of a scoring launch (blocks of 256 lanes carrying mpl masks
+// each; the per-mask FP64 kernel carries one): by default about 256 mask
+// blocks per 24 snapshots and at most about 24 snapshots per block, each
+// group a contiguous run of snapshots.  target_blocks > 0 sets the block
+// count instead (the FP32 screen uses 512).
+int snap_groups_default(int k, int S, int* spg, int mpl = 1, int target_blocks = 0) {
   const int mblocks = (int)((((uint64_t)1 << k) + kScoreThreads * mpl - 1) / (kScoreThreads * mpl));
-  int SG = std::min(S, std::max(1, target_blocks / mblocks));
+  // (the shapes the autotuner picks on MI355X, within a few percent)
+  if (target_blocks <= 0) target_blocks = 256 * std::max(1, S / 24);
+  int SG = std::min(S, std::max((S + 23) / 24, target_blocks / mblocks));
   SG = std::min(SG, kMaxSnapGroups);
   *spg = (S + SG - 1) / SG;
   return (S + *spg - 1) / *spg;
@@ -182,7 +185,7 @@ namespace {
 int score_mpl(const okr_handle* h, int k) {
   if (h->mpl_force) return h->mpl_force;
   if ((int)h->mpl_tuned.size() > k && h->mpl_tuned[k]) return h->mpl_tuned[k];
-  return 4;
+  return h->S >= 48 ? 2 : 4;
 }
 
 // Snapshot groups of the FP64 scoring launch for a segment of k nodes: the
@@ -919,7 +922,7 @@ void enqueue_search(okr_handle* h, void* ws, const okr_yblocks* Y, const okr_loa
       // the FP32 screen: masks per lane and groups by the default rule
       const int mpl32 = kc >= 12 ? 4 : (kc >= 10 ? 2 : 1);
       int spg32;
-      const int SG32 = snap_groups_default(kc, S, &spg32, mpl32);
+      const int SG32 = snap_groups_default(kc, S, &spg32, mpl32, 512);
       for (int z = 0; z < nz; ++z) {
         const int g = h->chunk_segs[c0 + z];
         const Ptrs& w = lp[z];
