@@ -842,7 +842,7 @@ void enqueue_search(okr_handle* h, void* ws, const okr_yblocks* Y, const okr_loa
       const bool staged = N1 < nm;
       int* stage = w.sstage + g;
       auto rank = [&](const uint32_t* masks, int nrow, const int* flag, int skip_if) {
-        hipLaunchKernelGGL(k_surr_rank, dim3((nrow + 63) / 64), dim3(256), 0, st, (const SegHdr*)w.hdrs, g,
+        hipLaunchKernelGGL(k_surr_rank, dim3((nrow + 31) / 32), dim3(512), 0, st, (const SegHdr*)w.hdrs, g,
                            (const int*)w.tab, (const float*)w.spz, (const float*)w.szs, (const SurrSlot*)w.sss,
                            (const double*)w.econst, masks, nrow, (const __bf16*)w.sW1b, (const __bf16*)w.sW2b,
                            mg->surrogate, ln_ebar, w.skeys, flag, skip_if);

@@ -648,21 +648,23 @@ __global__ __launch_bounds__(1024) void k_surr_decide(const SegHdr* __restrict__
 }
 
 // ------------------------------------------------------- fused ranking --
-// Ranking keys of 64 masks per block (masks[row], or mask = row), with the
+// Ranking keys of 32 masks per block (masks[row], or mask = row), with the
 // arithmetic of k_surr_features -> k_gemm_nt<1> -> k_gemm_nt<2> ->
 // k_rowdot_finish -> k_surr_keys: the segment's feature tables are staged in
 // LDS, the 64 feature rows, the first hidden layer (64 x 256, BF16) and the
 // per-row partial products stay on chip, and both layers run on MFMA in the
 // GEMM kernel's order (K in steps of 16, the same operand layouts), so the
-// keys equal the unfused path's.  4 waves: wave w owns row tile w & 1 and
-// column tiles 4 (w >> 1) .. 4 (w >> 1) + 3 of each layer.
-constexpr int kRankRows = 64;
+// keys equal the unfused path's.  8 waves share the one row tile; wave w owns
+// column tile w of each layer and fetches its W2 fragments before the first
+// layer.
+constexpr int kRankRows = 32;
+constexpr int kRankThreads = 64 * (kSurrH / 32);
 constexpr int kRankInts = kMaxK * kChainInts + kMaxK * kMaxK + kMaxK * kSlotInts;  // chains, nesting, slots
-// LDS: H1 [64][256 + 8] BF16; the feature tables and rows.
+// LDS: H1 [32][256 + 8] BF16; the feature tables and rows.
 constexpr int kRankH1 = kRankRows * (kSurrH + 8) * 2;
 constexpr int kRankU = kRankInts * 4 + 2 * kMaxPairs * 4 + kMaxK * (int)sizeof(SurrSlot) + kRankRows * (kSurrF + 8) * 2;
 
-__global__ __launch_bounds__(256) void k_surr_rank(const SegHdr* __restrict__ hdrs, int g,
+__global__ __launch_bounds__(kRankThreads) void k_surr_rank(const SegHdr* __restrict__ hdrs, int g,
                                                    const int* __restrict__ tab, const float* __restrict__ pz,
                                                    const float* __restrict__ zs, const SurrSlot* __restrict__ ss,
                                                    const double* __restrict__ econst,
@@ -686,6 +688,14 @@ __global__ __launch_bounds__(256) void k_surr_rank(const SegHdr* __restrict__ hd
   float* s_zs = s_pz + kMaxPairs;
   SurrSlot* s_ss = (SurrSlot*)(s_zs + kMaxPairs);
   __bf16 (*X)[kSurrF + 8] = (__bf16(*)[kSurrF + 8])(s_ss + kMaxK);
+  const int ct = wave;
+  const int arow = lane & 31, koff = 8 * (lane >> 5);
+  const int bcol = ct * 32 + (lane & 31);
+  // the W2 fragments of this wave's layer-2 tile, fetched first so the loads
+  // overlap the features and the first layer
+  bf16x8 bw[kSurrH / 16];
+#pragma unroll
+  for (int q = 0; q < kSurrH / 16; ++q) bw[q] = *(const bf16x8*)&W2b[(size_t)bcol * kSurrH + 16 * q + koff];
   // stage the feature tables (chains, nesting and slots: ints [0, o_pair))
   const int nint = min(H.o_pair, kRankInts);
   for (int q = tid; q < nint; q += blockDim.x) s_int[q] = tab[q];
@@ -711,13 +721,10 @@ __global__ __launch_bounds__(256) void k_surr_rank(const SegHdr* __restrict__ hd
     for (int q = 0; q < kSurrF; ++q) X[tid][q] = (__bf16)f[q];
   }
   __syncthreads();
-  const int rt = wave & 1, ct0 = (wave >> 1) * 4;
-  const int arow = rt * 32 + (lane & 31), koff = 8 * (lane >> 5);
   // layer 1: H1 = gelu(X W1^T + b1), K = 32
-  for (int ct = ct0; ct < ct0 + 4; ++ct) {
+  {
     f32x16 acc;
     for (int v = 0; v < 16; ++v) acc[v] = 0.f;
-    const int bcol = ct * 32 + (lane & 31);
 #pragma unroll
     for (int kk = 0; kk < kSurrF; kk += 16) {
       const bf16x8 a = *(const bf16x8*)&X[arow][kk + koff];
@@ -726,18 +733,13 @@ __global__ __launch_bounds__(256) void k_surr_rank(const SegHdr* __restrict__ hd
     }
 #pragma unroll
     for (int v = 0; v < 16; ++v) {
-      const int row = rt * 32 + 8 * (v >> 2) + 4 * (lane >> 5) + (v & 3);
+      const int row = 8 * (v >> 2) + 4 * (lane >> 5) + (v & 3);
       H1[row][bcol] = (__bf16)gelu_f(acc[v] + params[kOffB1 + bcol]);
     }
   }
   __syncthreads();
-  // layer 2: gelu(H1 W2^T + b2) . w3, K = 256; per output tile all 16 W2
-  // fragments are fetched first (one round trip), then the 16 MFMAs
-  for (int ct = ct0; ct < ct0 + 4; ++ct) {
-    const int bcol = ct * 32 + (lane & 31);
-    bf16x8 bw[kSurrH / 16];
-#pragma unroll
-    for (int q = 0; q < kSurrH / 16; ++q) bw[q] = *(const bf16x8*)&W2b[(size_t)bcol * kSurrH + 16 * q + koff];
+  // layer 2: gelu(H1 W2^T + b2) . w3, K = 256
+  {
     f32x16 acc;
     for (int v = 0; v < 16; ++v) acc[v] = 0.f;
 #pragma unroll
@@ -750,7 +752,7 @@ __global__ __launch_bounds__(256) void k_surr_rank(const SegHdr* __restrict__ hd
     for (int v = 0; v < 16; ++v) {
       float sdot = gelu_f(acc[v] + bias) * w3;
       for (int o = 1; o < 32; o <<= 1) sdot += __shfl_xor(sdot, o, 64);
-      const int row = rt * 32 + 8 * (v >> 2) + 4 * (lane >> 5) + (v & 3);
+      const int row = 8 * (v >> 2) + 4 * (lane >> 5) + (v & 3);
       if ((lane & 31) == 0) part[ct][row] = sdot;
     }
   }
