@@ -31,8 +31,8 @@ FP64_VECTOR_PEAK_TFLOPS = 78.6   # MI355X FP64 vector (256 CUs x 2.4 GHz x 128 f
 # they were taken with: any change to them reports null.
 TRAFFIC_SOURCES = ["paper_2510_19608_amd/csrc/okr_score.hip", "paper_2510_19608_amd/csrc/okr_device.h",
                    "paper_2510_19608_amd/csrc/okr_internal.h", "paper_2510_19608_amd/csrc/okr_host.cpp"]
-TRAFFIC_SHA1 = "8580e6a16e7ba32c4a7cf1c6faa0557275ae3996"
-TRAFFIC_BYTES_PER_LAUNCH = 9151365
+TRAFFIC_SHA1 = "9447c5cffe6c5c7ee96a1ad482f451681a5f83de"
+TRAFFIC_BYTES_PER_LAUNCH = 9143535
 
 
 def measured_traffic():

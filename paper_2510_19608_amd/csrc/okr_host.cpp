@@ -122,6 +122,14 @@ int snap_groups_default(int k, int S, int* spg, int mpl = 1, int target_blocks =
   return (S + *spg - 1) / *spg;
 }
 
+// Launch shape of the FP32 screen: masks per lane by segment size and about
+// 512 mask blocks.  The workspace planner sizes the screen's partial scores
+// from this same function.
+int screen32_shape(int k, int S, int* spg, int* mpl) {
+  *mpl = k >= 12 ? 4 : (k >= 10 ? 2 : 1);
+  return snap_groups_default(k, S, spg, *mpl, 512);
+}
+
 struct Layout {
   size_t topo, z, Zroot, Vhat, Vcur, A, J, absV, kept, sup, slot_of, zent_of, status, iters, hdrs, decs, tab, P, srec,
       headV, zrec, econst, part, fin, tiles, tickets, kp, yeq, Ykd, Yko, err;
@@ -542,8 +550,8 @@ extern "C" int okr_plan(okr_handle* h, const okr_topology* topo, const okr_margi
   {
     size_t most = 1;
     for (int k = 1; k <= h->kmax; ++k) {
-      int spg;
-      for (int mpl = 1; mpl <= 4; mpl *= 2) most = std::max(most, (size_t)snap_groups_default(k, S, &spg, mpl) << k);
+      int spg, mpl;
+      most = std::max(most, (size_t)screen32_shape(k, S, &spg, &mpl) << k);
     }
     const size_t nm = (size_t)1 << h->kmax, nt = (nm + 63) / 64;
     L.P32 = take(sizeof(Pair32) * 3 * (size_t)S * kMaxPairs);
@@ -920,9 +928,8 @@ void enqueue_search(okr_handle* h, void* ws, const okr_yblocks* Y, const okr_loa
       }
     } else {
       // the FP32 screen: masks per lane and groups by the default rule
-      const int mpl32 = kc >= 12 ? 4 : (kc >= 10 ? 2 : 1);
-      int spg32;
-      const int SG32 = snap_groups_default(kc, S, &spg32, mpl32, 512);
+      int spg32, mpl32;
+      const int SG32 = screen32_shape(kc, S, &spg32, &mpl32);
       for (int z = 0; z < nz; ++z) {
         const int g = h->chunk_segs[c0 + z];
         const Ptrs& w = lp[z];

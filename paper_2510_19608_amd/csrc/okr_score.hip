@@ -86,8 +86,7 @@ __global__ __launch_bounds__(kScoreThreads) void k_score_fp64(
   const cint* chains = as_cint(tab + H.o_chain);
   const cint* nest = as_cint(tab + H.o_nest);
   const int zst = min(H.nz, zcap);
-  const int cP = H.npairs * 3, cT = H.nslots * 6, cH = H.nchains * 3, cZ = zst * 2;
-  const int tot = cP + cT + cH + cZ;
+  const int cP = H.npairs * 3, cT = H.nslots * 6, cH = H.nchains * 3, cZ = zst * 2;  // 16-byte chunks
   double e = 0.0, qmn[M], qmx[M];
 #pragma unroll
   for (int j = 0; j < M; ++j) {
@@ -95,29 +94,27 @@ __global__ __launch_bounds__(kScoreThreads) void k_score_fp64(
     qmx[j] = -INFINITY;
   }
   for (int l = l0; l < l1; l += M) {
-    for (int i = tid; i < M * tot; i += kScoreThreads) {
-      const int j = i / tot;
-      int r = i - j * tot;
-      const int lj = min(l + j, l1 - 1);
-      if (r < cP) {
-        ((uint4*)Ps)[r * M + j] = ((const uint4*)(P + (size_t)lj * H.npairs * 3))[r];
-        continue;
-      }
-      r -= cP;
-      if (r < cT) {
-        ((uint4*)Ts)[((r >> 1) * M + j) * 2 + (r & 1)] = ((const uint4*)(srec + (size_t)lj * H.nslots * 3))[r];
-        continue;
-      }
-      r -= cT;
-      if (r < cH) {
-        const uint4 v = ((const uint4*)(headV + (size_t)lj * H.nchains * 3))[r];
-        ((uint4*)Hv)[r * M + j] = v;
-        const double2 hv = make_double2(__hiloint2double((int)v.y, (int)v.x), __hiloint2double((int)v.w, (int)v.z));
-        Hm[r * M + j] = (hv.x != 0.0 || hv.y != 0.0) ? hmag(hv) : 0.0;
-        continue;
-      }
-      r -= cH;
-      ((uint4*)Zs)[((r >> 1) * M + j) * 2 + (r & 1)] = ((const uint4*)(zrec + (size_t)lj * H.nz))[r];
+    // one loop per table; element i = r * M + j (snapshot j fastest, M a
+    // power of two), so the LDS writes are contiguous
+    constexpr int LM = M == 4 ? 2 : (M == 2 ? 1 : 0);
+    for (int i = tid; i < (cP << LM); i += kScoreThreads) {
+      const int r = i >> LM, j = i & (M - 1);
+      ((uint4*)Ps)[i] = ((const uint4*)(P + (size_t)min(l + j, l1 - 1) * H.npairs * 3))[r];
+    }
+    for (int i = tid; i < (cT << LM); i += kScoreThreads) {  // 2 chunks per record
+      const int e = i >> (LM + 1), j = (i >> 1) & (M - 1), h = i & 1;
+      ((uint4*)Ts)[i] = ((const uint4*)(srec + (size_t)min(l + j, l1 - 1) * H.nslots * 3))[2 * e + h];
+    }
+    for (int i = tid; i < (cH << LM); i += kScoreThreads) {
+      const int r = i >> LM, j = i & (M - 1);
+      const uint4 v = ((const uint4*)(headV + (size_t)min(l + j, l1 - 1) * H.nchains * 3))[r];
+      ((uint4*)Hv)[i] = v;
+      const double2 hv = make_double2(__hiloint2double((int)v.y, (int)v.x), __hiloint2double((int)v.w, (int)v.z));
+      Hm[i] = (hv.x != 0.0 || hv.y != 0.0) ? hmag(hv) : 0.0;
+    }
+    for (int i = tid; i < (cZ << LM); i += kScoreThreads) {  // 2 chunks per record
+      const int e = i >> (LM + 1), j = (i >> 1) & (M - 1), h = i & 1;
+      ((uint4*)Zs)[i] = ((const uint4*)(zrec + (size_t)min(l + j, l1 - 1) * H.nz))[2 * e + h];
     }
     if (tid < M) Ec[tid] = econst[min(l + tid, l1 - 1)];
     __syncthreads();
