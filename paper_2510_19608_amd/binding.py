@@ -87,6 +87,25 @@ class Result(ctypes.Structure):
                 ("pf_iterations", ctypes.c_int32), ("n_score_launches", ctypes.c_int32)]
 
 
+class GreedyParams(ctypes.Structure):
+    _fields_ = [("e_bar", ctypes.c_double), ("tie_tol", ctypes.c_double), ("amb_tol", ctypes.c_double),
+                ("max_iter", ctypes.c_int32), ("flags", ctypes.c_uint32), ("pf_tol", ctypes.c_double),
+                ("pf_maxit", ctypes.c_int32), ("pad", ctypes.c_int32)]
+
+
+class GreedyStep(ctypes.Structure):
+    _fields_ = [("cand", ctypes.c_int32), ("s", ctypes.c_int32), ("r", ctypes.c_int32),
+                ("ambiguous", ctypes.c_int32), ("n_cand", ctypes.c_int32), ("n_feasible", ctypes.c_int32),
+                ("smice", ctypes.c_double), ("emax", ctypes.c_double)]
+
+
+class GreedyResult(ctypes.Structure):
+    _fields_ = [("super", ctypes.c_void_p), ("steps", ctypes.c_void_p), ("err_per_snapshot", ctypes.c_void_p),
+                ("n_steps", ctypes.c_int32), ("n_kept", ctypes.c_int32), ("max_err", ctypes.c_double),
+                ("t_pf_ms", ctypes.c_double), ("t_search_ms", ctypes.c_double),
+                ("pf_iterations", ctypes.c_int32), ("pad", ctypes.c_int32)]
+
+
 _lib = None
 
 
@@ -114,9 +133,19 @@ def lib():
         L.okr_surrogate_grad.argtypes = [vp, vp, vp, ctypes.c_int32, vp, ctypes.POINTER(ctypes.c_float), vp,
                                          ctypes.c_size_t, vp]
         L.okr_surrogate_forward.argtypes = [vp, vp, ctypes.c_int64, vp, vp, ctypes.c_size_t, vp]
+        L.okr_greedy_create.argtypes = [ctypes.POINTER(vp), vp]
+        L.okr_greedy_plan.argtypes = [vp, ctypes.c_int32, vp, vp, ctypes.c_int32, ctypes.POINTER(ctypes.c_size_t)]
+        L.okr_greedy_run.argtypes = [vp, ctypes.POINTER(YBlocks), ctypes.POINTER(Loads),
+                                     ctypes.POINTER(GreedyParams), vp, ctypes.POINTER(GreedyResult)]
+        L.okr_greedy_evaluate.argtypes = [vp, ctypes.POINTER(YBlocks), ctypes.POINTER(Loads), vp,
+                                          ctypes.POINTER(GreedyParams), vp, vp, ctypes.POINTER(ctypes.c_double)]
+        L.okr_greedy_destroy.argtypes = [vp]
+        L.okr_greedy_last_error.argtypes = [vp]
+        L.okr_greedy_last_error.restype = ctypes.c_char_p
         for fn in ("okr_create", "okr_plan", "okr_reduce_feeder", "okr_dump_scores", "okr_destroy",
                    "okr_surrogate_workspace", "okr_train_surrogate", "okr_surrogate_grad",
-                   "okr_surrogate_forward"):
+                   "okr_surrogate_forward", "okr_greedy_create", "okr_greedy_plan", "okr_greedy_run",
+                   "okr_greedy_evaluate", "okr_greedy_destroy"):
             getattr(L, fn).restype = ctypes.c_int
         _lib = L
     return _lib
@@ -377,3 +406,138 @@ def reduce_feeder(f, device="cuda:0", vhat=None, want_vhat=True, **margin_kw):
         return out
     finally:
         R.close()
+
+
+# ---- greedy single-move search (Algorithm 1) and fixed-reduction scoring ----
+
+def okr_greedy_create(stream=None):
+    g = ctypes.c_void_p()
+    rc = lib().okr_greedy_create(ctypes.byref(g), stream)
+    if rc != 0:
+        raise OkrError(rc, "okr_greedy_create failed")
+    return g
+
+
+def okr_greedy_last_error(g):
+    return lib().okr_greedy_last_error(g).decode()
+
+
+def _gcheck(g, rc):
+    if rc < 0:
+        raise OkrError(rc, okr_greedy_last_error(g))
+    return rc
+
+
+def okr_greedy_plan(g, parent, phase, S):
+    parent = np.ascontiguousarray(parent, dtype=np.int32)
+    phase = np.ascontiguousarray(phase, dtype=np.uint8)
+    ws = ctypes.c_size_t(0)
+    _gcheck(g, lib().okr_greedy_plan(g, len(parent), parent.ctypes.data, phase.ctypes.data, S, ctypes.byref(ws)))
+    return ws.value
+
+
+def okr_greedy_run(g, Y: YBlocks, loads: Loads, params: GreedyParams, d_ws, out: GreedyResult):
+    return _gcheck(g, lib().okr_greedy_run(g, ctypes.byref(Y), ctypes.byref(loads), ctypes.byref(params), d_ws,
+                                           ctypes.byref(out)))
+
+
+def okr_greedy_evaluate(g, Y: YBlocks, loads: Loads, sup, params: GreedyParams, d_ws, err):
+    sup = np.ascontiguousarray(sup, dtype=np.int32)
+    mx = ctypes.c_double(0.0)
+    _gcheck(g, lib().okr_greedy_evaluate(g, ctypes.byref(Y), ctypes.byref(loads), sup.ctypes.data,
+                                         ctypes.byref(params), d_ws, err.ctypes.data, ctypes.byref(mx)))
+    return mx.value
+
+
+def okr_greedy_destroy(g):
+    return lib().okr_greedy_destroy(g)
+
+
+class Greedy:
+    """Plans once for a feeder's topology and scenario count, keeps its inputs
+    on the device and runs Algorithm 1 (``run``) or scores a fixed
+    assignment over the feeder's scenarios (``evaluate``)."""
+
+    def __init__(self, f, device="cuda:0", vhat=None):
+        import torch
+        if not torch.cuda.is_available():
+            raise OkrError(OKR.E_HIP, "no GPU visible: the search runs only on the HIP device")
+        lib()
+        self.torch = torch
+        self.device = torch.device(device)
+        n, S = int(f["n"]), int(np.asarray(f["S_load"]).shape[0])
+        self.n, self.S = n, S
+
+        def dev(a):
+            t = torch.from_numpy(np.ascontiguousarray(a, dtype=np.complex128))
+            return torch.view_as_real(t).contiguous().to(self.device)
+
+        with torch.cuda.device(self.device):
+            self.Yd = dev(f["Y_diag"])
+            self.Yo = dev(f["Y_off"])
+            self.Sl = dev(f["S_load"])
+            self.Vh = dev(vhat) if vhat is not None else None
+            self.stream = torch.cuda.Stream(device=self.device)
+            self.g = okr_greedy_create(ctypes.c_void_p(self.stream.cuda_stream))
+            self.ws_bytes = okr_greedy_plan(self.g, f["parent"], f["phase"], S)
+            self.ws = torch.empty(max(self.ws_bytes, 1), dtype=torch.uint8, device=self.device)
+        self.V0 = np.ascontiguousarray(f["V0"], dtype=np.complex128)
+        self.Y = YBlocks(self.Yd.data_ptr(), self.Yo.data_ptr())
+        self.loads = Loads(S, self.Sl.data_ptr(), self.V0.ctypes.data,
+                           self.Vh.data_ptr() if self.Vh is not None else None)
+        self.flags = OKR.FLAG_VHAT_GIVEN if vhat is not None else 0
+        self.out_super = np.zeros(n, np.int32)
+        self.out_steps = (GreedyStep * n)()
+        self.out_err = np.zeros(S)
+        self.res = GreedyResult(self.out_super.ctypes.data, ctypes.cast(self.out_steps, ctypes.c_void_p),
+                                self.out_err.ctypes.data)
+
+    def params(self, e_bar, max_iter=0, tie_tol=1e-11, amb_tol=1e-13):
+        return GreedyParams(e_bar, tie_tol, amb_tol, max_iter, self.flags, 0.0, 0, 0)
+
+    def run(self, e_bar, max_iter=0, tie_tol=1e-11, amb_tol=1e-13):
+        self.stream.wait_stream(self.torch.cuda.current_stream(self.device))
+        okr_greedy_run(self.g, self.Y, self.loads, self.params(e_bar, max_iter, tie_tol, amb_tol),
+                       ctypes.c_void_p(self.ws.data_ptr()), self.res)
+        r = self.res
+        steps = [dict(cand=s.cand, s=s.s, r=s.r, smice=s.smice, emax=s.emax, ambiguous=bool(s.ambiguous),
+                      n_cand=s.n_cand, n_feasible=s.n_feasible) for s in list(self.out_steps)[:r.n_steps]]
+        return dict(super=self.out_super.copy(), steps=steps, err_per_snapshot=self.out_err.copy(),
+                    n_steps=r.n_steps, n_kept=r.n_kept, max_err=r.max_err, t_pf_ms=r.t_pf_ms,
+                    t_search_ms=r.t_search_ms, pf_iterations=r.pf_iterations)
+
+    def evaluate(self, sup):
+        self.stream.wait_stream(self.torch.cuda.current_stream(self.device))
+        err = np.zeros(self.S)
+        mx = okr_greedy_evaluate(self.g, self.Y, self.loads, sup, self.params(0.0),
+                                 ctypes.c_void_p(self.ws.data_ptr()), err)
+        return err, mx
+
+    def close(self):
+        if getattr(self, "g", None) is not None:
+            okr_greedy_destroy(self.g)
+            self.g = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def greedy(f, e_bar=None, device="cuda:0", vhat=None, max_iter=0):
+    """Run Algorithm 1 once on a feeder dict and return the result dict."""
+    G = Greedy(f, device=device, vhat=vhat)
+    try:
+        return G.run(f["e_bar"] if e_bar is None else e_bar, max_iter=max_iter)
+    finally:
+        G.close()
+
+
+def evaluate_assignment(f, sup, device="cuda:0", vhat=None):
+    """Largest error per scenario of a fixed assignment over f's scenarios."""
+    G = Greedy(f, device=device, vhat=vhat)
+    try:
+        return G.evaluate(sup)
+    finally:
+        G.close()

@@ -1,0 +1,749 @@
+// Greedy single-move reduction search (Algorithm 1, Section IV) and the
+// evaluation of a fixed reduction over many scenarios (Section VI), on
+// gfx950: kernels and the C ABI of include/okr_greedy.h.
+//
+// Design.  The full network is radial with the slack as source, so with the
+// currents fixed its solution is V = V0 - sum_j Zcp(., j) I_j, where Zcp(y, j)
+// is the series impedance of the common part of the root paths of y and j,
+// i.e. Zroot(lca(y, j)).  Moving the aggregated load current J of super-node
+// r to super-node s therefore changes every voltage by
+//     dV_y = (Zroot(lca(y, r)) - Zroot(lca(y, s))) J,
+// which vanishes outside the subtree of lca(r, s).  One block scores one
+// candidate: the root paths of r and s go to LDS (position ranges of their
+// DFS subtrees by depth, so lca(y, r) is a binary search), each node takes
+// its post-move super-node's voltage, and the cluster maxima (MICE) gather
+// in an LDS table by atomic max on the bit patterns of non-negative doubles.
+// The applied move refreshes the state by a fresh fixed-current sweep (no
+// accumulated updates), so every iteration starts from the exact solve.
+
+#include <hip/hip_runtime.h>
+
+#include <chrono>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <new>
+#include <string>
+#include <vector>
+
+#include "../../include/okr_greedy.h"
+#include "okr_device.h"
+#include "okr_internal.h"
+
+namespace okr {
+
+__global__ void k_branch_z(int, const int*, const uint8_t*, const int*, const int*, const double2*, const double2*,
+                           double2*, int*);
+__global__ void k_powerflow(int, const int*, const uint8_t*, const int*, const int*, int, const int*, const int*,
+                            const double2*, const double2*, double2, double2, double2, double, int, double, double,
+                            double2*, double2*, double2*, double*, int*, int*);
+__global__ void k_from_vhat(int, int, const uint8_t*, const double2*, const double2*, double, double, double2*,
+                            double*, int*);
+__global__ void k_zroot(int, const int*, const int*, const int*, int, const double2*, double2*);
+
+struct GState {
+  int iter;  // moves applied
+  int done;  // no feasible candidate, or the move cap reached
+  int s, r;  // the move chosen by the last pick
+};
+
+struct GStep {  // layout of okr_greedy_step
+  int cand, s, r, ambiguous, n_cand, n_feasible;
+  double smice, emax;
+};
+
+struct PathRec {
+  int node, lo, hi;  // an ancestor and the DFS position range of its subtree
+};
+
+constexpr int kGreedyThreads = 256;
+constexpr int kGreedyMaxS = 64;      // scenarios of a search (moved currents staged in LDS)
+constexpr int kGreedyMaxSN = 6144;   // scenarios x nodes of a search (cluster maxima in LDS)
+
+// Depth of lca(y, t) where path[d] is t's ancestor at depth d (d <= dmax) and
+// q is y's DFS position: the deepest d whose subtree range holds q.
+__device__ __forceinline__ int lca_depth(const PathRec* path, int dmax, int q) {
+  int lo = 0, hi = dmax;
+  while (lo < hi) {
+    const int mid = (lo + hi + 1) >> 1;
+    if (path[mid].lo <= q && q < path[mid].hi) lo = mid;
+    else hi = mid - 1;
+  }
+  return lo;
+}
+
+// Fixed-current solve of one scenario on the radial network: branch currents
+// by subtree sums of the load currents I (deepest level first), then
+// V(x) = V(parent) - z_x Ib(x) level by level from the slack (V0).  One block.
+__device__ void sweep_block(int n, const int* parent, const uint8_t* phase, const int* lvl_off,
+                            const int* lvl_nodes, int nlev, const int* ch_off, const int* ch, const double2* z,
+                            const double2 (&v0)[3], const double2* I, double2* Ib, double2* V) {
+  for (int q = threadIdx.x; q < n * 3; q += blockDim.x) Ib[q] = I[q];
+  __syncthreads();
+  for (int lev = nlev - 2; lev >= 0; --lev) {
+    for (int q = lvl_off[lev] + threadIdx.x; q < lvl_off[lev + 1]; q += blockDim.x) {
+      const int i = lvl_nodes[q];
+      double2 s0 = Ib[i * 3], s1 = Ib[i * 3 + 1], s2 = Ib[i * 3 + 2];
+      for (int e = ch_off[i]; e < ch_off[i + 1]; ++e) {
+        const int c = ch[e];
+        s0 = cadd(s0, Ib[c * 3]);
+        s1 = cadd(s1, Ib[c * 3 + 1]);
+        s2 = cadd(s2, Ib[c * 3 + 2]);
+      }
+      Ib[i * 3] = s0;
+      Ib[i * 3 + 1] = s1;
+      Ib[i * 3 + 2] = s2;
+    }
+    __syncthreads();
+  }
+  if (threadIdx.x < 3) V[threadIdx.x] = (phase[0] >> threadIdx.x & 1u) ? v0[threadIdx.x] : make_double2(0.0, 0.0);
+  __syncthreads();
+  for (int lev = 1; lev < nlev; ++lev) {
+    for (int q = lvl_off[lev] + threadIdx.x; q < lvl_off[lev + 1]; q += blockDim.x) {
+      const int i = lvl_nodes[q], pv = parent[i];
+      const double2* zi = z + (size_t)i * 9;
+      const double2 j0 = Ib[i * 3], j1 = Ib[i * 3 + 1], j2 = Ib[i * 3 + 2];
+      for (int p = 0; p < 3; ++p) {
+        double2 v = make_double2(0.0, 0.0);
+        if (phase[i] >> p & 1u) {
+          const double2 d = cadd(cadd(cmul(zi[p * 3], j0), cmul(zi[p * 3 + 1], j1)), cmul(zi[p * 3 + 2], j2));
+          v = csub(V[pv * 3 + p], d);
+        }
+        V[i * 3 + p] = v;
+      }
+    }
+    __syncthreads();
+  }
+}
+
+// Start of the search: every node its own super-node, I = the load currents.
+__global__ void k_greedy_init(int n, int S, const double2* __restrict__ A, double2* __restrict__ Iagg,
+                              int* __restrict__ sup, GState* __restrict__ gs) {
+  const size_t t = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (t < (size_t)S * n * 3) Iagg[t] = A[t];
+  if (t < (size_t)n) sup[t] = (int)t;
+  if (t == 0) {
+    gs->iter = 0;
+    gs->done = 0;
+    gs->s = gs->r = -1;
+  }
+}
+
+// Fixed-current solve of every scenario (one block each) from Iagg.
+__global__ __launch_bounds__(kGreedyThreads) void k_greedy_sweep(
+    int n, const int* __restrict__ parent, const uint8_t* __restrict__ phase, const int* __restrict__ lvl_off,
+    const int* __restrict__ lvl_nodes, int nlev, const int* __restrict__ ch_off, const int* __restrict__ ch,
+    const double2* __restrict__ z, double2 v0a, double2 v0b, double2 v0c, const double2* __restrict__ Iagg,
+    double2* __restrict__ Ib, double2* __restrict__ V) {
+  const size_t base = (size_t)blockIdx.x * n * 3;
+  const double2 v0[3] = {v0a, v0b, v0c};
+  sweep_block(n, parent, phase, lvl_off, lvl_nodes, nlev, ch_off, ch, z, v0, Iagg + base, Ib + base, V + base);
+}
+
+// Score of one candidate per block (grid: 2n blocks, id = blockIdx.x):
+// SMICE (+inf when infeasible) and the largest error (-1 when the id is not a
+// candidate in this state).  Dynamic LDS: S * n cluster maxima (as uint64
+// bit patterns), then the two root paths.
+__global__ __launch_bounds__(kGreedyThreads) void k_greedy_score(
+    int n, int S, const int* __restrict__ parent, const uint8_t* __restrict__ phase, const int* __restrict__ pos,
+    const int* __restrict__ size, const int* __restrict__ depth, const int* __restrict__ sup,
+    const double2* __restrict__ Zr, const double2* __restrict__ Iagg, const double2* __restrict__ Vcur,
+    const double* __restrict__ absV, double e_bar, const GState* __restrict__ gs, double* __restrict__ sm,
+    double* __restrict__ em) {
+  extern __shared__ __align__(16) unsigned char g_lds[];
+  __shared__ double2 J[kGreedyMaxS * 3];
+  __shared__ double red[kGreedyThreads / 64];
+  if (gs->done) return;
+  const int cand = blockIdx.x, x = cand >> 1, dir = cand & 1, tid = threadIdx.x;
+  int r = -1, s = -1;
+  if (x > 0) {
+    const int a = sup[x], b = sup[parent[x]];
+    if (a != b) {
+      r = dir ? b : a;
+      s = dir ? a : b;
+      if (r == 0 || (phase[r] & ~phase[s])) r = -1;
+    }
+  }
+  if (r < 0) {  // not a candidate (uniform over the block)
+    if (tid == 0) {
+      sm[cand] = INFINITY;
+      em[cand] = -1.0;
+    }
+    return;
+  }
+  unsigned long long* mice = (unsigned long long*)g_lds;
+  PathRec* pr = (PathRec*)(mice + (size_t)S * n);
+  const int dr = depth[r], ds = depth[s];
+  PathRec* ps = pr + dr + 1;
+  for (int q = tid; q < S * n; q += kGreedyThreads) mice[q] = 0ull;
+  const int qr = pos[r], qs = pos[s];
+  for (int u = tid; u < n; u += kGreedyThreads) {
+    const int lo = pos[u], hi = lo + size[u];
+    if (lo <= qr && qr < hi) pr[depth[u]] = PathRec{u, lo, hi};
+    if (lo <= qs && qs < hi) ps[depth[u]] = PathRec{u, lo, hi};
+  }
+  for (int q = tid; q < S * 3; q += kGreedyThreads) J[q] = Iagg[((size_t)(q / 3) * n + r) * 3 + q % 3];
+  __syncthreads();
+  double emax = 0.0;
+  for (int xn = tid; xn < n; xn += kGreedyThreads) {
+    int y = sup[xn];
+    if (y == r) y = s;
+    const int qy = pos[y], dy = depth[y];
+    const int da = lca_depth(pr, min(dy, dr), qy), db = lca_depth(ps, min(dy, ds), qy);
+    double2 dZ[9];
+    const bool moved = da != db;  // equal depths: the same ancestor, no change
+    if (moved) {
+      const double2* Za = Zr + (size_t)pr[da].node * 9;
+      const double2* Zb = Zr + (size_t)ps[db].node * 9;
+#pragma unroll
+      for (int q = 0; q < 9; ++q) dZ[q] = csub(Za[q], Zb[q]);
+    }
+    const unsigned ph = phase[xn];
+    for (int l = 0; l < S; ++l) {
+      const size_t vb = ((size_t)l * n + y) * 3, xb = ((size_t)l * n + xn) * 3;
+      double ex = 0.0;
+#pragma unroll
+      for (int p = 0; p < 3; ++p) {
+        if (!(ph >> p & 1u)) continue;
+        double2 v = Vcur[vb + p];
+        if (moved) {
+          const double2 d = cadd(cadd(cmul(dZ[p * 3], J[l * 3]), cmul(dZ[p * 3 + 1], J[l * 3 + 1])),
+                                 cmul(dZ[p * 3 + 2], J[l * 3 + 2]));
+          v = cadd(v, d);
+        }
+        ex = fmax(ex, fabs(absV[xb + p] - sqrt(cabs2(v))));
+      }
+      atomicMax(&mice[(size_t)l * n + y], (unsigned long long)__double_as_longlong(ex));
+      emax = fmax(emax, ex);
+    }
+  }
+  __syncthreads();
+  // SMICE: every thread sums its strided share in order, then a fixed tree
+  double acc = 0.0;
+  for (int q = tid; q < S * n; q += kGreedyThreads) acc += __longlong_as_double((long long)mice[q]);
+  for (int o = 32; o > 0; o >>= 1) {
+    acc += __shfl_xor(acc, o, 64);
+    emax = fmax(emax, __shfl_xor(emax, o, 64));
+  }
+  if ((tid & 63) == 0) red[tid >> 6] = acc;
+  __syncthreads();
+  const double tot = (red[0] + red[1]) + (red[2] + red[3]);
+  __syncthreads();
+  if ((tid & 63) == 0) red[tid >> 6] = emax;
+  __syncthreads();
+  if (tid == 0) {
+    const double e = fmax(fmax(red[0], red[1]), fmax(red[2], red[3]));
+    em[cand] = e;
+    sm[cand] = e <= e_bar ? tot : INFINITY;
+  }
+}
+
+// Choice of the iteration's move (one block of 1024): the smallest SMICE
+// among feasible candidates, ties within tie_tol to the lowest id; records
+// the step, or marks the search done.
+__global__ __launch_bounds__(1024) void k_greedy_pick(int ncand, const int* __restrict__ parent,
+                                                      const int* __restrict__ sup, const double* __restrict__ sm,
+                                                      const double* __restrict__ em, double e_bar, double tie,
+                                                      double amb, int max_iter, GState* __restrict__ gs,
+                                                      GStep* __restrict__ steps) {
+  __shared__ double shd[16];
+  __shared__ int shi[16];
+  if (gs->done) return;
+  if (max_iter > 0 && gs->iter >= max_iter) {
+    __syncthreads();
+    if (threadIdx.x == 0) gs->done = 1;
+    return;
+  }
+  double mn = INFINITY;
+  int nact = 0, nfeas = 0;
+  for (int c = threadIdx.x; c < ncand; c += blockDim.x) {
+    mn = fmin(mn, sm[c]);
+    nact += em[c] >= 0.0;
+    nfeas += sm[c] < INFINITY;
+  }
+  mn = block_reduce(mn, [](double a, double b) { return fmin(a, b); }, shd);
+  nact = block_reduce(nact, [](int a, int b) { return a + b; }, shi);
+  nfeas = block_reduce(nfeas, [](int a, int b) { return a + b; }, shi);
+  if (!(mn < INFINITY)) {
+    if (threadIdx.x == 0) gs->done = 1;
+    return;
+  }
+  const double thr = mn + tie;
+  int win = 0x7fffffff, fl = 0;
+  for (int c = threadIdx.x; c < ncand; c += blockDim.x) {
+    const double v = sm[c];
+    if (v <= thr) win = min(win, c);
+    if (v < INFINITY && fabs(v - thr) <= amb) fl = 1;
+    if (em[c] >= 0.0 && fabs(em[c] - e_bar) <= amb) fl = 1;
+  }
+  win = block_reduce(win, [](int a, int b) { return min(a, b); }, shi);
+  fl = block_reduce(fl, [](int a, int b) { return max(a, b); }, shi);
+  if (threadIdx.x == 0) {
+    const int x = win >> 1, a = sup[x], b = sup[parent[x]];
+    const int r = (win & 1) ? b : a, s = (win & 1) ? a : b;
+    GStep st;
+    st.cand = win;
+    st.s = s;
+    st.r = r;
+    st.ambiguous = fl;
+    st.n_cand = nact;
+    st.n_feasible = nfeas;
+    st.smice = sm[win];
+    st.emax = em[win];
+    steps[gs->iter] = st;
+    gs->s = s;
+    gs->r = r;
+    gs->iter += 1;
+  }
+}
+
+// The chosen move (one block per scenario): r's current joins s's, the
+// scenario is solved again; block 0 also reassigns r's cluster to s.
+__global__ __launch_bounds__(kGreedyThreads) void k_greedy_apply(
+    int n, const int* __restrict__ parent, const uint8_t* __restrict__ phase, const int* __restrict__ lvl_off,
+    const int* __restrict__ lvl_nodes, int nlev, const int* __restrict__ ch_off, const int* __restrict__ ch,
+    const double2* __restrict__ z, double2 v0a, double2 v0b, double2 v0c, const GState* __restrict__ gs,
+    int* __restrict__ sup, double2* __restrict__ Iagg, double2* __restrict__ Ib, double2* __restrict__ V) {
+  if (gs->done) return;
+  const int s = gs->s, r = gs->r, l = blockIdx.x;
+  const size_t base = (size_t)l * n * 3;
+  if (threadIdx.x < 3) {
+    const int p = threadIdx.x;
+    Iagg[base + s * 3 + p] = cadd(Iagg[base + s * 3 + p], Iagg[base + r * 3 + p]);
+    Iagg[base + r * 3 + p] = make_double2(0.0, 0.0);
+  }
+  if (l == 0)
+    for (int x = threadIdx.x; x < n; x += blockDim.x)
+      if (sup[x] == r) sup[x] = s;
+  __syncthreads();
+  const double2 v0[3] = {v0a, v0b, v0c};
+  sweep_block(n, parent, phase, lvl_off, lvl_nodes, nlev, ch_off, ch, z, v0, Iagg + base, Ib + base, V + base);
+}
+
+// I = A I^ for a given assignment: one thread per (scenario, phase) adds the
+// members' currents in node order.
+__global__ void k_greedy_aggregate(int n, int S, const int* __restrict__ sup, const double2* __restrict__ A,
+                                   double2* __restrict__ Iagg) {
+  const int t = blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= S * 3) return;
+  const int l = t / 3, p = t % 3;
+  const size_t base = (size_t)l * n * 3;
+  for (int x = 0; x < n; ++x) Iagg[base + x * 3 + p] = make_double2(0.0, 0.0);
+  for (int x = 0; x < n; ++x) {
+    const size_t d = base + (size_t)sup[x] * 3 + p;
+    Iagg[d] = cadd(Iagg[d], A[base + x * 3 + p]);
+  }
+}
+
+// Largest error of the current state per scenario (one block each): every
+// node against its super-node's voltage.
+__global__ __launch_bounds__(kGreedyThreads) void k_greedy_err(int n, const uint8_t* __restrict__ phase,
+                                                               const int* __restrict__ sup,
+                                                               const double2* __restrict__ V,
+                                                               const double* __restrict__ absV,
+                                                               double* __restrict__ err) {
+  __shared__ double shd[16];
+  const size_t base = (size_t)blockIdx.x * n * 3;
+  double e = 0.0;
+  for (int x = threadIdx.x; x < n; x += blockDim.x)
+    for (int p = 0; p < 3; ++p)
+      if (phase[x] >> p & 1u) e = fmax(e, fabs(absV[base + x * 3 + p] - sqrt(cabs2(V[base + sup[x] * 3 + p]))));
+  e = block_reduce(e, [](double a, double b) { return fmax(a, b); }, shd);
+  if (threadIdx.x == 0) err[blockIdx.x] = e;
+}
+
+}  // namespace okr
+
+using namespace okr;
+
+struct okr_greedy {
+  hipStream_t stream = nullptr;
+  std::string err;
+  bool planned = false;
+  int n = 0, S = 0, nlev = 0;
+  std::vector<int> parent, pos, size, depth, lvl_off, lvl_nodes, ch_off, ch;
+  std::vector<uint8_t> phase;
+  // workspace layout (byte offsets)
+  size_t o_topo = 0, o_phase = 0, o_z = 0, o_Zr = 0, o_Vhat = 0, o_A = 0, o_absV = 0, o_I = 0, o_V = 0, o_Ib = 0,
+         o_sup = 0, o_sm = 0, o_em = 0, o_steps = 0, o_gs = 0, o_status = 0, o_iters = 0, o_err = 0, total = 0;
+  // packed int arrays: parent, pos, size, depth, lvl_off, lvl_nodes, ch_off, ch
+  size_t t_parent = 0, t_pos = 0, t_size = 0, t_depth = 0, t_lvl_off = 0, t_lvl_nodes = 0, t_ch_off = 0, t_ch = 0;
+  std::vector<int> topo_host;
+};
+
+#define OKRG_FAIL(g, code, ...)            \
+  do {                                     \
+    char _b[512];                          \
+    snprintf(_b, sizeof _b, __VA_ARGS__);  \
+    (g)->err = _b;                         \
+    return code;                           \
+  } while (0)
+
+#define OKRG_HIP(g, call)                                                                   \
+  do {                                                                                      \
+    hipError_t _e = (call);                                                                 \
+    if (_e != hipSuccess) OKRG_FAIL(g, OKR_E_HIP, "%s: %s", #call, hipGetErrorString(_e)); \
+  } while (0)
+
+extern "C" int okr_greedy_create(okr_greedy** g, void* hip_stream) {
+  if (!g) return OKR_E_ARG;
+  okr_greedy* G = new (std::nothrow) okr_greedy();
+  if (!G) return OKR_E_ARG;
+  G->stream = static_cast<hipStream_t>(hip_stream);
+  *g = G;
+  return OKR_OK;
+}
+
+extern "C" int okr_greedy_destroy(okr_greedy* g) {
+  if (!g) return OKR_E_ARG;
+  delete g;
+  return OKR_OK;
+}
+
+extern "C" const char* okr_greedy_last_error(const okr_greedy* g) { return g ? g->err.c_str() : "null handle"; }
+
+extern "C" int okr_greedy_plan(okr_greedy* g, int32_t n, const int32_t* parent, const uint8_t* phase, int32_t S,
+                               size_t* workspace_bytes) {
+  if (!g) return OKR_E_ARG;
+  g->planned = false;
+  if (!parent || !phase || !workspace_bytes || n < 1 || S < 1) OKRG_FAIL(g, OKR_E_ARG, "null argument, n < 1 or S < 1");
+  g->n = n;
+  g->S = S;
+  g->parent.assign(parent, parent + n);
+  g->phase.assign(phase, phase + n);
+  if (g->parent[0] != -1) OKRG_FAIL(g, OKR_E_NOT_TREE, "parent[0] must be -1");
+  for (int i = 1; i < n; ++i)
+    if (g->parent[i] < 0 || g->parent[i] >= n || g->parent[i] == i)
+      OKRG_FAIL(g, OKR_E_NOT_TREE, "parent[%d] = %d out of range", i, g->parent[i]);
+  g->ch_off.assign(n + 1, 0);
+  for (int i = 1; i < n; ++i) g->ch_off[g->parent[i] + 1]++;
+  for (int i = 0; i < n; ++i) g->ch_off[i + 1] += g->ch_off[i];
+  g->ch.assign(std::max(n - 1, 1), 0);
+  {
+    std::vector<int> fill(n, 0);
+    for (int i = 1; i < n; ++i) g->ch[g->ch_off[g->parent[i]] + fill[g->parent[i]]++] = i;
+  }
+  std::vector<int> pre;
+  pre.reserve(n);
+  {
+    std::vector<int> st{0};
+    while (!st.empty() && (int)pre.size() <= n) {
+      const int v = st.back();
+      st.pop_back();
+      pre.push_back(v);
+      for (int e = g->ch_off[v + 1] - 1; e >= g->ch_off[v]; --e) st.push_back(g->ch[e]);
+    }
+  }
+  if ((int)pre.size() != n) OKRG_FAIL(g, OKR_E_NOT_TREE, "parent[] is not a tree rooted at node 0");
+  g->pos.assign(n, 0);
+  for (int q = 0; q < n; ++q) g->pos[pre[q]] = q;
+  g->size.assign(n, 1);
+  for (int q = n - 1; q >= 1; --q) g->size[g->parent[pre[q]]] += g->size[pre[q]];
+  g->depth.assign(n, 0);
+  int dmax = 0;
+  for (int q = 1; q < n; ++q) {
+    const int v = pre[q];
+    g->depth[v] = g->depth[g->parent[v]] + 1;
+    dmax = std::max(dmax, g->depth[v]);
+  }
+  g->nlev = dmax + 1;
+  g->lvl_off.assign(g->nlev + 1, 0);
+  for (int i = 0; i < n; ++i) g->lvl_off[g->depth[i] + 1]++;
+  for (int d = 0; d < g->nlev; ++d) g->lvl_off[d + 1] += g->lvl_off[d];
+  g->lvl_nodes.assign(n, 0);
+  {
+    std::vector<int> fill(g->nlev, 0);
+    for (int i = 0; i < n; ++i) g->lvl_nodes[g->lvl_off[g->depth[i]] + fill[g->depth[i]]++] = i;
+  }
+  for (int i = 0; i < n; ++i) {
+    if (g->phase[i] == 0 || g->phase[i] > 7) OKRG_FAIL(g, OKR_E_PHASE, "node %d has phase mask %d", i, g->phase[i]);
+    if (i > 0 && (g->phase[i] & ~g->phase[g->parent[i]]))
+      OKRG_FAIL(g, OKR_E_PHASE, "phases of node %d are not a subset of its parent's", i);
+  }
+  // packed topology
+  g->topo_host.clear();
+  auto put = [&](const std::vector<int>& v) {
+    const size_t at = g->topo_host.size();
+    g->topo_host.insert(g->topo_host.end(), v.begin(), v.end());
+    return at;
+  };
+  g->t_parent = put(g->parent);
+  g->t_pos = put(g->pos);
+  g->t_size = put(g->size);
+  g->t_depth = put(g->depth);
+  g->t_lvl_off = put(g->lvl_off);
+  g->t_lvl_nodes = put(g->lvl_nodes);
+  g->t_ch_off = put(g->ch_off);
+  g->t_ch = put(g->ch);
+  size_t off = 0;
+  auto take = [&](size_t bytes) {
+    const size_t at = off;
+    off += (bytes + 255) & ~size_t(255);
+    return at;
+  };
+  const size_t c3 = (size_t)S * n * 3;
+  g->o_topo = take(sizeof(int) * g->topo_host.size());
+  g->o_phase = take(n);
+  g->o_z = take(sizeof(double2) * 9 * n);
+  g->o_Zr = take(sizeof(double2) * 9 * n);
+  g->o_Vhat = take(sizeof(double2) * c3);
+  g->o_A = take(sizeof(double2) * c3);
+  g->o_absV = take(sizeof(double) * c3);
+  g->o_I = take(sizeof(double2) * c3);
+  g->o_V = take(sizeof(double2) * c3);
+  g->o_Ib = take(sizeof(double2) * c3);
+  g->o_sup = take(sizeof(int) * n);
+  g->o_sm = take(sizeof(double) * 2 * n);
+  g->o_em = take(sizeof(double) * 2 * n);
+  g->o_steps = take(sizeof(GStep) * n);
+  g->o_gs = take(sizeof(GState));
+  g->o_status = take(sizeof(int) * 4);
+  g->o_iters = take(sizeof(int) * S);
+  g->o_err = take(sizeof(double) * S);
+  g->total = off;
+  *workspace_bytes = off;
+  g->planned = true;
+  return OKR_OK;
+}
+
+namespace {
+struct GPtrs {
+  int *topo, *parent, *pos, *size, *depth, *lvl_off, *lvl_nodes, *ch_off, *ch, *sup, *status, *iters;
+  uint8_t* phase;
+  double2 *z, *Zr, *Vhat, *A, *I, *V, *Ib;
+  double *absV, *sm, *em, *err;
+  GStep* steps;
+  GState* gs;
+};
+
+GPtrs gptrs(const okr_greedy* g, void* ws) {
+  char* b = (char*)ws;
+  GPtrs p;
+  p.topo = (int*)(b + g->o_topo);
+  p.parent = p.topo + g->t_parent;
+  p.pos = p.topo + g->t_pos;
+  p.size = p.topo + g->t_size;
+  p.depth = p.topo + g->t_depth;
+  p.lvl_off = p.topo + g->t_lvl_off;
+  p.lvl_nodes = p.topo + g->t_lvl_nodes;
+  p.ch_off = p.topo + g->t_ch_off;
+  p.ch = p.topo + g->t_ch;
+  p.phase = (uint8_t*)(b + g->o_phase);
+  p.z = (double2*)(b + g->o_z);
+  p.Zr = (double2*)(b + g->o_Zr);
+  p.Vhat = (double2*)(b + g->o_Vhat);
+  p.A = (double2*)(b + g->o_A);
+  p.absV = (double*)(b + g->o_absV);
+  p.I = (double2*)(b + g->o_I);
+  p.V = (double2*)(b + g->o_V);
+  p.Ib = (double2*)(b + g->o_Ib);
+  p.sup = (int*)(b + g->o_sup);
+  p.sm = (double*)(b + g->o_sm);
+  p.em = (double*)(b + g->o_em);
+  p.steps = (GStep*)(b + g->o_steps);
+  p.gs = (GState*)(b + g->o_gs);
+  p.status = (int*)(b + g->o_status);
+  p.iters = (int*)(b + g->o_iters);
+  p.err = (double*)(b + g->o_err);
+  return p;
+}
+
+// Common set-up of a run or an evaluation: topology upload, branch
+// impedances, impedances from the root, scenario library (load flow unless
+// V^ is given); returns the status word and the largest load-flow count.
+int setup(okr_greedy* g, const GPtrs& p, const okr_yblocks* Y, const okr_loads* L, const okr_greedy_params* prm) {
+  const hipStream_t st = g->stream;
+  const int n = g->n, S = g->S;
+  OKRG_HIP(g, hipMemcpyAsync(p.topo, g->topo_host.data(), sizeof(int) * g->topo_host.size(), hipMemcpyHostToDevice, st));
+  OKRG_HIP(g, hipMemcpyAsync(p.phase, g->phase.data(), n, hipMemcpyHostToDevice, st));
+  OKRG_HIP(g, hipMemsetAsync(p.status, 0, sizeof(int) * 4, st));
+  hipLaunchKernelGGL(k_branch_z, dim3((n + 127) / 128), dim3(128), 0, st, n, (const int*)p.parent,
+                     (const uint8_t*)p.phase, (const int*)p.ch_off, (const int*)p.ch, (const double2*)Y->Y_diag,
+                     (const double2*)Y->Y_off, p.z, p.status);
+  hipLaunchKernelGGL(k_zroot, dim3(1), dim3(256), 0, st, n, (const int*)p.parent, (const int*)p.lvl_off,
+                     (const int*)p.lvl_nodes, g->nlev, (const double2*)p.z, p.Zr);
+  const size_t c3 = (size_t)S * n * 3;
+  const double2* V0 = (const double2*)L->V0;
+  if (prm->flags & OKR_FLAG_VHAT_GIVEN) {
+    OKRG_HIP(g, hipMemcpyAsync(p.Vhat, L->Vhat, sizeof(double2) * c3, hipMemcpyDeviceToDevice, st));
+    hipLaunchKernelGGL(k_from_vhat, dim3((unsigned)((c3 + 255) / 256)), dim3(256), 0, st, n, S,
+                       (const uint8_t*)p.phase, (const double2*)L->S_load, (const double2*)p.Vhat, 0.0, 1e300, p.A,
+                       p.absV, p.status);
+  } else {
+    hipLaunchKernelGGL(k_powerflow, dim3(S), dim3(256), 0, st, n, (const int*)p.parent, (const uint8_t*)p.phase,
+                       (const int*)p.lvl_off, (const int*)p.lvl_nodes, g->nlev, (const int*)p.ch_off,
+                       (const int*)p.ch, (const double2*)p.z, (const double2*)L->S_load, V0[0], V0[1], V0[2],
+                       prm->pf_tol > 0 ? prm->pf_tol : 1e-13, prm->pf_maxit > 0 ? prm->pf_maxit : 100, 0.0, 1e300,
+                       p.Vhat, p.Ib, p.A, p.absV, p.iters, p.status);
+  }
+  OKRG_HIP(g, hipGetLastError());
+  return OKR_OK;
+}
+
+int check_status(okr_greedy* g, int hs) {
+  if (hs & 1) OKRG_FAIL(g, OKR_E_SINGULAR, "a present-phase branch block is singular");
+  if (hs & 2) OKRG_FAIL(g, OKR_E_PHASE, "nonzero admittance entries on absent phases");
+  if (hs & (4 | 8)) OKRG_FAIL(g, OKR_E_UNSUPPORTED, "admittance blocks asymmetric or with shunts");
+  if (hs & 16) OKRG_FAIL(g, OKR_E_PF_DIVERGED, "load flow did not converge");
+  return OKR_OK;
+}
+
+int check_call(okr_greedy* g, const okr_yblocks* Y, const okr_loads* L, const okr_greedy_params* prm, void* ws) {
+  if (!g->planned) OKRG_FAIL(g, OKR_E_ARG, "okr_greedy_plan has not succeeded");
+  if (!Y || !L || !prm || !Y->Y_diag || !Y->Y_off || !L->S_load || !L->V0) OKRG_FAIL(g, OKR_E_ARG, "null argument");
+  if (L->S != g->S) OKRG_FAIL(g, OKR_E_ARG, "loads->S = %d, planned for %d", L->S, g->S);
+  if ((prm->flags & OKR_FLAG_VHAT_GIVEN) && !L->Vhat) OKRG_FAIL(g, OKR_E_ARG, "OKR_FLAG_VHAT_GIVEN without Vhat");
+  if (!ws) OKRG_FAIL(g, OKR_E_WORKSPACE, "no workspace");
+  return OKR_OK;
+}
+}  // namespace
+
+extern "C" int okr_greedy_run(okr_greedy* g, const okr_yblocks* Y, const okr_loads* L, const okr_greedy_params* prm,
+                              void* ws, okr_greedy_result* out) {
+  if (!g) return OKR_E_ARG;
+  int rc = check_call(g, Y, L, prm, ws);
+  if (rc) return rc;
+  if (!out || !out->super || !out->steps || !out->err_per_snapshot) OKRG_FAIL(g, OKR_E_ARG, "null result buffer");
+  const int n = g->n, S = g->S;
+  if (S > kGreedyMaxS) OKRG_FAIL(g, OKR_E_UNSUPPORTED, "the search takes at most %d scenarios", kGreedyMaxS);
+  const size_t lds = sizeof(unsigned long long) * (size_t)S * n + sizeof(PathRec) * 2 * (size_t)g->nlev;
+  if ((size_t)S * n > kGreedyMaxSN || lds > 64 * 1024)
+    OKRG_FAIL(g, OKR_E_UNSUPPORTED, "S * n = %zu above %d, or the tree too deep, for the search's LDS tables",
+              (size_t)S * n, kGreedyMaxSN);
+  const hipStream_t st = g->stream;
+  const GPtrs p = gptrs(g, ws);
+  hipEvent_t ev[3];
+  for (auto& e : ev) OKRG_HIP(g, hipEventCreate(&e));
+  struct EvGuard {
+    hipEvent_t* e;
+    ~EvGuard() {
+      for (int i = 0; i < 3; ++i) (void)hipEventDestroy(e[i]);
+    }
+  } guard{ev};
+  OKRG_HIP(g, hipEventRecord(ev[0], st));
+  rc = setup(g, p, Y, L, prm);
+  if (rc) return rc;
+  const double2* V0 = (const double2*)L->V0;
+  const size_t c3 = (size_t)S * n * 3;
+  hipLaunchKernelGGL(k_greedy_init, dim3((unsigned)((std::max(c3, (size_t)n) + 255) / 256)), dim3(256), 0, st, n, S,
+                     (const double2*)p.A, p.I, p.sup, p.gs);
+  hipLaunchKernelGGL(k_greedy_sweep, dim3(S), dim3(kGreedyThreads), 0, st, n, (const int*)p.parent,
+                     (const uint8_t*)p.phase, (const int*)p.lvl_off, (const int*)p.lvl_nodes, g->nlev,
+                     (const int*)p.ch_off, (const int*)p.ch, (const double2*)p.z, V0[0], V0[1], V0[2],
+                     (const double2*)p.I, p.Ib, p.V);
+  OKRG_HIP(g, hipGetLastError());
+  OKRG_HIP(g, hipEventRecord(ev[1], st));
+  const double e_bar = prm->e_bar, tie = prm->tie_tol > 0 ? prm->tie_tol : 1e-11;
+  const double amb = prm->amb_tol > 0 ? prm->amb_tol : 1e-13;
+  const int cap = prm->max_iter > 0 ? std::min(prm->max_iter, n - 1) : n - 1;
+  GState hs{};
+  int enq = 0;
+  constexpr int kBatch = 32;  // moves enqueued between checks of the done flag
+  while (enq < cap) {
+    const int b = std::min(kBatch, cap - enq);
+    for (int t = 0; t < b; ++t) {
+      hipLaunchKernelGGL(k_greedy_score, dim3(2 * n), dim3(kGreedyThreads), lds, st, n, S, (const int*)p.parent,
+                         (const uint8_t*)p.phase, (const int*)p.pos, (const int*)p.size, (const int*)p.depth,
+                         (const int*)p.sup, (const double2*)p.Zr, (const double2*)p.I, (const double2*)p.V,
+                         (const double*)p.absV, e_bar, (const GState*)p.gs, p.sm, p.em);
+      hipLaunchKernelGGL(k_greedy_pick, dim3(1), dim3(1024), 0, st, 2 * n, (const int*)p.parent, (const int*)p.sup,
+                         (const double*)p.sm, (const double*)p.em, e_bar, tie, amb, cap, p.gs, p.steps);
+      hipLaunchKernelGGL(k_greedy_apply, dim3(S), dim3(kGreedyThreads), 0, st, n, (const int*)p.parent,
+                         (const uint8_t*)p.phase, (const int*)p.lvl_off, (const int*)p.lvl_nodes, g->nlev,
+                         (const int*)p.ch_off, (const int*)p.ch, (const double2*)p.z, V0[0], V0[1], V0[2],
+                         (const GState*)p.gs, p.sup, p.I, p.Ib, p.V);
+    }
+    OKRG_HIP(g, hipGetLastError());
+    enq += b;
+    OKRG_HIP(g, hipMemcpyAsync(&hs, p.gs, sizeof(GState), hipMemcpyDeviceToHost, st));
+    OKRG_HIP(g, hipStreamSynchronize(st));
+    if (hs.done) break;
+  }
+  OKRG_HIP(g, hipEventRecord(ev[2], st));
+  hipLaunchKernelGGL(k_greedy_err, dim3(S), dim3(kGreedyThreads), 0, st, n, (const uint8_t*)p.phase,
+                     (const int*)p.sup, (const double2*)p.V, (const double*)p.absV, p.err);
+  OKRG_HIP(g, hipGetLastError());
+  int status[4] = {0, 0, 0, 0};
+  std::vector<int> iters(S, 0);
+  OKRG_HIP(g, hipMemcpyAsync(status, p.status, sizeof(status), hipMemcpyDeviceToHost, st));
+  if (!(prm->flags & OKR_FLAG_VHAT_GIVEN))
+    OKRG_HIP(g, hipMemcpyAsync(iters.data(), p.iters, sizeof(int) * S, hipMemcpyDeviceToHost, st));
+  OKRG_HIP(g, hipMemcpyAsync(&hs, p.gs, sizeof(GState), hipMemcpyDeviceToHost, st));
+  OKRG_HIP(g, hipMemcpyAsync(out->super, p.sup, sizeof(int) * n, hipMemcpyDeviceToHost, st));
+  OKRG_HIP(g, hipMemcpyAsync(out->err_per_snapshot, p.err, sizeof(double) * S, hipMemcpyDeviceToHost, st));
+  OKRG_HIP(g, hipStreamSynchronize(st));
+  rc = check_status(g, status[0]);
+  if (rc) return rc;
+  if (hs.iter > 0)
+  {
+    OKRG_HIP(g, hipMemcpyAsync(out->steps, p.steps, sizeof(GStep) * hs.iter, hipMemcpyDeviceToHost, st));
+    OKRG_HIP(g, hipStreamSynchronize(st));
+  }
+  out->n_steps = hs.iter;
+  out->n_kept = n - hs.iter;
+  double mx = 0.0;
+  for (int l = 0; l < S; ++l) mx = std::max(mx, out->err_per_snapshot[l]);
+  out->max_err = mx;
+  float a = 0.f, b = 0.f;
+  OKRG_HIP(g, hipEventElapsedTime(&a, ev[0], ev[1]));
+  OKRG_HIP(g, hipEventElapsedTime(&b, ev[1], ev[2]));
+  out->t_pf_ms = a;
+  out->t_search_ms = b;
+  int im = 0;
+  for (int v : iters) im = std::max(im, v);
+  out->pf_iterations = im;
+  return OKR_OK;
+}
+
+extern "C" int okr_greedy_evaluate(okr_greedy* g, const okr_yblocks* Y, const okr_loads* L, const int32_t* super,
+                                   const okr_greedy_params* prm, void* ws, double* err, double* max_err) {
+  if (!g) return OKR_E_ARG;
+  int rc = check_call(g, Y, L, prm, ws);
+  if (rc) return rc;
+  if (!super || !err) OKRG_FAIL(g, OKR_E_ARG, "null assignment or output");
+  const int n = g->n, S = g->S;
+  // an assignment: supers are their own super, clusters are connected (the
+  // path from a member up to the cluster's top stays in the cluster) and a
+  // member's phases lie within its super-node's
+  std::vector<int> top(n, -1);
+  for (int x = 0; x < n; ++x) {
+    const int s = super[x];
+    if (s < 0 || s >= n || super[s] != s) OKRG_FAIL(g, OKR_E_ARG, "super[%d] = %d is not a super-node", x, s);
+    if (g->phase[x] & ~g->phase[s]) OKRG_FAIL(g, OKR_E_ARG, "node %d has phases outside its super-node's", x);
+  }
+  if (super[0] != 0) OKRG_FAIL(g, OKR_E_ARG, "the slack must stay its own super-node");
+  for (int x = 0; x < n; ++x) {  // each cluster has one node whose parent lies outside it
+    const int s = super[x];
+    if (x == 0 || super[g->parent[x]] != s) {
+      if (top[s] >= 0) OKRG_FAIL(g, OKR_E_ARG, "the cluster of super-node %d is not connected", s);
+      top[s] = x;
+    }
+  }
+  const GPtrs p = gptrs(g, ws);
+  const hipStream_t st = g->stream;
+  rc = setup(g, p, Y, L, prm);
+  if (rc) return rc;
+  const double2* V0 = (const double2*)L->V0;
+  OKRG_HIP(g, hipMemcpyAsync(p.sup, super, sizeof(int) * n, hipMemcpyHostToDevice, st));
+  hipLaunchKernelGGL(k_greedy_aggregate, dim3((S * 3 + 63) / 64), dim3(64), 0, st, n, S, (const int*)p.sup,
+                     (const double2*)p.A, p.I);
+  hipLaunchKernelGGL(k_greedy_sweep, dim3(S), dim3(kGreedyThreads), 0, st, n, (const int*)p.parent,
+                     (const uint8_t*)p.phase, (const int*)p.lvl_off, (const int*)p.lvl_nodes, g->nlev,
+                     (const int*)p.ch_off, (const int*)p.ch, (const double2*)p.z, V0[0], V0[1], V0[2],
+                     (const double2*)p.I, p.Ib, p.V);
+  hipLaunchKernelGGL(k_greedy_err, dim3(S), dim3(kGreedyThreads), 0, st, n, (const uint8_t*)p.phase,
+                     (const int*)p.sup, (const double2*)p.V, (const double*)p.absV, p.err);
+  OKRG_HIP(g, hipGetLastError());
+  int status[4] = {0, 0, 0, 0};
+  OKRG_HIP(g, hipMemcpyAsync(status, p.status, sizeof(status), hipMemcpyDeviceToHost, st));
+  OKRG_HIP(g, hipMemcpyAsync(err, p.err, sizeof(double) * S, hipMemcpyDeviceToHost, st));
+  OKRG_HIP(g, hipStreamSynchronize(st));
+  rc = check_status(g, status[0]);
+  if (rc) return rc;
+  if (max_err) {
+    double mx = 0.0;
+    for (int l = 0; l < S; ++l) mx = std::max(mx, err[l]);
+    *max_err = mx;
+  }
+  return OKR_OK;
+}

@@ -6,6 +6,6 @@ eligible-node mask and the segment ids.  It contains none of the search's
 arithmetic (no power flow, no Kron reduction, no scoring); both the HIP
 library and the CPU oracle consume what it produces.
 """
-from .feeders import CONFIGS, FeederConfig, make_feeder, dfs_preorder
+from .feeders import CONFIGS, FeederConfig, make_feeder, dfs_preorder, hourly_feeder, extreme_scenarios
 
-__all__ = ["CONFIGS", "FeederConfig", "make_feeder", "dfs_preorder"]
+__all__ = ["CONFIGS", "FeederConfig", "make_feeder", "dfs_preorder", "hourly_feeder", "extreme_scenarios"]

@@ -204,3 +204,25 @@ def make_feeder(cfg, seed: int, **overrides) -> dict:
         e_bar=cfg.e_bar, v_min=cfg.v_min, v_max=cfg.v_max, kappa=cfg.kappa,
         n_segments=sid,
     )
+
+
+def hourly_feeder(cfg, seed: int, hours: int = 168, **overrides) -> dict:
+    """A feeder of ``cfg`` (with overrides) whose scenarios are ``hours``
+    hourly load snapshots: every node's base load times a daily profile
+    (night trough, daytime peak) times a per-(hour, node) factor
+    U(0.85, 1.15).  Stands in for a week of hourly utility load data."""
+    f = make_feeder(cfg, seed, **dict(overrides, snapshots=1))
+    rng = np.random.default_rng(np.random.SeedSequence([2510_19608, seed, f["n"], hours]))
+    h = np.arange(hours) % 24
+    daily = 0.45 + 0.55 * np.clip(np.sin(np.pi * (h - 6) / 16.0), 0.0, None)
+    scale = daily[:, None] * rng.uniform(0.85, 1.15, size=(hours, f["n"]))
+    base = np.asarray(f["S_load"])[0]
+    return dict(f, snapshots=hours, S_load=np.ascontiguousarray(scale[:, :, None] * base[None, :, :]))
+
+
+def extreme_scenarios(f) -> dict:
+    """The feeder restricted to its highest- and lowest-loaded scenarios (by
+    total apparent power), in that order."""
+    tot = np.abs(np.asarray(f["S_load"])).sum(axis=(1, 2))
+    pick = [int(np.argmax(tot)), int(np.argmin(tot))]
+    return dict(f, snapshots=2, S_load=np.ascontiguousarray(np.asarray(f["S_load"])[pick]), hours_picked=pick)

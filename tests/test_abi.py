@@ -14,8 +14,9 @@ ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 
 
 def declared_functions():
-    src = open(os.path.join(ROOT, "include", "okr.h")).read()
-    return sorted(set(re.findall(r"^\s*(?:int|const char \*)\s*(okr_\w+)\s*\(", src, re.M)))
+    inc = os.path.join(ROOT, "include")
+    src = "".join(open(os.path.join(inc, h)).read() for h in sorted(os.listdir(inc)) if h.endswith(".h"))
+    return sorted(set(re.findall(r"^\s*(?:int|const char\s*\*)\s*(okr_\w+)\s*\(", src, re.M)))
 
 
 def test_library_exports_every_declared_symbol():
@@ -23,7 +24,8 @@ def test_library_exports_every_declared_symbol():
     L = okr.lib()
     names = declared_functions()
     assert {"okr_create", "okr_plan", "okr_reduce_feeder", "okr_destroy", "okr_last_error",
-            "okr_dump_scores"} <= set(names)
+            "okr_dump_scores", "okr_greedy_create", "okr_greedy_plan", "okr_greedy_run", "okr_greedy_evaluate",
+            "okr_greedy_destroy", "okr_greedy_last_error"} <= set(names)
     for name in names:
         assert hasattr(L, name), name
 
@@ -122,3 +124,28 @@ def test_product_sources_do_not_reference_the_oracle():
                 if fn.endswith((".py", ".hip", ".cpp", ".h")):
                     src = open(os.path.join(root, fn)).read()
                     assert "import oracle" not in src and "okr_oracle" not in src and "okro_" not in src, fn
+
+
+def test_greedy_plan_validation():
+    """Host-side checks of okr_greedy_plan: tree, phases, workspace size."""
+    import paper_2510_19608_amd as okr
+    f = make_feeder("c2", 0, n=100, snapshots=2)
+    g = okr.okr_greedy_create(None)
+    try:
+        ws = okr.okr_greedy_plan(g, f["parent"], f["phase"], 2)
+        assert ws > 6 * 2 * 100 * 3 * 16
+        bad = f["parent"].copy()
+        bad[5] = 7
+        bad[7] = 5
+        with pytest.raises(okr.OkrError) as e:
+            okr.okr_greedy_plan(g, bad, f["phase"], 2)
+        assert e.value.code == okr.OKR.E_NOT_TREE
+        ph = f["phase"].copy()
+        leaf = int(np.flatnonzero(f["parent"] > 0)[0])
+        ph[leaf] = 7
+        ph[f["parent"][leaf]] = 1
+        with pytest.raises(okr.OkrError) as e:
+            okr.okr_greedy_plan(g, f["parent"], ph, 2)
+        assert e.value.code == okr.OKR.E_PHASE
+    finally:
+        okr.okr_greedy_destroy(g)
