@@ -43,7 +43,7 @@ __global__ void k_zroot(int, const int*, const int*, const int*, int, const doub
 
 struct GState {
   int iter;  // moves applied
-  int done;  // no feasible candidate, or the move cap reached
+  int done;  // no feasible candidate left
   int s, r;  // the move chosen by the last pick
 };
 
@@ -57,6 +57,7 @@ struct PathRec {
 };
 
 constexpr int kGreedyThreads = 256;
+constexpr int kGreedyPickThreads = 1024;
 constexpr int kGreedyMaxS = 64;      // scenarios of a search (moved currents staged in LDS)
 constexpr int kGreedyMaxSN = 6144;   // scenarios x nodes of a search (cluster maxima in LDS)
 
@@ -140,10 +141,44 @@ __global__ __launch_bounds__(kGreedyThreads) void k_greedy_sweep(
   sweep_block(n, parent, phase, lvl_off, lvl_nodes, nlev, ch_off, ch, z, v0, Iagg + base, Ib + base, V + base);
 }
 
+// Root paths of r and s in LDS: pr[d] / ps[d] = the ancestor at depth d and
+// its DFS position range (every depth up to the node's own has one).
+__device__ __forceinline__ void load_paths(int n, const int* pos, const int* size, const int* depth, int r, int s,
+                                           PathRec* pr, PathRec* ps) {
+  const int qr = pos[r], qs = pos[s];
+  for (int u = threadIdx.x; u < n; u += blockDim.x) {
+    const int lo = pos[u], hi = lo + size[u];
+    if (lo <= qr && qr < hi) pr[depth[u]] = PathRec{u, lo, hi};
+    if (lo <= qs && qs < hi) ps[depth[u]] = PathRec{u, lo, hi};
+  }
+}
+
+// Voltage change at node y of moving load current J (one scenario, 3 phases)
+// from r to s: (Zroot(lca(y, r)) - Zroot(lca(y, s))) J; `moved` is false when
+// both lca are the same node (no change).
+struct MoveDelta {
+  double2 dZ[9];
+  bool moved;
+  __device__ __forceinline__ void at(const PathRec* pr, int dr, const PathRec* ps, int ds, const double2* Zr, int qy,
+                                     int dy) {
+    const int da = lca_depth(pr, min(dy, dr), qy), db = lca_depth(ps, min(dy, ds), qy);
+    moved = da != db;
+    if (moved) {
+      const double2* Za = Zr + (size_t)pr[da].node * 9;
+      const double2* Zb = Zr + (size_t)ps[db].node * 9;
+#pragma unroll
+      for (int q = 0; q < 9; ++q) dZ[q] = csub(Za[q], Zb[q]);
+    }
+  }
+  __device__ __forceinline__ double2 dv(int p, const double2* J) const {
+    return cadd(cadd(cmul(dZ[p * 3], J[0]), cmul(dZ[p * 3 + 1], J[1])), cmul(dZ[p * 3 + 2], J[2]));
+  }
+};
+
 // Score of one candidate per block (grid: 2n blocks, id = blockIdx.x):
 // SMICE (+inf when infeasible) and the largest error (-1 when the id is not a
-// candidate in this state).  Dynamic LDS: S * n cluster maxima (as uint64
-// bit patterns), then the two root paths.
+// candidate in this state).  Dynamic LDS: S * n cluster maxima (uint64 bit
+// patterns), then the two root paths.
 __global__ __launch_bounds__(kGreedyThreads) void k_greedy_score(
     int n, int S, const int* __restrict__ parent, const uint8_t* __restrict__ phase, const int* __restrict__ pos,
     const int* __restrict__ size, const int* __restrict__ depth, const int* __restrict__ sup,
@@ -176,28 +211,15 @@ __global__ __launch_bounds__(kGreedyThreads) void k_greedy_score(
   const int dr = depth[r], ds = depth[s];
   PathRec* ps = pr + dr + 1;
   for (int q = tid; q < S * n; q += kGreedyThreads) mice[q] = 0ull;
-  const int qr = pos[r], qs = pos[s];
-  for (int u = tid; u < n; u += kGreedyThreads) {
-    const int lo = pos[u], hi = lo + size[u];
-    if (lo <= qr && qr < hi) pr[depth[u]] = PathRec{u, lo, hi};
-    if (lo <= qs && qs < hi) ps[depth[u]] = PathRec{u, lo, hi};
-  }
+  load_paths(n, pos, size, depth, r, s, pr, ps);
   for (int q = tid; q < S * 3; q += kGreedyThreads) J[q] = Iagg[((size_t)(q / 3) * n + r) * 3 + q % 3];
   __syncthreads();
   double emax = 0.0;
   for (int xn = tid; xn < n; xn += kGreedyThreads) {
     int y = sup[xn];
     if (y == r) y = s;
-    const int qy = pos[y], dy = depth[y];
-    const int da = lca_depth(pr, min(dy, dr), qy), db = lca_depth(ps, min(dy, ds), qy);
-    double2 dZ[9];
-    const bool moved = da != db;  // equal depths: the same ancestor, no change
-    if (moved) {
-      const double2* Za = Zr + (size_t)pr[da].node * 9;
-      const double2* Zb = Zr + (size_t)ps[db].node * 9;
-#pragma unroll
-      for (int q = 0; q < 9; ++q) dZ[q] = csub(Za[q], Zb[q]);
-    }
+    MoveDelta md;
+    md.at(pr, dr, ps, ds, Zr, pos[y], depth[y]);
     const unsigned ph = phase[xn];
     for (int l = 0; l < S; ++l) {
       const size_t vb = ((size_t)l * n + y) * 3, xb = ((size_t)l * n + xn) * 3;
@@ -206,11 +228,7 @@ __global__ __launch_bounds__(kGreedyThreads) void k_greedy_score(
       for (int p = 0; p < 3; ++p) {
         if (!(ph >> p & 1u)) continue;
         double2 v = Vcur[vb + p];
-        if (moved) {
-          const double2 d = cadd(cadd(cmul(dZ[p * 3], J[l * 3]), cmul(dZ[p * 3 + 1], J[l * 3 + 1])),
-                                 cmul(dZ[p * 3 + 2], J[l * 3 + 2]));
-          v = cadd(v, d);
-        }
+        if (md.moved) v = cadd(v, md.dv(p, J + l * 3));
         ex = fmax(ex, fabs(absV[xb + p] - sqrt(cabs2(v))));
       }
       atomicMax(&mice[(size_t)l * n + y], (unsigned long long)__double_as_longlong(ex));
@@ -238,25 +256,26 @@ __global__ __launch_bounds__(kGreedyThreads) void k_greedy_score(
   }
 }
 
-// Choice of the iteration's move (one block of 1024): the smallest SMICE
-// among feasible candidates, ties within tie_tol to the lowest id; records
-// the step, or marks the search done.
-__global__ __launch_bounds__(1024) void k_greedy_pick(int ncand, const int* __restrict__ parent,
-                                                      const int* __restrict__ sup, const double* __restrict__ sm,
-                                                      const double* __restrict__ em, double e_bar, double tie,
-                                                      double amb, int max_iter, GState* __restrict__ gs,
-                                                      GStep* __restrict__ steps) {
-  __shared__ double shd[16];
-  __shared__ int shi[16];
+// The iteration's move (one block of 1024): the smallest SMICE among
+// feasible candidates, ties within tie_tol to the lowest id; the step is
+// recorded, r's current joins s's, r's cluster is reassigned, and every
+// node's voltage takes the move's change (the same expression the scoring
+// evaluated).  With no feasible candidate the search is marked done.
+// Dynamic LDS: the two root paths.
+__global__ __launch_bounds__(kGreedyPickThreads) void k_greedy_pick_apply(
+    int n, int S, const int* __restrict__ parent, const int* __restrict__ pos, const int* __restrict__ size,
+    const int* __restrict__ depth, const double2* __restrict__ Zr, const double* __restrict__ sm,
+    const double* __restrict__ em, double e_bar, double tie, double amb, GState* __restrict__ gs,
+    GStep* __restrict__ steps, int* __restrict__ sup, double2* __restrict__ Iagg, double2* __restrict__ V) {
+  extern __shared__ __align__(16) unsigned char g_lds[];
+  __shared__ double shd[kGreedyPickThreads / 64];
+  __shared__ int shi[kGreedyPickThreads / 64];
+  __shared__ double2 J[kGreedyMaxS * 3];
   if (gs->done) return;
-  if (max_iter > 0 && gs->iter >= max_iter) {
-    __syncthreads();
-    if (threadIdx.x == 0) gs->done = 1;
-    return;
-  }
+  const int tid = threadIdx.x, ncand = 2 * n;
   double mn = INFINITY;
   int nact = 0, nfeas = 0;
-  for (int c = threadIdx.x; c < ncand; c += blockDim.x) {
+  for (int c = tid; c < ncand; c += kGreedyPickThreads) {
     mn = fmin(mn, sm[c]);
     nact += em[c] >= 0.0;
     nfeas += sm[c] < INFINITY;
@@ -265,12 +284,12 @@ __global__ __launch_bounds__(1024) void k_greedy_pick(int ncand, const int* __re
   nact = block_reduce(nact, [](int a, int b) { return a + b; }, shi);
   nfeas = block_reduce(nfeas, [](int a, int b) { return a + b; }, shi);
   if (!(mn < INFINITY)) {
-    if (threadIdx.x == 0) gs->done = 1;
+    if (tid == 0) gs->done = 1;
     return;
   }
   const double thr = mn + tie;
   int win = 0x7fffffff, fl = 0;
-  for (int c = threadIdx.x; c < ncand; c += blockDim.x) {
+  for (int c = tid; c < ncand; c += kGreedyPickThreads) {
     const double v = sm[c];
     if (v <= thr) win = min(win, c);
     if (v < INFINITY && fabs(v - thr) <= amb) fl = 1;
@@ -278,9 +297,15 @@ __global__ __launch_bounds__(1024) void k_greedy_pick(int ncand, const int* __re
   }
   win = block_reduce(win, [](int a, int b) { return min(a, b); }, shi);
   fl = block_reduce(fl, [](int a, int b) { return max(a, b); }, shi);
-  if (threadIdx.x == 0) {
-    const int x = win >> 1, a = sup[x], b = sup[parent[x]];
-    const int r = (win & 1) ? b : a, s = (win & 1) ? a : b;
+  const int wx = win >> 1, wa = sup[wx], wb = sup[parent[wx]];
+  const int r = (win & 1) ? wb : wa, s = (win & 1) ? wa : wb;
+  PathRec* pr = (PathRec*)g_lds;
+  const int dr = depth[r], ds = depth[s];
+  PathRec* ps = pr + dr + 1;
+  load_paths(n, pos, size, depth, r, s, pr, ps);
+  for (int q = tid; q < S * 3; q += kGreedyPickThreads) J[q] = Iagg[((size_t)(q / 3) * n + r) * 3 + q % 3];
+  __syncthreads();  // sup and Iagg read by every thread before they change
+  if (tid == 0) {
     GStep st;
     st.cand = win;
     st.s = s;
@@ -295,29 +320,22 @@ __global__ __launch_bounds__(1024) void k_greedy_pick(int ncand, const int* __re
     gs->r = r;
     gs->iter += 1;
   }
-}
-
-// The chosen move (one block per scenario): r's current joins s's, the
-// scenario is solved again; block 0 also reassigns r's cluster to s.
-__global__ __launch_bounds__(kGreedyThreads) void k_greedy_apply(
-    int n, const int* __restrict__ parent, const uint8_t* __restrict__ phase, const int* __restrict__ lvl_off,
-    const int* __restrict__ lvl_nodes, int nlev, const int* __restrict__ ch_off, const int* __restrict__ ch,
-    const double2* __restrict__ z, double2 v0a, double2 v0b, double2 v0c, const GState* __restrict__ gs,
-    int* __restrict__ sup, double2* __restrict__ Iagg, double2* __restrict__ Ib, double2* __restrict__ V) {
-  if (gs->done) return;
-  const int s = gs->s, r = gs->r, l = blockIdx.x;
-  const size_t base = (size_t)l * n * 3;
-  if (threadIdx.x < 3) {
-    const int p = threadIdx.x;
-    Iagg[base + s * 3 + p] = cadd(Iagg[base + s * 3 + p], Iagg[base + r * 3 + p]);
-    Iagg[base + r * 3 + p] = make_double2(0.0, 0.0);
+  for (int q = tid; q < S * 3; q += kGreedyPickThreads) {
+    const size_t lr = ((size_t)(q / 3) * n + r) * 3 + q % 3, ls = ((size_t)(q / 3) * n + s) * 3 + q % 3;
+    Iagg[ls] = cadd(Iagg[ls], J[q]);
+    Iagg[lr] = make_double2(0.0, 0.0);
   }
-  if (l == 0)
-    for (int x = threadIdx.x; x < n; x += blockDim.x)
-      if (sup[x] == r) sup[x] = s;
-  __syncthreads();
-  const double2 v0[3] = {v0a, v0b, v0c};
-  sweep_block(n, parent, phase, lvl_off, lvl_nodes, nlev, ch_off, ch, z, v0, Iagg + base, Ib + base, V + base);
+  for (int u = tid; u < n; u += kGreedyPickThreads)
+    if (sup[u] == r) sup[u] = s;
+  for (int t = tid; t < n * S; t += kGreedyPickThreads) {
+    const int xn = t % n, l = t / n;
+    MoveDelta md;
+    md.at(pr, dr, ps, ds, Zr, pos[xn], depth[xn]);
+    if (!md.moved) continue;
+    const size_t vb = ((size_t)l * n + xn) * 3;
+#pragma unroll
+    for (int p = 0; p < 3; ++p) V[vb + p] = cadd(V[vb + p], md.dv(p, J + l * 3));
+  }
 }
 
 // I = A I^ for a given assignment: one thread per (scenario, phase) adds the
@@ -635,7 +653,9 @@ extern "C" int okr_greedy_run(okr_greedy* g, const okr_yblocks* Y, const okr_loa
   OKRG_HIP(g, hipEventRecord(ev[1], st));
   const double e_bar = prm->e_bar, tie = prm->tie_tol > 0 ? prm->tie_tol : 1e-11;
   const double amb = prm->amb_tol > 0 ? prm->amb_tol : 1e-13;
+  // at most one move per enqueued iteration: the cap is the number enqueued
   const int cap = prm->max_iter > 0 ? std::min(prm->max_iter, n - 1) : n - 1;
+  const size_t lds_paths = sizeof(PathRec) * 2 * (size_t)g->nlev;
   GState hs{};
   int enq = 0;
   constexpr int kBatch = 32;  // moves enqueued between checks of the done flag
@@ -646,12 +666,10 @@ extern "C" int okr_greedy_run(okr_greedy* g, const okr_yblocks* Y, const okr_loa
                          (const uint8_t*)p.phase, (const int*)p.pos, (const int*)p.size, (const int*)p.depth,
                          (const int*)p.sup, (const double2*)p.Zr, (const double2*)p.I, (const double2*)p.V,
                          (const double*)p.absV, e_bar, (const GState*)p.gs, p.sm, p.em);
-      hipLaunchKernelGGL(k_greedy_pick, dim3(1), dim3(1024), 0, st, 2 * n, (const int*)p.parent, (const int*)p.sup,
-                         (const double*)p.sm, (const double*)p.em, e_bar, tie, amb, cap, p.gs, p.steps);
-      hipLaunchKernelGGL(k_greedy_apply, dim3(S), dim3(kGreedyThreads), 0, st, n, (const int*)p.parent,
-                         (const uint8_t*)p.phase, (const int*)p.lvl_off, (const int*)p.lvl_nodes, g->nlev,
-                         (const int*)p.ch_off, (const int*)p.ch, (const double2*)p.z, V0[0], V0[1], V0[2],
-                         (const GState*)p.gs, p.sup, p.I, p.Ib, p.V);
+      hipLaunchKernelGGL(k_greedy_pick_apply, dim3(1), dim3(kGreedyPickThreads), lds_paths, st, n, S,
+                         (const int*)p.parent, (const int*)p.pos, (const int*)p.size, (const int*)p.depth,
+                         (const double2*)p.Zr, (const double*)p.sm, (const double*)p.em, e_bar, tie, amb, p.gs,
+                         p.steps, p.sup, p.I, p.V);
     }
     OKRG_HIP(g, hipGetLastError());
     enq += b;
