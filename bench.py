@@ -12,6 +12,9 @@ library's stream inside the timed region.  `modes` gives the time-to-optimal
 (median of repeated whole searches, graph-captured) of the plain, mixed
 precision and surrogate-pruned forms and their agreement with the plain
 decisions.  `cpu_baseline` is the FP64 CPU oracle on a bounded sample.
+`greedy_alg1` measures the paper's greedy single-move search (Algorithm 1)
+on 100-1000-node feeders with two extreme scenarios, the 168-hour
+robustness check of its 1000-node reduction, and its own oracle baseline.
 """
 import argparse
 import json
@@ -123,6 +126,86 @@ def surrogate_mode(f, args, plain_ms, ref, ncand):
                            train_loss_last=float(loss[-1]), train_s=t_train, collect_s=t_collect))
 
 
+GREEDY_SIZES = (100, 300, 500, 1000)
+
+
+def greedy_section(seed, reps=3, cpu=True):
+    """Algorithm 1 (the greedy single-move search) on the Table III workload
+    shape: sub-feeders of 100-1000 nodes with the highest- and lowest-loaded
+    of 168 hourly scenarios; the 168-hour robustness check of the 1000-node
+    reduction; and the oracle's scoring of one iteration as the CPU baseline.
+    Roofline of the candidate-scoring kernel: 9 flops per present node-phase
+    and scenario per candidate (voltage magnitude, error, maxima; the
+    voltage-change products of moved nodes are not counted, so this is a lower
+    bound) against the FP64 vector peak."""
+    import numpy as np
+    from paper_2510_19608_amd import Greedy
+    from synth_feeders import extreme_scenarios, hourly_feeder
+    out = {"workload": "Algorithm 1 on synthetic sub-feeders (1000-node generator, n nodes) with the highest- "
+                       "and lowest-loaded of 168 hourly scenarios, e_bar 0.003", "sizes": {}}
+    sup1000, fh1000 = None, None
+    for n in GREEDY_SIZES:
+        fh = hourly_feeder("c2", seed, n=n)
+        f = extreme_scenarios(fh)
+        G = Greedy(f)
+        G.run(f["e_bar"])
+        runs = [G.run(f["e_bar"], timing=True) for _ in range(reps)]
+        G.close()
+        r = runs[-1]
+        ms = statistics.median(x["t_search_ms"] for x in runs)
+        sms = statistics.median(x["t_score_ms"] for x in runs)
+        node_phases = int(sum(bin(int(v)).count("1") for v in f["phase"]))
+        flops = r["n_scored"] * 9.0 * node_phases * f["snapshots"]
+        achieved = flops / (sms * 1e-3) / 1e12 if sms > 0 else None
+        out["sizes"][str(n)] = dict(
+            moves=r["n_steps"], kept=r["n_kept"], reduction_pct=100.0 * (1 - r["n_kept"] / n), max_err=r["max_err"],
+            search_ms=ms, per_iteration_us=1e3 * ms / max(r["n_steps"], 1), candidates_scored=r["n_scored"],
+            candidates_per_s=r["n_scored"] / (ms * 1e-3),
+            score_kernel_avg_us=1e3 * sms / max(r["n_score_launches"], 1),
+            roofline={"bound": "alu", "achieved": achieved, "peak": FP64_VECTOR_PEAK_TFLOPS, "unit": "TFLOP/s",
+                      "frac": achieved / FP64_VECTOR_PEAK_TFLOPS if achieved else None, "traffic": None,
+                      "kernel": "okr::k_greedy_score"})
+        if n == 1000:
+            sup1000, fh1000 = r["super"], fh
+    E = Greedy(fh1000)
+    ts = []
+    for _ in range(reps + 1):
+        t0 = time.perf_counter()
+        err, mx = E.evaluate(sup1000)
+        ts.append((time.perf_counter() - t0) * 1e3)
+    E.close()
+    eb = 0.003
+    out["robustness_1000"] = dict(hours=int(len(err)), max_err=float(mx), mean_err=float(err.mean()),
+                                  p95_err=float(np.percentile(err, 95)), frac_within_e_bar=float((err <= eb).mean()),
+                                  evaluate_ms=statistics.median(ts[1:]))
+    if cpu:
+        out["cpu_baseline"] = greedy_cpu_baseline(seed)
+    return out
+
+
+def greedy_cpu_baseline(seed):
+    """The oracle scoring every candidate move of the first iteration of the
+    1000-node search (dense LU once, one solve per candidate and scenario),
+    on one thread."""
+    import numpy as np
+    from threadpoolctl import threadpool_limits
+    import oracle
+    from oracle import greedy as OG
+    from synth_feeders import extreme_scenarios, hourly_feeder
+    f = extreme_scenarios(hourly_feeder("c2", seed, n=1000))
+    V, I, _, _ = oracle.powerflow(f)
+    with threadpool_limits(limits=1):
+        t0 = time.perf_counter()
+        net = OG.Network(f)
+        sup = np.arange(f["n"])
+        cands = OG.candidates(f["parent"], f["phase"], sup)
+        OG.score(net, V, I, sup, cands, f["e_bar"])
+        dt = time.perf_counter() - t0
+    return dict(value=len(cands) / dt, unit="candidates/s", cores=1, kind="oracle",
+                sample=f"all {len(cands)} candidate moves of the first iteration of the 1000-node search "
+                       f"(LU factorisation included), {dt:.1f} s on 1 thread")
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -134,6 +217,7 @@ def main():
     ap.add_argument("--surr-epochs", type=int, default=6)
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-modes", action="store_true")
+    ap.add_argument("--no-greedy", action="store_true", help="skip the Algorithm 1 greedy-search section")
     ap.add_argument("--modes", default="plain,mixed,surrogate,factored",
                     help="comma-separated forms timed for time-to-optimal (plain is always timed)")
     ap.add_argument("--lanes", type=int, default=0,
@@ -234,6 +318,8 @@ def main():
             Rf.close()
             modes["factored_fp64"] = mode_entry("factored", ms, plain_ms, m, p, res, ref_masks, ref_pops, ncand)
         line["modes"] = modes
+    if not args.no_greedy:
+        line["greedy_alg1"] = greedy_section(args.seed, cpu=not args.no_cpu)
     if not args.no_cpu:
         line["cpu_baseline"] = cpu_baseline(f)
     print(json.dumps(line))

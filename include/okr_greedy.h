@@ -45,7 +45,8 @@ typedef struct {
   double tie_tol;    /* SMICE tie tolerance (1e-11 if 0) */
   double amb_tol;    /* ambiguity margin of the step flags (1e-13 if 0) */
   int32_t max_iter;  /* stop after this many moves (0: until none is feasible) */
-  uint32_t flags;    /* OKR_FLAG_VHAT_GIVEN: loads->Vhat holds V^ (no load flow) */
+  uint32_t flags;    /* OKR_FLAG_VHAT_GIVEN: loads->Vhat holds V^ (no load flow);
+                        OKR_FLAG_TIMING: time the candidate-scoring launches */
   double pf_tol;     /* load-flow stopping rule (1e-13 if 0) */
   int32_t pf_maxit;  /* load-flow iteration cap (100 if 0) */
   int32_t pad;
@@ -73,7 +74,12 @@ typedef struct {
   double t_pf_ms;            /* load flow and set-up, HIP events */
   double t_search_ms;        /* the iterations, HIP events */
   int32_t pf_iterations;     /* largest load-flow iteration count (0 when V^ given) */
-  int32_t pad;
+  int32_t n_score_launches;  /* candidate-scoring launches that ran */
+  double t_score_ms;         /* with OKR_FLAG_TIMING: summed duration of the
+                                candidate-scoring launches (HIP events on the
+                                handle's stream), else 0 */
+  int64_t n_scored;          /* candidates scored in the iterations that applied
+                                a move */
 } okr_greedy_result;
 
 /* Handle on a HIP stream (NULL = the null stream).  Returns OKR_E_ARG on a

@@ -103,7 +103,8 @@ class GreedyResult(ctypes.Structure):
     _fields_ = [("super", ctypes.c_void_p), ("steps", ctypes.c_void_p), ("err_per_snapshot", ctypes.c_void_p),
                 ("n_steps", ctypes.c_int32), ("n_kept", ctypes.c_int32), ("max_err", ctypes.c_double),
                 ("t_pf_ms", ctypes.c_double), ("t_search_ms", ctypes.c_double),
-                ("pf_iterations", ctypes.c_int32), ("pad", ctypes.c_int32)]
+                ("pf_iterations", ctypes.c_int32), ("n_score_launches", ctypes.c_int32),
+                ("t_score_ms", ctypes.c_double), ("n_scored", ctypes.c_int64)]
 
 
 _lib = None
@@ -492,19 +493,21 @@ class Greedy:
         self.res = GreedyResult(self.out_super.ctypes.data, ctypes.cast(self.out_steps, ctypes.c_void_p),
                                 self.out_err.ctypes.data)
 
-    def params(self, e_bar, max_iter=0, tie_tol=1e-11, amb_tol=1e-13):
-        return GreedyParams(e_bar, tie_tol, amb_tol, max_iter, self.flags, 0.0, 0, 0)
+    def params(self, e_bar, max_iter=0, tie_tol=1e-11, amb_tol=1e-13, timing=False):
+        flags = self.flags | (OKR.FLAG_TIMING if timing else 0)
+        return GreedyParams(e_bar, tie_tol, amb_tol, max_iter, flags, 0.0, 0, 0)
 
-    def run(self, e_bar, max_iter=0, tie_tol=1e-11, amb_tol=1e-13):
+    def run(self, e_bar, max_iter=0, tie_tol=1e-11, amb_tol=1e-13, timing=False):
         self.stream.wait_stream(self.torch.cuda.current_stream(self.device))
-        okr_greedy_run(self.g, self.Y, self.loads, self.params(e_bar, max_iter, tie_tol, amb_tol),
+        okr_greedy_run(self.g, self.Y, self.loads, self.params(e_bar, max_iter, tie_tol, amb_tol, timing),
                        ctypes.c_void_p(self.ws.data_ptr()), self.res)
         r = self.res
         steps = [dict(cand=s.cand, s=s.s, r=s.r, smice=s.smice, emax=s.emax, ambiguous=bool(s.ambiguous),
                       n_cand=s.n_cand, n_feasible=s.n_feasible) for s in list(self.out_steps)[:r.n_steps]]
         return dict(super=self.out_super.copy(), steps=steps, err_per_snapshot=self.out_err.copy(),
                     n_steps=r.n_steps, n_kept=r.n_kept, max_err=r.max_err, t_pf_ms=r.t_pf_ms,
-                    t_search_ms=r.t_search_ms, pf_iterations=r.pf_iterations)
+                    t_search_ms=r.t_search_ms, pf_iterations=r.pf_iterations,
+                    n_score_launches=r.n_score_launches, t_score_ms=r.t_score_ms, n_scored=r.n_scored)
 
     def evaluate(self, sup):
         self.stream.wait_stream(self.torch.cuda.current_stream(self.device))

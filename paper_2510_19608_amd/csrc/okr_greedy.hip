@@ -338,19 +338,18 @@ __global__ __launch_bounds__(kGreedyPickThreads) void k_greedy_pick_apply(
   }
 }
 
-// I = A I^ for a given assignment: one thread per (scenario, phase) adds the
-// members' currents in node order.
-__global__ void k_greedy_aggregate(int n, int S, const int* __restrict__ sup, const double2* __restrict__ A,
-                                   double2* __restrict__ Iagg) {
-  const int t = blockIdx.x * blockDim.x + threadIdx.x;
-  if (t >= S * 3) return;
-  const int l = t / 3, p = t % 3;
-  const size_t base = (size_t)l * n * 3;
-  for (int x = 0; x < n; ++x) Iagg[base + x * 3 + p] = make_double2(0.0, 0.0);
-  for (int x = 0; x < n; ++x) {
-    const size_t d = base + (size_t)sup[x] * 3 + p;
-    Iagg[d] = cadd(Iagg[d], A[base + x * 3 + p]);
-  }
+// I = A I^ for a given assignment: one thread per (scenario, node, phase)
+// adds its cluster's members' currents in node order (members of super-node
+// y: mem[moff[y] .. moff[y + 1]); zero for nodes that are not super-nodes).
+__global__ void k_greedy_aggregate(int n, int S, const int* __restrict__ moff, const int* __restrict__ mem,
+                                   const double2* __restrict__ A, double2* __restrict__ Iagg) {
+  const size_t t = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= (size_t)S * n * 3) return;
+  const int p = (int)(t % 3), y = (int)((t / 3) % n);
+  const size_t base = (t / 3 / n) * n * 3;
+  double2 acc = make_double2(0.0, 0.0);
+  for (int q = moff[y]; q < moff[y + 1]; ++q) acc = cadd(acc, A[base + (size_t)mem[q] * 3 + p]);
+  Iagg[t] = acc;
 }
 
 // Largest error of the current state per scenario (one block each): every
@@ -659,22 +658,45 @@ extern "C" int okr_greedy_run(okr_greedy* g, const okr_yblocks* Y, const okr_loa
   GState hs{};
   int enq = 0;
   constexpr int kBatch = 32;  // moves enqueued between checks of the done flag
+  const bool timing = (prm->flags & OKR_FLAG_TIMING) != 0;
+  std::vector<hipEvent_t> tev(timing ? 2 * kBatch : 0);
+  for (auto& e : tev) OKRG_HIP(g, hipEventCreate(&e));
+  struct TevGuard {
+    std::vector<hipEvent_t>* v;
+    ~TevGuard() {
+      for (hipEvent_t e : *v) (void)hipEventDestroy(e);
+    }
+  } tguard{&tev};
+  double score_ms = 0.0;
+  int launches = 0;
   while (enq < cap) {
     const int b = std::min(kBatch, cap - enq);
     for (int t = 0; t < b; ++t) {
+      if (timing) OKRG_HIP(g, hipEventRecord(tev[2 * t], st));
       hipLaunchKernelGGL(k_greedy_score, dim3(2 * n), dim3(kGreedyThreads), lds, st, n, S, (const int*)p.parent,
                          (const uint8_t*)p.phase, (const int*)p.pos, (const int*)p.size, (const int*)p.depth,
                          (const int*)p.sup, (const double2*)p.Zr, (const double2*)p.I, (const double2*)p.V,
                          (const double*)p.absV, e_bar, (const GState*)p.gs, p.sm, p.em);
+      if (timing) OKRG_HIP(g, hipEventRecord(tev[2 * t + 1], st));
       hipLaunchKernelGGL(k_greedy_pick_apply, dim3(1), dim3(kGreedyPickThreads), lds_paths, st, n, S,
                          (const int*)p.parent, (const int*)p.pos, (const int*)p.size, (const int*)p.depth,
                          (const double2*)p.Zr, (const double*)p.sm, (const double*)p.em, e_bar, tie, amb, p.gs,
                          p.steps, p.sup, p.I, p.V);
     }
     OKRG_HIP(g, hipGetLastError());
-    enq += b;
+    const int before = hs.iter;
     OKRG_HIP(g, hipMemcpyAsync(&hs, p.gs, sizeof(GState), hipMemcpyDeviceToHost, st));
     OKRG_HIP(g, hipStreamSynchronize(st));
+    // score launches that did work: one per move, plus the one that found none
+    const int ran = std::min(b, hs.iter - before + (hs.done ? 1 : 0));
+    launches += ran;
+    if (timing)
+      for (int t = 0; t < ran; ++t) {
+        float ms = 0.f;
+        OKRG_HIP(g, hipEventElapsedTime(&ms, tev[2 * t], tev[2 * t + 1]));
+        score_ms += ms;
+      }
+    enq += b;
     if (hs.done) break;
   }
   OKRG_HIP(g, hipEventRecord(ev[2], st));
@@ -699,6 +721,13 @@ extern "C" int okr_greedy_run(okr_greedy* g, const okr_yblocks* Y, const okr_loa
   }
   out->n_steps = hs.iter;
   out->n_kept = n - hs.iter;
+  out->n_score_launches = launches;
+  out->t_score_ms = score_ms;
+  {
+    int64_t sc = 0;
+    for (int i = 0; i < hs.iter; ++i) sc += out->steps[i].n_cand;
+    out->n_scored = sc;
+  }
   double mx = 0.0;
   for (int l = 0; l < S; ++l) mx = std::max(mx, out->err_per_snapshot[l]);
   out->max_err = mx;
@@ -742,9 +771,21 @@ extern "C" int okr_greedy_evaluate(okr_greedy* g, const okr_yblocks* Y, const ok
   rc = setup(g, p, Y, L, prm);
   if (rc) return rc;
   const double2* V0 = (const double2*)L->V0;
+  // members of every cluster in node order (CSR), staged in the candidate
+  // score buffers (unused by an evaluation)
+  std::vector<int> csr(2 * (size_t)n + 1, 0);
+  for (int x = 0; x < n; ++x) csr[super[x] + 1]++;
+  for (int y = 0; y < n; ++y) csr[y + 1] += csr[y];
+  {
+    std::vector<int> fill(csr.begin(), csr.begin() + n);
+    for (int x = 0; x < n; ++x) csr[n + 1 + fill[super[x]]++] = x;
+  }
+  int* moff = (int*)p.sm;
   OKRG_HIP(g, hipMemcpyAsync(p.sup, super, sizeof(int) * n, hipMemcpyHostToDevice, st));
-  hipLaunchKernelGGL(k_greedy_aggregate, dim3((S * 3 + 63) / 64), dim3(64), 0, st, n, S, (const int*)p.sup,
-                     (const double2*)p.A, p.I);
+  OKRG_HIP(g, hipMemcpyAsync(moff, csr.data(), sizeof(int) * csr.size(), hipMemcpyHostToDevice, st));
+  const size_t c3 = (size_t)S * n * 3;
+  hipLaunchKernelGGL(k_greedy_aggregate, dim3((unsigned)((c3 + 255) / 256)), dim3(256), 0, st, n, S,
+                     (const int*)moff, (const int*)(moff + n + 1), (const double2*)p.A, p.I);
   hipLaunchKernelGGL(k_greedy_sweep, dim3(S), dim3(kGreedyThreads), 0, st, n, (const int*)p.parent,
                      (const uint8_t*)p.phase, (const int*)p.lvl_off, (const int*)p.lvl_nodes, g->nlev,
                      (const int*)p.ch_off, (const int*)p.ch, (const double2*)p.z, V0[0], V0[1], V0[2],
