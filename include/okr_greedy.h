@@ -40,13 +40,21 @@ extern "C" {
 
 typedef struct okr_greedy okr_greedy;
 
+/* okr_greedy_params.flags: score candidates incrementally (only the clusters
+ * whose super-node lies under lca(r, s) towards r or s, and the merged
+ * cluster) even where every node of every candidate could be scored.  The
+ * incremental form is used anyway when S * n exceeds 6144; it needs
+ * n <= 12288.  Both forms give the same moves. */
+#define OKR_GREEDY_INCREMENTAL 0x100u
+
 typedef struct {
   double e_bar;      /* error bound of Algorithm 1 (p.u.), inclusive */
   double tie_tol;    /* SMICE tie tolerance (1e-11 if 0) */
   double amb_tol;    /* ambiguity margin of the step flags (1e-13 if 0) */
   int32_t max_iter;  /* stop after this many moves (0: until none is feasible) */
   uint32_t flags;    /* OKR_FLAG_VHAT_GIVEN: loads->Vhat holds V^ (no load flow);
-                        OKR_FLAG_TIMING: time the candidate-scoring launches */
+                        OKR_FLAG_TIMING: time the candidate-scoring launches;
+                        OKR_GREEDY_INCREMENTAL (below) */
   double pf_tol;     /* load-flow stopping rule (1e-13 if 0) */
   int32_t pf_maxit;  /* load-flow iteration cap (100 if 0) */
   int32_t pad;
@@ -80,6 +88,9 @@ typedef struct {
                                 handle's stream), else 0 */
   int64_t n_scored;          /* candidates scored in the iterations that applied
                                 a move */
+  int32_t incremental;       /* 1 when only the clusters a move can change were
+                                scored again (see OKR_GREEDY_INCREMENTAL) */
+  int32_t pad2;
 } okr_greedy_result;
 
 /* Handle on a HIP stream (NULL = the null stream).  Returns OKR_E_ARG on a
@@ -89,9 +100,9 @@ int okr_greedy_create(okr_greedy** g, void* hip_stream);
 /* Validates the tree (parent[0] = -1, every node reachable from node 0) and
  * the phases (1..7, each node's phases within its parent's), HOST arrays of n
  * entries, and reports the device workspace needed for S scenarios.  The
- * search (okr_greedy_run) additionally needs S <= 64 and S * n <= 6144 (its
- * per-candidate cluster table lives in LDS); okr_greedy_evaluate has no such
- * limit.
+ * search (okr_greedy_run) additionally needs S <= 64 (the moved currents are
+ * staged in LDS) and, when S * n > 6144, n <= 12288; okr_greedy_evaluate has
+ * no such limits.
  * Errors: OKR_E_ARG, OKR_E_NOT_TREE, OKR_E_PHASE. */
 int okr_greedy_plan(okr_greedy* g, int32_t n, const int32_t* parent, const uint8_t* phase, int32_t S,
                     size_t* workspace_bytes);
@@ -100,7 +111,7 @@ int okr_greedy_plan(okr_greedy* g, int32_t n, const int32_t* parent, const uint8
  * DEVICE, V0 HOST, loads->S must equal the planned S); d_workspace DEVICE of
  * at least the planned size; out's arrays HOST, caller-owned.  Synchronous
  * on the handle's stream.  Errors: OKR_E_ARG, OKR_E_WORKSPACE,
- * OKR_E_UNSUPPORTED (S * n above the limit, or shunts / asymmetric blocks),
+ * OKR_E_UNSUPPORTED (S or n above the limits, or shunts / asymmetric blocks),
  * OKR_E_SINGULAR, OKR_E_PHASE, OKR_E_PF_DIVERGED, OKR_E_HIP. */
 int okr_greedy_run(okr_greedy* g, const okr_yblocks* Y, const okr_loads* loads, const okr_greedy_params* p,
                    void* d_workspace, okr_greedy_result* out);

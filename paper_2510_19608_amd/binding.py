@@ -35,6 +35,7 @@ class OKR:
     FLAG_DUMP_SCORES = 4
     FLAG_GRAPH = 8
     FLAG_AUTOTUNE = 16
+    GREEDY_INCREMENTAL = 0x100
 
 
 class OkrError(RuntimeError):
@@ -104,7 +105,8 @@ class GreedyResult(ctypes.Structure):
                 ("n_steps", ctypes.c_int32), ("n_kept", ctypes.c_int32), ("max_err", ctypes.c_double),
                 ("t_pf_ms", ctypes.c_double), ("t_search_ms", ctypes.c_double),
                 ("pf_iterations", ctypes.c_int32), ("n_score_launches", ctypes.c_int32),
-                ("t_score_ms", ctypes.c_double), ("n_scored", ctypes.c_int64)]
+                ("t_score_ms", ctypes.c_double), ("n_scored", ctypes.c_int64), ("incremental", ctypes.c_int32),
+                ("pad2", ctypes.c_int32)]
 
 
 _lib = None
@@ -493,13 +495,14 @@ class Greedy:
         self.res = GreedyResult(self.out_super.ctypes.data, ctypes.cast(self.out_steps, ctypes.c_void_p),
                                 self.out_err.ctypes.data)
 
-    def params(self, e_bar, max_iter=0, tie_tol=1e-11, amb_tol=1e-13, timing=False):
-        flags = self.flags | (OKR.FLAG_TIMING if timing else 0)
+    def params(self, e_bar, max_iter=0, tie_tol=1e-11, amb_tol=1e-13, timing=False, incremental=False):
+        flags = self.flags | (OKR.FLAG_TIMING if timing else 0) | (OKR.GREEDY_INCREMENTAL if incremental else 0)
         return GreedyParams(e_bar, tie_tol, amb_tol, max_iter, flags, 0.0, 0, 0)
 
-    def run(self, e_bar, max_iter=0, tie_tol=1e-11, amb_tol=1e-13, timing=False):
+    def run(self, e_bar, max_iter=0, tie_tol=1e-11, amb_tol=1e-13, timing=False, incremental=False):
         self.stream.wait_stream(self.torch.cuda.current_stream(self.device))
-        okr_greedy_run(self.g, self.Y, self.loads, self.params(e_bar, max_iter, tie_tol, amb_tol, timing),
+        okr_greedy_run(self.g, self.Y, self.loads,
+                       self.params(e_bar, max_iter, tie_tol, amb_tol, timing, incremental),
                        ctypes.c_void_p(self.ws.data_ptr()), self.res)
         r = self.res
         steps = [dict(cand=s.cand, s=s.s, r=s.r, smice=s.smice, emax=s.emax, ambiguous=bool(s.ambiguous),
@@ -507,7 +510,8 @@ class Greedy:
         return dict(super=self.out_super.copy(), steps=steps, err_per_snapshot=self.out_err.copy(),
                     n_steps=r.n_steps, n_kept=r.n_kept, max_err=r.max_err, t_pf_ms=r.t_pf_ms,
                     t_search_ms=r.t_search_ms, pf_iterations=r.pf_iterations,
-                    n_score_launches=r.n_score_launches, t_score_ms=r.t_score_ms, n_scored=r.n_scored)
+                    n_score_launches=r.n_score_launches, t_score_ms=r.t_score_ms, n_scored=r.n_scored,
+                    incremental=bool(r.incremental))
 
     def evaluate(self, sup):
         self.stream.wait_stream(self.torch.cuda.current_stream(self.device))
@@ -528,11 +532,11 @@ class Greedy:
             pass
 
 
-def greedy(f, e_bar=None, device="cuda:0", vhat=None, max_iter=0):
+def greedy(f, e_bar=None, device="cuda:0", vhat=None, max_iter=0, incremental=False):
     """Run Algorithm 1 once on a feeder dict and return the result dict."""
     G = Greedy(f, device=device, vhat=vhat)
     try:
-        return G.run(f["e_bar"] if e_bar is None else e_bar, max_iter=max_iter)
+        return G.run(f["e_bar"] if e_bar is None else e_bar, max_iter=max_iter, incremental=incremental)
     finally:
         G.close()
 

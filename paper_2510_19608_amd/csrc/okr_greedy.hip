@@ -6,15 +6,18 @@
 // currents fixed its solution is V = V0 - sum_j Zcp(., j) I_j, where Zcp(y, j)
 // is the series impedance of the common part of the root paths of y and j,
 // i.e. Zroot(lca(y, j)).  Moving the aggregated load current J of super-node
-// r to super-node s therefore changes every voltage by
+// r to super-node s therefore changes node y's voltage by
 //     dV_y = (Zroot(lca(y, r)) - Zroot(lca(y, s))) J,
-// which vanishes outside the subtree of lca(r, s).  One block scores one
-// candidate: the root paths of r and s go to LDS (position ranges of their
-// DFS subtrees by depth, so lca(y, r) is a binary search), each node takes
-// its post-move super-node's voltage, and the cluster maxima (MICE) gather
-// in an LDS table by atomic max on the bit patterns of non-negative doubles.
-// The applied move refreshes the state by a fresh fixed-current sweep (no
-// accumulated updates), so every iteration starts from the exact solve.
+// which is nonzero exactly on the subtrees of w = lca(r, s)'s children
+// towards r and towards s.  Lowest common ancestors are O(1) lookups in a
+// sparse table over the Euler tour (built once per topology).  Every
+// iteration keeps each cluster's MICE, their total, block maxima over DFS
+// positions and the member lists; one block scores one candidate by
+// re-scoring only the clusters whose super-node lies in those two subtrees
+// and the merged cluster, and one block picks the move, applies it to the
+// voltages with the scoring's expression and rebuilds the cluster state.
+// A search starts from the exact fixed-current solve (a level-synchronous
+// sweep), which also serves the evaluation of a given assignment.
 
 #include <hip/hip_runtime.h>
 
@@ -52,25 +55,180 @@ struct GStep {  // layout of okr_greedy_step
   double smice, emax;
 };
 
-struct PathRec {
-  int node, lo, hi;  // an ancestor and the DFS position range of its subtree
-};
-
 constexpr int kGreedyThreads = 256;
 constexpr int kGreedyPickThreads = 1024;
 constexpr int kGreedyMaxS = 64;      // scenarios of a search (moved currents staged in LDS)
-constexpr int kGreedyMaxSN = 6144;   // scenarios x nodes of a search (cluster maxima in LDS)
+constexpr int kGreedyMaxN = 12288;   // nodes of a search (member counts in LDS)
+constexpr int kSmallCluster = 32;   // clusters up to this size are scored by one lane
+constexpr int kGreedyFullSN = 6144;  // S x n up to which every candidate scores every node
 
-// Depth of lca(y, t) where path[d] is t's ancestor at depth d (d <= dmax) and
-// q is y's DFS position: the deepest d whose subtree range holds q.
-__device__ __forceinline__ int lca_depth(const PathRec* path, int dmax, int q) {
-  int lo = 0, hi = dmax;
+// O(1) lowest common ancestors: the Euler tour of the DFS (E = 2n - 1
+// entries), every node's first index in it, and a sparse table of the
+// shallowest node over power-of-two ranges of the tour (level k at st[k * E]).
+struct LcaTab {
+  const int* first;
+  const int* st;
+  const int* depth;
+  int E;
+  __device__ __forceinline__ int lca(int u, int v) const {
+    int a = first[u], b = first[v];
+    if (a > b) {
+      const int t = a;
+      a = b;
+      b = t;
+    }
+    const int k = 31 - __clz(b - a + 1);
+    const int x = st[(size_t)k * E + a], y = st[(size_t)k * E + b - (1 << k) + 1];
+    return depth[x] <= depth[y] ? x : y;
+  }
+};
+
+// The child of w whose subtree holds t (t strictly below w): children are
+// stored in increasing DFS position.
+__device__ __forceinline__ int child_toward(const int* ch_off, const int* ch, const int* pos, int w, int t) {
+  int lo = ch_off[w], hi = ch_off[w + 1] - 1;
+  const int q = pos[t];
   while (lo < hi) {
     const int mid = (lo + hi + 1) >> 1;
-    if (path[mid].lo <= q && q < path[mid].hi) lo = mid;
+    if (pos[ch[mid]] <= q) lo = mid;
     else hi = mid - 1;
   }
-  return lo;
+  return ch[lo];
+}
+
+// Voltage change at node y of moving load current J (one scenario, 3 phases)
+// from r to s: (Zroot(lca(y, r)) - Zroot(lca(y, s))) J; `moved` is false when
+// both lca are the same node (no change).
+struct MoveDelta {
+  double2 dZ[9];
+  bool moved;
+  __device__ __forceinline__ void at(const LcaTab& T, const double2* Zr, int y, int r, int s) {
+    const int a = T.lca(y, r), b = T.lca(y, s);
+    moved = a != b;
+    if (moved) {
+      const double2* Za = Zr + (size_t)a * 9;
+      const double2* Zb = Zr + (size_t)b * 9;
+#pragma unroll
+      for (int q = 0; q < 9; ++q) dZ[q] = csub(Za[q], Zb[q]);
+    }
+  }
+  __device__ __forceinline__ double2 dv(int p, const double2* J) const {
+    return cadd(cadd(cmul(dZ[p * 3], J[0]), cmul(dZ[p * 3 + 1], J[1])), cmul(dZ[p * 3 + 2], J[2]));
+  }
+};
+
+// Per-iteration cluster state (device): MICE of every cluster per scenario
+// (0 for nodes that are not super-nodes), their sum, the largest MICE over
+// scenarios by DFS position and its maxima over blocks of 64 positions, and
+// every cluster's members (CSR, any order: only maxima are taken over them).
+// The member counts are built in LDS: a search takes at most kGreedyMaxN
+// nodes.
+struct Clusters {
+  double* mice;   // [S][n]
+  double* arr;    // [n], by DFS position
+  double* bmax;   // [ceil(n / 64)]
+  int* moff;      // [n + 1]
+  int* mem;       // [n]
+  double* tot;    // [1]
+};
+
+// Largest error over scenarios' phases of member x against magnitudes mag
+// (3 per scenario): e_l = max_p ||V^_x| - mag_p|.
+__device__ __forceinline__ double member_err(const double* absV, int n, int x, int l, unsigned ph,
+                                             const double* mag) {
+  const size_t xb = ((size_t)l * n + x) * 3;
+  double e = 0.0;
+#pragma unroll
+  for (int p = 0; p < 3; ++p)
+    if (ph >> p & 1u) e = fmax(e, fabs(absV[xb + p] - mag[p]));
+  return e;
+}
+
+// Builds the cluster state of the current assignment and voltages (one
+// block; called with every thread).  Member counts and fill pointers live in
+// LDS (lcnt, n ints); every cluster's MICE is a wave-wide maximum over its
+// members (one wave per super-node, 64 members at a time), so large clusters
+// cost neither serial walks nor same-address atomics.
+__device__ void cluster_prep(int n, int S, const uint8_t* phase, const int* pre, const int* sup, const double2* V,
+                             const double* absV, const Clusters& C, int* lcnt, int* shi, double* shd) {
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6, nw = blockDim.x >> 6;
+  for (int y = threadIdx.x; y < n; y += blockDim.x) lcnt[y] = 0;
+  __syncthreads();
+  for (int x = threadIdx.x; x < n; x += blockDim.x) atomicAdd(&lcnt[sup[x]], 1);
+  __syncthreads();
+  // member offsets: each thread scans a contiguous chunk, the chunk sums are
+  // scanned across the block
+  const int chunk = (n + blockDim.x - 1) / blockDim.x, c0 = threadIdx.x * chunk, c1 = min(n, c0 + chunk);
+  int loc = 0;
+  for (int y = c0; y < c1; ++y) loc += lcnt[y];
+  const int base = block_exclusive_scan(loc, shi);
+  for (int y = c0, acc = base; y < c1; ++y) {
+    const int c = lcnt[y];
+    C.moff[y] = acc;
+    lcnt[y] = acc;  // fill pointer
+    acc += c;
+  }
+  if (threadIdx.x == blockDim.x - 1) C.moff[n] = base + loc;
+  __syncthreads();
+  for (int x = threadIdx.x; x < n; x += blockDim.x) C.mem[atomicAdd(&lcnt[sup[x]], 1)] = x;
+  __syncthreads();
+  // MICE of every cluster (0 for nodes that are not super-nodes): a lane
+  // takes a cluster of at most kSmallCluster members, a wave the larger ones
+  for (int y0 = wv * 64; y0 < n; y0 += nw * 64) {
+    const int y = y0 + lane;
+    const bool is = y < n && sup[y] == y;
+    const int m0 = is ? C.moff[y] : 0, m1 = is ? C.moff[y + 1] : 0;
+    const bool big = is && m1 - m0 > kSmallCluster;
+    if (y < n && !big)
+      for (int l = 0; l < S; ++l) {
+        double mx = 0.0;
+        if (is) {
+          double mag[3];
+#pragma unroll
+          for (int p = 0; p < 3; ++p) mag[p] = sqrt(cabs2(V[((size_t)l * n + y) * 3 + p]));
+          for (int k = m0; k < m1; ++k) {
+            const int m = C.mem[k];
+            mx = fmax(mx, member_err(absV, n, m, l, phase[m], mag));
+          }
+        }
+        C.mice[(size_t)l * n + y] = mx;
+      }
+    unsigned long long mask = __ballot(big);
+    while (mask) {
+      const int bit = __ffsll((long long)mask) - 1;
+      mask &= mask - 1;
+      const int u = y0 + bit, k0 = __shfl(m0, bit, 64), k1 = __shfl(m1, bit, 64);
+      for (int l = 0; l < S; ++l) {
+        double mag[3];
+#pragma unroll
+        for (int p = 0; p < 3; ++p) mag[p] = sqrt(cabs2(V[((size_t)l * n + u) * 3 + p]));
+        double mx = 0.0;
+        for (int k = k0 + lane; k < k1; k += 64) {
+          const int m = C.mem[k];
+          mx = fmax(mx, member_err(absV, n, m, l, phase[m], mag));
+        }
+        for (int o = 32; o > 0; o >>= 1) mx = fmax(mx, __shfl_xor(mx, o, 64));
+        if (lane == 0) C.mice[(size_t)l * n + u] = mx;
+      }
+    }
+  }
+  __syncthreads();
+  for (int q = threadIdx.x; q < n; q += blockDim.x) {
+    double m = 0.0;
+    for (int l = 0; l < S; ++l) m = fmax(m, C.mice[(size_t)l * n + pre[q]]);
+    C.arr[q] = m;
+  }
+  double t = 0.0;
+  for (int q = threadIdx.x; q < S * n; q += blockDim.x) t += C.mice[q];
+  t = block_reduce(t, [](double a, double b) { return a + b; }, shd);
+  __syncthreads();
+  for (int k = threadIdx.x; k < (n + 63) / 64; k += blockDim.x) {
+    double m = 0.0;
+    for (int q = k * 64; q < min(n, k * 64 + 64); ++q) m = fmax(m, C.arr[q]);
+    C.bmax[k] = m;
+  }
+  if (threadIdx.x == 0) *C.tot = t;
+  __syncthreads();
 }
 
 // Fixed-current solve of one scenario on the radial network: branch currents
@@ -141,6 +299,303 @@ __global__ __launch_bounds__(kGreedyThreads) void k_greedy_sweep(
   sweep_block(n, parent, phase, lvl_off, lvl_nodes, nlev, ch_off, ch, z, v0, Iagg + base, Ib + base, V + base);
 }
 
+// Cluster state of the search's starting point (one block).
+__global__ __launch_bounds__(kGreedyPickThreads) void k_greedy_prep(int n, int S, const uint8_t* __restrict__ phase,
+                                                                    const int* __restrict__ pre,
+                                                                    const int* __restrict__ sup,
+                                                                    const double2* __restrict__ V,
+                                                                    const double* __restrict__ absV, Clusters C) {
+  extern __shared__ __align__(16) unsigned char g_lds[];
+  __shared__ int shi[kGreedyPickThreads];
+  __shared__ double shd[kGreedyPickThreads / 64];
+  cluster_prep(n, S, phase, pre, sup, V, absV, C, (int*)g_lds, shi, shd);
+}
+
+// Score of one candidate per block (grid: 2n blocks, id = blockIdx.x):
+// SMICE (+inf when infeasible) and the largest error (-1 when the id is not a
+// candidate in this state).  Only the clusters the move can change are
+// scored again: with w = lca(r, s), voltages change exactly on the subtrees
+// of w's children towards r and towards s (DFS intervals I_r, I_s), so the
+// clusters whose super-node lies there (which, other than r's and s's, lie
+// wholly inside them) and the merged cluster s + r; every other cluster keeps
+// its MICE.  SMICE = (total - old MICE of the changed clusters) + their new
+// MICE; the largest error is the maximum of the new MICE and of the other
+// clusters' (block maxima over DFS positions outside the intervals and w).
+__global__ __launch_bounds__(kGreedyThreads) void k_greedy_score(
+    int n, int S, const int* __restrict__ parent, const uint8_t* __restrict__ phase, const int* __restrict__ pos,
+    const int* __restrict__ size, const int* __restrict__ pre, const int* __restrict__ ch_off,
+    const int* __restrict__ ch, const int* __restrict__ sup, LcaTab T, const double2* __restrict__ Zr,
+    const double2* __restrict__ Iagg, const double2* __restrict__ Vcur, const double* __restrict__ absV,
+    double e_bar, const GState* __restrict__ gs, Clusters C, double* __restrict__ sm, double* __restrict__ em) {
+  __shared__ double2 J[kGreedyMaxS * 3];
+  __shared__ double magS[kGreedyMaxS * 3];
+  __shared__ unsigned long long newS[kGreedyMaxS];
+  __shared__ double red[kGreedyThreads / 64];
+  if (gs->done) return;
+  const int cand = blockIdx.x, x = cand >> 1, dir = cand & 1, tid = threadIdx.x;
+  int r = -1, s = -1;
+  if (x > 0) {
+    const int a = sup[x], b = sup[parent[x]];
+    if (a != b) {
+      r = dir ? b : a;
+      s = dir ? a : b;
+      if (r == 0 || (phase[r] & ~phase[s])) r = -1;
+    }
+  }
+  if (r < 0) {  // not a candidate (uniform over the block)
+    if (tid == 0) {
+      sm[cand] = INFINITY;
+      em[cand] = -1.0;
+    }
+    return;
+  }
+  const int w = T.lca(r, s);
+  int a1 = 0, b1 = 0, a2 = 0, b2 = 0;  // I_r = [a1, b1), I_s = [a2, b2)
+  if (r != w) {
+    const int c = child_toward(ch_off, ch, pos, w, r);
+    a1 = pos[c];
+    b1 = a1 + size[c];
+  }
+  if (s != w) {
+    const int c = child_toward(ch_off, ch, pos, w, s);
+    a2 = pos[c];
+    b2 = a2 + size[c];
+  }
+  const int qw = pos[w];
+  MoveDelta msd;
+  msd.at(T, Zr, s, r, s);
+  for (int q = tid; q < S * 3; q += kGreedyThreads) {
+    J[q] = Iagg[((size_t)(q / 3) * n + r) * 3 + q % 3];
+  }
+  for (int l = tid; l < S; l += kGreedyThreads) newS[l] = 0ull;
+  __syncthreads();
+  for (int q = tid; q < S * 3; q += kGreedyThreads) {
+    const int l = q / 3, p = q % 3;
+    double2 v = Vcur[((size_t)l * n + s) * 3 + p];
+    if (msd.moved) v = cadd(v, msd.dv(p, J + l * 3));
+    magS[q] = sqrt(cabs2(v));
+  }
+  __syncthreads();
+  double olds = 0.0, news = 0.0, emx = 0.0;
+  // clusters whose super-node lies in I_r or I_s (other than r and s): each
+  // wave takes 64 positions at a time; a lane scores the cluster of its
+  // position when it has at most kSmallCluster members, and the wave scores
+  // the larger ones together (64 members at a time)
+  {
+    const int lane = tid & 63, wv = tid >> 6;
+    for (int iv = 0; iv < 2; ++iv) {
+      const int lo = iv ? a2 : a1, hi = iv ? b2 : b1;
+      for (int c0 = lo + wv * 64; c0 < hi; c0 += kGreedyThreads) {
+        const int q = c0 + lane;
+        int u = -1, m0 = 0, m1 = 0;
+        bool is = false;
+        if (q < hi) {
+          u = pre[q];
+          is = sup[u] == u && u != r && u != s;
+          if (is) {
+            m0 = C.moff[u];
+            m1 = C.moff[u + 1];
+          }
+        }
+        const bool big = is && m1 - m0 > kSmallCluster;
+        if (is && !big) {
+          MoveDelta md;
+          md.at(T, Zr, u, r, s);
+          for (int l = 0; l < S; ++l) {
+            double mag[3];
+#pragma unroll
+            for (int p = 0; p < 3; ++p) {
+              double2 v = Vcur[((size_t)l * n + u) * 3 + p];
+              if (md.moved) v = cadd(v, md.dv(p, J + l * 3));
+              mag[p] = sqrt(cabs2(v));
+            }
+            double mx = 0.0;
+            for (int k = m0; k < m1; ++k) {
+              const int m = C.mem[k];
+              mx = fmax(mx, member_err(absV, n, m, l, phase[m], mag));
+            }
+            olds += C.mice[(size_t)l * n + u];
+            news += mx;
+            emx = fmax(emx, mx);
+          }
+        }
+        unsigned long long mask = __ballot(big);
+        while (mask) {
+          const int bit = __ffsll((long long)mask) - 1;
+          mask &= mask - 1;
+          const int uu = __shfl(u, bit, 64), k0 = __shfl(m0, bit, 64), k1 = __shfl(m1, bit, 64);
+          MoveDelta md;
+          md.at(T, Zr, uu, r, s);
+          for (int l = 0; l < S; ++l) {
+            double mag[3];
+#pragma unroll
+            for (int p = 0; p < 3; ++p) {
+              double2 v = Vcur[((size_t)l * n + uu) * 3 + p];
+              if (md.moved) v = cadd(v, md.dv(p, J + l * 3));
+              mag[p] = sqrt(cabs2(v));
+            }
+            double mx = 0.0;
+            for (int k = k0 + lane; k < k1; k += 64) {
+              const int m = C.mem[k];
+              mx = fmax(mx, member_err(absV, n, m, l, phase[m], mag));
+            }
+            for (int o = 32; o > 0; o >>= 1) mx = fmax(mx, __shfl_xor(mx, o, 64));
+            if (lane == 0) {
+              olds += C.mice[(size_t)l * n + uu];
+              news += mx;
+              emx = fmax(emx, mx);
+            }
+          }
+        }
+      }
+    }
+  }
+  // the merged cluster: r's members, and s's own when s's voltage moves
+  for (int pass = 0; pass < 2; ++pass) {
+    const int y = pass ? s : r;
+    if (pass && !msd.moved) break;
+    for (int k = C.moff[y] + tid; k < C.moff[y + 1]; k += kGreedyThreads) {
+      const int m = C.mem[k];
+      const unsigned ph = phase[m];
+      for (int l = 0; l < S; ++l)
+        atomicMax(&newS[l], (unsigned long long)__double_as_longlong(member_err(absV, n, m, l, ph, magS + l * 3)));
+    }
+  }
+  // every other cluster keeps its MICE: largest over positions outside
+  // I_r, I_s and w's
+  double umax = 0.0;
+  const int nb = (n + 63) / 64;
+  for (int k = tid; k < nb; k += kGreedyThreads) {
+    const int lo = k * 64, hi = min(n, lo + 64);
+    const bool touch = (lo <= qw && qw < hi) || (lo < b1 && a1 < hi) || (lo < b2 && a2 < hi);
+    if (!touch) {
+      umax = fmax(umax, C.bmax[k]);
+      continue;
+    }
+    for (int q = lo; q < hi; ++q)
+      if (q != qw && !(a1 <= q && q < b1) && !(a2 <= q && q < b2)) umax = fmax(umax, C.arr[q]);
+  }
+  __syncthreads();
+  olds = block_reduce(olds, [](double a, double b) { return a + b; }, red);
+  news = block_reduce(news, [](double a, double b) { return a + b; }, red);
+  emx = block_reduce(fmax(emx, umax), [](double a, double b) { return fmax(a, b); }, red);
+  if (tid == 0) {
+    for (int l = 0; l < S; ++l) {
+      double v = __longlong_as_double((long long)newS[l]);
+      if (!msd.moved) v = fmax(v, C.mice[(size_t)l * n + s]);
+      olds += C.mice[(size_t)l * n + s] + C.mice[(size_t)l * n + r];
+      news += v;
+      emx = fmax(emx, v);
+    }
+    em[cand] = emx;
+    sm[cand] = emx <= e_bar ? (*C.tot - olds) + news : INFINITY;
+  }
+}
+
+// The iteration's move (one block of 1024): the smallest SMICE among
+// feasible candidates, ties within tie_tol to the lowest id; the step is
+// recorded, r's current joins s's, r's cluster is reassigned, every node's
+// voltage takes the move's change (the expression the scoring evaluated),
+// and the cluster state is rebuilt.  With no feasible candidate the search
+// is marked done.
+__global__ __launch_bounds__(kGreedyPickThreads) void k_greedy_pick_apply(
+    int n, int S, const int* __restrict__ parent, const uint8_t* __restrict__ phase, const int* __restrict__ pre,
+    LcaTab T, const double2* __restrict__ Zr, const double* __restrict__ absV, const double* __restrict__ sm,
+    const double* __restrict__ em, double e_bar, double tie, double amb, GState* __restrict__ gs,
+    GStep* __restrict__ steps, int* __restrict__ sup, double2* __restrict__ Iagg, double2* __restrict__ V,
+    Clusters C) {
+  extern __shared__ __align__(16) unsigned char g_lds[];
+  __shared__ double shd[kGreedyPickThreads / 64];
+  __shared__ int shi[kGreedyPickThreads];
+  __shared__ double2 J[kGreedyMaxS * 3];
+  if (gs->done) return;
+  const int tid = threadIdx.x, ncand = 2 * n;
+  double mn = INFINITY;
+  int nact = 0, nfeas = 0;
+  for (int c = tid; c < ncand; c += kGreedyPickThreads) {
+    mn = fmin(mn, sm[c]);
+    nact += em[c] >= 0.0;
+    nfeas += sm[c] < INFINITY;
+  }
+  mn = block_reduce(mn, [](double a, double b) { return fmin(a, b); }, shd);
+  nact = block_reduce(nact, [](int a, int b) { return a + b; }, shi);
+  nfeas = block_reduce(nfeas, [](int a, int b) { return a + b; }, shi);
+  if (!(mn < INFINITY)) {
+    if (tid == 0) gs->done = 1;
+    return;
+  }
+  const double thr = mn + tie;
+  int win = 0x7fffffff, fl = 0;
+  for (int c = tid; c < ncand; c += kGreedyPickThreads) {
+    const double v = sm[c];
+    if (v <= thr) win = min(win, c);
+    if (v < INFINITY && fabs(v - thr) <= amb) fl = 1;
+    if (em[c] >= 0.0 && fabs(em[c] - e_bar) <= amb) fl = 1;
+  }
+  win = block_reduce(win, [](int a, int b) { return min(a, b); }, shi);
+  fl = block_reduce(fl, [](int a, int b) { return max(a, b); }, shi);
+  const int wx = win >> 1, wa = sup[wx], wb = sup[parent[wx]];
+  const int r = (win & 1) ? wb : wa, s = (win & 1) ? wa : wb;
+  for (int q = tid; q < S * 3; q += kGreedyPickThreads) J[q] = Iagg[((size_t)(q / 3) * n + r) * 3 + q % 3];
+  __syncthreads();  // sup and Iagg read by every thread before they change
+  if (tid == 0) {
+    GStep st;
+    st.cand = win;
+    st.s = s;
+    st.r = r;
+    st.ambiguous = fl;
+    st.n_cand = nact;
+    st.n_feasible = nfeas;
+    st.smice = sm[win];
+    st.emax = em[win];
+    steps[gs->iter] = st;
+    gs->s = s;
+    gs->r = r;
+    gs->iter += 1;
+  }
+  for (int q = tid; q < S * 3; q += kGreedyPickThreads) {
+    const size_t lr = ((size_t)(q / 3) * n + r) * 3 + q % 3, ls = ((size_t)(q / 3) * n + s) * 3 + q % 3;
+    Iagg[ls] = cadd(Iagg[ls], J[q]);
+    Iagg[lr] = make_double2(0.0, 0.0);
+  }
+  for (int u = tid; u < n; u += kGreedyPickThreads)
+    if (sup[u] == r) sup[u] = s;
+  for (int xn = tid; xn < n; xn += kGreedyPickThreads) {
+    MoveDelta md;
+    md.at(T, Zr, xn, r, s);
+    if (!md.moved) continue;
+    for (int l = 0; l < S; ++l) {
+      const size_t vb = ((size_t)l * n + xn) * 3;
+#pragma unroll
+      for (int p = 0; p < 3; ++p) V[vb + p] = cadd(V[vb + p], md.dv(p, J + l * 3));
+    }
+  }
+  __syncthreads();
+  cluster_prep(n, S, phase, pre, sup, V, absV, C, (int*)g_lds, shi, shd);
+}
+
+// ---- full-scoring form --------------------------------------------------
+
+struct PathRec {
+  int node, lo, hi;  // an ancestor and the DFS position range of its subtree
+};
+
+// Depth of lca(y, t) where path[d] is t's ancestor at depth d (d <= dmax) and
+// q is y's DFS position: the deepest d whose subtree range holds q.
+// Depth of lca(y, t) where path[d] is t's ancestor at depth d (d <= dmax) and
+// q is y's DFS position: the deepest d whose subtree range holds q.
+__device__ __forceinline__ int lca_depth(const PathRec* path, int dmax, int q) {
+  int lo = 0, hi = dmax;
+  while (lo < hi) {
+    const int mid = (lo + hi + 1) >> 1;
+    if (path[mid].lo <= q && q < path[mid].hi) lo = mid;
+    else hi = mid - 1;
+  }
+  return lo;
+}
+
+// Root paths of r and s in LDS: pr[d] / ps[d] = the ancestor at depth d and
+// its DFS position range (every depth up to the node's own has one).
 // Root paths of r and s in LDS: pr[d] / ps[d] = the ancestor at depth d and
 // its DFS position range (every depth up to the node's own has one).
 __device__ __forceinline__ void load_paths(int n, const int* pos, const int* size, const int* depth, int r, int s,
@@ -153,10 +608,9 @@ __device__ __forceinline__ void load_paths(int n, const int* pos, const int* siz
   }
 }
 
-// Voltage change at node y of moving load current J (one scenario, 3 phases)
-// from r to s: (Zroot(lca(y, r)) - Zroot(lca(y, s))) J; `moved` is false when
-// both lca are the same node (no change).
-struct MoveDelta {
+// MoveDelta with the lowest common ancestors found in the root paths of r
+// and s staged in LDS (binary search by DFS position; the full-scoring form).
+struct PathDelta {
   double2 dZ[9];
   bool moved;
   __device__ __forceinline__ void at(const PathRec* pr, int dr, const PathRec* ps, int ds, const double2* Zr, int qy,
@@ -175,11 +629,12 @@ struct MoveDelta {
   }
 };
 
-// Score of one candidate per block (grid: 2n blocks, id = blockIdx.x):
-// SMICE (+inf when infeasible) and the largest error (-1 when the id is not a
-// candidate in this state).  Dynamic LDS: S * n cluster maxima (uint64 bit
-// patterns), then the two root paths.
-__global__ __launch_bounds__(kGreedyThreads) void k_greedy_score(
+// Full-scoring form (every node of every candidate; for S * n up to
+// kGreedyFullSN): one candidate per block (grid: 2n blocks, id =
+// blockIdx.x), SMICE (+inf when infeasible) and the largest error (-1 when
+// the id is not a candidate).  Dynamic LDS: S * n cluster maxima (uint64 bit
+// patterns), then the root paths of r and s.
+__global__ __launch_bounds__(kGreedyThreads) void k_greedy_score_full(
     int n, int S, const int* __restrict__ parent, const uint8_t* __restrict__ phase, const int* __restrict__ pos,
     const int* __restrict__ size, const int* __restrict__ depth, const int* __restrict__ sup,
     const double2* __restrict__ Zr, const double2* __restrict__ Iagg, const double2* __restrict__ Vcur,
@@ -218,7 +673,7 @@ __global__ __launch_bounds__(kGreedyThreads) void k_greedy_score(
   for (int xn = tid; xn < n; xn += kGreedyThreads) {
     int y = sup[xn];
     if (y == r) y = s;
-    MoveDelta md;
+    PathDelta md;
     md.at(pr, dr, ps, ds, Zr, pos[y], depth[y]);
     const unsigned ph = phase[xn];
     for (int l = 0; l < S; ++l) {
@@ -256,13 +711,10 @@ __global__ __launch_bounds__(kGreedyThreads) void k_greedy_score(
   }
 }
 
-// The iteration's move (one block of 1024): the smallest SMICE among
-// feasible candidates, ties within tie_tol to the lowest id; the step is
-// recorded, r's current joins s's, r's cluster is reassigned, and every
-// node's voltage takes the move's change (the same expression the scoring
-// evaluated).  With no feasible candidate the search is marked done.
-// Dynamic LDS: the two root paths.
-__global__ __launch_bounds__(kGreedyPickThreads) void k_greedy_pick_apply(
+// The move of the full-scoring form (one block of 1024): as
+// k_greedy_pick_apply without the cluster state.  Dynamic LDS: the two root
+// paths.
+__global__ __launch_bounds__(kGreedyPickThreads) void k_greedy_pick_apply_full(
     int n, int S, const int* __restrict__ parent, const int* __restrict__ pos, const int* __restrict__ size,
     const int* __restrict__ depth, const double2* __restrict__ Zr, const double* __restrict__ sm,
     const double* __restrict__ em, double e_bar, double tie, double amb, GState* __restrict__ gs,
@@ -329,7 +781,7 @@ __global__ __launch_bounds__(kGreedyPickThreads) void k_greedy_pick_apply(
     if (sup[u] == r) sup[u] = s;
   for (int t = tid; t < n * S; t += kGreedyPickThreads) {
     const int xn = t % n, l = t / n;
-    MoveDelta md;
+    PathDelta md;
     md.at(pr, dr, ps, ds, Zr, pos[xn], depth[xn]);
     if (!md.moved) continue;
     const size_t vb = ((size_t)l * n + xn) * 3;
@@ -384,7 +836,11 @@ struct okr_greedy {
   size_t o_topo = 0, o_phase = 0, o_z = 0, o_Zr = 0, o_Vhat = 0, o_A = 0, o_absV = 0, o_I = 0, o_V = 0, o_Ib = 0,
          o_sup = 0, o_sm = 0, o_em = 0, o_steps = 0, o_gs = 0, o_status = 0, o_iters = 0, o_err = 0, total = 0;
   // packed int arrays: parent, pos, size, depth, lvl_off, lvl_nodes, ch_off, ch
-  size_t t_parent = 0, t_pos = 0, t_size = 0, t_depth = 0, t_lvl_off = 0, t_lvl_nodes = 0, t_ch_off = 0, t_ch = 0;
+  size_t t_parent = 0, t_pos = 0, t_size = 0, t_depth = 0, t_lvl_off = 0, t_lvl_nodes = 0, t_ch_off = 0, t_ch = 0,
+         t_pre = 0, t_first = 0, t_st = 0;
+  int euler_len = 0;
+  // cluster state of the search
+  size_t o_mice = 0, o_arr = 0, o_bmax = 0, o_moff = 0, o_mem = 0, o_tot = 0;
   std::vector<int> topo_host;
 };
 
@@ -492,6 +948,44 @@ extern "C" int okr_greedy_plan(okr_greedy* g, int32_t n, const int32_t* parent, 
   g->t_lvl_nodes = put(g->lvl_nodes);
   g->t_ch_off = put(g->ch_off);
   g->t_ch = put(g->ch);
+  g->t_pre = put(pre);
+  // Euler tour of the DFS (children in increasing id, i.e. increasing DFS
+  // position), first occurrences, and the sparse table of shallowest nodes
+  {
+    std::vector<int> euler, first(n, -1);
+    euler.reserve(2 * (size_t)n);
+    std::vector<std::pair<int, int>> stk{{0, g->ch_off[0]}};
+    euler.push_back(0);
+    first[0] = 0;
+    while (!stk.empty()) {
+      const int v = stk.back().first, e = stk.back().second;
+      if (e < g->ch_off[v + 1]) {
+        stk.back().second = e + 1;
+        const int c = g->ch[e];
+        first[c] = (int)euler.size();
+        euler.push_back(c);
+        stk.push_back({c, g->ch_off[c]});
+      } else {
+        stk.pop_back();
+        if (!stk.empty()) euler.push_back(stk.back().first);
+      }
+    }
+    const int E = (int)euler.size();
+    int L = 1;
+    while ((1 << L) <= E) ++L;
+    std::vector<int> sp((size_t)L * E);
+    for (int i = 0; i < E; ++i) sp[i] = euler[i];
+    for (int k = 1; k < L; ++k)
+      for (int i = 0; i < E; ++i) {
+        const int a = sp[(size_t)(k - 1) * E + i];
+        const int j = i + (1 << (k - 1));
+        const int b = j < E ? sp[(size_t)(k - 1) * E + j] : a;
+        sp[(size_t)k * E + i] = g->depth[a] <= g->depth[b] ? a : b;
+      }
+    g->euler_len = E;
+    g->t_first = put(first);
+    g->t_st = put(sp);
+  }
   size_t off = 0;
   auto take = [&](size_t bytes) {
     const size_t at = off;
@@ -517,6 +1011,12 @@ extern "C" int okr_greedy_plan(okr_greedy* g, int32_t n, const int32_t* parent, 
   g->o_status = take(sizeof(int) * 4);
   g->o_iters = take(sizeof(int) * S);
   g->o_err = take(sizeof(double) * S);
+  g->o_mice = take(sizeof(double) * (size_t)S * n);
+  g->o_arr = take(sizeof(double) * n);
+  g->o_bmax = take(sizeof(double) * ((n + 63) / 64));
+  g->o_moff = take(sizeof(int) * (n + 1));
+  g->o_mem = take(sizeof(int) * n);
+  g->o_tot = take(sizeof(double));
   g->total = off;
   *workspace_bytes = off;
   g->planned = true;
@@ -525,7 +1025,9 @@ extern "C" int okr_greedy_plan(okr_greedy* g, int32_t n, const int32_t* parent, 
 
 namespace {
 struct GPtrs {
-  int *topo, *parent, *pos, *size, *depth, *lvl_off, *lvl_nodes, *ch_off, *ch, *sup, *status, *iters;
+  int *topo, *parent, *pos, *size, *depth, *lvl_off, *lvl_nodes, *ch_off, *ch, *pre, *first, *sp, *sup, *status,
+      *iters;
+  Clusters C;
   uint8_t* phase;
   double2 *z, *Zr, *Vhat, *A, *I, *V, *Ib;
   double *absV, *sm, *em, *err;
@@ -545,6 +1047,15 @@ GPtrs gptrs(const okr_greedy* g, void* ws) {
   p.lvl_nodes = p.topo + g->t_lvl_nodes;
   p.ch_off = p.topo + g->t_ch_off;
   p.ch = p.topo + g->t_ch;
+  p.pre = p.topo + g->t_pre;
+  p.first = p.topo + g->t_first;
+  p.sp = p.topo + g->t_st;
+  p.C.mice = (double*)(b + g->o_mice);
+  p.C.arr = (double*)(b + g->o_arr);
+  p.C.bmax = (double*)(b + g->o_bmax);
+  p.C.moff = (int*)(b + g->o_moff);
+  p.C.mem = (int*)(b + g->o_mem);
+  p.C.tot = (double*)(b + g->o_tot);
   p.phase = (uint8_t*)(b + g->o_phase);
   p.z = (double2*)(b + g->o_z);
   p.Zr = (double2*)(b + g->o_Zr);
@@ -623,10 +1134,15 @@ extern "C" int okr_greedy_run(okr_greedy* g, const okr_yblocks* Y, const okr_loa
   if (!out || !out->super || !out->steps || !out->err_per_snapshot) OKRG_FAIL(g, OKR_E_ARG, "null result buffer");
   const int n = g->n, S = g->S;
   if (S > kGreedyMaxS) OKRG_FAIL(g, OKR_E_UNSUPPORTED, "the search takes at most %d scenarios", kGreedyMaxS);
-  const size_t lds = sizeof(unsigned long long) * (size_t)S * n + sizeof(PathRec) * 2 * (size_t)g->nlev;
-  if ((size_t)S * n > kGreedyMaxSN || lds > 64 * 1024)
-    OKRG_FAIL(g, OKR_E_UNSUPPORTED, "S * n = %zu above %d, or the tree too deep, for the search's LDS tables",
-              (size_t)S * n, kGreedyMaxSN);
+  // every candidate scores every node while the cluster table fits in LDS;
+  // beyond that (or when asked) only the clusters a move can change
+  const size_t lds_full = sizeof(unsigned long long) * (size_t)S * n + sizeof(PathRec) * 2 * (size_t)g->nlev;
+  const size_t lds_paths = sizeof(PathRec) * 2 * (size_t)g->nlev;
+  const bool incremental =
+      (prm->flags & OKR_GREEDY_INCREMENTAL) || (size_t)S * n > kGreedyFullSN || lds_full > 64 * 1024;
+  if (incremental && n > kGreedyMaxN)
+    OKRG_FAIL(g, OKR_E_UNSUPPORTED, "the search takes at most %d nodes", kGreedyMaxN);
+  const size_t lds_cnt = sizeof(int) * (size_t)n;
   const hipStream_t st = g->stream;
   const GPtrs p = gptrs(g, ws);
   hipEvent_t ev[3];
@@ -648,13 +1164,20 @@ extern "C" int okr_greedy_run(okr_greedy* g, const okr_yblocks* Y, const okr_loa
                      (const uint8_t*)p.phase, (const int*)p.lvl_off, (const int*)p.lvl_nodes, g->nlev,
                      (const int*)p.ch_off, (const int*)p.ch, (const double2*)p.z, V0[0], V0[1], V0[2],
                      (const double2*)p.I, p.Ib, p.V);
+  LcaTab T;
+  T.first = p.first;
+  T.st = p.sp;
+  T.depth = p.depth;
+  T.E = g->euler_len;
+  if (incremental)
+    hipLaunchKernelGGL(k_greedy_prep, dim3(1), dim3(kGreedyPickThreads), lds_cnt, st, n, S, (const uint8_t*)p.phase,
+                       (const int*)p.pre, (const int*)p.sup, (const double2*)p.V, (const double*)p.absV, p.C);
   OKRG_HIP(g, hipGetLastError());
   OKRG_HIP(g, hipEventRecord(ev[1], st));
   const double e_bar = prm->e_bar, tie = prm->tie_tol > 0 ? prm->tie_tol : 1e-11;
   const double amb = prm->amb_tol > 0 ? prm->amb_tol : 1e-13;
   // at most one move per enqueued iteration: the cap is the number enqueued
   const int cap = prm->max_iter > 0 ? std::min(prm->max_iter, n - 1) : n - 1;
-  const size_t lds_paths = sizeof(PathRec) * 2 * (size_t)g->nlev;
   GState hs{};
   int enq = 0;
   constexpr int kBatch = 32;  // moves enqueued between checks of the done flag
@@ -673,15 +1196,28 @@ extern "C" int okr_greedy_run(okr_greedy* g, const okr_yblocks* Y, const okr_loa
     const int b = std::min(kBatch, cap - enq);
     for (int t = 0; t < b; ++t) {
       if (timing) OKRG_HIP(g, hipEventRecord(tev[2 * t], st));
-      hipLaunchKernelGGL(k_greedy_score, dim3(2 * n), dim3(kGreedyThreads), lds, st, n, S, (const int*)p.parent,
-                         (const uint8_t*)p.phase, (const int*)p.pos, (const int*)p.size, (const int*)p.depth,
-                         (const int*)p.sup, (const double2*)p.Zr, (const double2*)p.I, (const double2*)p.V,
-                         (const double*)p.absV, e_bar, (const GState*)p.gs, p.sm, p.em);
-      if (timing) OKRG_HIP(g, hipEventRecord(tev[2 * t + 1], st));
-      hipLaunchKernelGGL(k_greedy_pick_apply, dim3(1), dim3(kGreedyPickThreads), lds_paths, st, n, S,
-                         (const int*)p.parent, (const int*)p.pos, (const int*)p.size, (const int*)p.depth,
-                         (const double2*)p.Zr, (const double*)p.sm, (const double*)p.em, e_bar, tie, amb, p.gs,
-                         p.steps, p.sup, p.I, p.V);
+      if (incremental) {
+        hipLaunchKernelGGL(k_greedy_score, dim3(2 * n), dim3(kGreedyThreads), 0, st, n, S, (const int*)p.parent,
+                           (const uint8_t*)p.phase, (const int*)p.pos, (const int*)p.size, (const int*)p.pre,
+                           (const int*)p.ch_off, (const int*)p.ch, (const int*)p.sup, T, (const double2*)p.Zr,
+                           (const double2*)p.I, (const double2*)p.V, (const double*)p.absV, e_bar,
+                           (const GState*)p.gs, p.C, p.sm, p.em);
+        if (timing) OKRG_HIP(g, hipEventRecord(tev[2 * t + 1], st));
+        hipLaunchKernelGGL(k_greedy_pick_apply, dim3(1), dim3(kGreedyPickThreads), lds_cnt, st, n, S,
+                           (const int*)p.parent, (const uint8_t*)p.phase, (const int*)p.pre, T,
+                           (const double2*)p.Zr, (const double*)p.absV, (const double*)p.sm, (const double*)p.em,
+                           e_bar, tie, amb, p.gs, p.steps, p.sup, p.I, p.V, p.C);
+      } else {
+        hipLaunchKernelGGL(k_greedy_score_full, dim3(2 * n), dim3(kGreedyThreads), lds_full, st, n, S,
+                           (const int*)p.parent, (const uint8_t*)p.phase, (const int*)p.pos, (const int*)p.size,
+                           (const int*)p.depth, (const int*)p.sup, (const double2*)p.Zr, (const double2*)p.I,
+                           (const double2*)p.V, (const double*)p.absV, e_bar, (const GState*)p.gs, p.sm, p.em);
+        if (timing) OKRG_HIP(g, hipEventRecord(tev[2 * t + 1], st));
+        hipLaunchKernelGGL(k_greedy_pick_apply_full, dim3(1), dim3(kGreedyPickThreads), lds_paths, st, n, S,
+                           (const int*)p.parent, (const int*)p.pos, (const int*)p.size, (const int*)p.depth,
+                           (const double2*)p.Zr, (const double*)p.sm, (const double*)p.em, e_bar, tie, amb, p.gs,
+                           p.steps, p.sup, p.I, p.V);
+      }
     }
     OKRG_HIP(g, hipGetLastError());
     const int before = hs.iter;
@@ -722,6 +1258,7 @@ extern "C" int okr_greedy_run(okr_greedy* g, const okr_yblocks* Y, const okr_loa
   out->n_steps = hs.iter;
   out->n_kept = n - hs.iter;
   out->n_score_launches = launches;
+  out->incremental = incremental ? 1 : 0;
   out->t_score_ms = score_ms;
   {
     int64_t sc = 0;

@@ -42,19 +42,23 @@ def same_steps(got, want):
     assert [s["n_feasible"] for s in got] == [s["n_feasible"] for s in want]
 
 
+@pytest.mark.parametrize("incremental", [False, True])
 @pytest.mark.parametrize("n,S,seed,kappa,e_bar", [
     (30, 1, 0, 1.0, 3e-3), (40, 2, 1, 1.0, 3e-4), (60, 2, 2, 1.0, 1e-3), (80, 2, 3, 0.25, 3e-3),
     (100, 2, 4, 1.0, 1e-3)])
-def test_every_step_matches_oracle(okr, n, S, seed, kappa, e_bar):
-    """Whole searches on small feeders: the same moves in the same order, the
-    same SMICE and errors, the same final assignment and errors."""
-    _say(f"greedy n={n} S={S} seed={seed} kappa={kappa} e_bar={e_bar}")
+def test_every_step_matches_oracle(okr, n, S, seed, kappa, e_bar, incremental):
+    """Whole searches on small feeders, in both scoring forms (every node of
+    every candidate, or only the clusters a move can change): the same moves
+    in the same order, the same SMICE and errors, the same final assignment
+    and errors."""
+    _say(f"greedy n={n} S={S} seed={seed} kappa={kappa} e_bar={e_bar} incremental={incremental}")
     f = make_feeder("c2", seed, n=n, snapshots=S, kappa=kappa)
     V, I, _, _ = oracle.powerflow(f)
     sup, steps, err = G.greedy(f, V, I, e_bar=e_bar)
     if any(s["ambiguous"] for s in steps):
         pytest.skip("a near-tie within the ambiguity margin in the oracle's search")
-    out = okr.greedy(f, e_bar=e_bar)
+    out = okr.greedy(f, e_bar=e_bar, incremental=incremental)
+    assert out["incremental"] == incremental
     same_steps(out["steps"], steps)
     np.testing.assert_array_equal(out["super"], sup)
     np.testing.assert_allclose(out["err_per_snapshot"], err, rtol=0, atol=TOL)
@@ -112,17 +116,19 @@ def test_evaluate_rejects_bad_assignments(okr):
     assert e.value.code == okr.OKR.E_ARG
 
 
-def test_1000_node_first_move_and_termination(okr):
+@pytest.mark.parametrize("incremental", [False, True])
+def test_1000_node_first_move_and_termination(okr, incremental):
     """1000-node feeder with its two extreme scenarios (the Table III workload
-    shape): the first move is the oracle's choice among all ~2000 candidates
-    with the oracle's SMICE, and at the end no candidate is feasible in the
-    oracle's scoring of the final state."""
+    shape), both scoring forms: the first move is the oracle's choice among
+    all ~2000 candidates with the oracle's SMICE, and at the end no candidate
+    is feasible in the oracle's scoring of the final state."""
     fh = hourly_feeder("c2", 0, n=1000)
     f = extreme_scenarios(fh)
     V, I, _, _ = oracle.powerflow(f)
     e_bar = f["e_bar"]
-    _say("greedy 1000-node: GPU run")
-    out = okr.greedy(f, e_bar=e_bar)
+    _say(f"greedy 1000-node: GPU run, incremental={incremental}")
+    out = okr.greedy(f, e_bar=e_bar, incremental=incremental)
+    assert out["incremental"] == incremental
     assert out["n_steps"] > 0 and out["max_err"] <= e_bar
     net = G.Network(f)
     sup0 = np.arange(f["n"])
@@ -141,3 +147,18 @@ def test_1000_node_first_move_and_termination(okr):
     smf, emf = G.score(net, V, G.aggregate(I, supf), supf, cf, e_bar)
     assert not np.isfinite(smf).any()
     np.testing.assert_allclose(out["err_per_snapshot"], G.evaluate(f, V, I, supf, net=net), rtol=0, atol=TOL)
+
+
+def test_scoring_forms_agree_at_3000_nodes(okr):
+    """Where both forms fit (S * n = 6000), the incremental scoring makes the
+    same moves as scoring every node, with the same SMICE (the forms differ
+    only in summation order), on a 3000-node feeder."""
+    f = extreme_scenarios(hourly_feeder("c2", 1, n=3000))
+    _say("greedy 3000-node: both scoring forms")
+    a = okr.greedy(f, e_bar=f["e_bar"])
+    b = okr.greedy(f, e_bar=f["e_bar"], incremental=True)
+    assert not a["incremental"] and b["incremental"]
+    assert a["n_steps"] > 100
+    same_steps(b["steps"], a["steps"])
+    np.testing.assert_array_equal(b["super"], a["super"])
+    np.testing.assert_allclose(b["err_per_snapshot"], a["err_per_snapshot"], rtol=0, atol=TOL)
