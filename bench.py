@@ -246,8 +246,15 @@ def e_bar_sweep_section(seed):
         gpts = []
         for eb in E_BAR_SWEEP_GREEDY:
             r = G.run(eb)
+            t0 = time.perf_counter()
+            rad = G.radialize(r["super"])
+            rad_ms = (time.perf_counter() - t0) * 1e3
+            kept_rad = int(rad["kept_radial"].sum())
             gpts.append(dict(e_bar=eb, reduction_pct=100.0 * (1 - r["n_kept"] / n), max_err=r["max_err"],
-                             moves=r["n_steps"], search_ms=r["t_search_ms"], incremental=r["incremental"]))
+                             moves=r["n_steps"], search_ms=r["t_search_ms"], incremental=r["incremental"],
+                             radialized_reduction_pct=100.0 * (1 - kept_rad / n), critical_nodes=rad["n_critical"],
+                             radial_voltage_check=rad["dv_radial"], meshed_voltage_check=rad["dv_meshed"],
+                             radialize_ms=rad_ms))
         G.close()
         out["feeders"][name] = dict(n=n, eligible=int(f["eligible"].sum()), segments=int(f["n_segments"]),
                                     points=pts, greedy_points=gpts)

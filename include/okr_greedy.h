@@ -1,8 +1,9 @@
 /*
  * okr_greedy.h -- C ABI of the greedy single-move reduction search
- * (Algorithm 1 of arXiv 2510.19608, Section IV) and of the evaluation of a
+ * (Algorithm 1 of arXiv 2510.19608, Section IV), of the evaluation of a
  * fixed reduction over many loading scenarios (the robustness study of
- * Section VI), on MI355X (gfx950).
+ * Section VI) and of the three-phase radialization of a reduction
+ * (Section V), on MI355X (gfx950).
  *
  * Algorithm 1, as computed here:
  *   state: every node's super-node (initially itself) and the aggregated load
@@ -124,6 +125,28 @@ int okr_greedy_run(okr_greedy* g, const okr_yblocks* Y, const okr_loads* loads, 
  * OKR_E_ARG for an invalid assignment. */
 int okr_greedy_evaluate(okr_greedy* g, const okr_yblocks* Y, const okr_loads* loads, const int32_t* super,
                         const okr_greedy_params* p, void* d_workspace, double* err_per_snapshot, double* max_err);
+
+/* Three-phase radialization (Section V) of a fixed assignment (super[n],
+ * HOST, as for okr_greedy_evaluate).  The Kron-reduced network of the
+ * super-nodes is an edge-disjoint union of cliques, one per connected group
+ * of reduced nodes, over the kept nodes bordering it (Lemma 2: the pattern
+ * is that of the single-phase network); a clique of three or more kept nodes
+ * is a mesh.  Its critical nodes, the nodes of degree 3 or more in the
+ * sub-tree of the feeder spanning the clique, are kept again (with no
+ * injection of their own), which makes the reduced network radial.
+ * Outputs (HOST): kept_radial[n] (1 for super-nodes and critical nodes),
+ * kept_parent[n] (each node's nearest kept proper ancestor in the radialized
+ * set, -1 at the slack: the edges of the radial reduced network),
+ * *n_critical, and the voltage checks over loads->S scenarios (may be NULL):
+ * *dv_radial, the largest distance between the kept nodes' voltages of the
+ * radial network built on kept_parent (series impedances, aggregated
+ * currents) and those of the full network (about 1e-15 when radialization
+ * succeeded), and *dv_meshed, the same for the network built on the kept
+ * parents of the super-nodes alone (nonzero when the reduction meshes).
+ * Synchronous.  Errors as okr_greedy_evaluate. */
+int okr_greedy_radialize(okr_greedy* g, const okr_yblocks* Y, const okr_loads* loads, const int32_t* super,
+                         const okr_greedy_params* p, void* d_workspace, uint8_t* kept_radial, int32_t* kept_parent,
+                         int32_t* n_critical, double* dv_radial, double* dv_meshed);
 
 int okr_greedy_destroy(okr_greedy* g);
 const char* okr_greedy_last_error(const okr_greedy* g);

@@ -142,13 +142,16 @@ def lib():
                                      ctypes.POINTER(GreedyParams), vp, ctypes.POINTER(GreedyResult)]
         L.okr_greedy_evaluate.argtypes = [vp, ctypes.POINTER(YBlocks), ctypes.POINTER(Loads), vp,
                                           ctypes.POINTER(GreedyParams), vp, vp, ctypes.POINTER(ctypes.c_double)]
+        L.okr_greedy_radialize.argtypes = [vp, ctypes.POINTER(YBlocks), ctypes.POINTER(Loads), vp,
+                                           ctypes.POINTER(GreedyParams), vp, vp, vp, ctypes.POINTER(ctypes.c_int32),
+                                           ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_double)]
         L.okr_greedy_destroy.argtypes = [vp]
         L.okr_greedy_last_error.argtypes = [vp]
         L.okr_greedy_last_error.restype = ctypes.c_char_p
         for fn in ("okr_create", "okr_plan", "okr_reduce_feeder", "okr_dump_scores", "okr_destroy",
                    "okr_surrogate_workspace", "okr_train_surrogate", "okr_surrogate_grad",
                    "okr_surrogate_forward", "okr_greedy_create", "okr_greedy_plan", "okr_greedy_run",
-                   "okr_greedy_evaluate", "okr_greedy_destroy"):
+                   "okr_greedy_evaluate", "okr_greedy_radialize", "okr_greedy_destroy"):
             getattr(L, fn).restype = ctypes.c_int
         _lib = L
     return _lib
@@ -452,6 +455,19 @@ def okr_greedy_evaluate(g, Y: YBlocks, loads: Loads, sup, params: GreedyParams, 
     return mx.value
 
 
+def okr_greedy_radialize(g, Y: YBlocks, loads: Loads, sup, params: GreedyParams, d_ws):
+    sup = np.ascontiguousarray(sup, dtype=np.int32)
+    n = len(sup)
+    kept = np.zeros(n, np.uint8)
+    kp = np.zeros(n, np.int32)
+    nc = ctypes.c_int32(0)
+    d1, d2 = ctypes.c_double(0.0), ctypes.c_double(0.0)
+    _gcheck(g, lib().okr_greedy_radialize(g, ctypes.byref(Y), ctypes.byref(loads), sup.ctypes.data,
+                                          ctypes.byref(params), d_ws, kept.ctypes.data, kp.ctypes.data,
+                                          ctypes.byref(nc), ctypes.byref(d1), ctypes.byref(d2)))
+    return dict(kept_radial=kept, kept_parent=kp, n_critical=nc.value, dv_radial=d1.value, dv_meshed=d2.value)
+
+
 def okr_greedy_destroy(g):
     return lib().okr_greedy_destroy(g)
 
@@ -519,6 +535,12 @@ class Greedy:
         mx = okr_greedy_evaluate(self.g, self.Y, self.loads, sup, self.params(0.0),
                                  ctypes.c_void_p(self.ws.data_ptr()), err)
         return err, mx
+
+    def radialize(self, sup):
+        """Section V radialization of an assignment over this feeder."""
+        self.stream.wait_stream(self.torch.cuda.current_stream(self.device))
+        return okr_greedy_radialize(self.g, self.Y, self.loads, sup, self.params(0.0),
+                                    ctypes.c_void_p(self.ws.data_ptr()))
 
     def close(self):
         if getattr(self, "g", None) is not None:

@@ -790,6 +790,112 @@ __global__ __launch_bounds__(kGreedyPickThreads) void k_greedy_pick_apply_full(
   }
 }
 
+// ---- radialization (Section V) --------------------------------------------
+
+// Critical nodes of a kept set (one block, level by level): a node that is
+// not kept is critical when three or more of its tree directions reach a
+// kept node through nodes that are not kept (its degree in the sub-tree that
+// spans the kept nodes of its Kron clique).  Writes the radialized kept set
+// and, for both kept sets, every node's nearest kept proper ancestor (-1 at
+// the slack).  Scratch: down, up, cnt (n ints each).
+__global__ __launch_bounds__(kGreedyPickThreads) void k_radialize(
+    int n, const int* __restrict__ parent, const int* __restrict__ ch_off, const int* __restrict__ ch,
+    const int* __restrict__ lvl_off, const int* __restrict__ lvl_nodes, int nlev, const int* __restrict__ sup,
+    int* __restrict__ down, int* __restrict__ up, int* __restrict__ cnt, uint8_t* __restrict__ kept_rad,
+    int* __restrict__ kp_rad, int* __restrict__ kp_mesh, int* __restrict__ ncrit) {
+  __shared__ int shi[kGreedyPickThreads / 64];
+  // down[x]: x is kept, or a kept node lies below x through non-kept nodes;
+  // cnt[x]: children c with down[c]
+  for (int lev = nlev - 1; lev >= 0; --lev) {
+    for (int q = lvl_off[lev] + threadIdx.x; q < lvl_off[lev + 1]; q += blockDim.x) {
+      const int x = lvl_nodes[q];
+      int c = 0;
+      for (int e = ch_off[x]; e < ch_off[x + 1]; ++e) c += down[ch[e]];
+      cnt[x] = c;
+      down[x] = (sup[x] == x || c > 0) ? 1 : 0;
+    }
+    __syncthreads();
+  }
+  // up[x]: the direction towards the parent reaches a kept node
+  for (int lev = 0; lev < nlev; ++lev) {
+    for (int q = lvl_off[lev] + threadIdx.x; q < lvl_off[lev + 1]; q += blockDim.x) {
+      const int x = lvl_nodes[q];
+      if (x == 0) {
+        up[x] = 0;
+        continue;
+      }
+      const int p = parent[x];
+      up[x] = (sup[p] == p || up[p] || cnt[p] - down[x] > 0) ? 1 : 0;
+    }
+    __syncthreads();
+  }
+  int nc = 0;
+  for (int x = threadIdx.x; x < n; x += blockDim.x) {
+    const bool kept = sup[x] == x;
+    const bool crit = !kept && up[x] + cnt[x] >= 3;
+    nc += crit;
+    kept_rad[x] = (kept || crit) ? 1 : 0;
+  }
+  nc = block_reduce(nc, [](int a, int b) { return a + b; }, shi);
+  if (threadIdx.x == 0) *ncrit = nc;
+  __syncthreads();
+  for (int lev = 0; lev < nlev; ++lev) {
+    for (int q = lvl_off[lev] + threadIdx.x; q < lvl_off[lev + 1]; q += blockDim.x) {
+      const int x = lvl_nodes[q];
+      if (x == 0) {
+        kp_rad[x] = kp_mesh[x] = -1;
+        continue;
+      }
+      const int p = parent[x];
+      kp_rad[x] = kept_rad[p] ? p : kp_rad[p];
+      kp_mesh[x] = sup[p] == p ? p : kp_mesh[p];
+    }
+    __syncthreads();
+  }
+}
+
+// Voltage check of a radial reduced network (one thread per node and
+// scenario): for every kept node x, the voltage of the radial network whose
+// edges join each kept node to its nearest kept proper ancestor kp, with the
+// aggregated load currents, is V0 - sum_j Zroot(a(lca(x, j))) I_j, a(v) = v
+// when v is kept, else kp[v]; its largest distance from the full network's
+// voltage V goes to *dv (bit pattern of a non-negative double).  Zero when
+// every kept pair's lowest common ancestor is kept, i.e. when the network is
+// radial with the same voltages.
+__global__ __launch_bounds__(kGreedyThreads) void k_radial_check(
+    int n, int S, const uint8_t* __restrict__ phase, LcaTab T, const double2* __restrict__ Zr,
+    const int* __restrict__ sup, const uint8_t* __restrict__ kept_rad, const int* __restrict__ kp, int use_rad,
+    const double2* __restrict__ Iagg, const double2* __restrict__ V, double2 v0a, double2 v0b, double2 v0c,
+    unsigned long long* __restrict__ dv) {
+  const int t = blockIdx.x * blockDim.x + threadIdx.x;
+  double e = 0.0;
+  if (t < n * S) {
+    const int x = t % n, l = t / n;
+    const bool kx = use_rad ? kept_rad[x] != 0 : sup[x] == x;
+    if (kx) {
+      const double2 v0[3] = {v0a, v0b, v0c};
+      double2 acc[3] = {v0[0], v0[1], v0[2]};
+      for (int j = 1; j < n; ++j) {
+        if (sup[j] != j) continue;  // only super-nodes carry current
+        int a = T.lca(x, j);
+        const bool ka = use_rad ? kept_rad[a] != 0 : sup[a] == a;
+        if (!ka) a = kp[a];
+        const double2* Za = Zr + (size_t)a * 9;
+        const double2* Ij = Iagg + ((size_t)l * n + j) * 3;
+#pragma unroll
+        for (int p = 0; p < 3; ++p)
+          acc[p] = csub(acc[p], cadd(cadd(cmul(Za[p * 3], Ij[0]), cmul(Za[p * 3 + 1], Ij[1])), cmul(Za[p * 3 + 2], Ij[2])));
+      }
+      const double2* Vx = V + ((size_t)l * n + x) * 3;
+#pragma unroll
+      for (int p = 0; p < 3; ++p)
+        if (phase[x] >> p & 1u) e = fmax(e, sqrt(cabs2(csub(acc[p], Vx[p]))));
+    }
+  }
+  for (int o = 32; o > 0; o >>= 1) e = fmax(e, __shfl_xor(e, o, 64));
+  if ((threadIdx.x & 63) == 0 && e > 0.0) atomicMax(dv, (unsigned long long)__double_as_longlong(e));
+}
+
 // I = A I^ for a given assignment: one thread per (scenario, node, phase)
 // adds its cluster's members' currents in node order (members of super-node
 // y: mem[moff[y] .. moff[y + 1]); zero for nodes that are not super-nodes).
@@ -841,6 +947,8 @@ struct okr_greedy {
   int euler_len = 0;
   // cluster state of the search
   size_t o_mice = 0, o_arr = 0, o_bmax = 0, o_moff = 0, o_mem = 0, o_tot = 0;
+  // radialization: 5 int arrays of n, kept flags, counter, two maxima
+  size_t o_rad = 0, o_radk = 0, o_radx = 0;
   std::vector<int> topo_host;
 };
 
@@ -1017,6 +1125,9 @@ extern "C" int okr_greedy_plan(okr_greedy* g, int32_t n, const int32_t* parent, 
   g->o_moff = take(sizeof(int) * (n + 1));
   g->o_mem = take(sizeof(int) * n);
   g->o_tot = take(sizeof(double));
+  g->o_rad = take(sizeof(int) * 5 * (size_t)n);
+  g->o_radk = take(n);
+  g->o_radx = take(sizeof(unsigned long long) * 4);
   g->total = off;
   *workspace_bytes = off;
   g->planned = true;
@@ -1122,6 +1233,27 @@ int check_call(okr_greedy* g, const okr_yblocks* Y, const okr_loads* L, const ok
   if (L->S != g->S) OKRG_FAIL(g, OKR_E_ARG, "loads->S = %d, planned for %d", L->S, g->S);
   if ((prm->flags & OKR_FLAG_VHAT_GIVEN) && !L->Vhat) OKRG_FAIL(g, OKR_E_ARG, "OKR_FLAG_VHAT_GIVEN without Vhat");
   if (!ws) OKRG_FAIL(g, OKR_E_WORKSPACE, "no workspace");
+  return OKR_OK;
+}
+// An assignment: super-nodes are their own super-node, every cluster is
+// connected (one member whose parent lies outside it), the slack is a
+// super-node, and a member's phases lie within its super-node's.
+int check_assignment(okr_greedy* g, const int32_t* super) {
+  const int n = g->n;
+  std::vector<int> top(n, -1);
+  for (int x = 0; x < n; ++x) {
+    const int s = super[x];
+    if (s < 0 || s >= n || super[s] != s) OKRG_FAIL(g, OKR_E_ARG, "super[%d] = %d is not a super-node", x, s);
+    if (g->phase[x] & ~g->phase[s]) OKRG_FAIL(g, OKR_E_ARG, "node %d has phases outside its super-node's", x);
+  }
+  if (super[0] != 0) OKRG_FAIL(g, OKR_E_ARG, "the slack must stay its own super-node");
+  for (int x = 0; x < n; ++x) {  // each cluster has one node whose parent lies outside it
+    const int s = super[x];
+    if (x == 0 || super[g->parent[x]] != s) {
+      if (top[s] >= 0) OKRG_FAIL(g, OKR_E_ARG, "the cluster of super-node %d is not connected", s);
+      top[s] = x;
+    }
+  }
   return OKR_OK;
 }
 }  // namespace
@@ -1286,23 +1418,8 @@ extern "C" int okr_greedy_evaluate(okr_greedy* g, const okr_yblocks* Y, const ok
   if (rc) return rc;
   if (!super || !err) OKRG_FAIL(g, OKR_E_ARG, "null assignment or output");
   const int n = g->n, S = g->S;
-  // an assignment: supers are their own super, clusters are connected (the
-  // path from a member up to the cluster's top stays in the cluster) and a
-  // member's phases lie within its super-node's
-  std::vector<int> top(n, -1);
-  for (int x = 0; x < n; ++x) {
-    const int s = super[x];
-    if (s < 0 || s >= n || super[s] != s) OKRG_FAIL(g, OKR_E_ARG, "super[%d] = %d is not a super-node", x, s);
-    if (g->phase[x] & ~g->phase[s]) OKRG_FAIL(g, OKR_E_ARG, "node %d has phases outside its super-node's", x);
-  }
-  if (super[0] != 0) OKRG_FAIL(g, OKR_E_ARG, "the slack must stay its own super-node");
-  for (int x = 0; x < n; ++x) {  // each cluster has one node whose parent lies outside it
-    const int s = super[x];
-    if (x == 0 || super[g->parent[x]] != s) {
-      if (top[s] >= 0) OKRG_FAIL(g, OKR_E_ARG, "the cluster of super-node %d is not connected", s);
-      top[s] = x;
-    }
-  }
+  rc = check_assignment(g, super);
+  if (rc) return rc;
   const GPtrs p = gptrs(g, ws);
   const hipStream_t st = g->stream;
   rc = setup(g, p, Y, L, prm);
@@ -1341,5 +1458,80 @@ extern "C" int okr_greedy_evaluate(okr_greedy* g, const okr_yblocks* Y, const ok
     for (int l = 0; l < S; ++l) mx = std::max(mx, err[l]);
     *max_err = mx;
   }
+  return OKR_OK;
+}
+
+extern "C" int okr_greedy_radialize(okr_greedy* g, const okr_yblocks* Y, const okr_loads* L, const int32_t* super,
+                                    const okr_greedy_params* prm, void* ws, uint8_t* kept_radial,
+                                    int32_t* kept_parent, int32_t* n_critical, double* dv_radial,
+                                    double* dv_meshed) {
+  if (!g) return OKR_E_ARG;
+  int rc = check_call(g, Y, L, prm, ws);
+  if (rc) return rc;
+  if (!super || !kept_radial || !kept_parent || !n_critical) OKRG_FAIL(g, OKR_E_ARG, "null assignment or output");
+  rc = check_assignment(g, super);
+  if (rc) return rc;
+  const int n = g->n, S = g->S;
+  const GPtrs p = gptrs(g, ws);
+  const hipStream_t st = g->stream;
+  rc = setup(g, p, Y, L, prm);
+  if (rc) return rc;
+  const double2* V0 = (const double2*)L->V0;
+  std::vector<int> csr(2 * (size_t)n + 1, 0);
+  for (int x = 0; x < n; ++x) csr[super[x] + 1]++;
+  for (int y = 0; y < n; ++y) csr[y + 1] += csr[y];
+  {
+    std::vector<int> fill(csr.begin(), csr.begin() + n);
+    for (int x = 0; x < n; ++x) csr[n + 1 + fill[super[x]]++] = x;
+  }
+  int* moff = (int*)p.sm;
+  OKRG_HIP(g, hipMemcpyAsync(p.sup, super, sizeof(int) * n, hipMemcpyHostToDevice, st));
+  OKRG_HIP(g, hipMemcpyAsync(moff, csr.data(), sizeof(int) * csr.size(), hipMemcpyHostToDevice, st));
+  const size_t c3 = (size_t)S * n * 3;
+  hipLaunchKernelGGL(k_greedy_aggregate, dim3((unsigned)((c3 + 255) / 256)), dim3(256), 0, st, n, S,
+                     (const int*)moff, (const int*)(moff + n + 1), (const double2*)p.A, p.I);
+  hipLaunchKernelGGL(k_greedy_sweep, dim3(S), dim3(kGreedyThreads), 0, st, n, (const int*)p.parent,
+                     (const uint8_t*)p.phase, (const int*)p.lvl_off, (const int*)p.lvl_nodes, g->nlev,
+                     (const int*)p.ch_off, (const int*)p.ch, (const double2*)p.z, V0[0], V0[1], V0[2],
+                     (const double2*)p.I, p.Ib, p.V);
+  char* b = (char*)ws;
+  int* rad = (int*)(b + g->o_rad);
+  int *down = rad, *up = rad + n, *cnt = rad + 2 * n, *kp_rad = rad + 3 * n, *kp_mesh = rad + 4 * n;
+  uint8_t* krad = (uint8_t*)(b + g->o_radk);
+  unsigned long long* x = (unsigned long long*)(b + g->o_radx);  // [0] critical count, [1] dv radial, [2] dv meshed
+  OKRG_HIP(g, hipMemsetAsync(x, 0, sizeof(unsigned long long) * 4, st));
+  hipLaunchKernelGGL(k_radialize, dim3(1), dim3(kGreedyPickThreads), 0, st, n, (const int*)p.parent,
+                     (const int*)p.ch_off, (const int*)p.ch, (const int*)p.lvl_off, (const int*)p.lvl_nodes, g->nlev,
+                     (const int*)p.sup, down, up, cnt, krad, kp_rad, kp_mesh, (int*)x);
+  LcaTab T;
+  T.first = p.first;
+  T.st = p.sp;
+  T.depth = p.depth;
+  T.E = g->euler_len;
+  const unsigned nb = (unsigned)(((size_t)n * S + kGreedyThreads - 1) / kGreedyThreads);
+  hipLaunchKernelGGL(k_radial_check, dim3(nb), dim3(kGreedyThreads), 0, st, n, S, (const uint8_t*)p.phase, T,
+                     (const double2*)p.Zr, (const int*)p.sup, (const uint8_t*)krad, (const int*)kp_rad, 1,
+                     (const double2*)p.I, (const double2*)p.V, V0[0], V0[1], V0[2], x + 1);
+  hipLaunchKernelGGL(k_radial_check, dim3(nb), dim3(kGreedyThreads), 0, st, n, S, (const uint8_t*)p.phase, T,
+                     (const double2*)p.Zr, (const int*)p.sup, (const uint8_t*)krad, (const int*)kp_mesh, 0,
+                     (const double2*)p.I, (const double2*)p.V, V0[0], V0[1], V0[2], x + 2);
+  OKRG_HIP(g, hipGetLastError());
+  int status[4] = {0, 0, 0, 0};
+  unsigned long long hx[4] = {0, 0, 0, 0};
+  OKRG_HIP(g, hipMemcpyAsync(status, p.status, sizeof(status), hipMemcpyDeviceToHost, st));
+  OKRG_HIP(g, hipMemcpyAsync(hx, x, sizeof(hx), hipMemcpyDeviceToHost, st));
+  OKRG_HIP(g, hipMemcpyAsync(kept_radial, krad, n, hipMemcpyDeviceToHost, st));
+  OKRG_HIP(g, hipMemcpyAsync(kept_parent, kp_rad, sizeof(int) * n, hipMemcpyDeviceToHost, st));
+  OKRG_HIP(g, hipStreamSynchronize(st));
+  rc = check_status(g, status[0]);
+  if (rc) return rc;
+  int nc;
+  std::memcpy(&nc, &hx[0], sizeof(int));
+  *n_critical = nc;
+  double d1, d2;
+  std::memcpy(&d1, &hx[1], sizeof(double));
+  std::memcpy(&d2, &hx[2], sizeof(double));
+  if (dv_radial) *dv_radial = d1;
+  if (dv_meshed) *dv_meshed = d2;
   return OKR_OK;
 }
