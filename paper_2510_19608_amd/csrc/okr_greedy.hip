@@ -1270,8 +1270,9 @@ extern "C" int okr_greedy_run(okr_greedy* g, const okr_yblocks* Y, const okr_loa
   // beyond that (or when asked) only the clusters a move can change
   const size_t lds_full = sizeof(unsigned long long) * (size_t)S * n + sizeof(PathRec) * 2 * (size_t)g->nlev;
   const size_t lds_paths = sizeof(PathRec) * 2 * (size_t)g->nlev;
+  // (the full-scoring kernel also holds about 3 KB of static LDS)
   const bool incremental =
-      (prm->flags & OKR_GREEDY_INCREMENTAL) || (size_t)S * n > kGreedyFullSN || lds_full > 64 * 1024;
+      (prm->flags & OKR_GREEDY_INCREMENTAL) || (size_t)S * n > kGreedyFullSN || lds_full > 60 * 1024;
   if (incremental && n > kGreedyMaxN)
     OKRG_FAIL(g, OKR_E_UNSUPPORTED, "the search takes at most %d nodes", kGreedyMaxN);
   const size_t lds_cnt = sizeof(int) * (size_t)n;
