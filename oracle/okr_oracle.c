@@ -18,8 +18,8 @@
  *   scenario library from AC load flow .......... Section III (library L)
  *
  * Readings of points the paper leaves open (segments, assignment direction,
- * lexicographic objective, tie rule, band margins) are listed in the design doc
- * and restated at the functions that use them.
+ * lexicographic objective, tie rule, band margins) are stated at the
+ * functions that use them.
  *
  * Parity status: every function here is pinned by CPU tests (dense pinv
  * brute force, closed forms, invariants); see tests/test_oracle.py.
@@ -707,7 +707,7 @@ typedef struct {
 
 static int popc(uint32_t m) { int c = 0; while (m) { m &= m - 1; ++c; } return c; }
 
-/* Full search (readings in the design doc):
+/* Full search (the readings taken where the paper is open):
  *  - segments in increasing id, each against the cumulative kept state left
  *    by the earlier ones (Algorithm 1's "assign previously reduced" and
  *    I <- A I^);

@@ -117,7 +117,7 @@ def lib():
     global _lib
     if _lib is None:
         if not os.path.exists(_LIB_PATH):
-            raise OkrError(OKR.E_HIP, f"{_LIB_PATH} is missing: run __graft_entry__.build()")
+            raise OkrError(OKR.E_HIP, f"{_LIB_PATH} is missing: build it (python -m paper_2510_19608_amd.build)")
         L = ctypes.CDLL(_LIB_PATH)
         vp = ctypes.c_void_p
         L.okr_create.argtypes = [ctypes.POINTER(vp), vp]

@@ -55,7 +55,7 @@ class FeederConfig:
     p_kw: Tuple[float, float] = (0.0, 50.0)
     pf: Tuple[float, float] = (0.90, 0.98)
     scale: Tuple[float, float] = (0.3, 1.0)
-    kappa: float = 1.0             # global load multiplier (generator readings)
+    kappa: float = 1.0             # global load multiplier (largest power of two keeping every snapshot in band)
     n_eligible: Optional[int] = None   # sample this many eligible nodes (None: all)
     seg_size: Tuple[int, int] = (16, 16)  # inclusive range of segment sizes
     v_min: float = 0.95
