@@ -1325,32 +1325,70 @@ extern "C" int okr_greedy_run(okr_greedy* g, const okr_yblocks* Y, const okr_loa
   } tguard{&tev};
   double score_ms = 0.0;
   int launches = 0;
+  // one iteration's two launches (and the timing events around the scoring)
+  auto enqueue_iteration = [&](int t) -> hipError_t {
+    if (timing) {
+      const hipError_t e = hipEventRecord(tev[2 * t], st);
+      if (e != hipSuccess) return e;
+    }
+    if (incremental) {
+      hipLaunchKernelGGL(k_greedy_score, dim3(2 * n), dim3(kGreedyThreads), 0, st, n, S, (const int*)p.parent,
+                         (const uint8_t*)p.phase, (const int*)p.pos, (const int*)p.size, (const int*)p.pre,
+                         (const int*)p.ch_off, (const int*)p.ch, (const int*)p.sup, T, (const double2*)p.Zr,
+                         (const double2*)p.I, (const double2*)p.V, (const double*)p.absV, e_bar,
+                         (const GState*)p.gs, p.C, p.sm, p.em);
+      if (timing) {
+        const hipError_t e = hipEventRecord(tev[2 * t + 1], st);
+        if (e != hipSuccess) return e;
+      }
+      hipLaunchKernelGGL(k_greedy_pick_apply, dim3(1), dim3(kGreedyPickThreads), lds_cnt, st, n, S,
+                         (const int*)p.parent, (const uint8_t*)p.phase, (const int*)p.pre, T, (const double2*)p.Zr,
+                         (const double*)p.absV, (const double*)p.sm, (const double*)p.em, e_bar, tie, amb, p.gs,
+                         p.steps, p.sup, p.I, p.V, p.C);
+    } else {
+      hipLaunchKernelGGL(k_greedy_score_full, dim3(2 * n), dim3(kGreedyThreads), lds_full, st, n, S,
+                         (const int*)p.parent, (const uint8_t*)p.phase, (const int*)p.pos, (const int*)p.size,
+                         (const int*)p.depth, (const int*)p.sup, (const double2*)p.Zr, (const double2*)p.I,
+                         (const double2*)p.V, (const double*)p.absV, e_bar, (const GState*)p.gs, p.sm, p.em);
+      if (timing) {
+        const hipError_t e = hipEventRecord(tev[2 * t + 1], st);
+        if (e != hipSuccess) return e;
+      }
+      hipLaunchKernelGGL(k_greedy_pick_apply_full, dim3(1), dim3(kGreedyPickThreads), lds_paths, st, n, S,
+                         (const int*)p.parent, (const int*)p.pos, (const int*)p.size, (const int*)p.depth,
+                         (const double2*)p.Zr, (const double*)p.sm, (const double*)p.em, e_bar, tie, amb, p.gs,
+                         p.steps, p.sup, p.I, p.V);
+    }
+    return hipGetLastError();
+  };
+  // Without timing, a full batch of iterations is captured once into a graph
+  // and replayed (the launches' arguments do not change between
+  // iterations; the state lives in the workspace).  No memset is captured.
+  hipGraphExec_t bexec = nullptr;
+  struct GraphGuard {
+    hipGraphExec_t* e;
+    ~GraphGuard() {
+      if (*e) (void)hipGraphExecDestroy(*e);
+    }
+  } gguard{&bexec};
+  if (!timing && st != nullptr && cap >= kBatch) {
+    hipGraph_t graph = nullptr;
+    OKRG_HIP(g, hipStreamBeginCapture(st, hipStreamCaptureModeThreadLocal));
+    hipError_t ce = hipSuccess;
+    for (int t = 0; t < kBatch && ce == hipSuccess; ++t) ce = enqueue_iteration(t);
+    const hipError_t ee = hipStreamEndCapture(st, &graph);
+    if (ce != hipSuccess || ee != hipSuccess)
+      OKRG_FAIL(g, OKR_E_HIP, "graph capture failed: %s", hipGetErrorString(ce != hipSuccess ? ce : ee));
+    const hipError_t ie = hipGraphInstantiate(&bexec, graph, nullptr, nullptr, 0);
+    (void)hipGraphDestroy(graph);
+    if (ie != hipSuccess) OKRG_FAIL(g, OKR_E_HIP, "graph instantiate failed: %s", hipGetErrorString(ie));
+  }
   while (enq < cap) {
     const int b = std::min(kBatch, cap - enq);
-    for (int t = 0; t < b; ++t) {
-      if (timing) OKRG_HIP(g, hipEventRecord(tev[2 * t], st));
-      if (incremental) {
-        hipLaunchKernelGGL(k_greedy_score, dim3(2 * n), dim3(kGreedyThreads), 0, st, n, S, (const int*)p.parent,
-                           (const uint8_t*)p.phase, (const int*)p.pos, (const int*)p.size, (const int*)p.pre,
-                           (const int*)p.ch_off, (const int*)p.ch, (const int*)p.sup, T, (const double2*)p.Zr,
-                           (const double2*)p.I, (const double2*)p.V, (const double*)p.absV, e_bar,
-                           (const GState*)p.gs, p.C, p.sm, p.em);
-        if (timing) OKRG_HIP(g, hipEventRecord(tev[2 * t + 1], st));
-        hipLaunchKernelGGL(k_greedy_pick_apply, dim3(1), dim3(kGreedyPickThreads), lds_cnt, st, n, S,
-                           (const int*)p.parent, (const uint8_t*)p.phase, (const int*)p.pre, T,
-                           (const double2*)p.Zr, (const double*)p.absV, (const double*)p.sm, (const double*)p.em,
-                           e_bar, tie, amb, p.gs, p.steps, p.sup, p.I, p.V, p.C);
-      } else {
-        hipLaunchKernelGGL(k_greedy_score_full, dim3(2 * n), dim3(kGreedyThreads), lds_full, st, n, S,
-                           (const int*)p.parent, (const uint8_t*)p.phase, (const int*)p.pos, (const int*)p.size,
-                           (const int*)p.depth, (const int*)p.sup, (const double2*)p.Zr, (const double2*)p.I,
-                           (const double2*)p.V, (const double*)p.absV, e_bar, (const GState*)p.gs, p.sm, p.em);
-        if (timing) OKRG_HIP(g, hipEventRecord(tev[2 * t + 1], st));
-        hipLaunchKernelGGL(k_greedy_pick_apply_full, dim3(1), dim3(kGreedyPickThreads), lds_paths, st, n, S,
-                           (const int*)p.parent, (const int*)p.pos, (const int*)p.size, (const int*)p.depth,
-                           (const double2*)p.Zr, (const double*)p.sm, (const double*)p.em, e_bar, tie, amb, p.gs,
-                           p.steps, p.sup, p.I, p.V);
-      }
+    if (bexec && b == kBatch) {
+      OKRG_HIP(g, hipGraphLaunch(bexec, st));
+    } else {
+      for (int t = 0; t < b; ++t) OKRG_HIP(g, enqueue_iteration(t));
     }
     OKRG_HIP(g, hipGetLastError());
     const int before = hs.iter;

@@ -162,3 +162,23 @@ def test_scoring_forms_agree_at_3000_nodes(okr):
     same_steps(b["steps"], a["steps"])
     np.testing.assert_array_equal(b["super"], a["super"])
     np.testing.assert_allclose(b["err_per_snapshot"], a["err_per_snapshot"], rtol=0, atol=TOL)
+
+
+@pytest.mark.parametrize("incremental", [False, True])
+def test_graph_replay_equals_stream_launches(okr, incremental):
+    """Without timing, full batches of 32 iterations replay one captured
+    graph; with timing every launch goes to the stream.  Both give the same
+    moves, bit for bit, over many replays with host synchronisations
+    between them."""
+    f = extreme_scenarios(hourly_feeder("c2", 2, n=300))
+    Gr = okr.Greedy(f)
+    try:
+        a = Gr.run(f["e_bar"], incremental=incremental)
+        b = Gr.run(f["e_bar"], timing=True, incremental=incremental)
+    finally:
+        Gr.close()
+    assert a["n_steps"] > 64
+    assert [(s["cand"], s["s"], s["r"]) for s in a["steps"]] == [(s["cand"], s["s"], s["r"]) for s in b["steps"]]
+    assert [s["smice"] for s in a["steps"]] == [s["smice"] for s in b["steps"]]
+    np.testing.assert_array_equal(a["super"], b["super"])
+    np.testing.assert_array_equal(a["err_per_snapshot"], b["err_per_snapshot"])
