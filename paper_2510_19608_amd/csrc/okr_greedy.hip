@@ -608,6 +608,26 @@ __device__ __forceinline__ void load_paths(int n, const int* pos, const int* siz
   }
 }
 
+// DFS intervals of the subtrees of w = lca(r, s)'s children towards r and
+// towards s (empty when r or s is w itself), from the staged root paths:
+// only nodes in them can change voltage when r's current moves to s.
+struct MoveIntervals {
+  int a1, b1, a2, b2;
+  __device__ __forceinline__ void from(const PathRec* pr, int dr, const PathRec* ps, int ds, int qs) {
+    const int dw = lca_depth(pr, min(dr, ds), qs);
+    a1 = b1 = a2 = b2 = 0;
+    if (dr > dw) {
+      a1 = pr[dw + 1].lo;
+      b1 = pr[dw + 1].hi;
+    }
+    if (ds > dw) {
+      a2 = ps[dw + 1].lo;
+      b2 = ps[dw + 1].hi;
+    }
+  }
+  __device__ __forceinline__ bool holds(int q) const { return (a1 <= q && q < b1) || (a2 <= q && q < b2); }
+};
+
 // MoveDelta with the lowest common ancestors found in the root paths of r
 // and s staged in LDS (binary search by DFS position; the full-scoring form).
 struct PathDelta {
@@ -669,12 +689,16 @@ __global__ __launch_bounds__(kGreedyThreads) void k_greedy_score_full(
   load_paths(n, pos, size, depth, r, s, pr, ps);
   for (int q = tid; q < S * 3; q += kGreedyThreads) J[q] = Iagg[((size_t)(q / 3) * n + r) * 3 + q % 3];
   __syncthreads();
+  MoveIntervals mi;
+  mi.from(pr, dr, ps, ds, pos[s]);
   double emax = 0.0;
   for (int xn = tid; xn < n; xn += kGreedyThreads) {
     int y = sup[xn];
     if (y == r) y = s;
+    const int qy = pos[y];
     PathDelta md;
-    md.at(pr, dr, ps, ds, Zr, pos[y], depth[y]);
+    if (mi.holds(qy)) md.at(pr, dr, ps, ds, Zr, qy, depth[y]);
+    else md.moved = false;
     const unsigned ph = phase[xn];
     for (int l = 0; l < S; ++l) {
       const size_t vb = ((size_t)l * n + y) * 3, xb = ((size_t)l * n + xn) * 3;
@@ -779,10 +803,14 @@ __global__ __launch_bounds__(kGreedyPickThreads) void k_greedy_pick_apply_full(
   }
   for (int u = tid; u < n; u += kGreedyPickThreads)
     if (sup[u] == r) sup[u] = s;
+  MoveIntervals mi;
+  mi.from(pr, dr, ps, ds, pos[s]);
   for (int t = tid; t < n * S; t += kGreedyPickThreads) {
     const int xn = t % n, l = t / n;
+    const int qx = pos[xn];
+    if (!mi.holds(qx)) continue;
     PathDelta md;
-    md.at(pr, dr, ps, ds, Zr, pos[xn], depth[xn]);
+    md.at(pr, dr, ps, ds, Zr, qx, depth[xn]);
     if (!md.moved) continue;
     const size_t vb = ((size_t)l * n + xn) * 3;
 #pragma unroll
