@@ -576,6 +576,33 @@ __global__ __launch_bounds__(kGreedyPickThreads) void k_greedy_pick_apply(
 
 // ---- full-scoring form --------------------------------------------------
 
+// Every node's largest error per scenario against its super-node's voltage
+// in the current state (e0[l][x]); the full-form scoring reads it for nodes
+// whose super-node's voltage a move leaves unchanged.
+__device__ __forceinline__ void node_errors(int n, int S, const uint8_t* phase, const int* sup, const double2* V,
+                                            const double* absV, double* e0, int t0, int dt) {
+  for (int t = t0; t < n * S; t += dt) {
+    const int x = t % n, l = t / n;
+    const unsigned ph = phase[x];
+    const size_t vb = ((size_t)l * n + sup[x]) * 3, xb = ((size_t)l * n + x) * 3;
+    double ex = 0.0;
+#pragma unroll
+    for (int p = 0; p < 3; ++p)
+      if (ph >> p & 1u) ex = fmax(ex, fabs(absV[xb + p] - sqrt(cabs2(V[vb + p]))));
+    e0[t] = ex;
+  }
+}
+
+__global__ __launch_bounds__(kGreedyThreads) void k_greedy_e0(int n, int S, const uint8_t* __restrict__ phase,
+                                                               const int* __restrict__ sup,
+                                                               const double2* __restrict__ V,
+                                                               const double* __restrict__ absV,
+                                                               double* __restrict__ e0) {
+  node_errors(n, S, phase, sup, V, absV, e0, blockIdx.x * blockDim.x + threadIdx.x, gridDim.x * blockDim.x);
+}
+
+
+
 struct PathRec {
   int node, lo, hi;  // an ancestor and the DFS position range of its subtree
 };
@@ -658,8 +685,8 @@ __global__ __launch_bounds__(kGreedyThreads) void k_greedy_score_full(
     int n, int S, const int* __restrict__ parent, const uint8_t* __restrict__ phase, const int* __restrict__ pos,
     const int* __restrict__ size, const int* __restrict__ depth, const int* __restrict__ sup,
     const double2* __restrict__ Zr, const double2* __restrict__ Iagg, const double2* __restrict__ Vcur,
-    const double* __restrict__ absV, double e_bar, const GState* __restrict__ gs, double* __restrict__ sm,
-    double* __restrict__ em) {
+    const double* __restrict__ absV, const double* __restrict__ e0, double e_bar, const GState* __restrict__ gs,
+    double* __restrict__ sm, double* __restrict__ em) {
   extern __shared__ __align__(16) unsigned char g_lds[];
   __shared__ double2 J[kGreedyMaxS * 3];
   __shared__ double red[kGreedyThreads / 64];
@@ -693,9 +720,16 @@ __global__ __launch_bounds__(kGreedyThreads) void k_greedy_score_full(
   mi.from(pr, dr, ps, ds, pos[s]);
   double emax = 0.0;
   for (int xn = tid; xn < n; xn += kGreedyThreads) {
-    int y = sup[xn];
-    if (y == r) y = s;
+    const int y0 = sup[xn], y = y0 == r ? s : y0;
     const int qy = pos[y];
+    if (y0 != r && !mi.holds(qy)) {  // same super-node, same voltage: the stored errors
+      for (int l = 0; l < S; ++l) {
+        const double ex = e0[(size_t)l * n + xn];
+        atomicMax(&mice[(size_t)l * n + y], (unsigned long long)__double_as_longlong(ex));
+        emax = fmax(emax, ex);
+      }
+      continue;
+    }
     PathDelta md;
     if (mi.holds(qy)) md.at(pr, dr, ps, ds, Zr, qy, depth[y]);
     else md.moved = false;
@@ -742,7 +776,8 @@ __global__ __launch_bounds__(kGreedyPickThreads) void k_greedy_pick_apply_full(
     int n, int S, const int* __restrict__ parent, const int* __restrict__ pos, const int* __restrict__ size,
     const int* __restrict__ depth, const double2* __restrict__ Zr, const double* __restrict__ sm,
     const double* __restrict__ em, double e_bar, double tie, double amb, GState* __restrict__ gs,
-    GStep* __restrict__ steps, int* __restrict__ sup, double2* __restrict__ Iagg, double2* __restrict__ V) {
+    GStep* __restrict__ steps, int* __restrict__ sup, double2* __restrict__ Iagg, double2* __restrict__ V,
+    const uint8_t* __restrict__ phase, const double* __restrict__ absV, double* __restrict__ e0) {
   extern __shared__ __align__(16) unsigned char g_lds[];
   __shared__ double shd[kGreedyPickThreads / 64];
   __shared__ int shi[kGreedyPickThreads / 64];
@@ -816,6 +851,8 @@ __global__ __launch_bounds__(kGreedyPickThreads) void k_greedy_pick_apply_full(
 #pragma unroll
     for (int p = 0; p < 3; ++p) V[vb + p] = cadd(V[vb + p], md.dv(p, J + l * 3));
   }
+  __syncthreads();
+  node_errors(n, S, phase, sup, V, absV, e0, tid, kGreedyPickThreads);
 }
 
 // ---- radialization (Section V) --------------------------------------------
@@ -977,6 +1014,7 @@ struct okr_greedy {
   size_t o_mice = 0, o_arr = 0, o_bmax = 0, o_moff = 0, o_mem = 0, o_tot = 0;
   // radialization: 5 int arrays of n, kept flags, counter, two maxima
   size_t o_rad = 0, o_radk = 0, o_radx = 0;
+  size_t o_e0 = 0;  // every node's error per scenario in the current state
   std::vector<int> topo_host;
 };
 
@@ -1156,6 +1194,7 @@ extern "C" int okr_greedy_plan(okr_greedy* g, int32_t n, const int32_t* parent, 
   g->o_rad = take(sizeof(int) * 5 * (size_t)n);
   g->o_radk = take(n);
   g->o_radx = take(sizeof(unsigned long long) * 4);
+  g->o_e0 = take(sizeof(double) * (size_t)S * n);
   g->total = off;
   *workspace_bytes = off;
   g->planned = true;
@@ -1169,7 +1208,7 @@ struct GPtrs {
   Clusters C;
   uint8_t* phase;
   double2 *z, *Zr, *Vhat, *A, *I, *V, *Ib;
-  double *absV, *sm, *em, *err;
+  double *absV, *sm, *em, *err, *e0;
   GStep* steps;
   GState* gs;
 };
@@ -1212,6 +1251,7 @@ GPtrs gptrs(const okr_greedy* g, void* ws) {
   p.status = (int*)(b + g->o_status);
   p.iters = (int*)(b + g->o_iters);
   p.err = (double*)(b + g->o_err);
+  p.e0 = (double*)(b + g->o_e0);
   return p;
 }
 
@@ -1333,6 +1373,10 @@ extern "C" int okr_greedy_run(okr_greedy* g, const okr_yblocks* Y, const okr_loa
   if (incremental)
     hipLaunchKernelGGL(k_greedy_prep, dim3(1), dim3(kGreedyPickThreads), lds_cnt, st, n, S, (const uint8_t*)p.phase,
                        (const int*)p.pre, (const int*)p.sup, (const double2*)p.V, (const double*)p.absV, p.C);
+  else
+    hipLaunchKernelGGL(k_greedy_e0, dim3((unsigned)(((size_t)n * S + kGreedyThreads - 1) / kGreedyThreads)),
+                       dim3(kGreedyThreads), 0, st, n, S, (const uint8_t*)p.phase, (const int*)p.sup,
+                       (const double2*)p.V, (const double*)p.absV, p.e0);
   OKRG_HIP(g, hipGetLastError());
   OKRG_HIP(g, hipEventRecord(ev[1], st));
   const double e_bar = prm->e_bar, tie = prm->tie_tol > 0 ? prm->tie_tol : 1e-11;
@@ -1377,7 +1421,8 @@ extern "C" int okr_greedy_run(okr_greedy* g, const okr_yblocks* Y, const okr_loa
       hipLaunchKernelGGL(k_greedy_score_full, dim3(2 * n), dim3(kGreedyThreads), lds_full, st, n, S,
                          (const int*)p.parent, (const uint8_t*)p.phase, (const int*)p.pos, (const int*)p.size,
                          (const int*)p.depth, (const int*)p.sup, (const double2*)p.Zr, (const double2*)p.I,
-                         (const double2*)p.V, (const double*)p.absV, e_bar, (const GState*)p.gs, p.sm, p.em);
+                         (const double2*)p.V, (const double*)p.absV, (const double*)p.e0, e_bar,
+                         (const GState*)p.gs, p.sm, p.em);
       if (timing) {
         const hipError_t e = hipEventRecord(tev[2 * t + 1], st);
         if (e != hipSuccess) return e;
@@ -1385,7 +1430,7 @@ extern "C" int okr_greedy_run(okr_greedy* g, const okr_yblocks* Y, const okr_loa
       hipLaunchKernelGGL(k_greedy_pick_apply_full, dim3(1), dim3(kGreedyPickThreads), lds_paths, st, n, S,
                          (const int*)p.parent, (const int*)p.pos, (const int*)p.size, (const int*)p.depth,
                          (const double2*)p.Zr, (const double*)p.sm, (const double*)p.em, e_bar, tie, amb, p.gs,
-                         p.steps, p.sup, p.I, p.V);
+                         p.steps, p.sup, p.I, p.V, (const uint8_t*)p.phase, (const double*)p.absV, p.e0);
     }
     return hipGetLastError();
   };
