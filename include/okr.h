@@ -164,8 +164,10 @@ typedef struct {
     double e_min;       /* smallest error at the chosen level */
     int32_t ambiguous;  /* a candidate lay within amb_tol of a decision boundary */
     int32_t n_scored;   /* masks scored exactly */
-    double flops;       /* algorithmic flops of the per-mask scoring kernel
-                           (0 with OKR_PRECISION_FP64_FACTORED) */
+    double flops;       /* algorithmic flops of scoring the segment's 2^k
+                           candidates (the method's own work per candidate and
+                           snapshot, see okr_result.algorithmic_flops; 0 with
+                           OKR_PRECISION_FP64_FACTORED) */
     float score_ms;     /* scoring-kernel time of the segment's chunk divided
                            by the chunk's segments (OKR_FLAG_TIMING) */
     int32_t n_refined;  /* MIXED: masks rescored in FP64 (shortlists A + B) */
@@ -173,6 +175,9 @@ typedef struct {
     int32_t score_groups;   /* FP64 scoring launch shape: snapshot groups ... */
     int32_t score_mpl;      /* ... and masks per lane (default rule or autotuned) */
     int32_t chunk;          /* index of the launch chunk the segment ran in */
+    double kernel_flops;    /* flops the per-mask scoring kernel itself performs
+                               (shared tables replace the per-candidate
+                               voltage-change products; 0 with FACTORED) */
 } okr_segment_result;
 
 /* Outputs (HOST buffers owned by the caller). */
@@ -193,8 +198,15 @@ typedef struct {
     double max_err;
     /* wall-clock phase times (ms) and summed kernel times (OKR_FLAG_TIMING) */
     double t_setup_ms, t_pf_ms, t_search_ms, t_final_ms;
+    /* algorithmic_flops: per candidate and snapshot, 2|phi_r| per reduced
+       node and hop to its super-node (moved current), 8|phi_e|^2 + 2|phi_e|
+       per edge carrying it (voltage change), 2|phi| per segment node (shift),
+       10 per node-phase of the affected region (magnitude, error, margins);
+       plus 18 per reduced node per candidate (series sums); averaged exactly
+       over the masks.  kernel_form_flops: what the scoring kernel computes. */
     double score_kernel_ms, algorithmic_flops;
     int32_t pf_iterations, n_score_launches; /* scoring launches: one per chunk */
+    double kernel_form_flops;
 } okr_result;
 
 /* One handle per HIP stream (hip_stream may be NULL for the null stream).

@@ -74,7 +74,8 @@ class SegmentResult(ctypes.Structure):
                 ("popcount", ctypes.c_int32), ("e_loc", ctypes.c_double), ("e_min", ctypes.c_double),
                 ("ambiguous", ctypes.c_int32), ("n_scored", ctypes.c_int32), ("flops", ctypes.c_double),
                 ("score_ms", ctypes.c_float), ("n_refined", ctypes.c_int32), ("fp32_dev", ctypes.c_double),
-                ("score_groups", ctypes.c_int32), ("score_mpl", ctypes.c_int32), ("chunk", ctypes.c_int32)]
+                ("score_groups", ctypes.c_int32), ("score_mpl", ctypes.c_int32), ("chunk", ctypes.c_int32),
+                ("kernel_flops", ctypes.c_double)]
 
 
 class Result(ctypes.Structure):
@@ -85,7 +86,8 @@ class Result(ctypes.Structure):
                 ("max_err", ctypes.c_double), ("t_setup_ms", ctypes.c_double), ("t_pf_ms", ctypes.c_double),
                 ("t_search_ms", ctypes.c_double), ("t_final_ms", ctypes.c_double),
                 ("score_kernel_ms", ctypes.c_double), ("algorithmic_flops", ctypes.c_double),
-                ("pf_iterations", ctypes.c_int32), ("n_score_launches", ctypes.c_int32)]
+                ("pf_iterations", ctypes.c_int32), ("n_score_launches", ctypes.c_int32),
+                ("kernel_form_flops", ctypes.c_double)]
 
 
 class GreedyParams(ctypes.Structure):
@@ -372,7 +374,8 @@ class Reducer:
         segs = [dict(segment=s.segment, k=s.k, mask=s.mask, popcount=s.popcount, e_loc=s.e_loc,
                      e_min=s.e_min, ambiguous=bool(s.ambiguous), n_scored=s.n_scored, flops=s.flops,
                      score_ms=s.score_ms, n_refined=s.n_refined, fp32_dev=s.fp32_dev,
-                     score_groups=s.score_groups, score_mpl=s.score_mpl, chunk=s.chunk)
+                     score_groups=s.score_groups, score_mpl=s.score_mpl, chunk=s.chunk,
+                     kernel_flops=s.kernel_flops)
                 for s in list(self.out_seg)[:self.sizes.n_segments]]
         return dict(super=self.out_super.copy(), kept_parent=self.out_kp.copy(),
                     kept=(self.out_super == np.arange(self.n)).astype(np.uint8),
@@ -380,7 +383,8 @@ class Reducer:
                     err_per_snapshot=self.out_err.copy(), max_err=r.max_err, n_kept=r.n_kept,
                     warnings=r.warnings, segments=segs, t_pf_ms=r.t_pf_ms, t_search_ms=r.t_search_ms,
                     t_final_ms=r.t_final_ms, score_kernel_ms=r.score_kernel_ms,
-                    algorithmic_flops=r.algorithmic_flops, pf_iterations=r.pf_iterations,
+                    algorithmic_flops=r.algorithmic_flops, kernel_form_flops=r.kernel_form_flops,
+                    pf_iterations=r.pf_iterations,
                     n_score_launches=r.n_score_launches, Vhat=self.out_Vhat)
 
     def dump_scores(self, g):

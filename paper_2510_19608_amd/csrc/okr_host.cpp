@@ -281,6 +281,88 @@ extern "C" int okr_destroy(okr_handle* h) {
   return OKR_OK;
 }
 
+namespace {
+// The method's own work of scoring segment g's 2^k candidates over S
+// snapshots, from the kept state before the segment (keep): per candidate
+// and snapshot, 2|phi_r| per reduced node r and hop to its super-node (the
+// moved current), 8|phi_e|^2 + 2|phi_e| per edge carrying it (the voltage
+// change), 2|phi| per segment node (the shift below the segment), 10 per
+// node-phase of the affected region (magnitude, error, margins); plus 18 per
+// reduced node per candidate (series sums of the Kron step).  The first two
+// terms are averaged exactly over the masks, chain by chain: a reduced node's
+// current climbs through reduced nodes to the first kept one, so only the
+// segment nodes of its own chain matter.
+double method_flops(const okr_handle* h, int g, const std::vector<uint8_t>& keep, int S) {
+  const int k = h->seg_off[g + 1] - h->seg_off[g];
+  const int* nodes = h->seg_nodes.data() + h->seg_off[g];
+  auto ph = [&](int v) { return (double)__builtin_popcount(h->phase[v]); };
+  // chain tops: climb through segment nodes and reduced nodes
+  std::vector<int> top(k);
+  for (int j = 0; j < k; ++j) {
+    int c = nodes[j];
+    while (h->parent[c] >= 0 && (h->segment[h->parent[c]] == g || !keep[h->parent[c]])) c = h->parent[c];
+    top[j] = c;
+  }
+  // node-phases of the affected region: union of the tops' subtrees
+  std::vector<std::pair<int, int>> iv;
+  for (int j = 0; j < k; ++j) iv.push_back({h->pos[top[j]], h->pos[top[j]] + h->size[top[j]]});
+  std::sort(iv.begin(), iv.end());
+  double np_omega = 0.0;
+  int reach = -1;
+  for (auto& r : iv) {
+    for (int q = std::max(r.first, reach); q < r.second; ++q) np_omega += ph(h->pre[q]);
+    reach = std::max(reach, r.second);
+  }
+  double per = 10.0 * np_omega;
+  for (int j = 0; j < k; ++j) per += 2.0 * ph(nodes[j]);
+  // moved currents and voltage changes, chain by chain
+  std::vector<char> done(k, 0);
+  for (int j0 = 0; j0 < k; ++j0) {
+    if (done[j0]) continue;
+    // the chain: the path from its top down to its deepest segment node
+    int bottom = nodes[j0];
+    std::vector<int> bits;  // segment positions in this chain
+    for (int j = 0; j < k; ++j)
+      if (top[j] == top[j0]) {
+        bits.push_back(j);
+        done[j] = 1;
+        if (h->pos[nodes[j]] > h->pos[bottom]) bottom = nodes[j];
+      }
+    std::vector<int> path;  // bottom .. top
+    for (int c = bottom;; c = h->parent[c]) {
+      path.push_back(c);
+      if (c == top[j0]) break;
+    }
+    std::reverse(path.begin(), path.end());  // top .. bottom
+    const int L = (int)path.size(), b = (int)bits.size();
+    std::vector<int> bit_of(L, -1);
+    for (int i = 0; i < L; ++i)
+      for (int t = 0; t < b; ++t)
+        if (nodes[bits[t]] == path[i]) bit_of[i] = t;
+    double acc = 0.0;
+    std::vector<char> carry(L);
+    for (uint32_t m = 0; m < (1u << b); ++m) {
+      int stop = -1;  // index of the nearest kept node above (-1: the head)
+      std::fill(carry.begin(), carry.end(), 0);
+      for (int i = 0; i < L; ++i) {
+        if (bit_of[i] < 0) continue;  // reduced earlier: the current passes through
+        if (!(m >> bit_of[i] & 1u)) {
+          stop = i;
+          continue;
+        }
+        acc += 2.0 * ph(path[i]) * (i - stop);
+        for (int t = i; t > stop; --t) carry[t] = 1;
+      }
+      for (int i = 0; i < L; ++i)
+        if (carry[i]) acc += 8.0 * ph(path[i]) * ph(path[i]) + 2.0 * ph(path[i]);
+    }
+    per += acc / double(1u << b);
+  }
+  const double masks = double(int64_t(1) << k);
+  return per * masks * S + 18.0 * 0.5 * k * masks;
+}
+}  // namespace
+
 extern "C" const char* okr_last_error(const okr_handle* h) { return h ? h->err.c_str() : "null handle"; }
 
 // ------------------------------------------------------------------- plan --
@@ -1167,6 +1249,8 @@ extern "C" int okr_reduce_feeder(okr_handle* h, const okr_yblocks* Y, const okr_
   out->warnings = base_out ? OKR_W_BASE_OUT_OF_BAND : 0;
   out->score_kernel_ms = 0.0;
   out->algorithmic_flops = 0.0;
+  out->kernel_form_flops = 0.0;
+  std::vector<uint8_t> keep_before(n, 1);  // kept state before each segment, in segment order
   const int nchunk = (int)h->chunk_k.size();
   out->n_score_launches = nchunk;
   std::vector<int> chunk_of(std::max(nseg, 1), 0);
@@ -1198,17 +1282,21 @@ extern "C" int okr_reduce_feeder(okr_handle* h, const okr_yblocks* Y, const okr_
       R.score_mpl = sv_spp(score_mpl(h, kc), kc, spg);
       R.chunk = chunk_of[g];
     }
-    // algorithmic FP64 flops: per slot and mask, reduced -> 6 + 4|phi|,
-    // kept -> 14|phi| (half the masks each); per zone entry 14
+    // the scoring kernel's own FP64 work: per slot and mask, reduced ->
+    // 6 + 4|phi|, kept -> 14|phi| (half the masks each); per zone entry 14
     double fl = 0.0;
     for (int q = h->seg_off[g]; q < h->seg_off[g + 1]; ++q) {
       const int np = __builtin_popcount(h->phase[h->seg_nodes[q]]);
       fl += 0.5 * (6.0 + 4.0 * np) + 0.5 * (14.0 * np);
     }
     fl += 14.0 * hdrs[g].nz;
-    // (the per-mask form's count; the factored form does not do this work)
-    R.flops = mg->precision == OKR_PRECISION_FP64_FACTORED ? 0.0 : fl * double(int64_t(1) << k) * S;
+    const bool per_mask = mg->precision != OKR_PRECISION_FP64_FACTORED;
+    R.kernel_flops = per_mask ? fl * double(int64_t(1) << k) * S : 0.0;
+    out->kernel_form_flops += R.kernel_flops;
+    R.flops = per_mask ? method_flops(h, g, keep_before, S) : 0.0;
     out->algorithmic_flops += R.flops;
+    for (int j = 0; j < k; ++j)  // the state the next segments see
+      if (decs[g].mask >> j & 1u) keep_before[h->seg_nodes[h->seg_off[g] + j]] = 0;
     if (mixed) {
       R.n_refined = mstate[g].nA + mstate[g].nB;
       R.fp32_dev = mstate[g].max_dev;
