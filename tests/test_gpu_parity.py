@@ -9,7 +9,7 @@ import numpy as np
 import pytest
 
 import oracle
-from synth_feeders import make_feeder
+from synth_feeders import dfs_preorder, make_feeder
 
 pytestmark = pytest.mark.gpu
 
@@ -318,3 +318,62 @@ def test_concurrent_lanes_give_identical_results(okr, cfg, lanes, precision, gra
     np.testing.assert_array_equal(out["err_per_snapshot"], ref["err_per_snapshot"])
     np.testing.assert_array_equal(out["Yk_diag"], ref["Yk_diag"])
     np.testing.assert_array_equal(out["kept"], ref["kept"])
+
+
+def _method_flops_brute(f, keep, g, S):
+    """Per-candidate work of segment g by brute force over its masks: 2|phi|
+    per reduced node and hop to its super-node, 8|phi|^2 + 2|phi| per edge
+    carrying a moved current, 2|phi| per segment node, 10 per node-phase of
+    the affected region, 18 per reduced node per candidate."""
+    parent, phase, seg = f["parent"], f["phase"], f["segment"]
+    ph = lambda v: bin(int(phase[v])).count("1")
+    nodes = [int(v) for v in dfs_preorder(parent) if seg[v] == g]
+    k = len(nodes)
+    tops = []
+    for e in nodes:
+        c = e
+        while parent[c] >= 0 and (seg[parent[c]] == g or not keep[parent[c]]):
+            c = int(parent[c])
+        tops.append(c)
+    order = dfs_preorder(parent)
+    pos = {int(v): i for i, v in enumerate(order)}
+    size = np.ones(len(parent), int)
+    for v in order[::-1]:
+        if parent[v] >= 0:
+            size[parent[v]] += size[v]
+    omega = set()
+    for t in tops:
+        omega.update(int(u) for u in order[pos[t]:pos[t] + size[t]])
+    const = 10 * sum(ph(u) for u in omega) + 2 * sum(ph(e) for e in nodes)
+    tot = 0.0
+    for m in range(1 << k):
+        red = {nodes[j] for j in range(k) if m >> j & 1}
+        carry, hop = set(), 0.0
+        for r in red:
+            c, h = r, 0
+            while True:
+                carry.add(c)
+                h += 1
+                p = int(parent[c])
+                if p < 0 or (p not in red and keep[p] and seg[p] != g) or (seg[p] == g and p not in red):
+                    break
+                c = p
+            hop += 2 * ph(r) * h
+        tot += (hop + sum(8 * ph(c) ** 2 + 2 * ph(c) for c in carry) + const) * S + 18 * len(red)
+    return tot
+
+
+def test_algorithmic_flop_count():
+    """The library's per-segment algorithmic flop count (exact mask averages,
+    chain by chain) equals a brute force over every mask of every segment."""
+    import paper_2510_19608_amd as okr
+    f = make_feeder("c1", 5, n=40, n_eligible=None, seg_size=(3, 7), snapshots=2)
+    out = okr.reduce_feeder(f, want_vhat=False, timing=True)
+    keep = np.ones(f["n"], bool)
+    for g, s in enumerate(out["segments"]):
+        want = _method_flops_brute(f, keep, g, 2)
+        assert abs(s["flops"] - want) <= 1e-9 * want, (g, s["flops"], want)
+        nodes = [int(v) for v in dfs_preorder(f["parent"]) if f["segment"][v] == g]
+        for j, v in enumerate(nodes):
+            if s["mask"] >> j & 1:
+                keep[v] = False
