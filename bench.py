@@ -36,8 +36,8 @@ FP64_VECTOR_PEAK_TFLOPS = 78.6   # MI355X FP64 vector (256 CUs x 2.4 GHz x 128 f
 # they were taken with: any change to them reports null.
 TRAFFIC_SOURCES = ["paper_2510_19608_amd/csrc/okr_score.hip", "paper_2510_19608_amd/csrc/okr_device.h",
                    "paper_2510_19608_amd/csrc/okr_internal.h", "paper_2510_19608_amd/csrc/okr_host.cpp"]
-TRAFFIC_SHA1 = "9447c5cffe6c5c7ee96a1ad482f451681a5f83de"
-TRAFFIC_BYTES_PER_LAUNCH = 9143535
+TRAFFIC_SHA1 = "7360338a88af12fd68d1b0f70f4bb42400703821"
+TRAFFIC_BYTES_PER_LAUNCH = 9143639
 
 
 def measured_traffic():
