@@ -182,3 +182,30 @@ def test_graph_replay_equals_stream_launches(okr, incremental):
     assert [s["smice"] for s in a["steps"]] == [s["smice"] for s in b["steps"]]
     np.testing.assert_array_equal(a["super"], b["super"])
     np.testing.assert_array_equal(a["err_per_snapshot"], b["err_per_snapshot"])
+
+
+def test_edge_cases(okr):
+    """Degenerate inputs: a two-node feeder (one candidate), a single node
+    (nothing to do), a bound no move meets (nothing reduced), the largest
+    scenario count (64) and one above it (refused)."""
+    f2 = make_feeder("c2", 0, n=2, snapshots=1)
+    V, I, _, _ = oracle.powerflow(f2)
+    sup, steps, err = G.greedy(f2, V, I, e_bar=1.0)
+    out = okr.greedy(f2, e_bar=1.0)
+    same_steps(out["steps"], steps)
+    assert out["n_steps"] == 1 and out["n_kept"] == 1 and list(out["super"]) == [0, 0]
+    f1 = make_feeder("c2", 0, n=1, snapshots=1)
+    out = okr.greedy(f1, e_bar=1.0)
+    assert out["n_steps"] == 0 and out["n_kept"] == 1 and out["max_err"] == 0.0
+    f = make_feeder("c2", 3, n=40, snapshots=2)
+    out = okr.greedy(f, e_bar=1e-14)
+    assert out["n_steps"] == 0 and list(out["super"]) == list(range(40))
+    f64 = make_feeder("c2", 4, n=30, snapshots=64)
+    V, I, _, _ = oracle.powerflow(f64)
+    sup, steps, err = G.greedy(f64, V, I, e_bar=1e-3, max_iter=5)
+    out = okr.greedy(f64, e_bar=1e-3, max_iter=5)
+    same_steps(out["steps"], steps)
+    f65 = make_feeder("c2", 4, n=30, snapshots=65)
+    with pytest.raises(okr.OkrError) as e:
+        okr.greedy(f65, e_bar=1e-3)
+    assert e.value.code == okr.OKR.E_UNSUPPORTED

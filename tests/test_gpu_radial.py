@@ -97,3 +97,13 @@ def test_radialize_1000_node_search(okr):
     np.testing.assert_array_equal(r["kept_radial"].astype(bool), want)
     assert r["n_critical"] == len(crit) > 0
     assert r["dv_radial"] <= 1e-12 < r["dv_meshed"]
+
+
+def test_radialize_degenerate_assignments(okr):
+    """Nothing reduced (no clique, nothing critical), and everything in the
+    slack's cluster (a single kept node: no clique either)."""
+    f = make_feeder("c2", 1, n=40, snapshots=1)
+    for sup in (np.arange(f["n"]), np.zeros(f["n"], int)):
+        out, crit = check(okr, f, sup)
+        assert crit == [] and out["n_critical"] == 0
+        assert out["dv_radial"] <= 1e-12 and out["dv_meshed"] <= 1e-12
