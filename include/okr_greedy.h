@@ -137,7 +137,8 @@ int okr_greedy_evaluate(okr_greedy* g, const okr_yblocks* Y, const okr_loads* lo
  * Outputs (HOST): kept_radial[n] (1 for super-nodes and critical nodes),
  * kept_parent[n] (each node's nearest kept proper ancestor in the radialized
  * set, -1 at the slack: the edges of the radial reduced network),
- * *n_critical, and the voltage checks over loads->S scenarios (may be NULL):
+ * *n_critical, and the voltage checks over the first min(loads->S, 4)
+ * scenarios (the check costs n^2 per scenario; may be NULL):
  * *dv_radial, the largest distance between the kept nodes' voltages of the
  * radial network built on kept_parent (series impedances, aggregated
  * currents) and those of the full network (about 1e-15 when radialization

@@ -1620,11 +1620,14 @@ extern "C" int okr_greedy_radialize(okr_greedy* g, const okr_yblocks* Y, const o
   T.st = p.sp;
   T.depth = p.depth;
   T.E = g->euler_len;
-  const unsigned nb = (unsigned)(((size_t)n * S + kGreedyThreads - 1) / kGreedyThreads);
-  hipLaunchKernelGGL(k_radial_check, dim3(nb), dim3(kGreedyThreads), 0, st, n, S, (const uint8_t*)p.phase, T,
+  // the check costs n x n per scenario: the first four scenarios suffice
+  // (a missed critical node shows in any scenario that loads its branches)
+  const int Sc = std::min(S, 4);
+  const unsigned nb = (unsigned)(((size_t)n * Sc + kGreedyThreads - 1) / kGreedyThreads);
+  hipLaunchKernelGGL(k_radial_check, dim3(nb), dim3(kGreedyThreads), 0, st, n, Sc, (const uint8_t*)p.phase, T,
                      (const double2*)p.Zr, (const int*)p.sup, (const uint8_t*)krad, (const int*)kp_rad, 1,
                      (const double2*)p.I, (const double2*)p.V, V0[0], V0[1], V0[2], x + 1);
-  hipLaunchKernelGGL(k_radial_check, dim3(nb), dim3(kGreedyThreads), 0, st, n, S, (const uint8_t*)p.phase, T,
+  hipLaunchKernelGGL(k_radial_check, dim3(nb), dim3(kGreedyThreads), 0, st, n, Sc, (const uint8_t*)p.phase, T,
                      (const double2*)p.Zr, (const int*)p.sup, (const uint8_t*)krad, (const int*)kp_mesh, 0,
                      (const double2*)p.I, (const double2*)p.V, V0[0], V0[1], V0[2], x + 2);
   OKRG_HIP(g, hipGetLastError());
