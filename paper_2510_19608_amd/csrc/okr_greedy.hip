@@ -369,82 +369,82 @@ __global__ __launch_bounds__(kGreedyThreads) void k_greedy_score(
   }
   for (int l = tid; l < S; l += kGreedyThreads) newS[l] = 0ull;
   __syncthreads();
-  for (int q = tid; q < S * 3; q += kGreedyThreads) {
-    const int l = q / 3, p = q % 3;
-    double2 v = Vcur[((size_t)l * n + s) * 3 + p];
-    if (msd.moved) v = cadd(v, msd.dv(p, J + l * 3));
-    magS[q] = sqrt(cabs2(v));
+  for (int l = tid; l < S; l += kGreedyThreads) {
+#pragma unroll
+    for (int p = 0; p < 3; ++p) {  // unrolled: msd.dZ stays in registers
+      double2 v = Vcur[((size_t)l * n + s) * 3 + p];
+      if (msd.moved) v = cadd(v, msd.dv(p, J + l * 3));
+      magS[l * 3 + p] = sqrt(cabs2(v));
+    }
   }
   __syncthreads();
   double olds = 0.0, news = 0.0, emx = 0.0;
-  // clusters whose super-node lies in I_r or I_s (other than r and s): each
-  // wave takes 64 positions at a time; a lane scores the cluster of its
-  // position when it has at most kSmallCluster members, and the wave scores
-  // the larger ones together (64 members at a time)
+  // clusters whose super-node lies in I_r or I_s (other than r and s), the
+  // two intervals walked as one range: each wave takes 64 positions at a
+  // time; a lane scores the cluster of its position when it has at most
+  // kSmallCluster members, and the wave scores the larger ones together (64
+  // members at a time)
   {
-    const int lane = tid & 63, wv = tid >> 6;
-    for (int iv = 0; iv < 2; ++iv) {
-      const int lo = iv ? a2 : a1, hi = iv ? b2 : b1;
-      for (int c0 = lo + wv * 64; c0 < hi; c0 += kGreedyThreads) {
-        const int q = c0 + lane;
-        int u = -1, m0 = 0, m1 = 0;
-        bool is = false;
-        if (q < hi) {
-          u = pre[q];
-          is = sup[u] == u && u != r && u != s;
-          if (is) {
-            m0 = C.moff[u];
-            m1 = C.moff[u + 1];
-          }
+    const int lane = tid & 63, wv = tid >> 6, L1 = b1 - a1, L = L1 + (b2 - a2);
+    for (int c0 = wv * 64; c0 < L; c0 += kGreedyThreads) {
+      const int qi = c0 + lane;  // index into I_r then I_s
+      int u = -1, m0 = 0, m1 = 0;
+      bool is = false;
+      if (qi < L) {
+        u = pre[qi < L1 ? a1 + qi : a2 + (qi - L1)];
+        is = sup[u] == u && u != r && u != s;
+        if (is) {
+          m0 = C.moff[u];
+          m1 = C.moff[u + 1];
         }
-        const bool big = is && m1 - m0 > kSmallCluster;
-        if (is && !big) {
-          MoveDelta md;
-          md.at(T, Zr, u, r, s);
-          for (int l = 0; l < S; ++l) {
-            double mag[3];
+      }
+      const bool big = is && m1 - m0 > kSmallCluster;
+      if (is && !big) {
+        MoveDelta md;
+        md.at(T, Zr, u, r, s);
+        for (int l = 0; l < S; ++l) {
+          double mag[3];
 #pragma unroll
-            for (int p = 0; p < 3; ++p) {
-              double2 v = Vcur[((size_t)l * n + u) * 3 + p];
-              if (md.moved) v = cadd(v, md.dv(p, J + l * 3));
-              mag[p] = sqrt(cabs2(v));
-            }
-            double mx = 0.0;
-            for (int k = m0; k < m1; ++k) {
-              const int m = C.mem[k];
-              mx = fmax(mx, member_err(absV, n, m, l, phase[m], mag));
-            }
-            olds += C.mice[(size_t)l * n + u];
+          for (int p = 0; p < 3; ++p) {
+            double2 v = Vcur[((size_t)l * n + u) * 3 + p];
+            if (md.moved) v = cadd(v, md.dv(p, J + l * 3));
+            mag[p] = sqrt(cabs2(v));
+          }
+          double mx = 0.0;
+          for (int k = m0; k < m1; ++k) {
+            const int m = C.mem[k];
+            mx = fmax(mx, member_err(absV, n, m, l, phase[m], mag));
+          }
+          olds += C.mice[(size_t)l * n + u];
+          news += mx;
+          emx = fmax(emx, mx);
+        }
+      }
+      unsigned long long mask = __ballot(big);
+      while (mask) {
+        const int bit = __ffsll((long long)mask) - 1;
+        mask &= mask - 1;
+        const int uu = __shfl(u, bit, 64), k0 = __shfl(m0, bit, 64), k1 = __shfl(m1, bit, 64);
+        MoveDelta md;
+        md.at(T, Zr, uu, r, s);
+        for (int l = 0; l < S; ++l) {
+          double mag[3];
+#pragma unroll
+          for (int p = 0; p < 3; ++p) {
+            double2 v = Vcur[((size_t)l * n + uu) * 3 + p];
+            if (md.moved) v = cadd(v, md.dv(p, J + l * 3));
+            mag[p] = sqrt(cabs2(v));
+          }
+          double mx = 0.0;
+          for (int k = k0 + lane; k < k1; k += 64) {
+            const int m = C.mem[k];
+            mx = fmax(mx, member_err(absV, n, m, l, phase[m], mag));
+          }
+          for (int o = 32; o > 0; o >>= 1) mx = fmax(mx, __shfl_xor(mx, o, 64));
+          if (lane == 0) {
+            olds += C.mice[(size_t)l * n + uu];
             news += mx;
             emx = fmax(emx, mx);
-          }
-        }
-        unsigned long long mask = __ballot(big);
-        while (mask) {
-          const int bit = __ffsll((long long)mask) - 1;
-          mask &= mask - 1;
-          const int uu = __shfl(u, bit, 64), k0 = __shfl(m0, bit, 64), k1 = __shfl(m1, bit, 64);
-          MoveDelta md;
-          md.at(T, Zr, uu, r, s);
-          for (int l = 0; l < S; ++l) {
-            double mag[3];
-#pragma unroll
-            for (int p = 0; p < 3; ++p) {
-              double2 v = Vcur[((size_t)l * n + uu) * 3 + p];
-              if (md.moved) v = cadd(v, md.dv(p, J + l * 3));
-              mag[p] = sqrt(cabs2(v));
-            }
-            double mx = 0.0;
-            for (int k = k0 + lane; k < k1; k += 64) {
-              const int m = C.mem[k];
-              mx = fmax(mx, member_err(absV, n, m, l, phase[m], mag));
-            }
-            for (int o = 32; o > 0; o >>= 1) mx = fmax(mx, __shfl_xor(mx, o, 64));
-            if (lane == 0) {
-              olds += C.mice[(size_t)l * n + uu];
-              news += mx;
-              emx = fmax(emx, mx);
-            }
           }
         }
       }
@@ -601,14 +601,10 @@ __global__ __launch_bounds__(kGreedyThreads) void k_greedy_e0(int n, int S, cons
   node_errors(n, S, phase, sup, V, absV, e0, blockIdx.x * blockDim.x + threadIdx.x, gridDim.x * blockDim.x);
 }
 
-
-
 struct PathRec {
   int node, lo, hi;  // an ancestor and the DFS position range of its subtree
 };
 
-// Depth of lca(y, t) where path[d] is t's ancestor at depth d (d <= dmax) and
-// q is y's DFS position: the deepest d whose subtree range holds q.
 // Depth of lca(y, t) where path[d] is t's ancestor at depth d (d <= dmax) and
 // q is y's DFS position: the deepest d whose subtree range holds q.
 __device__ __forceinline__ int lca_depth(const PathRec* path, int dmax, int q) {
@@ -621,8 +617,6 @@ __device__ __forceinline__ int lca_depth(const PathRec* path, int dmax, int q) {
   return lo;
 }
 
-// Root paths of r and s in LDS: pr[d] / ps[d] = the ancestor at depth d and
-// its DFS position range (every depth up to the node's own has one).
 // Root paths of r and s in LDS: pr[d] / ps[d] = the ancestor at depth d and
 // its DFS position range (every depth up to the node's own has one).
 __device__ __forceinline__ void load_paths(int n, const int* pos, const int* size, const int* depth, int r, int s,
