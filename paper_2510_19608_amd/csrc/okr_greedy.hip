@@ -103,7 +103,10 @@ struct MoveDelta {
   double2 dZ[9];
   bool moved;
   __device__ __forceinline__ void at(const LcaTab& T, const double2* Zr, int y, int r, int s) {
-    const int a = T.lca(y, r), b = T.lca(y, s);
+    between(Zr, T.lca(y, r), T.lca(y, s));
+  }
+  // a = lca(y, r), b = lca(y, s), when already known
+  __device__ __forceinline__ void between(const double2* Zr, int a, int b) {
     moved = a != b;
     if (moved) {
       const double2* Za = Zr + (size_t)a * 9;
@@ -363,7 +366,7 @@ __global__ __launch_bounds__(kGreedyThreads) void k_greedy_score(
   }
   const int qw = pos[w];
   MoveDelta msd;
-  msd.at(T, Zr, s, r, s);
+  msd.between(Zr, w, s);  // lca(s, r) = w, lca(s, s) = s
   for (int q = tid; q < S * 3; q += kGreedyThreads) {
     J[q] = Iagg[((size_t)(q / 3) * n + r) * 3 + q % 3];
   }
@@ -399,9 +402,12 @@ __global__ __launch_bounds__(kGreedyThreads) void k_greedy_score(
         }
       }
       const bool big = is && m1 - m0 > kSmallCluster;
+      // in I_r, lca(u, s) = w; in I_s, lca(u, r) = w: one lca to look up
+      const bool inR = qi < L1;
       if (is && !big) {
         MoveDelta md;
-        md.at(T, Zr, u, r, s);
+        const int a = T.lca(u, inR ? r : s);
+        md.between(Zr, inR ? a : w, inR ? w : a);
         for (int l = 0; l < S; ++l) {
           double mag[3];
 #pragma unroll
@@ -425,8 +431,10 @@ __global__ __launch_bounds__(kGreedyThreads) void k_greedy_score(
         const int bit = __ffsll((long long)mask) - 1;
         mask &= mask - 1;
         const int uu = __shfl(u, bit, 64), k0 = __shfl(m0, bit, 64), k1 = __shfl(m1, bit, 64);
+        const bool uinR = __shfl(qi, bit, 64) < L1;
         MoveDelta md;
-        md.at(T, Zr, uu, r, s);
+        const int a = T.lca(uu, uinR ? r : s);
+        md.between(Zr, uinR ? a : w, uinR ? w : a);
         for (int l = 0; l < S; ++l) {
           double mag[3];
 #pragma unroll
@@ -468,12 +476,20 @@ __global__ __launch_bounds__(kGreedyThreads) void k_greedy_score(
   for (int k = tid; k < nb; k += kGreedyThreads) {
     const int lo = k * 64, hi = min(n, lo + 64);
     const bool touch = (lo <= qw && qw < hi) || (lo < b1 && a1 < hi) || (lo < b2 && a2 < hi);
-    if (!touch) {
-      umax = fmax(umax, C.bmax[k]);
-      continue;
-    }
-    for (int q = lo; q < hi; ++q)
-      if (q != qw && !(a1 <= q && q < b1) && !(a2 <= q && q < b2)) umax = fmax(umax, C.arr[q]);
+    if (!touch) umax = fmax(umax, C.bmax[k]);
+  }
+  // a touched block holds an end of I_r or I_s or w's position, or lies
+  // wholly inside I_r or I_s (nothing to add): the five blocks that hold
+  // those positions are read by one wave each, a position per lane (a block
+  // named twice gives the same maximum)
+  for (int j = tid >> 6; j < 5; j += kGreedyThreads / 64) {
+    const int k = j == 0   ? qw >> 6
+                  : j == 1 ? (a1 < b1 ? a1 >> 6 : -1)
+                  : j == 2 ? (a1 < b1 ? (b1 - 1) >> 6 : -1)
+                  : j == 3 ? (a2 < b2 ? a2 >> 6 : -1)
+                           : (a2 < b2 ? (b2 - 1) >> 6 : -1);
+    const int q = k * 64 + (tid & 63);
+    if (k >= 0 && q < n && q != qw && !(a1 <= q && q < b1) && !(a2 <= q && q < b2)) umax = fmax(umax, C.arr[q]);
   }
   __syncthreads();
   olds = block_reduce(olds, [](double a, double b) { return a + b; }, red);
