@@ -59,7 +59,7 @@ constexpr int kGreedyThreads = 256;
 constexpr int kGreedyPickThreads = 1024;
 constexpr int kGreedyMaxS = 64;      // scenarios of a search (moved currents staged in LDS)
 constexpr int kGreedyMaxN = 12288;   // nodes of a search (member counts in LDS)
-constexpr int kSmallCluster = 32;   // clusters up to this size are scored by one lane
+constexpr int kSmallCluster = 8;    // clusters up to this size are scored by one lane
 constexpr int kGreedyFullSN = 6144;  // S x n up to which every candidate scores every node
 
 // O(1) lowest common ancestors: the Euler tour of the DFS (E = 2n - 1
@@ -225,10 +225,12 @@ __device__ void cluster_prep(int n, int S, const uint8_t* phase, const int* pre,
   for (int q = threadIdx.x; q < S * n; q += blockDim.x) t += C.mice[q];
   t = block_reduce(t, [](double a, double b) { return a + b; }, shd);
   __syncthreads();
-  for (int k = threadIdx.x; k < (n + 63) / 64; k += blockDim.x) {
-    double m = 0.0;
-    for (int q = k * 64; q < min(n, k * 64 + 64); ++q) m = fmax(m, C.arr[q]);
-    C.bmax[k] = m;
+  // block maxima: a wave per block of 64 positions, a position per lane
+  for (int k = wv; k < (n + 63) / 64; k += nw) {
+    const int q = k * 64 + lane;
+    double m = q < n ? C.arr[q] : 0.0;
+    for (int o = 32; o > 0; o >>= 1) m = fmax(m, __shfl_xor(m, o, 64));
+    if (lane == 0) C.bmax[k] = m;
   }
   if (threadIdx.x == 0) *C.tot = t;
   __syncthreads();
