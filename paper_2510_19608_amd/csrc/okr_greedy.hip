@@ -410,22 +410,34 @@ __global__ __launch_bounds__(kGreedyThreads) void k_greedy_score(
         MoveDelta md;
         const int a = T.lca(u, inR ? r : s);
         md.between(Zr, inR ? a : w, inR ? w : a);
-        for (int l = 0; l < S; ++l) {
-          double mag[3];
+        for (int l = 0; l < S; l += 2) {  // two scenarios per pass over the members
+          const int l1 = l + 1 < S ? l + 1 : l;
+          double mag0[3], mag1[3];
 #pragma unroll
           for (int p = 0; p < 3; ++p) {
-            double2 v = Vcur[((size_t)l * n + u) * 3 + p];
-            if (md.moved) v = cadd(v, md.dv(p, J + l * 3));
-            mag[p] = sqrt(cabs2(v));
+            double2 v0 = Vcur[((size_t)l * n + u) * 3 + p], v1 = Vcur[((size_t)l1 * n + u) * 3 + p];
+            if (md.moved) {
+              v0 = cadd(v0, md.dv(p, J + l * 3));
+              v1 = cadd(v1, md.dv(p, J + l1 * 3));
+            }
+            mag0[p] = sqrt(cabs2(v0));
+            mag1[p] = sqrt(cabs2(v1));
           }
-          double mx = 0.0;
+          double mx0 = 0.0, mx1 = 0.0;
           for (int k = m0; k < m1; ++k) {
             const int m = C.mem[k];
-            mx = fmax(mx, member_err(absV, n, m, l, phase[m], mag));
+            const unsigned ph = phase[m];
+            mx0 = fmax(mx0, member_err(absV, n, m, l, ph, mag0));
+            mx1 = fmax(mx1, member_err(absV, n, m, l1, ph, mag1));
           }
           olds += C.mice[(size_t)l * n + u];
-          news += mx;
-          emx = fmax(emx, mx);
+          news += mx0;
+          emx = fmax(emx, mx0);
+          if (l1 != l) {
+            olds += C.mice[(size_t)l1 * n + u];
+            news += mx1;
+            emx = fmax(emx, mx1);
+          }
         }
       }
       unsigned long long mask = __ballot(big);
@@ -437,24 +449,39 @@ __global__ __launch_bounds__(kGreedyThreads) void k_greedy_score(
         MoveDelta md;
         const int a = T.lca(uu, uinR ? r : s);
         md.between(Zr, uinR ? a : w, uinR ? w : a);
-        for (int l = 0; l < S; ++l) {
-          double mag[3];
+        for (int l = 0; l < S; l += 2) {  // two scenarios per pass over the members
+          const int l1 = l + 1 < S ? l + 1 : l;
+          double mag0[3], mag1[3];
 #pragma unroll
           for (int p = 0; p < 3; ++p) {
-            double2 v = Vcur[((size_t)l * n + uu) * 3 + p];
-            if (md.moved) v = cadd(v, md.dv(p, J + l * 3));
-            mag[p] = sqrt(cabs2(v));
+            double2 v0 = Vcur[((size_t)l * n + uu) * 3 + p], v1 = Vcur[((size_t)l1 * n + uu) * 3 + p];
+            if (md.moved) {
+              v0 = cadd(v0, md.dv(p, J + l * 3));
+              v1 = cadd(v1, md.dv(p, J + l1 * 3));
+            }
+            mag0[p] = sqrt(cabs2(v0));
+            mag1[p] = sqrt(cabs2(v1));
           }
-          double mx = 0.0;
+          double mx0 = 0.0, mx1 = 0.0;
           for (int k = k0 + lane; k < k1; k += 64) {
             const int m = C.mem[k];
-            mx = fmax(mx, member_err(absV, n, m, l, phase[m], mag));
+            const unsigned ph = phase[m];
+            mx0 = fmax(mx0, member_err(absV, n, m, l, ph, mag0));
+            mx1 = fmax(mx1, member_err(absV, n, m, l1, ph, mag1));
           }
-          for (int o = 32; o > 0; o >>= 1) mx = fmax(mx, __shfl_xor(mx, o, 64));
+          for (int o = 32; o > 0; o >>= 1) {
+            mx0 = fmax(mx0, __shfl_xor(mx0, o, 64));
+            mx1 = fmax(mx1, __shfl_xor(mx1, o, 64));
+          }
           if (lane == 0) {
             olds += C.mice[(size_t)l * n + uu];
-            news += mx;
-            emx = fmax(emx, mx);
+            news += mx0;
+            emx = fmax(emx, mx0);
+            if (l1 != l) {
+              olds += C.mice[(size_t)l1 * n + uu];
+              news += mx1;
+              emx = fmax(emx, mx1);
+            }
           }
         }
       }
