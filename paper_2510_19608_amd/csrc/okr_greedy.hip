@@ -183,35 +183,54 @@ __device__ void cluster_prep(int n, int S, const uint8_t* phase, const int* pre,
     const int m0 = is ? C.moff[y] : 0, m1 = is ? C.moff[y + 1] : 0;
     const bool big = is && m1 - m0 > kSmallCluster;
     if (y < n && !big)
-      for (int l = 0; l < S; ++l) {
-        double mx = 0.0;
+      for (int l = 0; l < S; l += 2) {  // two scenarios per pass over the members
+        const int l1 = l + 1 < S ? l + 1 : l;
+        double mx0 = 0.0, mx1 = 0.0;
         if (is) {
-          double mag[3];
+          double mag0[3], mag1[3];
 #pragma unroll
-          for (int p = 0; p < 3; ++p) mag[p] = sqrt(cabs2(V[((size_t)l * n + y) * 3 + p]));
+          for (int p = 0; p < 3; ++p) {
+            mag0[p] = sqrt(cabs2(V[((size_t)l * n + y) * 3 + p]));
+            mag1[p] = sqrt(cabs2(V[((size_t)l1 * n + y) * 3 + p]));
+          }
           for (int k = m0; k < m1; ++k) {
             const int m = C.mem[k];
-            mx = fmax(mx, member_err(absV, n, m, l, phase[m], mag));
+            const unsigned ph = phase[m];
+            mx0 = fmax(mx0, member_err(absV, n, m, l, ph, mag0));
+            mx1 = fmax(mx1, member_err(absV, n, m, l1, ph, mag1));
           }
         }
-        C.mice[(size_t)l * n + y] = mx;
+        C.mice[(size_t)l * n + y] = mx0;
+        if (l1 != l) C.mice[(size_t)l1 * n + y] = mx1;
       }
     unsigned long long mask = __ballot(big);
     while (mask) {
       const int bit = __ffsll((long long)mask) - 1;
       mask &= mask - 1;
       const int u = y0 + bit, k0 = __shfl(m0, bit, 64), k1 = __shfl(m1, bit, 64);
-      for (int l = 0; l < S; ++l) {
-        double mag[3];
+      for (int l = 0; l < S; l += 2) {  // two scenarios per pass over the members
+        const int l1 = l + 1 < S ? l + 1 : l;
+        double mag0[3], mag1[3];
 #pragma unroll
-        for (int p = 0; p < 3; ++p) mag[p] = sqrt(cabs2(V[((size_t)l * n + u) * 3 + p]));
-        double mx = 0.0;
+        for (int p = 0; p < 3; ++p) {
+          mag0[p] = sqrt(cabs2(V[((size_t)l * n + u) * 3 + p]));
+          mag1[p] = sqrt(cabs2(V[((size_t)l1 * n + u) * 3 + p]));
+        }
+        double mx0 = 0.0, mx1 = 0.0;
         for (int k = k0 + lane; k < k1; k += 64) {
           const int m = C.mem[k];
-          mx = fmax(mx, member_err(absV, n, m, l, phase[m], mag));
+          const unsigned ph = phase[m];
+          mx0 = fmax(mx0, member_err(absV, n, m, l, ph, mag0));
+          mx1 = fmax(mx1, member_err(absV, n, m, l1, ph, mag1));
         }
-        for (int o = 32; o > 0; o >>= 1) mx = fmax(mx, __shfl_xor(mx, o, 64));
-        if (lane == 0) C.mice[(size_t)l * n + u] = mx;
+        for (int o = 32; o > 0; o >>= 1) {
+          mx0 = fmax(mx0, __shfl_xor(mx0, o, 64));
+          mx1 = fmax(mx1, __shfl_xor(mx1, o, 64));
+        }
+        if (lane == 0) {
+          C.mice[(size_t)l * n + u] = mx0;
+          if (l1 != l) C.mice[(size_t)l1 * n + u] = mx1;
+        }
       }
     }
   }
