@@ -564,7 +564,8 @@ __global__ __launch_bounds__(kGreedyThreads) void k_greedy_score(
 // is marked done.
 __global__ __launch_bounds__(kGreedyPickThreads) void k_greedy_pick_apply(
     int n, int S, const int* __restrict__ parent, const uint8_t* __restrict__ phase, const int* __restrict__ pre,
-    LcaTab T, const double2* __restrict__ Zr, const double* __restrict__ absV, const double* __restrict__ sm,
+    const int* __restrict__ pos, const int* __restrict__ size, const int* __restrict__ ch_off,
+    const int* __restrict__ ch, LcaTab T, const double2* __restrict__ Zr, const double* __restrict__ absV, const double* __restrict__ sm,
     const double* __restrict__ em, double e_bar, double tie, double amb, GState* __restrict__ gs,
     GStep* __restrict__ steps, int* __restrict__ sup, double2* __restrict__ Iagg, double2* __restrict__ V,
     Clusters C) {
@@ -624,10 +625,27 @@ __global__ __launch_bounds__(kGreedyPickThreads) void k_greedy_pick_apply(
   }
   for (int u = tid; u < n; u += kGreedyPickThreads)
     if (sup[u] == r) sup[u] = s;
+  // only the subtrees of w = lca(r, s)'s children towards r and s (DFS
+  // intervals I_r, I_s) change; in I_r, lca(x, s) = w, in I_s lca(x, r) = w
+  const int w = T.lca(r, s);
+  int a1 = 0, b1 = 0, a2 = 0, b2 = 0;
+  if (r != w) {
+    const int c = child_toward(ch_off, ch, pos, w, r);
+    a1 = pos[c];
+    b1 = a1 + size[c];
+  }
+  if (s != w) {
+    const int c = child_toward(ch_off, ch, pos, w, s);
+    a2 = pos[c];
+    b2 = a2 + size[c];
+  }
   for (int xn = tid; xn < n; xn += kGreedyPickThreads) {
+    const int q = pos[xn];
+    const bool inR = a1 <= q && q < b1;
+    if (!inR && !(a2 <= q && q < b2)) continue;
     MoveDelta md;
-    md.at(T, Zr, xn, r, s);
-    if (!md.moved) continue;
+    const int a = T.lca(xn, inR ? r : s);
+    md.between(Zr, inR ? a : w, inR ? w : a);
     for (int l = 0; l < S; ++l) {
       const size_t vb = ((size_t)l * n + xn) * 3;
 #pragma unroll
@@ -1472,7 +1490,8 @@ extern "C" int okr_greedy_run(okr_greedy* g, const okr_yblocks* Y, const okr_loa
         if (e != hipSuccess) return e;
       }
       hipLaunchKernelGGL(k_greedy_pick_apply, dim3(1), dim3(kGreedyPickThreads), lds_cnt, st, n, S,
-                         (const int*)p.parent, (const uint8_t*)p.phase, (const int*)p.pre, T, (const double2*)p.Zr,
+                         (const int*)p.parent, (const uint8_t*)p.phase, (const int*)p.pre, (const int*)p.pos,
+                         (const int*)p.size, (const int*)p.ch_off, (const int*)p.ch, T, (const double2*)p.Zr,
                          (const double*)p.absV, (const double*)p.sm, (const double*)p.em, e_bar, tie, amb, p.gs,
                          p.steps, p.sup, p.I, p.V, p.C);
     } else {
