@@ -134,6 +134,19 @@ def score_masks(f, Vhat, Ihat, keep_before, g, masks):
     return out
 
 
+def omega(f, keep, g):
+    """Omega_g of segment g against the kept flags `keep` (bool [n])."""
+    parent, phase, segment, Yd, Yo = _net(f)
+    keep = np.ascontiguousarray(keep, dtype=np.uint8)
+    n = len(parent)
+    om = np.zeros(n, dtype=np.uint8)
+    st = lib().okro_omega(ctypes.c_int(n), _p(parent), _p(phase), _p(segment), _p(Yd), _p(Yo),
+                          _p(keep), ctypes.c_int(g), _p(om))
+    if st != OK:
+        raise RuntimeError(f"okro_omega failed: {st}")
+    return om.astype(bool)
+
+
 def search(f, Vhat, Ihat, tie_tol=1e-11, amb_tol=1e-13, mode=1):
     """Full segment-exhaustive search.  Returns (keep, decisions, status)."""
     parent, phase, segment, Yd, Yo = _net(f)

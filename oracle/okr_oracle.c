@@ -586,6 +586,24 @@ static void omega_of_segment(const okro_net *N, const uint8_t *keep, int g,
     free(stack);
 }
 
+/* Exported for the pin tests of Omega_g: omega_out[i] = 1 for the nodes of
+ * segment g's affected region against the kept flags `keep`. */
+int okro_omega(int n, const int32_t *parent, const uint8_t *phase,
+               const int32_t *segment, const double *Ydiag, const double *Yoff,
+               const uint8_t *keep, int g, uint8_t *omega_out)
+{
+    int st;
+    okro_net *N = net_new(n, parent, phase, segment, Ydiag, Yoff, &st);
+    if (st != OKRO_OK) { net_free(N); return st; }
+    int *nodes = (int *)malloc(sizeof(int) * (size_t)n);
+    int k = 0;
+    for (int q = 0; q < n; ++q)
+        if (segment[N->pre[q]] == g) nodes[k++] = N->pre[q];
+    omega_of_segment(N, keep, g, nodes, k, omega_out);
+    free(nodes); net_free(N);
+    return OKRO_OK;
+}
+
 /* Score one kept set: errors per eq. (iter_obj) / Algorithm 1
  * (e = ||V^|-|V^c|| per node-phase-snapshot), the E_bar bound (eq. v_abs,
  * inclusive) and the voltage band on every node-phase.  Globals run over all

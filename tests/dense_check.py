@@ -106,6 +106,45 @@ def vc_full_route(f, Ihat, keep):
     return Vc
 
 
+def v_full_raw(f, Ihat, keep):
+    """Physical voltages of every node of the full network carrying the
+    aggregated currents (Y V = I^c, Algorithm 1's solve), before any copy from
+    super-nodes, and the super-node map."""
+    n = f["n"]
+    pres = present(f)
+    Y = dense_Y(f)
+    Iagg, sup = aggregate(f, Ihat, keep)
+    unk = [q for q in range(3, 3 * n) if pres[q]]
+    S = Ihat.shape[0]
+    V = np.zeros((S, 3 * n), dtype=np.complex128)
+    for l in range(S):
+        rhs = Iagg[l].reshape(-1)[unk] - Y[np.ix_(unk, [0, 1, 2])] @ f["V0"]
+        V[l, :3] = f["V0"]
+        V[l, unk] = np.linalg.solve(Y[np.ix_(unk, unk)], rhs)
+    return V.reshape(S, n, 3), sup
+
+
+def omega_behavioural(f, Ihat, keep, nodes, tol=1e-12):
+    """The nodes a segment's masks can touch, found by experiment rather than
+    by a formula: every node whose physical voltage or super-node differs
+    from the empty mask's under some single-node mask.  Returns (omega,
+    smallest voltage change among the nodes taken in, largest among the nodes
+    left out) so callers can check the threshold separates them."""
+    base, sup0 = v_full_raw(f, Ihat, keep)
+    n = f["n"]
+    om = np.zeros(n, dtype=bool)
+    dmax = np.zeros(n)
+    for v in nodes:
+        keep2 = keep.copy()
+        keep2[v] = 0
+        V, sup = v_full_raw(f, Ihat, keep2)
+        d = np.abs(V - base).max(axis=(0, 2))
+        om |= (d > tol) | (sup != sup0)
+        dmax = np.maximum(dmax, np.where(sup != sup0, np.inf, d))
+    inside = dmax[om & np.isfinite(dmax)]
+    return om, (inside.min() if inside.size else np.inf), dmax[~om].max(initial=0.0)
+
+
 def omega(f, keep, g):
     parent = f["parent"]
     seg = f["segment"]

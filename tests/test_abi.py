@@ -15,7 +15,11 @@ ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 
 def declared_functions():
     inc = os.path.join(ROOT, "include")
-    src = "".join(open(os.path.join(inc, h)).read() for h in sorted(os.listdir(inc)) if h.endswith(".h"))
+    src = ""
+    for h in sorted(os.listdir(inc)):
+        if h.endswith(".h"):
+            with open(os.path.join(inc, h)) as fh:
+                src += fh.read()
     return sorted(set(re.findall(r"^\s*(?:int|const char\s*\*)\s*(okr_\w+)\s*\(", src, re.M)))
 
 
@@ -122,7 +126,8 @@ def test_product_sources_do_not_reference_the_oracle():
         for root, _, files in os.walk(os.path.join(ROOT, d)):
             for fn in files:
                 if fn.endswith((".py", ".hip", ".cpp", ".h")):
-                    src = open(os.path.join(root, fn)).read()
+                    with open(os.path.join(root, fn)) as fh:
+                        src = fh.read()
                     assert "import oracle" not in src and "okr_oracle" not in src and "okro_" not in src, fn
 
 

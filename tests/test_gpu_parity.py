@@ -44,6 +44,7 @@ def check_outputs(f, out, V, I, keep, dec):
     amb = [d["ambiguous"] for d in dec]
     assert not any(amb), "oracle flags a near-tie; pick another seed"
     assert got == want
+    assert [bool(s["ambiguous"]) for s in out["segments"]] == amb
     np.testing.assert_array_equal(out["kept"], keep)
     # scenario voltages
     np.testing.assert_allclose(out["Vhat"], V, rtol=0, atol=1e-12)
@@ -69,6 +70,46 @@ def test_c1_decisions_and_outputs(okr, seed, e_bar):
     V, I, keep, dec, st = oracle_run(f)
     out = okr.reduce_feeder(f)
     check_outputs(f, out, V, I, keep, dec)
+
+
+def _level_errors(f, V, I, level):
+    nodes = [int(v) for v in dfs_preorder(f["parent"]) if f["segment"][v] == 0]
+    masks = np.array([m for m in range(1 << len(nodes)) if bin(m).count("1") == level], np.uint32)
+    sc = oracle.score_masks(f, V, I, np.ones(f["n"], np.uint8), 0, masks)
+    return masks, sc
+
+
+@pytest.mark.parametrize("precision", ["fp64", "factored", "mixed"])
+def test_ambiguity_flags_match_the_oracle(okr, precision):
+    """Decisions placed on a boundary on purpose: e_bar on the all-nodes
+    mask's error, and tie_tol on the gap between the two best masks of the
+    chosen level.  Both sides flag the segment (and agree 1e-12 away from
+    the boundary, where neither flags and the decisions are equal)."""
+    cases = []
+    f = make_feeder("c1", 0, n=20, n_eligible=8, seg_size=(8, 8))
+    V, I, _, _ = oracle.powerflow(f)
+    masks, sc = _level_errors(f, V, I, 8)
+    e_all = float(sc["e_loc"][0])
+    for shift in (0.0, 1e-12):
+        cases.append((dict(f, e_bar=e_all + shift), {}))
+    f = make_feeder("c1", 1, n=20, n_eligible=8, seg_size=(8, 8), e_bar=1e-4)
+    V, I, _, _ = oracle.powerflow(f)
+    _, dec, _ = oracle.search(f, V, I)
+    masks, sc = _level_errors(f, V, I, dec[0]["popcount"])
+    e = np.sort(sc["e_loc"][sc["feasible"]])
+    for shift in (0.0, 1e-12, -1e-12):
+        cases.append((f, dict(tie_tol=float(e[1] - e[0]) + shift)))
+    flags = []
+    for fc, kw in cases:
+        _say(f"ambiguity case {kw} e_bar={fc['e_bar']} {precision}")
+        V, I, _, _ = oracle.powerflow(fc)
+        keep, dec, st = oracle.search(fc, V, I, **kw)
+        out = okr.reduce_feeder(fc, precision=precision, **kw)
+        assert bool(out["segments"][0]["ambiguous"]) == dec[0]["ambiguous"]
+        if not dec[0]["ambiguous"]:
+            assert out["segments"][0]["mask"] == dec[0]["mask"]
+        flags.append(dec[0]["ambiguous"])
+    assert flags == [True, False, True, False, False]
 
 
 @pytest.mark.parametrize("seed", [0, 3])

@@ -283,6 +283,185 @@ def test_masks_leave_errors_outside_omega_unchanged(oracle_lib):
                 keep[v] = 0
 
 
+def test_omega_under_cumulative_state_is_what_masks_touch(oracle_lib):
+    """Omega_g against a cumulative state (Algorithm 1's "assign previously
+    reduced"): the oracle's region equals, node for node, the set found by
+    experiment -- every node whose physical voltage (full-network solve with
+    aggregated currents) or super-node changes under some single-node mask of
+    the segment.  Earlier segments' reductions sit above later segments'
+    chains on these deep-lateral feeders, so the region must climb through
+    already-reduced nodes.  The oracle's e_loc is then the error maximum over
+    exactly that set (dense route)."""
+    climbs = 0
+    rng = np.random.default_rng(11)
+    for seed in range(8):
+        f = make_feeder("c1", seed, n=24, n_eligible=None, seg_size=(2, 3), snapshots=2,
+                        scale=(0.3, 1.0), p_deep=0.6)
+        V, I, st, _ = oracle_lib.powerflow(f)
+        assert st == 0
+        keep = np.ones(f["n"], np.uint8)
+        for g in range(int(f["segment"].max()) + 1):
+            nodes = dc.seg_nodes(f, g)
+            om = oracle_lib.omega(f, keep, g)
+            ob, dmin_in, dmax_out = dc.omega_behavioural(f, I, keep, nodes)
+            assert dmin_in > 1e-9 and dmax_out < 1e-13  # the experiment separates cleanly
+            np.testing.assert_array_equal(om, ob)
+            # a reduced node sits above a chain of this segment: the region
+            # reaches above the segment's own topmost nodes
+            tops = {v for v in nodes if f["segment"][f["parent"][v]] != g}
+            if any(not keep[f["parent"][v]] for v in tops):
+                climbs += 1
+            masks = np.unique(np.concatenate([[0, (1 << len(nodes)) - 1],
+                                              rng.integers(0, 1 << len(nodes), 3)])).astype(np.uint32)
+            got = oracle_lib.score_masks(f, V, I, keep, g, masks)
+            for q, m in enumerate(masks):
+                keep2 = keep.copy()
+                for j, v in enumerate(nodes):
+                    if m >> j & 1:
+                        keep2[v] = 0
+                ref = dc.score(f, V, I, keep2, ob)
+                assert abs(got["e_loc"][q] - ref["e_loc"]) < 1e-12
+                assert abs(got["slack_loc"][q] - ref["slack_loc"]) < 1e-12 or \
+                    (np.isinf(got["slack_loc"][q]) and np.isinf(ref["slack_loc"]))
+            if (seed + g) % 3:  # cumulative state: reduce the whole segment
+                for v in nodes:
+                    keep[v] = 0
+    assert climbs >= 10
+
+
+def _dense_level_scores(f, V, I, level):
+    """Dense-route (e_loc, feasible) of every mask of segment 0 at `level`,
+    from the full state."""
+    nodes = dc.seg_nodes(f, 0)
+    keep = np.ones(f["n"], np.uint8)
+    om = dc.omega(f, keep, 0)
+    rows = []
+    for m in range(1 << len(nodes)):
+        if bin(m).count("1") != level:
+            continue
+        keep2 = keep.copy()
+        for j, v in enumerate(nodes):
+            if m >> j & 1:
+                keep2[v] = 0
+        sc = dc.score(f, V, I, keep2, om)
+        rows.append((m, sc["e_loc"], sc["feasible"]))
+    return rows
+
+
+@pytest.mark.parametrize("seed", [0, 3])
+def test_ambiguity_flag_at_the_e_bar_boundary(oracle_lib, seed):
+    """A segment is flagged when a mask at the chosen level or above lies
+    within amb_tol of the e_bar boundary: with e_bar set to the all-nodes
+    mask's error (dense route) the flag is raised; 1e-12 away it is not."""
+    f = make_feeder("c1", seed, n=20, n_eligible=8, seg_size=(8, 8))
+    V, I, st, _ = oracle_lib.powerflow(f)
+    assert st == 0
+    k = len(dc.seg_nodes(f, 0))
+    (m_all, e_all, _), = _dense_level_scores(f, V, I, k)
+    for shift, want in ((0.0, True), (1e-12, False), (-1e-12, False)):
+        keep, dec, st = oracle_lib.search(dict(f, e_bar=e_all + shift), V, I)
+        assert st == 0
+        assert dec[0]["ambiguous"] == want, (shift, dec[0])
+    # just above the bound the all-nodes mask is feasible and wins outright
+    _, dec, _ = oracle_lib.search(dict(f, e_bar=e_all + 1e-12), V, I)
+    assert dec[0]["mask"] == m_all
+
+
+def test_ambiguity_flag_at_the_tie_boundary(oracle_lib):
+    """A segment is flagged when a feasible mask at the chosen level lies
+    within amb_tol of e_min + tie_tol.  Place tie_tol on the gap between the
+    two best masks of the level (dense route): flagged; 1e-12 wider: the two
+    tie, the lower mask wins, no flag; 1e-12 narrower: the best one wins."""
+    f = make_feeder("c1", 1, n=20, n_eligible=8, seg_size=(8, 8), e_bar=1e-4)
+    V, I, st, _ = oracle_lib.powerflow(f)
+    keep, dec, st = oracle_lib.search(f, V, I)
+    assert st == 0 and not dec[0]["ambiguous"]
+    level = dec[0]["popcount"]
+    rows = sorted((e, m) for m, e, feas in _dense_level_scores(f, V, I, level) if feas)
+    assert len(rows) >= 2
+    (e1, m1), (e2, m2) = rows[0], rows[1]
+    assert dec[0]["mask"] == m1
+    gap = e2 - e1
+    assert gap > 1e-11  # room for the three placements below
+    _, dec, _ = oracle_lib.search(f, V, I, tie_tol=gap)
+    assert dec[0]["ambiguous"]
+    _, dec, _ = oracle_lib.search(f, V, I, tie_tol=gap + 1e-12)
+    assert not dec[0]["ambiguous"] and dec[0]["mask"] == min(m1, m2)
+    _, dec, _ = oracle_lib.search(f, V, I, tie_tol=gap - 1e-12)
+    assert not dec[0]["ambiguous"] and dec[0]["mask"] == m1
+
+
+def test_exact_tie_lower_mask_wins(oracle_lib):
+    """Two feasible masks at the chosen level share their error (the dense
+    route agrees to rounding): they tie, the lower mask is chosen, and the
+    segment is not flagged (the tie is exact, far from the tie boundary)."""
+    f = make_feeder("c1", 1, n=20, n_eligible=8, seg_size=(8, 8), e_bar=5e-5)
+    V, I, st, _ = oracle_lib.powerflow(f)
+    keep, dec, st = oracle_lib.search(f, V, I)
+    assert st == 0
+    level = dec[0]["popcount"]
+    rows = sorted((e, m) for m, e, feas in _dense_level_scores(f, V, I, level) if feas)
+    (e1, m1), (e2, m2) = rows[0], rows[1]
+    assert e2 - e1 < 1e-15 and (len(rows) == 2 or rows[2][0] - e1 > 1e-9)
+    assert dec[0]["mask"] == min(m1, m2) and max(m1, m2) != min(m1, m2)
+    assert not dec[0]["ambiguous"]
+
+
+def test_superposition_over_non_interacting_chains(oracle_lib):
+    """Fixed currents make candidate voltages linear in the moved currents:
+    for two segment nodes whose affected regions are disjoint, reducing both
+    changes every voltage by the sum of the two single changes, and the error
+    over the segment's region is the larger of the two single errors."""
+    pairs = 0
+    for seed in range(4):
+        f = make_feeder("c1", seed, n=24, n_eligible=None, seg_size=(6, 6), snapshots=2,
+                        scale=(0.3, 1.0))
+        V, I, st, _ = oracle_lib.powerflow(f)
+        assert st == 0
+        keep = np.ones(f["n"], np.uint8)
+        nodes = dc.seg_nodes(f, 0)
+        regions = [dc.omega_behavioural(f, I, keep, [v])[0] for v in nodes]
+        base = oracle_lib.candidate_voltages(f, I, keep)
+        for a in range(len(nodes)):
+            for b in range(a + 1, len(nodes)):
+                if (regions[a] & regions[b]).any():
+                    continue
+                pairs += 1
+                single = []
+                for v in (nodes[a], nodes[b]):
+                    k2 = keep.copy()
+                    k2[v] = 0
+                    single.append(oracle_lib.candidate_voltages(f, I, k2) - base)
+                k2 = keep.copy()
+                k2[nodes[a]] = k2[nodes[b]] = 0
+                both = oracle_lib.candidate_voltages(f, I, k2) - base
+                np.testing.assert_allclose(both, single[0] + single[1], rtol=0, atol=1e-13)
+                sc = oracle_lib.score_masks(f, V, I, keep, 0,
+                                            np.array([1 << a, 1 << b, (1 << a) | (1 << b)], np.uint32))
+                assert abs(sc["e_loc"][2] - max(sc["e_loc"][0], sc["e_loc"][1])) < 1e-14
+    assert pairs >= 20
+
+
+def test_empty_mask_scores_the_cumulative_state(oracle_lib):
+    """The empty mask changes nothing: its error is the error of the state the
+    earlier segments left (dense route), about the load flow's residual for
+    the first segment."""
+    f = make_feeder("c1", 4, n=24, n_eligible=None, seg_size=(3, 3), snapshots=2, scale=(0.3, 1.0),
+                    p_deep=0.6)
+    V, I, st, _ = oracle_lib.powerflow(f)
+    keep = np.ones(f["n"], np.uint8)
+    for g in range(int(f["segment"].max()) + 1):
+        nodes = dc.seg_nodes(f, g)
+        sc = oracle_lib.score_masks(f, V, I, keep, g, np.array([0], np.uint32))
+        ref = dc.score(f, V, I, keep, np.ones(f["n"], bool))
+        assert abs(sc["e_glob"][0] - ref["e_glob"]) < 1e-13
+        if g == 0:
+            assert sc["e_glob"][0] < 1e-12
+        for v in nodes[::2]:
+            keep[v] = 0
+    assert ref["e_glob"] > 1e-6  # the later states carry real errors
+
+
 def test_base_out_of_band_warns_and_reduces_nothing(oracle_lib):
     f = make_feeder("c1", 0, v_min=0.999)
     V, I, st, _ = oracle_lib.powerflow(f)
