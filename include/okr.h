@@ -172,12 +172,13 @@ typedef struct {
                            by the chunk's segments (OKR_FLAG_TIMING) */
     int32_t n_refined;  /* MIXED: masks rescored in FP64 (shortlists A + B) */
     double fp32_dev;    /* MIXED: max |e32 - e64| over rescored masks with e64 <= 2 e_bar */
-    int32_t score_groups;   /* FP64 scoring launch shape: snapshot groups ... */
-    int32_t score_mpl;      /* ... and masks per lane (default rule or autotuned) */
+    int32_t score_groups;   /* FP64 scoring launch shape: snapshot groups, ... */
+    int32_t score_mpl;      /* ... snapshots per pass, ... */
     int32_t chunk;          /* index of the launch chunk the segment ran in */
     double kernel_flops;    /* flops the per-mask scoring kernel itself performs
                                (shared tables replace the per-candidate
                                voltage-change products; 0 with FACTORED) */
+    int32_t score_waves;    /* ... and waves sharing each 64 masks' chains (default rule or autotuned) */
 } okr_segment_result;
 
 /* Outputs (HOST buffers owned by the caller). */

@@ -75,7 +75,7 @@ class SegmentResult(ctypes.Structure):
                 ("ambiguous", ctypes.c_int32), ("n_scored", ctypes.c_int32), ("flops", ctypes.c_double),
                 ("score_ms", ctypes.c_float), ("n_refined", ctypes.c_int32), ("fp32_dev", ctypes.c_double),
                 ("score_groups", ctypes.c_int32), ("score_mpl", ctypes.c_int32), ("chunk", ctypes.c_int32),
-                ("kernel_flops", ctypes.c_double)]
+                ("kernel_flops", ctypes.c_double), ("score_waves", ctypes.c_int32)]
 
 
 class Result(ctypes.Structure):
@@ -374,7 +374,7 @@ class Reducer:
         segs = [dict(segment=s.segment, k=s.k, mask=s.mask, popcount=s.popcount, e_loc=s.e_loc,
                      e_min=s.e_min, ambiguous=bool(s.ambiguous), n_scored=s.n_scored, flops=s.flops,
                      score_ms=s.score_ms, n_refined=s.n_refined, fp32_dev=s.fp32_dev,
-                     score_groups=s.score_groups, score_mpl=s.score_mpl, chunk=s.chunk,
+                     score_groups=s.score_groups, score_mpl=s.score_mpl, score_waves=s.score_waves, chunk=s.chunk,
                      kernel_flops=s.kernel_flops)
                 for s in list(self.out_seg)[:self.sizes.n_segments]]
         return dict(super=self.out_super.copy(), kept_parent=self.out_kp.copy(),

@@ -28,18 +28,18 @@ __device__ __forceinline__ double2 cdiv(double2 a, double2 b) {
 
 // ---------------------------------------------------------------- scoring --
 // sqrt for arguments in the normal range (here |V|^2 of a bus voltage): the
-// hardware reciprocal-square-root estimate refined by Newton-Raphson steps in
-// Goldschmidt form (g -> sqrt(x), h -> 1/(2 sqrt(x))), two residual
-// corrections at the end.  No range scaling: callers pass x in [2^-500, 2^500].
+// hardware reciprocal-square-root estimate (relative error about 2^-24)
+// refined by one Newton-Raphson step in Goldschmidt form (g -> sqrt(x),
+// h -> 1/(2 sqrt(x)); error about 2^-48) and one residual correction
+// g + (x - g^2) h, which leaves it within an ulp (the rounding test checks it
+// against libm).  No range scaling: callers pass x in [2^-500, 2^500].
 __device__ __forceinline__ double sqrt_nr(double x) {
   const double r = __builtin_amdgcn_rsq(x);
   double g = x * r, h = 0.5 * r;
   const double e = fma(-h, g, 0.5);
   g = fma(g, e, g);
   h = fma(h, e, h);
-  double d = fma(-g, g, x);
-  g = fma(d, h, g);
-  d = fma(-g, g, x);
+  const double d = fma(-g, g, x);
   return fma(d, h, g);
 }
 // |a|^2 in one fixed evaluation order (every magnitude of the scoring goes
@@ -165,10 +165,6 @@ __device__ __forceinline__ void sqrt_nr_v(const double (&x)[M], double (&y)[M]) 
     g[j] = fma(g[j], e[j], g[j]);
     h[j] = fma(h[j], e[j], h[j]);
   }
-#pragma unroll
-  for (int j = 0; j < M; ++j) e[j] = fma(-g[j], g[j], x[j]);
-#pragma unroll
-  for (int j = 0; j < M; ++j) g[j] = fma(e[j], h[j], g[j]);
 #pragma unroll
   for (int j = 0; j < M; ++j) e[j] = fma(-g[j], g[j], x[j]);
 #pragma unroll

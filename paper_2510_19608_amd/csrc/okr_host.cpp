@@ -32,7 +32,7 @@ __global__ void k_build_members(const SegHdr*, const int*, size_t, const int*, T
                                 const double*, TargetRec*, TargetRec*, double*);
 template <int M>
 __global__ void k_score_fp64(const SegHdr*, const int*, size_t, const int*, const double2*, const TargetRec*,
-                           const double2*, const TargetRec*, const double*, int, int, int, int, int, SelParams,
+                           const double2*, const TargetRec*, const double*, int, int, int, int, int, int, SelParams,
                            MaskScore*, MaskScore*, TileRec*, int*, const int*);
 __global__ void k_terms_init(const SegHdr*, const int*, size_t, int, const int*, int, const double*,
                              unsigned long long*, unsigned long long*);
@@ -122,6 +122,18 @@ int snap_groups_default(int k, int S, int* spg, int mpl = 1, int target_blocks =
   return (S + *spg - 1) / *spg;
 }
 
+// Snapshot groups of the per-mask FP64 launch (blocks of 64 masks, one per
+// lane, 4 waves sharing the chains): about 1024 blocks per 24 snapshots and at
+// most about 24 snapshots per block.
+int score64_groups_default(int k, int S, int* spg) {
+  const int tiles = (int)((((uint64_t)1 << k) + kScoreBlock - 1) / kScoreBlock);
+  const int target = 1024 * std::max(1, S / 24);
+  int SG = std::min(S, std::max((S + 23) / 24, target / tiles));
+  SG = std::min(SG, kMaxSnapGroups);
+  *spg = (S + SG - 1) / SG;
+  return (S + *spg - 1) / *spg;
+}
+
 // Launch shape of the FP32 screen: masks per lane by segment size and about
 // 512 mask blocks.  The workspace planner sizes the screen's partial scores
 // from this same function.
@@ -175,8 +187,8 @@ struct okr_handle {
   // shape of the FP64 scoring launches, autotuned per segment size (0 = the
   // default rule): snapshot groups and masks per lane; values forced while
   // tuning; the partial-score capacity (masks x groups) of the workspace
-  std::vector<int> sg_tuned, mpl_tuned;
-  int sg_force = 0, mpl_force = 0;
+  std::vector<int> sg_tuned, mpl_tuned, ws_tuned;
+  int sg_force = 0, mpl_force = 0, ws_force = 0;
   size_t part_cap = 0;
   // segment chunks: every search step is one launch over a chunk of
   // mutually independent segments (chunk c = chunk_segs[chunk_off[c] ..
@@ -187,13 +199,28 @@ struct okr_handle {
 };
 
 namespace {
-// Masks per lane of the FP64 scoring launch for a segment of k nodes: forced,
-// tuned, else 4 for large segments, fewer for small ones (each lane must
-// still get masks).
-int score_mpl(const okr_handle* h, int k) {
+// Launch shape of the per-mask FP64 scoring for a chunk of nz segments whose
+// largest has k nodes: snapshots per pass, waves sharing each 64 masks'
+// chains, snapshot groups.  Each is forced (while autotuning), tuned for
+// (k, nz), or the default rule.
+int shape_key(int k, int nz) { return k * (kMaxLanes + 1) + nz; }
+int tuned(const std::vector<int>& t, int k, int nz) {
+  const int i = shape_key(k, nz);
+  return i < (int)t.size() ? t[i] : 0;
+}
+// Snapshots per pass: 2 by default (measured on MI355X).
+int score_mpl(const okr_handle* h, int k, int nz) {
   if (h->mpl_force) return h->mpl_force;
-  if ((int)h->mpl_tuned.size() > k && h->mpl_tuned[k]) return h->mpl_tuned[k];
-  return h->S >= 48 ? 2 : 4;
+  const int t = tuned(h->mpl_tuned, k, nz);
+  return t ? t : 2;
+}
+// Waves sharing the chains of each 64 masks (1, 2 or 4): 2 by default (the
+// autotuner's pick on MI355X for the 1000-node workload's 16-node segments at
+// 2 snapshots per pass).
+int score_ws(const okr_handle* h, int k, int nz) {
+  if (h->ws_force) return h->ws_force;
+  const int t = tuned(h->ws_tuned, k, nz);
+  return t ? t : 2;
 }
 
 // Snapshot groups of the FP64 scoring launch for a segment of k nodes: the
@@ -228,10 +255,17 @@ int sv_spp(int want, int k, int spg) {
   return spp;
 }
 
-int snap_groups(const okr_handle* h, int k, int* spg) {
+// Default groups: at least about 4096 waves per launch (4 per SIMD) while the
+// general rule gives fewer, at most a group per 8 snapshots.
+int snap_groups(const okr_handle* h, int k, int nz, int* spg) {
   const int S = h->S;
-  int SG = h->sg_force ? h->sg_force : ((int)h->sg_tuned.size() > k && h->sg_tuned[k] ? h->sg_tuned[k] : 0);
-  if (SG <= 0) SG = snap_groups_default(k, S, spg);
+  int SG = h->sg_force ? h->sg_force : tuned(h->sg_tuned, k, nz);
+  if (SG <= 0) {
+    SG = score64_groups_default(k, S, spg);
+    const int64_t waves = (int64_t)((((uint64_t)1 << k) + kScoreBlock - 1) / kScoreBlock) * score_ws(h, k, nz) * nz;
+    const int want = (int)std::min<int64_t>(std::max(1, S / 8), (4096 + waves - 1) / waves);
+    SG = std::max(SG, want);
+  }
   SG = std::min(std::min(SG, S), kMaxSnapGroups);
   while (SG > 1 && ((size_t)SG << k) > h->part_cap) --SG;
   *spg = (S + SG - 1) / SG;
@@ -610,16 +644,17 @@ extern "C" int okr_plan(okr_handle* h, const okr_topology* topo, const okr_margi
     // partial scores: every default shape, and room to tune up to 32 groups
     // for segments of up to 16 nodes
     size_t most = (size_t)std::min(S, kMaxSnapGroups) << std::min(h->kmax, 16);
-    for (int k = 1; k <= h->kmax; ++k)
-      for (int mpl = 1; mpl <= 4; mpl *= 2) {
-        int spg;
-        most = std::max(most, (size_t)snap_groups_default(k, S, &spg, mpl) << k);
-      }
+    for (int k = 1; k <= h->kmax; ++k) {
+      int spg;
+      most = std::max(most, (size_t)score64_groups_default(k, S, &spg) << k);
+    }
     L.part = take(sizeof(MaskScore) * most);
     h->part_cap = most;
-    if ((int)h->sg_tuned.size() != h->kmax + 1) {  // tuning survives a re-plan of the same sizes
-      h->sg_tuned.assign(h->kmax + 1, 0);
-      h->mpl_tuned.assign(h->kmax + 1, 0);
+    const size_t nkey = (size_t)shape_key(h->kmax + 1, 0);
+    if (h->sg_tuned.size() != nkey) {  // tuning survives a re-plan of the same sizes
+      h->sg_tuned.assign(nkey, 0);
+      h->mpl_tuned.assign(nkey, 0);
+      h->ws_tuned.assign(nkey, 0);
     }
     const size_t nm = (size_t)1 << h->kmax, nt = (nm + 63) / 64;
     L.fin = take(sizeof(MaskScore) * nm);
@@ -896,11 +931,14 @@ void enqueue_search(okr_handle* h, void* ws, const okr_yblocks* Y, const okr_loa
                        q.zrec, q.econst);
     const uint32_t nmask = 1u << kc;
     int spg;
-    const int SG = snap_groups(h, kc, &spg);
-    // per-mask FP64 launch: one mask per lane, spp snapshots per pass, LDS for spp snapshots
-    const int mblocks = (int)((nmask + kScoreThreads - 1) / kScoreThreads);
+    const int SG = snap_groups(h, kc, nz, &spg);
+    // per-mask FP64 launch: one mask per lane, groups of ws waves sharing the
+    // chains of 64 masks, spp snapshots per pass, LDS for spp snapshots
+    const int sws = score_ws(h, kc, nz);
+    const uint32_t bmask = kScoreBlock * (kScoreThreads / 64 / sws);
+    const int mblocks = (int)((nmask + bmask - 1) / bmask);
     const int pcap = kc * (kc + 1) / 2;
-    const int spp = sv_spp(score_mpl(h, kc), kc, spg);
+    const int spp = sv_spp(score_mpl(h, kc, nz), kc, spg);
     const size_t lds = sv_lds_bytes(spp, kc);
     const int* gates = surr ? q.sgates : nullptr;
     for (int z = 0; z < nz; ++z) {
@@ -981,7 +1019,7 @@ void enqueue_search(okr_handle* h, void* ws, const okr_yblocks* Y, const okr_loa
   hipLaunchKernelGGL(k_score_fp64<M_>, dim3(mblocks, SG, nz), dim3(kScoreThreads), lds, st, (const SegHdr*)q.hdrs, segs, \
                      lstride, (const int*)q.tab, (const double2*)q.P, (const TargetRec*)q.srec,                      \
                      (const double2*)q.headV, (const TargetRec*)q.zrec, (const double*)q.econst, spg, SG, pcap, kc,   \
-                     kSvZone, sp, q.part, q.fin, q.tiles, q.tickets, gates)
+                     kSvZone, sws, sp, q.part, q.fin, q.tiles, q.tickets, gates)
         if (spp == 4) OKR_SCORE64(4);
         else if (spp == 2) OKR_SCORE64(2);
         else OKR_SCORE64(1);
@@ -1138,43 +1176,52 @@ extern "C" int okr_reduce_feeder(okr_handle* h, const okr_yblocks* Y, const okr_
     mt.precision = OKR_PRECISION_FP64;
     mt.top_k = 0;
     mt.surrogate = nullptr;
-    // tsum[k][mpl index][groups]
-    std::vector<double> tsum((size_t)(h->kmax + 1) * 3 * (kMaxSnapGroups + 1), 0.0);
-    auto T_ = [&](int k, int mi, int c) -> double& { return tsum[((size_t)k * 3 + mi) * (kMaxSnapGroups + 1) + c]; };
+    // tsum[k][mpl index][waves index][groups]
+    const int NG = kMaxSnapGroups + 1;
+    const int nkey = shape_key(h->kmax + 1, 0);
+    std::vector<double> tsum((size_t)nkey * 3 * 3 * NG, 0.0);
+    auto T_ = [&](int key, int mi, int wi, int c) -> double& {
+      return tsum[(((size_t)key * 3 + mi) * 3 + wi) * NG + c];
+    };
     for (int mi = 0; mi < 3; ++mi)
-      for (int c = 1; c <= std::min(S, kMaxSnapGroups); c *= 2) {
-        h->sg_force = c;
-        h->mpl_force = 1 << mi;
-        enqueue_search(h, d_workspace, Y, loads, &mt, st, &h->ev, nullptr, nullptr, nullptr, nullptr);
-        const hipError_t e1 = hipGetLastError(), e2 = hipStreamSynchronize(st);
-        if (e1 != hipSuccess || e2 != hipSuccess) {
-          h->sg_force = h->mpl_force = 0;
-          OKR_FAIL(h, OKR_E_HIP, "autotune run failed: %s", hipGetErrorString(e1 != hipSuccess ? e1 : e2));
-        }
-        for (int cc = 0; cc < (int)h->chunk_k.size(); ++cc) {
-          const int k = h->chunk_k[cc];
-          int spg;
-          const int used = snap_groups(h, k, &spg);
-          float ms = 0.f;
-          const hipError_t ee = hipEventElapsedTime(&ms, h->ev[2 * cc], h->ev[2 * cc + 1]);
-          if (ee != hipSuccess) {
-            h->sg_force = h->mpl_force = 0;
-            OKR_FAIL(h, OKR_E_HIP, "autotune timing failed: %s", hipGetErrorString(ee));
+      for (int wi = 0; wi < 3; ++wi)
+        for (int c = 1; c <= std::min(S, kMaxSnapGroups); c *= 2) {
+          h->sg_force = c;
+          h->mpl_force = 1 << mi;
+          h->ws_force = 1 << wi;
+          enqueue_search(h, d_workspace, Y, loads, &mt, st, &h->ev, nullptr, nullptr, nullptr, nullptr);
+          const hipError_t e1 = hipGetLastError(), e2 = hipStreamSynchronize(st);
+          if (e1 != hipSuccess || e2 != hipSuccess) {
+            h->sg_force = h->mpl_force = h->ws_force = 0;
+            OKR_FAIL(h, OKR_E_HIP, "autotune run failed: %s", hipGetErrorString(e1 != hipSuccess ? e1 : e2));
           }
-          if (used == c) T_(k, mi, c) += ms;
+          for (int cc = 0; cc < (int)h->chunk_k.size(); ++cc) {
+            const int k = h->chunk_k[cc], nzc = h->chunk_off[cc + 1] - h->chunk_off[cc];
+            int spg;
+            const int used = snap_groups(h, k, nzc, &spg);
+            float ms = 0.f;
+            const hipError_t ee = hipEventElapsedTime(&ms, h->ev[2 * cc], h->ev[2 * cc + 1]);
+            if (ee != hipSuccess) {
+              h->sg_force = h->mpl_force = h->ws_force = 0;
+              OKR_FAIL(h, OKR_E_HIP, "autotune timing failed: %s", hipGetErrorString(ee));
+            }
+            if (used == c) T_(shape_key(k, nzc), mi, wi, c) += ms;
+          }
+          h->sg_force = h->mpl_force = h->ws_force = 0;
         }
-        h->sg_force = h->mpl_force = 0;
-      }
-    for (int k = 1; k <= h->kmax; ++k) {
-      int bc = 0, bm = 0;
+    for (int key = 0; key < nkey; ++key) {
+      int bc = 0, bm = 0, bw = 0;
       for (int mi = 0; mi < 3; ++mi)
-        for (int c = 1; c <= kMaxSnapGroups; c *= 2)
-          if (T_(k, mi, c) > 0.0 && (bc == 0 || T_(k, mi, c) < T_(k, bm, bc))) {
-            bc = c;
-            bm = mi;
-          }
-      h->sg_tuned[k] = bc;
-      h->mpl_tuned[k] = bc ? 1 << bm : 0;
+        for (int wi = 0; wi < 3; ++wi)
+          for (int c = 1; c <= kMaxSnapGroups; c *= 2)
+            if (T_(key, mi, wi, c) > 0.0 && (bc == 0 || T_(key, mi, wi, c) < T_(key, bm, bw, bc))) {
+              bc = c;
+              bm = mi;
+              bw = wi;
+            }
+      h->sg_tuned[key] = bc;
+      h->mpl_tuned[key] = bc ? 1 << bm : 0;
+      h->ws_tuned[key] = bc ? 1 << bw : 0;
     }
     drop_graph(h);  // a captured search used the earlier group counts
   }
@@ -1278,8 +1325,10 @@ extern "C" int okr_reduce_feeder(okr_handle* h, const okr_yblocks* Y, const okr_
       // launch shape of the segment's chunk (set by its largest segment)
       const int kc = h->chunk_k[chunk_of[g]];
       int spg;
-      R.score_groups = snap_groups(h, kc, &spg);
-      R.score_mpl = sv_spp(score_mpl(h, kc), kc, spg);
+      const int nzc = h->chunk_off[chunk_of[g] + 1] - h->chunk_off[chunk_of[g]];
+      R.score_groups = snap_groups(h, kc, nzc, &spg);
+      R.score_mpl = sv_spp(score_mpl(h, kc, nzc), kc, spg);
+      R.score_waves = score_ws(h, kc, nzc);
       R.chunk = chunk_of[g];
     }
     // the scoring kernel's own FP64 work: per slot and mask, reduced ->

@@ -37,30 +37,36 @@ __device__ __forceinline__ void tile_record(const MaskScore& r, uint32_t m, bool
   }
 }
 
-// Per-mask FP64 scoring, snapshot-vectorised: one mask per lane (a block is
-// 4 waves, 256 consecutive masks), the block's snapshot group in passes of M
-// snapshots staged together in LDS (snapshot fastest), every chain's terms
-// for the M snapshots at once (score_chain_sv).  A pass past the group's
-// last snapshot repeats it (max / min unchanged).  The last block of a mask
-// range to finish (ticket counter) folds the snapshot groups into the final
-// per-mask score and writes the 64-mask tile records.  Dynamic LDS per
-// snapshot: pcap pairs, kcap slots and chains, zcap zone records (later
-// zone records are read from global memory).
+// Per-mask FP64 scoring, snapshot-vectorised: one mask per lane; a block's 4
+// waves form groups of ws waves (1, 2 or 4) over 64 consecutive masks each,
+// the waves of a group splitting the segment's chains (each chain's terms,
+// nesting path and zone entries included, are independent of the others')
+// and folding their maxima and minima in LDS at the end.  The block's
+// snapshot group is walked in passes of M snapshots staged together in LDS
+// (snapshot fastest), every chain's terms for the M snapshots at once
+// (score_chain_sv).  A pass past the group's last snapshot repeats it.  With
+// one snapshot group the block writes the final per-mask scores and tile
+// records itself; with several, the last block of a tile to finish (ticket
+// counter) folds the groups.  Dynamic LDS per snapshot: pcap pairs, kcap
+// slots and chains, zcap zone records (later zone records are read from
+// global memory).
 template <int M>
 __global__ __launch_bounds__(kScoreThreads) void k_score_fp64(
     const SegHdr* __restrict__ hdrs, const int* __restrict__ segs, size_t lstride, const int* __restrict__ tab,
     const double2* __restrict__ P, const TargetRec* __restrict__ srec, const double2* __restrict__ headV,
     const TargetRec* __restrict__ zrec, const double* __restrict__ econst, int snaps_per_group, int SG, int pcap,
-    int kcap, int zcap, SelParams sp, MaskScore* __restrict__ part, MaskScore* __restrict__ fin,
+    int kcap, int zcap, int ws, SelParams sp, MaskScore* __restrict__ part, MaskScore* __restrict__ fin,
     TileRec* __restrict__ tiles, int* __restrict__ tickets, const int* __restrict__ gates) {
+  constexpr int NW = kScoreThreads / 64;
   extern __shared__ __align__(16) unsigned char sv_lds[];
-  __shared__ int ticket;
+  __shared__ double f_e[NW][64], f_qn[NW][64], f_qx[NW][64];
   const int g = *as_cint(segs + blockIdx.z);
   const SegHdr H = load_hdr(hdrs, segs);
   if (!H.valid || (gates && gates[g] == 0)) return;
   // blocks past this segment's masks (a chunk's launch covers its largest segment)
   const uint32_t nmask = 1u << H.k;
-  if ((uint64_t)blockIdx.x * kScoreThreads >= nmask) return;
+  const uint32_t bmasks = kScoreBlock * (NW / ws);
+  if ((uint64_t)blockIdx.x * bmasks >= nmask) return;
   tab = lane_ptr(tab, lstride);
   P = lane_ptr(P, lstride);
   srec = lane_ptr(srec, lstride);
@@ -78,7 +84,10 @@ __global__ __launch_bounds__(kScoreThreads) void k_score_fp64(
   double* Hm = (double*)(Zs + (size_t)zcap * M);
   double* Ec = Hm + (size_t)kcap * 3 * M;
   const int tid = threadIdx.x;
-  const uint32_t m = blockIdx.x * kScoreThreads + tid;
+  const int w = __builtin_amdgcn_readfirstlane(tid >> 6);
+  const int lane = tid & 63;
+  const int c0 = w % ws;  // this wave's first chain within its group
+  const uint32_t m = blockIdx.x * bmasks + (uint32_t)(w / ws) * kScoreBlock + lane;
   const bool valid = m < nmask;
   const int sg = blockIdx.y;
   const int l0 = sg * snaps_per_group;
@@ -125,7 +134,7 @@ __global__ __launch_bounds__(kScoreThreads) void k_score_fp64(
       el[j] = Ec[j];
       zg[j] = zrec + (size_t)min(l + j, l1 - 1) * H.nz;
     }
-    for (int c = 0; c < H.nchains; ++c)
+    for (int c = c0; c < H.nchains; c += ws)
       score_chain_sv<M>(chains, nest, c, Ps, Ts, Hv, Hm, Zs, zst, zg, m, el, qmn, qmx);
 #pragma unroll
     for (int j = 0; j < M; ++j) e = fmax(e, el[j]);
@@ -137,18 +146,37 @@ __global__ __launch_bounds__(kScoreThreads) void k_score_fp64(
     qmin = fmin(qmin, qmn[j]);
     qmax = fmax(qmax, qmx[j]);
   }
-  if (valid) {
-    MaskScore r;
-    r.e = e;
-    r.slack = band_slack(qmin, qmax, sp.vmin, sp.vmax);
-    part[(size_t)sg * nmask + m] = r;
+  // fold the chains of a group's waves into its first wave (max and min are
+  // exact in any order)
+  if (ws > 1) {
+    f_e[w][lane] = e;
+    f_qn[w][lane] = qmin;
+    f_qx[w][lane] = qmax;
+    __syncthreads();
+    if (c0 != 0) return;
+    for (int q = 1; q < ws; ++q) {
+      e = fmax(e, f_e[w + q][lane]);
+      qmin = fmin(qmin, f_qn[w + q][lane]);
+      qmax = fmax(qmax, f_qx[w + q][lane]);
+    }
   }
-  __threadfence();
-  if (tid == 0) ticket = atomicAdd(&tickets[blockIdx.x], 1);
-  __syncthreads();
-  if (ticket != SG - 1) return;
-  // last block of this mask range: combine the snapshot groups
+  const uint32_t tile = m / kScoreBlock;
   MaskScore r;
+  r.e = e;
+  r.slack = band_slack(qmin, qmax, sp.vmin, sp.vmax);
+  if (SG == 1) {  // the block holds every snapshot: final scores and tile record directly
+    if (valid) fin[m] = r;
+    tile_record(r, m, valid, nmask, sp, tiles);
+    return;
+  }
+  if (valid) part[(size_t)sg * nmask + m] = r;
+  __threadfence();
+  int t = 0;
+  if (lane == 0) t = atomicAdd(&tickets[tile], 1);
+  t = __shfl(t, 0, 64);
+  if (t != SG - 1) return;
+  __threadfence();
+  // last block of this tile: combine the snapshot groups
   r.e = 0.0;
   r.slack = INFINITY;
   if (valid) {
@@ -160,13 +188,14 @@ __global__ __launch_bounds__(kScoreThreads) void k_score_fp64(
     fin[m] = r;
   }
   tile_record(r, m, valid, nmask, sp, tiles);
-  if (tid == 0) tickets[blockIdx.x] = 0;  // ready for the next launch
+  if (lane == 0) tickets[tile] = 0;  // ready for the next launch
 }
 
 #define OKR_SCORE64_INST(M_)                                                                                               \
   template __global__ void k_score_fp64<M_>(const SegHdr*, const int*, size_t, const int*, const double2*,              \
                                           const TargetRec*, const double2*, const TargetRec*, const double*, int, int, \
-                                          int, int, int, SelParams, MaskScore*, MaskScore*, TileRec*, int*, const int*);
+                                          int, int, int, int, SelParams, MaskScore*, MaskScore*, TileRec*, int*,       \
+                                          const int*);
 OKR_SCORE64_INST(1)
 OKR_SCORE64_INST(2)
 OKR_SCORE64_INST(4)

@@ -1,5 +1,5 @@
-"""Writes the oracle's full-size decisions for the 6000- and 8400-node
-workloads (TEST INFRASTRUCTURE: calls only oracle/ and the input generator).
+"""Writes the oracle's full-size decisions (TEST INFRASTRUCTURE: calls only
+oracle/ and the input generator).
 
 For each case: per-segment chosen mask, popcount, e_loc and ambiguity flag,
 the final per-snapshot errors and the kept count, as JSON next to this
@@ -7,7 +7,12 @@ script.  The oracle runs its descending-popcount search (every mask of a
 level scored before the next lower level; the first level holding a feasible
 mask decides), which selects the same mask as scoring all 2^k masks.
 
-    python tests/golden/make_golden.py
+Cases: the 6000- and 8400-node workloads at e_bar = 3e-3 (where nearly every
+segment keeps its top level), and the 1000-, 6000- and 8400-node workloads at
+an error bound that binds (a quarter or more of the segments choose a mask
+below the top level, so the arg-min is decided among many candidates).
+
+    python tests/golden/make_golden.py [case-name ...]
 """
 import json
 import os
@@ -22,11 +27,17 @@ import numpy as np  # noqa: E402
 import oracle  # noqa: E402
 from synth_feeders import make_feeder  # noqa: E402
 
-CASES = [("c3", 0, 3e-3), ("c4", 0, 3e-3)]
+CASES = {"c3": ("c3", 0, 3e-3, "oracle_c3_seed0.json"),
+         "c4": ("c4", 0, 3e-3, "oracle_c4_seed0.json"),
+         "c2_bind": ("c2", 0, 1e-4, "oracle_c2_seed0_ebar1e-4.json"),
+         "c3_bind": ("c3", 0, 7e-5, "oracle_c3_seed0_ebar7e-5.json"),
+         "c4_bind": ("c4", 0, 7e-5, "oracle_c4_seed0_ebar7e-5.json")}
 
 
 def main():
-    for cfg, seed, e_bar in CASES:
+    names = sys.argv[1:] or list(CASES)
+    for key in names:
+        cfg, seed, e_bar, fname = CASES[key]
         t0 = time.time()
         f = make_feeder(cfg, seed, e_bar=e_bar)
         V, I, st, _ = oracle.powerflow(f)
@@ -37,7 +48,7 @@ def main():
                    err_per_snapshot=[float(x) for x in err],
                    segments=[dict(mask=int(d["mask"]), popcount=int(d["popcount"]), e_loc=float(d["e_loc"]),
                                   ambiguous=int(d["ambiguous"])) for d in dec])
-        name = os.path.join(HERE, f"oracle_{cfg}_seed{seed}.json")
+        name = os.path.join(HERE, fname)
         with open(name, "w") as fh:
             json.dump(out, fh)
         print(f"{name}: {len(dec)} segments, kept {out['n_kept']}, {time.time() - t0:.0f} s", flush=True)
