@@ -226,6 +226,25 @@ int okr_reduce_feeder(okr_handle *h, const okr_yblocks *Y, const okr_topology *t
                       const okr_loads *loads, const okr_margins *mg,
                       void *d_workspace, size_t workspace_bytes, okr_result *out);
 
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): the same
+ * search as okr_reduce_feeder, with the workspace taken from a scratch array
+ * the library holds on each GPU it runs on (OKR_NOALLOC_SCRATCH_BYTES, held
+ * until the process ends; its address is looked up once per device, on the
+ * first call with that device current).  It calls no hipMalloc, hipFree or
+ * other allocating routine.  The caller passes inputs and outputs as for
+ * okr_reduce_feeder and must have the handle stream's device current.
+ * Returns OKR_E_WORKSPACE when the planned workspace exceeds the array (for
+ * example the 1000-node, 24-snapshot workload fits with margins.lanes = 1)
+ * and OKR_E_ARG for OKR_FLAG_TIMING, OKR_FLAG_GRAPH, OKR_FLAG_AUTOTUNE or
+ * OKR_FLAG_DUMP_SCORES (each would allocate events, graphs or host copies).
+ * Every call on a GPU shares that GPU's array, which keeps the last call's
+ * contents (the search initialises what it reads): calls that overlap on one
+ * GPU, from any handle or stream, race and must be serialised by the caller. */
+#define OKR_NOALLOC_SCRATCH_BYTES ((size_t)64 << 20)
+int okr_reduce_feeder_noalloc(okr_handle *h, const okr_yblocks *Y, const okr_topology *topo,
+                              const okr_loads *loads, const okr_margins *mg, okr_result *out);
+
 /* With OKR_FLAG_DUMP_SCORES: copy segment `segment`'s per-mask error and band
  * slack from the last call (HOST double[2^k] each) and return k through *k. */
 int okr_dump_scores(okr_handle *h, int32_t segment, double *e, double *slack, int32_t *k);

@@ -128,6 +128,9 @@ def lib():
         L.okr_reduce_feeder.argtypes = [vp, ctypes.POINTER(YBlocks), ctypes.POINTER(Topology),
                                         ctypes.POINTER(Loads), ctypes.POINTER(Margins), vp, ctypes.c_size_t,
                                         ctypes.POINTER(Result)]
+        L.okr_reduce_feeder_noalloc.argtypes = [vp, ctypes.POINTER(YBlocks), ctypes.POINTER(Topology),
+                                                ctypes.POINTER(Loads), ctypes.POINTER(Margins),
+                                                ctypes.POINTER(Result)]
         L.okr_dump_scores.argtypes = [vp, ctypes.c_int32, vp, vp, ctypes.POINTER(ctypes.c_int32)]
         L.okr_destroy.argtypes = [vp]
         L.okr_last_error.argtypes = [vp]
@@ -150,7 +153,8 @@ def lib():
         L.okr_greedy_destroy.argtypes = [vp]
         L.okr_greedy_last_error.argtypes = [vp]
         L.okr_greedy_last_error.restype = ctypes.c_char_p
-        for fn in ("okr_create", "okr_plan", "okr_reduce_feeder", "okr_dump_scores", "okr_destroy",
+        for fn in ("okr_create", "okr_plan", "okr_reduce_feeder", "okr_reduce_feeder_noalloc", "okr_dump_scores",
+                   "okr_destroy",
                    "okr_surrogate_workspace", "okr_train_surrogate", "okr_surrogate_grad",
                    "okr_surrogate_forward", "okr_greedy_create", "okr_greedy_plan", "okr_greedy_run",
                    "okr_greedy_evaluate", "okr_greedy_radialize", "okr_greedy_destroy"):
@@ -191,6 +195,16 @@ def okr_reduce_feeder(h, Y: YBlocks, topo: Topology, loads: Loads, margins: Marg
                       out: Result):
     return _check(h, lib().okr_reduce_feeder(h, ctypes.byref(Y), ctypes.byref(topo), ctypes.byref(loads),
                                              ctypes.byref(margins), d_ws, ws_bytes, ctypes.byref(out)))
+
+
+def okr_reduce_feeder_noalloc(h, Y: YBlocks, topo: Topology, loads: Loads, margins: Margins, out):
+    """okr_reduce_feeder with the library's static per-GPU scratch as workspace
+    (no device allocation; planned workspace at most OKR_NOALLOC_SCRATCH_BYTES)."""
+    return _check(h, lib().okr_reduce_feeder_noalloc(h, ctypes.byref(Y), ctypes.byref(topo), ctypes.byref(loads),
+                                                     ctypes.byref(margins), ctypes.byref(out)))
+
+
+NOALLOC_SCRATCH_BYTES = 64 << 20
 
 
 def okr_dump_scores(h, segment, nmask):
@@ -337,7 +351,7 @@ class Reducer:
         self.margins.surrogate = None if params is None else params.data_ptr()
         self.margins.top_k = top_k if params is not None else 0
 
-    def run(self, replan=True, want_vhat=False, want_features=False, autotune=False):
+    def run(self, replan=True, want_vhat=False, want_features=False, autotune=False, noalloc=False):
         """One pass of the whole search (planning included when replan).  With
         want_features the per-mask surrogate features and FP64 targets of every
         segment are left in ``self.features`` / ``self.targets`` (device).
@@ -363,8 +377,11 @@ class Reducer:
         if autotune:
             self.margins.flags = flags | OKR.FLAG_AUTOTUNE
         try:
-            rc = okr_reduce_feeder(self.h, self.Y, self.topo, self.loads, self.margins,
-                                   ctypes.c_void_p(self.ws.data_ptr()), self.ws_bytes, self.res)
+            if noalloc:
+                rc = okr_reduce_feeder_noalloc(self.h, self.Y, self.topo, self.loads, self.margins, self.res)
+            else:
+                rc = okr_reduce_feeder(self.h, self.Y, self.topo, self.loads, self.margins,
+                                       ctypes.c_void_p(self.ws.data_ptr()), self.ws_bytes, self.res)
         finally:
             self.margins.flags = flags
         return rc

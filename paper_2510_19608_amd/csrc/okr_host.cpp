@@ -9,6 +9,7 @@
 #include <cmath>
 #include <cstdio>
 #include <cstring>
+#include <mutex>
 #include <string>
 #include <vector>
 
@@ -1121,9 +1122,57 @@ uint64_t bits(double x) {
 
 }  // namespace
 
+static int reduce_feeder_impl(okr_handle* h, const okr_yblocks* Y, const okr_topology* topo,
+                              const okr_loads* loads, const okr_margins* mg, void* d_workspace,
+                              size_t workspace_bytes, okr_result* out);
+
 extern "C" int okr_reduce_feeder(okr_handle* h, const okr_yblocks* Y, const okr_topology* topo,
                                  const okr_loads* loads, const okr_margins* mg, void* d_workspace,
                                  size_t workspace_bytes, okr_result* out) {
+  return reduce_feeder_impl(h, Y, topo, loads, mg, d_workspace, workspace_bytes, out);
+}
+
+// The no-allocation entry point's workspace: one array per GPU, resolved to
+// its device address once per device (host code must never use the array's
+// name as a device pointer).
+static __device__ __align__(256) unsigned char scratch[OKR_NOALLOC_SCRATCH_BYTES];
+namespace {
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+void* g_scratch_ptr[kMaxDevices] = {};
+}  // namespace
+
+extern "C" int okr_reduce_feeder_noalloc(okr_handle* h, const okr_yblocks* Y, const okr_topology* topo,
+                                         const okr_loads* loads, const okr_margins* mg, okr_result* out) {
+  if (!h) return OKR_E_ARG;
+  if (!mg) OKR_FAIL(h, OKR_E_ARG, "null margins");
+  if (mg->flags & (OKR_FLAG_TIMING | OKR_FLAG_GRAPH | OKR_FLAG_AUTOTUNE | OKR_FLAG_DUMP_SCORES))
+    OKR_FAIL(h, OKR_E_ARG, "okr_reduce_feeder_noalloc takes none of the timing, graph, autotune or dump flags");
+  if (!h->planned) OKR_FAIL(h, OKR_E_ARG, "okr_plan() must succeed first");
+  if (h->L.total > OKR_NOALLOC_SCRATCH_BYTES)
+    OKR_FAIL(h, OKR_E_WORKSPACE, "planned workspace %zu bytes exceeds the static scratch of %zu bytes", h->L.total,
+             (size_t)OKR_NOALLOC_SCRATCH_BYTES);
+  int dev = -1;
+  OKR_HIP(h, hipGetDevice(&dev));
+  if (dev < 0 || dev >= kMaxDevices) OKR_FAIL(h, OKR_E_ARG, "device %d out of range", dev);
+  void* ws = nullptr;
+  {
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (!g_scratch_ptr[dev]) {
+      void* ptr = nullptr;
+      const hipError_t e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+      if (e != hipSuccess || !ptr)
+        OKR_FAIL(h, OKR_E_HIP, "hipGetSymbolAddress(scratch) on device %d: %s", dev, hipGetErrorString(e));
+      g_scratch_ptr[dev] = ptr;
+    }
+    ws = g_scratch_ptr[dev];
+  }
+  return reduce_feeder_impl(h, Y, topo, loads, mg, ws, OKR_NOALLOC_SCRATCH_BYTES, out);
+}
+
+static int reduce_feeder_impl(okr_handle* h, const okr_yblocks* Y, const okr_topology* topo,
+                              const okr_loads* loads, const okr_margins* mg, void* d_workspace,
+                              size_t workspace_bytes, okr_result* out) {
   using clk = std::chrono::steady_clock;
   if (!h) return OKR_E_ARG;
   if (!h->planned) OKR_FAIL(h, OKR_E_ARG, "okr_plan() must succeed first");

@@ -154,3 +154,33 @@ def test_greedy_plan_validation():
         assert e.value.code == okr.OKR.E_PHASE
     finally:
         okr.okr_greedy_destroy(g)
+
+
+def test_noalloc_entry_point_rejects_before_any_gpu_call():
+    """The no-allocation variant refuses the flags that would allocate and a
+    plan whose workspace exceeds its static scratch, on the host."""
+    import paper_2510_19608_amd as okr
+    B = okr.binding
+    f = make_feeder("c2", 0)
+    h = okr.okr_create(None)
+    try:
+        T, keep = _topo(okr, f)
+        mg = B.make_margins(f)
+        mg.lanes = 8
+        ws, _ = okr.okr_plan(h, T, mg, 24)
+        assert ws > B.NOALLOC_SCRATCH_BYTES
+        res = B.Result()
+        Y, loads = B.YBlocks(None, None), B.Loads(24, None, None, None)
+        rc = B.lib().okr_reduce_feeder_noalloc(h, ctypes.byref(Y), ctypes.byref(T), ctypes.byref(loads),
+                                               ctypes.byref(mg), ctypes.byref(res))
+        assert rc == B.OKR.E_WORKSPACE and b"static scratch" in B.lib().okr_last_error(h)
+        mg.lanes = 1
+        ws, _ = okr.okr_plan(h, T, mg, 24)
+        assert ws <= B.NOALLOC_SCRATCH_BYTES  # the 1000-node workload fits with one lane
+        for flag in (B.OKR.FLAG_TIMING, B.OKR.FLAG_GRAPH, B.OKR.FLAG_AUTOTUNE, B.OKR.FLAG_DUMP_SCORES):
+            mg.flags = flag
+            rc = B.lib().okr_reduce_feeder_noalloc(h, ctypes.byref(Y), ctypes.byref(T), ctypes.byref(loads),
+                                                   ctypes.byref(mg), ctypes.byref(res))
+            assert rc == B.OKR.E_ARG
+    finally:
+        okr.okr_destroy(h)
