@@ -141,31 +141,80 @@ def mode_entry(name, ms, plain_ms, masks, pops, res, ref_masks, ref_pops, ncand,
     return d
 
 
-def surrogate_mode(f, args, plain_ms, ref, ncand):
-    """Train the ranking MLP on the exhaustive search's own (features, error)
-    pairs from other feeders, then run the pruned search on this one."""
+def train_surrogate(args):
+    """The ranking MLP trained on the exhaustive search's own (features, error)
+    pairs from feeders other than the evaluated ones (the 30-bus feeder, seeds
+    0-15, and two 1000-node feeders), and its calibrated margin (99.9%
+    quantile of its over-prediction on those rows)."""
     import torch
-    from paper_2510_19608_amd import Reducer, surrogate
+    from paper_2510_19608_amd import surrogate
     from synth_feeders import make_feeder
     t0 = time.perf_counter()
-    train_feeders = [make_feeder("c2", s) for s in (101, 102)] + [make_feeder("c1", s) for s in range(10)]
+    train_feeders = [make_feeder("c1", s) for s in range(16)] + [make_feeder("c2", s) for s in (101, 102)]
     X, t, _ = surrogate.collect(train_feeders)
     t_collect = time.perf_counter() - t0
     t0 = time.perf_counter()
     params, loss = surrogate.train(X, t, epochs=args.surr_epochs, batch=4096, lr=1e-3, seed=0)
     torch.cuda.synchronize()
     t_train = time.perf_counter() - t0
-    n_pairs = int(X.shape[0])
+    margin = surrogate.calibrate(params, X, t, 0.999)
+    info = dict(train_pairs=int(X.shape[0]), train_epochs=args.surr_epochs, train_loss_first=float(loss[0]),
+                train_loss_last=float(loss[-1]), train_s=t_train, collect_s=t_collect, margin=margin)
     del X, t
-    R = Reducer(f, device="cuda:0", graph=True, surrogate=params, top_k=args.top_k)
+    return params, margin, info
+
+
+def surrogate_mode(f, args, plain_ms, ref, ncand, trained):
+    """The pruned search (top_k masks rescored exactly, full enumeration as
+    fallback) with the trained network on this feeder."""
+    from paper_2510_19608_amd import Reducer
+    params, margin, info = trained
+    R = Reducer(f, device="cuda:0", graph=True, surrogate=params, top_k=args.top_k, surrogate_margin=margin)
     ms = timed_runs(R, args.reps, args.autotune)
     masks, pops, res = decisions(R)
     fallback = sum(1 for s in res["segments"] if s["n_scored"] > s["n_refined"])
     R.close()
     return mode_entry("surrogate", ms, plain_ms, masks, pops, res, ref[0], ref[1], ncand,
-                      dict(top_k=args.top_k, fallback_segments=fallback, train_pairs=n_pairs,
-                           train_epochs=args.surr_epochs, train_loss_first=float(loss[0]),
-                           train_loss_last=float(loss[-1]), train_s=t_train, collect_s=t_collect))
+                      dict(top_k=args.top_k, fallback_segments=fallback, **info))
+
+
+def modes_section(f, args, trained):
+    """Time-to-optimal of the plain FP64, mixed, surrogate and factored
+    searches on one feeder (graph replays), each with its agreement with the
+    plain decisions and its reduction deficit."""
+    from paper_2510_19608_amd import Reducer
+    ncand = None
+    modes = {}
+    Rg = Reducer(f, device="cuda:0", graph=True)
+    ncand = int(Rg.sizes.n_candidates)
+    plain_ms = timed_runs(Rg, args.reps, args.autotune)
+    ref_masks, ref_pops, res = decisions(Rg)
+    Rg.close()
+    below = sum(1 for s in res["segments"] if s["popcount"] < s["k"])
+    modes["e_bar"] = f["e_bar"]
+    modes["segments_below_top_level"] = below
+    modes["segments"] = len(res["segments"])
+    modes["plain_fp64"] = mode_entry("plain", plain_ms, plain_ms, ref_masks, ref_pops, res, ref_masks, ref_pops, ncand)
+    wanted = set(args.modes.split(","))
+    if "mixed" in wanted:
+        Rm = Reducer(f, device="cuda:0", graph=True, precision="mixed")
+        ms = timed_runs(Rm, args.reps, args.autotune)
+        m, p, res = decisions(Rm)
+        refined = sum(s["n_refined"] for s in res["segments"])
+        dev = max(s["fp32_dev"] for s in res["segments"])
+        Rm.close()
+        modes["mixed"] = mode_entry("mixed", ms, plain_ms, m, p, res, ref_masks, ref_pops, ncand,
+                                    dict(fp64_rescored_masks=refined, max_fp32_vs_fp64_error=dev))
+    if "surrogate" in wanted and trained is not None:
+        modes["surrogate"] = surrogate_mode(f, args, plain_ms, (ref_masks, ref_pops), ncand, trained)
+    if "factored" in wanted:
+        # exact per-mask scores assembled from per-chain pattern tables
+        Rf = Reducer(f, device="cuda:0", graph=True, precision="factored")
+        ms = timed_runs(Rf, args.reps, False)
+        m, p, res = decisions(Rf)
+        Rf.close()
+        modes["factored_fp64"] = mode_entry("factored", ms, plain_ms, m, p, res, ref_masks, ref_pops, ncand)
+    return modes
 
 
 GREEDY_SIZES = (100, 300, 500, 1000)
@@ -314,18 +363,21 @@ def main():
     ap.add_argument("--surr-epochs", type=int, default=6)
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-modes", action="store_true")
+    ap.add_argument("--no-c5", action="store_true", help="skip the surrogate run on the 6000-node feeder")
     ap.add_argument("--no-greedy", action="store_true", help="skip the Algorithm 1 greedy-search section")
     ap.add_argument("--no-sweep", action="store_true", help="skip the e_bar sweep section")
     ap.add_argument("--modes", default="plain,mixed,surrogate,factored",
                     help="comma-separated forms timed for time-to-optimal (plain is always timed)")
     ap.add_argument("--lanes", type=int, default=0,
                     help="segments per launch chunk of the timed searches (0 = the library default, 8)")
-    ap.add_argument("--autotune", action="store_true",
-                    help="tune the scoring launch shape before the warm-up (default: the library's default shape)")
+    ap.add_argument("--no-autotune", action="store_true",
+                    help="keep the library's default scoring launch shape (default: tune it once per handle "
+                         "before the warm-up, a search per candidate shape)")
     ap.add_argument("--copy-probe-mib", type=int, default=0,
                     help="first run one device-to-device copy of this many MiB (a known-size reference "
                          "for hardware byte counters)")
     args = ap.parse_args()
+    args.autotune = not args.no_autotune
     if args.gpus != 1:
         print(json.dumps({"error": "this search runs on one GPU; --gpus above 1 is not supported "
                                    "(segments would shard across GPUs by subtree, see the design notes)"}))
@@ -403,32 +455,20 @@ def main():
                      "launch_shapes_k_groups_mpl": shapes},
     }
     if not args.no_modes:
-        modes = {}
-        Rg = Reducer(f, device="cuda:0", graph=True)
-        plain_ms = timed_runs(Rg, args.reps, args.autotune)
-        m, p, res = decisions(Rg)
-        Rg.close()
-        modes["plain_fp64"] = mode_entry("plain", plain_ms, plain_ms, m, p, res, ref_masks, ref_pops, ncand)
-        wanted = set(args.modes.split(","))
-        if "mixed" in wanted:
-            Rm = Reducer(f, device="cuda:0", graph=True, precision="mixed")
-            ms = timed_runs(Rm, args.reps, args.autotune)
-            m, p, res = decisions(Rm)
-            refined = sum(s["n_refined"] for s in res["segments"])
-            dev = max(s["fp32_dev"] for s in res["segments"])
-            Rm.close()
-            modes["mixed"] = mode_entry("mixed", ms, plain_ms, m, p, res, ref_masks, ref_pops, ncand,
-                                        dict(fp64_rescored_masks=refined, max_fp32_vs_fp64_error=dev))
-        if "surrogate" in wanted:
-            modes["surrogate"] = surrogate_mode(f, args, plain_ms, (ref_masks, ref_pops), ncand)
-        if "factored" in wanted:
-            # exact per-mask scores assembled from per-chain pattern tables
-            Rf = Reducer(f, device="cuda:0", graph=True, precision="factored")
-            ms = timed_runs(Rf, args.reps, False)
-            m, p, res = decisions(Rf)
-            Rf.close()
-            modes["factored_fp64"] = mode_entry("factored", ms, plain_ms, m, p, res, ref_masks, ref_pops, ncand)
-        line["modes"] = modes
+        trained = train_surrogate(args) if "surrogate" in args.modes.split(",") else None
+        # time-to-optimal at the configured bound (nearly every segment keeps
+        # its top level) and at a bound that binds (most segments choose a
+        # mask below the top level, so the arg-min is decided among many)
+        line["modes"] = modes_section(f, args, trained)
+        line["modes_binding"] = modes_section(make_feeder("c2", args.seed, e_bar=1e-4), args, trained)
+        if trained is not None and not args.no_c5:
+            # surrogate-pruned search on the 6000-node, 96-snapshot feeder
+            # (trained on the 30- and 1000-node dumps above), at a bound that
+            # binds, against the plain FP64 search of the same feeder
+            args_c5 = argparse.Namespace(**vars(args))
+            args_c5.reps = 3
+            args_c5.modes = "surrogate"
+            line["c5_surrogate_6000node"] = modes_section(make_feeder("c3", args.seed, e_bar=1e-4), args_c5, trained)
     if not args.no_greedy:
         line["greedy_alg1"] = greedy_section(args.seed, cpu=not args.no_cpu)
     if not args.no_sweep:

@@ -146,6 +146,11 @@ typedef struct {
                          region or chain head), conflicting segments keep
                          their order; read by okr_plan (each chunk position
                          has its own scratch block) */
+    float surrogate_margin; /* with `surrogate`: a mask counts as predicted
+                               feasible while its predicted ln error is at
+                               most ln(e_bar) + surrogate_margin (the
+                               calibrated over-prediction of the network, so
+                               that feasible masks are not ranked out) */
 } okr_margins;
 
 /* Sizes okr_plan() reports. */

@@ -62,7 +62,8 @@ class Margins(ctypes.Structure):
     _fields_ = [("e_bar", ctypes.c_double), ("v_min", ctypes.c_double), ("v_max", ctypes.c_double),
                 ("tie_tol", ctypes.c_double), ("amb_tol", ctypes.c_double), ("pf_tol", ctypes.c_double),
                 ("pf_maxit", ctypes.c_int32), ("precision", ctypes.c_int32), ("flags", ctypes.c_uint32),
-                ("top_k", ctypes.c_int32), ("surrogate", ctypes.c_void_p), ("lanes", ctypes.c_int32)]
+                ("top_k", ctypes.c_int32), ("surrogate", ctypes.c_void_p), ("lanes", ctypes.c_int32),
+                ("surrogate_margin", ctypes.c_float)]
 
 
 class Sizes(ctypes.Structure):
@@ -274,7 +275,7 @@ def okr_surrogate_forward(params, X, y, work):
 
 def make_margins(f=None, *, e_bar=None, v_min=None, v_max=None, tie_tol=1e-11, amb_tol=1e-13,
                  precision="fp64", timing=False, dump=False, vhat_given=False, graph=False, pf_tol=1e-13,
-                 pf_maxit=100, top_k=0, surrogate=None, lanes=0):
+                 pf_maxit=100, top_k=0, surrogate=None, lanes=0, surrogate_margin=0.0):
     f = f or {}
     flags = (OKR.FLAG_TIMING if timing else 0) | (OKR.FLAG_DUMP_SCORES if dump else 0) | \
             (OKR.FLAG_VHAT_GIVEN if vhat_given else 0) | (OKR.FLAG_GRAPH if graph else 0)
@@ -285,7 +286,8 @@ def make_margins(f=None, *, e_bar=None, v_min=None, v_max=None, tie_tol=1e-11, a
                    precision={"fp64": OKR.PRECISION_FP64, "mixed": OKR.PRECISION_MIXED,
                               "factored": OKR.PRECISION_FP64_FACTORED}[precision],
                    flags=flags, top_k=top_k,
-                   surrogate=None if surrogate is None else surrogate.data_ptr(), lanes=lanes)
+                   surrogate=None if surrogate is None else surrogate.data_ptr(), lanes=lanes,
+                   surrogate_margin=surrogate_margin)
 
 
 class Reducer:
@@ -344,12 +346,14 @@ class Reducer:
                           self.out_Yko.ctypes.data, self.out_err.ctypes.data, None,
                           ctypes.cast(self.out_seg, ctypes.c_void_p))
 
-    def set_surrogate(self, params, top_k):
+    def set_surrogate(self, params, top_k, margin=0.0):
         """Switch learned pruning on (params: device tensor) or off (None);
-        top_k must not exceed the value planned with."""
+        top_k must not exceed the value planned with; margin: the ln-error
+        slack of the predicted-feasible test."""
         self.surrogate = params
         self.margins.surrogate = None if params is None else params.data_ptr()
         self.margins.top_k = top_k if params is not None else 0
+        self.margins.surrogate_margin = margin
 
     def run(self, replan=True, want_vhat=False, want_features=False, autotune=False, noalloc=False):
         """One pass of the whole search (planning included when replan).  With

@@ -959,7 +959,8 @@ void enqueue_search(okr_handle* h, void* ws, const okr_yblocks* Y, const okr_loa
       // top_k of the full ranking (predicted-feasible masks rank by level
       // first) and stage 2, the ranking of every mask, is skipped on device.
       const int K = mg->top_k;
-      const float ln_ebar = (float)std::log(mg->e_bar);
+      // predicted feasible: predicted ln error within the calibrated margin of ln(e_bar)
+      const float ln_ebar = (float)(std::log(mg->e_bar) + (double)mg->surrogate_margin);
       int L1 = k;
       uint64_t N1 = 1;
       while (L1 > 0 && N1 < (uint64_t)4 * K) {
@@ -1282,7 +1283,8 @@ static int reduce_feeder_impl(okr_handle* h, const okr_yblocks* Y, const okr_top
         (uint64_t)loads->Vhat, (uint64_t)st, (uint64_t)mg->flags, bits(mg->e_bar), bits(mg->v_min),
         bits(mg->v_max), bits(mg->tie_tol), bits(mg->amb_tol), bits(mg->pf_tol), (uint64_t)mg->pf_maxit,
         bits(V0[0].x), bits(V0[0].y), bits(V0[1].x), bits(V0[1].y), bits(V0[2].x), bits(V0[2].y),
-        (uint64_t)mg->precision, (uint64_t)(int64_t)mg->top_k, (uint64_t)mg->surrogate};
+        (uint64_t)mg->precision, (uint64_t)(int64_t)mg->top_k, (uint64_t)mg->surrogate,
+        bits((double)mg->surrogate_margin)};
     if (!h->gexec || key != h->gkey) {
       drop_graph(h);
       OKR_HIP(h, hipStreamSynchronize(st));

@@ -77,6 +77,17 @@ def train(X, t, epochs=6, batch=4096, lr=1e-3, seed=0, params=None):
     return params, loss
 
 
+def calibrate(params, X, t, q=0.99):
+    """The network's over-prediction at quantile q on (X, t): the ln-error
+    slack that keeps a fraction q of masks ranked as predicted feasible when
+    they are (okr_margins.surrogate_margin).  Computed with the library's own
+    forward pass; the quantile is taken on the host from the residuals."""
+    import numpy as np
+    y = predict(params, X)
+    r = (y - t).float().cpu().numpy()
+    return float(max(0.0, np.quantile(r, q)))
+
+
 def predict(params, X, batch=65536):
     """Surrogate predictions for every row of X (device), in chunks."""
     import torch
