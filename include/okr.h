@@ -151,6 +151,11 @@ typedef struct {
                                most ln(e_bar) + surrogate_margin (the
                                calibrated over-prediction of the network, so
                                that feasible masks are not ranked out) */
+    double mixed_delta;     /* MIXED: the bound assumed on |e32 - e64| and
+                               |slack32 - slack64| (0 = 1e-8, above the proven
+                               2e-9); a segment whose measured deviation over
+                               its rescored masks exceeds it is scored again in
+                               FP64 over every mask */
 } okr_margins;
 
 /* Sizes okr_plan() reports. */
@@ -184,6 +189,10 @@ typedef struct {
                                (shared tables replace the per-candidate
                                voltage-change products; 0 with FACTORED) */
     int32_t score_waves;    /* ... and waves sharing each 64 masks' chains (default rule or autotuned) */
+    double key_gap;         /* margin of the decision: the smallest e_loc of a feasible mask of the chosen
+                               level outside the tie window, minus e_min (+inf if none).  Exact for FP64 and
+                               FP64_FACTORED; MIXED and top_k take it over their FP64-rescored masks, which
+                               can only overstate it */
 } okr_segment_result;
 
 /* Outputs (HOST buffers owned by the caller). */

@@ -34,7 +34,8 @@ class Decision(ctypes.Structure):
     _fields_ = [("segment", ctypes.c_int32), ("k", ctypes.c_int32),
                 ("mask", ctypes.c_uint32), ("popcount", ctypes.c_int32),
                 ("e_loc", ctypes.c_double), ("e_min", ctypes.c_double),
-                ("ambiguous", ctypes.c_int32), ("n_scored", ctypes.c_int32)]
+                ("ambiguous", ctypes.c_int32), ("n_scored", ctypes.c_int32),
+                ("key_gap", ctypes.c_double)]
 
 
 _lib = None
@@ -168,7 +169,7 @@ def search(f, Vhat, Ihat, tie_tol=1e-11, amb_tol=1e-13, mode=1):
         raise RuntimeError(f"okro_search failed: {st}")
     decs = [dict(segment=d.segment, k=d.k, mask=d.mask, popcount=d.popcount,
                  e_loc=d.e_loc, e_min=d.e_min, ambiguous=bool(d.ambiguous),
-                 n_scored=d.n_scored) for d in list(dec)[:nseg.value]]
+                 n_scored=d.n_scored, key_gap=d.key_gap) for d in list(dec)[:nseg.value]]
     return keep, decs, st
 
 

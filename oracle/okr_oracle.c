@@ -721,6 +721,7 @@ typedef struct {
     int32_t popcount;
     double e_loc, e_min;
     int32_t ambiguous, n_scored;
+    double key_gap; /* smallest e_loc above the tie window at the chosen level, minus e_min (inf if none) */
 } okro_decision;
 
 static int popc(uint32_t m) { int c = 0; while (m) { m &= m - 1; ++c; } return c; }
@@ -802,7 +803,7 @@ int okro_search(int n, const int32_t *parent, const uint8_t *phase,
             D->n_scored = nscored;
             if (best_level < 0) {
                 D->mask = 0; D->popcount = 0; D->e_loc = el[0]; D->e_min = el[0];
-                D->ambiguous = 1;
+                D->ambiguous = 1; D->key_gap = INFINITY;
             } else {
                 double emin = INFINITY;
                 for (uint32_t m = 0; m < nm; ++m)
@@ -817,8 +818,15 @@ int okro_search(int n, const int32_t *parent, const uint8_t *phase,
                     if (fabs(el[m] - (emin + tie_tol)) <= amb_tol) amb = 1;
                     if (!found && el[m] <= emin + tie_tol) { pick = m; found = 1; }
                 }
+                /* the margin of the decision: the best feasible mask of the
+                 * chosen level outside the tie window */
+                double runner = INFINITY;
+                for (uint32_t m = 0; m < nm; ++m)
+                    if (done[m] && fe[m] && popc(m) == best_level && el[m] > emin + tie_tol && el[m] < runner)
+                        runner = el[m];
                 D->mask = pick; D->popcount = best_level; D->e_loc = el[pick];
                 D->e_min = emin; D->ambiguous = amb;
+                D->key_gap = runner - emin;
                 for (int j = 0; j < k; ++j)
                     if (pick >> j & 1u) keep_out[nodes[j]] = 0;
             }

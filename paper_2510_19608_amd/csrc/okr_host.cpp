@@ -40,7 +40,7 @@ __global__ void k_terms_init(const SegHdr*, const int*, size_t, int, const int*,
 __global__ void k_chain_terms(const SegHdr*, const int*, size_t, int, const int*, const double2*, const TargetRec*,
                               const double2*, const TargetRec*, const double*, const uint32_t*, const int*, int, int,
                               int, unsigned long long*, unsigned long long*);
-__global__ void k_list_finish(const int*, const unsigned long long*, int, SelParams, MaskScore*);
+__global__ void k_list_finish(const int*, const unsigned long long*, int, SelParams, MaskScore*, size_t);
 __global__ void k_surr_rank(const SegHdr*, int, const int*, const float*, const float*, const SurrSlot*, const double*,
                             const uint32_t*, int, const __bf16*, const __bf16*, const float*, float, uint32_t*,
                             const int*, int);
@@ -56,18 +56,21 @@ __global__ void k_final_err(int, const uint8_t*, const int*, const double2*, con
 __global__ void k_kron_yeq(Topo, State, const double2*, double2*, double2*, int*, int*);
 __global__ void k_kron_diag(Topo, State, const double2*, double2*);
 __global__ void k_sqrt_selftest(const double*, double*, int);
-__global__ void k_build_mixed(const SegHdr*, int, const int*, int, const double2*, const double2*, const TargetRec*,
-                              const double2*, const TargetRec*, double, double, Pair32*, Rec32*, Head32*, Rec32*);
+__global__ void k_build_mixed(const SegHdr*, const int*, size_t, const int*, int, const double2*, const double2*,
+                              const TargetRec*, const double2*, const TargetRec*, double, double, Pair32*, Rec32*,
+                              Head32*, Rec32*);
 template <int M>
-__global__ void k_score_fp32(const SegHdr*, int, const int*, const Pair32*, const Rec32*, const Head32*, const Rec32*,
-                             const double*, int, int, SelParams, MaskScore32*, MaskScore32*, TileRec32*, int*);
-__global__ void k_mixed_select_a(const SegHdr*, int, const MaskScore32*, const TileRec32*, SelParams, const int*,
-                                 MixedState*, uint32_t*, int*);
-__global__ void k_mixed_select_b(const SegHdr*, int, const MaskScore32*, const TileRec32*, SelParams, const int*,
-                                 MixedState*, const uint32_t*, const int*, const MaskScore*, uint32_t*, int*);
-__global__ void k_mixed_final(const SegHdr*, int, SelParams, const int*, MixedState*, const MaskScore32*,
-                              const uint32_t*, const int*, const MaskScore*, const uint32_t*, const int*,
-                              const MaskScore*, DevDecision*);
+__global__ void k_score_fp32(const SegHdr*, const int*, size_t, const int*, const Pair32*, const Rec32*, const Head32*,
+                             const Rec32*, const double*, int, int, SelParams, MaskScore32*, MaskScore32*, TileRec32*,
+                             int*);
+__global__ void k_mixed_select_a(const SegHdr*, const int*, size_t, const MaskScore32*, const TileRec32*, SelParams,
+                                 const int*, MixedState*, uint32_t*, int*);
+__global__ void k_mixed_select_b(const SegHdr*, const int*, size_t, const MaskScore32*, const TileRec32*, SelParams,
+                                 const int*, MixedState*, const uint32_t*, const int*, const MaskScore*, uint32_t*,
+                                 int*);
+__global__ void k_mixed_final(const SegHdr*, const int*, size_t, SelParams, const int*, MixedState*,
+                              const MaskScore32*, const uint32_t*, const int*, const MaskScore*, const uint32_t*,
+                              const int*, const MaskScore*, DevDecision*, int*);
 __global__ void k_surr_tables(const SegHdr*, int, const int*, int, const double2*, const double2*, const double2*,
                               const TargetRec*, float*, float*, SurrSlot*);
 __global__ void k_surr_features(const SegHdr*, int, const int*, const float*, const float*, const SurrSlot*,
@@ -846,23 +849,24 @@ Ptrs pointers(okr_handle* h, void* d_workspace, int lane = 0) {
 // FP64 scores of list[0 .. *count) (at most cap masks) of one segment into
 // out: one lane per (listed mask, chain, snapshot), folded by atomics.  w
 // holds the segment's scratch pointers and segp its id in device memory.
-void list_score(const okr_handle* h, const Ptrs& w, const int* segp, int k, const uint32_t* list, const int* count,
-                int cap, MaskScore* out, const SelParams& sp, hipStream_t st) {
+// FP64 scores of a mask list per chunk position (list, count and out in each
+// position's scratch block; cap bounds every list): accumulators, chain
+// terms of every (listed mask, chain), final scores.
+void list_score(const okr_handle* h, const Ptrs& w, const int* segp, int nz, int k, const uint32_t* list,
+                const int* count, int cap, MaskScore* out, const SelParams& sp, hipStream_t st) {
+  const size_t ls = h->L.lane_stride;
   const int fb = std::max(1, std::min(64, (cap + 255) / 256));
   const int cb = std::max(1, std::min(16, (int)(((size_t)cap * k + 255) / 256)));
-  hipLaunchKernelGGL(k_terms_init, dim3(fb), dim3(256), 0, st, (const SegHdr*)w.hdrs, segp, (size_t)0, (int)0, count,
+  hipLaunchKernelGGL(k_terms_init, dim3(fb, 1, nz), dim3(256), 0, st, (const SegHdr*)w.hdrs, segp, ls, (int)0, count,
                      cap, (const double*)w.econst, w.lacc, (unsigned long long*)nullptr);
-  hipLaunchKernelGGL(k_chain_terms, dim3(cb, h->S), dim3(256), terms_lds_bytes(k), st, (const SegHdr*)w.hdrs, segp,
-                     (size_t)0, (int)0, (const int*)w.tab, (const double2*)w.P, (const TargetRec*)w.srec,
+  hipLaunchKernelGGL(k_chain_terms, dim3(cb, h->S, nz), dim3(256), terms_lds_bytes(k), st, (const SegHdr*)w.hdrs,
+                     segp, ls, (int)0, (const int*)w.tab, (const double2*)w.P, (const TargetRec*)w.srec,
                      (const double2*)w.headV, (const TargetRec*)w.zrec, (const double*)w.econst, list, count, cap,
                      terms_icap(k), kTermsZone, w.lacc, (unsigned long long*)nullptr);
-  hipLaunchKernelGGL(k_list_finish, dim3(fb), dim3(256), 0, st, count, (const unsigned long long*)w.lacc, cap, sp,
-                     out);
+  hipLaunchKernelGGL(k_list_finish, dim3(fb, 1, nz), dim3(256), 0, st, count, (const unsigned long long*)w.lacc, cap,
+                     sp, out, ls);
 }
 
-// Enqueue one whole search on `st` without host synchronisation.  With `ev`
-// (2 events per chunk) the scoring launches are bracketed by events; with
-// `dump` every segment's final per-mask scores are copied out.
 void enqueue_search(okr_handle* h, void* ws, const okr_yblocks* Y, const okr_loads* loads,
                     const okr_margins* mg, hipStream_t st, const std::vector<hipEvent_t>* ev,
                     std::vector<std::vector<MaskScore>>* dump, std::vector<std::vector<MaskScore32>>* dump32,
@@ -903,7 +907,7 @@ void enqueue_search(okr_handle* h, void* ws, const okr_yblocks* Y, const okr_loa
   sp.vmax = mg->v_max;
   sp.tie = mg->tie_tol;
   sp.amb = mg->amb_tol;
-  sp.delta = kMixedDelta;
+  sp.delta = mg->mixed_delta > 0.0 ? mg->mixed_delta : kMixedDelta;
   const bool mixed = mg->precision == OKR_PRECISION_MIXED;
   const bool factored = mg->precision == OKR_PRECISION_FP64_FACTORED;
   const bool surr = mg->top_k > 0 && mg->top_k <= h->topk && mg->surrogate != nullptr &&
@@ -996,7 +1000,8 @@ void enqueue_search(okr_handle* h, void* ws, const okr_yblocks* Y, const okr_loa
                            (const uint32_t*)nullptr, (int)nm, K, (const int*)w.status, w.slist, w.scount,
                            (const int*)nullptr, 0);
       }
-      list_score(h, w, p.chunks + c0 + z, k, w.slist, w.scount, K, w.sscore, sp, st);
+      // one segment: its own position's buffers are the launch's position 0
+      list_score(h, w, p.chunks + c0 + z, 1, k, w.slist, w.scount, K, w.sscore, sp, st);
       hipLaunchKernelGGL(k_surr_decide, dim3(1), dim3(1024), 0, st, (const SegHdr*)w.hdrs, g, sp,
                          (const int*)w.status, (const uint32_t*)w.slist, (const int*)w.scount,
                          (const MaskScore*)w.sscore, w.decs, w.sgates + g);
@@ -1049,60 +1054,63 @@ void enqueue_search(okr_handle* h, void* ws, const okr_yblocks* Y, const okr_loa
         }
       }
     } else {
-      // the FP32 screen: masks per lane and groups by the default rule
+      // mixed precision, one launch per step over the chunk: FP32 tables and
+      // screen, shortlist A and its FP64 scores, shortlist B and its FP64
+      // scores, the decision; then the FP64 scoring and arg-min of the
+      // segments whose FP32 deviation exceeded the bound (gated on device)
       int spg32, mpl32;
       const int SG32 = screen32_shape(kc, S, &spg32, &mpl32);
-      for (int z = 0; z < nz; ++z) {
-        const int g = h->chunk_segs[c0 + z];
-        const Ptrs& w = lp[z];
-        hipLaunchKernelGGL(k_build_mixed, dim3(256, 4), dim3(256), 0, st, (const SegHdr*)w.hdrs, g, (const int*)w.tab,
-                           n, (const double2*)w.Vcur, (const double2*)w.P, (const TargetRec*)w.srec,
-                           (const double2*)w.headV, (const TargetRec*)w.zrec, mg->v_min, mg->v_max, w.P32, w.S32,
-                           w.H32, w.Z32);
-      }
+      hipLaunchKernelGGL(k_build_mixed, dim3(256, 4, nz), dim3(256), 0, st, (const SegHdr*)q.hdrs, segs, lstride,
+                         (const int*)q.tab, n, (const double2*)q.Vcur, (const double2*)q.P, (const TargetRec*)q.srec,
+                         (const double2*)q.headV, (const TargetRec*)q.zrec, mg->v_min, mg->v_max, q.P32, q.S32, q.H32,
+                         q.Z32);
       if (ev) (void)hipEventRecord((*ev)[2 * c], st);
-      for (int z = 0; z < nz; ++z) {
-        const int g = h->chunk_segs[c0 + z];
-        const int k = h->seg_off[g + 1] - h->seg_off[g];
-        const Ptrs& w = lp[z];
-        const uint32_t nm = 1u << k;
-        const int mblocks32 = (int)((nm + kScoreThreads * mpl32 - 1) / (kScoreThreads * mpl32));
-#define OKR_SCORE32(M_)                                                                                       \
-  hipLaunchKernelGGL(k_score_fp32<M_>, dim3(mblocks32, SG32), dim3(kScoreThreads), 0, st, (const SegHdr*)w.hdrs, g, \
-                     (const int*)w.tab, (const Pair32*)w.P32, (const Rec32*)w.S32, (const Head32*)w.H32,         \
-                     (const Rec32*)w.Z32, (const double*)w.econst, spg32, SG32, sp, w.part32, w.fin32, w.tiles32, \
-                     w.tickets)
-        if (mpl32 == 4) OKR_SCORE32(4);
-        else if (mpl32 == 2) OKR_SCORE32(2);
-        else OKR_SCORE32(1);
+      const int mblocks32 = (int)((nmask + kScoreThreads * mpl32 - 1) / (kScoreThreads * mpl32));
+#define OKR_SCORE32(M_)                                                                                          \
+  hipLaunchKernelGGL(k_score_fp32<M_>, dim3(mblocks32, SG32, nz), dim3(kScoreThreads), 0, st, (const SegHdr*)q.hdrs, \
+                     segs, lstride, (const int*)q.tab, (const Pair32*)q.P32, (const Rec32*)q.S32,                  \
+                     (const Head32*)q.H32, (const Rec32*)q.Z32, (const double*)q.econst, spg32, SG32, sp, q.part32,  \
+                     q.fin32, q.tiles32, q.tickets)
+      if (mpl32 == 4) OKR_SCORE32(4);
+      else if (mpl32 == 2) OKR_SCORE32(2);
+      else OKR_SCORE32(1);
 #undef OKR_SCORE32
-      }
       if (ev) (void)hipEventRecord((*ev)[2 * c + 1], st);
-      for (int z = 0; z < nz; ++z) {
-        const int g = h->chunk_segs[c0 + z];
-        const int k = h->seg_off[g + 1] - h->seg_off[g];
-        const uint32_t nm = 1u << k;
-        const Ptrs& w = lp[z];
-        int* cA = w.counts;
-        int* cB = w.counts + 1;
-        hipLaunchKernelGGL(k_mixed_select_a, dim3(1), dim3(1024), 0, st, (const SegHdr*)w.hdrs, g,
-                           (const MaskScore32*)w.fin32, (const TileRec32*)w.tiles32, sp, (const int*)w.status,
-                           w.mstate, w.listA, cA);
-        list_score(h, w, p.chunks + c0 + z, k, w.listA, cA, (int)nm, w.scoreA, sp, st);
-        hipLaunchKernelGGL(k_mixed_select_b, dim3(1), dim3(1024), 0, st, (const SegHdr*)w.hdrs, g,
-                           (const MaskScore32*)w.fin32, (const TileRec32*)w.tiles32, sp, (const int*)w.status,
-                           w.mstate, (const uint32_t*)w.listA, (const int*)cA, (const MaskScore*)w.scoreA, w.listB,
-                           cB);
-        list_score(h, w, p.chunks + c0 + z, k, w.listB, cB, (int)nm, w.scoreB, sp, st);
-        hipLaunchKernelGGL(k_mixed_final, dim3(1), dim3(1024), 0, st, (const SegHdr*)w.hdrs, g, sp,
-                           (const int*)w.status, w.mstate, (const MaskScore32*)w.fin32, (const uint32_t*)w.listA,
-                           (const int*)cA, (const MaskScore*)w.scoreA, (const uint32_t*)w.listB, (const int*)cB,
-                           (const MaskScore*)w.scoreB, w.decs);
-        if (dump) {
-          (*dump32)[g].resize(nm);
-          (void)hipMemcpyAsync((*dump32)[g].data(), w.fin32, sizeof(MaskScore32) * nm, hipMemcpyDeviceToHost, st);
-        }
+      int* cA = q.counts;
+      int* cB = q.counts + 1;
+      hipLaunchKernelGGL(k_mixed_select_a, dim3(1, 1, nz), dim3(1024), 0, st, (const SegHdr*)q.hdrs, segs, lstride,
+                         (const MaskScore32*)q.fin32, (const TileRec32*)q.tiles32, sp, (const int*)q.status, q.mstate,
+                         q.listA, cA);
+      list_score(h, q, segs, nz, kc, q.listA, cA, (int)nmask, q.scoreA, sp, st);
+      hipLaunchKernelGGL(k_mixed_select_b, dim3(1, 1, nz), dim3(1024), 0, st, (const SegHdr*)q.hdrs, segs, lstride,
+                         (const MaskScore32*)q.fin32, (const TileRec32*)q.tiles32, sp, (const int*)q.status, q.mstate,
+                         (const uint32_t*)q.listA, (const int*)cA, (const MaskScore*)q.scoreA, q.listB, cB);
+      list_score(h, q, segs, nz, kc, q.listB, cB, (int)nmask, q.scoreB, sp, st);
+      hipLaunchKernelGGL(k_mixed_final, dim3(1, 1, nz), dim3(1024), 0, st, (const SegHdr*)q.hdrs, segs, lstride, sp,
+                         (const int*)q.status, q.mstate, (const MaskScore32*)q.fin32, (const uint32_t*)q.listA,
+                         (const int*)cA, (const MaskScore*)q.scoreA, (const uint32_t*)q.listB, (const int*)cB,
+                         (const MaskScore*)q.scoreB, q.decs, q.sgates);
+      {
+        const int* redo = q.sgates;
+#define OKR_SCORE64(M_)                                                                                             \
+  hipLaunchKernelGGL(k_score_fp64<M_>, dim3(mblocks, SG, nz), dim3(kScoreThreads), lds, st, (const SegHdr*)q.hdrs, segs, \
+                     lstride, (const int*)q.tab, (const double2*)q.P, (const TargetRec*)q.srec,                      \
+                     (const double2*)q.headV, (const TargetRec*)q.zrec, (const double*)q.econst, spg, SG, pcap, kc,   \
+                     kSvZone, sws, sp, q.part, q.fin, q.tiles, q.tickets, redo)
+        if (spp == 4) OKR_SCORE64(4);
+        else if (spp == 2) OKR_SCORE64(2);
+        else OKR_SCORE64(1);
+#undef OKR_SCORE64
+        hipLaunchKernelGGL(k_argmin, dim3(1, 1, nz), dim3(1024), 0, st, (const SegHdr*)q.hdrs, segs, lstride,
+                           (const MaskScore*)q.fin, (const TileRec*)q.tiles, sp, (const int*)q.status, q.decs, redo);
       }
+      if (dump)
+        for (int z = 0; z < nz; ++z) {
+          const int g = h->chunk_segs[c0 + z];
+          const uint32_t nm = 1u << (h->seg_off[g + 1] - h->seg_off[g]);
+          (*dump32)[g].resize(nm);
+          (void)hipMemcpyAsync((*dump32)[g].data(), lp[z].fin32, sizeof(MaskScore32) * nm, hipMemcpyDeviceToHost, st);
+        }
     }
     hipLaunchKernelGGL(k_apply, dim3(S, 1, nz), dim3(64), 0, st, (const SegHdr*)q.hdrs, segs, lstride,
                        (const int*)q.tab, q.T, q.St, (const DevDecision*)q.decs, (const double2*)q.P,
@@ -1284,7 +1292,7 @@ static int reduce_feeder_impl(okr_handle* h, const okr_yblocks* Y, const okr_top
         bits(mg->v_max), bits(mg->tie_tol), bits(mg->amb_tol), bits(mg->pf_tol), (uint64_t)mg->pf_maxit,
         bits(V0[0].x), bits(V0[0].y), bits(V0[1].x), bits(V0[1].y), bits(V0[2].x), bits(V0[2].y),
         (uint64_t)mg->precision, (uint64_t)(int64_t)mg->top_k, (uint64_t)mg->surrogate,
-        bits((double)mg->surrogate_margin)};
+        bits((double)mg->surrogate_margin), bits(mg->mixed_delta)};
     if (!h->gexec || key != h->gkey) {
       drop_graph(h);
       OKR_HIP(h, hipStreamSynchronize(st));
@@ -1321,7 +1329,7 @@ static int reduce_feeder_impl(okr_handle* h, const okr_yblocks* Y, const okr_top
     OKR_HIP(h, hipMemcpyAsync(hdrs.data(), p.hdrs, sizeof(SegHdr) * nseg, hipMemcpyDeviceToHost, st));
     if (mixed)
       OKR_HIP(h, hipMemcpyAsync(mstate.data(), p.mstate, sizeof(MixedState) * nseg, hipMemcpyDeviceToHost, st));
-    if (surr_used)
+    if (surr_used || mixed)
       OKR_HIP(h, hipMemcpyAsync(gates.data(), p.sgates, sizeof(int) * nseg, hipMemcpyDeviceToHost, st));
   }
   OKR_HIP(h, hipMemcpyAsync(sup.data(), p.St.sup, sizeof(int) * n, hipMemcpyDeviceToHost, st));
@@ -1371,6 +1379,7 @@ static int reduce_feeder_impl(okr_handle* h, const okr_yblocks* Y, const okr_top
     R.e_loc = decs[g].e_loc;
     R.e_min = decs[g].e_min;
     R.ambiguous = decs[g].ambiguous;
+    R.key_gap = decs[g].key_gap;
     R.n_scored = 1 << k;
     {
       // launch shape of the segment's chunk (set by its largest segment)
@@ -1397,8 +1406,8 @@ static int reduce_feeder_impl(okr_handle* h, const okr_yblocks* Y, const okr_top
     out->algorithmic_flops += R.flops;
     for (int j = 0; j < k; ++j)  // the state the next segments see
       if (decs[g].mask >> j & 1u) keep_before[h->seg_nodes[h->seg_off[g] + j]] = 0;
-    if (mixed) {
-      R.n_refined = mstate[g].nA + mstate[g].nB;
+    if (mixed) {  // (every mask again in FP64 when the deviation exceeded the bound)
+      R.n_refined = mstate[g].nA + mstate[g].nB + (gates[g] ? (1 << k) : 0);
       R.fp32_dev = mstate[g].max_dev;
     }
     if (surr_used) {

@@ -115,6 +115,7 @@ struct DevDecision {
   double e_min;
   int32_t ambiguous;
   int32_t found;
+  double key_gap;  // smallest e_loc above the tie window at the chosen level, minus e_min (inf if none)
 };
 
 // Per-mask partial score: max error and min band slack over a snapshot group.

@@ -261,6 +261,7 @@ __global__ __launch_bounds__(1024) void k_argmin(const SegHdr* __restrict__ hdrs
     if (threadIdx.x == 0) {
       DevDecision d;
       d.mask = 0; d.popcount = 0; d.e_loc = 0.0; d.e_min = 0.0; d.ambiguous = 0; d.found = 0;
+      d.key_gap = INFINITY;
       *dec = d;
     }
     return;
@@ -281,6 +282,9 @@ __global__ __launch_bounds__(1024) void k_argmin(const SegHdr* __restrict__ hdrs
   emin = block_reduce(emin, [](double a, double b) { return fmin(a, b); }, shd);
   unsigned pick = 0xffffffffu;
   const double thr = emin + sp.tie;
+  // runner-up: the smallest error above the tie window at the chosen level
+  // (a tile not rescanned holds it at its own minimum)
+  double runner = INFINITY;
   // candidate tiles, processed in chunks of 1024 tiles
   for (int base = 0; base < ntiles && best >= 0; base += 1024) {
     if (threadIdx.x == 0) ncand = 0;
@@ -289,6 +293,7 @@ __global__ __launch_bounds__(1024) void k_argmin(const SegHdr* __restrict__ hdrs
     if (t < ntiles) {
       const TileRec r = tiles[t];
       if (r.best == best && r.emin <= thr + sp.amb) cand[atomicAdd(&ncand, 1)] = t;
+      else if (r.best == best) runner = fmin(runner, r.emin);
     }
     __syncthreads();
     const int nc = ncand;
@@ -299,17 +304,21 @@ __global__ __launch_bounds__(1024) void k_argmin(const SegHdr* __restrict__ hdrs
       if (__popc(mm) != best || !feasible(r, sp.e_bar)) continue;
       if (fabs(r.e - thr) <= sp.amb) amb = 1;
       if (r.e <= thr) pick = min(pick, mm);
+      else runner = fmin(runner, r.e);
     }
     __syncthreads();
   }
   pick = block_reduce(pick, [](unsigned a, unsigned b) { return min(a, b); }, shu);
   amb = block_reduce(amb, [](int a, int b) { return a | b; }, shi);
+  runner = block_reduce(runner, [](double a, double b) { return fmin(a, b); }, shd);
   if (threadIdx.x == 0) {
     DevDecision d;
     if (best < 0) {
       d.mask = 0; d.popcount = 0; d.e_loc = fin[0].e; d.e_min = fin[0].e; d.ambiguous = 1; d.found = 0;
+      d.key_gap = INFINITY;
     } else {
       d.mask = pick; d.popcount = best; d.e_loc = fin[pick].e; d.e_min = emin; d.ambiguous = amb; d.found = 1;
+      d.key_gap = runner - emin;
     }
     *dec = d;
   }

@@ -23,8 +23,8 @@
 
 namespace okr {
 
-__global__ __launch_bounds__(256) void k_build_mixed(const SegHdr* __restrict__ hdrs, int g,
-                                                     const int* __restrict__ tab, int n,
+__global__ __launch_bounds__(256) void k_build_mixed(const SegHdr* __restrict__ hdrs, const int* __restrict__ segs,
+                                                     size_t lstride, const int* __restrict__ tab, int n,
                                                      const double2* __restrict__ Vcur,
                                                      const double2* __restrict__ P,
                                                      const TargetRec* __restrict__ srec,
@@ -32,8 +32,17 @@ __global__ __launch_bounds__(256) void k_build_mixed(const SegHdr* __restrict__ 
                                                      const TargetRec* __restrict__ zrec, double vmin, double vmax,
                                                      Pair32* __restrict__ P32, Rec32* __restrict__ S32,
                                                      Head32* __restrict__ H32, Rec32* __restrict__ Z32) {
-  const SegHdr H = load_hdr_g(hdrs, g);
+  const SegHdr H = load_hdr(hdrs, segs);
   if (!H.valid) return;
+  tab = lane_ptr(tab, lstride);
+  P = lane_ptr(P, lstride);
+  srec = lane_ptr(srec, lstride);
+  headV = lane_ptr(headV, lstride);
+  zrec = lane_ptr(zrec, lstride);
+  P32 = lane_ptr(P32, lstride);
+  S32 = lane_ptr(S32, lstride);
+  H32 = lane_ptr(H32, lstride);
+  Z32 = lane_ptr(Z32, lstride);
   const int part = blockIdx.y, S = H.S;
   const int stride = gridDim.x * blockDim.x;
   const float NEG = -INFINITY, POS = INFINITY;
@@ -108,14 +117,19 @@ __device__ __forceinline__ bool skip_segment(const SegHdr& H, const int* status)
 
 // List A: masks whose FP32 verdict is uncertain, at or above the best level
 // holding a surely feasible mask.
-__global__ __launch_bounds__(1024) void k_mixed_select_a(const SegHdr* __restrict__ hdrs, int g,
-                                                         const MaskScore32* __restrict__ fin,
+__global__ __launch_bounds__(1024) void k_mixed_select_a(const SegHdr* __restrict__ hdrs, const int* __restrict__ segs,
+                                                         size_t lstride, const MaskScore32* __restrict__ fin,
                                                          const TileRec32* __restrict__ tiles, SelParams sp,
                                                          const int* __restrict__ status, MixedState* __restrict__ ms,
                                                          uint32_t* __restrict__ listA, int* __restrict__ countA) {
   __shared__ int shi[16];
   __shared__ int cnt;
+  const int g = segs[blockIdx.z];
   const SegHdr H = load_hdr_g(hdrs, g);
+  fin = lane_ptr(fin, lstride);
+  tiles = lane_ptr(tiles, lstride);
+  listA = lane_ptr(listA, lstride);
+  countA = lane_ptr(countA, lstride);
   if (threadIdx.x == 0) cnt = 0;
   if (skip_segment(H, status)) {
     if (threadIdx.x == 0) { *countA = 0; ms[g].lo_level = -1; ms[g].hi_level = -1; }
@@ -152,8 +166,8 @@ __global__ __launch_bounds__(1024) void k_mixed_select_a(const SegHdr* __restric
 }
 
 // Best level P* and list B.
-__global__ __launch_bounds__(1024) void k_mixed_select_b(const SegHdr* __restrict__ hdrs, int g,
-                                                         const MaskScore32* __restrict__ fin,
+__global__ __launch_bounds__(1024) void k_mixed_select_b(const SegHdr* __restrict__ hdrs, const int* __restrict__ segs,
+                                                         size_t lstride, const MaskScore32* __restrict__ fin,
                                                          const TileRec32* __restrict__ tiles, SelParams sp,
                                                          const int* __restrict__ status, MixedState* __restrict__ ms,
                                                          const uint32_t* __restrict__ listA,
@@ -163,7 +177,15 @@ __global__ __launch_bounds__(1024) void k_mixed_select_b(const SegHdr* __restric
   __shared__ int shi[16];
   __shared__ double shd[16];
   __shared__ int cnt;
+  const int g = segs[blockIdx.z];
   const SegHdr H = load_hdr_g(hdrs, g);
+  fin = lane_ptr(fin, lstride);
+  tiles = lane_ptr(tiles, lstride);
+  listA = lane_ptr(listA, lstride);
+  countA = lane_ptr(countA, lstride);
+  scoreA = lane_ptr(scoreA, lstride);
+  listB = lane_ptr(listB, lstride);
+  countB = lane_ptr(countB, lstride);
   if (threadIdx.x == 0) cnt = 0;
   if (skip_segment(H, status)) {
     if (threadIdx.x == 0) { *countB = 0; ms[g].best = -1; }
@@ -218,25 +240,35 @@ __global__ __launch_bounds__(1024) void k_mixed_select_b(const SegHdr* __restric
 
 // FP64 arg-min over list B; ambiguity from the FP64 scores of A and B; the
 // largest FP32 deviation seen on refined masks is kept for reporting.
-__global__ __launch_bounds__(1024) void k_mixed_final(const SegHdr* __restrict__ hdrs, int g, SelParams sp,
-                                                      const int* __restrict__ status, MixedState* __restrict__ ms,
-                                                      const MaskScore32* __restrict__ fin,
+__global__ __launch_bounds__(1024) void k_mixed_final(const SegHdr* __restrict__ hdrs, const int* __restrict__ segs,
+                                                      size_t lstride, SelParams sp, const int* __restrict__ status,
+                                                      MixedState* __restrict__ ms, const MaskScore32* __restrict__ fin,
                                                       const uint32_t* __restrict__ listA, const int* __restrict__ countA,
                                                       const MaskScore* __restrict__ scoreA,
                                                       const uint32_t* __restrict__ listB, const int* __restrict__ countB,
                                                       const MaskScore* __restrict__ scoreB,
-                                                      DevDecision* __restrict__ decs) {
+                                                      DevDecision* __restrict__ decs, int* __restrict__ redo) {
   __shared__ double shd[16];
   __shared__ int shi[16];
   __shared__ unsigned shu[16];
+  const int g = segs[blockIdx.z];
   const SegHdr H = load_hdr_g(hdrs, g);
+  fin = lane_ptr(fin, lstride);
+  listA = lane_ptr(listA, lstride);
+  countA = lane_ptr(countA, lstride);
+  scoreA = lane_ptr(scoreA, lstride);
+  listB = lane_ptr(listB, lstride);
+  countB = lane_ptr(countB, lstride);
+  scoreB = lane_ptr(scoreB, lstride);
   DevDecision* dec = decs + g;
   const int best = ms[g].best;
+  if (threadIdx.x == 0) redo[g] = 0;
   if (skip_segment(H, status) || best < 0) {
     if (threadIdx.x == 0) {
       DevDecision d;
       d.mask = 0; d.popcount = 0; d.e_loc = 0.0; d.e_min = 0.0; d.ambiguous = skip_segment(H, status) ? 0 : 1;
       d.found = 0;
+      d.key_gap = INFINITY;
       *dec = d;
     }
     return;
@@ -252,11 +284,13 @@ __global__ __launch_bounds__(1024) void k_mixed_final(const SegHdr* __restrict__
   const double thr = emin + sp.tie;
   unsigned pick = 0xffffffffu;
   int amb = 0;
+  double runner = INFINITY;  // among the FP64-rescored masks of list B
   for (int q = threadIdx.x; q < nB; q += blockDim.x) {
     const MaskScore r = scoreB[q];
     if (!feasible(r, sp.e_bar)) continue;
     if (fabs(r.e - thr) <= sp.amb) amb = 1;
     if (r.e <= thr) pick = min(pick, listB[q]);
+    else runner = fmin(runner, r.e);
   }
   for (int q = threadIdx.x; q < nA; q += blockDim.x) {
     const MaskScore r = scoreA[q];
@@ -266,6 +300,7 @@ __global__ __launch_bounds__(1024) void k_mixed_final(const SegHdr* __restrict__
   pick = block_reduce(pick, [](unsigned a, unsigned b) { return min(a, b); }, shu);
   amb = block_reduce(amb, [](int a, int b) { return a | b; }, shi);
   dev = block_reduce(dev, [](double a, double b) { return fmax(a, b); }, shd);
+  runner = block_reduce(runner, [](double a, double b) { return fmin(a, b); }, shd);
   if (threadIdx.x == 0) {
     DevDecision d;
     double epick = 0.0;
@@ -277,8 +312,13 @@ __global__ __launch_bounds__(1024) void k_mixed_final(const SegHdr* __restrict__
     d.e_min = emin;
     d.ambiguous = amb;
     d.found = pick != 0xffffffffu;
+    d.key_gap = runner - emin;
     *dec = d;
     ms[g].max_dev = dev;
+    // the shortlists are complete only while |e32 - e64| <= delta: past the
+    // bound the segment is scored again in FP64 over every mask (and that
+    // decision replaces this one)
+    redo[g] = dev > sp.delta ? 1 : 0;
   }
 }
 

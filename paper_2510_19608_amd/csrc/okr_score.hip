@@ -353,7 +353,10 @@ __global__ __launch_bounds__(kTermsBlock) void k_chain_terms(
 
 // Scores of a short mask list from its accumulators.
 __global__ void k_list_finish(const int* __restrict__ count, const unsigned long long* __restrict__ acc, int cap,
-                              SelParams sp, MaskScore* __restrict__ out) {
+                              SelParams sp, MaskScore* __restrict__ out, size_t lstride) {
+  count = lane_ptr(count, lstride);
+  acc = lane_ptr(acc, lstride);
+  out = lane_ptr(out, lstride);
   const int n = min(*count, cap);
   for (int q = blockIdx.x * blockDim.x + threadIdx.x; q < n; q += gridDim.x * blockDim.x) {
     MaskScore r;
@@ -522,18 +525,31 @@ __device__ __forceinline__ void walk32(const int* __restrict__ cr, const Pair32*
 // tile records of sure / possible / uncertain feasibility.
 template <int M>
 __global__ __launch_bounds__(kScoreThreads) void k_score_fp32(
-    const SegHdr* __restrict__ hdrs, int g, const int* __restrict__ tab, const Pair32* __restrict__ P32,
-    const Rec32* __restrict__ S32, const Head32* __restrict__ H32, const Rec32* __restrict__ Z32,
-    const double* __restrict__ econst, int snaps_per_group, int SG, SelParams sp, MaskScore32* __restrict__ part,
-    MaskScore32* __restrict__ fin, TileRec32* __restrict__ tiles, int* __restrict__ tickets) {
+    const SegHdr* __restrict__ hdrs, const int* __restrict__ segs, size_t lstride, const int* __restrict__ tab,
+    const Pair32* __restrict__ P32, const Rec32* __restrict__ S32, const Head32* __restrict__ H32,
+    const Rec32* __restrict__ Z32, const double* __restrict__ econst, int snaps_per_group, int SG, SelParams sp,
+    MaskScore32* __restrict__ part, MaskScore32* __restrict__ fin, TileRec32* __restrict__ tiles,
+    int* __restrict__ tickets) {
   __shared__ Pair32 Ps[kMaxPairs * 3];
   __shared__ Rec32 Ts[kMaxK * 3];
   __shared__ Head32 Hv[kMaxK * 3];
   __shared__ Rec32 Zs[kZoneLds];
   __shared__ double s_ec;
   __shared__ int ticket;
-  const SegHdr H = load_hdr_g(hdrs, g);
+  const SegHdr H = load_hdr(hdrs, segs);
   if (!H.valid) return;
+  // blocks past this segment's masks (a chunk's launch covers its largest segment)
+  if ((uint64_t)blockIdx.x * (kScoreThreads * M) >= ((uint64_t)1 << H.k)) return;
+  tab = lane_ptr(tab, lstride);
+  P32 = lane_ptr(P32, lstride);
+  S32 = lane_ptr(S32, lstride);
+  H32 = lane_ptr(H32, lstride);
+  Z32 = lane_ptr(Z32, lstride);
+  econst = lane_ptr(econst, lstride);
+  part = lane_ptr(part, lstride);
+  fin = lane_ptr(fin, lstride);
+  tiles = lane_ptr(tiles, lstride);
+  tickets = lane_ptr(tickets, lstride);
   const int tid = threadIdx.x;
   uint32_t m[M];
 #pragma unroll
@@ -649,7 +665,7 @@ __global__ __launch_bounds__(kScoreThreads) void k_score_fp32(
 }
 
 #define OKR_SCORE32_INST(M_)                                                                                   \
-  template __global__ void k_score_fp32<M_>(const SegHdr*, int, const int*, const Pair32*, const Rec32*,       \
+  template __global__ void k_score_fp32<M_>(const SegHdr*, const int*, size_t, const int*, const Pair32*, const Rec32*,       \
                                             const Head32*, const Rec32*, const double*, int, int, SelParams,  \
                                             MaskScore32*, MaskScore32*, TileRec32*, int*);
 OKR_SCORE32_INST(1)

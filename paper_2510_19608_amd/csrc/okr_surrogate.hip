@@ -620,6 +620,7 @@ __global__ __launch_bounds__(1024) void k_surr_decide(const SegHdr* __restrict__
   const double thr = emin + sp.tie;
   unsigned pick = 0xffffffffu;
   int amb = 0;
+  double runner = INFINITY;  // among the rescored top-k
   for (int q = threadIdx.x; q < n; q += blockDim.x) {
     const MaskScore r = sc[q];
     const int pc = __popc(list[q]);
@@ -627,9 +628,11 @@ __global__ __launch_bounds__(1024) void k_surr_decide(const SegHdr* __restrict__
     if (pc != best || !feasible(r, sp.e_bar)) continue;
     if (fabs(r.e - thr) <= sp.amb) amb = 1;
     if (r.e <= thr) pick = min(pick, list[q]);
+    else runner = fmin(runner, r.e);
   }
   pick = block_reduce(pick, [](unsigned a, unsigned b) { return min(a, b); }, shu);
   amb = block_reduce(amb, [](int a, int b) { return a | b; }, shi);
+  runner = block_reduce(runner, [](double a, double b) { return fmin(a, b); }, shd);
   for (int q = threadIdx.x; q < n; q += blockDim.x)  // masks in the list are distinct
     if (list[q] == pick) shd[0] = sc[q].e;
   __syncthreads();
@@ -642,6 +645,7 @@ __global__ __launch_bounds__(1024) void k_surr_decide(const SegHdr* __restrict__
     d.e_min = emin;
     d.ambiguous = amb;
     d.found = 1;
+    d.key_gap = runner - emin;
     decs[g] = d;
     *gate = 0;
   }

@@ -38,7 +38,7 @@ def oracle_run(f):
     return V, I, keep, dec, st
 
 
-def check_outputs(f, out, V, I, keep, dec):
+def check_outputs(f, out, V, I, keep, dec, exact_gap=True):
     got = [s["mask"] for s in out["segments"]]
     want = [d["mask"] for d in dec]
     amb = [d["ambiguous"] for d in dec]
@@ -58,9 +58,13 @@ def check_outputs(f, out, V, I, keep, dec):
     scale = np.abs(Ykd).max()
     np.testing.assert_allclose(out["Yk_diag"], Ykd, rtol=0, atol=1e-9 * scale)
     np.testing.assert_allclose(out["Yk_off"], Yko, rtol=0, atol=1e-9 * scale)
-    # chosen masks' errors
+    # chosen masks' errors and the decisions' margins
     for s, d in zip(out["segments"], dec):
         assert abs(s["e_loc"] - d["e_loc"]) < TOL
+        if exact_gap:
+            assert (np.isinf(s["key_gap"]) and np.isinf(d["key_gap"])) or abs(s["key_gap"] - d["key_gap"]) < TOL
+        else:  # over the FP64-rescored masks only: at least the exact margin
+            assert s["key_gap"] >= d["key_gap"] - TOL
 
 
 @pytest.mark.parametrize("seed,e_bar", [(s, e) for s in range(6) for e in (3e-3, 3e-4, 1e-4)])
@@ -293,7 +297,7 @@ def test_mixed_precision_decisions_equal_fp64(okr, name, seed, e_bar, band):
     V, I, keep, dec, st = oracle_run(f)
     a = okr.reduce_feeder(f, precision="fp64")
     b = okr.reduce_feeder(f, precision="mixed")
-    check_outputs(f, b, V, I, keep, dec)
+    check_outputs(f, b, V, I, keep, dec, exact_gap=False)
     assert [s["mask"] for s in a["segments"]] == [s["mask"] for s in b["segments"]]
     for sa, sb in zip(a["segments"], b["segments"]):
         assert sa["e_loc"] == sb["e_loc"]  # the decision's error is the FP64 value
@@ -418,3 +422,21 @@ def test_algorithmic_flop_count():
         for j, v in enumerate(nodes):
             if s["mask"] >> j & 1:
                 keep[v] = False
+
+
+@pytest.mark.parametrize("seed", [0, 3])
+def test_mixed_reruns_fp64_past_its_bound(okr, seed):
+    """With the assumed FP32 bound set below the measured deviation, every
+    segment whose shortlist shows a larger deviation is scored again in FP64
+    over every mask; the decisions stay the FP64 path's and the oracle's."""
+    _say(f"mixed with a 1e-15 bound, ms seed={seed}")
+    f = make_feeder("c1", seed, n=40, n_eligible=None, seg_size=(4, 7), snapshots=3, scale=(0.3, 1.0), e_bar=2e-4)
+    V, I, keep, dec, st = oracle_run(f)
+    b = okr.reduce_feeder(f, precision="mixed", mixed_delta=1e-15)
+    check_outputs(f, b, V, I, keep, dec, exact_gap=False)
+    rerun = [s for s in b["segments"] if s["fp32_dev"] > 1e-15]
+    assert rerun, "no segment exceeded the bound"
+    for s in rerun:
+        assert s["n_refined"] >= (1 << s["k"])
+        want = next(d["key_gap"] for d in dec if d["segment"] == s["segment"])  # exact again after the re-run
+        assert (np.isinf(want) and np.isinf(s["key_gap"])) or abs(s["key_gap"] - want) < TOL

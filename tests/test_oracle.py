@@ -487,3 +487,26 @@ def test_score_masks_agrees_with_dense_scores(oracle_lib):
         for key in ("e_glob", "e_loc", "slack_glob", "slack_loc"):
             assert abs(got[key][q] - ref[key]) < 1e-12
         assert got["feasible"][q] == ref["feasible"]
+
+
+@pytest.mark.parametrize("seed", [0, 1, 2, 3])
+def test_key_gap_is_the_runner_up_margin(oracle_lib, seed):
+    """The search's decision margin equals the one read off the per-mask
+    scores of every mask (a separate route through score_masks): the smallest
+    error of a feasible mask of the chosen level outside the tie window,
+    minus the smallest error of that level."""
+    import oracle
+    f = make_feeder("c1", seed, e_bar=3e-4)
+    V, I, st, _ = oracle.powerflow(f)
+    keep, dec, st = oracle.search(f, V, I)
+    k = dec[0]["k"]
+    ref = oracle.score_masks(f, V, I, np.ones(f["n"], np.uint8), 0, np.arange(1 << k))
+    pc = np.array([bin(m).count("1") for m in range(1 << k)])
+    lvl = (pc == dec[0]["popcount"]) & ref["feasible"].astype(bool)
+    e = ref["e_loc"][lvl]
+    emin = e.min()
+    outside = e[e > emin + 1e-11]
+    want = (outside.min() - emin) if outside.size else np.inf
+    got = dec[0]["key_gap"]
+    assert (np.isinf(want) and np.isinf(got)) or got == want
+    assert got >= 0.0
