@@ -212,19 +212,21 @@ int tuned(const std::vector<int>& t, int k, int nz) {
   const int i = shape_key(k, nz);
   return i < (int)t.size() ? t[i] : 0;
 }
-// Snapshots per pass: 2 by default (measured on MI355X).
+// Defaults follow the autotuner's picks on MI355X for the 1000-node workload
+// (segments of 15-16 nodes, chunks of 1-8 segments): a lone segment takes 4
+// snapshots per pass and 4 waves per 64 masks (2 from 16 nodes), a chunk of
+// several 2 snapshots and 2 waves, a full chunk of 8 one wave per 64 masks.
 int score_mpl(const okr_handle* h, int k, int nz) {
   if (h->mpl_force) return h->mpl_force;
   const int t = tuned(h->mpl_tuned, k, nz);
-  return t ? t : 2;
+  return t ? t : (nz == 1 ? 4 : 2);
 }
-// Waves sharing the chains of each 64 masks (1, 2 or 4): 2 by default (the
-// autotuner's pick on MI355X for the 1000-node workload's 16-node segments at
-// 2 snapshots per pass).
 int score_ws(const okr_handle* h, int k, int nz) {
   if (h->ws_force) return h->ws_force;
   const int t = tuned(h->ws_tuned, k, nz);
-  return t ? t : 2;
+  if (t) return t;
+  if (nz >= kMaxLanes) return 1;
+  return (nz == 1 && k <= 15) ? 4 : 2;
 }
 
 // Snapshot groups of the FP64 scoring launch for a segment of k nodes: the
@@ -259,7 +261,7 @@ int sv_spp(int want, int k, int spg) {
   return spp;
 }
 
-// Default groups: at least about 4096 waves per launch (4 per SIMD) while the
+// Default groups: at least about 2048 waves per launch (2 per SIMD) while the
 // general rule gives fewer, at most a group per 8 snapshots.
 int snap_groups(const okr_handle* h, int k, int nz, int* spg) {
   const int S = h->S;
@@ -267,7 +269,7 @@ int snap_groups(const okr_handle* h, int k, int nz, int* spg) {
   if (SG <= 0) {
     SG = score64_groups_default(k, S, spg);
     const int64_t waves = (int64_t)((((uint64_t)1 << k) + kScoreBlock - 1) / kScoreBlock) * score_ws(h, k, nz) * nz;
-    const int want = (int)std::min<int64_t>(std::max(1, S / 8), (4096 + waves - 1) / waves);
+    const int want = (int)std::min<int64_t>(std::max(1, S / 8), (2048 + waves - 1) / waves);
     SG = std::max(SG, want);
   }
   SG = std::min(std::min(SG, S), kMaxSnapGroups);
