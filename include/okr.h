@@ -81,11 +81,13 @@ extern "C" {
 #define OKR_FLAG_DUMP_SCORES 4u /* keep every segment's per-mask (e, slack) for
                                    okr_dump_scores() */
 #define OKR_FLAG_AUTOTUNE 16u  /* before this call's search, run the search
-                                  once per candidate snapshot-group count
-                                  of the scoring launch (1, 2, 4, ... 32,
-                                  within the planned workspace), keep the
-                                  fastest per segment size in the handle for
-                                  this and later calls */
+                                  once per candidate shape of the FP64
+                                  scoring launch (snapshots per pass 1, 2 or
+                                  4; waves per 64 masks 1, 2 or 4; snapshot
+                                  groups 1, 2, 4, ... 32 within the planned
+                                  workspace) and keep the fastest per segment
+                                  size and chunk width in the handle for this
+                                  and later calls */
 #define OKR_FLAG_GRAPH 8u      /* capture the whole search (load flow, every
                                   segment, final outputs) as one hipGraph on
                                   the first call and replay it afterwards;
@@ -225,17 +227,32 @@ typedef struct {
 } okr_result;
 
 /* One handle per HIP stream (hip_stream may be NULL for the null stream).
- * The handle holds only host metadata. */
+ * The handle holds only host metadata (no paper passage: bookkeeping). */
 int okr_create(okr_handle **h, void *hip_stream);
 
-/* Validate the topology and report the device workspace size for S
- * snapshots, plus the output sizes. */
+/* Validate the topology of the three-phase radial network (Section II.A: a
+ * tree rooted at the slack, phase sets shrinking from parent to child, the
+ * eligible nodes the reduction may remove) and the segments (the candidate
+ * set of Section IV's search taken per segment: every subset of a segment's
+ * eligible nodes), group independent segments into launch chunks, and report
+ * the device workspace size for S snapshots plus the output sizes.  HOST
+ * only; OKR_E_NOT_TREE / OKR_E_PHASE / OKR_E_UNSUPPORTED / OKR_E_ARG on
+ * invalid input. */
 int okr_plan(okr_handle *h, const okr_topology *topo, const okr_margins *mg,
              int32_t S, size_t *workspace_bytes, okr_sizes *sizes);
 
-/* The search.  topo must be the planned topology; d_workspace (DEVICE) must
- * hold workspace_bytes >= the planned size.  Synchronous on the handle's
- * stream: outputs are complete in `out` on return. */
+/* The search (Section IV, Algorithm 1 generalised to every subset of each
+ * segment's eligible nodes): the scenario library by AC load flow (Section
+ * III, library L) unless V^ is given; per segment and mask, the assignment
+ * and current aggregation (Section II.C, eq. i_agg), the Kron-reduced
+ * network (Section II.B, eq. Y_kron) and its fixed-current solve with
+ * reduced nodes copying their super-node's voltage (Algorithm 1), the error
+ * (eq. iter_obj) and margins (eq. v_abs and the voltage band), the
+ * lexicographic arg-min; after the last segment the reduced network's
+ * blocks (eq. Y_kron) and per-snapshot errors.  topo must be the planned
+ * topology; d_workspace (DEVICE) must hold workspace_bytes >= the planned
+ * size (OKR_E_WORKSPACE otherwise).  Synchronous on the handle's stream:
+ * outputs are complete in `out` on return. */
 int okr_reduce_feeder(okr_handle *h, const okr_yblocks *Y, const okr_topology *topo,
                       const okr_loads *loads, const okr_margins *mg,
                       void *d_workspace, size_t workspace_bytes, okr_result *out);
@@ -259,11 +276,14 @@ int okr_reduce_feeder(okr_handle *h, const okr_yblocks *Y, const okr_topology *t
 int okr_reduce_feeder_noalloc(okr_handle *h, const okr_yblocks *Y, const okr_topology *topo,
                               const okr_loads *loads, const okr_margins *mg, okr_result *out);
 
-/* With OKR_FLAG_DUMP_SCORES: copy segment `segment`'s per-mask error and band
- * slack from the last call (HOST double[2^k] each) and return k through *k. */
+/* With OKR_FLAG_DUMP_SCORES: copy segment `segment`'s per-mask error over
+ * the affected nodes (eq. iter_obj) and band slack from the last call (HOST
+ * double[2^k] each) and return k through *k. */
 int okr_dump_scores(okr_handle *h, int32_t segment, double *e, double *slack, int32_t *k);
 
-/* Surrogate MLP (learned pruning).  Parameters are one FP32 buffer in
+/* Surrogate MLP (learned pruning; not in the paper, which scores every
+ * candidate: a ranking that lets okr_reduce_feeder rescore only the top_k
+ * masks exactly, full enumeration as fallback).  Parameters are one FP32 buffer in
  * [out][in] layout: W1[256][32] b1[256] W2[256][256] b2[256] w3[256] b3[1]
  * (OKR_SURR_PARAMS floats).  The network maps 32 per-mask features (from
  * okr_result.features) through two GELU layers to y = ln(e_loc + 1e-12); its
