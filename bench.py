@@ -217,6 +217,46 @@ def modes_section(f, args, trained):
     return modes
 
 
+def fullsize_section(seed, reps=3):
+    """Time-to-optimal of the whole search on the 6000-node feeder (96
+    snapshots, segments of 8-18 eligible nodes) and the 8400-node feeder (288
+    snapshots, segments of 8-20), plain FP64 and mixed precision, each as one
+    captured graph (launch shapes from the library's defaults); with the
+    launch structure of the search (chunks of independent segments, one
+    scoring launch each) and, from a stream-launched timed run, the wall time
+    of the search against the time inside its scoring launches."""
+    import torch
+    from paper_2510_19608_amd import Reducer
+    from synth_feeders import make_feeder
+    out = {}
+    for name, cfg in (("c3_6000node_96snap", "c3"), ("c4_8400node_288snap", "c4")):
+        f = make_feeder(cfg, seed)
+        e = dict(e_bar=f["e_bar"], n=int(f["n"]), snapshots=int(f["S_load"].shape[0]))
+        ref = None
+        for prec in ("fp64", "mixed"):
+            R = Reducer(f, device="cuda:0", graph=True, precision=prec)
+            ms = timed_runs(R, reps, False)
+            masks, pops, res = decisions(R)
+            ncand = int(R.sizes.n_candidates)
+            R.close()
+            if ref is None:
+                ref = masks
+                e.update(segments=len(masks), n_candidates=ncand,
+                         scoring_launches=int(res["n_score_launches"]),
+                         segments_below_top_level=sum(1 for s in res["segments"] if s["popcount"] < s["k"]))
+            e[prec] = dict(time_to_optimal_ms=ms, candidates_per_s=ncand / (ms * 1e-3),
+                           agreement=sum(a == b for a, b in zip(masks, ref)) / max(len(ref), 1),
+                           n_kept=int(res["n_kept"]), max_err=res["max_err"])
+        R = Reducer(f, device="cuda:0", timing=True)
+        R.run(replan=False)
+        R.run(replan=False)
+        torch.cuda.synchronize()
+        e["stream_timed"] = dict(search_ms=R.res.t_search_ms, scoring_kernels_ms=R.res.score_kernel_ms)
+        R.close()
+        out[name] = e
+    return out
+
+
 GREEDY_SIZES = (100, 300, 500, 1000)
 
 
@@ -366,6 +406,10 @@ def main():
     ap.add_argument("--no-c5", action="store_true", help="skip the surrogate run on the 6000-node feeder")
     ap.add_argument("--no-greedy", action="store_true", help="skip the Algorithm 1 greedy-search section")
     ap.add_argument("--no-sweep", action="store_true", help="skip the e_bar sweep section")
+    ap.add_argument("--no-fullsize", action="store_true",
+                    help="skip the whole-search timings on the 6000- and 8400-node feeders")
+    ap.add_argument("--fullsize-only", action="store_true",
+                    help="print only the whole-search timings on the 6000- and 8400-node feeders")
     ap.add_argument("--modes", default="plain,mixed,surrogate,factored",
                     help="comma-separated forms timed for time-to-optimal (plain is always timed)")
     ap.add_argument("--lanes", type=int, default=0,
@@ -382,6 +426,10 @@ def main():
         print(json.dumps({"error": "this search runs on one GPU; --gpus above 1 is not supported "
                                    "(segments would shard across GPUs by subtree, see the design notes)"}))
         sys.exit(2)
+
+    if args.fullsize_only:
+        print(json.dumps({"fullsize": fullsize_section(args.seed, args.reps)}))
+        return
 
     all_cores = None if args.no_cpu else cpu_baseline_all_cores(args.seed)
 
@@ -463,12 +511,15 @@ def main():
         line["modes_binding"] = modes_section(make_feeder("c2", args.seed, e_bar=1e-4), args, trained)
         if trained is not None and not args.no_c5:
             # surrogate-pruned search on the 6000-node, 96-snapshot feeder
-            # (trained on the 30- and 1000-node dumps above), at a bound that
-            # binds, against the plain FP64 search of the same feeder
+            # (trained on the 30- and 1000-node dumps above) and mixed
+            # precision, at a bound that binds, against the plain FP64 search
+            # of the same feeder
             args_c5 = argparse.Namespace(**vars(args))
             args_c5.reps = 3
-            args_c5.modes = "surrogate"
+            args_c5.modes = "mixed,surrogate"
             line["c5_surrogate_6000node"] = modes_section(make_feeder("c3", args.seed, e_bar=1e-4), args_c5, trained)
+    if not args.no_fullsize:
+        line["fullsize"] = fullsize_section(args.seed, 3)
     if not args.no_greedy:
         line["greedy_alg1"] = greedy_section(args.seed, cpu=not args.no_cpu)
     if not args.no_sweep:
