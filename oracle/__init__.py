@@ -35,7 +35,7 @@ class Decision(ctypes.Structure):
                 ("mask", ctypes.c_uint32), ("popcount", ctypes.c_int32),
                 ("e_loc", ctypes.c_double), ("e_min", ctypes.c_double),
                 ("ambiguous", ctypes.c_int32), ("n_scored", ctypes.c_int32),
-                ("key_gap", ctypes.c_double)]
+                ("key_gap", ctypes.c_double), ("smice_rise", ctypes.c_double)]
 
 
 _lib = None
@@ -119,7 +119,7 @@ def score_masks(f, Vhat, Ihat, keep_before, g, masks):
     keep = np.ascontiguousarray(keep_before, dtype=np.uint8)
     masks = np.ascontiguousarray(masks, dtype=np.uint32)
     m = len(masks)
-    out = {k: np.zeros(m) for k in ("e_glob", "e_loc", "slack_glob", "slack_loc")}
+    out = {k: np.zeros(m) for k in ("e_glob", "e_loc", "slack_glob", "slack_loc", "smice")}
     feas = np.zeros(m, dtype=np.int32)
     nS, n = Vhat.shape[0], Vhat.shape[1]
     st = lib().okro_score_masks(
@@ -128,7 +128,7 @@ def score_masks(f, Vhat, Ihat, keep_before, g, masks):
         _p(masks), ctypes.c_int(m), ctypes.c_double(f["e_bar"]),
         ctypes.c_double(f["v_min"]), ctypes.c_double(f["v_max"]),
         _p(out["e_glob"]), _p(out["e_loc"]), _p(out["slack_glob"]), _p(out["slack_loc"]),
-        _p(feas))
+        _p(feas), _p(out["smice"]))
     if st != OK:
         raise RuntimeError(f"okro_score_masks failed: {st}")
     out["feasible"] = feas.astype(bool)
@@ -148,8 +148,11 @@ def omega(f, keep, g):
     return om.astype(bool)
 
 
-def search(f, Vhat, Ihat, tie_tol=1e-11, amb_tol=1e-13, mode=1):
-    """Full segment-exhaustive search.  Returns (keep, decisions, status)."""
+def search(f, Vhat, Ihat, tie_tol=1e-11, amb_tol=1e-13, mode=1, secondary="maxerr", smice_tol=1e-9):
+    """Full segment-exhaustive search.  Returns (keep, decisions, status).
+    secondary: the key among the most-reducing feasible masks, "maxerr"
+    (eq. iter_obj) or "smice" (Algorithm 1's sum of MICE)."""
+    sec = {"maxerr": 0, "smice": 1}[secondary]
     parent, phase, segment, Yd, Yo = _net(f)
     Vhat = np.ascontiguousarray(Vhat, dtype=np.complex128)
     Ihat = np.ascontiguousarray(Ihat, dtype=np.complex128)
@@ -164,12 +167,14 @@ def search(f, Vhat, Ihat, tie_tol=1e-11, amb_tol=1e-13, mode=1):
         ctypes.c_int(nS), _p(Vhat), _p(Ihat), _p(V0), ctypes.c_double(f["e_bar"]),
         ctypes.c_double(f["v_min"]), ctypes.c_double(f["v_max"]),
         ctypes.c_double(tie_tol), ctypes.c_double(amb_tol), ctypes.c_int(mode),
-        _p(keep), dec, ctypes.c_int(max(nseg_max, 1)), ctypes.byref(nseg))
+        ctypes.c_int(sec), ctypes.c_double(smice_tol), _p(keep), dec, ctypes.c_int(max(nseg_max, 1)),
+        ctypes.byref(nseg))
     if st < 0:
         raise RuntimeError(f"okro_search failed: {st}")
     decs = [dict(segment=d.segment, k=d.k, mask=d.mask, popcount=d.popcount,
                  e_loc=d.e_loc, e_min=d.e_min, ambiguous=bool(d.ambiguous),
-                 n_scored=d.n_scored, key_gap=d.key_gap) for d in list(dec)[:nseg.value]]
+                 n_scored=d.n_scored, key_gap=d.key_gap, smice_rise=d.smice_rise)
+            for d in list(dec)[:nseg.value]]
     return keep, decs, st
 
 

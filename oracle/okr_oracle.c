@@ -545,6 +545,7 @@ typedef struct {
 
 typedef struct {
     double e_glob, e_loc, slack_glob, slack_loc;
+    double smice; /* sum over snapshots and clusters of the cluster's largest error */
     int feasible;
 } okro_score;
 
@@ -557,6 +558,7 @@ typedef struct {
     cx *Iagg;        /* work */
     int *sup;
     uint8_t *omega;  /* work: node in Omega_g */
+    double *mice;    /* work [n]: MICE of the cluster whose super-node is i */
 } okro_ctx;
 
 /* Omega_g: for every e in the segment, c(e) is the highest node on e's root
@@ -607,7 +609,11 @@ int okro_omega(int n, const int32_t *parent, const uint8_t *phase,
 /* Score one kept set: errors per eq. (iter_obj) / Algorithm 1
  * (e = ||V^|-|V^c|| per node-phase-snapshot), the E_bar bound (eq. v_abs,
  * inclusive) and the voltage band on every node-phase.  Globals run over all
- * nodes; locals over Omega_g (slack_loc over the kept nodes in Omega_g). */
+ * nodes; locals over Omega_g (slack_loc over the kept nodes in Omega_g).
+ * SMICE (Algorithm 1's selection key, MICE of Section II.C): per snapshot,
+ * every kept node's cluster (itself and the nodes whose super-node it is)
+ * contributes its largest error over members and phases; summed over the
+ * clusters and the snapshots. */
 static int score_keepset(okro_ctx *C, const uint8_t *keep2, const uint8_t *omega,
                          const okro_margins *mg, okro_score *out)
 {
@@ -625,8 +631,9 @@ static int score_keepset(okro_ctx *C, const uint8_t *keep2, const uint8_t *omega
     st = solve_reduced(N, M, C->Iagg, C->V0, S, C->Vc);
     sp_free(M);
     if (st != OKRO_OK) return st;
-    double eg = 0, el = 0, sg = INFINITY, sl = INFINITY;
-    for (int l = 0; l < S; ++l)
+    double eg = 0, el = 0, sg = INFINITY, sl = INFINITY, smice = 0;
+    for (int l = 0; l < S; ++l) {
+        for (int i = 0; i < n; ++i) C->mice[i] = 0.0;
         for (int i = 0; i < n; ++i) {
             int s = C->sup[i];
             for (int p = 0; p < 3; ++p) {
@@ -636,13 +643,18 @@ static int score_keepset(okro_ctx *C, const uint8_t *keep2, const uint8_t *omega
                 double sk = fmin(mag - mg->v_min, mg->v_max - mag);
                 if (e > eg) eg = e;
                 if (sk < sg) sg = sk;
+                if (e > C->mice[s]) C->mice[s] = e;
                 if (omega[i]) {
                     if (e > el) el = e;
                     if (keep2[i] && sk < sl) sl = sk;
                 }
             }
         }
+        for (int i = 0; i < n; ++i)
+            if (C->sup[i] == i) smice += C->mice[i];
+    }
     out->e_glob = eg; out->e_loc = el; out->slack_glob = sg; out->slack_loc = sl;
+    out->smice = smice;
     out->feasible = (eg <= mg->e_bar) && (sg >= 0.0);
     return OKRO_OK;
 }
@@ -660,13 +672,14 @@ static okro_ctx *ctx_new(okro_net *N, int S, const double *Vhat, const double *I
     C->Iagg = (cx *)malloc(sizeof(cx) * (size_t)S * n * 3);
     C->sup = (int *)malloc(sizeof(int) * (size_t)n);
     C->omega = (uint8_t *)malloc((size_t)n);
+    C->mice = (double *)malloc(sizeof(double) * (size_t)n);
     return C;
 }
 
 static void ctx_free(okro_ctx *C)
 {
     if (!C) return;
-    free(C->absVhat); free(C->Vc); free(C->Iagg); free(C->sup); free(C->omega);
+    free(C->absVhat); free(C->Vc); free(C->Iagg); free(C->sup); free(C->omega); free(C->mice);
     free(C);
 }
 
@@ -689,7 +702,7 @@ int okro_score_masks(int n, const int32_t *parent, const uint8_t *phase,
                      const uint8_t *keep_before, int g, const uint32_t *masks, int nmask,
                      double e_bar, double v_min, double v_max,
                      double *e_glob, double *e_loc, double *slack_glob,
-                     double *slack_loc, int32_t *feasible)
+                     double *slack_loc, int32_t *feasible, double *smice)
 {
     int st;
     okro_net *N = net_new(n, parent, phase, segment, Ydiag, Yoff, &st);
@@ -709,6 +722,7 @@ int okro_score_masks(int n, const int32_t *parent, const uint8_t *phase,
         e_glob[q] = sc.e_glob; e_loc[q] = sc.e_loc;
         slack_glob[q] = sc.slack_glob; slack_loc[q] = sc.slack_loc;
         feasible[q] = sc.feasible;
+        if (smice) smice[q] = sc.smice;
     }
     free(keep2); free(nodes); ctx_free(C); net_free(N);
     return st;
@@ -721,7 +735,9 @@ typedef struct {
     int32_t popcount;
     double e_loc, e_min;
     int32_t ambiguous, n_scored;
-    double key_gap; /* smallest e_loc above the tie window at the chosen level, minus e_min (inf if none) */
+    double key_gap; /* margin of the decision under the selection key: the smallest key above
+                       the tie window at the chosen level minus the smallest key (inf if none) */
+    double smice_rise; /* SMICE of the chosen mask minus SMICE of mask 0 (nothing reduced) */
 } okro_decision;
 
 static int popc(uint32_t m) { int c = 0; while (m) { m &= m - 1; ++c; } return c; }
@@ -731,12 +747,16 @@ static int popc(uint32_t m) { int c = 0; while (m) { m &= m - 1; ++c; } return c
  *    by the earlier ones (Algorithm 1's "assign previously reduced" and
  *    I <- A I^);
  *  - feasible <=> e_glob <= E_bar and v_min <= |V^c| <= v_max everywhere;
- *  - objective: most reduced nodes, then smallest e_loc (eq. iter_obj over
- *    Omega_g), then lowest mask; masks with e_loc <= e_min + tie_tol tie;
+ *  - objective: most reduced nodes, then the smallest key, then lowest mask.
+ *    secondary 0: the key is e_loc (eq. iter_obj over Omega_g), masks with
+ *    e_loc <= e_min + tie_tol tie; secondary 1: the key is SMICE over the
+ *    whole network (Algorithm 1's selection), masks within smice_tol of the
+ *    smallest tie;
  *  - a segment is flagged ambiguous when a feasible mask at the chosen level
- *    has e_loc within amb_tol of e_min + tie_tol, or a mask at that level or
- *    above has e_loc or its band slack over Omega_g within amb_tol of the
- *    E_bar or band boundary.
+ *    has its key within the ambiguity window (amb_tol for e_loc, smice_tol /
+ *    100 for SMICE) of the tie-window edge, or a mask at that level or above
+ *    has e_loc or its band slack over Omega_g within amb_tol of the E_bar or
+ *    band boundary.
  * mode 0 scores all 2^k masks; mode 1 scores levels from popcount k down and
  * stops after the first level holding a feasible mask (same decision).
  * Returns OKRO_W_BASE_OUT_OF_BAND (and reduces nothing) when the full
@@ -745,8 +765,9 @@ int okro_search(int n, const int32_t *parent, const uint8_t *phase,
                 const int32_t *segment, const double *Ydiag, const double *Yoff,
                 int S, const double *Vhat, const double *Ihat, const double *V0,
                 double e_bar, double v_min, double v_max, double tie_tol,
-                double amb_tol, int mode, uint8_t *keep_out,
-                okro_decision *dec, int max_segments, int *n_segments_out)
+                double amb_tol, int mode, int secondary, double smice_tol,
+                uint8_t *keep_out, okro_decision *dec, int max_segments,
+                int *n_segments_out)
 {
     int st;
     okro_net *N = net_new(n, parent, phase, segment, Ydiag, Yoff, &st);
@@ -775,6 +796,7 @@ int okro_search(int n, const int32_t *parent, const uint8_t *phase,
         omega_of_segment(N, keep_out, g, nodes, k, C->omega);
         uint32_t nm = 1u << k;
         double *el = (double *)malloc(sizeof(double) * nm);
+        double *sm = (double *)malloc(sizeof(double) * nm);
         int8_t *fe = (int8_t *)malloc(nm);
         int8_t *near = (int8_t *)malloc(nm);
         uint8_t *done = (uint8_t *)calloc(nm, 1);
@@ -791,6 +813,7 @@ int okro_search(int n, const int32_t *parent, const uint8_t *phase,
                 ++nscored;
                 done[m] = 1;
                 el[m] = sc.e_loc;
+                sm[m] = sc.smice;
                 fe[m] = (int8_t)sc.feasible;
                 int robust_in = sc.e_loc <= e_bar - amb_tol && sc.slack_loc >= amb_tol;
                 int robust_out = sc.e_loc > e_bar + amb_tol || sc.slack_loc < -amb_tol;
@@ -799,15 +822,32 @@ int okro_search(int n, const int32_t *parent, const uint8_t *phase,
             }
             if (mode == 1 && best_level >= 0) break;
         }
+        /* mask 0 (nothing of the segment reduced), for the SMICE rise */
+        double smice0 = 0.0;
+        if (st == OKRO_OK) {
+            if (done[0]) smice0 = sm[0];
+            else {
+                okro_score sc;
+                st = score_keepset(C, keep_out, C->omega, &mg, &sc);
+                smice0 = sc.smice;
+            }
+        }
         if (st == OKRO_OK) {
             D->n_scored = nscored;
             if (best_level < 0) {
                 D->mask = 0; D->popcount = 0; D->e_loc = el[0]; D->e_min = el[0];
-                D->ambiguous = 1; D->key_gap = INFINITY;
+                D->ambiguous = 1; D->key_gap = INFINITY; D->smice_rise = 0.0;
             } else {
-                double emin = INFINITY;
+                /* the selection key of every feasible mask of the chosen level */
+                const double *key = secondary ? sm : el;
+                const double tol = secondary ? smice_tol : tie_tol;
+                const double atol = secondary ? smice_tol / 100.0 : amb_tol;
+                double emin = INFINITY, kmin = INFINITY;
                 for (uint32_t m = 0; m < nm; ++m)
-                    if (done[m] && fe[m] && popc(m) == best_level && el[m] < emin) emin = el[m];
+                    if (done[m] && fe[m] && popc(m) == best_level) {
+                        if (el[m] < emin) emin = el[m];
+                        if (key[m] < kmin) kmin = key[m];
+                    }
                 uint32_t pick = 0;
                 int found = 0, amb = 0;
                 for (uint32_t m = 0; m < nm; ++m) {
@@ -815,23 +855,24 @@ int okro_search(int n, const int32_t *parent, const uint8_t *phase,
                     int pc = popc(m);
                     if (pc >= best_level && near[m]) amb = 1;
                     if (pc != best_level || !fe[m]) continue;
-                    if (fabs(el[m] - (emin + tie_tol)) <= amb_tol) amb = 1;
-                    if (!found && el[m] <= emin + tie_tol) { pick = m; found = 1; }
+                    if (fabs(key[m] - (kmin + tol)) <= atol) amb = 1;
+                    if (!found && key[m] <= kmin + tol) { pick = m; found = 1; }
                 }
                 /* the margin of the decision: the best feasible mask of the
                  * chosen level outside the tie window */
                 double runner = INFINITY;
                 for (uint32_t m = 0; m < nm; ++m)
-                    if (done[m] && fe[m] && popc(m) == best_level && el[m] > emin + tie_tol && el[m] < runner)
-                        runner = el[m];
+                    if (done[m] && fe[m] && popc(m) == best_level && key[m] > kmin + tol && key[m] < runner)
+                        runner = key[m];
                 D->mask = pick; D->popcount = best_level; D->e_loc = el[pick];
                 D->e_min = emin; D->ambiguous = amb;
-                D->key_gap = runner - emin;
+                D->key_gap = runner - kmin;
+                D->smice_rise = sm[pick] - smice0;
                 for (int j = 0; j < k; ++j)
                     if (pick >> j & 1u) keep_out[nodes[j]] = 0;
             }
         }
-        free(el); free(fe); free(near); free(done);
+        free(el); free(sm); free(fe); free(near); free(done);
     }
     free(nodes); free(keep2); ctx_free(C); net_free(N);
     if (st != OKRO_OK) return st;

@@ -175,9 +175,17 @@ def score(f, Vhat, Ihat, keep2, om, route=vc_full_route):
     slack = np.minimum(mag - f["v_min"], f["v_max"] - mag)
     slack[:, ~pres] = np.inf
     kept_om = om & keep2.astype(bool)
+    # SMICE: per snapshot, the largest error of each cluster (a kept node and
+    # the nodes assigned to it, over their phases), summed over clusters
+    sup = super_of(f["parent"], keep2)
+    node_err = err.max(axis=2)                      # [S, n]
+    mice = np.zeros((err.shape[0], n))
+    for i in range(n):
+        mice[:, sup[i]] = np.maximum(mice[:, sup[i]], node_err[:, i])
     return dict(e_glob=err.max(), e_loc=err[:, om].max(initial=0.0),
                 slack_glob=slack.min(), slack_loc=slack[:, kept_om].min(initial=np.inf),
-                feasible=bool(err.max() <= f["e_bar"] and slack.min() >= 0))
+                feasible=bool(err.max() <= f["e_bar"] and slack.min() >= 0),
+                smice=float(mice.sum()))
 
 
 def seg_nodes(f, g):
@@ -186,10 +194,11 @@ def seg_nodes(f, g):
     return [int(v) for v in order if f["segment"][v] == g]
 
 
-def brute_search(f, Vhat, Ihat, tie_tol=1e-11):
+def brute_search(f, Vhat, Ihat, tie_tol=1e-11, secondary="maxerr", smice_tol=1e-9):
     """Exhaustive search over every mask of every segment, in segment order,
-    with the lexicographic objective (most reduced, then smallest e_loc,
-    then lowest mask; e_loc within tie_tol of the minimum ties)."""
+    with the lexicographic objective (most reduced, then the smallest key,
+    then lowest mask): the key is e_loc (ties within tie_tol) or, with
+    secondary="smice", SMICE (ties within smice_tol)."""
     n = f["n"]
     keep = np.ones(n, dtype=np.uint8)
     masks = []
@@ -205,11 +214,13 @@ def brute_search(f, Vhat, Ihat, tie_tol=1e-11):
                 if m >> j & 1:
                     keep2[nodes[j]] = 0
             sc = score(f, Vhat, Ihat, keep2, om)
-            rows.append((m, bin(m).count("1"), sc["e_loc"], sc["feasible"]))
+            key = sc["smice"] if secondary == "smice" else sc["e_loc"]
+            rows.append((m, bin(m).count("1"), key, sc["feasible"]))
+        tol = smice_tol if secondary == "smice" else tie_tol
         feas = [r for r in rows if r[3]]
         best = max(r[1] for r in feas)
         emin = min(r[2] for r in feas if r[1] == best)
-        pick = min(r[0] for r in feas if r[1] == best and r[2] <= emin + tie_tol)
+        pick = min(r[0] for r in feas if r[1] == best and r[2] <= emin + tol)
         masks.append(pick)
         for j in range(k):
             if pick >> j & 1:

@@ -243,15 +243,17 @@ def test_hand_example_three_node_chain(oracle_lib):
 
 # --------------------------------------------------------------- search --
 
+@pytest.mark.parametrize("secondary", ["maxerr", "smice"])
 @pytest.mark.parametrize("seed,e_bar", [(0, 3e-4), (1, 1e-4), (2, 3e-4), (3, 1e-3), (4, 2e-4), (5, 3e-3)])
-def test_search_matches_dense_brute_force(oracle_lib, seed, e_bar):
+def test_search_matches_dense_brute_force(oracle_lib, seed, e_bar, secondary):
     """Every mask of every segment of a tiny feeder, scored with the dense
-    full-network route, picks the same aggregation as the oracle."""
+    full-network route, picks the same aggregation as the oracle, under
+    either selection key."""
     f = tiny(seed, n=11, snapshots=2, scale=(0.3, 1.0), e_bar=e_bar)
     V, I, st, _ = oracle_lib.powerflow(f)
-    keep_b, masks_b = dc.brute_search(f, V, I)
+    keep_b, masks_b = dc.brute_search(f, V, I, secondary=secondary)
     for mode in (0, 1):
-        keep, dec, st = oracle_lib.search(f, V, I, mode=mode)
+        keep, dec, st = oracle_lib.search(f, V, I, mode=mode, secondary=secondary)
         assert st == 0
         assert [d["mask"] for d in dec] == masks_b
         assert not any(d["ambiguous"] for d in dec)
@@ -510,3 +512,107 @@ def test_key_gap_is_the_runner_up_margin(oracle_lib, seed):
     got = dec[0]["key_gap"]
     assert (np.isinf(want) and np.isinf(got)) or got == want
     assert got >= 0.0
+
+
+# ---------------------------------------------------------------- SMICE --
+
+def _leaf_pairs(f):
+    """(leaf, parent) pairs with the parent off the slack."""
+    par = f["parent"]
+    nch = np.bincount(par[1:], minlength=f["n"])
+    return [(int(i), int(par[i])) for i in range(1, f["n"]) if nch[i] == 0 and par[i] > 0]
+
+
+def _leaf_err(V, r, s, phase_r):
+    """Per snapshot: the largest over r's phases of ||V^_r| - |V^_s||, the
+    error of leaf r once its load moves to s (nothing else moves: every other
+    node shares its whole root path with s, so the moved current changes no
+    other voltage, and s's own voltage stays V^_s)."""
+    ph = [p for p in range(3) if phase_r >> p & 1]
+    return np.abs(np.abs(V[:, r, ph]) - np.abs(V[:, s, ph])).max(axis=1)
+
+
+def test_smice_closed_forms(oracle_lib):
+    """SMICE (Algorithm 1, MICE of Section II.C) on reductions whose errors are
+    fixed by the load-flow voltages alone: nothing reduced -> 0 (the full
+    network reproduces V^); one leaf into its parent -> the sum over snapshots
+    of the leaf's error; two sibling leaves into their common parent -> one
+    cluster, the sum of their per-snapshot maximum; two leaves under different
+    parents -> two clusters, the sum of both."""
+    f = make_feeder("c1", 3)
+    V, I, st, _ = oracle_lib.powerflow(f)
+    assert st == 0
+    pairs = _leaf_pairs(f)
+    by_parent = {}
+    for r, s in pairs:
+        by_parent.setdefault(s, []).append(r)
+    sib = next(v for v in by_parent.values() if len(v) >= 2)[:2]
+    r1, r2 = sib
+    s12 = int(f["parent"][r1])
+    ra, rb = next((a, b) for (a, sa) in pairs for (b, sb) in pairs if sa != sb and a < b)
+    keep = np.ones(f["n"], np.uint8)
+
+    def smice_of(nodes, masks):
+        seg = np.full(f["n"], -1, np.int32)
+        seg[sorted(nodes)] = 0
+        return oracle_lib.score_masks(dict(f, segment=seg), V, I, keep, 0, np.asarray(masks, np.uint32))["smice"]
+
+    e1 = _leaf_err(V, r1, s12, f["phase"][r1])
+    e2 = _leaf_err(V, r2, s12, f["phase"][r2])
+    lo, hi = sorted((r1, r2))   # bit j = j-th segment node in DFS preorder (children in index order)
+    sm = smice_of([r1, r2], [0, 1, 2, 3])
+    assert abs(sm[0]) < 1e-12
+    elo, ehi = (e1, e2) if lo == r1 else (e2, e1)
+    np.testing.assert_allclose(sm[1:], [elo.sum(), ehi.sum(), np.maximum(e1, e2).sum()], rtol=1e-9, atol=1e-13)
+    assert np.maximum(e1, e2).sum() < e1.sum() + e2.sum() - 1e-9   # one cluster, not two
+    ea = _leaf_err(V, ra, int(f["parent"][ra]), f["phase"][ra])
+    eb = _leaf_err(V, rb, int(f["parent"][rb]), f["phase"][rb])
+    sm = smice_of([ra, rb], [3])
+    np.testing.assert_allclose(sm, [ea.sum() + eb.sum()], rtol=1e-9, atol=1e-13)
+
+
+@pytest.mark.parametrize("seed", [0, 1, 2, 3])
+def test_smice_scores_and_rise_match_dense(oracle_lib, seed):
+    """Per-mask SMICE of the oracle equals the dense full-network route's on
+    every mask of the first segment of a tiny feeder, and each decision's
+    SMICE rise is the chosen mask's SMICE minus mask 0's at that state."""
+    f = tiny(seed, n=11, snapshots=2, scale=(0.3, 1.0), e_bar=3e-4)
+    V, I, st, _ = oracle_lib.powerflow(f)
+    keep = np.ones(f["n"], np.uint8)
+    k = int((f["segment"] == 0).sum())
+    nodes = dc.seg_nodes(f, 0)
+    om = dc.omega(f, keep, 0)
+    got = oracle_lib.score_masks(f, V, I, keep, 0, np.arange(1 << k))["smice"]
+    for m in range(1 << k):
+        keep2 = keep.copy()
+        for j in range(k):
+            if m >> j & 1:
+                keep2[nodes[j]] = 0
+        assert abs(got[m] - dc.score(f, V, I, keep2, om)["smice"]) < 1e-12
+    keep_s, dec, st = oracle_lib.search(f, V, I, secondary="smice")
+    state = np.ones(f["n"], np.uint8)
+    for d in dec:
+        sc = oracle_lib.score_masks(f, V, I, state, d["segment"], np.array([0, d["mask"]], np.uint32))
+        assert abs(d["smice_rise"] - (sc["smice"][1] - sc["smice"][0])) < 1e-12
+        for j, v in enumerate(dc.seg_nodes(f, d["segment"])):
+            if d["mask"] >> j & 1:
+                state[v] = 0
+
+
+def test_smice_key_changes_decisions(oracle_lib):
+    """The two keys differ somewhere: on the 30-bus feeders at a bound that
+    binds, some segment's SMICE choice is not its smallest-maximum-error
+    choice, and it never has a larger SMICE nor a smaller maximum error."""
+    differ = 0
+    for seed in range(8):
+        f = make_feeder("c1", seed, e_bar=3e-4)
+        V, I, st, _ = oracle_lib.powerflow(f)
+        _, dm, _ = oracle_lib.search(f, V, I)
+        _, ds, _ = oracle_lib.search(f, V, I, secondary="smice")
+        if dm[0]["mask"] != ds[0]["mask"] and dm[0]["popcount"] == ds[0]["popcount"]:
+            differ += 1
+            keep = np.ones(f["n"], np.uint8)
+            sc = oracle_lib.score_masks(f, V, I, keep, 0, np.array([dm[0]["mask"], ds[0]["mask"]], np.uint32))
+            assert sc["smice"][1] <= sc["smice"][0] + 1e-9
+            assert sc["e_loc"][0] <= sc["e_loc"][1] + 1e-11
+    assert differ >= 2
