@@ -76,6 +76,14 @@ extern "C" {
                                   the scores equal OKR_PRECISION_FP64's bit for
                                   bit */
 
+#define OKR_SECONDARY_MAXERR 0 /* key: the largest error over the affected
+                                  nodes (eq. iter_obj) */
+#define OKR_SECONDARY_SMICE 1  /* key: SMICE, Algorithm 1's selection: per
+                                  snapshot, each cluster's largest member
+                                  error over members and phases (MICE,
+                                  Section II.C), summed over clusters and
+                                  snapshots */
+
 #define OKR_FLAG_TIMING 1u     /* record per-kernel HIP-event timings */
 #define OKR_FLAG_VHAT_GIVEN 2u /* loads->Vhat holds the scenario voltages */
 #define OKR_FLAG_DUMP_SCORES 4u /* keep every segment's per-mask (e, slack) for
@@ -158,6 +166,16 @@ typedef struct {
                                2e-9); a segment whose measured deviation over
                                its rescored masks exceeds it is scored again in
                                FP64 over every mask */
+    int32_t secondary;      /* key among the feasible masks of the most
+                               reducing level: OKR_SECONDARY_MAXERR (0) or
+                               OKR_SECONDARY_SMICE, the latter with
+                               OKR_PRECISION_FP64 or FP64_FACTORED and no
+                               surrogate (OKR_E_UNSUPPORTED otherwise); read by
+                               okr_plan too, which sizes the SMICE buffers */
+    double smice_tol;       /* SMICE: masks within smice_tol of the smallest
+                               SMICE tie, the lowest mask wins (0 = 1e-9); a
+                               candidate within smice_tol / 100 of that window's
+                               edge flags the segment ambiguous */
 } okr_margins;
 
 /* Sizes okr_plan() reports. */
@@ -191,10 +209,14 @@ typedef struct {
                                (shared tables replace the per-candidate
                                voltage-change products; 0 with FACTORED) */
     int32_t score_waves;    /* ... and waves sharing each 64 masks' chains (default rule or autotuned) */
-    double key_gap;         /* margin of the decision: the smallest e_loc of a feasible mask of the chosen
-                               level outside the tie window, minus e_min (+inf if none).  Exact for FP64 and
-                               FP64_FACTORED; MIXED and top_k take it over their FP64-rescored masks, which
-                               can only overstate it */
+    double key_gap;         /* margin of the decision: the smallest key (e_loc, or SMICE with
+                               OKR_SECONDARY_SMICE) of a feasible mask of the chosen level outside the tie
+                               window, minus the smallest (+inf if none).  Exact for FP64 and FP64_FACTORED;
+                               MIXED and top_k take it over their FP64-rescored masks, which can only
+                               overstate it */
+    double smice_rise;      /* OKR_SECONDARY_SMICE: SMICE of the chosen mask minus SMICE of mask 0 (the
+                               error the segment's reduction adds, summed over clusters and snapshots);
+                               NaN with OKR_SECONDARY_MAXERR */
 } okr_segment_result;
 
 /* Outputs (HOST buffers owned by the caller). */

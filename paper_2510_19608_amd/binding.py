@@ -30,6 +30,8 @@ class OKR:
     PRECISION_FP64 = 0
     PRECISION_MIXED = 1
     PRECISION_FP64_FACTORED = 2
+    SECONDARY_MAXERR = 0
+    SECONDARY_SMICE = 1
     FLAG_TIMING = 1
     FLAG_VHAT_GIVEN = 2
     FLAG_DUMP_SCORES = 4
@@ -63,7 +65,8 @@ class Margins(ctypes.Structure):
                 ("tie_tol", ctypes.c_double), ("amb_tol", ctypes.c_double), ("pf_tol", ctypes.c_double),
                 ("pf_maxit", ctypes.c_int32), ("precision", ctypes.c_int32), ("flags", ctypes.c_uint32),
                 ("top_k", ctypes.c_int32), ("surrogate", ctypes.c_void_p), ("lanes", ctypes.c_int32),
-                ("surrogate_margin", ctypes.c_float), ("mixed_delta", ctypes.c_double)]
+                ("surrogate_margin", ctypes.c_float), ("mixed_delta", ctypes.c_double),
+                ("secondary", ctypes.c_int32), ("smice_tol", ctypes.c_double)]
 
 
 class Sizes(ctypes.Structure):
@@ -76,7 +79,8 @@ class SegmentResult(ctypes.Structure):
                 ("ambiguous", ctypes.c_int32), ("n_scored", ctypes.c_int32), ("flops", ctypes.c_double),
                 ("score_ms", ctypes.c_float), ("n_refined", ctypes.c_int32), ("fp32_dev", ctypes.c_double),
                 ("score_groups", ctypes.c_int32), ("score_mpl", ctypes.c_int32), ("chunk", ctypes.c_int32),
-                ("kernel_flops", ctypes.c_double), ("score_waves", ctypes.c_int32), ("key_gap", ctypes.c_double)]
+                ("kernel_flops", ctypes.c_double), ("score_waves", ctypes.c_int32), ("key_gap", ctypes.c_double),
+                ("smice_rise", ctypes.c_double)]
 
 
 class Result(ctypes.Structure):
@@ -275,7 +279,8 @@ def okr_surrogate_forward(params, X, y, work):
 
 def make_margins(f=None, *, e_bar=None, v_min=None, v_max=None, tie_tol=1e-11, amb_tol=1e-13,
                  precision="fp64", timing=False, dump=False, vhat_given=False, graph=False, pf_tol=1e-13,
-                 pf_maxit=100, top_k=0, surrogate=None, lanes=0, surrogate_margin=0.0, mixed_delta=0.0):
+                 pf_maxit=100, top_k=0, surrogate=None, lanes=0, surrogate_margin=0.0, mixed_delta=0.0,
+                 secondary="maxerr", smice_tol=0.0):
     f = f or {}
     flags = (OKR.FLAG_TIMING if timing else 0) | (OKR.FLAG_DUMP_SCORES if dump else 0) | \
             (OKR.FLAG_VHAT_GIVEN if vhat_given else 0) | (OKR.FLAG_GRAPH if graph else 0)
@@ -287,7 +292,9 @@ def make_margins(f=None, *, e_bar=None, v_min=None, v_max=None, tie_tol=1e-11, a
                               "factored": OKR.PRECISION_FP64_FACTORED}[precision],
                    flags=flags, top_k=top_k,
                    surrogate=None if surrogate is None else surrogate.data_ptr(), lanes=lanes,
-                   surrogate_margin=surrogate_margin, mixed_delta=mixed_delta)
+                   surrogate_margin=surrogate_margin, mixed_delta=mixed_delta,
+                   secondary={"maxerr": OKR.SECONDARY_MAXERR, "smice": OKR.SECONDARY_SMICE}[secondary],
+                   smice_tol=smice_tol)
 
 
 class Reducer:
@@ -396,7 +403,7 @@ class Reducer:
                      e_min=s.e_min, ambiguous=bool(s.ambiguous), n_scored=s.n_scored, flops=s.flops,
                      score_ms=s.score_ms, n_refined=s.n_refined, fp32_dev=s.fp32_dev,
                      score_groups=s.score_groups, score_mpl=s.score_mpl, score_waves=s.score_waves, chunk=s.chunk,
-                     key_gap=s.key_gap,
+                     key_gap=s.key_gap, smice_rise=s.smice_rise,
                      kernel_flops=s.kernel_flops)
                 for s in list(self.out_seg)[:self.sizes.n_segments]]
         return dict(super=self.out_super.copy(), kept_parent=self.out_kp.copy(),

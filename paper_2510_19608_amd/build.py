@@ -18,7 +18,7 @@ CSRC = os.path.join(HERE, "csrc")
 OBJ = os.path.join(HERE, "_build")
 LIB = os.path.join(HERE, "libokr.so")
 SOURCES = ["okr_kernels.hip", "okr_build.hip", "okr_score.hip", "okr_mixed.hip", "okr_surrogate.hip",
-           "okr_greedy.hip", "okr_host.cpp"]
+           "okr_greedy.hip", "okr_smice.hip", "okr_host.cpp"]
 FLAGS = [
     "--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC",
     # no packed-FP32 instructions anywhere in the device code

@@ -97,6 +97,14 @@ __global__ void k_topk(const SegHdr*, int, const uint32_t*, const uint32_t*, int
 __global__ void k_surr_decide(const SegHdr*, int, SelParams, const int*, const uint32_t*, const int*,
                               const MaskScore*, DevDecision*, int*);
 __global__ void k_zero_f32(float*, int);
+__global__ void k_smice_prep(const SegHdr*, const int*, size_t, const int*, Topo, State, int*, double*, int);
+__global__ void k_smice_hconst(const SegHdr*, const int*, size_t, Topo, State, const double2*, const double*,
+                               const int*, double*, int);
+__global__ void k_smice_score(const SegHdr*, const int*, size_t, const int*, const double2*, const TargetRec*,
+                              const double2*, const TargetRec*, const int*, const double*, const MaskScore*,
+                              const DevDecision*, SelParams, double*, double*);
+__global__ void k_smice_argmin(const SegHdr*, const int*, size_t, const MaskScore*, const TileRec*, const double*,
+                               const double*, double, DevDecision*);
 }  // namespace okr
 
 using namespace okr;
@@ -108,6 +116,8 @@ constexpr int kMaxLanes = 8;      // segments per chunk (each needs a scratch bl
 constexpr int kDefaultLanes = 8;
 constexpr int kStatusInts = 16;
 constexpr double kMixedDelta = 1e-8;  // bound on |e32 - e64| used by the shortlist
+constexpr double kSmiceTol = 1e-9;    // default SMICE tie window
+constexpr int kSmiceThreadsHost = 128;  // masks per block of the SMICE scoring
 
 size_t align256(size_t x) { return (x + 255) & ~size_t(255); }
 
@@ -157,6 +167,8 @@ struct Layout {
   // surrogate: feature tables (always), ranking buffers (when planned with top_k)
   size_t spz, szs, sss, skeys, slist, sscore, scount, sgates, sW1b, sW2b, sW2tb, slevel,
       sstage;
+  // SMICE key (when planned with it): prep table, fixed head maxima, per-mask SMICE, mask 0's
+  size_t stab, hK, smv, smv0;
   size_t lane0, lane_stride;  // per-lane scratch block (tab .. scount)
   size_t total;
 };
@@ -174,6 +186,7 @@ struct okr_handle {
   // plan
   bool planned = false;
   int n = 0, S = 0, nseg = 0, kmax = 0, nlev = 0, tab_cap = 0, topk = 0;
+  bool smice = false;  // planned with SMICE as the key (its buffers exist)
   int64_t ncand = 0;
   std::vector<int> parent, segment, pre, pos, size, ch_off, ch, lvl_off, lvl_nodes, seg_off, seg_nodes;
   std::vector<uint8_t> phase, eligible;
@@ -412,6 +425,9 @@ extern "C" int okr_plan(okr_handle* h, const okr_topology* topo, const okr_margi
   h->planned = false;
   drop_graph(h);
   if (!topo || !mg || !workspace_bytes || S < 1) OKR_FAIL(h, OKR_E_ARG, "null argument or S < 1");
+  if (mg->secondary != OKR_SECONDARY_MAXERR && mg->secondary != OKR_SECONDARY_SMICE)
+    OKR_FAIL(h, OKR_E_ARG, "unknown secondary key %d", mg->secondary);
+  h->smice = mg->secondary == OKR_SECONDARY_SMICE;
   const int n = topo->n;
   if (n < 1 || !topo->parent || !topo->phase || !topo->eligible || !topo->segment)
     OKR_FAIL(h, OKR_E_ARG, "topology arrays missing or n < 1");
@@ -702,6 +718,13 @@ extern "C" int okr_plan(okr_handle* h, const okr_topology* topo, const okr_margi
     L.sscore = take(sizeof(MaskScore) * std::max(h->topk, 1));
     L.scount = take(sizeof(int) * 4);
   }
+  {
+    const size_t on = h->smice ? 1 : 0;
+    L.stab = take(sizeof(int) * on * ((size_t)SM_ZREC + (size_t)kZrecInts * n));
+    L.hK = take(sizeof(double) * on * (size_t)kMaxK * S);
+    L.smv = take(sizeof(double) * on * ((size_t)1 << h->kmax));
+    L.smv0 = take(sizeof(double) * on);
+  }
   L.lane_stride = off - L.lane0;
   off = L.lane0 + L.lane_stride * (size_t)h->nlanes;
   // per-segment records and shared weights
@@ -758,6 +781,8 @@ struct Ptrs {
   uint32_t *skeys, *slist, *slevel;
   MaskScore* sscore;
   int *scount, *sgates, *sstage;
+  int* stab;
+  double *hK, *smv, *smv0;
 };
 
 // Device pointers, with the scratch block of chunk position `lane`.
@@ -845,6 +870,10 @@ Ptrs pointers(okr_handle* h, void* d_workspace, int lane = 0) {
   p.sW1b = (__bf16*)at(L.sW1b);
   p.sW2b = (__bf16*)at(L.sW2b);
   p.sW2tb = (__bf16*)at(L.sW2tb);
+  p.stab = (int*)at(L.stab);
+  p.hK = (double*)at(L.hK);
+  p.smv = (double*)at(L.smv);
+  p.smv0 = (double*)at(L.smv0);
   return p;
 }
 
@@ -1037,6 +1066,22 @@ void enqueue_search(okr_handle* h, void* ws, const okr_yblocks* Y, const okr_loa
       if (ev) (void)hipEventRecord((*ev)[2 * c + 1], st);
       hipLaunchKernelGGL(k_argmin, dim3(1, 1, nz), dim3(1024), 0, st, (const SegHdr*)q.hdrs, segs, lstride,
                          (const MaskScore*)q.fin, (const TileRec*)q.tiles, sp, (const int*)q.status, q.decs, gates);
+      if (mg->secondary == OKR_SECONDARY_SMICE && !surr) {
+        // SMICE of the feasible masks of the chosen level, and the decision under it
+        hipLaunchKernelGGL(k_smice_prep, dim3(1, 1, nz), dim3(256), 0, st, (const SegHdr*)q.hdrs, segs, lstride,
+                           (const int*)q.tab, q.T, q.St, q.stab, q.hK, S);
+        hipLaunchKernelGGL(k_smice_hconst, dim3(members_blocks, 1, nz), dim3(256), 0, st, (const SegHdr*)q.hdrs, segs,
+                           lstride, q.T, q.St, (const double2*)q.Vcur, (const double*)q.absV, (const int*)q.stab,
+                           q.hK, S);
+        hipLaunchKernelGGL(k_smice_score, dim3((nmask + kSmiceThreadsHost - 1) / kSmiceThreadsHost, 1, nz),
+                           dim3(kSmiceThreadsHost), 0, st, (const SegHdr*)q.hdrs, segs, lstride, (const int*)q.tab,
+                           (const double2*)q.P, (const TargetRec*)q.srec, (const double2*)q.headV,
+                           (const TargetRec*)q.zrec, (const int*)q.stab, (const double*)q.hK,
+                           (const MaskScore*)q.fin, (const DevDecision*)q.decs, sp, q.smv, q.smv0);
+        hipLaunchKernelGGL(k_smice_argmin, dim3(1, 1, nz), dim3(1024), 0, st, (const SegHdr*)q.hdrs, segs, lstride,
+                           (const MaskScore*)q.fin, (const TileRec*)q.tiles, (const double*)q.smv,
+                           (const double*)q.smv0, mg->smice_tol > 0.0 ? mg->smice_tol : kSmiceTol, q.decs);
+      }
       for (int z = 0; z < nz; ++z) {
         const int g = h->chunk_segs[c0 + z];
         const uint32_t nm = 1u << (h->seg_off[g + 1] - h->seg_off[g]);
@@ -1208,6 +1253,15 @@ static int reduce_feeder_impl(okr_handle* h, const okr_yblocks* Y, const okr_top
   if (mg->top_k > 0 && mg->surrogate && mg->top_k > h->topk)
     OKR_FAIL(h, OKR_E_ARG, "top_k %d exceeds the planned %d", mg->top_k, h->topk);
   if (out->targets && mg->precision == OKR_PRECISION_MIXED) OKR_FAIL(h, OKR_E_ARG, "targets need FP64 scores");
+  if (mg->secondary != OKR_SECONDARY_MAXERR && mg->secondary != OKR_SECONDARY_SMICE)
+    OKR_FAIL(h, OKR_E_ARG, "unknown secondary key %d", mg->secondary);
+  if (mg->secondary == OKR_SECONDARY_SMICE) {
+    if (!h->smice) OKR_FAIL(h, OKR_E_ARG, "SMICE as the key needs a plan made with it (okr_margins.secondary)");
+    if (mg->precision == OKR_PRECISION_MIXED || (mg->top_k > 0 && mg->surrogate))
+      OKR_FAIL(h, OKR_E_UNSUPPORTED, "SMICE as the key needs every feasible mask of the chosen level scored in FP64 "
+                                     "(OKR_PRECISION_FP64 or FP64_FACTORED, no surrogate)");
+    if (!(mg->smice_tol >= 0)) OKR_FAIL(h, OKR_E_ARG, "bad smice_tol");
+  }
   const int n = h->n, S = h->S, nseg = h->nseg;
   hipStream_t st = h->stream;
   const Ptrs p = pointers(h, d_workspace);
@@ -1294,7 +1348,7 @@ static int reduce_feeder_impl(okr_handle* h, const okr_yblocks* Y, const okr_top
         bits(mg->v_max), bits(mg->tie_tol), bits(mg->amb_tol), bits(mg->pf_tol), (uint64_t)mg->pf_maxit,
         bits(V0[0].x), bits(V0[0].y), bits(V0[1].x), bits(V0[1].y), bits(V0[2].x), bits(V0[2].y),
         (uint64_t)mg->precision, (uint64_t)(int64_t)mg->top_k, (uint64_t)mg->surrogate,
-        bits((double)mg->surrogate_margin), bits(mg->mixed_delta)};
+        bits((double)mg->surrogate_margin), bits(mg->mixed_delta), (uint64_t)mg->secondary, bits(mg->smice_tol)};
     if (!h->gexec || key != h->gkey) {
       drop_graph(h);
       OKR_HIP(h, hipStreamSynchronize(st));
@@ -1382,6 +1436,7 @@ static int reduce_feeder_impl(okr_handle* h, const okr_yblocks* Y, const okr_top
     R.e_min = decs[g].e_min;
     R.ambiguous = decs[g].ambiguous;
     R.key_gap = decs[g].key_gap;
+    R.smice_rise = mg->secondary == OKR_SECONDARY_SMICE ? decs[g].smice_rise : NAN;
     R.n_scored = 1 << k;
     {
       // launch shape of the segment's chunk (set by its largest segment)

@@ -115,7 +115,8 @@ struct DevDecision {
   double e_min;
   int32_t ambiguous;
   int32_t found;
-  double key_gap;  // smallest e_loc above the tie window at the chosen level, minus e_min (inf if none)
+  double key_gap;  // smallest key above the tie window at the chosen level, minus the smallest (inf if none)
+  double smice_rise;  // with SMICE as the key: SMICE of the chosen mask minus SMICE of mask 0
 };
 
 // Per-mask partial score: max error and min band slack over a snapshot group.
@@ -188,6 +189,14 @@ struct SurrSlot {   // per slot of the segment being ranked
   int nph;          // phases
   int pos;          // position in its chain
 };
+
+// SMICE prep table (int32, per segment): head count, zone-target count, head
+// index of each chain, head nodes, head-inside-Omega flags, first zone target
+// of each chain, then the zone targets [node, entry of phases 0..2 (-1 if
+// absent), head index (-1 if not a head)].
+enum { SM_NH = 0, SM_NZN = 1, SM_CHX = 2, SM_HNODE = SM_CHX + kMaxK, SM_HIN = SM_HNODE + kMaxK,
+       SM_ZOFF = SM_HIN + kMaxK, SM_ZREC = SM_ZOFF + kMaxK + 1 };
+constexpr int kZrecInts = 5;
 
 struct MixedState {  // per segment: the screening levels and shortlist sizes
   int lo_level, hi_level, best, nA, nB, pad;

@@ -262,6 +262,7 @@ __global__ __launch_bounds__(1024) void k_argmin(const SegHdr* __restrict__ hdrs
       DevDecision d;
       d.mask = 0; d.popcount = 0; d.e_loc = 0.0; d.e_min = 0.0; d.ambiguous = 0; d.found = 0;
       d.key_gap = INFINITY;
+      d.smice_rise = 0.0;
       *dec = d;
     }
     return;
@@ -316,9 +317,11 @@ __global__ __launch_bounds__(1024) void k_argmin(const SegHdr* __restrict__ hdrs
     if (best < 0) {
       d.mask = 0; d.popcount = 0; d.e_loc = fin[0].e; d.e_min = fin[0].e; d.ambiguous = 1; d.found = 0;
       d.key_gap = INFINITY;
+      d.smice_rise = 0.0;
     } else {
       d.mask = pick; d.popcount = best; d.e_loc = fin[pick].e; d.e_min = emin; d.ambiguous = amb; d.found = 1;
       d.key_gap = runner - emin;
+      d.smice_rise = 0.0;
     }
     *dec = d;
   }

@@ -269,6 +269,7 @@ __global__ __launch_bounds__(1024) void k_mixed_final(const SegHdr* __restrict__
       d.mask = 0; d.popcount = 0; d.e_loc = 0.0; d.e_min = 0.0; d.ambiguous = skip_segment(H, status) ? 0 : 1;
       d.found = 0;
       d.key_gap = INFINITY;
+      d.smice_rise = 0.0;
       *dec = d;
     }
     return;
@@ -313,6 +314,7 @@ __global__ __launch_bounds__(1024) void k_mixed_final(const SegHdr* __restrict__
     d.ambiguous = amb;
     d.found = pick != 0xffffffffu;
     d.key_gap = runner - emin;
+    d.smice_rise = 0.0;
     *dec = d;
     ms[g].max_dev = dev;
     // the shortlists are complete only while |e32 - e64| <= delta: past the

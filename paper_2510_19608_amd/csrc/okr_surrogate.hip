@@ -646,6 +646,7 @@ __global__ __launch_bounds__(1024) void k_surr_decide(const SegHdr* __restrict__
     d.ambiguous = amb;
     d.found = 1;
     d.key_gap = runner - emin;
+    d.smice_rise = 0.0;
     decs[g] = d;
     *gate = 0;
   }
