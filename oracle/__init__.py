@@ -178,6 +178,70 @@ def search(f, Vhat, Ihat, tie_tol=1e-11, amb_tol=1e-13, mode=1, secondary="maxer
     return keep, decs, st
 
 
+class _RTopology(ctypes.Structure):
+    _fields_ = [("n", ctypes.c_int32), ("parent", ctypes.c_void_p), ("phase", ctypes.c_void_p),
+                ("eligible", ctypes.c_void_p), ("segment", ctypes.c_void_p)]
+
+
+class _RYBlocks(ctypes.Structure):
+    _fields_ = [("Y_diag", ctypes.c_void_p), ("Y_off", ctypes.c_void_p)]
+
+
+class _RLoads(ctypes.Structure):
+    _fields_ = [("S", ctypes.c_int32), ("S_load", ctypes.c_void_p), ("V0", ctypes.c_void_p),
+                ("Vhat", ctypes.c_void_p)]
+
+
+class _RMargins(ctypes.Structure):
+    _fields_ = [("e_bar", ctypes.c_double), ("v_min", ctypes.c_double), ("v_max", ctypes.c_double),
+                ("tie_tol", ctypes.c_double), ("amb_tol", ctypes.c_double), ("pf_tol", ctypes.c_double),
+                ("pf_maxit", ctypes.c_int32), ("secondary", ctypes.c_int32), ("smice_tol", ctypes.c_double)]
+
+
+class _RResult(ctypes.Structure):
+    _fields_ = [("super", ctypes.c_void_p), ("kept_parent", ctypes.c_void_p), ("Yk_diag", ctypes.c_void_p),
+                ("Yk_off", ctypes.c_void_p), ("err_per_snapshot", ctypes.c_void_p), ("Vhat", ctypes.c_void_p),
+                ("seg", ctypes.c_void_p), ("n_segments", ctypes.c_int32), ("n_kept", ctypes.c_int32),
+                ("max_err", ctypes.c_double)]
+
+
+def reduce_feeder(f, vhat=None, tie_tol=1e-11, amb_tol=1e-13, secondary="maxerr", smice_tol=1e-9,
+                  pf_tol=1e-13, pf_maxit=100):
+    """The whole reduction in one call (okr_oracle_reduce_feeder): load flow
+    (or the given scenario voltages), the segment search, the Kron-reduced
+    radial blocks and the final errors, in the result layout of the GPU
+    library's reduce_feeder."""
+    parent, phase, segment, Yd, Yo = _net(f)
+    eligible = np.ascontiguousarray(f.get("eligible", segment >= 0), dtype=np.uint8)
+    S_load = np.ascontiguousarray(f["S_load"], dtype=np.complex128)
+    V0 = np.ascontiguousarray(f["V0"], dtype=np.complex128)
+    nS, n = S_load.shape[0], S_load.shape[1]
+    vh_in = None if vhat is None else np.ascontiguousarray(vhat, dtype=np.complex128)
+    nseg = int(segment.max()) + 1 if len(segment) and segment.max() >= 0 else 0
+    out = dict(super=np.zeros(n, np.int32), kept_parent=np.zeros(n, np.int32),
+               Yk_diag=np.zeros((n, 3, 3), np.complex128), Yk_off=np.zeros((n, 3, 3), np.complex128),
+               err_per_snapshot=np.zeros(nS), Vhat=np.zeros((nS, n, 3), np.complex128))
+    dec = (Decision * max(nseg, 1))()
+    T = _RTopology(n, parent.ctypes.data, phase.ctypes.data, eligible.ctypes.data, segment.ctypes.data)
+    Y = _RYBlocks(Yd.ctypes.data, Yo.ctypes.data)
+    L = _RLoads(nS, S_load.ctypes.data, V0.ctypes.data, None if vh_in is None else vh_in.ctypes.data)
+    M = _RMargins(f["e_bar"], f["v_min"], f["v_max"], tie_tol, amb_tol, pf_tol, pf_maxit,
+                  {"maxerr": 0, "smice": 1}[secondary], smice_tol)
+    R = _RResult(out["super"].ctypes.data, out["kept_parent"].ctypes.data, out["Yk_diag"].ctypes.data,
+                 out["Yk_off"].ctypes.data, out["err_per_snapshot"].ctypes.data, out["Vhat"].ctypes.data,
+                 ctypes.addressof(dec), 0, 0, 0.0)
+    st = lib().okr_oracle_reduce_feeder(ctypes.byref(Y), ctypes.byref(T), ctypes.byref(L), ctypes.byref(M),
+                                        ctypes.byref(R))
+    if st < 0:
+        raise RuntimeError(f"okr_oracle_reduce_feeder failed: {st}")
+    out.update(status=st, n_kept=R.n_kept, max_err=R.max_err,
+               kept=(out["super"] == np.arange(n)).astype(np.uint8),
+               segments=[dict(segment=d.segment, k=d.k, mask=d.mask, popcount=d.popcount, e_loc=d.e_loc,
+                              e_min=d.e_min, ambiguous=bool(d.ambiguous), n_scored=d.n_scored,
+                              key_gap=d.key_gap, smice_rise=d.smice_rise) for d in list(dec)[:R.n_segments]])
+    return out
+
+
 def final_errors(f, Vhat, Ihat, keep):
     parent, phase, _, Yd, Yo = _net(f)
     Vhat = np.ascontiguousarray(Vhat, dtype=np.complex128)

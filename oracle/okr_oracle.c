@@ -902,3 +902,120 @@ int okro_final_errors(int n, const int32_t *parent, const uint8_t *phase,
     }
     return OKRO_OK;
 }
+
+/* ------------------------------------------------------------------ */
+/* The whole reduction in one call, with the argument contents of the  */
+/* GPU library's reduce_feeder (topology, Y blocks, loads, margins in; */
+/* aggregation map, Kron-reduced radial blocks, errors and per-segment */
+/* decisions out), minus its workspace and stream.  The oracle's own   */
+/* structs: it includes no header of the GPU path.                     */
+/* ------------------------------------------------------------------ */
+
+typedef struct {
+    int32_t n;
+    const int32_t *parent;
+    const uint8_t *phase;
+    const uint8_t *eligible;  /* not read: segment[] >= 0 marks the eligible nodes */
+    const int32_t *segment;
+} okro_topology;
+
+typedef struct {
+    const double *Y_diag;  /* [n][3][3] complex128 */
+    const double *Y_off;   /* [n][3][3] complex128, Y_{i,parent(i)} */
+} okro_yblocks;
+
+typedef struct {
+    int32_t S;
+    const double *S_load;  /* [S][n][3] complex128, consumed power */
+    const double *V0;      /* [3] complex128, slack */
+    const double *Vhat;    /* [S][n][3] complex128 scenario voltages, or NULL: load flow */
+} okro_loads;
+
+typedef struct {
+    double e_bar, v_min, v_max, tie_tol, amb_tol, pf_tol;
+    int32_t pf_maxit;
+    int32_t secondary;     /* 0: largest error over Omega_g, 1: SMICE */
+    double smice_tol;      /* 0 = 1e-9 */
+} okro_rmargins;
+
+typedef struct {
+    int32_t *super;            /* [n] nearest kept ancestor (itself when kept) */
+    int32_t *kept_parent;      /* [n] kept parent in the reduced network (-1: reduced or slack) */
+    double *Yk_diag, *Yk_off;  /* [n][3][3] complex128 (zero for reduced nodes) */
+    double *err_per_snapshot;  /* [S] */
+    double *Vhat;              /* [S][n][3] complex128 or NULL */
+    okro_decision *seg;        /* [max(segment) + 1] */
+    int32_t n_segments, n_kept;
+    double max_err;
+} okro_rresult;
+
+int okr_oracle_reduce_feeder(const okro_yblocks *Y, const okro_topology *T,
+                             const okro_loads *L, const okro_rmargins *mg,
+                             okro_rresult *out)
+{
+    if (!Y || !T || !L || !mg || !out || !out->super || !out->kept_parent || !out->Yk_diag ||
+        !out->Yk_off || !out->err_per_snapshot || !out->seg || T->n < 1 || L->S < 1)
+        return OKRO_E_ARG;
+    const int n = T->n, S = L->S;
+    const size_t c3 = (size_t)S * n * 3;
+    double *Vh = (double *)malloc(sizeof(cx) * c3);
+    double *Ih = (double *)malloc(sizeof(cx) * c3);
+    int st = OKRO_OK;
+    if (L->Vhat) {
+        /* injections of the given scenario voltages: -conj(S/V) at every
+         * load node-phase, the slack supplying the rest (Section III) */
+        memcpy(Vh, L->Vhat, sizeof(cx) * c3);
+        const cx *Vc = (const cx *)Vh, *Sl = (const cx *)L->S_load;
+        cx *Ic = (cx *)Ih;
+        for (int l = 0; l < S; ++l) {
+            cx *Il = Ic + (size_t)l * n * 3;
+            for (int q = 0; q < n * 3; ++q) Il[q] = 0.0;
+            for (int i = 1; i < n; ++i)
+                for (int p = 0; p < 3; ++p)
+                    if (T->phase[i] >> p & 1u) {
+                        size_t q = ((size_t)l * n + i) * 3 + p;
+                        Il[i * 3 + p] = -conj(Sl[q] / Vc[q]);
+                    }
+            for (int i = 1; i < n; ++i)
+                for (int p = 0; p < 3; ++p) Il[p] -= Il[i * 3 + p];
+        }
+    } else {
+        int it = 0;
+        st = okro_powerflow(n, T->parent, T->phase, Y->Y_diag, Y->Y_off, S, L->S_load, L->V0,
+                            mg->pf_tol > 0 ? mg->pf_tol : 1e-13, mg->pf_maxit > 0 ? mg->pf_maxit : 100,
+                            Vh, Ih, &it);
+    }
+    uint8_t *keep = (uint8_t *)malloc((size_t)n);
+    int nseg = 0;
+    if (st == OKRO_OK)
+        st = okro_search(n, T->parent, T->phase, T->segment, Y->Y_diag, Y->Y_off, S, Vh, Ih, L->V0,
+                         mg->e_bar, mg->v_min, mg->v_max, mg->tie_tol, mg->amb_tol, 1, mg->secondary,
+                         mg->smice_tol > 0 ? mg->smice_tol : 1e-9, keep, out->seg, n, &nseg);
+    const int warn = st == OKRO_W_BASE_OUT_OF_BAND;
+    if (st >= 0) {
+        double *Vc = (double *)malloc(sizeof(cx) * c3);
+        st = okro_final_errors(n, T->parent, T->phase, Y->Y_diag, Y->Y_off, S, Vh, Ih, L->V0, keep,
+                               out->err_per_snapshot, Vc);
+        free(Vc);
+    }
+    int extra = 0;
+    if (st >= 0) st = okro_kron_blocks(n, T->parent, T->phase, Y->Y_diag, Y->Y_off, keep, out->kept_parent,
+                                       out->Yk_diag, out->Yk_off, &extra);
+    if (st >= 0) {
+        int nk = 0;
+        for (int i = 0; i < n; ++i) {
+            int v = i;
+            while (!keep[v]) v = T->parent[v];
+            out->super[i] = v;
+            nk += keep[i] ? 1 : 0;
+        }
+        out->n_kept = nk;
+        out->n_segments = nseg;
+        out->max_err = 0.0;
+        for (int l = 0; l < S; ++l) out->max_err = fmax(out->max_err, out->err_per_snapshot[l]);
+        if (out->Vhat) memcpy(out->Vhat, Vh, sizeof(cx) * c3);
+    }
+    free(Vh); free(Ih); free(keep);
+    if (st < 0) return st;
+    return warn ? OKRO_W_BASE_OUT_OF_BAND : OKRO_OK;
+}

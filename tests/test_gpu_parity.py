@@ -440,3 +440,29 @@ def test_mixed_reruns_fp64_past_its_bound(okr, seed):
         assert s["n_refined"] >= (1 << s["k"])
         want = next(d["key_gap"] for d in dec if d["segment"] == s["segment"])  # exact again after the re-run
         assert (np.isinf(want) and np.isinf(s["key_gap"])) or abs(s["key_gap"] - want) < TOL
+
+
+@pytest.mark.parametrize("secondary", ["maxerr", "smice"])
+def test_whole_call_against_the_oracle_entry(okr, secondary):
+    """The library's reduce_feeder against the oracle's one-call reduction
+    (okr_oracle_reduce_feeder) on a feeder of several segments: the same
+    result fields, element by element."""
+    _say(f"whole call vs oracle entry, {secondary}")
+    f = make_feeder("c1", 2, n=40, n_eligible=None, seg_size=(4, 7), snapshots=3, scale=(0.3, 1.0), e_bar=3e-4)
+    ref = oracle.reduce_feeder(f, secondary=secondary)
+    out = okr.reduce_feeder(f, secondary=secondary)
+    assert not any(s["ambiguous"] for s in ref["segments"])
+    for key in ("mask", "popcount", "ambiguous", "k"):
+        assert [s[key] for s in out["segments"]] == [s[key] for s in ref["segments"]]
+    for a, b in zip(out["segments"], ref["segments"]):
+        assert abs(a["e_loc"] - b["e_loc"]) < TOL and abs(a["e_min"] - b["e_min"]) < TOL
+        if secondary == "smice":
+            assert abs(a["smice_rise"] - b["smice_rise"]) < 1e-10
+    np.testing.assert_array_equal(out["super"], ref["super"])
+    np.testing.assert_array_equal(out["kept_parent"], ref["kept_parent"])
+    assert out["n_kept"] == ref["n_kept"]
+    np.testing.assert_allclose(out["err_per_snapshot"], ref["err_per_snapshot"], rtol=0, atol=TOL)
+    np.testing.assert_allclose(out["Vhat"], ref["Vhat"], rtol=0, atol=1e-12)
+    scale = np.abs(ref["Yk_diag"]).max()
+    np.testing.assert_allclose(out["Yk_diag"], ref["Yk_diag"], rtol=0, atol=1e-9 * scale)
+    np.testing.assert_allclose(out["Yk_off"], ref["Yk_off"], rtol=0, atol=1e-9 * scale)

@@ -616,3 +616,31 @@ def test_smice_key_changes_decisions(oracle_lib):
             assert sc["smice"][1] <= sc["smice"][0] + 1e-9
             assert sc["e_loc"][0] <= sc["e_loc"][1] + 1e-11
     assert differ >= 2
+
+
+# ------------------------------------------------- one-call reduction --
+
+@pytest.mark.parametrize("secondary", ["maxerr", "smice"])
+def test_one_call_reduction_composes_the_pinned_steps(oracle_lib, secondary):
+    """okr_oracle_reduce_feeder equals its steps called one by one (load
+    flow, search, final errors, Kron blocks), and with the scenario voltages
+    given instead of the load flow it reaches the same reduction."""
+    f = make_feeder("c1", 2, n=40, n_eligible=None, seg_size=(4, 7), snapshots=3, scale=(0.3, 1.0), e_bar=3e-4)
+    out = oracle_lib.reduce_feeder(f, secondary=secondary)
+    V, I, st, _ = oracle_lib.powerflow(f)
+    keep, dec, st = oracle_lib.search(f, V, I, secondary=secondary)
+    assert out["status"] == st == 0
+    assert [s["mask"] for s in out["segments"]] == [d["mask"] for d in dec]
+    assert [s["smice_rise"] for s in out["segments"]] == [d["smice_rise"] for d in dec]
+    np.testing.assert_array_equal(out["kept"], keep)
+    np.testing.assert_array_equal(out["super"], dc.super_of(f["parent"], keep))
+    err, _ = oracle_lib.final_errors(f, V, I, keep)
+    np.testing.assert_array_equal(out["err_per_snapshot"], err)
+    assert out["max_err"] == err.max() and out["n_kept"] == int(keep.sum())
+    kp, Ykd, Yko, _ = oracle_lib.kron_blocks(f, keep)
+    np.testing.assert_array_equal(out["kept_parent"], kp)
+    np.testing.assert_array_equal(out["Yk_diag"], Ykd)
+    np.testing.assert_array_equal(out["Vhat"], V)
+    given = oracle_lib.reduce_feeder(f, vhat=V, secondary=secondary)
+    assert [s["mask"] for s in given["segments"]] == [d["mask"] for d in dec]
+    np.testing.assert_allclose(given["err_per_snapshot"], err, rtol=0, atol=1e-13)
