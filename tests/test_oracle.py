@@ -87,6 +87,37 @@ def test_power_balance_residual(oracle_lib, seed):
                                    rtol=0, atol=1e-10)
 
 
+@pytest.mark.parametrize("seed", [0, 4])
+def test_powerflow_agrees_with_newton(oracle_lib, seed):
+    """A second solver of the same load flow: Newton-Raphson (analytic
+    Jacobian of the complex power mismatch, in rectangular coordinates) on the
+    dense Y, started from the flat profile, reaches the oracle's sweep
+    solution."""
+    f = make_feeder("c1", seed, snapshots=2)
+    V, I, st, it = oracle_lib.powerflow(f)
+    assert st == 0
+    Y = dc.dense_Y(f)
+    pres = dc.present(f)
+    unk = np.nonzero(pres & (np.arange(len(pres)) >= 3))[0]
+    Yuu, Yus = Y[np.ix_(unk, unk)], Y[np.ix_(unk, [0, 1, 2])]
+    for l in range(V.shape[0]):
+        S = f["S_load"][l].reshape(-1)[unk]
+        v = np.tile(f["V0"], f["n"])[unk].astype(complex)
+        for _ in range(30):
+            i_net = Yuu @ v + Yus @ f["V0"]
+            F = v * np.conj(i_net) + S                     # injected = -consumed
+            if np.abs(F).max() < 1e-14:
+                break
+            # dF = dv conj(i) + v conj(Y dv): real 2m x 2m system in (Re dv, Im dv)
+            m = len(unk)
+            A = np.diag(np.conj(i_net))                    # coefficient of dv
+            B = np.diag(v) @ np.conj(Yuu)                  # coefficient of conj(dv)
+            J = np.block([[(A + B).real, -(A - B).imag], [(A + B).imag, (A - B).real]])
+            d = np.linalg.solve(J, -np.concatenate([F.real, F.imag]))
+            v = v + d[:m] + 1j * d[m:]
+        np.testing.assert_allclose(v, V[l].reshape(-1)[unk], rtol=0, atol=1e-11)
+
+
 def test_powerflow_reports_divergence(oracle_lib):
     f = make_feeder("c1", 0)
     f = dict(f, S_load=f["S_load"] * 400.0)
