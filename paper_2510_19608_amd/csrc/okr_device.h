@@ -178,8 +178,10 @@ __device__ __forceinline__ void sqrt_nr_v(const double (&x)[M], double (&y)[M]) 
 // bits above the lane bits a whole wave takes one side.  el, qmin and qmax
 // are per snapshot (folded later: max and min are exact).  LDS layout,
 // snapshot fastest: P[(pair * 3 + p) * M + j], T[(slot * 3 + p) * M + j],
-// H and Hm [(chain * 3 + p) * M + j].
-template <bool ERR, int M>
+// H and Hm [(chain * 3 + p) * M + j].  With HM_FROM_H the magnitudes of
+// heads no mask moves are formed from H here (as the LDS stage forms Hm)
+// instead of read from Hm.
+template <bool ERR, int M, bool HM_FROM_H = false>
 __device__ __forceinline__ void walk_chain_sv(const cint* cr, const double2* Ps, const TargetRec* Ts,
                                               const double2* Hs, const double* Hm, int c, uint32_t m,
                                               double2 (&B)[M][3], double (&el)[M], double (&qmin)[M],
@@ -199,7 +201,14 @@ __device__ __forceinline__ void walk_chain_sv(const cint* cr, const double2* Ps,
 #pragma unroll
       for (int p = 0; p < 3; ++p)
 #pragma unroll
-        for (int j = 0; j < M; ++j) sm[j][p] = Hm[(c * 3 + p) * M + j];
+        for (int j = 0; j < M; ++j) {
+          if (HM_FROM_H) {
+            const double2 hv = Hs[(c * 3 + p) * M + j];
+            sm[j][p] = (hv.x != 0.0 || hv.y != 0.0) ? hmag(hv) : 0.0;
+          } else {
+            sm[j][p] = Hm[(c * 3 + p) * M + j];
+          }
+        }
     } else {
 #pragma unroll
       for (int p = 0; p < 3; ++p)
@@ -276,7 +285,7 @@ __device__ __forceinline__ void walk_chain_sv(const cint* cr, const double2* Ps,
 // score_chain): the nesting path, the chain, then its zone entries (the first
 // zcap from the LDS stage Zs[q * M + j], the rest from global memory, where
 // snapshot j's records start at zg[j]).
-template <int M>
+template <int M, bool HM_FROM_H = false>
 __device__ __forceinline__ void score_chain_sv(const cint* chains, const cint* nest, int c,
                                                const double2* Ps, const TargetRec* Ts, const double2* Hs,
                                                const double* Hm, const TargetRec* Zs, int zcap,
@@ -291,9 +300,9 @@ __device__ __forceinline__ void score_chain_sv(const cint* chains, const cint* n
   const int nl = cr[C_NEST_LEN], no = cr[C_NEST_OFF];
   for (int q = 0; q + 1 < nl; ++q) {
     const int oc = nest[no + q];
-    walk_chain_sv<false, M>(chains + oc * kChainInts, Ps, Ts, Hs, Hm, oc, m, B, el, qmin, qmax);
+    walk_chain_sv<false, M, HM_FROM_H>(chains + oc * kChainInts, Ps, Ts, Hs, Hm, oc, m, B, el, qmin, qmax);
   }
-  walk_chain_sv<true, M>(cr, Ps, Ts, Hs, Hm, c, m, B, el, qmin, qmax);
+  walk_chain_sv<true, M, HM_FROM_H>(cr, Ps, Ts, Hs, Hm, c, m, B, el, qmin, qmax);
 #pragma unroll
   for (int p = 0; p < 3; ++p)
     for (int q = cr[C_ZOFF0 + p], qe = q + cr[C_ZCNT0 + p]; q < qe; ++q) {

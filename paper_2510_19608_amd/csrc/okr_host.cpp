@@ -34,7 +34,7 @@ __global__ void k_build_members(const SegHdr*, const int*, size_t, const int*, T
 template <int M>
 __global__ void k_score_fp64(const SegHdr*, const int*, size_t, const int*, const double2*, const TargetRec*,
                            const double2*, const TargetRec*, const double*, int, int, int, int, int, int, SelParams,
-                           MaskScore*, MaskScore*, TileRec*, int*, const int*);
+                           MaskScore*, MaskScore*, TileRec*, int*, const int*, int);
 __global__ void k_terms_init(const SegHdr*, const int*, size_t, int, const int*, int, const double*,
                              unsigned long long*, unsigned long long*);
 __global__ void k_chain_terms(const SegHdr*, const int*, size_t, int, const int*, const double2*, const TargetRec*,
@@ -102,7 +102,7 @@ __global__ void k_smice_hconst(const SegHdr*, const int*, size_t, Topo, State, c
                                const int*, double*, int);
 __global__ void k_smice_score(const SegHdr*, const int*, size_t, const int*, const double2*, const TargetRec*,
                               const double2*, const TargetRec*, const int*, const double*, const MaskScore*,
-                              const DevDecision*, SelParams, double*, double*);
+                              const TileRec*, const DevDecision*, SelParams, double*, double*);
 __global__ void k_smice_argmin(const SegHdr*, const int*, size_t, const MaskScore*, const TileRec*, const double*,
                                const double*, double, DevDecision*);
 }  // namespace okr
@@ -228,7 +228,8 @@ int tuned(const std::vector<int>& t, int k, int nz) {
 // Defaults follow the autotuner's picks on MI355X for the 1000-node workload
 // (segments of 15-16 nodes, chunks of 1-8 segments): a lone segment takes 4
 // snapshots per pass and 4 waves per 64 masks (2 from 16 nodes), a chunk of
-// several 2 snapshots and 2 waves, a full chunk of 8 one wave per 64 masks.
+// two 2 snapshots and 2 waves, a chunk of three or more one wave per 64
+// masks.
 int score_mpl(const okr_handle* h, int k, int nz) {
   if (h->mpl_force) return h->mpl_force;
   const int t = tuned(h->mpl_tuned, k, nz);
@@ -238,7 +239,7 @@ int score_ws(const okr_handle* h, int k, int nz) {
   if (h->ws_force) return h->ws_force;
   const int t = tuned(h->ws_tuned, k, nz);
   if (t) return t;
-  if (nz >= kMaxLanes) return 1;
+  if (nz >= 3) return 1;
   return (nz == 1 && k <= 15) ? 4 : 2;
 }
 
@@ -952,6 +953,8 @@ void enqueue_search(okr_handle* h, void* ws, const okr_yblocks* Y, const okr_loa
   for (int g = 0; g < h->nseg; ++g) foff[g + 1] = foff[g] + ((size_t)1 << (h->seg_off[g + 1] - h->seg_off[g]));
   const size_t lstride = h->L.lane_stride;
   const int nchunk = (int)h->chunk_k.size();
+  // every mask's final FP64 score is stored only when it is read back
+  const int full_fin = (dump || feat_out) ? 1 : 0;
   for (int c = 0; c < nchunk; ++c) {
     const int c0 = h->chunk_off[c], nz = h->chunk_off[c + 1] - c0;
     const int* segs = p.chunks + c0;  // device copy of this chunk's segment ids
@@ -1057,7 +1060,7 @@ void enqueue_search(okr_handle* h, void* ws, const okr_yblocks* Y, const okr_loa
   hipLaunchKernelGGL(k_score_fp64<M_>, dim3(mblocks, SG, nz), dim3(kScoreThreads), lds, st, (const SegHdr*)q.hdrs, segs, \
                      lstride, (const int*)q.tab, (const double2*)q.P, (const TargetRec*)q.srec,                      \
                      (const double2*)q.headV, (const TargetRec*)q.zrec, (const double*)q.econst, spg, SG, pcap, kc,   \
-                     kSvZone, sws, sp, q.part, q.fin, q.tiles, q.tickets, gates)
+                     kSvZone, sws, sp, q.part, q.fin, q.tiles, q.tickets, gates, full_fin)
         if (spp == 4) OKR_SCORE64(4);
         else if (spp == 2) OKR_SCORE64(2);
         else OKR_SCORE64(1);
@@ -1077,7 +1080,8 @@ void enqueue_search(okr_handle* h, void* ws, const okr_yblocks* Y, const okr_loa
                            dim3(kSmiceThreadsHost), 0, st, (const SegHdr*)q.hdrs, segs, lstride, (const int*)q.tab,
                            (const double2*)q.P, (const TargetRec*)q.srec, (const double2*)q.headV,
                            (const TargetRec*)q.zrec, (const int*)q.stab, (const double*)q.hK,
-                           (const MaskScore*)q.fin, (const DevDecision*)q.decs, sp, q.smv, q.smv0);
+                           (const MaskScore*)q.fin, (const TileRec*)q.tiles, (const DevDecision*)q.decs, sp, q.smv,
+                           q.smv0);
         hipLaunchKernelGGL(k_smice_argmin, dim3(1, 1, nz), dim3(1024), 0, st, (const SegHdr*)q.hdrs, segs, lstride,
                            (const MaskScore*)q.fin, (const TileRec*)q.tiles, (const double*)q.smv,
                            (const double*)q.smv0, mg->smice_tol > 0.0 ? mg->smice_tol : kSmiceTol, q.decs);
@@ -1143,7 +1147,7 @@ void enqueue_search(okr_handle* h, void* ws, const okr_yblocks* Y, const okr_loa
   hipLaunchKernelGGL(k_score_fp64<M_>, dim3(mblocks, SG, nz), dim3(kScoreThreads), lds, st, (const SegHdr*)q.hdrs, segs, \
                      lstride, (const int*)q.tab, (const double2*)q.P, (const TargetRec*)q.srec,                      \
                      (const double2*)q.headV, (const TargetRec*)q.zrec, (const double*)q.econst, spg, SG, pcap, kc,   \
-                     kSvZone, sws, sp, q.part, q.fin, q.tiles, q.tickets, redo)
+                     kSvZone, sws, sp, q.part, q.fin, q.tiles, q.tickets, redo, full_fin)
         if (spp == 4) OKR_SCORE64(4);
         else if (spp == 2) OKR_SCORE64(2);
         else OKR_SCORE64(1);

@@ -301,8 +301,9 @@ __global__ __launch_bounds__(1024) void k_argmin(const SegHdr* __restrict__ hdrs
     for (int q = threadIdx.x; q < nc * 64; q += blockDim.x) {
       const uint32_t mm = (uint32_t)cand[q >> 6] * 64 + (q & 63);
       if (mm >= nm) continue;
+      if (__popc(mm) != best) continue;  // (only these masks' scores are stored)
       const MaskScore r = fin[mm];
-      if (__popc(mm) != best || !feasible(r, sp.e_bar)) continue;
+      if (!feasible(r, sp.e_bar)) continue;
       if (fabs(r.e - thr) <= sp.amb) amb = 1;
       if (r.e <= thr) pick = min(pick, mm);
       else runner = fmin(runner, r.e);

@@ -15,8 +15,8 @@ namespace okr {
 // Tile record of one wave's 64 consecutive masks (lane i holds mask
 // tile * 64 + i, final score r): highest feasible level, smallest error at
 // that level, highest level of a mask near the e_bar / band boundary.
-__device__ __forceinline__ void tile_record(const MaskScore& r, uint32_t m, bool valid, uint32_t nmask,
-                                            const SelParams& sp, TileRec* __restrict__ tiles) {
+__device__ __forceinline__ int tile_record(const MaskScore& r, uint32_t m, bool valid, uint32_t nmask,
+                                           const SelParams& sp, TileRec* __restrict__ tiles) {
   const int pc = __popc(m);
   const bool feas = valid && feasible(r, sp.e_bar);
   int best = feas ? pc : -1;
@@ -35,6 +35,16 @@ __device__ __forceinline__ void tile_record(const MaskScore& r, uint32_t m, bool
     t.emin = em;
     tiles[tile] = t;
   }
+  return best;
+}
+
+// Whether a mask's final score is stored: every mask when all are wanted
+// (dumps, surrogate targets), else only the masks the arg-min can read -- a
+// tile's masks at its best feasible level (no mask of a lower level of the
+// tile can be at the chosen level) and mask 0 (the decision's error when no
+// mask is feasible).
+__device__ __forceinline__ bool keep_score(bool full, uint32_t m, int tile_best) {
+  return full || __popc(m) == tile_best || m == 0;
 }
 
 // Per-mask FP64 scoring, snapshot-vectorised: one mask per lane; a block's 4
@@ -47,16 +57,18 @@ __device__ __forceinline__ void tile_record(const MaskScore& r, uint32_t m, bool
 // (score_chain_sv).  A pass past the group's last snapshot repeats it.  With
 // one snapshot group the block writes the final per-mask scores and tile
 // records itself; with several, the last block of a tile to finish (ticket
-// counter) folds the groups.  Dynamic LDS per snapshot: pcap pairs, kcap
+// counter) folds the groups.  Final per-mask scores are stored for every
+// mask only with full_fin (keep_score).  Dynamic LDS per snapshot: pcap pairs, kcap
 // slots and chains, zcap zone records (later zone records are read from
 // global memory).
+constexpr int kLaneBits = kScoreBlock - 1;  // mask bits that vary across a wave's 64 lanes
 template <int M>
 __global__ __launch_bounds__(kScoreThreads) void k_score_fp64(
     const SegHdr* __restrict__ hdrs, const int* __restrict__ segs, size_t lstride, const int* __restrict__ tab,
     const double2* __restrict__ P, const TargetRec* __restrict__ srec, const double2* __restrict__ headV,
     const TargetRec* __restrict__ zrec, const double* __restrict__ econst, int snaps_per_group, int SG, int pcap,
     int kcap, int zcap, int ws, SelParams sp, MaskScore* __restrict__ part, MaskScore* __restrict__ fin,
-    TileRec* __restrict__ tiles, int* __restrict__ tickets, const int* __restrict__ gates) {
+    TileRec* __restrict__ tiles, int* __restrict__ tickets, const int* __restrict__ gates, int full_fin) {
   constexpr int NW = kScoreThreads / 64;
   extern __shared__ __align__(16) unsigned char sv_lds[];
   __shared__ double f_e[NW][64], f_qn[NW][64], f_qx[NW][64];
@@ -135,7 +147,8 @@ __global__ __launch_bounds__(kScoreThreads) void k_score_fp64(
       zg[j] = zrec + (size_t)min(l + j, l1 - 1) * H.nz;
     }
     for (int c = c0; c < H.nchains; c += ws)
-      score_chain_sv<M>(chains, nest, c, Ps, Ts, Hv, Hm, Zs, zst, zg, m, el, qmn, qmx);
+      if (chains[c * kChainInts + C_PMASK] & kLaneBits)  // (the others below)
+        score_chain_sv<M>(chains, nest, c, Ps, Ts, Hv, Hm, Zs, zst, zg, m, el, qmn, qmx);
 #pragma unroll
     for (int j = 0; j < M; ++j) e = fmax(e, el[j]);
     __syncthreads();
@@ -145,6 +158,40 @@ __global__ __launch_bounds__(kScoreThreads) void k_score_fp64(
   for (int j = 1; j < M; ++j) {
     qmin = fmin(qmin, qmn[j]);
     qmax = fmax(qmax, qmx[j]);
+  }
+  // Chains whose terms depend on no lane bit (their own and their nesting
+  // path's mask bits all above the 6 that vary across the wave) are the same
+  // for the wave's 64 masks: the wave evaluates each once, one snapshot per
+  // lane, from the tables in global memory, and every lane takes the maxima
+  // and minima over the snapshots.
+  {
+    const uint32_t mu = (uint32_t)__builtin_amdgcn_readfirstlane((int)m);
+    double ue = 0.0, uqn = INFINITY, uqx = -INFINITY;
+    bool any = false;
+    for (int c = c0; c < H.nchains; c += ws) {
+      if (chains[c * kChainInts + C_PMASK] & kLaneBits) continue;
+      any = true;
+      for (int l = l0 + lane; l < l1; l += 64) {
+        double e1[1] = {0.0}, qn1[1] = {INFINITY}, qx1[1] = {-INFINITY};
+        const TargetRec* zl = zrec + (size_t)l * H.nz;
+        const TargetRec* const zg1[1] = {zl};
+        score_chain_sv<1, true>(chains, nest, c, P + (size_t)l * H.npairs * 3, srec + (size_t)l * H.nslots * 3,
+                                headV + (size_t)l * H.nchains * 3, nullptr, zl, H.nz, zg1, mu, e1, qn1, qx1);
+        ue = fmax(ue, e1[0]);
+        uqn = fmin(uqn, qn1[0]);
+        uqx = fmax(uqx, qx1[0]);
+      }
+    }
+    if (any) {
+      for (int o = 32; o > 0; o >>= 1) {
+        ue = fmax(ue, __shfl_xor(ue, o, 64));
+        uqn = fmin(uqn, __shfl_xor(uqn, o, 64));
+        uqx = fmax(uqx, __shfl_xor(uqx, o, 64));
+      }
+      e = fmax(e, ue);
+      qmin = fmin(qmin, uqn);
+      qmax = fmax(qmax, uqx);
+    }
   }
   // fold the chains of a group's waves into its first wave (max and min are
   // exact in any order)
@@ -165,8 +212,8 @@ __global__ __launch_bounds__(kScoreThreads) void k_score_fp64(
   r.e = e;
   r.slack = band_slack(qmin, qmax, sp.vmin, sp.vmax);
   if (SG == 1) {  // the block holds every snapshot: final scores and tile record directly
-    if (valid) fin[m] = r;
-    tile_record(r, m, valid, nmask, sp, tiles);
+    const int tb = tile_record(r, m, valid, nmask, sp, tiles);
+    if (valid && keep_score(full_fin, m, tb)) fin[m] = r;
     return;
   }
   if (valid) part[(size_t)sg * nmask + m] = r;
@@ -185,9 +232,9 @@ __global__ __launch_bounds__(kScoreThreads) void k_score_fp64(
       r.e = fmax(r.e, x->e);
       r.slack = fmin(r.slack, x->slack);
     }
-    fin[m] = r;
   }
-  tile_record(r, m, valid, nmask, sp, tiles);
+  const int tb = tile_record(r, m, valid, nmask, sp, tiles);
+  if (valid && keep_score(full_fin, m, tb)) fin[m] = r;
   if (lane == 0) tickets[tile] = 0;  // ready for the next launch
 }
 
@@ -195,7 +242,7 @@ __global__ __launch_bounds__(kScoreThreads) void k_score_fp64(
   template __global__ void k_score_fp64<M_>(const SegHdr*, const int*, size_t, const int*, const double2*,              \
                                           const TargetRec*, const double2*, const TargetRec*, const double*, int, int, \
                                           int, int, int, int, SelParams, MaskScore*, MaskScore*, TileRec*, int*,       \
-                                          const int*);
+                                          const int*, int);
 OKR_SCORE64_INST(1)
 OKR_SCORE64_INST(2)
 OKR_SCORE64_INST(4)

@@ -216,8 +216,8 @@ __global__ __launch_bounds__(kSmiceThreads) void k_smice_score(
     const SegHdr* __restrict__ hdrs, const int* __restrict__ segs, size_t lstride, const int* __restrict__ tab,
     const double2* __restrict__ P, const TargetRec* __restrict__ srec, const double2* __restrict__ headV,
     const TargetRec* __restrict__ zrec, const int* __restrict__ stab, const double* __restrict__ hK,
-    const MaskScore* __restrict__ fin, const DevDecision* __restrict__ decs, SelParams sp,
-    double* __restrict__ smv, double* __restrict__ smv0) {
+    const MaskScore* __restrict__ fin, const TileRec* __restrict__ tiles, const DevDecision* __restrict__ decs,
+    SelParams sp, double* __restrict__ smv, double* __restrict__ smv0) {
   __shared__ double s_acc[kMaxK][kSmiceThreads];
   const int g = segs[blockIdx.z];
   const SegHdr H = load_hdr_g(hdrs, g);
@@ -235,9 +235,13 @@ __global__ __launch_bounds__(kSmiceThreads) void k_smice_score(
   stab = lane_ptr(stab, lstride);
   hK = lane_ptr(hK, lstride);
   fin = lane_ptr(fin, lstride);
+  tiles = lane_ptr(tiles, lstride);
   smv = lane_ptr(smv, lstride);
   smv0 = lane_ptr(smv0, lstride);
-  const bool cand = __popc(m) == d.popcount && feasible(fin[m], sp.e_bar);
+  // (a tile stores the scores of its best feasible level only: a tile whose
+  // best is below the chosen level has no feasible mask at it)
+  const bool cand = __popc(m) == d.popcount && tiles[m / kScoreBlock].best == d.popcount &&
+                    feasible(fin[m], sp.e_bar);
   if (!cand && m != 0) {
     smv[m] = INFINITY;
     return;
