@@ -10,6 +10,7 @@
 //
 // The tables have the layout the scoring kernel reads (okr_internal.h).
 #include <hip/hip_runtime.h>
+#include <limits.h>
 #include <math.h>
 #include <stdint.h>
 
@@ -55,6 +56,10 @@ __global__ __launch_bounds__(256) void k_build_struct(Topo T, State St, const in
   __shared__ int s_keycnt[kMaxK * 3], s_keyoff[kMaxK * 3], s_keycur[kMaxK * 3];
   __shared__ SegHdr s_h;
   __shared__ int s_err, s_nch;
+  __shared__ int s_cw[kMaxK];                 // chain c: its per-lane scoring work
+  __shared__ uint32_t s_clos[kMaxK];          // chain c: chains whose terms depend on c's bits
+  __shared__ long long s_pick[kMaxK];         // lane-bit choice: ratio key per candidate chain
+  __shared__ uint32_t s_lane, s_touched;
   __shared__ int s_zi[kOmegaLds], s_zk[kOmegaLds];  // zone pass: node and key of Omega index q
   __shared__ int s_tab[kTabLds];                     // structural tables before they are written out
   const int g = segs[blockIdx.z];
@@ -375,6 +380,60 @@ __global__ __launch_bounds__(256) void k_build_struct(Topo T, State St, const in
       if (s_h.total_ints > tab_cap) s_err = 1;
     }
   }
+  // Lane bits of the scoring kernel: a wave's 64 lanes vary 6 mask bits, and
+  // a chain none of whose bits (its own and its nesting path's) is among them
+  // is evaluated once per wave instead of per lane.  Chosen greedily: take
+  // the bits of the chain that adds the least per-lane work per bit gained
+  // (work of a chain: 2 per slot-phase, 1 per zone record, 1 per slot walked
+  // on its nesting path), until 6 bits are taken.
+  if (!s_err && tid < nch) {
+    const int c = tid;
+    int wk = 0;
+    for (int q = s_cslot0[c]; q < s_cslot0[c + 1]; ++q) wk += 2 * __popc(s_sph[s_slotbit[q]]);
+    for (int p = 0; p < 3; ++p) wk += s_keycnt[c * 3 + p];
+    for (int x = s_outer[c]; x >= 0; x = s_outer[x]) wk += s_cslot0[x + 1] - s_cslot0[x];
+    s_cw[c] = wk;
+    const int n = s_cslot0[c + 1] - s_cslot0[c];
+    const uint32_t own = ((1u << n) - 1u) << s_slotbit[s_cslot0[c]];
+    uint32_t cl = 0;
+    for (int d = 0; d < nch; ++d)
+      if ((uint32_t)s_pmask[d] & own) cl |= 1u << d;
+    s_clos[c] = cl;
+  }
+  if (tid == 0) {
+    s_lane = 0;
+    s_touched = 0;
+  }
+  __syncthreads();
+  for (int need = min(6, k); need > 0 && !s_err;) {
+    if (tid < nch) {
+      const int c = tid;
+      const int n = s_cslot0[c + 1] - s_cslot0[c];
+      const uint32_t own = ((1u << n) - 1u) << s_slotbit[s_cslot0[c]];
+      const int nb = min(__popc(own & ~s_lane), need);
+      long long key = LLONG_MAX;
+      if (nb > 0) {
+        int add = 0;
+        for (uint32_t x = s_clos[c] & ~s_touched; x; x &= x - 1) add += s_cw[__builtin_ctz(x)];
+        // added work per bit, in 1/720 units (exact for 1..6 bits), then the chain
+        key = ((long long)(add * (720 / nb)) << 8) | c;
+      }
+      s_pick[c] = key;
+    }
+    __syncthreads();
+    if (tid == 0) {
+      int best = 0;
+      for (int c = 1; c < nch; ++c)
+        if (s_pick[c] < s_pick[best]) best = c;
+      const int n = s_cslot0[best + 1] - s_cslot0[best];
+      uint32_t free_bits = (((1u << n) - 1u) << s_slotbit[s_cslot0[best]]) & ~s_lane;
+      for (int b = 0; b < need && free_bits; ++b, free_bits &= free_bits - 1) s_lane |= free_bits & (0u - free_bits);
+      s_touched |= s_clos[best];
+    }
+    __syncthreads();
+    need = min(6, k) - __popc(s_lane);
+  }
+  if (tid == 0) s_h.lanebits = (int)s_lane;
   __syncthreads();
   if (!s_err)
     for (int q = threadIdx.x; q < nom; q += blockDim.x) {

@@ -32,7 +32,19 @@ struct SegHdr {
   int o_zent;     // [nz][3]: node, phase, chain
   int total_ints;
   int npat;       // chain patterns: sum over chains of 2^popcount(C_PMASK)
+  int lanebits;   // the mask bits that vary across a scoring wave's 64 lanes
+                  // (6 of them, all k when k < 6); a tile is the 64 masks
+                  // sharing every other bit (tile_mask)
 };
+
+// Mask of scoring tile t, lane q: q's bits at the positions of the segment's
+// lane bits L, t's bits at the other positions of the k mask bits.
+__host__ __device__ __forceinline__ uint32_t tile_mask(uint32_t L, uint32_t t, uint32_t q, int k) {
+  uint32_t m = 0;
+  for (uint32_t l = L; l; l &= l - 1, q >>= 1) m |= (q & 1u) << __builtin_ctz(l);
+  for (uint32_t o = ((k >= 32 ? 0u : (1u << k)) - 1u) & ~L; o; o &= o - 1, t >>= 1) m |= (t & 1u) << __builtin_ctz(o);
+  return m;
+}
 
 // A search step launched over a chunk of mutually independent segments:
 // blockIdx.z picks the segment (segs[blockIdx.z]) and its scratch block; each

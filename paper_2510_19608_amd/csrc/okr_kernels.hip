@@ -269,7 +269,9 @@ __global__ __launch_bounds__(1024) void k_argmin(const SegHdr* __restrict__ hdrs
   }
   const int k = H.k;
   const uint32_t nm = 1u << k;
-  const int ntiles = (int)((nm + 63) / 64);
+  const uint32_t L = (uint32_t)H.lanebits;  // tile t, lane q holds tile_mask(L, t, q, k)
+  const int lb = __popc(L);
+  const int ntiles = (int)(nm >> lb);
   int best = -1;
   for (int t = threadIdx.x; t < ntiles; t += blockDim.x) best = max(best, tiles[t].best);
   best = block_reduce(best, [](int a, int b) { return max(a, b); }, shi);
@@ -299,8 +301,8 @@ __global__ __launch_bounds__(1024) void k_argmin(const SegHdr* __restrict__ hdrs
     __syncthreads();
     const int nc = ncand;
     for (int q = threadIdx.x; q < nc * 64; q += blockDim.x) {
-      const uint32_t mm = (uint32_t)cand[q >> 6] * 64 + (q & 63);
-      if (mm >= nm) continue;
+      if ((q & 63) >> lb) continue;
+      const uint32_t mm = tile_mask(L, (uint32_t)cand[q >> 6], (uint32_t)(q & 63), k);
       if (__popc(mm) != best) continue;  // (only these masks' scores are stored)
       const MaskScore r = fin[mm];
       if (!feasible(r, sp.e_bar)) continue;

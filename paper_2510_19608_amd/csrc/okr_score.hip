@@ -12,10 +12,11 @@
 namespace okr {
 
 // ---------------------------------------------------------------- scoring --
-// Tile record of one wave's 64 consecutive masks (lane i holds mask
-// tile * 64 + i, final score r): highest feasible level, smallest error at
-// that level, highest level of a mask near the e_bar / band boundary.
-__device__ __forceinline__ int tile_record(const MaskScore& r, uint32_t m, bool valid, uint32_t nmask,
+// Tile record of one wave's 64 masks (lane q holds mask
+// tile_mask(lanebits, tile, q, k), final score r): highest feasible level,
+// smallest error at that level, highest level of a mask near the e_bar /
+// band boundary.
+__device__ __forceinline__ int tile_record(const MaskScore& r, uint32_t m, uint32_t tile, bool valid,
                                            const SelParams& sp, TileRec* __restrict__ tiles) {
   const int pc = __popc(m);
   const bool feas = valid && feasible(r, sp.e_bar);
@@ -27,8 +28,7 @@ __device__ __forceinline__ int tile_record(const MaskScore& r, uint32_t m, bool 
   }
   double em = (feas && pc == best) ? r.e : INFINITY;
   for (int o = 32; o > 0; o >>= 1) em = fmin(em, __shfl_xor(em, o, 64));
-  const uint32_t tile = m / kScoreBlock;
-  if ((threadIdx.x & 63) == 0 && tile * kScoreBlock < nmask) {
+  if ((threadIdx.x & 63) == 0) {
     TileRec t;
     t.best = best;
     t.near = nearl;
@@ -61,7 +61,6 @@ __device__ __forceinline__ bool keep_score(bool full, uint32_t m, int tile_best)
 // mask only with full_fin (keep_score).  Dynamic LDS per snapshot: pcap pairs, kcap
 // slots and chains, zcap zone records (later zone records are read from
 // global memory).
-constexpr int kLaneBits = kScoreBlock - 1;  // mask bits that vary across a wave's 64 lanes
 template <int M>
 __global__ __launch_bounds__(kScoreThreads) void k_score_fp64(
     const SegHdr* __restrict__ hdrs, const int* __restrict__ segs, size_t lstride, const int* __restrict__ tab,
@@ -99,8 +98,12 @@ __global__ __launch_bounds__(kScoreThreads) void k_score_fp64(
   const int w = __builtin_amdgcn_readfirstlane(tid >> 6);
   const int lane = tid & 63;
   const int c0 = w % ws;  // this wave's first chain within its group
-  const uint32_t m = blockIdx.x * bmasks + (uint32_t)(w / ws) * kScoreBlock + lane;
-  const bool valid = m < nmask;
+  // this wave's tile and this lane's mask (the lane bits vary across the wave)
+  const uint32_t L = (uint32_t)H.lanebits;
+  const uint32_t tile = blockIdx.x * (NW / ws) + (uint32_t)(w / ws);
+  const uint32_t m = tile_mask(L, tile, (uint32_t)lane, H.k);
+  const bool tile_ok = (tile << __popc(L)) < nmask;  // (a block's last waves can lie past the masks)
+  const bool valid = tile_ok && ((uint32_t)lane >> __popc(L)) == 0;
   const int sg = blockIdx.y;
   const int l0 = sg * snaps_per_group;
   const int l1 = min(H.S, l0 + snaps_per_group);
@@ -147,7 +150,7 @@ __global__ __launch_bounds__(kScoreThreads) void k_score_fp64(
       zg[j] = zrec + (size_t)min(l + j, l1 - 1) * H.nz;
     }
     for (int c = c0; c < H.nchains; c += ws)
-      if (chains[c * kChainInts + C_PMASK] & kLaneBits)  // (the others below)
+      if (chains[c * kChainInts + C_PMASK] & L)  // (the others below)
         score_chain_sv<M>(chains, nest, c, Ps, Ts, Hv, Hm, Zs, zst, zg, m, el, qmn, qmx);
 #pragma unroll
     for (int j = 0; j < M; ++j) e = fmax(e, el[j]);
@@ -159,8 +162,8 @@ __global__ __launch_bounds__(kScoreThreads) void k_score_fp64(
     qmin = fmin(qmin, qmn[j]);
     qmax = fmax(qmax, qmx[j]);
   }
-  // Chains whose terms depend on no lane bit (their own and their nesting
-  // path's mask bits all above the 6 that vary across the wave) are the same
+  // Chains whose terms depend on no lane bit (none of their own and their
+  // nesting path's mask bits among the 6 that vary across the wave) are the same
   // for the wave's 64 masks: the wave evaluates each once, one snapshot per
   // lane, from the tables in global memory, and every lane takes the maxima
   // and minima over the snapshots.
@@ -169,7 +172,7 @@ __global__ __launch_bounds__(kScoreThreads) void k_score_fp64(
     double ue = 0.0, uqn = INFINITY, uqx = -INFINITY;
     bool any = false;
     for (int c = c0; c < H.nchains; c += ws) {
-      if (chains[c * kChainInts + C_PMASK] & kLaneBits) continue;
+      if (chains[c * kChainInts + C_PMASK] & L) continue;
       any = true;
       for (int l = l0 + lane; l < l1; l += 64) {
         double e1[1] = {0.0}, qn1[1] = {INFINITY}, qx1[1] = {-INFINITY};
@@ -207,12 +210,12 @@ __global__ __launch_bounds__(kScoreThreads) void k_score_fp64(
       qmax = fmax(qmax, f_qx[w + q][lane]);
     }
   }
-  const uint32_t tile = m / kScoreBlock;
+  if (!tile_ok) return;
   MaskScore r;
   r.e = e;
   r.slack = band_slack(qmin, qmax, sp.vmin, sp.vmax);
   if (SG == 1) {  // the block holds every snapshot: final scores and tile record directly
-    const int tb = tile_record(r, m, valid, nmask, sp, tiles);
+    const int tb = tile_record(r, m, tile, valid, sp, tiles);
     if (valid && keep_score(full_fin, m, tb)) fin[m] = r;
     return;
   }
@@ -233,7 +236,7 @@ __global__ __launch_bounds__(kScoreThreads) void k_score_fp64(
       r.slack = fmin(r.slack, x->slack);
     }
   }
-  const int tb = tile_record(r, m, valid, nmask, sp, tiles);
+  const int tb = tile_record(r, m, tile, valid, sp, tiles);
   if (valid && keep_score(full_fin, m, tb)) fin[m] = r;
   if (lane == 0) tickets[tile] = 0;  // ready for the next launch
 }
@@ -445,8 +448,11 @@ __global__ __launch_bounds__(256) void k_fac_combine(const SegHdr* __restrict__ 
   for (int i = tid; i < 3 * np; i += blockDim.x) s_pat[i] = __longlong_as_double((long long)pat[i]);
   __syncthreads();
   const uint32_t nmask = 1u << H.k;
-  const uint32_t m = blockIdx.x * blockDim.x + tid;
-  const bool valid = m < nmask;
+  const uint32_t L = (uint32_t)H.lanebits;
+  const uint32_t tile = (blockIdx.x * blockDim.x + tid) / kScoreBlock;
+  const uint32_t m = tile_mask(L, tile, (uint32_t)(tid & (kScoreBlock - 1)), H.k);
+  const bool tile_ok = (tile << __popc(L)) < nmask;
+  const bool valid = tile_ok && ((uint32_t)(tid & (kScoreBlock - 1)) >> __popc(L)) == 0;
   double e = __longlong_as_double((long long)*ecmax), qn = INFINITY, qx = 0.0;
   for (int c = 0; c < nch; ++c) {
     uint32_t pm = (uint32_t)__builtin_amdgcn_readfirstlane(s_pm[c]);
@@ -480,7 +486,7 @@ __global__ __launch_bounds__(256) void k_fac_combine(const SegHdr* __restrict__ 
   r.e = e;
   r.slack = band_slack(qn, qx, sp.vmin, sp.vmax);
   if (valid) fin[m] = r;
-  tile_record(r, m, valid, nmask, sp, tiles);
+  if (tile_ok) tile_record(r, m, tile, valid, sp, tiles);
 }
 
 // d = |W + S| - |W| in difference form (w = |W| given):

@@ -225,8 +225,13 @@ __global__ __launch_bounds__(kSmiceThreads) void k_smice_score(
   const DevDecision d = decs[g];
   if (!d.found) return;
   const uint32_t nmask = 1u << H.k;
-  const uint32_t m = blockIdx.x * kSmiceThreads + threadIdx.x;
-  if (m >= nmask) return;
+  // thread i: lane i % 64 of scoring tile i / 64 (tile_mask), so that the
+  // tile record of its mask is at hand
+  const uint32_t L = (uint32_t)H.lanebits;
+  const uint32_t ti = blockIdx.x * kSmiceThreads + threadIdx.x;
+  const uint32_t tile = ti / kScoreBlock, q = ti % kScoreBlock;
+  if ((tile << __popc(L)) >= nmask || (q >> __popc(L)) != 0) return;
+  const uint32_t m = tile_mask(L, tile, q, H.k);
   tab = lane_ptr(tab, lstride);
   P = lane_ptr(P, lstride);
   srec = lane_ptr(srec, lstride);
@@ -240,7 +245,7 @@ __global__ __launch_bounds__(kSmiceThreads) void k_smice_score(
   smv0 = lane_ptr(smv0, lstride);
   // (a tile stores the scores of its best feasible level only: a tile whose
   // best is below the chosen level has no feasible mask at it)
-  const bool cand = __popc(m) == d.popcount && tiles[m / kScoreBlock].best == d.popcount &&
+  const bool cand = __popc(m) == d.popcount && tiles[tile].best == d.popcount &&
                     feasible(fin[m], sp.e_bar);
   if (!cand && m != 0) {
     smv[m] = INFINITY;
@@ -359,7 +364,7 @@ __global__ __launch_bounds__(1024) void k_smice_argmin(const SegHdr* __restrict_
   smv = lane_ptr(smv, lstride);
   smv0 = lane_ptr(smv0, lstride);
   const uint32_t nm = 1u << H.k;
-  const int ntiles = (int)((nm + 63) / 64);
+  const int ntiles = (int)(nm >> __popc((uint32_t)H.lanebits));
   double smin = INFINITY;
   for (uint32_t m = threadIdx.x; m < nm; m += blockDim.x) smin = fmin(smin, smv[m]);
   smin = block_reduce(smin, [](double a, double b) { return fmin(a, b); }, shd);
