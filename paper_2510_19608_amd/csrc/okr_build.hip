@@ -58,8 +58,6 @@ __global__ __launch_bounds__(256) void k_build_struct(Topo T, State St, const in
   __shared__ int s_err, s_nch;
   __shared__ int s_cw[kMaxK];                 // chain c: its per-lane scoring work
   __shared__ uint32_t s_clos[kMaxK];          // chain c: chains whose terms depend on c's bits
-  __shared__ long long s_pick[kMaxK];         // lane-bit choice: ratio key per candidate chain
-  __shared__ uint32_t s_lane, s_touched;
   __shared__ int s_zi[kOmegaLds], s_zk[kOmegaLds];  // zone pass: node and key of Omega index q
   __shared__ int s_tab[kTabLds];                     // structural tables before they are written out
   const int g = segs[blockIdx.z];
@@ -400,40 +398,38 @@ __global__ __launch_bounds__(256) void k_build_struct(Topo T, State St, const in
       if ((uint32_t)s_pmask[d] & own) cl |= 1u << d;
     s_clos[c] = cl;
   }
-  if (tid == 0) {
-    s_lane = 0;
-    s_touched = 0;
-  }
   __syncthreads();
-  for (int need = min(6, k); need > 0 && !s_err;) {
-    if (tid < nch) {
-      const int c = tid;
-      const int n = s_cslot0[c + 1] - s_cslot0[c];
-      const uint32_t own = ((1u << n) - 1u) << s_slotbit[s_cslot0[c]];
-      const int nb = min(__popc(own & ~s_lane), need);
+  // the greedy choice itself in one wave (candidates in lanes, wave-wide
+  // minimum; the chosen bits and the chains they touch kept in registers)
+  if (tid < 64) {
+    uint32_t lane_bits = 0, touched = 0;
+    for (int need = s_err ? 0 : min(6, k); need > 0;) {
       long long key = LLONG_MAX;
-      if (nb > 0) {
-        int add = 0;
-        for (uint32_t x = s_clos[c] & ~s_touched; x; x &= x - 1) add += s_cw[__builtin_ctz(x)];
-        // added work per bit, in 1/720 units (exact for 1..6 bits), then the chain
-        key = ((long long)(add * (720 / nb)) << 8) | c;
+      if (tid < nch) {
+        const int c = tid;
+        const int n = s_cslot0[c + 1] - s_cslot0[c];
+        const uint32_t own = ((1u << n) - 1u) << s_slotbit[s_cslot0[c]];
+        const int nb = min(__popc(own & ~lane_bits), need);
+        if (nb > 0) {
+          int add = 0;
+          for (uint32_t x = s_clos[c] & ~touched; x; x &= x - 1) add += s_cw[__builtin_ctz(x)];
+          // added work per bit, in 1/720 units (exact for 1..6 bits), then the chain
+          key = ((long long)(add * (720 / nb)) << 8) | c;
+        }
       }
-      s_pick[c] = key;
-    }
-    __syncthreads();
-    if (tid == 0) {
-      int best = 0;
-      for (int c = 1; c < nch; ++c)
-        if (s_pick[c] < s_pick[best]) best = c;
+      for (int o = 32; o > 0; o >>= 1) {
+        const long long other = __shfl_xor(key, o, 64);
+        key = other < key ? other : key;
+      }
+      const int best = (int)(key & 255);
       const int n = s_cslot0[best + 1] - s_cslot0[best];
-      uint32_t free_bits = (((1u << n) - 1u) << s_slotbit[s_cslot0[best]]) & ~s_lane;
-      for (int b = 0; b < need && free_bits; ++b, free_bits &= free_bits - 1) s_lane |= free_bits & (0u - free_bits);
-      s_touched |= s_clos[best];
+      uint32_t free_bits = (((1u << n) - 1u) << s_slotbit[s_cslot0[best]]) & ~lane_bits;
+      for (int b = 0; b < need && free_bits; ++b, free_bits &= free_bits - 1) lane_bits |= free_bits & (0u - free_bits);
+      touched |= s_clos[best];
+      need = min(6, k) - __popc(lane_bits);
     }
-    __syncthreads();
-    need = min(6, k) - __popc(s_lane);
+    if (tid == 0) s_h.lanebits = (int)lane_bits;
   }
-  if (tid == 0) s_h.lanebits = (int)s_lane;
   __syncthreads();
   if (!s_err)
     for (int q = threadIdx.x; q < nom; q += blockDim.x) {
