@@ -79,11 +79,11 @@ __global__ __launch_bounds__(256) void k_build_struct(Topo T, State St, const in
   // one step: their nearest kept ancestor is known)
   if (!s_err && tid < k) {
     const int e = T.seg_nodes[o0 + tid];
-    int c = e, guard = 0;
+    int c = T.seg_top[e], guard = 0;  // (runs of this segment's nodes climbed at plan time)
     for (;;) {
       const int p = parent[c];
       if (p < 0 || ++guard > T.n) break;
-      if (segment[p] == g) { c = p; continue; }
+      if (segment[p] == g) { c = T.seg_top[p]; continue; }
       if (St.kept[p]) break;
       const int h = St.sup[p];
       const int x = (h >= 0 && h != p) ? child_toward(T, h, p) : -1;

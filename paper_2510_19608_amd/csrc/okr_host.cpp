@@ -175,7 +175,8 @@ struct Layout {
 
 // offsets (in int32) of the static topology arrays inside the topology buffer
 struct TopoOffsets {
-  int parent, phase, segment, pos, size, pre, ch_off, ch, lvl_off, lvl_nodes, seg_off, seg_nodes, chunks, total;
+  int parent, phase, segment, pos, size, pre, ch_off, ch, lvl_off, lvl_nodes, seg_off, seg_nodes, chunks, seg_top,
+      total;
 };
 
 }  // namespace
@@ -623,6 +624,18 @@ extern "C" int okr_plan(okr_handle* h, const okr_topology* topo, const okr_margi
   TO.seg_off = put(h->seg_off);
   TO.seg_nodes = put(h->seg_nodes.empty() ? std::vector<int>{0} : h->seg_nodes);
   TO.chunks = put(h->chunk_segs.empty() ? std::vector<int>{0} : h->chunk_segs);
+  {
+    // static part of the chain-top climb: through nodes of the same segment
+    // (preorder: a parent's entry is final before its children's)
+    std::vector<int> top(n, -1);
+    for (int q = 0; q < n; ++q) {
+      const int v = h->pre[q];
+      if (h->segment[v] < 0) continue;
+      const int pv = h->parent[v];
+      top[v] = (pv >= 0 && h->segment[pv] == h->segment[v]) ? top[pv] : v;
+    }
+    TO.seg_top = put(top);
+  }
   TO.phase = (int)tp.size();
   tp.resize(tp.size() + (n + 3) / 4, 0);
   std::memcpy(tp.data() + TO.phase, h->phase.data(), n);
@@ -809,6 +822,7 @@ Ptrs pointers(okr_handle* h, void* d_workspace, int lane = 0) {
   p.T.ch = tp + TO.ch;
   p.T.seg_off = tp + TO.seg_off;
   p.T.seg_nodes = tp + TO.seg_nodes;
+  p.T.seg_top = tp + TO.seg_top;
   p.lvl_off = tp + TO.lvl_off;
   p.lvl_nodes = tp + TO.lvl_nodes;
   p.chunks = tp + TO.chunks;

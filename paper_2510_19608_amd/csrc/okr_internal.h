@@ -87,6 +87,7 @@ struct Topo {
   const int* ch;
   const int* seg_off;   // segment -> first index in seg_nodes
   const int* seg_nodes; // segment nodes in DFS preorder
+  const int* seg_top;   // segment node -> highest ancestor reachable through its own segment's nodes
 };
 
 // Cumulative search state on the device.
