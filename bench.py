@@ -35,9 +35,10 @@ FP64_VECTOR_PEAK_TFLOPS = 78.6   # MI355X FP64 vector (256 CUs x 2.4 GHz x 128 f
 # profiles/k_score_fp64_c2_1000node_24snap.md), valid only for the sources
 # they were taken with: any change to them reports null.
 TRAFFIC_SOURCES = ["paper_2510_19608_amd/csrc/okr_score.hip", "paper_2510_19608_amd/csrc/okr_device.h",
-                   "paper_2510_19608_amd/csrc/okr_internal.h", "paper_2510_19608_amd/csrc/okr_host.cpp"]
-TRAFFIC_SHA1 = "cb67feb56648f021a083a6da174b7090b424ce71"
-TRAFFIC_BYTES_PER_LAUNCH = 4268677
+                   "paper_2510_19608_amd/csrc/okr_internal.h", "paper_2510_19608_amd/csrc/okr_host.cpp",
+                   "paper_2510_19608_amd/csrc/okr_build.hip"]
+TRAFFIC_SHA1 = "a7aeaeb7041b6842247f5e4fdb824bad4448a1e2"
+TRAFFIC_BYTES_PER_LAUNCH = 2014346
 
 
 def measured_traffic():
