@@ -638,6 +638,7 @@ __global__ __launch_bounds__(kScoreThreads) void k_score_fp32(
     for (int i = 0; i < M; ++i) el[i] = ec;
     for (int c = 0; c < H.nchains; ++c) {
       const int* cr = chains + c * kChainInts;
+      if (!(cr[C_PMASK] & (kScoreBlock - 1))) continue;  // the same for the wave's lanes: below
       float2 B[M][3];
 #pragma unroll
       for (int i = 0; i < M; ++i)
@@ -666,6 +667,54 @@ __global__ __launch_bounds__(kScoreThreads) void k_score_fp32(
 #pragma unroll
     for (int i = 0; i < M; ++i) e[i] = fmaxf(e[i], el[i]);
     __syncthreads();
+  }
+  // Chains none of whose bits is among the 6 that vary across a wave's lanes
+  // have the same terms for the wave's 64 masks of each of its M mask sets:
+  // evaluated once per wave and mask set, one snapshot per lane, from the
+  // tables in global memory, folded across the lanes.
+  {
+    const int lane = tid & 63;
+    for (int c = 0; c < H.nchains; ++c) {
+      const int* cr = chains + c * kChainInts;
+      if (cr[C_PMASK] & (kScoreBlock - 1)) continue;
+      const int nl = cr[C_NEST_LEN], no = cr[C_NEST_OFF];
+#pragma unroll
+      for (int i = 0; i < M; ++i) {
+        const uint32_t mi[1] = {(uint32_t)__builtin_amdgcn_readfirstlane((int)m[i])};
+        float ue = 0.f, us = INFINITY;
+        for (int l = l0 + lane; l < l1; l += 64) {
+          const Pair32* P_l = P32 + (size_t)l * H.npairs * 3;
+          const Rec32* S_l = S32 + (size_t)l * H.nslots * 3;
+          const Head32* H_l = H32 + (size_t)l * H.nchains * 3;
+          const Rec32* Z_l = Z32 + (size_t)l * H.nz;
+          float2 B[1][3];
+#pragma unroll
+          for (int p = 0; p < 3; ++p) B[0][p] = make_float2(0.f, 0.f);
+          float el1[1] = {0.f}, sl1[1] = {INFINITY};
+          for (int q = 0; q + 1 < nl; ++q) {
+            const int oc = nest[no + q];
+            walk32<false, 1>(chains + oc * kChainInts, P_l, S_l, H_l, oc, mi, B, el1, sl1);
+          }
+          walk32<true, 1>(cr, P_l, S_l, H_l, c, mi, B, el1, sl1);
+#pragma unroll
+          for (int p = 0; p < 3; ++p)
+            for (int q = cr[C_ZOFF0 + p], qe = q + cr[C_ZCNT0 + p]; q < qe; ++q) {
+              const Rec32 t = Z_l[q];
+              const float d = diff32(t.W, t.w, B[0][p]);
+              el1[0] = fmaxf(el1[0], fmaxf(t.a + d, t.b - d));
+              sl1[0] = fminf(sl1[0], fminf(t.bmin + d, t.bmax - d));
+            }
+          ue = fmaxf(ue, el1[0]);
+          us = fminf(us, sl1[0]);
+        }
+        for (int o = 32; o > 0; o >>= 1) {
+          ue = fmaxf(ue, __shfl_xor(ue, o, 64));
+          us = fminf(us, __shfl_xor(us, o, 64));
+        }
+        e[i] = fmaxf(e[i], ue);
+        slack[i] = fminf(slack[i], us);
+      }
+    }
   }
   const uint32_t nmask = 1u << H.k;
 #pragma unroll
