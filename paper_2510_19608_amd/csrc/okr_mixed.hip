@@ -136,7 +136,9 @@ __global__ __launch_bounds__(1024) void k_mixed_select_a(const SegHdr* __restric
     return;
   }
   const uint32_t nm = 1u << H.k;
-  const int ntiles = (int)((nm + 63) / 64);
+  const uint32_t L = (uint32_t)H.lanebits;  // tile t, lane j holds tile_mask(L, t, j, k)
+  const int lb = __popc(L);
+  const int ntiles = (int)(nm >> lb);
   int lo = -1, hi = -1;
   for (int t = threadIdx.x; t < ntiles; t += blockDim.x) {
     lo = max(lo, tiles[t].sure);
@@ -148,8 +150,8 @@ __global__ __launch_bounds__(1024) void k_mixed_select_a(const SegHdr* __restric
   for (int t = threadIdx.x; t < ntiles; t += blockDim.x) {
     if (tiles[t].unc < lo || tiles[t].unc < 0) continue;
     for (int j = 0; j < 64; ++j) {
-      const uint32_t mm = (uint32_t)t * 64 + j;
-      if (mm >= nm) break;
+      if (j >> lb) break;
+      const uint32_t mm = tile_mask(L, (uint32_t)t, (uint32_t)j, H.k);
       const MaskScore32 r = fin[mm];
       const bool sure = (double)r.e <= sp.e_bar - dd && (double)r.slack >= dd;
       const bool poss = (double)r.e <= sp.e_bar + dd && (double)r.slack >= -dd;
@@ -192,7 +194,9 @@ __global__ __launch_bounds__(1024) void k_mixed_select_b(const SegHdr* __restric
     return;
   }
   const uint32_t nm = 1u << H.k;
-  const int ntiles = (int)((nm + 63) / 64);
+  const uint32_t L = (uint32_t)H.lanebits;  // tile t, lane j holds tile_mask(L, t, j, k)
+  const int lb = __popc(L);
+  const int ntiles = (int)(nm >> lb);
   const double dd = sp.delta + sp.amb;
   const int nA = *countA;
   int best = ms[g].lo_level;
@@ -205,8 +209,8 @@ __global__ __launch_bounds__(1024) void k_mixed_select_b(const SegHdr* __restric
     for (int t = threadIdx.x; t < ntiles; t += blockDim.x) {
       if (tiles[t].sure < best) continue;
       for (int j = 0; j < 64; ++j) {
-        const uint32_t mm = (uint32_t)t * 64 + j;
-        if (mm >= nm) break;
+        if (j >> lb) break;
+        const uint32_t mm = tile_mask(L, (uint32_t)t, (uint32_t)j, H.k);
         const MaskScore32 r = fin[mm];
         if (__popc(mm) == best && (double)r.e <= sp.e_bar - dd && (double)r.slack >= dd)
           eup = fmin(eup, (double)r.e + sp.delta);
@@ -221,8 +225,8 @@ __global__ __launch_bounds__(1024) void k_mixed_select_b(const SegHdr* __restric
     for (int t = threadIdx.x; t < ntiles; t += blockDim.x) {
       if (tiles[t].poss < best) continue;
       for (int j = 0; j < 64; ++j) {
-        const uint32_t mm = (uint32_t)t * 64 + j;
-        if (mm >= nm) break;
+        if (j >> lb) break;
+        const uint32_t mm = tile_mask(L, (uint32_t)t, (uint32_t)j, H.k);
         const MaskScore32 r = fin[mm];
         const bool poss = (double)r.e <= sp.e_bar + dd && (double)r.slack >= -dd;
         if (poss && __popc(mm) == best && (double)r.e <= bound) listB[atomicAdd(&cnt, 1)] = mm;

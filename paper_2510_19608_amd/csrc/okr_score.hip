@@ -604,9 +604,14 @@ __global__ __launch_bounds__(kScoreThreads) void k_score_fp32(
   tiles = lane_ptr(tiles, lstride);
   tickets = lane_ptr(tickets, lstride);
   const int tid = threadIdx.x;
-  uint32_t m[M];
+  // lane set i of the block: tile x[i] / 64 (tile_mask over the segment's lane bits)
+  const uint32_t L = (uint32_t)H.lanebits;
+  uint32_t x[M], m[M];
 #pragma unroll
-  for (int i = 0; i < M; ++i) m[i] = blockIdx.x * (kScoreThreads * M) + i * kScoreThreads + tid;
+  for (int i = 0; i < M; ++i) {
+    x[i] = blockIdx.x * (kScoreThreads * M) + i * kScoreThreads + tid;
+    m[i] = tile_mask(L, x[i] / kScoreBlock, x[i] % kScoreBlock, H.k);
+  }
   const int sg = blockIdx.y;
   const int l0 = sg * snaps_per_group;
   const int l1 = min(H.S, l0 + snaps_per_group);
@@ -638,7 +643,7 @@ __global__ __launch_bounds__(kScoreThreads) void k_score_fp32(
     for (int i = 0; i < M; ++i) el[i] = ec;
     for (int c = 0; c < H.nchains; ++c) {
       const int* cr = chains + c * kChainInts;
-      if (!(cr[C_PMASK] & (kScoreBlock - 1))) continue;  // the same for the wave's lanes: below
+      if (!(cr[C_PMASK] & L)) continue;  // the same for the wave's lanes: below
       float2 B[M][3];
 #pragma unroll
       for (int i = 0; i < M; ++i)
@@ -668,15 +673,16 @@ __global__ __launch_bounds__(kScoreThreads) void k_score_fp32(
     for (int i = 0; i < M; ++i) e[i] = fmaxf(e[i], el[i]);
     __syncthreads();
   }
-  // Chains none of whose bits is among the 6 that vary across a wave's lanes
-  // have the same terms for the wave's 64 masks of each of its M mask sets:
+  // Chains none of whose bits is among the lane bits (the 6 that vary across
+  // a wave's lanes) have the same terms for the wave's 64 masks of each of
+  // its M mask sets:
   // evaluated once per wave and mask set, one snapshot per lane, from the
   // tables in global memory, folded across the lanes.
   {
     const int lane = tid & 63;
     for (int c = 0; c < H.nchains; ++c) {
       const int* cr = chains + c * kChainInts;
-      if (cr[C_PMASK] & (kScoreBlock - 1)) continue;
+      if (cr[C_PMASK] & L) continue;
       const int nl = cr[C_NEST_LEN], no = cr[C_NEST_OFF];
 #pragma unroll
       for (int i = 0; i < M; ++i) {
@@ -719,7 +725,7 @@ __global__ __launch_bounds__(kScoreThreads) void k_score_fp32(
   const uint32_t nmask = 1u << H.k;
 #pragma unroll
   for (int i = 0; i < M; ++i)
-    if (m[i] < nmask) {
+    if (x[i] < nmask) {
       MaskScore32 r;
       r.e = e[i];
       r.slack = slack[i];
@@ -732,7 +738,7 @@ __global__ __launch_bounds__(kScoreThreads) void k_score_fp32(
   const double dlt = sp.delta + sp.amb;
 #pragma unroll
   for (int i = 0; i < M; ++i) {
-    const bool valid = m[i] < nmask;
+    const bool valid = x[i] < nmask;
     MaskScore32 r;
     r.e = 0.f;
     r.slack = INFINITY;
@@ -753,7 +759,7 @@ __global__ __launch_bounds__(kScoreThreads) void k_score_fp32(
       b = max(b, __shfl_xor(b, o, 64));
       c = max(c, __shfl_xor(c, o, 64));
     }
-    const uint32_t tile = m[i] / kScoreBlock;
+    const uint32_t tile = x[i] / kScoreBlock;
     if ((tid & 63) == 0 && tile * kScoreBlock < nmask) {
       TileRec32 t;
       t.sure = a;
