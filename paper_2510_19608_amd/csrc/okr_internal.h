@@ -39,11 +39,19 @@ struct SegHdr {
 
 // Mask of scoring tile t, lane q: q's bits at the positions of the segment's
 // lane bits L, t's bits at the other positions of the k mask bits.
-__host__ __device__ __forceinline__ uint32_t tile_mask(uint32_t L, uint32_t t, uint32_t q, int k) {
+// (lane_part: q's bits at L's positions; tile_part: t's bits at the others)
+__host__ __device__ __forceinline__ uint32_t lane_part(uint32_t L, uint32_t q) {
   uint32_t m = 0;
   for (uint32_t l = L; l; l &= l - 1, q >>= 1) m |= (q & 1u) << __builtin_ctz(l);
+  return m;
+}
+__host__ __device__ __forceinline__ uint32_t tile_part(uint32_t L, uint32_t t, int k) {
+  uint32_t m = 0;
   for (uint32_t o = ((k >= 32 ? 0u : (1u << k)) - 1u) & ~L; o; o &= o - 1, t >>= 1) m |= (t & 1u) << __builtin_ctz(o);
   return m;
+}
+__host__ __device__ __forceinline__ uint32_t tile_mask(uint32_t L, uint32_t t, uint32_t q, int k) {
+  return tile_part(L, t, k) | lane_part(L, q);
 }
 
 // A search step launched over a chunk of mutually independent segments:

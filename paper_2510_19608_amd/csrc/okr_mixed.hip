@@ -124,8 +124,10 @@ __global__ __launch_bounds__(1024) void k_mixed_select_a(const SegHdr* __restric
                                                          uint32_t* __restrict__ listA, int* __restrict__ countA) {
   __shared__ int shi[16];
   __shared__ int cnt;
+  __shared__ uint32_t s_lp[64];  // lane part of the mask of each of a tile's lanes
   const int g = segs[blockIdx.z];
   const SegHdr H = load_hdr_g(hdrs, g);
+  if (threadIdx.x < 64) s_lp[threadIdx.x] = lane_part((uint32_t)H.lanebits, threadIdx.x);
   fin = lane_ptr(fin, lstride);
   tiles = lane_ptr(tiles, lstride);
   listA = lane_ptr(listA, lstride);
@@ -149,9 +151,10 @@ __global__ __launch_bounds__(1024) void k_mixed_select_a(const SegHdr* __restric
   const double dd = sp.delta + sp.amb;
   for (int t = threadIdx.x; t < ntiles; t += blockDim.x) {
     if (tiles[t].unc < lo || tiles[t].unc < 0) continue;
+    const uint32_t tb = tile_part(L, (uint32_t)t, H.k);
     for (int j = 0; j < 64; ++j) {
       if (j >> lb) break;
-      const uint32_t mm = tile_mask(L, (uint32_t)t, (uint32_t)j, H.k);
+      const uint32_t mm = tb | s_lp[j];
       const MaskScore32 r = fin[mm];
       const bool sure = (double)r.e <= sp.e_bar - dd && (double)r.slack >= dd;
       const bool poss = (double)r.e <= sp.e_bar + dd && (double)r.slack >= -dd;
@@ -179,8 +182,10 @@ __global__ __launch_bounds__(1024) void k_mixed_select_b(const SegHdr* __restric
   __shared__ int shi[16];
   __shared__ double shd[16];
   __shared__ int cnt;
+  __shared__ uint32_t s_lp[64];  // lane part of the mask of each of a tile's lanes
   const int g = segs[blockIdx.z];
   const SegHdr H = load_hdr_g(hdrs, g);
+  if (threadIdx.x < 64) s_lp[threadIdx.x] = lane_part((uint32_t)H.lanebits, threadIdx.x);
   fin = lane_ptr(fin, lstride);
   tiles = lane_ptr(tiles, lstride);
   listA = lane_ptr(listA, lstride);
@@ -208,9 +213,10 @@ __global__ __launch_bounds__(1024) void k_mixed_select_b(const SegHdr* __restric
   if (best >= 0) {
     for (int t = threadIdx.x; t < ntiles; t += blockDim.x) {
       if (tiles[t].sure < best) continue;
+      const uint32_t tb = tile_part(L, (uint32_t)t, H.k);
       for (int j = 0; j < 64; ++j) {
         if (j >> lb) break;
-        const uint32_t mm = tile_mask(L, (uint32_t)t, (uint32_t)j, H.k);
+        const uint32_t mm = tb | s_lp[j];
         const MaskScore32 r = fin[mm];
         if (__popc(mm) == best && (double)r.e <= sp.e_bar - dd && (double)r.slack >= dd)
           eup = fmin(eup, (double)r.e + sp.delta);
@@ -224,9 +230,10 @@ __global__ __launch_bounds__(1024) void k_mixed_select_b(const SegHdr* __restric
   if (best >= 0) {
     for (int t = threadIdx.x; t < ntiles; t += blockDim.x) {
       if (tiles[t].poss < best) continue;
+      const uint32_t tb = tile_part(L, (uint32_t)t, H.k);
       for (int j = 0; j < 64; ++j) {
         if (j >> lb) break;
-        const uint32_t mm = tile_mask(L, (uint32_t)t, (uint32_t)j, H.k);
+        const uint32_t mm = tb | s_lp[j];
         const MaskScore32 r = fin[mm];
         const bool poss = (double)r.e <= sp.e_bar + dd && (double)r.slack >= -dd;
         if (poss && __popc(mm) == best && (double)r.e <= bound) listB[atomicAdd(&cnt, 1)] = mm;
