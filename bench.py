@@ -29,6 +29,7 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 FP64_VECTOR_PEAK_TFLOPS = 78.6   # MI355X FP64 vector (256 CUs x 2.4 GHz x 128 flop/clk)
+BF16_MFMA_PEAK_TFLOPS = 2500.0   # MI355X dense BF16 matrix peak
 
 # HBM bytes per launch of the FP64 scoring kernel on this workload, from the
 # FETCH_SIZE / WRITE_SIZE counters scaled by a known-size copy (see
@@ -159,8 +160,16 @@ def train_surrogate(args):
     torch.cuda.synchronize()
     t_train = time.perf_counter() - t0
     margin = surrogate.calibrate(params, X, t, 0.999)
+    # MFMA work of training: forward 2 (32*256 + 256*256 + 256) flops per row,
+    # the backward pass twice that (both operand gradients of each layer)
+    fwd = 2.0 * (32 * 256 + 256 * 256 + 256)
+    tflops = 3.0 * fwd * int(X.shape[0]) * args.surr_epochs / t_train / 1e12
     info = dict(train_pairs=int(X.shape[0]), train_epochs=args.surr_epochs, train_loss_first=float(loss[0]),
-                train_loss_last=float(loss[-1]), train_s=t_train, collect_s=t_collect, margin=margin)
+                train_loss_last=float(loss[-1]), train_s=t_train, collect_s=t_collect, margin=margin,
+                train_roofline={"bound": "mfma", "achieved": tflops, "peak": BF16_MFMA_PEAK_TFLOPS, "unit": "TFLOP/s",
+                                "frac": tflops / BF16_MFMA_PEAK_TFLOPS,
+                                "flop_count": "3 x 2 (32*256 + 256*256 + 256) per row and epoch (forward, both "
+                                              "backward products); Adam and the loss not counted"})
     del X, t
     return params, margin, info
 
