@@ -125,7 +125,7 @@ size_t align256(size_t x) { return (x + 255) & ~size_t(255); }
 // each; the per-mask FP64 kernel carries one): by default about 256 mask
 // blocks per 24 snapshots and at most about 24 snapshots per block, each
 // group a contiguous run of snapshots.  target_blocks > 0 sets the block
-// count instead (the FP32 screen uses 512).
+// count instead (the FP32 screen uses 128).
 int snap_groups_default(int k, int S, int* spg, int mpl = 1, int target_blocks = 0) {
   const int mblocks = (int)((((uint64_t)1 << k) + kScoreThreads * mpl - 1) / (kScoreThreads * mpl));
   // (the shapes the autotuner picks on MI355X, within a few percent)
@@ -149,11 +149,13 @@ int score64_groups_default(int k, int S, int* spg) {
 }
 
 // Launch shape of the FP32 screen: masks per lane by segment size and about
-// 512 mask blocks.  The workspace planner sizes the screen's partial scores
-// from this same function.
+// 128 mask blocks (few snapshot groups: a group's snapshots are the lanes of
+// the once-per-wave chains; measured best on the 1000- and 8400-node
+// workloads, within 2% of the best on the 6000-node one).  The workspace
+// planner sizes the screen's partial scores from this same function.
 int screen32_shape(int k, int S, int* spg, int* mpl) {
   *mpl = k >= 12 ? 4 : (k >= 10 ? 2 : 1);
-  return snap_groups_default(k, S, spg, *mpl, 512);
+  return snap_groups_default(k, S, spg, *mpl, 128);
 }
 
 struct Layout {
