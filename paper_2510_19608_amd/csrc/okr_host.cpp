@@ -23,6 +23,9 @@ __global__ void k_branch_z(int, const int*, const uint8_t*, const int*, const in
 __global__ void k_powerflow(int, const int*, const uint8_t*, const int*, const int*, int, const int*, const int*,
                             const double2*, const double2*, double2, double2, double2, double, int, double, double,
                             double2*, double2*, double2*, double*, int*, int*);
+__global__ void k_powerflow_lds(int, const int*, const uint8_t*, const int*, const int*, int, const int*, const int*,
+                                const double2*, const double2*, double2, double2, double2, double, int, double, double,
+                                double2*, double2*, double2*, double*, int*, int*);
 __global__ void k_from_vhat(int, int, const uint8_t*, const double2*, const double2*, double, double, double2*,
                             double*, int*);
 __global__ void k_build_struct(Topo, State, const int*, size_t, int, SegHdr*, int*, int, int*);
@@ -117,6 +120,13 @@ constexpr int kDefaultLanes = 8;
 constexpr int kStatusInts = 16;
 constexpr double kMixedDelta = 1e-8;  // bound on |e32 - e64| used by the shortlist
 constexpr double kSmiceTol = 1e-9;    // default SMICE tie window
+// Dynamic LDS of the load flow with its iterates in shared memory (0: too
+// large, the global-memory form runs).
+constexpr size_t kPfLdsMax = 150 * 1024;
+size_t pf_lds_bytes(int n) {
+  const size_t b = (size_t)n * 3 * 2 * sizeof(double2);
+  return b <= kPfLdsMax ? b : 0;
+}
 constexpr int kSmiceThreadsHost = 128;  // masks per block of the SMICE scoring
 
 size_t align256(size_t x) { return (x + 255) & ~size_t(255); }
@@ -943,6 +953,13 @@ void enqueue_search(okr_handle* h, void* ws, const okr_yblocks* Y, const okr_loa
                        p.status);
   } else {
     const double2* V0 = (const double2*)loads->V0;
+    const size_t pf_lds = pf_lds_bytes(n);
+    if (pf_lds)
+      hipLaunchKernelGGL(k_powerflow_lds, dim3(S), dim3(256), pf_lds, st, n, p.T.parent, p.T.phase, p.lvl_off,
+                         p.lvl_nodes, h->nlev, p.T.ch_off, p.T.ch, (const double2*)p.z, (const double2*)loads->S_load,
+                         V0[0], V0[1], V0[2], mg->pf_tol > 0 ? mg->pf_tol : 1e-13, mg->pf_maxit > 0 ? mg->pf_maxit : 100,
+                         mg->v_min, mg->v_max, p.Vhat, p.J, p.A, p.absV, p.iters, p.status);
+    else
     hipLaunchKernelGGL(k_powerflow, dim3(S), dim3(256), 0, st, n, p.T.parent, p.T.phase, p.lvl_off, p.lvl_nodes,
                        h->nlev, p.T.ch_off, p.T.ch, (const double2*)p.z, (const double2*)loads->S_load, V0[0], V0[1],
                        V0[2], mg->pf_tol > 0 ? mg->pf_tol : 1e-13, mg->pf_maxit > 0 ? mg->pf_maxit : 100,
@@ -1285,6 +1302,9 @@ static int reduce_feeder_impl(okr_handle* h, const okr_yblocks* Y, const okr_top
   const int n = h->n, S = h->S, nseg = h->nseg;
   hipStream_t st = h->stream;
   const Ptrs p = pointers(h, d_workspace);
+  if (pf_lds_bytes(n) > 64 * 1024 && !(mg->flags & OKR_FLAG_VHAT_GIVEN))  // (set before any capture)
+    OKR_HIP(h, hipFuncSetAttribute(reinterpret_cast<const void*>(&k_powerflow_lds),
+                                   hipFuncAttributeMaxDynamicSharedMemorySize, (int)kPfLdsMax));
   const auto t0 = clk::now();
   OKR_HIP(h, hipMemcpyAsync((void*)p.T.parent, h->topo_host.data(), sizeof(int) * h->TO.total,
                             hipMemcpyHostToDevice, st));

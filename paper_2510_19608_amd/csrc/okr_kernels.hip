@@ -118,18 +118,21 @@ __global__ void k_branch_z(int n, const int* __restrict__ parent, const uint8_t*
 // Scenario library (Section III): constant-PQ wye loads, backward/forward
 // sweep on the radial tree, one block per snapshot, level-synchronous.
 // status bit 16: not converged; bit 32: base network outside the band.
-__global__ __launch_bounds__(256) void k_powerflow(
+template <bool LDS>
+__device__ __forceinline__ void powerflow_body(
     int n, const int* __restrict__ parent, const uint8_t* __restrict__ phase,
     const int* __restrict__ lvl_off, const int* __restrict__ lvl_nodes, int nlev,
     const int* __restrict__ ch_off, const int* __restrict__ ch, const double2* __restrict__ z,
     const double2* __restrict__ Sload, double2 v0a, double2 v0b, double2 v0c, double tol, int maxit,
     double vmin, double vmax, double2* __restrict__ V, double2* __restrict__ J,
-    double2* __restrict__ A, double* __restrict__ absV, int* __restrict__ iters, int* __restrict__ status) {
-  __shared__ double shd[16];
+    double2* __restrict__ A, double* __restrict__ absV, int* __restrict__ iters, int* __restrict__ status,
+    double2* sbuf, double* shd) {
   const int l = blockIdx.x;
   const size_t base = (size_t)l * n * 3;
-  double2* Vl = V + base;
-  double2* Jl = J + base;
+  // (with LDS the iterates live in shared memory: every level step of the
+  // sweeps then waits on LDS instead of global memory)
+  double2* Vl = LDS ? sbuf : V + base;
+  double2* Jl = LDS ? sbuf + (size_t)n * 3 : J + base;
   const double2* Sl = Sload + base;
   const double2 v0[3] = {v0a, v0b, v0c};
   for (int i = threadIdx.x; i < n; i += blockDim.x)
@@ -183,6 +186,7 @@ __global__ __launch_bounds__(256) void k_powerflow(
     for (int p = 0; p < 3; ++p) {
       const bool pr = (phase[i] >> p & 1u);
       const double2 v = Vl[i * 3 + p];
+      if (LDS) V[base + i * 3 + p] = v;
       A[base + i * 3 + p] = (i > 0 && pr) ? cconj(cdiv(Sl[i * 3 + p], v)) : make_double2(0.0, 0.0);
       const double m = pr ? sqrt(cabs2(v)) : 0.0;
       absV[base + i * 3 + p] = m;
@@ -195,6 +199,34 @@ __global__ __launch_bounds__(256) void k_powerflow(
     if (!conv) atomicOr(status, 16);
     if (vlo < vmin || vhi > vmax) atomicOr(status, 32);
   }
+}
+
+
+__global__ __launch_bounds__(256) void k_powerflow(
+    int n, const int* __restrict__ parent, const uint8_t* __restrict__ phase,
+    const int* __restrict__ lvl_off, const int* __restrict__ lvl_nodes, int nlev,
+    const int* __restrict__ ch_off, const int* __restrict__ ch, const double2* __restrict__ z,
+    const double2* __restrict__ Sload, double2 v0a, double2 v0b, double2 v0c, double tol, int maxit,
+    double vmin, double vmax, double2* __restrict__ V, double2* __restrict__ J,
+    double2* __restrict__ A, double* __restrict__ absV, int* __restrict__ iters, int* __restrict__ status) {
+  __shared__ double shd[16];
+  powerflow_body<false>(n, parent, phase, lvl_off, lvl_nodes, nlev, ch_off, ch, z, Sload, v0a, v0b, v0c, tol, maxit,
+                        vmin, vmax, V, J, A, absV, iters, status, nullptr, shd);
+}
+
+// The same with the voltage and current iterates in dynamic LDS (2 x n x 3
+// double2; for feeders small enough to fit).
+__global__ __launch_bounds__(256) void k_powerflow_lds(
+    int n, const int* __restrict__ parent, const uint8_t* __restrict__ phase,
+    const int* __restrict__ lvl_off, const int* __restrict__ lvl_nodes, int nlev,
+    const int* __restrict__ ch_off, const int* __restrict__ ch, const double2* __restrict__ z,
+    const double2* __restrict__ Sload, double2 v0a, double2 v0b, double2 v0c, double tol, int maxit,
+    double vmin, double vmax, double2* __restrict__ V, double2* __restrict__ J,
+    double2* __restrict__ A, double* __restrict__ absV, int* __restrict__ iters, int* __restrict__ status) {
+  extern __shared__ double2 pf_lds[];
+  __shared__ double shd[16];
+  powerflow_body<true>(n, parent, phase, lvl_off, lvl_nodes, nlev, ch_off, ch, z, Sload, v0a, v0b, v0c, tol, maxit,
+                       vmin, vmax, V, J, A, absV, iters, status, pf_lds, shd);
 }
 
 // Cumulative series impedance from the root, Zroot(v) = Zroot(parent) + z(v)

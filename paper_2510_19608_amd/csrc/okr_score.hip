@@ -731,10 +731,14 @@ __global__ __launch_bounds__(kScoreThreads) void k_score_fp32(
       r.slack = slack[i];
       part[(size_t)sg * nmask + m[i]] = r;
     }
+  // every wave's partial scores are written and visible before the block
+  // takes its ticket (the last block to take one reads them all)
   __threadfence();
+  __syncthreads();
   if (tid == 0) ticket = atomicAdd(&tickets[blockIdx.x], 1);
   __syncthreads();
   if (ticket != SG - 1) return;
+  __threadfence();
   const double dlt = sp.delta + sp.amb;
 #pragma unroll
   for (int i = 0; i < M; ++i) {
