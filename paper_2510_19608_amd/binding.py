@@ -342,12 +342,20 @@ class Reducer:
         self.loads = Loads(S, self.Sl.data_ptr(), self.V0.ctypes.data,
                            self.Vh.data_ptr() if self.Vh is not None else None)
         nseg = self.sizes.n_segments
-        self.out_super = np.zeros(n, np.int32)
-        self.out_kp = np.zeros(n, np.int32)
-        self.out_Ykd = np.zeros((n, 3, 3), np.complex128)
-        self.out_Yko = np.zeros((n, 3, 3), np.complex128)
-        self.out_err = np.zeros(S)
-        self.out_Vhat = np.zeros((S, n, 3), np.complex128)
+
+        def host(shape, dtype):
+            # page-locked host buffers (torch allocates them): the library's
+            # device-to-host copies of the outputs then go straight to them
+            t = torch.zeros(shape, dtype=dtype, pin_memory=True)
+            self._pinned.append(t)
+            return t.numpy()
+        self._pinned = []
+        self.out_super = host((n,), torch.int32)
+        self.out_kp = host((n,), torch.int32)
+        self.out_Ykd = host((n, 3, 3), torch.complex128)
+        self.out_Yko = host((n, 3, 3), torch.complex128)
+        self.out_err = host((S,), torch.float64)
+        self.out_Vhat = host((S, n, 3), torch.complex128)
         self.out_seg = (SegmentResult * max(nseg, 1))()
         self.res = Result(self.out_super.ctypes.data, self.out_kp.ctypes.data, self.out_Ykd.ctypes.data,
                           self.out_Yko.ctypes.data, self.out_err.ctypes.data, None,
