@@ -12,6 +12,8 @@
 namespace okr {
 
 // ---------------------------------------------------------------- scoring --
+constexpr int kStageBatch = 2;  // LDS-stage chunks each thread loads before it stores any
+
 // Tile record of one wave's 64 masks (lane q holds mask
 // tile_mask(lanebits, tile, q, k), final score r): highest feasible level,
 // smallest error at that level, highest level of a mask near the e_bar /
@@ -117,28 +119,46 @@ __global__ __launch_bounds__(kScoreThreads) void k_score_fp64(
     qmn[j] = INFINITY;
     qmx[j] = -INFINITY;
   }
+  // LDS offsets of the staged tables in 16-byte units (capacities)
+  const int oT = pcap * 3 * M, oH = oT + kcap * 3 * M * 2, oZ = oH + kcap * 3 * M;
+  constexpr int LM = M == 4 ? 2 : (M == 2 ? 1 : 0);
+  const int nP = cP << LM, nT = cT << LM, nH = cH << LM, nZ = cZ << LM;
+  const int nst = nP + nT + nH + nZ;
   for (int l = l0; l < l1; l += M) {
-    // one loop per table; element i = r * M + j (snapshot j fastest, M a
-    // power of two), so the LDS writes are contiguous
-    constexpr int LM = M == 4 ? 2 : (M == 2 ? 1 : 0);
-    for (int i = tid; i < (cP << LM); i += kScoreThreads) {
-      const int r = i >> LM, j = i & (M - 1);
-      ((uint4*)Ps)[i] = ((const uint4*)(P + (size_t)min(l + j, l1 - 1) * H.npairs * 3))[r];
-    }
-    for (int i = tid; i < (cT << LM); i += kScoreThreads) {  // 2 chunks per record
-      const int e = i >> (LM + 1), j = (i >> 1) & (M - 1), h = i & 1;
-      ((uint4*)Ts)[i] = ((const uint4*)(srec + (size_t)min(l + j, l1 - 1) * H.nslots * 3))[2 * e + h];
-    }
-    for (int i = tid; i < (cH << LM); i += kScoreThreads) {
-      const int r = i >> LM, j = i & (M - 1);
-      const uint4 v = ((const uint4*)(headV + (size_t)min(l + j, l1 - 1) * H.nchains * 3))[r];
-      ((uint4*)Hv)[i] = v;
-      const double2 hv = make_double2(__hiloint2double((int)v.y, (int)v.x), __hiloint2double((int)v.w, (int)v.z));
-      Hm[i] = (hv.x != 0.0 || hv.y != 0.0) ? hmag(hv) : 0.0;
-    }
-    for (int i = tid; i < (cZ << LM); i += kScoreThreads) {  // 2 chunks per record
-      const int e = i >> (LM + 1), j = (i >> 1) & (M - 1), h = i & 1;
-      ((uint4*)Zs)[i] = ((const uint4*)(zrec + (size_t)min(l + j, l1 - 1) * H.nz))[2 * e + h];
+    // Stage the pass's tables: chunk i of one index space over the four
+    // tables (element r * M + j of each, snapshot j fastest, M a power of
+    // two, so the LDS writes are contiguous).  Each thread issues the loads
+    // of kStageBatch chunks before it writes any, so their latencies overlap.
+    for (int b = 0; b < nst; b += kStageBatch * kScoreThreads) {
+      uint4 v[kStageBatch];
+      int dst[kStageBatch];
+#pragma unroll
+      for (int u = 0; u < kStageBatch; ++u) {
+        // chunk i (past the end: the last chunk is loaded again, not stored);
+        // its table by selects, no branches, so the loads issue back to back
+        const int i = min(b + u * kScoreThreads + tid, nst - 1);
+        const int iT = i - nP, iH = iT - nT, iZ = iH - nH;
+        const bool isP = i < nP, isT = !isP && iT < nT, isH = !isP && !isT && iH < nH;
+        const bool rec = !isP && !isH;  // slot and zone records: 2 chunks each
+        const int ii = isP ? i : (isT ? iT : (isH ? iH : iZ));
+        const int j = rec ? (ii >> 1) & (M - 1) : ii & (M - 1);
+        const int chunk = rec ? ((ii >> (LM + 1)) << 1) + (ii & 1) : ii >> LM;
+        const uint4* base =
+            isP ? (const uint4*)P : (isT ? (const uint4*)srec : (isH ? (const uint4*)headV : (const uint4*)zrec));
+        const int per = isP ? cP : (isT ? H.nslots * 6 : (isH ? cH : H.nz * 2));  // chunks per snapshot
+        dst[u] = b + u * kScoreThreads + tid < nst ? (isP ? 0 : (isT ? oT : (isH ? oH : oZ))) + ii : -1;
+        v[u] = base[(size_t)min(l + j, l1 - 1) * per + chunk];
+      }
+#pragma unroll
+      for (int u = 0; u < kStageBatch; ++u) {
+        if (dst[u] < 0) continue;
+        ((uint4*)sv_lds)[dst[u]] = v[u];
+        if (dst[u] >= oH && dst[u] < oZ) {  // a chain head: its magnitude too
+          const double2 hv =
+              make_double2(__hiloint2double((int)v[u].y, (int)v[u].x), __hiloint2double((int)v[u].w, (int)v[u].z));
+          Hm[dst[u] - oH] = (hv.x != 0.0 || hv.y != 0.0) ? hmag(hv) : 0.0;
+        }
+      }
     }
     if (tid < M) Ec[tid] = econst[min(l + tid, l1 - 1)];
     __syncthreads();
