@@ -2,6 +2,7 @@
 // of the plan, workspace layout, and the launch sequence of a search (one
 // stream of kernels, optionally replayed as a captured hipGraph; one host
 // synchronisation at the end).
+#include <hip/hip_ext.h>
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -53,7 +54,7 @@ __global__ void k_argmin(const SegHdr*, const int*, size_t, const MaskScore*, co
                          DevDecision*, const int*);
 __global__ void k_apply(const SegHdr*, const int*, size_t, const int*, Topo, State, const DevDecision*,
                         const double2*, const TargetRec*, const TargetRec*, double2*, double2*);
-__global__ void k_init_state(int, State, int*, int, int*, int);
+__global__ void k_init_state(int, State, int*, int, int*, int, int, size_t);
 __global__ void k_copy2(const double2*, double2*, size_t);
 __global__ void k_final_err(int, const uint8_t*, const int*, const double2*, const double*, double*);
 __global__ void k_kron_yeq(Topo, State, const double2*, double2*, double2*, int*, int*);
@@ -176,6 +177,9 @@ struct Layout {
   size_t pat, ecmax, lacc;
   // mixed precision
   size_t P32, S32, H32, Z32, part32, fin32, tiles32, listA, listB, scoreA, scoreB, counts, mstate;
+  // results the host reads after a search, contiguous (one transfer):
+  // status .. err, from res0, res_bytes long
+  size_t res0, res_bytes;
   // surrogate: feature tables (always), ranking buffers (when planned with top_k)
   size_t spz, szs, sss, skeys, slist, sscore, scount, sgates, sW1b, sW2b, sW2tb, slevel,
       sstage;
@@ -206,6 +210,15 @@ struct okr_handle {
   Layout L{};
   TopoOffsets TO{};
   std::vector<int> topo_host;  // packed static arrays uploaded at each call
+  // page-locked host copy of the result block (allocated by the first call
+  // that may allocate; the no-allocation entry point copies region by region)
+  void* rstage = nullptr;
+  size_t rstage_bytes = 0;
+  // page-locked copy of topo_host (the upload at each call is then a plain
+  // asynchronous transfer); filled again after every plan
+  void* tstage = nullptr;
+  size_t tstage_bytes = 0;
+  bool tstage_fresh = false;
   // timing
   std::vector<hipEvent_t> ev;
   // captured graph of one whole search, and the arguments it was captured with
@@ -344,6 +357,8 @@ extern "C" int okr_destroy(okr_handle* h) {
   if (!h) return OKR_E_ARG;
   drop_graph(h);
   drop_events(h);
+  if (h->rstage) (void)hipHostFree(h->rstage);
+  if (h->tstage) (void)hipHostFree(h->tstage);
   delete h;
   return OKR_OK;
 }
@@ -437,6 +452,7 @@ extern "C" int okr_plan(okr_handle* h, const okr_topology* topo, const okr_margi
                         size_t* workspace_bytes, okr_sizes* sizes) {
   if (!h) return OKR_E_ARG;
   h->planned = false;
+  h->tstage_fresh = false;
   drop_graph(h);
   if (!topo || !mg || !workspace_bytes || S < 1) OKR_FAIL(h, OKR_E_ARG, "null argument or S < 1");
   if (mg->secondary != OKR_SECONDARY_MAXERR && mg->secondary != OKR_SECONDARY_SMICE)
@@ -673,13 +689,8 @@ extern "C" int okr_plan(okr_handle* h, const okr_topology* topo, const okr_margi
   L.J = take(sizeof(double2) * c3);
   L.absV = take(sizeof(double) * c3);
   L.kept = take(n);
-  L.sup = take(sizeof(int) * n);
   L.slot_of = take(sizeof(int) * n);
   L.zent_of = take(sizeof(int) * 3 * n);
-  L.status = take(sizeof(int) * kStatusInts);
-  L.iters = take(sizeof(int) * S);
-  L.hdrs = take(sizeof(SegHdr) * std::max(nseg, 1));
-  L.decs = take(sizeof(DevDecision) * std::max(nseg, 1));
   // per-segment scratch (one block per chunk position z, at + z * lane_stride)
   L.lane0 = off;
   L.tab = take(sizeof(int) * h->tab_cap);
@@ -754,17 +765,25 @@ extern "C" int okr_plan(okr_handle* h, const okr_topology* topo, const okr_margi
   L.lane_stride = off - L.lane0;
   off = L.lane0 + L.lane_stride * (size_t)h->nlanes;
   // per-segment records and shared weights
-  L.mstate = take(sizeof(MixedState) * std::max(nseg, 1));
   L.sstage = take(sizeof(int) * std::max(nseg, 1));
-  L.sgates = take(sizeof(int) * std::max(nseg, 1));
   L.sW1b = take(sizeof(uint16_t) * kSurrH * kSurrF * (h->topk ? 1 : 0));
   L.sW2b = take(sizeof(uint16_t) * kSurrH * kSurrH * (h->topk ? 1 : 0));
   L.sW2tb = take(8);
-  L.kp = take(sizeof(int) * n);
   L.yeq = take(sizeof(double2) * 9 * n);
+  // the results the host reads, contiguous
+  L.res0 = off;
+  L.status = take(sizeof(int) * kStatusInts);
+  L.iters = take(sizeof(int) * S);
+  L.hdrs = take(sizeof(SegHdr) * std::max(nseg, 1));
+  L.decs = take(sizeof(DevDecision) * std::max(nseg, 1));
+  L.mstate = take(sizeof(MixedState) * std::max(nseg, 1));
+  L.sgates = take(sizeof(int) * std::max(nseg, 1));
+  L.sup = take(sizeof(int) * n);
+  L.kp = take(sizeof(int) * n);
   L.Ykd = take(sizeof(double2) * 9 * n);
   L.Yko = take(sizeof(double2) * 9 * n);
   L.err = take(sizeof(double) * S);
+  L.res_bytes = off - L.res0;
   L.total = off;
   *workspace_bytes = L.total;
   if (sizes) {
@@ -937,10 +956,7 @@ void enqueue_search(okr_handle* h, void* ws, const okr_yblocks* Y, const okr_loa
   const int ntick = (int)((((size_t)1 << h->kmax) + 63) / 64);
   const int ninit = std::max(n, std::max(kStatusInts, ntick));
   hipLaunchKernelGGL(k_init_state, dim3((ninit + 255) / 256), dim3(256), 0, st, n, p.St, p.status, kStatusInts,
-                     p.tickets, ntick);
-  for (int l = 1; l < h->nlanes; ++l)  // the other lanes' ticket counters
-    hipLaunchKernelGGL(k_init_state, dim3((ntick + 255) / 256), dim3(256), 0, st, 0, p.St, p.status, 0,
-                       lp[l].tickets, ntick);
+                     p.tickets, ntick, h->nlanes, h->L.lane_stride);
   hipLaunchKernelGGL(k_branch_z, dim3((n + 127) / 128), dim3(128), 0, st, n, p.T.parent, p.T.phase, p.T.ch_off,
                      p.T.ch, (const double2*)Y->Y_diag, (const double2*)Y->Y_off, p.z, p.status);
   hipLaunchKernelGGL(k_zroot, dim3(1), dim3(256), 0, st, n, p.T.parent, p.lvl_off, p.lvl_nodes, h->nlev,
@@ -1074,7 +1090,12 @@ void enqueue_search(okr_handle* h, void* ws, const okr_yblocks* Y, const okr_loa
                          (const MaskScore*)w.sscore, w.decs, w.sgates + g);
     }
     if (!mixed) {
-      if (ev) (void)hipEventRecord((*ev)[2 * c], st);
+      // timing: the factored form's three launches between two recorded
+      // events; the per-mask kernel's own start and end through its launch
+      // (no marker packets around it)
+      if (ev && factored) (void)hipEventRecord((*ev)[2 * c], st);
+      hipEvent_t e0 = (ev && !factored) ? (*ev)[2 * c] : nullptr;
+      hipEvent_t e1 = (ev && !factored) ? (*ev)[2 * c + 1] : nullptr;
       if (factored) {
         // pattern table (up to 2^(k+1) patterns; one block column per snapshot), then every mask
         const int pb = (int)std::min<uint64_t>(16, std::max<uint64_t>(1, ((uint64_t)2 << kc) / 256));
@@ -1090,16 +1111,17 @@ void enqueue_search(okr_handle* h, void* ws, const okr_yblocks* Y, const okr_loa
                            (const unsigned long long*)q.ecmax, sp, q.fin, q.tiles);
       } else {
 #define OKR_SCORE64(M_)                                                                                             \
-  hipLaunchKernelGGL(k_score_fp64<M_>, dim3(mblocks, SG, nz), dim3(kScoreThreads), lds, st, (const SegHdr*)q.hdrs, segs, \
-                     lstride, (const int*)q.tab, (const double2*)q.P, (const TargetRec*)q.srec,                      \
-                     (const double2*)q.headV, (const TargetRec*)q.zrec, (const double*)q.econst, spg, SG, pcap, kc,   \
-                     kSvZone, sws, sp, q.part, q.fin, q.tiles, q.tickets, gates, full_fin)
+  hipExtLaunchKernelGGL(k_score_fp64<M_>, dim3(mblocks, SG, nz), dim3(kScoreThreads), lds, st, e0, e1, 0,            \
+                        (const SegHdr*)q.hdrs, segs, lstride, (const int*)q.tab, (const double2*)q.P,              \
+                        (const TargetRec*)q.srec, (const double2*)q.headV, (const TargetRec*)q.zrec,               \
+                        (const double*)q.econst, spg, SG, pcap, kc, kSvZone, sws, sp, q.part, q.fin, q.tiles,      \
+                        q.tickets, gates, full_fin)
         if (spp == 4) OKR_SCORE64(4);
         else if (spp == 2) OKR_SCORE64(2);
         else OKR_SCORE64(1);
 #undef OKR_SCORE64
       }
-      if (ev) (void)hipEventRecord((*ev)[2 * c + 1], st);
+      if (ev && factored) (void)hipEventRecord((*ev)[2 * c + 1], st);
       hipLaunchKernelGGL(k_argmin, dim3(1, 1, nz), dim3(1024), 0, st, (const SegHdr*)q.hdrs, segs, lstride,
                          (const MaskScore*)q.fin, (const TileRec*)q.tiles, sp, (const int*)q.status, q.decs, gates);
       if (mg->secondary == OKR_SECONDARY_SMICE && !surr) {
@@ -1217,12 +1239,12 @@ uint64_t bits(double x) {
 
 static int reduce_feeder_impl(okr_handle* h, const okr_yblocks* Y, const okr_topology* topo,
                               const okr_loads* loads, const okr_margins* mg, void* d_workspace,
-                              size_t workspace_bytes, okr_result* out);
+                              size_t workspace_bytes, okr_result* out, bool may_alloc);
 
 extern "C" int okr_reduce_feeder(okr_handle* h, const okr_yblocks* Y, const okr_topology* topo,
                                  const okr_loads* loads, const okr_margins* mg, void* d_workspace,
                                  size_t workspace_bytes, okr_result* out) {
-  return reduce_feeder_impl(h, Y, topo, loads, mg, d_workspace, workspace_bytes, out);
+  return reduce_feeder_impl(h, Y, topo, loads, mg, d_workspace, workspace_bytes, out, true);
 }
 
 // The no-allocation entry point's workspace: one array per GPU, resolved to
@@ -1260,12 +1282,12 @@ extern "C" int okr_reduce_feeder_noalloc(okr_handle* h, const okr_yblocks* Y, co
     }
     ws = g_scratch_ptr[dev];
   }
-  return reduce_feeder_impl(h, Y, topo, loads, mg, ws, OKR_NOALLOC_SCRATCH_BYTES, out);
+  return reduce_feeder_impl(h, Y, topo, loads, mg, ws, OKR_NOALLOC_SCRATCH_BYTES, out, false);
 }
 
 static int reduce_feeder_impl(okr_handle* h, const okr_yblocks* Y, const okr_topology* topo,
                               const okr_loads* loads, const okr_margins* mg, void* d_workspace,
-                              size_t workspace_bytes, okr_result* out) {
+                              size_t workspace_bytes, okr_result* out, bool may_alloc) {
   using clk = std::chrono::steady_clock;
   if (!h) return OKR_E_ARG;
   if (!h->planned) OKR_FAIL(h, OKR_E_ARG, "okr_plan() must succeed first");
@@ -1306,8 +1328,24 @@ static int reduce_feeder_impl(okr_handle* h, const okr_yblocks* Y, const okr_top
     OKR_HIP(h, hipFuncSetAttribute(reinterpret_cast<const void*>(&k_powerflow_lds),
                                    hipFuncAttributeMaxDynamicSharedMemorySize, (int)kPfLdsMax));
   const auto t0 = clk::now();
-  OKR_HIP(h, hipMemcpyAsync((void*)p.T.parent, h->topo_host.data(), sizeof(int) * h->TO.total,
-                            hipMemcpyHostToDevice, st));
+  {
+    const size_t tb = sizeof(int) * h->TO.total;
+    if (may_alloc && h->tstage_bytes < tb) {
+      if (h->tstage) (void)hipHostFree(h->tstage);
+      h->tstage = nullptr;
+      h->tstage_bytes = 0;
+      OKR_HIP(h, hipHostMalloc(&h->tstage, tb, hipHostMallocDefault));
+      h->tstage_bytes = tb;
+      h->tstage_fresh = false;
+    }
+    if (may_alloc && h->tstage) {
+      if (!h->tstage_fresh) std::memcpy(h->tstage, h->topo_host.data(), tb);
+      h->tstage_fresh = true;
+      OKR_HIP(h, hipMemcpyAsync((void*)p.T.parent, h->tstage, tb, hipMemcpyHostToDevice, st));
+    } else {
+      OKR_HIP(h, hipMemcpyAsync((void*)p.T.parent, h->topo_host.data(), tb, hipMemcpyHostToDevice, st));
+    }
+  }
   if (dump) {
     h->dump.assign(nseg, {});
     h->dump32.assign(nseg, {});
@@ -1315,7 +1353,7 @@ static int reduce_feeder_impl(okr_handle* h, const okr_yblocks* Y, const okr_top
   if (timing && (int)h->ev.size() < 2 * nseg) {
     drop_events(h);
     h->ev.resize(2 * std::max(nseg, 1), nullptr);
-    for (auto& e : h->ev) OKR_HIP(h, hipEventCreate(&e));
+    for (auto& e : h->ev) OKR_HIP(h, hipEventCreateWithFlags(&e, hipEventDisableSystemFence));
   }
   if (mg->flags & OKR_FLAG_AUTOTUNE) {
     // time the scoring launches of a whole search once per candidate group
@@ -1323,7 +1361,7 @@ static int reduce_feeder_impl(okr_handle* h, const okr_yblocks* Y, const okr_top
     if ((int)h->ev.size() < 2 * nseg) {
       drop_events(h);
       h->ev.resize(2 * std::max(nseg, 1), nullptr);
-      for (auto& e : h->ev) OKR_HIP(h, hipEventCreate(&e));
+      for (auto& e : h->ev) OKR_HIP(h, hipEventCreateWithFlags(&e, hipEventDisableSystemFence));
     }
     // (the FP64 scoring kernel is tuned whatever the call's precision)
     okr_margins mt = *mg;
@@ -1420,26 +1458,48 @@ static int reduce_feeder_impl(okr_handle* h, const okr_yblocks* Y, const okr_top
   const bool surr_used = mg->top_k > 0 && mg->top_k <= h->topk && mg->surrogate && mg->precision == OKR_PRECISION_FP64;
   const bool mixed = mg->precision == OKR_PRECISION_MIXED;
   std::vector<int> sup(n), kp(n), iters(S, 0), status(kStatusInts, 0);
+  // (destination, result-block offset, bytes) of every result read back
+  struct Piece {
+    void* dst;
+    size_t off, bytes;
+  };
+  std::vector<Piece> pieces;
+  auto want = [&](void* dst, size_t off, size_t bytes) {
+    if (dst && bytes) pieces.push_back({dst, off, bytes});
+  };
+  const Layout& L = h->L;
   if (nseg > 0) {
-    OKR_HIP(h, hipMemcpyAsync(decs.data(), p.decs, sizeof(DevDecision) * nseg, hipMemcpyDeviceToHost, st));
-    OKR_HIP(h, hipMemcpyAsync(hdrs.data(), p.hdrs, sizeof(SegHdr) * nseg, hipMemcpyDeviceToHost, st));
-    if (mixed)
-      OKR_HIP(h, hipMemcpyAsync(mstate.data(), p.mstate, sizeof(MixedState) * nseg, hipMemcpyDeviceToHost, st));
-    if (surr_used || mixed)
-      OKR_HIP(h, hipMemcpyAsync(gates.data(), p.sgates, sizeof(int) * nseg, hipMemcpyDeviceToHost, st));
+    want(decs.data(), L.decs, sizeof(DevDecision) * nseg);
+    want(hdrs.data(), L.hdrs, sizeof(SegHdr) * nseg);
+    if (mixed) want(mstate.data(), L.mstate, sizeof(MixedState) * nseg);
+    if (surr_used || mixed) want(gates.data(), L.sgates, sizeof(int) * nseg);
   }
-  OKR_HIP(h, hipMemcpyAsync(sup.data(), p.St.sup, sizeof(int) * n, hipMemcpyDeviceToHost, st));
-  OKR_HIP(h, hipMemcpyAsync(kp.data(), p.kp, sizeof(int) * n, hipMemcpyDeviceToHost, st));
-  OKR_HIP(h, hipMemcpyAsync(status.data(), p.status, sizeof(int) * kStatusInts, hipMemcpyDeviceToHost, st));
-  if (!vhat_given) OKR_HIP(h, hipMemcpyAsync(iters.data(), p.iters, sizeof(int) * S, hipMemcpyDeviceToHost, st));
-  if (out->Yk_diag)
-    OKR_HIP(h, hipMemcpyAsync(out->Yk_diag, p.Ykd, sizeof(double2) * 9 * n, hipMemcpyDeviceToHost, st));
-  if (out->Yk_off) OKR_HIP(h, hipMemcpyAsync(out->Yk_off, p.Yko, sizeof(double2) * 9 * n, hipMemcpyDeviceToHost, st));
-  if (out->err_per_snapshot)
-    OKR_HIP(h, hipMemcpyAsync(out->err_per_snapshot, p.err, sizeof(double) * S, hipMemcpyDeviceToHost, st));
+  want(sup.data(), L.sup, sizeof(int) * n);
+  want(kp.data(), L.kp, sizeof(int) * n);
+  want(status.data(), L.status, sizeof(int) * kStatusInts);
+  if (!vhat_given) want(iters.data(), L.iters, sizeof(int) * S);
+  want(out->Yk_diag, L.Ykd, sizeof(double2) * 9 * n);
+  want(out->Yk_off, L.Yko, sizeof(double2) * 9 * n);
+  want(out->err_per_snapshot, L.err, sizeof(double) * S);
+  if (may_alloc && h->rstage_bytes < L.res_bytes) {
+    if (h->rstage) (void)hipHostFree(h->rstage);
+    h->rstage = nullptr;
+    h->rstage_bytes = 0;
+    OKR_HIP(h, hipHostMalloc(&h->rstage, L.res_bytes, hipHostMallocDefault));
+    h->rstage_bytes = L.res_bytes;
+  }
+  const bool staged = may_alloc && h->rstage;
+  if (staged) {  // the whole result block in one transfer, then placed on the host
+    OKR_HIP(h, hipMemcpyAsync(h->rstage, (const char*)d_workspace + L.res0, L.res_bytes, hipMemcpyDeviceToHost, st));
+  } else {
+    for (const Piece& q : pieces)
+      OKR_HIP(h, hipMemcpyAsync(q.dst, (const char*)d_workspace + q.off, q.bytes, hipMemcpyDeviceToHost, st));
+  }
   if (out->Vhat)
     OKR_HIP(h, hipMemcpyAsync(out->Vhat, p.Vhat, sizeof(double2) * (size_t)S * n * 3, hipMemcpyDeviceToHost, st));
   OKR_HIP(h, hipStreamSynchronize(st));
+  if (staged)
+    for (const Piece& q : pieces) std::memcpy(q.dst, (const char*)h->rstage + (q.off - L.res0), q.bytes);
   const auto t1 = clk::now();
   const int hs = status[0];
   if (hs & 1) OKR_FAIL(h, OKR_E_SINGULAR, "a present-phase branch block is singular");

@@ -464,7 +464,7 @@ __global__ __launch_bounds__(64) void k_apply(const SegHdr* __restrict__ hdrs, c
 // Reset of the search state at the start of a call (no memset nodes, so the
 // sequence can be captured in a graph).
 __global__ void k_init_state(int n, State St, int* __restrict__ status, int nstatus, int* __restrict__ tickets,
-                             int ntickets) {
+                             int ntickets, int nlanes, size_t lstride) {
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
   if (i < n) {
     St.kept[i] = 1;
@@ -473,7 +473,8 @@ __global__ void k_init_state(int n, State St, int* __restrict__ status, int nsta
     St.zent_of[3 * i] = St.zent_of[3 * i + 1] = St.zent_of[3 * i + 2] = -1;
   }
   if (i < nstatus) status[i] = 0;
-  if (i < ntickets) tickets[i] = 0;
+  if (i < ntickets)  // every chunk position's ticket counters (position z: z * lstride bytes further)
+    for (int z = 0; z < nlanes; ++z) ((int*)((char*)tickets + (size_t)z * lstride))[i] = 0;
 }
 
 __global__ void k_copy2(const double2* __restrict__ a, double2* __restrict__ b, size_t count) {
