@@ -124,8 +124,8 @@ constexpr double kSmiceTol = 1e-9;    // default SMICE tie window
 // Dynamic LDS of the load flow with its iterates in shared memory (0: too
 // large, the global-memory form runs).
 constexpr size_t kPfLdsMax = 150 * 1024;
-size_t pf_lds_bytes(int n) {
-  const size_t b = (size_t)n * 3 * 2 * sizeof(double2);
+size_t pf_lds_bytes(int n, int nlev) {
+  const size_t b = (size_t)n * 3 * 2 * sizeof(double2) + sizeof(int) * ((size_t)4 * n + nlev + 2) + (size_t)n;
   return b <= kPfLdsMax ? b : 0;
 }
 constexpr int kSmiceThreadsHost = 128;  // masks per block of the SMICE scoring
@@ -969,7 +969,7 @@ void enqueue_search(okr_handle* h, void* ws, const okr_yblocks* Y, const okr_loa
                        p.status);
   } else {
     const double2* V0 = (const double2*)loads->V0;
-    const size_t pf_lds = pf_lds_bytes(n);
+    const size_t pf_lds = pf_lds_bytes(n, h->nlev);
     if (pf_lds)
       hipLaunchKernelGGL(k_powerflow_lds, dim3(S), dim3(256), pf_lds, st, n, p.T.parent, p.T.phase, p.lvl_off,
                          p.lvl_nodes, h->nlev, p.T.ch_off, p.T.ch, (const double2*)p.z, (const double2*)loads->S_load,
@@ -1324,7 +1324,7 @@ static int reduce_feeder_impl(okr_handle* h, const okr_yblocks* Y, const okr_top
   const int n = h->n, S = h->S, nseg = h->nseg;
   hipStream_t st = h->stream;
   const Ptrs p = pointers(h, d_workspace);
-  if (pf_lds_bytes(n) > 64 * 1024 && !(mg->flags & OKR_FLAG_VHAT_GIVEN))  // (set before any capture)
+  if (pf_lds_bytes(n, h->nlev) > 64 * 1024 && !(mg->flags & OKR_FLAG_VHAT_GIVEN))  // (set before any capture)
     OKR_HIP(h, hipFuncSetAttribute(reinterpret_cast<const void*>(&k_powerflow_lds),
                                    hipFuncAttributeMaxDynamicSharedMemorySize, (int)kPfLdsMax));
   const auto t0 = clk::now();

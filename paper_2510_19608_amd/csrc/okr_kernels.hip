@@ -129,10 +129,34 @@ __device__ __forceinline__ void powerflow_body(
     double2* sbuf, double* shd) {
   const int l = blockIdx.x;
   const size_t base = (size_t)l * n * 3;
-  // (with LDS the iterates live in shared memory: every level step of the
-  // sweeps then waits on LDS instead of global memory)
+  // (with LDS the iterates, and the tree arrays the sweeps index, live in
+  // shared memory: every level step then waits on LDS instead of global
+  // memory; only the branch impedances are read from global memory)
   double2* Vl = LDS ? sbuf : V + base;
   double2* Jl = LDS ? sbuf + (size_t)n * 3 : J + base;
+  if (LDS) {
+    int* si = (int*)(sbuf + (size_t)n * 6);
+    int* s_lvl_off = si;
+    int* s_lvl_nodes = s_lvl_off + nlev + 1;
+    int* s_ch_off = s_lvl_nodes + n;
+    int* s_ch = s_ch_off + n + 1;
+    int* s_parent = s_ch + n;
+    uint8_t* s_phase = (uint8_t*)(s_parent + n);
+    for (int i = threadIdx.x; i <= nlev; i += blockDim.x) s_lvl_off[i] = lvl_off[i];
+    for (int i = threadIdx.x; i <= n; i += blockDim.x) s_ch_off[i] = ch_off[i];
+    for (int i = threadIdx.x; i < n; i += blockDim.x) {
+      s_lvl_nodes[i] = lvl_nodes[i];
+      s_ch[i] = i < n - 1 ? ch[i] : 0;
+      s_parent[i] = parent[i];
+      s_phase[i] = phase[i];
+    }
+    lvl_off = s_lvl_off;
+    lvl_nodes = s_lvl_nodes;
+    ch_off = s_ch_off;
+    ch = s_ch;
+    parent = s_parent;
+    phase = s_phase;
+  }
   const double2* Sl = Sload + base;
   const double2 v0[3] = {v0a, v0b, v0c};
   for (int i = threadIdx.x; i < n; i += blockDim.x)
@@ -215,7 +239,8 @@ __global__ __launch_bounds__(256) void k_powerflow(
 }
 
 // The same with the voltage and current iterates in dynamic LDS (2 x n x 3
-// double2; for feeders small enough to fit).
+// double2), followed by the level offsets and nodes, child offsets and
+// lists, parents and phases (for feeders small enough to fit).
 __global__ __launch_bounds__(256) void k_powerflow_lds(
     int n, const int* __restrict__ parent, const uint8_t* __restrict__ phase,
     const int* __restrict__ lvl_off, const int* __restrict__ lvl_nodes, int nlev,
