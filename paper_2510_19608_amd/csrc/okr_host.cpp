@@ -280,7 +280,8 @@ constexpr size_t kSvLdsMax = 60 * 1024;
 size_t sv_lds_bytes(int spp, int k) {
   const size_t pcap = (size_t)k * (k + 1) / 2;
   return (size_t)spp * (pcap * 3 * sizeof(double2) + (size_t)k * 3 * (sizeof(TargetRec) + sizeof(double2) + sizeof(double)) +
-                        kSvZone * sizeof(TargetRec) + sizeof(double));
+                        kSvZone * sizeof(TargetRec) + sizeof(double)) +
+         16;  // (the kernel packs the tables to the segment's own sizes: rounding room)
 }
 // LDS of the chain-term kernel for segments of up to k nodes: chain records
 // and nesting paths, one snapshot's pairs, slot and head records, and the

@@ -49,6 +49,58 @@ __device__ __forceinline__ bool keep_score(bool full, uint32_t m, int tile_best)
   return full || __popc(m) == tile_best || m == 0;
 }
 
+// LDS stage of one pass of the per-mask kernel, in 16-byte chunks: chunk i
+// of one index space over the pair rows, slot records (2 chunks each), chain
+// heads and the first zone records (2 chunks each) of the pass's M snapshots
+// (element r * M + j of each table, snapshot j fastest, M a power of two, so
+// the LDS writes are contiguous).  stage_issue loads kStageBatch chunks per
+// thread, from chunk b on (past the end the last chunk is loaded again and
+// not stored); stage_store writes them to the buffer at chunk bb of the LDS,
+// a chain head's magnitude too.
+struct StageMap {
+  int nP, nT, nH, nst;  // chunks of the pair, slot, head tables; all chunks
+  int oT, oH, oZ, oHm;  // their offsets in a buffer (pairs at 0), head magnitudes
+};
+template <int M>
+__device__ __forceinline__ void stage_issue(const StageMap& S, int b, int l, int l1, const SegHdr& H,
+                                            const double2* __restrict__ P, const TargetRec* __restrict__ srec,
+                                            const double2* __restrict__ headV, const TargetRec* __restrict__ zrec,
+                                            uint4 (&v)[kStageBatch], int (&dst)[kStageBatch]) {
+  constexpr int LM = M == 4 ? 2 : (M == 2 ? 1 : 0);
+#pragma unroll
+  for (int u = 0; u < kStageBatch; ++u) {
+    const int i0 = b + u * kScoreThreads + (int)threadIdx.x;
+    const int i = min(i0, S.nst - 1);
+    // its table by selects, no branches, so the loads issue back to back
+    const int iT = i - S.nP, iH = iT - S.nT, iZ = iH - S.nH;
+    const bool isP = i < S.nP, isT = !isP && iT < S.nT, isH = !isP && !isT && iH < S.nH;
+    const bool rec = !isP && !isH;  // slot and zone records: 2 chunks each
+    const int ii = isP ? i : (isT ? iT : (isH ? iH : iZ));
+    const int j = rec ? (ii >> 1) & (M - 1) : ii & (M - 1);
+    const int chunk = rec ? ((ii >> (LM + 1)) << 1) + (ii & 1) : ii >> LM;
+    const uint4* base =
+        isP ? (const uint4*)P : (isT ? (const uint4*)srec : (isH ? (const uint4*)headV : (const uint4*)zrec));
+    const int per = isP ? H.npairs * 3 : (isT ? H.nslots * 6 : (isH ? H.nchains * 3 : H.nz * 2));  // per snapshot
+    dst[u] = i0 < S.nst ? (isP ? 0 : (isT ? S.oT : (isH ? S.oH : S.oZ))) + ii : -1;
+    v[u] = base[(size_t)min(l + j, l1 - 1) * per + chunk];
+  }
+}
+__device__ __forceinline__ void stage_store(const StageMap& S, unsigned char* lds, int bb,
+                                            const uint4 (&v)[kStageBatch], const int (&dst)[kStageBatch]) {
+  uint4* buf = (uint4*)lds + bb;
+  double* Hm = (double*)(buf + S.oHm);
+#pragma unroll
+  for (int u = 0; u < kStageBatch; ++u) {
+    if (dst[u] < 0) continue;
+    buf[dst[u]] = v[u];
+    if (dst[u] >= S.oH && dst[u] < S.oZ) {  // a chain head: its magnitude too
+      const double2 hv =
+          make_double2(__hiloint2double((int)v[u].y, (int)v[u].x), __hiloint2double((int)v[u].w, (int)v[u].z));
+      Hm[dst[u] - S.oH] = (hv.x != 0.0 || hv.y != 0.0) ? hmag(hv) : 0.0;
+    }
+  }
+}
+
 // Per-mask FP64 scoring, snapshot-vectorised: one mask per lane; a block's 4
 // waves form groups of ws waves (1, 2 or 4) over 64 consecutive masks each,
 // the waves of a group splitting the segment's chains (each chain's terms,
@@ -90,12 +142,6 @@ __global__ __launch_bounds__(kScoreThreads) void k_score_fp64(
   fin = lane_ptr(fin, lstride);
   tiles = lane_ptr(tiles, lstride);
   tickets = lane_ptr(tickets, lstride);
-  double2* Ps = (double2*)sv_lds;
-  TargetRec* Ts = (TargetRec*)(Ps + (size_t)pcap * 3 * M);
-  double2* Hv = (double2*)(Ts + (size_t)kcap * 3 * M);
-  TargetRec* Zs = (TargetRec*)(Hv + (size_t)kcap * 3 * M);
-  double* Hm = (double*)(Zs + (size_t)zcap * M);
-  double* Ec = Hm + (size_t)kcap * 3 * M;
   const int tid = threadIdx.x;
   const int w = __builtin_amdgcn_readfirstlane(tid >> 6);
   const int lane = tid & 63;
@@ -112,56 +158,63 @@ __global__ __launch_bounds__(kScoreThreads) void k_score_fp64(
   const cint* chains = as_cint(tab + H.o_chain);
   const cint* nest = as_cint(tab + H.o_nest);
   const int zst = min(H.nz, zcap);
-  const int cP = H.npairs * 3, cT = H.nslots * 6, cH = H.nchains * 3, cZ = zst * 2;  // 16-byte chunks
+  const int cP = H.npairs * 3, cT = H.nslots * 6, cH = H.nchains * 3, cZ = zst * 2;  // 16-byte chunks per snapshot
   double e = 0.0, qmn[M], qmx[M];
 #pragma unroll
   for (int j = 0; j < M; ++j) {
     qmn[j] = INFINITY;
     qmx[j] = -INFINITY;
   }
-  // LDS offsets of the staged tables in 16-byte units (capacities)
-  const int oT = pcap * 3 * M, oH = oT + kcap * 3 * M * 2, oZ = oH + kcap * 3 * M;
+  // LDS: the pass's tables packed to this segment's own sizes.  The launch
+  // allocates the layout of the capacities (pcap pairs, kcap slots and
+  // chains, zcap zone records per snapshot, for the chunk's largest
+  // segment); when two packed buffers fit in it, the next pass is staged
+  // while this one is computed (its first loads in flight during the
+  // compute, one barrier per pass), else passes stage and compute in turn.
   constexpr int LM = M == 4 ? 2 : (M == 2 ? 1 : 0);
-  const int nP = cP << LM, nT = cT << LM, nH = cH << LM, nZ = cZ << LM;
-  const int nst = nP + nT + nH + nZ;
-  for (int l = l0; l < l1; l += M) {
-    // Stage the pass's tables: chunk i of one index space over the four
-    // tables (element r * M + j of each, snapshot j fastest, M a power of
-    // two, so the LDS writes are contiguous).  Each thread issues the loads
-    // of kStageBatch chunks before it writes any, so their latencies overlap.
-    for (int b = 0; b < nst; b += kStageBatch * kScoreThreads) {
-      uint4 v[kStageBatch];
-      int dst[kStageBatch];
-#pragma unroll
-      for (int u = 0; u < kStageBatch; ++u) {
-        // chunk i (past the end: the last chunk is loaded again, not stored);
-        // its table by selects, no branches, so the loads issue back to back
-        const int i = min(b + u * kScoreThreads + tid, nst - 1);
-        const int iT = i - nP, iH = iT - nT, iZ = iH - nH;
-        const bool isP = i < nP, isT = !isP && iT < nT, isH = !isP && !isT && iH < nH;
-        const bool rec = !isP && !isH;  // slot and zone records: 2 chunks each
-        const int ii = isP ? i : (isT ? iT : (isH ? iH : iZ));
-        const int j = rec ? (ii >> 1) & (M - 1) : ii & (M - 1);
-        const int chunk = rec ? ((ii >> (LM + 1)) << 1) + (ii & 1) : ii >> LM;
-        const uint4* base =
-            isP ? (const uint4*)P : (isT ? (const uint4*)srec : (isH ? (const uint4*)headV : (const uint4*)zrec));
-        const int per = isP ? cP : (isT ? H.nslots * 6 : (isH ? cH : H.nz * 2));  // chunks per snapshot
-        dst[u] = b + u * kScoreThreads + tid < nst ? (isP ? 0 : (isT ? oT : (isH ? oH : oZ))) + ii : -1;
-        v[u] = base[(size_t)min(l + j, l1 - 1) * per + chunk];
-      }
-#pragma unroll
-      for (int u = 0; u < kStageBatch; ++u) {
-        if (dst[u] < 0) continue;
-        ((uint4*)sv_lds)[dst[u]] = v[u];
-        if (dst[u] >= oH && dst[u] < oZ) {  // a chain head: its magnitude too
-          const double2 hv =
-              make_double2(__hiloint2double((int)v[u].y, (int)v[u].x), __hiloint2double((int)v[u].w, (int)v[u].z));
-          Hm[dst[u] - oH] = (hv.x != 0.0 || hv.y != 0.0) ? hmag(hv) : 0.0;
-        }
-      }
+  StageMap SM;
+  SM.nP = cP << LM;
+  SM.nT = cT << LM;
+  SM.nH = cH << LM;
+  SM.nst = SM.nP + SM.nT + SM.nH + (cZ << LM);
+  SM.oT = SM.nP;
+  SM.oH = SM.oT + SM.nT;
+  SM.oZ = SM.oH + SM.nH;
+  SM.oHm = SM.nst;  // then doubles: the head magnitudes (nchains * 3 * M), the constant errors (M)
+  const int nEc = H.nchains * 3 * M;             // (index of the first constant error among them)
+  const int ubuf = SM.oHm + (nEc + M + 1) / 2;  // chunks per buffer
+  // (the allocation: the capacities' layout and 16 bytes, which covers the
+  // rounding of the packed one)
+  const size_t cap_bytes = (size_t)M * ((size_t)pcap * 3 * sizeof(double2) +
+                                        (size_t)kcap * 3 * (sizeof(TargetRec) + sizeof(double2) + sizeof(double)) +
+                                        (size_t)zcap * sizeof(TargetRec) + sizeof(double)) +
+                           16;
+  const bool dbl = (size_t)2 * ubuf * 16 <= cap_bytes;
+  const int npass = (l1 - l0 + M - 1) / M;
+  uint4 sv[kStageBatch];
+  int sd[kStageBatch];
+  auto stage_all = [&](int l, int bb, int from) {  // chunks from `from` on, issued and stored in turn
+    for (int b = from; b < SM.nst; b += kStageBatch * kScoreThreads) {
+      stage_issue<M>(SM, b, l, l1, H, P, srec, headV, zrec, sv, sd);
+      stage_store(SM, sv_lds, bb, sv, sd);
     }
-    if (tid < M) Ec[tid] = econst[min(l + tid, l1 - 1)];
-    __syncthreads();
+    if (tid < M) ((double*)((uint4*)sv_lds + bb + SM.oHm))[nEc + tid] = econst[min(l + tid, l1 - 1)];
+  };
+  if (npass > 0) stage_all(l0, 0, 0);
+  __syncthreads();
+  for (int pi = 0; pi < npass; ++pi) {
+    const int l = l0 + pi * M;
+    const int cb = dbl ? (pi & 1) * ubuf : 0;  // this pass's buffer
+    const int nb = dbl ? ubuf - cb : 0;        // the next pass's
+    const bool ahead = dbl && pi + 1 < npass;
+    if (ahead) stage_issue<M>(SM, 0, l + M, l1, H, P, srec, headV, zrec, sv, sd);
+    uint4* buf = (uint4*)sv_lds + cb;
+    const double2* Ps = (const double2*)buf;
+    const TargetRec* Ts = (const TargetRec*)(buf + SM.oT);
+    const double2* Hv = (const double2*)(buf + SM.oH);
+    const TargetRec* Zs = (const TargetRec*)(buf + SM.oZ);
+    const double* Hm = (const double*)(buf + SM.oHm);
+    const double* Ec = Hm + nEc;
     double el[M];
     const TargetRec* zg[M];
 #pragma unroll
@@ -174,7 +227,15 @@ __global__ __launch_bounds__(kScoreThreads) void k_score_fp64(
         score_chain_sv<M>(chains, nest, c, Ps, Ts, Hv, Hm, Zs, zst, zg, m, el, qmn, qmx);
 #pragma unroll
     for (int j = 0; j < M; ++j) e = fmax(e, el[j]);
-    __syncthreads();
+    if (ahead) {
+      stage_store(SM, sv_lds, nb, sv, sd);
+      stage_all(l + M, nb, kStageBatch * kScoreThreads);
+      __syncthreads();
+    } else if (pi + 1 < npass) {
+      __syncthreads();  // every wave is done with the buffer
+      stage_all(l + M, 0, 0);
+      __syncthreads();
+    }
   }
   double qmin = qmn[0], qmax = qmx[0];
 #pragma unroll
