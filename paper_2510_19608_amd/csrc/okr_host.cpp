@@ -147,14 +147,16 @@ int snap_groups_default(int k, int S, int* spg, int mpl = 1, int target_blocks =
   return (S + *spg - 1) / *spg;
 }
 
-// Snapshot groups of the per-mask FP64 launch (blocks of 64 masks, one per
-// lane, 4 waves sharing the chains): about 1024 blocks per 24 snapshots and at
-// most about 24 snapshots per block.
+// Snapshot groups of the per-mask FP64 launch for segments of k nodes: a
+// group of about 8 snapshots for segments of up to 9 nodes, 16 up to 12, 32
+// up to 16 and 64 above, scaled by (S / 96)^0.37 for S above 96 (a fit to
+// the autotuner's picks on MI355X on the 1000-, 6000- and 8400-node
+// workloads: 24, 96 and 288 snapshots, segments of 8 to 20 nodes).
 int score64_groups_default(int k, int S, int* spg) {
-  const int tiles = (int)((((uint64_t)1 << k) + kScoreBlock - 1) / kScoreBlock);
-  const int target = 1024 * std::max(1, S / 24);
-  int SG = std::min(S, std::max((S + 23) / 24, target / tiles));
-  SG = std::min(SG, kMaxSnapGroups);
+  const double base = k <= 9 ? 8.0 : (k <= 12 ? 16.0 : (k <= 16 ? 32.0 : 64.0));
+  const double want = base * (S > 96 ? std::pow(S / 96.0, 0.37) : 1.0);
+  int SG = (int)std::ceil(S / want - 1e-9);
+  SG = std::max(1, std::min(std::min(SG, S), kMaxSnapGroups));
   *spg = (S + SG - 1) / SG;
   return (S + *spg - 1) / *spg;
 }
@@ -251,21 +253,25 @@ int tuned(const std::vector<int>& t, int k, int nz) {
   const int i = shape_key(k, nz);
   return i < (int)t.size() ? t[i] : 0;
 }
-// Defaults follow the autotuner's picks on MI355X for the 1000-node workload
-// (segments of 15-16 nodes, chunks of 1-8 segments): a lone segment takes 4
-// snapshots per pass and 4 waves per 64 masks (2 from 16 nodes), a chunk of
-// two 2 snapshots and 2 waves, a chunk of three or more one wave per 64
-// masks.
+// Defaults follow the autotuner's picks on MI355X for the 1000-, 6000- and
+// 8400-node workloads (segments of 8 to 20 nodes, chunks of 1-8 segments):
+// 4 snapshots per pass up to 14 nodes (and for a lone segment up to 16), 2 up
+// to 19, then 1; 4 waves per 64 masks up to 14 nodes in chunks of up to 5
+// (else 2), from 15 nodes one in chunks of three or more or from 18 nodes,
+// else 4 for a lone segment of 15 and 2 otherwise.
 int score_mpl(const okr_handle* h, int k, int nz) {
   if (h->mpl_force) return h->mpl_force;
   const int t = tuned(h->mpl_tuned, k, nz);
-  return t ? t : (nz == 1 ? 4 : 2);
+  if (t) return t;
+  if (k <= 14 || (nz == 1 && k <= 16)) return 4;
+  return k <= 19 ? 2 : 1;
 }
 int score_ws(const okr_handle* h, int k, int nz) {
   if (h->ws_force) return h->ws_force;
   const int t = tuned(h->ws_tuned, k, nz);
   if (t) return t;
-  if (nz >= 3) return 1;
+  if (k <= 14) return nz <= 5 ? 4 : 2;
+  if (nz >= 3 || k >= 18) return 1;
   return (nz == 1 && k <= 15) ? 4 : 2;
 }
 
@@ -302,17 +308,11 @@ int sv_spp(int want, int k, int spg) {
   return spp;
 }
 
-// Default groups: at least about 2048 waves per launch (2 per SIMD) while the
-// general rule gives fewer, at most a group per 8 snapshots.
+// (within the partial-score capacity of the workspace)
 int snap_groups(const okr_handle* h, int k, int nz, int* spg) {
   const int S = h->S;
   int SG = h->sg_force ? h->sg_force : tuned(h->sg_tuned, k, nz);
-  if (SG <= 0) {
-    SG = score64_groups_default(k, S, spg);
-    const int64_t waves = (int64_t)((((uint64_t)1 << k) + kScoreBlock - 1) / kScoreBlock) * score_ws(h, k, nz) * nz;
-    const int want = (int)std::min<int64_t>(std::max(1, S / 8), (2048 + waves - 1) / waves);
-    SG = std::max(SG, want);
-  }
+  if (SG <= 0) SG = score64_groups_default(k, S, spg);
   SG = std::min(std::min(SG, S), kMaxSnapGroups);
   while (SG > 1 && ((size_t)SG << k) > h->part_cap) --SG;
   *spg = (S + SG - 1) / SG;
