@@ -132,22 +132,8 @@ constexpr int kSmiceThreadsHost = 128;  // masks per block of the SMICE scoring
 
 size_t align256(size_t x) { return (x + 255) & ~size_t(255); }
 
-// Snapshot groups of a scoring launch (blocks of 256 lanes carrying mpl masks
-// each; the per-mask FP64 kernel carries one): by default about 256 mask
-// blocks per 24 snapshots and at most about 24 snapshots per block, each
-// group a contiguous run of snapshots.  target_blocks > 0 sets the block
-// count instead (the FP32 screen uses 128).
-int snap_groups_default(int k, int S, int* spg, int mpl = 1, int target_blocks = 0) {
-  const int mblocks = (int)((((uint64_t)1 << k) + kScoreThreads * mpl - 1) / (kScoreThreads * mpl));
-  // (the shapes the autotuner picks on MI355X, within a few percent)
-  if (target_blocks <= 0) target_blocks = 256 * std::max(1, S / 24);
-  int SG = std::min(S, std::max((S + 23) / 24, target_blocks / mblocks));
-  SG = std::min(SG, kMaxSnapGroups);
-  *spg = (S + SG - 1) / SG;
-  return (S + *spg - 1) / *spg;
-}
-
-// Snapshot groups of the per-mask FP64 launch for segments of k nodes: a
+// Snapshot groups of the scoring launches (per-mask FP64, FP32 screen) for
+// segments of k nodes, each group a contiguous run of snapshots: a
 // group of about 8 snapshots for segments of up to 9 nodes, 16 up to 12, 32
 // up to 16 and 64 above, scaled by (S / 96)^0.37 for S above 96 (a fit to
 // the autotuner's picks on MI355X on the 1000-, 6000- and 8400-node
@@ -161,14 +147,14 @@ int score64_groups_default(int k, int S, int* spg) {
   return (S + *spg - 1) / *spg;
 }
 
-// Launch shape of the FP32 screen: masks per lane by segment size and about
-// 128 mask blocks (few snapshot groups: a group's snapshots are the lanes of
-// the once-per-wave chains; measured best on the 1000- and 8400-node
-// workloads, within 2% of the best on the 6000-node one).  The workspace
-// planner sizes the screen's partial scores from this same function.
+// Launch shape of the FP32 screen: masks per lane by segment size, snapshot
+// groups by the per-mask FP64 kernel's rule (on MI355X 10% faster than a
+// block-count target on the 8400-node workload, within 2% on the 6000-node
+// one).  The workspace planner sizes the screen's partial scores from this
+// same function.
 int screen32_shape(int k, int S, int* spg, int* mpl) {
   *mpl = k >= 12 ? 4 : (k >= 10 ? 2 : 1);
-  return snap_groups_default(k, S, spg, *mpl, 128);
+  return score64_groups_default(k, S, spg);
 }
 
 struct Layout {
