@@ -231,8 +231,9 @@ def modes_section(f, args, trained):
 def fullsize_section(seed, reps=3):
     """Time-to-optimal of the whole search on the 6000-node feeder (96
     snapshots, segments of 8-18 eligible nodes) and the 8400-node feeder (288
-    snapshots, segments of 8-20), plain FP64 and mixed precision, each as one
-    captured graph (launch shapes from the library's defaults); with the
+    snapshots, segments of 8-20), plain FP64, mixed precision and the factored
+    FP64 form, each as one captured graph (launch shapes from the library's
+    defaults); with the
     launch structure of the search (chunks of independent segments, one
     scoring launch each) and, from a stream-launched timed run, the wall time
     of the search against the time inside its scoring launches."""
@@ -244,7 +245,7 @@ def fullsize_section(seed, reps=3):
         f = make_feeder(cfg, seed)
         e = dict(e_bar=f["e_bar"], n=int(f["n"]), snapshots=int(f["S_load"].shape[0]))
         ref = None
-        for prec in ("fp64", "mixed"):
+        for prec in ("fp64", "mixed", "factored"):
             R = Reducer(f, device="cuda:0", graph=True, precision=prec)
             ms = timed_runs(R, reps, False)
             masks, pops, res = decisions(R)
