@@ -301,9 +301,11 @@ __global__ __launch_bounds__(1024) void k_argmin(const SegHdr* __restrict__ hdrs
                                                  const TileRec* __restrict__ tiles, SelParams sp,
                                                  const int* __restrict__ status, DevDecision* __restrict__ decs,
                                                  const int* __restrict__ gates) {
-  __shared__ double shd[16];
-  __shared__ int shi[16];
-  __shared__ unsigned shu[16];
+  // one slot per wave for each reduction (each its own array, so no
+  // reduction's slots are written while another's are still being read)
+  __shared__ int s_best[16], s_amb[16], s_amb2[16];
+  __shared__ double s_emin[16], s_run[16];
+  __shared__ unsigned s_pick[16];
   __shared__ int ncand;
   __shared__ int cand[1024];
   const int g = segs[blockIdx.z];
@@ -324,40 +326,72 @@ __global__ __launch_bounds__(1024) void k_argmin(const SegHdr* __restrict__ hdrs
     }
     return;
   }
+  const int tid = threadIdx.x, bd = blockDim.x, lane = tid & 63, wv = tid >> 6, nw = bd >> 6;
   const int k = H.k;
   const uint32_t nm = 1u << k;
   const uint32_t L = (uint32_t)H.lanebits;  // tile t, lane q holds tile_mask(L, t, q, k)
   const int lb = __popc(L);
   const int ntiles = (int)(nm >> lb);
+  // up to one tile per thread (segments of up to 16 nodes): its record is
+  // read once and kept in registers
+  const bool one = ntiles <= bd;
+  TileRec r0;
+  r0.best = -1;
+  r0.near = -1;
+  r0.emin = INFINITY;
   int best = -1;
-  for (int t = threadIdx.x; t < ntiles; t += blockDim.x) best = max(best, tiles[t].best);
-  best = block_reduce(best, [](int a, int b) { return max(a, b); }, shi);
+  for (int t = tid; t < ntiles; t += bd) {
+    const TileRec r = tiles[t];
+    if (t == tid) r0 = r;
+    best = max(best, r.best);
+  }
+  for (int o = 32; o > 0; o >>= 1) best = max(best, __shfl_xor(best, o, 64));
+  if (lane == 0) s_best[wv] = best;
+  __syncthreads();
+  best = s_best[0];
+  for (int w = 1; w < nw; ++w) best = max(best, s_best[w]);
+  // the smallest error at the chosen level, and masks near the boundary
   double emin = INFINITY;
   int amb = 0;
-  for (int t = threadIdx.x; t < ntiles; t += blockDim.x) {
-    const TileRec r = tiles[t];
-    if (best >= 0 && r.best == best) emin = fmin(emin, r.emin);
-    if (best >= 0 && r.near >= best) amb = 1;
+  if (best >= 0)
+    for (int t = tid; t < ntiles; t += bd) {
+      const TileRec r = one ? r0 : tiles[t];
+      if (r.best == best) emin = fmin(emin, r.emin);
+      if (r.near >= best) amb = 1;
+    }
+  for (int o = 32; o > 0; o >>= 1) {
+    emin = fmin(emin, __shfl_xor(emin, o, 64));
+    amb |= __shfl_xor(amb, o, 64);
   }
-  emin = block_reduce(emin, [](double a, double b) { return fmin(a, b); }, shd);
+  if (lane == 0) {
+    s_emin[wv] = emin;
+    s_amb[wv] = amb;
+  }
+  __syncthreads();
+  emin = s_emin[0];
+  amb = s_amb[0];
+  for (int w = 1; w < nw; ++w) {
+    emin = fmin(emin, s_emin[w]);
+    amb |= s_amb[w];
+  }
   unsigned pick = 0xffffffffu;
   const double thr = emin + sp.tie;
   // runner-up: the smallest error above the tie window at the chosen level
   // (a tile not rescanned holds it at its own minimum)
   double runner = INFINITY;
-  // candidate tiles, processed in chunks of 1024 tiles
-  for (int base = 0; base < ntiles && best >= 0; base += 1024) {
-    if (threadIdx.x == 0) ncand = 0;
+  // candidate tiles, processed in chunks of one tile per thread
+  for (int base = 0; base < ntiles && best >= 0; base += bd) {
+    if (tid == 0) ncand = 0;
     __syncthreads();
-    const int t = base + threadIdx.x;
+    const int t = base + tid;
     if (t < ntiles) {
-      const TileRec r = tiles[t];
+      const TileRec r = one ? r0 : tiles[t];
       if (r.best == best && r.emin <= thr + sp.amb) cand[atomicAdd(&ncand, 1)] = t;
       else if (r.best == best) runner = fmin(runner, r.emin);
     }
     __syncthreads();
     const int nc = ncand;
-    for (int q = threadIdx.x; q < nc * 64; q += blockDim.x) {
+    for (int q = tid; q < nc * 64; q += bd) {
       if ((q & 63) >> lb) continue;
       const uint32_t mm = tile_mask(L, (uint32_t)cand[q >> 6], (uint32_t)(q & 63), k);
       if (__popc(mm) != best) continue;  // (only these masks' scores are stored)
@@ -369,10 +403,23 @@ __global__ __launch_bounds__(1024) void k_argmin(const SegHdr* __restrict__ hdrs
     }
     __syncthreads();
   }
-  pick = block_reduce(pick, [](unsigned a, unsigned b) { return min(a, b); }, shu);
-  amb = block_reduce(amb, [](int a, int b) { return a | b; }, shi);
-  runner = block_reduce(runner, [](double a, double b) { return fmin(a, b); }, shd);
-  if (threadIdx.x == 0) {
+  for (int o = 32; o > 0; o >>= 1) {
+    pick = min(pick, (unsigned)__shfl_xor((int)pick, o, 64));
+    amb |= __shfl_xor(amb, o, 64);
+    runner = fmin(runner, __shfl_xor(runner, o, 64));
+  }
+  if (lane == 0) {
+    s_pick[wv] = pick;
+    s_amb2[wv] = amb;
+    s_run[wv] = runner;
+  }
+  __syncthreads();
+  if (tid == 0) {
+    for (int w = 1; w < nw; ++w) {
+      pick = min(pick, s_pick[w]);
+      amb |= s_amb2[w];
+      runner = fmin(runner, s_run[w]);
+    }
     DevDecision d;
     if (best < 0) {
       d.mask = 0; d.popcount = 0; d.e_loc = fin[0].e; d.e_min = fin[0].e; d.ambiguous = 1; d.found = 0;
