@@ -53,6 +53,10 @@ __global__ __launch_bounds__(256) void k_build_struct(Topo T, State St, const in
                                                                         // first segment node with its top
   __shared__ int s_chpos[kMaxK], s_rkeep[kMaxK], s_depth[kMaxK];        // chain c: head position, new range, nesting
   __shared__ int s_pmask[kMaxK];                                        // chain c: mask bits of its nesting path
+  __shared__ int s_okey[kMaxK];  // chain c: (preorder position << 5) | j of the deepest segment node above its head
+  // exclusive prefix sums over the chains (entry nch: the totals) of: nesting
+  // depth, pairs, new Omega_g range, its nodes, chain patterns
+  __shared__ int s_xs[5][kMaxK + 1];
   __shared__ int s_keycnt[kMaxK * 3], s_keyoff[kMaxK * 3], s_keycur[kMaxK * 3];
   __shared__ SegHdr s_h;
   __shared__ int s_err, s_nch;
@@ -72,6 +76,10 @@ __global__ __launch_bounds__(256) void k_build_struct(Topo T, State St, const in
     // maps may be stale)
     s_err = ((*status & kStatusBuild) || k < 1 || k > kMaxK) ? 1 : 0;
     s_nch = 0;
+  }
+  if (tid < kMaxK) {
+    s_okey[tid] = -1;
+    s_rkeep[tid] = 1;
   }
   __syncthreads();
   // chain top of every segment node: the highest node above it reachable
@@ -150,12 +158,24 @@ __global__ __launch_bounds__(256) void k_build_struct(Topo T, State St, const in
   // top's subtree starts a new Omega_g range (laminar intervals in preorder:
   // a top inside an earlier top's subtree adds nothing)
   const int nch = s_nch;
+  // over (chain, segment node) pairs: the deepest segment node whose subtree
+  // holds the chain's head (positions are distinct, so the largest key is
+  // that node); over (chain, earlier chain) pairs: whether the chain's top
+  // lies in an earlier chain top's subtree (then it starts no new range)
+  if (!s_err) {
+    for (int x = tid; x < nch * k; x += blockDim.x) {
+      const int c = x / k, j = x - c * k, ph = s_chpos[c];
+      if (ph >= 0 && s_spos[j] <= ph && ph < s_spos[j] + s_ssize[j]) atomicMax(&s_okey[c], (s_spos[j] << 5) | j);
+    }
+    for (int x = tid; x < nch * nch; x += blockDim.x) {
+      const int c = x / nch, q = x - c * nch;
+      if (q < c && s_cpos[q] <= s_cpos[c] && s_cpos[c] < s_cpos[q] + s_csize[q]) s_rkeep[c] = 0;
+    }
+  }
+  __syncthreads();
   if (!s_err && tid < nch) {
-    const int c = tid, ph = s_chpos[c];
-    int best = -1;
-    for (int j = 0; j < k; ++j)
-      if (ph >= 0 && s_spos[j] <= ph && ph < s_spos[j] + s_ssize[j] && (best < 0 || s_spos[j] > s_spos[best]))
-        best = j;
+    const int c = tid;
+    const int best = s_okey[c] >= 0 ? (s_okey[c] & 31) : -1;
     int oc = -1;
     if (best >= 0) {
       const int s = s_jslot[best];
@@ -175,10 +195,6 @@ __global__ __launch_bounds__(256) void k_build_struct(Topo T, State St, const in
       pu = pv;
       su = s_ssize[j];
     }
-    int keep = 1;
-    for (int q = 0; q < c; ++q)
-      if (s_cpos[q] <= s_cpos[c] && s_cpos[c] < s_cpos[q] + s_csize[q]) keep = 0;
-    s_rkeep[c] = keep;
   }
   __syncthreads();
   if (tid < nch) {
@@ -194,16 +210,31 @@ __global__ __launch_bounds__(256) void k_build_struct(Topo T, State St, const in
     s_pmask[tid] = pm;
   }
   __syncthreads();
-  // table layout: every thread forms the same sums from shared memory
-  int nest_tot = 0, npairs = 0, nr = 0, nom = 0, npat = 0;
-  for (int c = 0; c < nch; ++c) {
-    const int n = s_cslot0[c + 1] - s_cslot0[c];
-    npat += 1 << __popc(s_pmask[c]);
-    nest_tot += s_depth[c];
-    npairs += n * (n + 1) / 2;
-    nr += s_rkeep[c];
-    nom += s_rkeep[c] ? s_csize[c] : 0;
+  // the chains' table offsets: prefix sums in one wave (lane = chain)
+  if (tid < 64) {
+    int v[5] = {0, 0, 0, 0, 0};
+    if (tid < nch) {
+      const int n = s_cslot0[tid + 1] - s_cslot0[tid];
+      v[0] = s_depth[tid];
+      v[1] = n * (n + 1) / 2;
+      v[2] = s_rkeep[tid];
+      v[3] = s_rkeep[tid] ? s_csize[tid] : 0;
+      v[4] = 1 << __popc(s_pmask[tid]);
+    }
+#pragma unroll
+    for (int i = 0; i < 5; ++i) {
+      int x = v[i];
+      for (int o = 1; o < 64; o <<= 1) {
+        const int y = __shfl_up(x, o, 64);
+        if (tid >= o) x += y;
+      }
+      if (tid <= nch) s_xs[i][tid] = x - v[i];
+    }
   }
+  __syncthreads();
+  // table layout
+  const int nest_tot = s_xs[0][nch], npairs = s_xs[1][nch], nr = s_xs[2][nch], nom = s_xs[3][nch],
+            npat = s_xs[4][nch];
   const int o_nest = nch * kChainInts, o_slot = o_nest + nest_tot, o_pair = o_slot + k * kSlotInts;
   const int o_range = o_pair + npairs * kPairInts, o_zent = o_range + 3 * nr;
   if (tid == 0) {
@@ -250,15 +281,7 @@ __global__ __launch_bounds__(256) void k_build_struct(Topo T, State St, const in
   // records: one thread per chain, one per slot
   if (tid < nch) {
     const int c = tid, s0 = s_cslot0[c], n = s_cslot0[c + 1] - s0;
-    int nest_off = 0, pair0 = 0, ridx = 0, rcum = 0, pbase = 0;
-    for (int q = 0; q < c; ++q) {
-      const int nq = s_cslot0[q + 1] - s_cslot0[q];
-      pbase += 1 << __popc(s_pmask[q]);
-      nest_off += s_depth[q];
-      pair0 += nq * (nq + 1) / 2;
-      ridx += s_rkeep[q];
-      rcum += s_rkeep[q] ? s_csize[q] : 0;
-    }
+    const int nest_off = s_xs[0][c], pair0 = s_xs[1][c], ridx = s_xs[2][c], rcum = s_xs[3][c], pbase = s_xs[4][c];
     const int d = s_depth[c];
     int q = d - 1;
     for (int x = c; x >= 0; x = s_outer[x]) s_tab[o_nest + nest_off + q--] = x;
@@ -293,12 +316,7 @@ __global__ __launch_bounds__(256) void k_build_struct(Topo T, State St, const in
     // slot s = r-th slot of chain c: pairs (super, reduced) with the super
     // node the head or one of the r slots above it
     const int s = tid, c = s_slotchain[s], s0 = s_cslot0[c], r = s - s0;
-    int pair0 = 0;
-    for (int q = 0; q < c; ++q) {
-      const int nq = s_cslot0[q + 1] - s_cslot0[q];
-      pair0 += nq * (nq + 1) / 2;
-    }
-    const int pb = pair0 + r * (r + 1) / 2;
+    const int pb = s_xs[1][c] + r * (r + 1) / 2;
     int* sr = s_tab + o_slot + s * kSlotInts;
     sr[SL_NODE] = s_slotnode[s];
     sr[SL_BIT] = s_slotbit[s];
@@ -318,13 +336,8 @@ __global__ __launch_bounds__(256) void k_build_struct(Topo T, State St, const in
   for (int q = tid; q < o_zent; q += blockDim.x) tab[q] = s_tab[q];
   // Omega_g ranges for the zone pass (shared copy)
   if (tid < nch && s_rkeep[tid]) {
-    int ridx = 0, rcum = 0;
-    for (int q = 0; q < tid; ++q) {
-      ridx += s_rkeep[q];
-      rcum += s_rkeep[q] ? s_csize[q] : 0;
-    }
-    s_rs[ridx] = s_cpos[tid];
-    s_rcum[ridx] = rcum;
+    s_rs[s_xs[2][tid]] = s_cpos[tid];
+    s_rcum[s_xs[2][tid]] = s_xs[3][tid];
   }
   if (tid == 0) s_rcum[nr] = nom;
   __syncthreads();
