@@ -118,6 +118,23 @@ __global__ void k_branch_z(int n, const int* __restrict__ parent, const uint8_t*
 // Scenario library (Section III): constant-PQ wye loads, backward/forward
 // sweep on the radial tree, one block per snapshot, level-synchronous.
 // status bit 16: not converged; bit 32: base network outside the band.
+// Forward-sweep update of node i: V(i) = V(parent) - z(i) J(i) on its
+// present phases, and the largest change into dmax (NaN-propagating).
+__device__ __forceinline__ void forward_node(int i, const int* __restrict__ parent, const uint8_t* __restrict__ phase,
+                                             const double2 (&zi)[9], const double2* Jl, double2* Vl, double& dmax) {
+  const int pv = parent[i];
+  const double2 j0 = Jl[i * 3], j1 = Jl[i * 3 + 1], j2 = Jl[i * 3 + 2];
+#pragma unroll
+  for (int p = 0; p < 3; ++p) {
+    if (!(phase[i] >> p & 1u)) continue;
+    const double2 d = cadd(cadd(cmul(zi[p * 3], j0), cmul(zi[p * 3 + 1], j1)), cmul(zi[p * 3 + 2], j2));
+    const double2 nv = csub(Vl[pv * 3 + p], d);
+    const double dd = sqrt(cabs2(csub(nv, Vl[i * 3 + p])));
+    dmax = (dd <= dmax) ? dmax : dd;
+    Vl[i * 3 + p] = nv;
+  }
+}
+
 template <bool LDS>
 __device__ __forceinline__ void powerflow_body(
     int n, const int* __restrict__ parent, const uint8_t* __restrict__ phase,
@@ -185,21 +202,46 @@ __device__ __forceinline__ void powerflow_body(
       __syncthreads();
     }
     double dmax = 0.0;
+    // the branch impedance of this thread's first node on the next level is
+    // loaded while the current level is computed (the impedances are the
+    // only global reads of the sweep; a thread with no node there loads the
+    // root's, unused)
+    const int tid = threadIdx.x, bd = blockDim.x;
+    double2 zn[9];
+    {
+      const int q1 = nlev > 1 ? lvl_off[1] + tid : 0;
+      const double2* zz = z + (size_t)((nlev > 1 && q1 < lvl_off[2]) ? lvl_nodes[q1] : 0) * 9;
+#pragma unroll
+      for (int e = 0; e < 9; ++e) zn[e] = zz[e];
+    }
     for (int lev = 1; lev < nlev; ++lev) {
-      for (int q = lvl_off[lev] + threadIdx.x; q < lvl_off[lev + 1]; q += blockDim.x) {
-        const int i = lvl_nodes[q], pv = parent[i];
-        const double2* zi = z + (size_t)i * 9;
-        const double2 j0 = Jl[i * 3], j1 = Jl[i * 3 + 1], j2 = Jl[i * 3 + 2];
-        for (int p = 0; p < 3; ++p) {
-          if (!(phase[i] >> p & 1u)) continue;
-          const double2 d = cadd(cadd(cmul(zi[p * 3], j0), cmul(zi[p * 3 + 1], j1)), cmul(zi[p * 3 + 2], j2));
-          const double2 nv = csub(Vl[pv * 3 + p], d);
-          const double dd = sqrt(cabs2(csub(nv, Vl[i * 3 + p])));
-          dmax = (dd <= dmax) ? dmax : dd;  // NaN-propagating
-          Vl[i * 3 + p] = nv;
-        }
+      double2 zc[9];
+#pragma unroll
+      for (int e = 0; e < 9; ++e) zc[e] = zn[e];
+      {
+        const int qn = lev + 1 < nlev ? lvl_off[lev + 1] + tid : 0;
+        const double2* zz = z + (size_t)((lev + 1 < nlev && qn < lvl_off[lev + 2]) ? lvl_nodes[qn] : 0) * 9;
+#pragma unroll
+        for (int e = 0; e < 9; ++e) zn[e] = zz[e];
       }
-      __syncthreads();
+      const int q0 = lvl_off[lev] + tid, q1 = lvl_off[lev + 1];
+      if (q0 < q1) forward_node(lvl_nodes[q0], parent, phase, zc, Jl, Vl, dmax);
+      for (int q = q0 + bd; q < q1; q += bd) {  // (levels wider than the block)
+        const int i = lvl_nodes[q];
+        double2 zi[9];
+#pragma unroll
+        for (int e = 0; e < 9; ++e) zi[e] = z[(size_t)i * 9 + e];
+        forward_node(i, parent, phase, zi, Jl, Vl, dmax);
+      }
+      if (LDS) {
+        // the iterates are in LDS: order LDS only, so the next level's
+        // impedance loads stay in flight across the barrier
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup", "local");
+        __builtin_amdgcn_s_barrier();
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup", "local");
+      } else {
+        __syncthreads();
+      }
     }
     dmax = block_reduce(dmax, [](double a, double b) { return (b <= a) ? a : b; }, shd);
     if (!(dmax <= 1e3)) break;
