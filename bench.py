@@ -38,8 +38,8 @@ BF16_MFMA_PEAK_TFLOPS = 2500.0   # MI355X dense BF16 matrix peak
 TRAFFIC_SOURCES = ["paper_2510_19608_amd/csrc/okr_score.hip", "paper_2510_19608_amd/csrc/okr_device.h",
                    "paper_2510_19608_amd/csrc/okr_internal.h", "paper_2510_19608_amd/csrc/okr_host.cpp",
                    "paper_2510_19608_amd/csrc/okr_build.hip"]
-TRAFFIC_SHA1 = "eb73278a0d3aa223a8ae51e6235f2e2a2ef4c299"
-TRAFFIC_BYTES_PER_LAUNCH = 1922917
+TRAFFIC_SHA1 = "f3b9a3df6b1e7bdfbc5f123981161bb93c09e35b"
+TRAFFIC_BYTES_PER_LAUNCH = 1922988
 
 
 def measured_traffic():
