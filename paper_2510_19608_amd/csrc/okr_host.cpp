@@ -27,6 +27,9 @@ __global__ void k_powerflow(int, const int*, const uint8_t*, const int*, const i
 __global__ void k_powerflow_lds(int, const int*, const uint8_t*, const int*, const int*, int, const int*, const int*,
                                 const double2*, const double2*, double2, double2, double2, double, int, double, double,
                                 double2*, double2*, double2*, double*, int*, int*);
+__global__ void k_powerflow_bfs(int, const uint8_t*, const int*, const int*, int, const int*, const int*,
+                                const double2*, const double2*, double2, double2, double2, double, int, double, double,
+                                double2*, double2*, double2*, double*, int*, int*);
 __global__ void k_from_vhat(int, int, const uint8_t*, const double2*, const double2*, double, double, double2*,
                             double*, int*);
 __global__ void k_build_struct(Topo, State, const int*, size_t, int, SegHdr*, int*, int, int*);
@@ -128,6 +131,13 @@ size_t pf_lds_bytes(int n, int nlev) {
   const size_t b = (size_t)n * 3 * 2 * sizeof(double2) + sizeof(int) * ((size_t)4 * n + nlev + 2) + (size_t)n;
   return b <= kPfLdsMax ? b : 0;
 }
+// Dynamic LDS of the breadth-first form (iterates in global memory, the
+// queue tables in LDS as 16-bit positions; 0: not usable, the node-order
+// global form runs).
+size_t pf_bfs_lds_bytes(int n, int nlev) {
+  const size_t b = sizeof(int) * ((size_t)nlev + 1) + sizeof(uint16_t) * ((size_t)3 * n + 1) + (size_t)n;
+  return (n < 65536 && b <= kPfLdsMax) ? b : 0;
+}
 constexpr int kSmiceThreadsHost = 128;  // masks per block of the SMICE scoring
 
 size_t align256(size_t x) { return (x + 255) & ~size_t(255); }
@@ -179,8 +189,8 @@ struct Layout {
 
 // offsets (in int32) of the static topology arrays inside the topology buffer
 struct TopoOffsets {
-  int parent, phase, segment, pos, size, pre, ch_off, ch, lvl_off, lvl_nodes, seg_off, seg_nodes, chunks, seg_top,
-      total;
+  int parent, phase, segment, pos, size, pre, ch_off, ch, lvl_off, lvl_nodes, bfs_cf, bfs_pp, seg_off, seg_nodes,
+      chunks, seg_top, total;
 };
 
 }  // namespace
@@ -193,7 +203,7 @@ struct okr_handle {
   int n = 0, S = 0, nseg = 0, kmax = 0, nlev = 0, tab_cap = 0, topk = 0;
   bool smice = false;  // planned with SMICE as the key (its buffers exist)
   int64_t ncand = 0;
-  std::vector<int> parent, segment, pre, pos, size, ch_off, ch, lvl_off, lvl_nodes, seg_off, seg_nodes;
+  std::vector<int> parent, segment, pre, pos, size, ch_off, ch, lvl_off, lvl_nodes, bfs_cf, bfs_pp, seg_off, seg_nodes;
   std::vector<uint8_t> phase, eligible;
   Layout L{};
   TopoOffsets TO{};
@@ -497,9 +507,26 @@ extern "C" int okr_plan(okr_handle* h, const okr_topology* topo, const okr_margi
     h->lvl_off.assign(h->nlev + 1, 0);
     for (int i = 0; i < n; ++i) h->lvl_off[depth[i] + 1]++;
     for (int d = 0; d < h->nlev; ++d) h->lvl_off[d + 1] += h->lvl_off[d];
-    h->lvl_nodes.assign(n, 0);
-    std::vector<int> fill(h->nlev, 0);
-    for (int i = 0; i < n; ++i) h->lvl_nodes[h->lvl_off[depth[i]] + fill[depth[i]]++] = i;
+    // breadth-first queue order: the root, then each listed node's children
+    // in child-list order.  Every level is then a contiguous run, and the
+    // children of the node at position q are the contiguous positions
+    // bfs_cf[q] .. bfs_cf[q+1]-1, in child-list order; bfs_pp[q] is the
+    // position of the parent.
+    h->lvl_nodes.assign(1, 0);
+    h->lvl_nodes.reserve(n);
+    h->bfs_cf.assign(n + 1, 0);
+    h->bfs_pp.assign(n, 0);
+    for (int q = 0; q < n; ++q) {
+      const int v = h->lvl_nodes[q];
+      h->bfs_cf[q] = (int)h->lvl_nodes.size();
+      for (int e = h->ch_off[v]; e < h->ch_off[v + 1]; ++e) {
+        h->bfs_pp[h->lvl_nodes.size()] = q;
+        h->lvl_nodes.push_back(h->ch[e]);
+      }
+    }
+    h->bfs_cf[n] = n;
+    for (int q = 1; q < n; ++q)
+      if (depth[h->lvl_nodes[q]] < depth[h->lvl_nodes[q - 1]]) OKR_FAIL(h, OKR_E_NOT_TREE, "level order broken");
   }
   // phases, eligibility, segments
   for (int i = 0; i < n; ++i) {
@@ -636,6 +663,8 @@ extern "C" int okr_plan(okr_handle* h, const okr_topology* topo, const okr_margi
   TO.ch = put(h->ch);
   TO.lvl_off = put(h->lvl_off);
   TO.lvl_nodes = put(h->lvl_nodes);
+  TO.bfs_cf = put(h->bfs_cf);
+  TO.bfs_pp = put(h->bfs_pp);
   TO.seg_off = put(h->seg_off);
   TO.seg_nodes = put(h->seg_nodes.empty() ? std::vector<int>{0} : h->seg_nodes);
   TO.chunks = put(h->chunk_segs.empty() ? std::vector<int>{0} : h->chunk_segs);
@@ -788,7 +817,7 @@ namespace {
 struct Ptrs {
   Topo T;
   State St;
-  const int *lvl_off, *lvl_nodes, *chunks;
+  const int *lvl_off, *lvl_nodes, *bfs_cf, *bfs_pp, *chunks;
   double2 *z, *Zroot, *Vhat, *Vcur, *A, *J, *P, *headV, *yeq, *Ykd, *Yko;
   double *absV, *econst, *err;
   int *status, *iters, *tab, *tickets, *kp;
@@ -843,6 +872,8 @@ Ptrs pointers(okr_handle* h, void* d_workspace, int lane = 0) {
   p.T.seg_top = tp + TO.seg_top;
   p.lvl_off = tp + TO.lvl_off;
   p.lvl_nodes = tp + TO.lvl_nodes;
+  p.bfs_cf = tp + TO.bfs_cf;
+  p.bfs_pp = tp + TO.bfs_pp;
   p.chunks = tp + TO.chunks;
   p.St.kept = (uint8_t*)at(L.kept);
   p.St.sup = (int*)at(L.sup);
@@ -956,17 +987,22 @@ void enqueue_search(okr_handle* h, void* ws, const okr_yblocks* Y, const okr_loa
                        p.status);
   } else {
     const double2* V0 = (const double2*)loads->V0;
-    const size_t pf_lds = pf_lds_bytes(n, h->nlev);
-    if (pf_lds)
-      hipLaunchKernelGGL(k_powerflow_lds, dim3(S), dim3(256), pf_lds, st, n, p.T.parent, p.T.phase, p.lvl_off,
-                         p.lvl_nodes, h->nlev, p.T.ch_off, p.T.ch, (const double2*)p.z, (const double2*)loads->S_load,
-                         V0[0], V0[1], V0[2], mg->pf_tol > 0 ? mg->pf_tol : 1e-13, mg->pf_maxit > 0 ? mg->pf_maxit : 100,
-                         mg->v_min, mg->v_max, p.Vhat, p.J, p.A, p.absV, p.iters, p.status);
+    // iterates and tree in LDS where both fit, else the breadth-first form
+    // with the queue tables in LDS, else everything in global memory (one
+    // block per snapshot in each form)
+    const size_t pf_lds = pf_lds_bytes(n, h->nlev), pf_bfs = pf_bfs_lds_bytes(n, h->nlev);
+    const double tol = mg->pf_tol > 0 ? mg->pf_tol : 1e-13;
+    const int maxit = mg->pf_maxit > 0 ? mg->pf_maxit : 100;
+    if (pf_lds || !pf_bfs)
+      hipLaunchKernelGGL(pf_lds ? k_powerflow_lds : k_powerflow, dim3(S), dim3(256), pf_lds, st, n, p.T.parent,
+                         p.T.phase, p.lvl_off, p.lvl_nodes, h->nlev, p.T.ch_off, p.T.ch, (const double2*)p.z,
+                         (const double2*)loads->S_load, V0[0], V0[1], V0[2], tol, maxit, mg->v_min, mg->v_max,
+                         p.Vhat, p.J, p.A, p.absV, p.iters, p.status);
     else
-    hipLaunchKernelGGL(k_powerflow, dim3(S), dim3(256), 0, st, n, p.T.parent, p.T.phase, p.lvl_off, p.lvl_nodes,
-                       h->nlev, p.T.ch_off, p.T.ch, (const double2*)p.z, (const double2*)loads->S_load, V0[0], V0[1],
-                       V0[2], mg->pf_tol > 0 ? mg->pf_tol : 1e-13, mg->pf_maxit > 0 ? mg->pf_maxit : 100,
-                       mg->v_min, mg->v_max, p.Vhat, p.J, p.A, p.absV, p.iters, p.status);
+      hipLaunchKernelGGL(k_powerflow_bfs, dim3(S), dim3(256), pf_bfs, st, n, p.T.phase, p.lvl_off, p.lvl_nodes,
+                         h->nlev, p.bfs_cf, p.bfs_pp, (const double2*)p.z, (const double2*)loads->S_load, V0[0],
+                         V0[1], V0[2], tol, maxit, mg->v_min, mg->v_max, p.Vhat, p.J, p.A, p.absV, p.iters,
+                         p.status);
   }
   hipLaunchKernelGGL(k_copy2, dim3(1024), dim3(256), 0, st, (const double2*)p.Vhat, p.Vcur, c3);
   SelParams sp;
@@ -1311,9 +1347,14 @@ static int reduce_feeder_impl(okr_handle* h, const okr_yblocks* Y, const okr_top
   const int n = h->n, S = h->S, nseg = h->nseg;
   hipStream_t st = h->stream;
   const Ptrs p = pointers(h, d_workspace);
-  if (pf_lds_bytes(n, h->nlev) > 64 * 1024 && !(mg->flags & OKR_FLAG_VHAT_GIVEN))  // (set before any capture)
-    OKR_HIP(h, hipFuncSetAttribute(reinterpret_cast<const void*>(&k_powerflow_lds),
-                                   hipFuncAttributeMaxDynamicSharedMemorySize, (int)kPfLdsMax));
+  if (!(mg->flags & OKR_FLAG_VHAT_GIVEN)) {  // (set before any capture)
+    if (pf_lds_bytes(n, h->nlev) > 64 * 1024)
+      OKR_HIP(h, hipFuncSetAttribute(reinterpret_cast<const void*>(&k_powerflow_lds),
+                                     hipFuncAttributeMaxDynamicSharedMemorySize, (int)kPfLdsMax));
+    else if (!pf_lds_bytes(n, h->nlev) && pf_bfs_lds_bytes(n, h->nlev) > 64 * 1024)
+      OKR_HIP(h, hipFuncSetAttribute(reinterpret_cast<const void*>(&k_powerflow_bfs),
+                                     hipFuncAttributeMaxDynamicSharedMemorySize, (int)kPfLdsMax));
+  }
   const auto t0 = clk::now();
   {
     const size_t tb = sizeof(int) * h->TO.total;

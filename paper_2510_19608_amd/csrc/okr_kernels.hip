@@ -135,37 +135,70 @@ __device__ __forceinline__ void forward_node(int i, const int* __restrict__ pare
   }
 }
 
-template <bool LDS>
+// Where the sweep's data lives: kPfGlobal reads everything from global
+// memory, kPfAll holds the iterates and the tree arrays in LDS.
+enum { kPfGlobal = 0, kPfAll = 1 };
+
+// Backward-sweep update of node i from its load s and voltage v: J(i) =
+// conj(s/v) on its present phases (zero on the others) plus the children's
+// branch currents, added in child-list order.
+__device__ __forceinline__ void backward_node(int i, const uint8_t* __restrict__ phase, const int* __restrict__ ch_off,
+                                              const int* __restrict__ ch, const double2 (&s)[3],
+                                              const double2 (&v)[3], double2* Jl) {
+  const unsigned ph = phase[i];
+  double2 a[3];
+#pragma unroll
+  for (int p = 0; p < 3; ++p) a[p] = (ph >> p & 1u) ? cconj(cdiv(s[p], v[p])) : make_double2(0.0, 0.0);
+  for (int e = ch_off[i]; e < ch_off[i + 1]; ++e) {
+    const int c = ch[e];
+#pragma unroll
+    for (int p = 0; p < 3; ++p) a[p] = cadd(a[p], Jl[c * 3 + p]);
+  }
+#pragma unroll
+  for (int p = 0; p < 3; ++p) Jl[i * 3 + p] = a[p];
+}
+
+template <int MODE>
 __device__ __forceinline__ void powerflow_body(
-    int n, const int* __restrict__ parent, const uint8_t* __restrict__ phase,
-    const int* __restrict__ lvl_off, const int* __restrict__ lvl_nodes, int nlev,
-    const int* __restrict__ ch_off, const int* __restrict__ ch, const double2* __restrict__ z,
+    int n, const int* __restrict__ gparent, const uint8_t* __restrict__ gphase,
+    const int* __restrict__ glvl_off, const int* __restrict__ glvl_nodes, int nlev,
+    const int* __restrict__ gch_off, const int* __restrict__ gch, const double2* __restrict__ z,
     const double2* __restrict__ Sload, double2 v0a, double2 v0b, double2 v0c, double tol, int maxit,
     double vmin, double vmax, double2* __restrict__ V, double2* __restrict__ J,
     double2* __restrict__ A, double* __restrict__ absV, int* __restrict__ iters, int* __restrict__ status,
     double2* sbuf, double* shd) {
+  constexpr bool LDS = MODE == kPfAll;
   const int l = blockIdx.x;
   const size_t base = (size_t)l * n * 3;
-  // (with LDS the iterates, and the tree arrays the sweeps index, live in
-  // shared memory: every level step then waits on LDS instead of global
-  // memory; only the branch impedances are read from global memory)
+  // (with the tree in LDS every level step indexes shared memory instead of
+  // waiting on a chain of global loads; with the iterates there too only
+  // the branch impedances and the loads are read from global memory)
   double2* Vl = LDS ? sbuf : V + base;
   double2* Jl = LDS ? sbuf + (size_t)n * 3 : J + base;
-  if (LDS) {
-    int* si = (int*)(sbuf + (size_t)n * 6);
-    int* s_lvl_off = si;
+  const int *parent, *lvl_nodes, *ch_off, *ch;
+  const int* lvl_off;
+  const uint8_t* phase;
+  if constexpr (MODE == kPfGlobal) {
+    parent = gparent;
+    lvl_nodes = glvl_nodes;
+    ch_off = gch_off;
+    ch = gch;
+    lvl_off = glvl_off;
+    phase = gphase;
+  } else {
+    int* s_lvl_off = (int*)(sbuf + (LDS ? (size_t)n * 6 : 0));
     int* s_lvl_nodes = s_lvl_off + nlev + 1;
     int* s_ch_off = s_lvl_nodes + n;
     int* s_ch = s_ch_off + n + 1;
     int* s_parent = s_ch + n;
     uint8_t* s_phase = (uint8_t*)(s_parent + n);
-    for (int i = threadIdx.x; i <= nlev; i += blockDim.x) s_lvl_off[i] = lvl_off[i];
-    for (int i = threadIdx.x; i <= n; i += blockDim.x) s_ch_off[i] = ch_off[i];
+    for (int i = threadIdx.x; i <= nlev; i += blockDim.x) s_lvl_off[i] = glvl_off[i];
+    for (int i = threadIdx.x; i <= n; i += blockDim.x) s_ch_off[i] = gch_off[i];
     for (int i = threadIdx.x; i < n; i += blockDim.x) {
-      s_lvl_nodes[i] = lvl_nodes[i];
-      s_ch[i] = i < n - 1 ? ch[i] : 0;
-      s_parent[i] = parent[i];
-      s_phase[i] = phase[i];
+      s_lvl_nodes[i] = glvl_nodes[i];
+      s_ch[i] = i < n - 1 ? gch[i] : 0;
+      s_parent[i] = gparent[i];
+      s_phase[i] = gphase[i];
     }
     lvl_off = s_lvl_off;
     lvl_nodes = s_lvl_nodes;
@@ -181,32 +214,53 @@ __device__ __forceinline__ void powerflow_body(
   __syncthreads();
   int it = 0;
   bool conv = false;
+  const int tid = threadIdx.x, bd = blockDim.x;
   for (it = 1; it <= maxit; ++it) {
-    for (int i = threadIdx.x; i < n; i += blockDim.x)
-      for (int p = 0; p < 3; ++p)
-        Jl[i * 3 + p] = (i > 0 && (phase[i] >> p & 1u)) ? cconj(cdiv(Sl[i * 3 + p], Vl[i * 3 + p]))
-                                                        : make_double2(0.0, 0.0);
-    __syncthreads();
-    for (int lev = nlev - 2; lev >= 0; --lev) {
-      for (int q = lvl_off[lev] + threadIdx.x; q < lvl_off[lev + 1]; q += blockDim.x) {
-        const int i = lvl_nodes[q];
-        double2 s0 = Jl[i * 3], s1 = Jl[i * 3 + 1], s2 = Jl[i * 3 + 2];
-        for (int e = ch_off[i]; e < ch_off[i + 1]; ++e) {
-          const int c = ch[e];
-          s0 = cadd(s0, Jl[c * 3]);
-          s1 = cadd(s1, Jl[c * 3 + 1]);
-          s2 = cadd(s2, Jl[c * 3 + 2]);
-        }
-        Jl[i * 3] = s0; Jl[i * 3 + 1] = s1; Jl[i * 3 + 2] = s2;
+    // backward sweep, deepest level first: a node's branch current is its
+    // own load current conj(S/V) plus its children's branch currents (one
+    // level deeper, finished on the previous step).  The load and voltage
+    // of this thread's first node on the next level up are loaded while the
+    // current level is computed (neither changes during the sweep; a thread
+    // with no node there loads the root's, unused).  The root's own branch
+    // current is never read and is not formed.
+    double2 sn[3], vn[3];
+    {
+      const int q = nlev > 1 ? lvl_off[nlev - 1] + tid : 0;
+      const int i = (nlev > 1 && q < lvl_off[nlev]) ? lvl_nodes[q] : 0;
+#pragma unroll
+      for (int p = 0; p < 3; ++p) { sn[p] = Sl[i * 3 + p]; vn[p] = Vl[i * 3 + p]; }
+    }
+    for (int lev = nlev - 1; lev >= 1; --lev) {
+      double2 sc[3], vc[3];
+#pragma unroll
+      for (int p = 0; p < 3; ++p) { sc[p] = sn[p]; vc[p] = vn[p]; }
+      {
+        const int q = lev > 1 ? lvl_off[lev - 1] + tid : 0;
+        const int i = (lev > 1 && q < lvl_off[lev]) ? lvl_nodes[q] : 0;
+#pragma unroll
+        for (int p = 0; p < 3; ++p) { sn[p] = Sl[i * 3 + p]; vn[p] = Vl[i * 3 + p]; }
       }
-      __syncthreads();
+      const int q0 = lvl_off[lev] + tid, q1 = lvl_off[lev + 1];
+      if (q0 < q1) backward_node(lvl_nodes[q0], phase, ch_off, ch, sc, vc, Jl);
+      for (int q = q0 + bd; q < q1; q += bd) {  // (levels wider than the block)
+        const int i = lvl_nodes[q];
+        double2 si[3], vi[3];
+#pragma unroll
+        for (int p = 0; p < 3; ++p) { si[p] = Sl[i * 3 + p]; vi[p] = Vl[i * 3 + p]; }
+        backward_node(i, phase, ch_off, ch, si, vi, Jl);
+      }
+      if (LDS) {
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup", "local");
+        __builtin_amdgcn_s_barrier();
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup", "local");
+      } else {
+        __syncthreads();
+      }
     }
     double dmax = 0.0;
     // the branch impedance of this thread's first node on the next level is
-    // loaded while the current level is computed (the impedances are the
-    // only global reads of the sweep; a thread with no node there loads the
-    // root's, unused)
-    const int tid = threadIdx.x, bd = blockDim.x;
+    // loaded while the current level is computed (a thread with no node
+    // there loads the root's, unused)
     double2 zn[9];
     {
       const int q1 = nlev > 1 ? lvl_off[1] + tid : 0;
@@ -276,8 +330,8 @@ __global__ __launch_bounds__(256) void k_powerflow(
     double vmin, double vmax, double2* __restrict__ V, double2* __restrict__ J,
     double2* __restrict__ A, double* __restrict__ absV, int* __restrict__ iters, int* __restrict__ status) {
   __shared__ double shd[16];
-  powerflow_body<false>(n, parent, phase, lvl_off, lvl_nodes, nlev, ch_off, ch, z, Sload, v0a, v0b, v0c, tol, maxit,
-                        vmin, vmax, V, J, A, absV, iters, status, nullptr, shd);
+  powerflow_body<kPfGlobal>(n, parent, phase, lvl_off, lvl_nodes, nlev, ch_off, ch, z, Sload, v0a, v0b, v0c, tol, maxit,
+                            vmin, vmax, V, J, A, absV, iters, status, nullptr, shd);
 }
 
 // The same with the voltage and current iterates in dynamic LDS (2 x n x 3
@@ -292,8 +346,150 @@ __global__ __launch_bounds__(256) void k_powerflow_lds(
     double2* __restrict__ A, double* __restrict__ absV, int* __restrict__ iters, int* __restrict__ status) {
   extern __shared__ double2 pf_lds[];
   __shared__ double shd[16];
-  powerflow_body<true>(n, parent, phase, lvl_off, lvl_nodes, nlev, ch_off, ch, z, Sload, v0a, v0b, v0c, tol, maxit,
-                       vmin, vmax, V, J, A, absV, iters, status, pf_lds, shd);
+  powerflow_body<kPfAll>(n, parent, phase, lvl_off, lvl_nodes, nlev, ch_off, ch, z, Sload, v0a, v0b, v0c, tol, maxit,
+                         vmin, vmax, V, J, A, absV, iters, status, pf_lds, shd);
+}
+
+// The same for feeders whose iterates do not fit in LDS (n < 65536): every
+// per-node quantity of the sweep is stored by breadth-first queue position
+// (each level a contiguous run, the children of position q at positions
+// cf[q] .. cf[q+1]-1 in child-list order, pp[q] the parent's position), so
+// each level step reads and writes contiguous records and a node's children
+// are one contiguous run.  The queue tables (16-bit) sit in dynamic LDS; the
+// snapshot's loads and voltages in queue order use the Vhat and A slices as
+// scratch until the end, the branch currents the J slice.  Each node's
+// arithmetic, and the order of every sum, is that of the node-order form.
+__global__ __launch_bounds__(256) void k_powerflow_bfs(
+    int n, const uint8_t* __restrict__ phase, const int* __restrict__ glvl_off, const int* __restrict__ glvl_nodes,
+    int nlev, const int* __restrict__ gcf, const int* __restrict__ gpp, const double2* __restrict__ z,
+    const double2* __restrict__ Sload, double2 v0a, double2 v0b, double2 v0c, double tol, int maxit,
+    double vmin, double vmax, double2* __restrict__ V, double2* __restrict__ J,
+    double2* __restrict__ A, double* __restrict__ absV, int* __restrict__ iters, int* __restrict__ status) {
+  extern __shared__ double2 pf_lds[];
+  __shared__ double shd[16];
+  const int l = blockIdx.x, tid = threadIdx.x, bd = blockDim.x;
+  const size_t base = (size_t)l * n * 3;
+  int* lvl_off = (int*)pf_lds;
+  uint16_t* node = (uint16_t*)(lvl_off + nlev + 1);
+  uint16_t* cf = node + n;
+  uint16_t* pp = cf + n + 1;
+  uint8_t* ph = (uint8_t*)(pp + n);
+  for (int i = tid; i <= nlev; i += bd) lvl_off[i] = glvl_off[i];
+  for (int q = tid; q <= n; q += bd) cf[q] = (uint16_t)gcf[q];
+  for (int q = tid; q < n; q += bd) {
+    const int i = glvl_nodes[q];
+    node[q] = (uint16_t)i;
+    pp[q] = (uint16_t)gpp[q];
+    ph[q] = phase[i];
+  }
+  const double2* Sl = Sload + base;
+  double2* Sb = V + base;
+  double2* Vb = A + base;
+  double2* Jb = J + base;
+  __syncthreads();
+  const double2 v0[3] = {v0a, v0b, v0c};
+  for (int q = tid; q < n; q += bd) {
+    const int i = node[q];
+    const unsigned m = ph[q];
+#pragma unroll
+    for (int p = 0; p < 3; ++p) {
+      Sb[q * 3 + p] = Sl[i * 3 + p];
+      Vb[q * 3 + p] = (m >> p & 1u) ? v0[p] : make_double2(0.0, 0.0);
+    }
+  }
+  __syncthreads();
+  int it = 0;
+  bool conv = false;
+  for (it = 1; it <= maxit; ++it) {
+    // backward sweep, deepest level first: branch current = own load
+    // current conj(S/V) on present phases + the children's branch currents
+    // (finished on the previous step), added in child order after all of
+    // them are loaded; the root's is never read and is not formed
+    for (int lev = nlev - 1; lev >= 1; --lev) {
+      for (int q = lvl_off[lev] + tid; q < lvl_off[lev + 1]; q += bd) {
+        const unsigned m = ph[q];
+        const int c0 = cf[q], c1 = cf[q + 1];
+        double2 s[3], v[3], a[3];
+#pragma unroll
+        for (int p = 0; p < 3; ++p) { s[p] = Sb[q * 3 + p]; v[p] = Vb[q * 3 + p]; }
+        for (int c = c0; c < c1; c += 2) {
+          double2 t0[3], t1[3];
+          const int cc = c + 1 < c1 ? c + 1 : c;
+#pragma unroll
+          for (int p = 0; p < 3; ++p) { t0[p] = Jb[c * 3 + p]; t1[p] = Jb[cc * 3 + p]; }
+          if (c == c0) {
+#pragma unroll
+            for (int p = 0; p < 3; ++p) a[p] = (m >> p & 1u) ? cconj(cdiv(s[p], v[p])) : make_double2(0.0, 0.0);
+          }
+#pragma unroll
+          for (int p = 0; p < 3; ++p) a[p] = cadd(a[p], t0[p]);
+          if (c + 1 < c1) {
+#pragma unroll
+            for (int p = 0; p < 3; ++p) a[p] = cadd(a[p], t1[p]);
+          }
+        }
+        if (c0 == c1) {
+#pragma unroll
+          for (int p = 0; p < 3; ++p) a[p] = (m >> p & 1u) ? cconj(cdiv(s[p], v[p])) : make_double2(0.0, 0.0);
+        }
+#pragma unroll
+        for (int p = 0; p < 3; ++p) Jb[q * 3 + p] = a[p];
+      }
+      __syncthreads();
+    }
+    // forward sweep: V(q) = V(parent) - z J(q) on present phases, the
+    // largest change into dmax (NaN-propagating)
+    double dmax = 0.0;
+    for (int lev = 1; lev < nlev; ++lev) {
+      for (int q = lvl_off[lev] + tid; q < lvl_off[lev + 1]; q += bd) {
+        const int i = node[q], pq = pp[q];
+        const unsigned m = ph[q];
+        double2 zi[9], j[3], vp[3], vo[3];
+#pragma unroll
+        for (int e = 0; e < 9; ++e) zi[e] = z[(size_t)i * 9 + e];
+#pragma unroll
+        for (int p = 0; p < 3; ++p) { j[p] = Jb[q * 3 + p]; vp[p] = Vb[pq * 3 + p]; vo[p] = Vb[q * 3 + p]; }
+#pragma unroll
+        for (int p = 0; p < 3; ++p) {
+          if (!(m >> p & 1u)) continue;
+          const double2 d = cadd(cadd(cmul(zi[p * 3], j[0]), cmul(zi[p * 3 + 1], j[1])), cmul(zi[p * 3 + 2], j[2]));
+          const double2 nv = csub(vp[p], d);
+          const double dd = sqrt(cabs2(csub(nv, vo[p])));
+          dmax = (dd <= dmax) ? dmax : dd;
+          Vb[q * 3 + p] = nv;
+        }
+      }
+      __syncthreads();
+    }
+    dmax = block_reduce(dmax, [](double a, double b) { return (b <= a) ? a : b; }, shd);
+    if (!(dmax <= 1e3)) break;
+    if (dmax <= tol) { conv = true; break; }
+  }
+  // voltages back to node order (over the loads, no longer read), then the
+  // load currents and magnitudes at the final voltages
+  for (int q = tid; q < n; q += bd) {
+    const int i = node[q];
+#pragma unroll
+    for (int p = 0; p < 3; ++p) V[base + i * 3 + p] = Vb[q * 3 + p];
+  }
+  __syncthreads();
+  double vlo = 1e300, vhi = -1e300;
+  for (int i = tid; i < n; i += bd)
+    for (int p = 0; p < 3; ++p) {
+      const bool pr = (phase[i] >> p & 1u);
+      const double2 v = V[base + i * 3 + p];
+      A[base + i * 3 + p] = (i > 0 && pr) ? cconj(cdiv(Sl[i * 3 + p], v)) : make_double2(0.0, 0.0);
+      const double m = pr ? sqrt(cabs2(v)) : 0.0;
+      absV[base + i * 3 + p] = m;
+      if (pr) { vlo = fmin(vlo, m); vhi = fmax(vhi, m); }
+    }
+  vlo = block_reduce(vlo, [](double a, double b) { return fmin(a, b); }, shd);
+  vhi = block_reduce(vhi, [](double a, double b) { return fmax(a, b); }, shd);
+  if (tid == 0) {
+    iters[l] = it;
+    if (!conv) atomicOr(status, 16);
+    if (vlo < vmin || vhi > vmax) atomicOr(status, 32);
+  }
 }
 
 // Cumulative series impedance from the root, Zroot(v) = Zroot(parent) + z(v)

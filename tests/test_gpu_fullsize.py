@@ -93,3 +93,17 @@ def test_fullsize_sampled_masks(okr, cfg):
         for j, v in enumerate(order):
             if G["segments"][g]["mask"] >> j & 1:
                 keep[v] = 0
+
+
+@pytest.mark.parametrize("cfg", ["c3", "c4"])
+def test_fullsize_load_flow(okr, cfg):
+    """Scenario voltages at full size, where the sweep keeps its iterates in
+    global memory and the tree in LDS: every snapshot against the oracle's
+    backward/forward sweep."""
+    _say(f"{cfg} seed 0 load flow")
+    G = golden(cfg)
+    f = make_feeder(cfg, 0, e_bar=G["e_bar"])
+    out = okr.reduce_feeder(f, want_vhat=True)
+    V, I, st, _ = oracle.powerflow(f)
+    assert st == 0
+    np.testing.assert_allclose(out["Vhat"], V, rtol=0, atol=1e-12)
