@@ -462,8 +462,8 @@ __global__ __launch_bounds__(kTermsBlock) void k_chain_terms(
     }
     return;
   }
+  int c = 0;  // (a thread's items increase, so its chain index only moves forward)
   for (int it = blockIdx.x * blockDim.x + threadIdx.x; it < items; it += gridDim.x * blockDim.x) {
-    int c = 0;
     while (c + 1 < nch && chains[(c + 1) * kChainInts + C_PBASE] <= it) ++c;
     const uint32_t u = (uint32_t)(it - chains[c * kChainInts + C_PBASE]);
     uint32_t pm = (uint32_t)chains[c * kChainInts + C_PMASK], mask = 0;
