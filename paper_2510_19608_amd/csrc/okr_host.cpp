@@ -951,9 +951,13 @@ void list_score(const okr_handle* h, const Ptrs& w, const int* segp, int nz, int
                 const int* count, int cap, MaskScore* out, const SelParams& sp, hipStream_t st) {
   const size_t ls = h->L.lane_stride;
   const int fb = std::max(1, std::min(64, (cap + 255) / 256));
-  const int cb = std::max(1, std::min(16, (int)(((size_t)cap * k + 255) / 256)));
   hipLaunchKernelGGL(k_terms_init, dim3(fb, 1, nz), dim3(256), 0, st, (const SegHdr*)w.hdrs, segp, ls, (int)0, count,
                      cap, (const double*)w.econst, w.lacc, (unsigned long long*)nullptr);
+  // blocks per (segment, snapshot): each stages the snapshot's records, so
+  // as few as fill the chip (about 1024 blocks in all), at most one per 256
+  // items and 16
+  const size_t pairs = (size_t)h->S * nz;
+  const int cb = std::max(1, std::min({16, (int)(((size_t)cap * k + 255) / 256), (int)((1024 + pairs - 1) / pairs)}));
   hipLaunchKernelGGL(k_chain_terms, dim3(cb, h->S, nz), dim3(256), terms_lds_bytes(k), st, (const SegHdr*)w.hdrs,
                      segp, ls, (int)0, (const int*)w.tab, (const double2*)w.P, (const TargetRec*)w.srec,
                      (const double2*)w.headV, (const TargetRec*)w.zrec, (const double*)w.econst, list, count, cap,
