@@ -107,3 +107,17 @@ def test_fullsize_load_flow(okr, cfg):
     V, I, st, _ = oracle.powerflow(f)
     assert st == 0
     np.testing.assert_allclose(out["Vhat"], V, rtol=0, atol=1e-12)
+
+
+def test_load_flow_node_order_global(okr):
+    """A 24,000-node feeder (4 snapshots) needs more LDS for the
+    breadth-first queue tables (7 bytes per node) than a block may take,
+    so the sweep runs from global memory in node order: every snapshot's
+    voltages against the oracle's sweep (a wide band keeps the heavily
+    loaded feeder valid)."""
+    _say("24000-node feeder, 4 snapshots, load flow")
+    f = make_feeder("c3", 0, n=24000, snapshots=4, v_min=0.5, v_max=1.5)
+    out = okr.reduce_feeder(f, want_vhat=True)
+    V, I, st, _ = oracle.powerflow(f)
+    assert st == 0
+    np.testing.assert_allclose(out["Vhat"], V, rtol=0, atol=1e-12)
