@@ -139,25 +139,6 @@ __device__ __forceinline__ void forward_node(int i, const int* __restrict__ pare
 // memory, kPfAll holds the iterates and the tree arrays in LDS.
 enum { kPfGlobal = 0, kPfAll = 1 };
 
-// Backward-sweep update of node i from its load s and voltage v: J(i) =
-// conj(s/v) on its present phases (zero on the others) plus the children's
-// branch currents, added in child-list order.
-__device__ __forceinline__ void backward_node(int i, const uint8_t* __restrict__ phase, const int* __restrict__ ch_off,
-                                              const int* __restrict__ ch, const double2 (&s)[3],
-                                              const double2 (&v)[3], double2* Jl) {
-  const unsigned ph = phase[i];
-  double2 a[3];
-#pragma unroll
-  for (int p = 0; p < 3; ++p) a[p] = (ph >> p & 1u) ? cconj(cdiv(s[p], v[p])) : make_double2(0.0, 0.0);
-  for (int e = ch_off[i]; e < ch_off[i + 1]; ++e) {
-    const int c = ch[e];
-#pragma unroll
-    for (int p = 0; p < 3; ++p) a[p] = cadd(a[p], Jl[c * 3 + p]);
-  }
-#pragma unroll
-  for (int p = 0; p < 3; ++p) Jl[i * 3 + p] = a[p];
-}
-
 template <int MODE>
 __device__ __forceinline__ void powerflow_body(
     int n, const int* __restrict__ gparent, const uint8_t* __restrict__ gphase,
@@ -170,9 +151,9 @@ __device__ __forceinline__ void powerflow_body(
   constexpr bool LDS = MODE == kPfAll;
   const int l = blockIdx.x;
   const size_t base = (size_t)l * n * 3;
-  // (with the tree in LDS every level step indexes shared memory instead of
-  // waiting on a chain of global loads; with the iterates there too only
-  // the branch impedances and the loads are read from global memory)
+  // (with LDS the iterates, and the tree arrays the sweeps index, live in
+  // shared memory: every level step then waits on LDS instead of global
+  // memory; only the branch impedances are read from global memory)
   double2* Vl = LDS ? sbuf : V + base;
   double2* Jl = LDS ? sbuf + (size_t)n * 3 : J + base;
   const int *parent, *lvl_nodes, *ch_off, *ch;
@@ -216,51 +197,33 @@ __device__ __forceinline__ void powerflow_body(
   bool conv = false;
   const int tid = threadIdx.x, bd = blockDim.x;
   for (it = 1; it <= maxit; ++it) {
-    // backward sweep, deepest level first: a node's branch current is its
-    // own load current conj(S/V) plus its children's branch currents (one
-    // level deeper, finished on the previous step).  The load and voltage
-    // of this thread's first node on the next level up are loaded while the
-    // current level is computed (neither changes during the sweep; a thread
-    // with no node there loads the root's, unused).  The root's own branch
-    // current is never read and is not formed.
-    double2 sn[3], vn[3];
-    {
-      const int q = nlev > 1 ? lvl_off[nlev - 1] + tid : 0;
-      const int i = (nlev > 1 && q < lvl_off[nlev]) ? lvl_nodes[q] : 0;
-#pragma unroll
-      for (int p = 0; p < 3; ++p) { sn[p] = Sl[i * 3 + p]; vn[p] = Vl[i * 3 + p]; }
-    }
-    for (int lev = nlev - 1; lev >= 1; --lev) {
-      double2 sc[3], vc[3];
-#pragma unroll
-      for (int p = 0; p < 3; ++p) { sc[p] = sn[p]; vc[p] = vn[p]; }
-      {
-        const int q = lev > 1 ? lvl_off[lev - 1] + tid : 0;
-        const int i = (lev > 1 && q < lvl_off[lev]) ? lvl_nodes[q] : 0;
-#pragma unroll
-        for (int p = 0; p < 3; ++p) { sn[p] = Sl[i * 3 + p]; vn[p] = Vl[i * 3 + p]; }
-      }
-      const int q0 = lvl_off[lev] + tid, q1 = lvl_off[lev + 1];
-      if (q0 < q1) backward_node(lvl_nodes[q0], phase, ch_off, ch, sc, vc, Jl);
-      for (int q = q0 + bd; q < q1; q += bd) {  // (levels wider than the block)
+    // load currents conj(S/V) of every node in one pass (off the level
+    // steps' latency chain), then the backward sweep adds each level's
+    // children into their parents, deepest level first
+    for (int i = tid; i < n; i += bd)
+      for (int p = 0; p < 3; ++p)
+        Jl[i * 3 + p] = (i > 0 && (phase[i] >> p & 1u)) ? cconj(cdiv(Sl[i * 3 + p], Vl[i * 3 + p]))
+                                                        : make_double2(0.0, 0.0);
+    __syncthreads();
+    for (int lev = nlev - 2; lev >= 0; --lev) {
+      for (int q = lvl_off[lev] + tid; q < lvl_off[lev + 1]; q += bd) {
         const int i = lvl_nodes[q];
-        double2 si[3], vi[3];
-#pragma unroll
-        for (int p = 0; p < 3; ++p) { si[p] = Sl[i * 3 + p]; vi[p] = Vl[i * 3 + p]; }
-        backward_node(i, phase, ch_off, ch, si, vi, Jl);
+        double2 s0 = Jl[i * 3], s1 = Jl[i * 3 + 1], s2 = Jl[i * 3 + 2];
+        for (int e = ch_off[i]; e < ch_off[i + 1]; ++e) {
+          const int c = ch[e];
+          s0 = cadd(s0, Jl[c * 3]);
+          s1 = cadd(s1, Jl[c * 3 + 1]);
+          s2 = cadd(s2, Jl[c * 3 + 2]);
+        }
+        Jl[i * 3] = s0; Jl[i * 3 + 1] = s1; Jl[i * 3 + 2] = s2;
       }
-      if (LDS) {
-        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup", "local");
-        __builtin_amdgcn_s_barrier();
-        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup", "local");
-      } else {
-        __syncthreads();
-      }
+      __syncthreads();
     }
     double dmax = 0.0;
     // the branch impedance of this thread's first node on the next level is
-    // loaded while the current level is computed (a thread with no node
-    // there loads the root's, unused)
+    // loaded while the current level is computed (the impedances are the
+    // only global reads of the sweep; a thread with no node there loads the
+    // root's, unused)
     double2 zn[9];
     {
       const int q1 = nlev > 1 ? lvl_off[1] + tid : 0;
