@@ -981,7 +981,7 @@ void enqueue_search(okr_handle* h, void* ws, const okr_yblocks* Y, const okr_loa
                      p.tickets, ntick, h->nlanes, h->L.lane_stride);
   hipLaunchKernelGGL(k_branch_z, dim3((n + 127) / 128), dim3(128), 0, st, n, p.T.parent, p.T.phase, p.T.ch_off,
                      p.T.ch, (const double2*)Y->Y_diag, (const double2*)Y->Y_off, p.z, p.status);
-  hipLaunchKernelGGL(k_zroot, dim3(1), dim3(256), 0, st, n, p.T.parent, p.lvl_off, p.lvl_nodes, h->nlev,
+  hipLaunchKernelGGL(k_zroot, dim3(1), dim3(1024), 0, st, n, p.T.parent, p.lvl_off, p.lvl_nodes, h->nlev,
                      (const double2*)p.z, p.Zroot);
   const size_t c3 = (size_t)S * n * 3;
   if (vhat_given) {

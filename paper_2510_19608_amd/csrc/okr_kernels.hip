@@ -458,9 +458,9 @@ __global__ __launch_bounds__(256) void k_powerflow_bfs(
 // Cumulative series impedance from the root, Zroot(v) = Zroot(parent) + z(v)
 // (3x3 blocks, zero on absent phases), level by level; the impedance of the
 // path between an ancestor s and r is Zroot(r) - Zroot(s).  One block.
-__global__ __launch_bounds__(256) void k_zroot(int n, const int* __restrict__ parent,
-                                               const int* __restrict__ lvl_off, const int* __restrict__ lvl_nodes,
-                                               int nlev, const double2* __restrict__ z, double2* __restrict__ Zroot) {
+__global__ __launch_bounds__(1024) void k_zroot(int n, const int* __restrict__ parent,
+                                                const int* __restrict__ lvl_off, const int* __restrict__ lvl_nodes,
+                                                int nlev, const double2* __restrict__ z, double2* __restrict__ Zroot) {
   for (int e = threadIdx.x; e < 9; e += blockDim.x) Zroot[e] = make_double2(0.0, 0.0);  // node 0, level 0
   __syncthreads();
   for (int L = 1; L < nlev; ++L) {
