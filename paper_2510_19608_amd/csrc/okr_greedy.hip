@@ -1343,7 +1343,7 @@ int setup(okr_greedy* g, const GPtrs& p, const okr_yblocks* Y, const okr_loads* 
   hipLaunchKernelGGL(k_branch_z, dim3((n + 127) / 128), dim3(128), 0, st, n, (const int*)p.parent,
                      (const uint8_t*)p.phase, (const int*)p.ch_off, (const int*)p.ch, (const double2*)Y->Y_diag,
                      (const double2*)Y->Y_off, p.z, p.status);
-  hipLaunchKernelGGL(k_zroot, dim3(1), dim3(256), 0, st, n, (const int*)p.parent, (const int*)p.lvl_off,
+  hipLaunchKernelGGL(k_zroot, dim3(1), dim3(1024), 0, st, n, (const int*)p.parent, (const int*)p.lvl_off,
                      (const int*)p.lvl_nodes, g->nlev, (const double2*)p.z, p.Zr);
   const size_t c3 = (size_t)S * n * 3;
   const double2* V0 = (const double2*)L->V0;
